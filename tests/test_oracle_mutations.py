@@ -1,0 +1,76 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that the pins
+catch each one.  A pin that passes on a broken oracle would prove nothing."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ckks as O
+from tests import test_oracle_pins as T
+
+
+def _expect_fail(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_mod_down_without_rounding_is_caught(monkeypatch):
+    def floor_mod_down(P, x, level):
+        Pb = math.prod(P.p)
+        r = O.bconv(x[level:], P.p, P.mods(level))
+        qs = P.mods(level)
+        return O.smul(O.sub(x[:level], r, qs), [pow(Pb, -1, q) for q in qs], qs)
+    monkeypatch.setattr(O, "mod_down", floor_mod_down)
+    _expect_fail(T.test_mod_down_rounds_up_to_the_fast_conversion_overflow)
+
+
+def test_rescale_truncating_is_caught(monkeypatch):
+    orig = O.add_int
+    monkeypatch.setattr(O, "add_int", lambda a, vals, mods: orig(a, [0] * len(vals), mods))
+    _expect_fail(T.test_rescale_is_rounded_division_by_last_prime)
+
+
+def test_wrong_slot_generator_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "_slot_exponents", lambda n: np.array([pow(3, j, 4 * n) for j in range(n)]))
+    _expect_fail(T.test_encoding_inverts_the_slot_evaluation, 8)
+
+
+def test_automorphism_without_sign_is_caught(monkeypatch):
+    def unsigned_auto(a, g, mods, logn):
+        n = 1 << logn
+        out = np.empty_like(a)
+        for i in range(n):
+            out[:, (i * g) % n] = a[:, i]
+        return out
+    monkeypatch.setattr(O, "automorphism", unsigned_auto)
+    _expect_fail(T.test_automorphism_matches_substitution_and_composes)
+
+
+def test_gadget_without_p_is_caught(monkeypatch):
+    def swk_gen_no_p(P, s, s_from_ext, a, e, galois):
+        mods = P.ext_mods(P.L)
+        s_ext = O.secret_rns(P, s, mods)
+        Qb = math.prod(P.q)
+        bs = []
+        for j, D in enumerate(P.digits(P.L)):
+            Qj = math.prod(P.q[i] for i in D)
+            w_j = (Qb // Qj) * pow(Qb // Qj, -1, Qj)
+            b = O.add(O.neg(O.polymul(a[j], s_ext, mods, P.ext_psis(P.L), P.logn), mods),
+                      O.from_ints(e[j], mods), mods)
+            bs.append(O.add(b, O.smul(s_from_ext, [w_j % m for m in mods], mods), mods))
+        return O.SwitchKey(np.stack(bs), a, galois)
+    monkeypatch.setattr(O, "swk_gen", swk_gen_no_p)
+    _expect_fail(T.test_switching_key_decrypts_to_gadget_times_secret)
+
+
+def test_cyclic_instead_of_negacyclic_is_caught(monkeypatch):
+    # a root of order N (cyclic convolution) instead of 2N breaks the product pin
+    def cyclic_root(q, n):
+        g = 2
+        while True:
+            x = pow(g, (q - 1) // n, q)
+            if pow(x, n // 2, q) == q - 1:
+                return x
+            g += 1
+    monkeypatch.setattr(O, "find_psi", cyclic_root)
+    _expect_fail(T.test_ntt_product_is_negacyclic_convolution, 3)
