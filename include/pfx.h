@@ -1,0 +1,248 @@
+/*
+ * pfx — RNS-CKKS homomorphic evaluation on AMD Instinct MI355X (gfx950).
+ *
+ * C-ABI of libpfx.so.  Plain pointers and sizes only.  The calls follow the
+ * roles of the paper's private database exploration (arXiv 2412.13269, Sec. 3
+ * and Sec. 5.5, Alg. 2): the scientist creates keys, encrypts and decrypts;
+ * the database owner evaluates on ciphertexts.  The scheme is RNS-CKKS with
+ * hybrid key switching (Sec. 2.3-2.5, App. A).
+ *
+ * Conventions
+ * -----------
+ * Status: every call returns PFX_OK (0) or a negative PFX_E* code; on error the
+ *   outputs are untouched and pfx_last_error() (thread-local) describes it.
+ * Ownership: objects come back through out-parameters; the caller frees them
+ *   with the matching pfx_*_destroy.  Host arrays are borrowed for the call.
+ * Device work: evaluation calls are enqueued on `stream` (a hipStream_t, NULL
+ *   for the default stream) and return before the device finishes.  An object
+ *   must outlive the stream work that reads it.  Outputs may alias inputs.
+ *   Calls that share a context and run on different streams each use that
+ *   stream's own scratch space; they are safe as long as they do not write
+ *   the same objects.
+ * Interchange words: uint64 residues in [0, q_i), COEFFICIENT domain, natural
+ *   coefficient order, limb-major: word (k, i, c) of a ciphertext sits at
+ *   ((k * n_limbs) + i) * N + c for polynomial k, limb i (prime q_i),
+ *   coefficient c.  On the device the library keeps its own representation
+ *   (NTT domain, residues held as exact FP64 integers); exported words are
+ *   canonical and bit-comparable.
+ * Randomness: the library draws nothing.  The secret key, the uniform
+ *   polynomials `a` and the errors `e` of encryption and key generation
+ *   (Sec. 2.3, Sec. 2.4.1) are inputs supplied by the caller.
+ * Moduli: every prime is below 2^50 and 1 mod 2^mod_log2 (see pfx_params).
+ */
+#ifndef PFX_H
+#define PFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pfx_status;
+#define PFX_OK 0
+#define PFX_EINVAL (-1)  /* bad argument, size or pointer */
+#define PFX_EPARAM (-2)  /* parameter set not supported */
+#define PFX_ELEVEL (-3)  /* too few limbs for the operation */
+#define PFX_ESCALE (-4)  /* operand scales differ by more than 2^-10 relative */
+#define PFX_ENOKEY (-5)  /* no key for the needed Galois element */
+#define PFX_ENOMEM (-6)  /* device allocation failed or budget exceeded */
+#define PFX_EBUSY (-7)   /* server did not admit the request (retry later) */
+#define PFX_EDEVICE (-8) /* HIP runtime error or no usable gfx950 device */
+
+#define PFX_MAX_PRIMES 64
+#define PFX_MAX_LOGN 16
+#define PFX_MIN_LOGN 4
+
+/*
+ * Parameter set (Sec. 6.1, Tab. 1 gives the paper's sets by bit sizes only).
+ * Ciphertext primes q_0..q_{n_q-1}, special primes p_0..p_{n_p-1} (the
+ * modulus P of hybrid key switching, Sec. 2.4.1).  Prime rule: every prime is
+ * 1 mod 2^mod_log2 (0 means log_n + 1); a prime of 50 bits is the next unused
+ * prime below 2^50, a smaller one the next unused prime nearest 2^bits
+ * (offsets 0, +1, -1, +2, ... multiples of 2^mod_log2); q's are chosen first,
+ * in order, then p's.  Bit sizes must lie in [20, 50].  alpha = primes per
+ * key-switching digit; digit j holds primes [alpha*j, alpha*j + alpha).
+ */
+typedef struct pfx_params {
+    uint32_t log_n;
+    uint32_t n_q;
+    uint32_t q_bits[PFX_MAX_PRIMES];
+    uint32_t n_p;
+    uint32_t p_bits[PFX_MAX_PRIMES];
+    uint32_t alpha;
+    uint32_t mod_log2;
+} pfx_params;
+
+typedef struct pfx_info {
+    uint32_t log_n;
+    uint32_t n_limbs;
+    uint32_t degree; /* 0 plaintext, 1 ciphertext, 2 after a product */
+    double scale;
+} pfx_info;
+
+typedef struct pfx_ctx pfx_ctx;
+typedef struct pfx_sk pfx_sk;
+typedef struct pfx_swk pfx_swk;
+typedef struct pfx_ct pfx_ct; /* ciphertexts and plaintexts (degree 0) */
+typedef struct pfx_ct pfx_pt;
+
+const char *pfx_status_str(pfx_status s);
+const char *pfx_last_error(void);
+
+/* Host only, no device needed: the primes q, p and the roots psi (2N-th,
+ * one per prime, q's then p's) that pfx_ctx_create would choose.  Arrays of
+ * n_q, n_p and n_q + n_p entries. */
+pfx_status pfx_params_primes(const pfx_params *prm, uint64_t *q, uint64_t *p, uint64_t *psi);
+
+/* Host only: the words of pfx_encode (n_limbs * N canonical residues,
+ * coefficient domain) without a device. */
+pfx_status pfx_encode_words(const pfx_params *prm, const double *re, const double *im, size_t n_slots,
+                            uint32_t n_limbs, double scale, uint64_t *words);
+/* Host only: pfx_decode of canonical coefficient-domain words. */
+pfx_status pfx_decode_words(const pfx_params *prm, const uint64_t *words, uint32_t n_limbs,
+                            double scale, double *re, double *im, size_t n_slots);
+
+/* ------------------------------------------------------------------ context */
+pfx_status pfx_ctx_create(const pfx_params *prm, int hip_device, pfx_ctx **out);
+void pfx_ctx_destroy(pfx_ctx *ctx);
+pfx_status pfx_ctx_moduli(const pfx_ctx *ctx, uint64_t *q, uint64_t *p, uint64_t *psi);
+/* Blocks until all work the library enqueued on `stream` has finished. */
+pfx_status pfx_sync(pfx_ctx *ctx, void *stream);
+
+/* ---------------------------------------------------------- scientist side */
+/* Secret key from its N coefficients in {-1, 0, 1} (Sec. 2.3). */
+pfx_status pfx_sk_create(pfx_ctx *ctx, const int8_t *s, pfx_sk **out);
+void pfx_sk_destroy(pfx_sk *sk);
+
+/*
+ * Switching key (Sec. 2.4.1 SwitchKeyGen): for each digit j < beta,
+ *   swk_j = (-a_j s + e_j + P w_j s_from, a_j)  over all n_q + n_p primes,
+ * w_j the CRT idempotent of digit j over the full Q.  galois = 0 builds the
+ * relinearisation key (s_from = s^2, App. A.2); an odd galois element g < 2N
+ * builds the key for phi_g (s_from = phi_g(s)), used by rotation (g = 5^k mod
+ * 2N rotates slots left by k, App. A.1) and conjugation (g = 2N - 1).
+ *   a: beta * (n_q + n_p) * N words, [j][prime][coefficient], each < its prime.
+ *   e: beta * N integers, [j][coefficient].
+ */
+pfx_status pfx_swk_create(pfx_ctx *ctx, const pfx_sk *sk, uint32_t galois, const uint64_t *a,
+                          const int64_t *e, pfx_swk **out);
+/* Words [j][t][prime][coefficient], t = 0 for the b part, 1 for a. */
+pfx_status pfx_swk_export(pfx_ctx *ctx, const pfx_swk *k, uint64_t *words, size_t cap_words);
+uint32_t pfx_swk_galois(const pfx_swk *k);
+void pfx_swk_destroy(pfx_swk *k);
+
+/* Slot encoding (App. A.1): n_slots (power of two, <= N/2) complex values
+ * (im may be NULL) -> round(scale * tau^-1(z)) at n_limbs limbs.  Rounding
+ * is half away from zero. */
+pfx_status pfx_encode(pfx_ctx *ctx, const double *re, const double *im, size_t n_slots,
+                      uint32_t n_limbs, double scale, pfx_pt **out);
+/* Inverse of pfx_encode on the centred CRT lift of the plaintext. */
+pfx_status pfx_decode(pfx_ctx *ctx, const pfx_pt *pt, double *re, double *im, size_t n_slots);
+pfx_status pfx_pt_import(pfx_ctx *ctx, const uint64_t *words, uint32_t n_limbs, double scale,
+                         pfx_pt **out);
+
+/* (c0, c1) = (-a s + e + m, a) at the plaintext's level (Sec. 2.3).
+ * a: n_limbs * N words; e: N integers.  `out` needs capacity >= n_limbs. */
+pfx_status pfx_encrypt(pfx_ctx *ctx, const pfx_sk *sk, const pfx_pt *pt, const uint64_t *a,
+                       const int64_t *e, pfx_ct *out, void *stream);
+/* m + e = c0 + c1 s (+ c2 s^2) into a new plaintext. */
+pfx_status pfx_decrypt(pfx_ctx *ctx, const pfx_sk *sk, const pfx_ct *ct, pfx_pt **out,
+                       void *stream);
+
+/* ----------------------------------------------------------- ciphertexts */
+/* Device ciphertext with room for cap_limbs limbs and cap_degree + 1
+ * polynomials (cap_degree 0 = plaintext).  Starts at degree 0, 0 limbs. */
+pfx_status pfx_ct_create(pfx_ctx *ctx, uint32_t cap_limbs, uint32_t cap_degree, pfx_ct **out);
+void pfx_ct_destroy(pfx_ct *ct);
+pfx_status pfx_ct_info(const pfx_ct *ct, pfx_info *info);
+pfx_status pfx_ct_set_scale(pfx_ct *ct, double scale);
+/* Import canonical words (layout above) of a degree-`degree` ciphertext. */
+pfx_status pfx_ct_import(pfx_ctx *ctx, const uint64_t *words, uint32_t n_limbs, uint32_t degree,
+                         double scale, pfx_ct *out, void *stream);
+/* Export to canonical words; cap_words >= (degree + 1) * n_limbs * N.
+ * Synchronises `stream`. */
+pfx_status pfx_ct_export(pfx_ctx *ctx, const pfx_ct *ct, uint64_t *words, size_t cap_words,
+                         pfx_info *info, void *stream);
+pfx_status pfx_ct_copy(pfx_ctx *ctx, const pfx_ct *src, pfx_ct *dst, void *stream);
+
+/* ------------------------------------------------------ database owner side */
+/* Binary operands at different levels: the higher one's extra limbs are
+ * dropped (exact).  Additions need scales within 2^-10 relative (PFX_ESCALE
+ * otherwise); the result carries the first operand's scale. */
+pfx_status pfx_add(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, void *stream);
+pfx_status pfx_sub(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, void *stream);
+pfx_status pfx_neg(pfx_ctx *ctx, const pfx_ct *a, pfx_ct *out, void *stream);
+pfx_status pfx_add_plain(pfx_ctx *ctx, const pfx_ct *a, const pfx_pt *m, pfx_ct *out, void *stream);
+/* Slot-wise product with a plaintext (App. A.1); scale multiplies. */
+pfx_status pfx_mul_plain(pfx_ctx *ctx, const pfx_ct *a, const pfx_pt *m, pfx_ct *out, void *stream);
+/* Product with an integer; the scale is unchanged. */
+pfx_status pfx_mul_int(pfx_ctx *ctx, const pfx_ct *a, int64_t k, pfx_ct *out, void *stream);
+/* Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1): degree-2 result. */
+pfx_status pfx_mul(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, void *stream);
+/* Relinearisation (App. A.2): (d0, d1) + SwitchKey(d2, swk_{s^2 -> s}). */
+pfx_status pfx_relinearize(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *rlk, pfx_ct *out,
+                           void *stream);
+/* HMult + relinearisation in one call. */
+pfx_status pfx_mul_relin(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk,
+                         pfx_ct *out, void *stream);
+/* Rescale (Sec. 2.5): round(c / q_last) with round-half-up of the [0, Q)
+ * lift; one limb fewer; scale / q_last.  PFX_ELEVEL below 2 limbs. */
+pfx_status pfx_rescale(pfx_ctx *ctx, const pfx_ct *a, pfx_ct *out, void *stream);
+/* Keep the first n_limbs limbs (exact modulus switch to Q_{n_limbs}). */
+pfx_status pfx_drop_level(pfx_ctx *ctx, const pfx_ct *a, uint32_t n_limbs, pfx_ct *out,
+                          void *stream);
+/* SwitchKey(d, swk) of the first polynomial of d (Sec. 2.4.1): out = (k0, k1)
+ * with k0 + k1 s ~ d s_from. */
+pfx_status pfx_key_switch(pfx_ctx *ctx, const pfx_ct *d, const pfx_swk *k, pfx_ct *out,
+                          void *stream);
+/* Automorphism phi_g with key switching back to s (Sec. 2.4.2, App. A.2):
+ * g is the key's Galois element. */
+pfx_status pfx_apply_galois(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *gk, pfx_ct *out,
+                            void *stream);
+/* Rotate slots left by `step` (App. A.1); the key for 5^step mod 2N must be
+ * among keys[0..n_keys) (PFX_ENOKEY otherwise). */
+pfx_status pfx_rotate(pfx_ctx *ctx, const pfx_ct *a, int32_t step, const pfx_swk *const *keys,
+                      size_t n_keys, pfx_ct *out, void *stream);
+pfx_status pfx_conjugate(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *const *keys, size_t n_keys,
+                         pfx_ct *out, void *stream);
+/* InnerSum (Alg. 2, last step): x <- x + rot(x, 2^k) for k < log_steps. */
+pfx_status pfx_rotate_sum(pfx_ctx *ctx, const pfx_ct *a, uint32_t log_steps,
+                          const pfx_swk *const *keys, size_t n_keys, pfx_ct *out, void *stream);
+
+/* Standalone negacyclic NTT on device words (canonical residues), in place:
+ * d_words holds `batch` blocks of n_limbs limbs of N words; limb i of every
+ * block uses prime first_prime + i (prime index: q's then p's).  Output order
+ * is NTT(a)[j] = sum_k a_k psi^(k (2 bitrev(j) + 1)); inverse = 1 undoes it. */
+pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32_t n_limbs,
+                   size_t batch, int inverse, void *stream);
+
+/* ------------------------------------------------------------ plumbing */
+/* Device memory and streams for callers that hold raw words (pfx_ntt).  The
+ * library links the system HIP runtime; a process should not load a second
+ * HIP runtime beside it (PyTorch wheels bundle their own), so these cover what
+ * such a caller would otherwise take from a framework. */
+pfx_status pfx_dev_alloc(pfx_ctx *ctx, size_t bytes, void **out);
+pfx_status pfx_dev_free(pfx_ctx *ctx, void *p);
+pfx_status pfx_memcpy_htod(pfx_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream);
+pfx_status pfx_memcpy_dtoh(pfx_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream);
+/* Streams at the default priority. */
+pfx_status pfx_stream_create(pfx_ctx *ctx, void **out);
+pfx_status pfx_stream_destroy(pfx_ctx *ctx, void *stream);
+
+/* ------------------------------------------------------------ profiling */
+/* When on, the library brackets each kernel launch with HIP events on the
+ * stream it launches on and accumulates per-kernel device time. */
+pfx_status pfx_profile_enable(pfx_ctx *ctx, int on);
+/* Completed launches and their summed device time (ms) for a kernel name
+ * (see pfx_profile_names); synchronises pending events. */
+pfx_status pfx_profile_get(pfx_ctx *ctx, const char *kernel, uint64_t *launches, double *total_ms);
+/* Newline-separated kernel names seen so far. */
+pfx_status pfx_profile_names(pfx_ctx *ctx, char *buf, size_t cap);
+pfx_status pfx_profile_reset(pfx_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFX_H */

@@ -326,7 +326,9 @@ def automorphism(a, g, mods, logn) -> np.ndarray:
 
 
 def crt_centered(words: np.ndarray, mods) -> np.ndarray:
-    """Centred integers in [-Q/2, Q/2) from residues (object array of ints)."""
+    """Centred integers in [-(Q-1)/2, (Q-1)/2] from residues (object array of
+    ints).  Sec. 2.2 centres coefficients around 0; Q is odd, so the symmetric
+    range holds exactly one lift of every residue."""
     mods = [int(m) for m in mods]
     Q = math.prod(mods)
     acc = np.zeros(words.shape[1], dtype=object)
@@ -335,7 +337,7 @@ def crt_centered(words: np.ndarray, mods) -> np.ndarray:
         acc = acc + words[i].astype(object) * (Qi * pow(Qi, -1, q))
     acc = acc % Q
     half = Q // 2
-    return np.where(acc >= half, acc - Q, acc)
+    return np.where(acc > half, acc - Q, acc)
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,1193 @@
+// C-ABI of libpfx: argument checks, host-side constants, and the sequence of
+// device launches behind each call.  The kernels are in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace pfx;
+
+namespace pfx {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+pfx_status fail(pfx_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+}  // namespace pfx
+
+#define HIPCHECK(x)                                                                          \
+    do {                                                                                     \
+        hipError_t e_ = (x);                                                                 \
+        if (e_ != hipSuccess) return fail(PFX_EDEVICE, std::string(#x ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define REQUIRE(cond, code, msg) \
+    do {                         \
+        if (!(cond)) return fail(code, msg); \
+    } while (0)
+
+namespace {
+
+unsigned bitrev(unsigned x, int bits) {
+    unsigned r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+    return r;
+}
+
+double2 shoup_pair(uint64_t w, uint64_t q) { return make_double2((double)w, (double)w / (double)q); }
+
+hipStream_t S(void *stream) { return (hipStream_t)stream; }
+
+// Scratch of one stream, sized for the top level.
+struct WsLayout {
+    size_t dcoef, ext, acc, mdtmp, t3, rs_last, rs_tmp, xport, total;
+};
+
+WsLayout ws_layout(const pfx_ctx *c) {
+    const size_t N = c->N, L = c->L, K = c->K, E = L + K;
+    WsLayout w;
+    size_t o = 0;
+    w.dcoef = o; o += L * N;
+    w.ext = o; o += (size_t)c->beta * E * N;
+    w.acc = o; o += 2 * E * N;
+    w.mdtmp = o; o += 2 * L * N;
+    w.t3 = o; o += 3 * L * N;
+    w.rs_last = o; o += 3 * N;
+    w.rs_tmp = o; o += 3 * L * N;
+    w.xport = o; o += std::max<size_t>(3 * L, (size_t)E) * N;   // u64 staging (same word size)
+    w.total = o;
+    return w;
+}
+
+struct Ws {
+    double *base;
+    WsLayout lay;
+    double *at(size_t off) const { return base + off; }
+};
+
+pfx_status get_ws(pfx_ctx *c, hipStream_t st, Ws &out) {
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->ws.find(st);
+    if (it == c->ws.end()) {
+        Workspace *w = new Workspace;
+        w->stream = st;
+        WsLayout lay = ws_layout(c);
+        w->doubles = lay.total;
+        if (hipMalloc(&w->buf, lay.total * sizeof(double)) != hipSuccess) {
+            delete w;
+            return fail(PFX_ENOMEM, "workspace allocation failed");
+        }
+        it = c->ws.emplace(st, w).first;
+    }
+    out.base = it->second->buf;
+    out.lay = ws_layout(c);
+    return PFX_OK;
+}
+
+LimbMap contiguous_map(int n, int pid0, int off0 = 0) {
+    LimbMap m;
+    m.n = n;
+    for (int i = 0; i < n; ++i) {
+        m.off[i] = off0 + i;
+        m.pid[i] = (int16_t)(pid0 + i);
+    }
+    return m;
+}
+
+// limbs [0, lv) of npoly polynomials spaced `stride_limbs` apart
+LimbMap poly_map(int npoly, int lv, int stride_limbs) {
+    LimbMap m;
+    m.n = npoly * lv;
+    for (int k = 0; k < npoly; ++k)
+        for (int i = 0; i < lv; ++i) {
+            m.off[k * lv + i] = k * stride_limbs + i;
+            m.pid[k * lv + i] = (int16_t)i;
+        }
+    return m;
+}
+
+bool scale_close(double a, double b) { return std::fabs(a / b - 1.0) <= std::ldexp(1.0, -10); }
+
+pfx_status check_ct(const pfx_ctx *c, const pfx_ct *x, const char *what) {
+    if (!x) return fail(PFX_EINVAL, std::string(what) + " is null");
+    if (x->ctx != c) return fail(PFX_EINVAL, std::string(what) + " belongs to another context");
+    if (x->n_limbs == 0) return fail(PFX_EINVAL, std::string(what) + " is empty");
+    return PFX_OK;
+}
+
+pfx_status check_out(const pfx_ct *o, uint32_t lv, uint32_t deg) {
+    if (!o) return fail(PFX_EINVAL, "output is null");
+    if (o->cap_limbs < lv || o->cap_degree < deg) return fail(PFX_EINVAL, "output capacity too small");
+    return PFX_OK;
+}
+
+// Key switching of the lv-limb NTT-domain polynomial d (Sec. 2.4.1):
+// out_u = ModDown(sum_j ModUp_j(d) * swk_{j,u}) (+ base_u).
+void ks_core(pfx_ctx *c, const Launch &L, const Ws &w, const double *d, int lv, const pfx_swk *key, double *out0,
+             double *out1, const double *base0, const double *base1) {
+    const int E = lv + c->K;
+    const int beta = (lv + c->alpha - 1) / c->alpha;
+    double *dcoef = w.at(w.lay.dcoef), *ext = w.at(w.lay.ext), *acc = w.at(w.lay.acc), *tmp = w.at(w.lay.mdtmp);
+    launch_ntt(L, dcoef, d, contiguous_map(lv, 0), true);
+    launch_modup(L, ext, dcoef, lv);
+    LimbMap m;
+    m.n = 0;
+    for (int j = 0; j < beta; ++j) {
+        const int sz = std::min(c->alpha, lv - j * c->alpha);
+        for (int t = 0; t < E - sz; ++t) {
+            int pid = t < j * c->alpha ? t : (t < lv - sz ? t + sz : c->L + (t - (lv - sz)));
+            m.off[m.n] = j * E + t;
+            m.pid[m.n] = (int16_t)pid;
+            ++m.n;
+            if (m.n == kMaxMapLimbs) {
+                launch_ntt(L, ext, nullptr, m, false);
+                m.n = 0;
+            }
+        }
+    }
+    launch_ntt(L, ext, nullptr, m, false);
+    launch_ks_inner(L, acc, ext, d, key->d_k, lv);
+    LimbMap pm;
+    pm.n = 2 * c->K;
+    for (int u = 0; u < 2; ++u)
+        for (int k = 0; k < c->K; ++k) {
+            pm.off[u * c->K + k] = u * E + lv + k;
+            pm.pid[u * c->K + k] = (int16_t)(c->L + k);
+        }
+    launch_ntt(L, acc, nullptr, pm, true);
+    launch_moddown_conv(L, tmp, acc, lv);
+    launch_ntt(L, tmp, nullptr, poly_map(2, lv, lv), false);
+    launch_moddown_final(L, out0, out1, acc, tmp, base0, base1, lv);
+}
+
+pfx_swk *find_key(pfx_ctx *c, uint32_t g, const pfx_swk *const *keys, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (keys[i] && keys[i]->ctx == c && keys[i]->galois == g) return const_cast<pfx_swk *>(keys[i]);
+    return nullptr;
+}
+
+pfx_status galois_apply(pfx_ctx *c, const pfx_ct *a, const pfx_swk *gk, pfx_ct *out, hipStream_t st) {
+    Ws w;
+    pfx_status r = get_ws(c, st, w);
+    if (r) return r;
+    const int lv = a->n_limbs;
+    Launch L{c, st};
+    double *t0 = w.at(w.lay.t3), *t1 = t0 + (size_t)c->L * c->N;
+    launch_automorph(L, t0, a->poly(0), (size_t)c->L * c->N, (size_t)a->cap_limbs * c->N, 2, lv, gk->galois);
+    ks_core(c, L, w, t1, lv, gk, out->poly(0), out->poly(1), t0, nullptr);
+    out->n_limbs = lv;
+    out->degree = 1;
+    out->scale = a->scale;
+    return PFX_OK;
+}
+
+uint32_t rot_element(const pfx_ctx *c, int64_t step) {
+    const int64_t half = c->N / 2;
+    int64_t s = ((step % half) + half) % half;
+    return (uint32_t)powmod_u64(5, (uint64_t)s, 2ull * c->N);
+}
+
+}  // namespace
+
+// ======================================================================= API
+extern "C" {
+
+const char *pfx_status_str(pfx_status s) {
+    switch (s) {
+        case PFX_OK: return "ok";
+        case PFX_EINVAL: return "invalid argument";
+        case PFX_EPARAM: return "unsupported parameters";
+        case PFX_ELEVEL: return "not enough limbs";
+        case PFX_ESCALE: return "scale mismatch";
+        case PFX_ENOKEY: return "missing key";
+        case PFX_ENOMEM: return "out of memory";
+        case PFX_EBUSY: return "busy";
+        case PFX_EDEVICE: return "device error";
+        default: return "unknown status";
+    }
+}
+
+const char *pfx_last_error(void) { return g_err.c_str(); }
+
+pfx_status pfx_params_primes(const pfx_params *prm, uint64_t *q, uint64_t *p, uint64_t *psi) {
+    std::vector<uint64_t> vq, vp, vpsi;
+    std::string err;
+    if (!build_primes(prm, vq, vp, vpsi, err)) return fail(PFX_EPARAM, err);
+    if (q) std::copy(vq.begin(), vq.end(), q);
+    if (p) std::copy(vp.begin(), vp.end(), p);
+    if (psi) std::copy(vpsi.begin(), vpsi.end(), psi);
+    return PFX_OK;
+}
+
+pfx_status pfx_encode_words(const pfx_params *prm, const double *re, const double *im, size_t n, uint32_t n_limbs,
+                            double scale, uint64_t *words) {
+    REQUIRE(re && words, PFX_EINVAL, "null argument");
+    std::vector<uint64_t> q, p, psi, out;
+    std::string err;
+    if (!build_primes(prm, q, p, psi, err)) return fail(PFX_EPARAM, err);
+    REQUIRE(n_limbs >= 1 && n_limbs <= q.size(), PFX_EINVAL, "n_limbs out of range");
+    REQUIRE(scale > 0 && std::isfinite(scale), PFX_EINVAL, "bad scale");
+    std::vector<uint64_t> mods(q.begin(), q.begin() + n_limbs);
+    if (!encode_coeffs(prm->log_n, re, im, n, scale, mods, out, err)) return fail(PFX_EINVAL, err);
+    std::copy(out.begin(), out.end(), words);
+    return PFX_OK;
+}
+
+pfx_status pfx_decode_words(const pfx_params *prm, const uint64_t *words, uint32_t n_limbs, double scale, double *re,
+                            double *im, size_t n) {
+    REQUIRE(re && words, PFX_EINVAL, "null argument");
+    std::vector<uint64_t> q, p, psi;
+    std::string err;
+    if (!build_primes(prm, q, p, psi, err)) return fail(PFX_EPARAM, err);
+    REQUIRE(n_limbs >= 1 && n_limbs <= q.size(), PFX_EINVAL, "n_limbs out of range");
+    const size_t N = (size_t)1 << prm->log_n;
+    REQUIRE(n >= 1 && !(n & (n - 1)) && n <= N / 2, PFX_EINVAL, "n_slots must be a power of two <= N/2");
+    for (size_t i = 0; i < (size_t)n_limbs * N; ++i) REQUIRE(words[i] < q[i / N], PFX_EINVAL, "word not below its prime");
+    std::vector<uint64_t> mods(q.begin(), q.begin() + n_limbs);
+    decode_words(prm->log_n, words, n_limbs, mods, scale, n, re, im);
+    return PFX_OK;
+}
+
+pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
+    REQUIRE(out, PFX_EINVAL, "out is null");
+    std::vector<uint64_t> q, p, psi;
+    std::string err;
+    if (!build_primes(prm, q, p, psi, err)) return fail(PFX_EPARAM, err);
+    REQUIRE(prm->n_p <= 8, PFX_EPARAM, "at most 8 special primes");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0)
+        return fail(PFX_EDEVICE, "no such HIP device");
+    HIPCHECK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIPCHECK(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(PFX_EDEVICE, std::string("libpfx is built for gfx950, device is ") + prop.gcnArchName);
+
+    std::unique_ptr<pfx_ctx> c(new pfx_ctx);
+    c->device = device;
+    c->logn = prm->log_n;
+    c->N = 1 << prm->log_n;
+    c->L = prm->n_q;
+    c->K = prm->n_p;
+    c->alpha = prm->alpha;
+    c->beta = (c->L + c->alpha - 1) / c->alpha;
+    c->mod_log2 = prm->mod_log2 ? prm->mod_log2 : prm->log_n + 1;
+    c->primes = q;
+    c->primes.insert(c->primes.end(), p.begin(), p.end());
+    c->psi = psi;
+    const int NP = c->L + c->K;
+    const size_t N = c->N;
+
+    // twiddles: tw[k] = psi^bitrev(k), itw[k] = psi^-bitrev(k), with their fl(w/q)
+    std::vector<double2> tw((size_t)2 * NP * N);
+    std::vector<uint64_t> pw(N), ipw(N);
+    for (int m = 0; m < NP; ++m) {
+        const uint64_t qq = c->primes[m];
+        const uint64_t ps = psi[m], ips = invmod_u64(ps, qq);
+        pw[0] = ipw[0] = 1;
+        for (size_t i = 1; i < N; ++i) {
+            pw[i] = mulmod_u64(pw[i - 1], ps, qq);
+            ipw[i] = mulmod_u64(ipw[i - 1], ips, qq);
+        }
+        for (size_t k = 0; k < N; ++k) {
+            const unsigned b = bitrev((unsigned)k, c->logn);
+            tw[(2 * (size_t)m) * N + k] = shoup_pair(pw[b], qq);
+            tw[(2 * (size_t)m + 1) * N + k] = shoup_pair(ipw[b], qq);
+        }
+    }
+    HIPCHECK(hipMalloc(&c->d_tw, tw.size() * sizeof(double2)));
+    HIPCHECK(hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
+    c->h_primes.resize(NP);
+    for (int m = 0; m < NP; ++m) {
+        const uint64_t qq = c->primes[m];
+        PrimeDev &d = c->h_primes[m];
+        d.q = (double)qq;
+        d.qinv = 1.0 / (double)qq;
+        const uint64_t ninv = invmod_u64(N % qq, qq);
+        d.ninv = (double)ninv;
+        d.ninv_q = (double)ninv / (double)qq;
+        const uint64_t w1 = mulmod_u64(ninv, powmod_u64(invmod_u64(psi[m], qq), N / 2, qq), qq);
+        d.ninv_w1 = (double)w1;
+        d.ninv_w1_q = (double)w1 / (double)qq;
+        d.tw = c->d_tw + (2 * (size_t)m) * N;
+        d.itw = c->d_tw + (2 * (size_t)m + 1) * N;
+    }
+    HIPCHECK(hipMalloc(&c->d_primes, NP * sizeof(PrimeDev)));
+    HIPCHECK(hipMemcpy(c->d_primes, c->h_primes.data(), NP * sizeof(PrimeDev), hipMemcpyHostToDevice));
+
+    // ModUp: for digit j with sz active primes D = {alpha j, ..., alpha j + sz - 1}
+    std::vector<ModUpConst> mu((size_t)c->beta * c->alpha);
+    std::memset(mu.data(), 0, mu.size() * sizeof(ModUpConst));
+    for (int j = 0; j < c->beta; ++j)
+        for (int sz = 1; sz <= c->alpha; ++sz) {
+            const int j0 = j * c->alpha;
+            if (j0 + sz > c->L) continue;
+            ModUpConst &x = mu[(size_t)j * c->alpha + (sz - 1)];
+            for (int i = 0; i < sz; ++i) {
+                const uint64_t qi = c->primes[j0 + i];
+                uint64_t prod = 1;   // (Q'/q_i) mod q_i
+                for (int i2 = 0; i2 < sz; ++i2)
+                    if (i2 != i) prod = mulmod_u64(prod, c->primes[j0 + i2] % qi, qi);
+                x.inv[i] = shoup_pair(invmod_u64(prod, qi), qi);
+                for (int m = 0; m < NP; ++m) {
+                    const uint64_t qm = c->primes[m];
+                    uint64_t h = 1;
+                    for (int i2 = 0; i2 < sz; ++i2)
+                        if (i2 != i) h = mulmod_u64(h, c->primes[j0 + i2] % qm, qm);
+                    x.hat[i][m] = shoup_pair(h, qm);
+                }
+            }
+        }
+    HIPCHECK(hipMalloc(&c->d_modup, mu.size() * sizeof(ModUpConst)));
+    HIPCHECK(hipMemcpy(c->d_modup, mu.data(), mu.size() * sizeof(ModUpConst), hipMemcpyHostToDevice));
+
+    // ModDown and key-generation constants
+    std::unique_ptr<ModDownConst> md(new ModDownConst);
+    std::memset(md.get(), 0, sizeof(ModDownConst));
+    for (int k = 0; k < c->K; ++k) {
+        const uint64_t pk = c->primes[c->L + k];
+        uint64_t prod = 1;
+        for (int k2 = 0; k2 < c->K; ++k2)
+            if (k2 != k) prod = mulmod_u64(prod, c->primes[c->L + k2] % pk, pk);
+        md->phat_inv[k] = shoup_pair(invmod_u64(prod, pk), pk);
+        for (int i = 0; i < c->L; ++i) {
+            const uint64_t qi = c->primes[i];
+            uint64_t h = 1;
+            for (int k2 = 0; k2 < c->K; ++k2)
+                if (k2 != k) h = mulmod_u64(h, c->primes[c->L + k2] % qi, qi);
+            md->phat[k][i] = shoup_pair(h, qi);
+        }
+    }
+    for (int m = 0; m < NP; ++m) {
+        const uint64_t qm = c->primes[m];
+        uint64_t pmod = 1;
+        for (int k = 0; k < c->K; ++k) pmod = mulmod_u64(pmod, c->primes[c->L + k] % qm, qm);
+        // floor(P/2) = (P - 1)/2 for odd P
+        const uint64_t half = mulmod_u64((pmod + qm - 1) % qm, invmod_u64(2, qm), qm);
+        md->half[m] = (double)half;
+        if (m < c->L) {
+            md->pinv[m] = shoup_pair(invmod_u64(pmod, qm), qm);
+            md->pmod[m] = shoup_pair(pmod, qm);
+        }
+    }
+    HIPCHECK(hipMalloc(&c->d_moddown, sizeof(ModDownConst)));
+    HIPCHECK(hipMemcpy(c->d_moddown, md.get(), sizeof(ModDownConst), hipMemcpyHostToDevice));
+
+    // Rescale: dropping prime l, for i < l
+    std::vector<RescaleConst> rc((size_t)PFX_MAX_PRIMES * PFX_MAX_PRIMES);
+    std::memset(rc.data(), 0, rc.size() * sizeof(RescaleConst));
+    for (int l = 1; l < c->L; ++l)
+        for (int i = 0; i < l; ++i) {
+            const uint64_t qi = c->primes[i], ql = c->primes[l];
+            RescaleConst &r = rc[(size_t)l * PFX_MAX_PRIMES + i];
+            r.inv = shoup_pair(invmod_u64(ql % qi, qi), qi);
+            r.half = (double)((ql / 2) % qi);
+        }
+    HIPCHECK(hipMalloc(&c->d_rescale, rc.size() * sizeof(RescaleConst)));
+    HIPCHECK(hipMemcpy(c->d_rescale, rc.data(), rc.size() * sizeof(RescaleConst), hipMemcpyHostToDevice));
+    *out = c.release();
+    return PFX_OK;
+}
+
+void pfx_ctx_destroy(pfx_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (auto &kv : c->ws) {
+        hipFree(kv.second->buf);
+        delete kv.second;
+    }
+    for (auto &e : c->prof_pending) {
+        hipEventDestroy(e.start);
+        hipEventDestroy(e.stop);
+    }
+    hipFree(c->d_tw);
+    hipFree(c->d_primes);
+    hipFree(c->d_modup);
+    hipFree(c->d_moddown);
+    hipFree(c->d_rescale);
+    delete c;
+}
+
+pfx_status pfx_ctx_moduli(const pfx_ctx *c, uint64_t *q, uint64_t *p, uint64_t *psi) {
+    REQUIRE(c, PFX_EINVAL, "null context");
+    if (q) std::copy(c->primes.begin(), c->primes.begin() + c->L, q);
+    if (p) std::copy(c->primes.begin() + c->L, c->primes.end(), p);
+    if (psi) std::copy(c->psi.begin(), c->psi.end(), psi);
+    return PFX_OK;
+}
+
+pfx_status pfx_sync(pfx_ctx *c, void *stream) {
+    REQUIRE(c, PFX_EINVAL, "null context");
+    HIPCHECK(hipStreamSynchronize(S(stream)));
+    return PFX_OK;
+}
+
+// ------------------------------------------------------------------ keys
+pfx_status pfx_sk_create(pfx_ctx *c, const int8_t *s, pfx_sk **out) {
+    REQUIRE(c && s && out, PFX_EINVAL, "null argument");
+    for (int i = 0; i < c->N; ++i) REQUIRE(s[i] >= -1 && s[i] <= 1, PFX_EINVAL, "secret coefficients must be -1, 0 or 1");
+    HIPCHECK(hipSetDevice(c->device));
+    const int NP = c->L + c->K;
+    std::unique_ptr<pfx_sk> k(new pfx_sk);
+    k->ctx = c;
+    k->h_s.assign(s, s + c->N);
+    HIPCHECK(hipMalloc(&k->d_s, (size_t)NP * c->N * sizeof(double)));
+    int8_t *tmp = nullptr;
+    HIPCHECK(hipMalloc(&tmp, c->N));
+    HIPCHECK(hipMemcpy(tmp, s, c->N, hipMemcpyHostToDevice));
+    Launch L{c, nullptr};
+    launch_s8_to_rns(L, k->d_s, tmp, NP);
+    launch_ntt(L, k->d_s, nullptr, contiguous_map(NP, 0), false);
+    HIPCHECK(hipStreamSynchronize(nullptr));
+    hipFree(tmp);
+    *out = k.release();
+    return PFX_OK;
+}
+
+void pfx_sk_destroy(pfx_sk *k) {
+    if (!k) return;
+    hipFree(k->d_s);
+    delete k;
+}
+
+pfx_status pfx_swk_create(pfx_ctx *c, const pfx_sk *sk, uint32_t galois, const uint64_t *a, const int64_t *e,
+                          pfx_swk **out) {
+    REQUIRE(c && sk && a && e && out, PFX_EINVAL, "null argument");
+    REQUIRE(sk->ctx == c, PFX_EINVAL, "secret key of another context");
+    REQUIRE(galois == 0 || ((galois & 1) && galois < 2u * c->N), PFX_EINVAL, "galois must be 0 or odd < 2N");
+    const int NP = c->L + c->K;
+    const size_t N = c->N, limb = N;
+    for (int j = 0; j < c->beta; ++j)
+        for (int m = 0; m < NP; ++m)
+            for (size_t i = 0; i < N; ++i)
+                REQUIRE(a[((size_t)j * NP + m) * N + i] < c->primes[m], PFX_EINVAL, "a word not below its prime");
+    for (size_t i = 0; i < (size_t)c->beta * N; ++i)
+        REQUIRE(e[i] > -(1ll << 40) && e[i] < (1ll << 40), PFX_EINVAL, "error coefficient too large");
+    HIPCHECK(hipSetDevice(c->device));
+    std::unique_ptr<pfx_swk> k(new pfx_swk);
+    k->ctx = c;
+    k->galois = galois;
+    HIPCHECK(hipMalloc(&k->d_k, (size_t)c->beta * 2 * NP * limb * sizeof(double)));
+    double *sfrom = nullptr, *etmp = nullptr;
+    uint64_t *stage = nullptr;
+    int64_t *edev = nullptr;
+    HIPCHECK(hipMalloc(&sfrom, (size_t)NP * limb * sizeof(double)));
+    HIPCHECK(hipMalloc(&etmp, (size_t)NP * limb * sizeof(double)));
+    HIPCHECK(hipMalloc(&stage, (size_t)NP * limb * sizeof(uint64_t)));
+    HIPCHECK(hipMalloc(&edev, N * sizeof(int64_t)));
+    Launch L{c, nullptr};
+    if (galois == 0) launch_ew(L, EW_MUL, sfrom, sk->d_s, sk->d_s, 0, 0, 0, 1, NP);
+    else launch_automorph(L, sfrom, sk->d_s, 0, 0, 1, NP, galois);
+    for (int j = 0; j < c->beta; ++j) {
+        double *b = k->d_k + (size_t)(2 * j) * NP * limb;
+        double *aa = k->d_k + (size_t)(2 * j + 1) * NP * limb;
+        HIPCHECK(hipMemcpy(stage, a + (size_t)j * NP * N, (size_t)NP * N * sizeof(uint64_t), hipMemcpyHostToDevice));
+        launch_u64_to_f64(L, aa, stage, (size_t)NP * N);
+        launch_ntt(L, aa, nullptr, contiguous_map(NP, 0), false);
+        HIPCHECK(hipMemcpy(edev, e + (size_t)j * N, N * sizeof(int64_t), hipMemcpyHostToDevice));
+        launch_int_to_rns(L, etmp, edev, NP, 0, 0, 0);
+        launch_ntt(L, etmp, nullptr, contiguous_map(NP, 0), false);
+        launch_keygen_b(L, b, aa, etmp, sk->d_s, sfrom, j);
+        HIPCHECK(hipStreamSynchronize(nullptr));
+    }
+    hipFree(sfrom);
+    hipFree(etmp);
+    hipFree(stage);
+    hipFree(edev);
+    *out = k.release();
+    return PFX_OK;
+}
+
+pfx_status pfx_swk_export(pfx_ctx *c, const pfx_swk *k, uint64_t *words, size_t cap) {
+    REQUIRE(c && k && words, PFX_EINVAL, "null argument");
+    const int NP = c->L + c->K;
+    const size_t per = (size_t)NP * c->N;
+    REQUIRE(cap >= (size_t)c->beta * 2 * per, PFX_EINVAL, "cap_words too small");
+    HIPCHECK(hipSetDevice(c->device));
+    double *tmp = nullptr;
+    uint64_t *u = nullptr;
+    HIPCHECK(hipMalloc(&tmp, per * sizeof(double)));
+    HIPCHECK(hipMalloc(&u, per * sizeof(uint64_t)));
+    Launch L{c, nullptr};
+    for (int p = 0; p < 2 * c->beta; ++p) {
+        launch_ntt(L, tmp, k->d_k + (size_t)p * per, contiguous_map(NP, 0), true);
+        launch_f64_to_u64(L, u, tmp, per);
+        HIPCHECK(hipMemcpy(words + (size_t)p * per, u, per * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    }
+    hipFree(tmp);
+    hipFree(u);
+    return PFX_OK;
+}
+
+uint32_t pfx_swk_galois(const pfx_swk *k) { return k ? k->galois : 0; }
+
+void pfx_swk_destroy(pfx_swk *k) {
+    if (!k) return;
+    hipFree(k->d_k);
+    delete k;
+}
+
+// ------------------------------------------------------------------ ciphertext objects
+pfx_status pfx_ct_create(pfx_ctx *c, uint32_t cap_limbs, uint32_t cap_degree, pfx_ct **out) {
+    REQUIRE(c && out, PFX_EINVAL, "null argument");
+    REQUIRE(cap_limbs >= 1 && cap_limbs <= (uint32_t)c->L, PFX_EINVAL, "cap_limbs must be in [1, n_q]");
+    REQUIRE(cap_degree <= 2, PFX_EINVAL, "cap_degree must be 0, 1 or 2");
+    HIPCHECK(hipSetDevice(c->device));
+    std::unique_ptr<pfx_ct> x(new pfx_ct);
+    x->ctx = c;
+    x->cap_limbs = cap_limbs;
+    x->cap_degree = cap_degree;
+    if (hipMalloc(&x->d, (size_t)(cap_degree + 1) * cap_limbs * c->N * sizeof(double)) != hipSuccess)
+        return fail(PFX_ENOMEM, "ciphertext allocation failed");
+    *out = x.release();
+    return PFX_OK;
+}
+
+void pfx_ct_destroy(pfx_ct *x) {
+    if (!x) return;
+    hipFree(x->d);
+    delete x;
+}
+
+pfx_status pfx_ct_info(const pfx_ct *x, pfx_info *info) {
+    REQUIRE(x && info, PFX_EINVAL, "null argument");
+    info->log_n = x->ctx->logn;
+    info->n_limbs = x->n_limbs;
+    info->degree = x->degree;
+    info->scale = x->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_ct_set_scale(pfx_ct *x, double scale) {
+    REQUIRE(x && scale > 0 && std::isfinite(scale), PFX_EINVAL, "bad scale");
+    x->scale = scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_ct_import(pfx_ctx *c, const uint64_t *words, uint32_t n_limbs, uint32_t degree, double scale,
+                         pfx_ct *out, void *stream) {
+    REQUIRE(c && words && out, PFX_EINVAL, "null argument");
+    REQUIRE(n_limbs >= 1 && n_limbs <= (uint32_t)c->L, PFX_EINVAL, "n_limbs out of range");
+    REQUIRE(degree <= 2, PFX_EINVAL, "degree out of range");
+    pfx_status r = check_out(out, n_limbs, degree);
+    if (r) return r;
+    const size_t N = c->N;
+    for (uint32_t k = 0; k <= degree; ++k)
+        for (uint32_t i = 0; i < n_limbs; ++i)
+            for (size_t t = 0; t < N; ++t)
+                REQUIRE(words[((size_t)k * n_limbs + i) * N + t] < c->primes[i], PFX_EINVAL, "word not below its prime");
+    HIPCHECK(hipSetDevice(c->device));
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    uint64_t *stage = (uint64_t *)w.at(w.lay.xport);
+    for (uint32_t k = 0; k <= degree; ++k) {
+        HIPCHECK(hipMemcpyAsync(stage, words + (size_t)k * n_limbs * N, (size_t)n_limbs * N * sizeof(uint64_t),
+                                hipMemcpyHostToDevice, S(stream)));
+        launch_u64_to_f64(L, out->poly(k), stage, (size_t)n_limbs * N);
+    }
+    launch_ntt(L, out->d, nullptr, poly_map(degree + 1, n_limbs, out->cap_limbs), false);
+    HIPCHECK(hipStreamSynchronize(S(stream)));
+    out->n_limbs = n_limbs;
+    out->degree = degree;
+    out->scale = scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_ct_export(pfx_ctx *c, const pfx_ct *x, uint64_t *words, size_t cap, pfx_info *info, void *stream) {
+    REQUIRE(c && words, PFX_EINVAL, "null argument");
+    pfx_status r = check_ct(c, x, "ciphertext");
+    if (r) return r;
+    const size_t N = c->N, per = (size_t)x->n_limbs * N;
+    REQUIRE(cap >= (size_t)(x->degree + 1) * per, PFX_EINVAL, "cap_words too small");
+    HIPCHECK(hipSetDevice(c->device));
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    double *tmp = w.at(w.lay.rs_tmp);
+    uint64_t *stage = (uint64_t *)w.at(w.lay.xport);
+    for (uint32_t k = 0; k <= x->degree; ++k) {
+        launch_ntt(L, tmp, x->poly(k), contiguous_map(x->n_limbs, 0), true);
+        launch_f64_to_u64(L, stage, tmp, per);
+        HIPCHECK(hipMemcpyAsync(words + k * per, stage, per * sizeof(uint64_t), hipMemcpyDeviceToHost, S(stream)));
+        HIPCHECK(hipStreamSynchronize(S(stream)));
+    }
+    if (info) pfx_ct_info(x, info);
+    return PFX_OK;
+}
+
+pfx_status pfx_ct_copy(pfx_ctx *c, const pfx_ct *src, pfx_ct *dst, void *stream) {
+    pfx_status r = check_ct(c, src, "source");
+    if (r) return r;
+    r = check_out(dst, src->n_limbs, src->degree);
+    if (r) return r;
+    if (src != dst) {
+        Launch L{c, S(stream)};
+        const size_t N = c->N;
+        launch_ew(L, EW_COPY, dst->d, src->d, nullptr, dst->cap_limbs * N, src->cap_limbs * N, 0, src->degree + 1,
+                  src->n_limbs);
+    }
+    dst->n_limbs = src->n_limbs;
+    dst->degree = src->degree;
+    dst->scale = src->scale;
+    return PFX_OK;
+}
+
+// ------------------------------------------------------------------ encoding and encryption
+pfx_status pfx_pt_import(pfx_ctx *c, const uint64_t *words, uint32_t n_limbs, double scale, pfx_pt **out) {
+    REQUIRE(c && out, PFX_EINVAL, "null argument");
+    REQUIRE(n_limbs >= 1 && n_limbs <= (uint32_t)c->L, PFX_EINVAL, "n_limbs out of range");
+    pfx_ct *x = nullptr;
+    pfx_status r = pfx_ct_create(c, n_limbs, 0, &x);
+    if (r) return r;
+    r = pfx_ct_import(c, words, n_limbs, 0, scale, x, nullptr);
+    if (r) { pfx_ct_destroy(x); return r; }
+    *out = x;
+    return PFX_OK;
+}
+
+pfx_status pfx_encode(pfx_ctx *c, const double *re, const double *im, size_t n, uint32_t n_limbs, double scale,
+                      pfx_pt **out) {
+    REQUIRE(c && re && out, PFX_EINVAL, "null argument");
+    REQUIRE(n_limbs >= 1 && n_limbs <= (uint32_t)c->L, PFX_EINVAL, "n_limbs out of range");
+    REQUIRE(scale > 0 && std::isfinite(scale), PFX_EINVAL, "bad scale");
+    std::vector<uint64_t> mods(c->primes.begin(), c->primes.begin() + n_limbs), words;
+    std::string err;
+    if (!encode_coeffs(c->logn, re, im, n, scale, mods, words, err)) return fail(PFX_EINVAL, err);
+    return pfx_pt_import(c, words.data(), n_limbs, scale, out);
+}
+
+pfx_status pfx_decode(pfx_ctx *c, const pfx_pt *pt, double *re, double *im, size_t n) {
+    REQUIRE(c && re, PFX_EINVAL, "null argument");
+    pfx_status r = check_ct(c, pt, "plaintext");
+    if (r) return r;
+    REQUIRE(pt->degree == 0, PFX_EINVAL, "decode needs a plaintext (degree 0)");
+    REQUIRE(n >= 1 && !(n & (n - 1)) && n <= (size_t)c->N / 2, PFX_EINVAL, "n_slots must be a power of two <= N/2");
+    std::vector<uint64_t> words((size_t)pt->n_limbs * c->N);
+    r = pfx_ct_export(c, pt, words.data(), words.size(), nullptr, nullptr);
+    if (r) return r;
+    std::vector<uint64_t> mods(c->primes.begin(), c->primes.begin() + pt->n_limbs);
+    decode_words(c->logn, words.data(), pt->n_limbs, mods, pt->scale, n, re, im);
+    return PFX_OK;
+}
+
+pfx_status pfx_encrypt(pfx_ctx *c, const pfx_sk *sk, const pfx_pt *pt, const uint64_t *a, const int64_t *e,
+                       pfx_ct *out, void *stream) {
+    REQUIRE(c && sk && a && e, PFX_EINVAL, "null argument");
+    pfx_status r = check_ct(c, pt, "plaintext");
+    if (r) return r;
+    const uint32_t lv = pt->n_limbs;
+    r = check_out(out, lv, 1);
+    if (r) return r;
+    const size_t N = c->N;
+    for (uint32_t i = 0; i < lv; ++i)
+        for (size_t t = 0; t < N; ++t) REQUIRE(a[(size_t)i * N + t] < c->primes[i], PFX_EINVAL, "a word not below its prime");
+    for (size_t t = 0; t < N; ++t) REQUIRE(e[t] > -(1ll << 40) && e[t] < (1ll << 40), PFX_EINVAL, "error too large");
+    HIPCHECK(hipSetDevice(c->device));
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    uint64_t *stage = (uint64_t *)w.at(w.lay.xport);
+    double *etmp = w.at(w.lay.rs_tmp);
+    HIPCHECK(hipMemcpyAsync(stage, a, (size_t)lv * N * sizeof(uint64_t), hipMemcpyHostToDevice, S(stream)));
+    launch_u64_to_f64(L, out->poly(1), stage, (size_t)lv * N);
+    launch_ntt(L, out->poly(1), nullptr, contiguous_map(lv, 0), false);
+    int64_t *edev = (int64_t *)w.at(w.lay.t3);
+    HIPCHECK(hipMemcpyAsync(edev, e, N * sizeof(int64_t), hipMemcpyHostToDevice, S(stream)));
+    launch_int_to_rns(L, etmp, edev, lv, 0, 0, 0);
+    launch_ntt(L, etmp, nullptr, contiguous_map(lv, 0), false);
+    launch_encrypt(L, out->poly(0), out->poly(1), etmp, sk->d_s, pt->poly(0), lv);
+    HIPCHECK(hipStreamSynchronize(S(stream)));
+    out->n_limbs = lv;
+    out->degree = 1;
+    out->scale = pt->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_decrypt(pfx_ctx *c, const pfx_sk *sk, const pfx_ct *x, pfx_pt **out, void *stream) {
+    REQUIRE(c && sk && out, PFX_EINVAL, "null argument");
+    pfx_status r = check_ct(c, x, "ciphertext");
+    if (r) return r;
+    REQUIRE(x->degree >= 1, PFX_EINVAL, "decrypt needs a ciphertext");
+    pfx_ct *m = nullptr;
+    r = pfx_ct_create(c, x->n_limbs, 0, &m);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    launch_decrypt(L, m->d, x->poly(0), x->poly(1), x->degree == 2 ? x->poly(2) : nullptr, sk->d_s, x->n_limbs);
+    if (hipStreamSynchronize(S(stream)) != hipSuccess) { pfx_ct_destroy(m); return fail(PFX_EDEVICE, "decrypt failed"); }
+    m->n_limbs = x->n_limbs;
+    m->degree = 0;
+    m->scale = x->scale;
+    *out = m;
+    return PFX_OK;
+}
+
+// ------------------------------------------------------------------ evaluation
+static pfx_status addsub(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, void *stream, bool sub) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_ct(c, b, "b");
+    if (r) return r;
+    if (!scale_close(a->scale, b->scale)) return fail(PFX_ESCALE, "operand scales differ");
+    const uint32_t lv = std::min(a->n_limbs, b->n_limbs);
+    const uint32_t deg = std::max(a->degree, b->degree), dmin = std::min(a->degree, b->degree);
+    r = check_out(out, lv, deg);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    launch_ew(L, sub ? EW_SUB : EW_ADD, out->d, a->d, b->d, out->cap_limbs * N, a->cap_limbs * N, b->cap_limbs * N,
+              dmin + 1, lv);
+    for (uint32_t k = dmin + 1; k <= deg; ++k) {
+        const pfx_ct *big = a->degree > b->degree ? a : b;
+        const bool negate = sub && big == b;
+        launch_ew(L, negate ? EW_NEG : EW_COPY, out->poly(k), big->poly(k), nullptr, 0, 0, 0, 1, lv);
+    }
+    out->n_limbs = lv;
+    out->degree = deg;
+    out->scale = a->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_add(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, void *stream) {
+    return addsub(c, a, b, out, stream, false);
+}
+pfx_status pfx_sub(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, void *stream) {
+    return addsub(c, a, b, out, stream, true);
+}
+
+pfx_status pfx_neg(pfx_ctx *c, const pfx_ct *a, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_out(out, a->n_limbs, a->degree);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    launch_ew(L, EW_NEG, out->d, a->d, nullptr, out->cap_limbs * N, a->cap_limbs * N, 0, a->degree + 1, a->n_limbs);
+    out->n_limbs = a->n_limbs;
+    out->degree = a->degree;
+    out->scale = a->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_add_plain(pfx_ctx *c, const pfx_ct *a, const pfx_pt *m, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_ct(c, m, "plaintext");
+    if (r) return r;
+    if (!scale_close(a->scale, m->scale)) return fail(PFX_ESCALE, "operand scales differ");
+    const uint32_t lv = std::min(a->n_limbs, m->n_limbs);
+    r = check_out(out, lv, a->degree);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    launch_ew(L, EW_ADD, out->d, a->d, m->d, 0, 0, 0, 1, lv);
+    if (a->degree >= 1 && out != a)
+        launch_ew(L, EW_COPY, out->poly(1), a->poly(1), nullptr, out->cap_limbs * c->N, a->cap_limbs * c->N, 0,
+                  a->degree, lv);
+    out->n_limbs = lv;
+    out->degree = a->degree;
+    out->scale = a->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_mul_plain(pfx_ctx *c, const pfx_ct *a, const pfx_pt *m, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_ct(c, m, "plaintext");
+    if (r) return r;
+    const uint32_t lv = std::min(a->n_limbs, m->n_limbs);
+    r = check_out(out, lv, a->degree);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    launch_ew(L, EW_MUL, out->d, a->d, m->d, out->cap_limbs * N, a->cap_limbs * N, 0, a->degree + 1, lv);
+    out->n_limbs = lv;
+    out->degree = a->degree;
+    out->scale = a->scale * m->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_mul_int(pfx_ctx *c, const pfx_ct *a, int64_t k, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_out(out, a->n_limbs, a->degree);
+    if (r) return r;
+    std::vector<uint64_t> cst(a->n_limbs);
+    for (uint32_t i = 0; i < a->n_limbs; ++i) {
+        const uint64_t q = c->primes[i];
+        const uint64_t mag = (uint64_t)(k < 0 ? -(k + 1) + 1ull : (uint64_t)k) % q;
+        cst[i] = k < 0 ? (q - mag) % q : mag;
+    }
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    launch_mulconst(L, out->d, a->d, out->cap_limbs * N, a->cap_limbs * N, a->degree + 1, a->n_limbs, cst.data());
+    out->n_limbs = a->n_limbs;
+    out->degree = a->degree;
+    out->scale = a->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_mul(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_ct(c, b, "b");
+    if (r) return r;
+    REQUIRE(a->degree == 1 && b->degree == 1, PFX_EINVAL, "tensor product needs two degree-1 ciphertexts");
+    const uint32_t lv = std::min(a->n_limbs, b->n_limbs);
+    r = check_out(out, lv, 2);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const double sc = a->scale * b->scale;
+    launch_tensor(L, out->poly(0), out->poly(1), out->poly(2), a->poly(0), a->poly(1), b->poly(0), b->poly(1), lv);
+    out->n_limbs = lv;
+    out->degree = 2;
+    out->scale = sc;
+    return PFX_OK;
+}
+
+pfx_status pfx_relinearize(pfx_ctx *c, const pfx_ct *a, const pfx_swk *rlk, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(rlk && rlk->ctx == c, PFX_EINVAL, "bad relinearisation key");
+    REQUIRE(rlk->galois == 0, PFX_ENOKEY, "key is not a relinearisation key");
+    REQUIRE(a->degree == 2, PFX_EINVAL, "relinearize needs a degree-2 ciphertext");
+    r = check_out(out, a->n_limbs, 1);
+    if (r) return r;
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const double sc = a->scale;
+    const uint32_t lv = a->n_limbs;
+    ks_core(c, L, w, a->poly(2), lv, rlk, out->poly(0), out->poly(1), a->poly(0), a->poly(1));
+    out->n_limbs = lv;
+    out->degree = 1;
+    out->scale = sc;
+    return PFX_OK;
+}
+
+pfx_status pfx_mul_relin(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk, pfx_ct *out,
+                         void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_ct(c, b, "b");
+    if (r) return r;
+    REQUIRE(rlk && rlk->ctx == c, PFX_EINVAL, "bad relinearisation key");
+    REQUIRE(rlk->galois == 0, PFX_ENOKEY, "key is not a relinearisation key");
+    REQUIRE(a->degree == 1 && b->degree == 1, PFX_EINVAL, "mul_relin needs two degree-1 ciphertexts");
+    const uint32_t lv = std::min(a->n_limbs, b->n_limbs);
+    r = check_out(out, lv, 1);
+    if (r) return r;
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const double sc = a->scale * b->scale;
+    const size_t PL = (size_t)c->L * c->N;
+    double *t0 = w.at(w.lay.t3), *t1 = t0 + PL, *t2 = t1 + PL;
+    launch_tensor(L, t0, t1, t2, a->poly(0), a->poly(1), b->poly(0), b->poly(1), lv);
+    ks_core(c, L, w, t2, lv, rlk, out->poly(0), out->poly(1), t0, t1);
+    out->n_limbs = lv;
+    out->degree = 1;
+    out->scale = sc;
+    return PFX_OK;
+}
+
+pfx_status pfx_rescale(pfx_ctx *c, const pfx_ct *a, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    const uint32_t lv = a->n_limbs;
+    REQUIRE(lv >= 2, PFX_ELEVEL, "rescale needs at least 2 limbs");
+    r = check_out(out, lv - 1, a->degree);
+    if (r) return r;
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    const int np = a->degree + 1;
+    double *last = w.at(w.lay.rs_last), *tmp = w.at(w.lay.rs_tmp);
+    // INTT of the last limbs, written compactly into `last` (out-of-place)
+    for (int k = 0; k < np; ++k) {
+        LimbMap one;
+        one.n = 1;
+        one.off[0] = 0;
+        one.pid[0] = (int16_t)(lv - 1);
+        launch_ntt(L, last + (size_t)k * N, a->poly(k) + (size_t)(lv - 1) * N, one, true);
+    }
+    launch_rescale_spread(L, tmp, last, np, lv);
+    launch_ntt(L, tmp, nullptr, poly_map(np, lv - 1, lv - 1), false);
+    const double sc = a->scale / (double)c->primes[lv - 1];
+    const uint32_t deg = a->degree;
+    launch_rescale_final(L, out->d, a->d, tmp, out->cap_limbs * N, a->cap_limbs * N, np, lv);
+    out->n_limbs = lv - 1;
+    out->degree = deg;
+    out->scale = sc;
+    return PFX_OK;
+}
+
+pfx_status pfx_drop_level(pfx_ctx *c, const pfx_ct *a, uint32_t n_limbs, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(n_limbs >= 1 && n_limbs <= a->n_limbs, PFX_ELEVEL, "cannot drop to that many limbs");
+    r = check_out(out, n_limbs, a->degree);
+    if (r) return r;
+    if (out != a) {
+        Launch L{c, S(stream)};
+        const size_t N = c->N;
+        launch_ew(L, EW_COPY, out->d, a->d, nullptr, out->cap_limbs * N, a->cap_limbs * N, 0, a->degree + 1, n_limbs);
+    }
+    out->n_limbs = n_limbs;
+    out->degree = a->degree;
+    out->scale = a->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_key_switch(pfx_ctx *c, const pfx_ct *d, const pfx_swk *k, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, d, "d");
+    if (r) return r;
+    REQUIRE(k && k->ctx == c, PFX_EINVAL, "bad key");
+    r = check_out(out, d->n_limbs, 1);
+    if (r) return r;
+    REQUIRE(out != d, PFX_EINVAL, "key_switch output must not alias its input");
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    ks_core(c, L, w, d->poly(0), d->n_limbs, k, out->poly(0), out->poly(1), nullptr, nullptr);
+    out->n_limbs = d->n_limbs;
+    out->degree = 1;
+    out->scale = d->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_apply_galois(pfx_ctx *c, const pfx_ct *a, const pfx_swk *gk, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(gk && gk->ctx == c && gk->galois != 0, PFX_ENOKEY, "not a Galois key");
+    REQUIRE(a->degree == 1, PFX_EINVAL, "automorphism needs a degree-1 ciphertext");
+    r = check_out(out, a->n_limbs, 1);
+    if (r) return r;
+    return galois_apply(c, a, gk, out, S(stream));
+}
+
+pfx_status pfx_rotate(pfx_ctx *c, const pfx_ct *a, int32_t step, const pfx_swk *const *keys, size_t n, pfx_ct *out,
+                      void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(a->degree == 1, PFX_EINVAL, "rotate needs a degree-1 ciphertext");
+    r = check_out(out, a->n_limbs, 1);
+    if (r) return r;
+    const uint32_t g = rot_element(c, step);
+    if (g == 1) return pfx_ct_copy(c, a, out, stream);
+    pfx_swk *k = find_key(c, g, keys, n);
+    if (!k) return fail(PFX_ENOKEY, "no Galois key for rotation step " + std::to_string(step));
+    return galois_apply(c, a, k, out, S(stream));
+}
+
+pfx_status pfx_conjugate(pfx_ctx *c, const pfx_ct *a, const pfx_swk *const *keys, size_t n, pfx_ct *out,
+                         void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(a->degree == 1, PFX_EINVAL, "conjugate needs a degree-1 ciphertext");
+    r = check_out(out, a->n_limbs, 1);
+    if (r) return r;
+    pfx_swk *k = find_key(c, 2u * c->N - 1, keys, n);
+    if (!k) return fail(PFX_ENOKEY, "no conjugation key");
+    return galois_apply(c, a, k, out, S(stream));
+}
+
+pfx_status pfx_rotate_sum(pfx_ctx *c, const pfx_ct *a, uint32_t log_steps, const pfx_swk *const *keys, size_t n,
+                          pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(a->degree == 1, PFX_EINVAL, "rotate_sum needs a degree-1 ciphertext");
+    REQUIRE(log_steps < (uint32_t)c->logn, PFX_EINVAL, "log_steps must be < log_n");
+    r = check_out(out, a->n_limbs, 1);
+    if (r) return r;
+    std::vector<pfx_swk *> ks(log_steps);
+    for (uint32_t k = 0; k < log_steps; ++k) {
+        ks[k] = find_key(c, rot_element(c, 1ll << k), keys, n);
+        if (!ks[k]) return fail(PFX_ENOKEY, "no Galois key for rotation step " + std::to_string(1 << k));
+    }
+    pfx_ct *tmp = nullptr;
+    r = pfx_ct_create(c, a->n_limbs, 1, &tmp);
+    if (r) return r;
+    r = pfx_ct_copy(c, a, out, stream);
+    for (uint32_t k = 0; k < log_steps && !r; ++k) {
+        r = galois_apply(c, out, ks[k], tmp, S(stream));
+        if (!r) r = pfx_add(c, out, tmp, out, stream);
+    }
+    hipStreamSynchronize(S(stream));
+    pfx_ct_destroy(tmp);
+    return r;
+}
+
+pfx_status pfx_ntt(pfx_ctx *c, uint64_t *d_words, uint32_t first_prime, uint32_t n_limbs, size_t batch, int inverse,
+                   void *stream) {
+    REQUIRE(c && d_words, PFX_EINVAL, "null argument");
+    REQUIRE(n_limbs >= 1 && first_prime + n_limbs <= (uint32_t)(c->L + c->K), PFX_EINVAL, "prime range out of bounds");
+    REQUIRE(batch >= 1, PFX_EINVAL, "empty batch");
+    Ws w;
+    pfx_status r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    // convert to FP64 residues in the workspace in chunks of at most ext-sized limb counts
+    const size_t cap_limbs = (w.lay.acc - w.lay.ext) / N;
+    double *buf = w.at(w.lay.ext);
+    const size_t total_limbs = batch * n_limbs;
+    for (size_t l0 = 0; l0 < total_limbs; l0 += cap_limbs) {
+        const size_t nl = std::min(cap_limbs, total_limbs - l0);
+        launch_u64_to_f64(L, buf, d_words + l0 * N, nl * N);
+        for (size_t b0 = 0; b0 < nl; b0 += kMaxMapLimbs) {
+            LimbMap m;
+            m.n = (int)std::min<size_t>(kMaxMapLimbs, nl - b0);
+            for (int i = 0; i < m.n; ++i) {
+                m.off[i] = (int32_t)(b0 + i);
+                m.pid[i] = (int16_t)(first_prime + (l0 + b0 + i) % n_limbs);
+            }
+            launch_ntt(L, buf, nullptr, m, inverse != 0);
+        }
+        launch_f64_to_u64(L, d_words + l0 * N, buf, nl * N);
+    }
+    return PFX_OK;
+}
+
+// ------------------------------------------------------------------ plumbing
+pfx_status pfx_dev_alloc(pfx_ctx *c, size_t bytes, void **out) {
+    REQUIRE(c && out, PFX_EINVAL, "null argument");
+    HIPCHECK(hipSetDevice(c->device));
+    if (hipMalloc(out, bytes ? bytes : 1) != hipSuccess) return fail(PFX_ENOMEM, "device allocation failed");
+    return PFX_OK;
+}
+
+pfx_status pfx_dev_free(pfx_ctx *c, void *p) {
+    REQUIRE(c, PFX_EINVAL, "null context");
+    HIPCHECK(hipFree(p));
+    return PFX_OK;
+}
+
+pfx_status pfx_memcpy_htod(pfx_ctx *c, void *dst, const void *src, size_t bytes, void *stream) {
+    REQUIRE(c && dst && src, PFX_EINVAL, "null argument");
+    HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, S(stream)));
+    HIPCHECK(hipStreamSynchronize(S(stream)));
+    return PFX_OK;
+}
+
+pfx_status pfx_memcpy_dtoh(pfx_ctx *c, void *dst, const void *src, size_t bytes, void *stream) {
+    REQUIRE(c && dst && src, PFX_EINVAL, "null argument");
+    HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, S(stream)));
+    HIPCHECK(hipStreamSynchronize(S(stream)));
+    return PFX_OK;
+}
+
+pfx_status pfx_stream_create(pfx_ctx *c, void **out) {
+    REQUIRE(c && out, PFX_EINVAL, "null argument");
+    HIPCHECK(hipSetDevice(c->device));
+    hipStream_t st;
+    HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    *out = st;
+    return PFX_OK;
+}
+
+pfx_status pfx_stream_destroy(pfx_ctx *c, void *stream) {
+    REQUIRE(c && stream, PFX_EINVAL, "null argument");
+    HIPCHECK(hipStreamSynchronize(S(stream)));
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        auto it = c->ws.find(S(stream));
+        if (it != c->ws.end()) {
+            hipFree(it->second->buf);
+            delete it->second;
+            c->ws.erase(it);
+        }
+    }
+    HIPCHECK(hipStreamDestroy(S(stream)));
+    return PFX_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+pfx_status pfx_profile_enable(pfx_ctx *c, int on) {
+    REQUIRE(c, PFX_EINVAL, "null context");
+    c->prof_on = on != 0;
+    return PFX_OK;
+}
+
+static void prof_drain(pfx_ctx *c) {
+    for (auto &e : c->prof_pending) {
+        hipEventSynchronize(e.stop);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e.start, e.stop);
+        auto &slot = c->prof_done[e.name];
+        slot.first += 1;
+        slot.second += ms;
+        hipEventDestroy(e.start);
+        hipEventDestroy(e.stop);
+    }
+    c->prof_pending.clear();
+}
+
+pfx_status pfx_profile_get(pfx_ctx *c, const char *kernel, uint64_t *launches, double *total_ms) {
+    REQUIRE(c && kernel, PFX_EINVAL, "null argument");
+    std::lock_guard<std::mutex> g(c->mu);
+    prof_drain(c);
+    auto it = c->prof_done.find(kernel);
+    if (launches) *launches = it == c->prof_done.end() ? 0 : it->second.first;
+    if (total_ms) *total_ms = it == c->prof_done.end() ? 0.0 : it->second.second;
+    return PFX_OK;
+}
+
+pfx_status pfx_profile_names(pfx_ctx *c, char *buf, size_t cap) {
+    REQUIRE(c && buf && cap, PFX_EINVAL, "null argument");
+    std::lock_guard<std::mutex> g(c->mu);
+    prof_drain(c);
+    std::string s;
+    for (auto &kv : c->prof_done) s += kv.first + "\n";
+    std::strncpy(buf, s.c_str(), cap - 1);
+    buf[cap - 1] = 0;
+    return PFX_OK;
+}
+
+pfx_status pfx_profile_reset(pfx_ctx *c) {
+    REQUIRE(c, PFX_EINVAL, "null context");
+    std::lock_guard<std::mutex> g(c->mu);
+    prof_drain(c);
+    c->prof_done.clear();
+    return PFX_OK;
+}
+
+}  // extern "C"
+
+namespace pfx {
+
+void prof_begin(const Launch &L, const char *, hipEvent_t *ev) {
+    *ev = nullptr;
+    if (!L.ctx->prof_on) return;
+    hipEventCreate(ev);
+    hipEventRecord(*ev, L.st);
+}
+
+void prof_end(const Launch &L, const char *name, hipEvent_t ev) {
+    if (!L.ctx->prof_on || !ev) return;
+    hipEvent_t stop;
+    hipEventCreate(&stop);
+    hipEventRecord(stop, L.st);
+    std::lock_guard<std::mutex> g(L.ctx->mu);
+    L.ctx->prof_pending.push_back(ProfEntry{ev, stop, name});
+}
+
+}  // namespace pfx

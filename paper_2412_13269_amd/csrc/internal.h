@@ -1,0 +1,178 @@
+// Internal structures of libpfx: context, objects, device tables, launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pfx.h"
+
+namespace pfx {
+
+constexpr int kMaxAlpha = 8;
+constexpr int kMaxSpecial = 8;    // special primes p_k
+constexpr int kMaxMapLimbs = 256;   // limbs per NTT launch (kernel-argument map)
+
+// Per-prime device record.  Prime ids: q_0..q_{L-1} are 0..L-1, p_k is L+k.
+struct PrimeDev {
+    double q, qinv;              // q and fl(1/q)
+    double ninv, ninv_q;         // N^-1 mod q and fl(N^-1 / q)
+    double ninv_w1, ninv_w1_q;   // N^-1 * psi^-(N/2), the last inverse stage folded with N^-1
+    const double2 *tw;           // tw[k]  = {psi^bitrev(k),  fl(./q)}, k < N
+    const double2 *itw;          // itw[k] = {psi^-bitrev(k), fl(./q)}, k < N
+};
+
+// Limbs of one batched NTT launch: limb b sits at base + off[b] * N and uses prime pid[b].
+struct LimbMap {
+    int n;
+    int32_t off[kMaxMapLimbs];
+    int16_t pid[kMaxMapLimbs];
+};
+
+// Constants of the fast basis conversion of one key-switching digit variant
+// (digit j with sz active primes): y_i = [d_i * inv_i]_{q_i};
+// out_m = sum_i y_i * hat[i][m] mod m, for every prime id m.
+struct ModUpConst {
+    double2 inv[kMaxAlpha];                   // {(Q'/q_i)^-1 mod q_i, ./q_i}
+    double2 hat[kMaxAlpha][PFX_MAX_PRIMES];   // {(Q'/q_i) mod m, ./m}
+};
+
+// ModDown constants (independent of the level).
+struct ModDownConst {
+    double2 phat_inv[PFX_MAX_PRIMES];                   // (P/p_k)^-1 mod p_k
+    double2 phat[PFX_MAX_PRIMES][PFX_MAX_PRIMES];       // [k][i]: (P/p_k) mod q_i
+    double2 pinv[PFX_MAX_PRIMES];                       // P^-1 mod q_i
+    double half[2 * PFX_MAX_PRIMES];                    // floor(P/2) mod prime id m
+    double2 pmod[PFX_MAX_PRIMES];                       // P mod q_i (key generation gadget)
+};
+
+// Rescale constants for dropping prime l: entry [l][i], i < l.
+struct RescaleConst {
+    double2 inv;     // q_l^-1 mod q_i
+    double half;     // floor(q_l / 2) mod q_i
+    double pad;
+};
+
+struct Workspace {
+    hipStream_t stream = nullptr;
+    double *buf = nullptr;
+    size_t doubles = 0;
+};
+
+struct ProfEntry {
+    hipEvent_t start, stop;
+    std::string name;
+};
+
+}  // namespace pfx
+
+struct pfx_ctx {
+    int device = 0;
+    int logn = 0;
+    int N = 0;
+    int L = 0, K = 0, alpha = 0, beta = 0, mod_log2 = 0;
+    std::vector<uint64_t> primes;   // L q's then K p's
+    std::vector<uint64_t> psi;
+
+    pfx::PrimeDev *d_primes = nullptr;
+    double2 *d_tw = nullptr;
+    pfx::ModUpConst *d_modup = nullptr;     // [beta][alpha] variants (j, sz-1)
+    pfx::ModDownConst *d_moddown = nullptr;
+    pfx::RescaleConst *d_rescale = nullptr; // [L][L]
+    std::vector<pfx::PrimeDev> h_primes;
+
+    std::mutex mu;
+    std::map<hipStream_t, pfx::Workspace *> ws;
+
+    bool prof_on = false;
+    std::vector<pfx::ProfEntry> prof_pending;
+    std::map<std::string, std::pair<uint64_t, double>> prof_done;
+};
+
+struct pfx_sk {
+    pfx_ctx *ctx;
+    double *d_s;          // (L + K) limbs, NTT domain
+    std::vector<int8_t> h_s;
+};
+
+struct pfx_swk {
+    pfx_ctx *ctx;
+    uint32_t galois;
+    double *d_k;          // [beta][2][L + K][N], NTT domain
+};
+
+struct pfx_ct {
+    pfx_ctx *ctx;
+    uint32_t cap_limbs, cap_degree;
+    uint32_t n_limbs = 0, degree = 0;
+    double scale = 1.0;
+    double *d = nullptr;  // poly k, limb i at d + (k * cap_limbs + i) * N
+    double *poly(uint32_t k) const { return d + (size_t)k * cap_limbs * (size_t)ctx->N; }
+};
+
+namespace pfx {
+
+// ---------------------------------------------------------------- host helpers
+void set_error(const std::string &msg);
+pfx_status fail(pfx_status s, const std::string &msg);
+
+bool build_primes(const pfx_params *prm, std::vector<uint64_t> &q, std::vector<uint64_t> &p,
+                  std::vector<uint64_t> &psi, std::string &err);
+uint64_t mulmod_u64(uint64_t a, uint64_t b, uint64_t m);
+uint64_t powmod_u64(uint64_t a, uint64_t e, uint64_t m);
+uint64_t invmod_u64(uint64_t a, uint64_t m);
+
+// Host encoder (slot FFT) in encoder.cpp.
+bool encode_coeffs(int logn, const double *re, const double *im, size_t n, double scale,
+                   const std::vector<uint64_t> &mods, std::vector<uint64_t> &words, std::string &err);
+void decode_words(int logn, const uint64_t *words, int n_limbs, const std::vector<uint64_t> &mods,
+                  double scale, size_t n, double *re, double *im);
+
+// ---------------------------------------------------------------- launchers
+struct Launch {
+    pfx_ctx *ctx;
+    hipStream_t st;
+};
+
+void prof_begin(const Launch &L, const char *name, hipEvent_t *ev);
+void prof_end(const Launch &L, const char *name, hipEvent_t ev);
+
+// Batched NTT over the limbs of `map`; src == nullptr means in place.
+void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap &map, bool inverse);
+void launch_u64_to_f64(const Launch &L, double *out, const uint64_t *in, size_t n);
+void launch_f64_to_u64(const Launch &L, uint64_t *out, const double *in, size_t n);
+void launch_int_to_rns(const Launch &L, double *out, const int64_t *in, int n_limbs, int pid0,
+                       int pid_gap_at, int pid_gap);
+void launch_s8_to_rns(const Launch &L, double *out, const int8_t *in, int n_limbs);
+
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4 };
+// out[k][i] = a[k][i] op b[k][i] over npoly polynomials of nl limbs (prime ids 0..nl-1).
+void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const double *b, size_t so,
+               size_t sa, size_t sb, int npoly, int nl);
+// out[k][i] = a[k][i] * cst_i (+ 0) with per-limb constant words.
+void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, size_t sa, int npoly,
+                     int nl, const uint64_t *cst);
+void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const double *a0,
+                   const double *a1, const double *b0, const double *b1, int nl);
+void launch_automorph(const Launch &L, double *out, const double *in, size_t so, size_t si, int npoly,
+                      int nl, uint32_t g);
+void launch_rescale_spread(const Launch &L, double *tmp, const double *lastc, int npoly, int lv);
+void launch_rescale_final(const Launch &L, double *out, const double *in, const double *tmp, size_t so,
+                          size_t si, int npoly, int lv);
+void launch_modup(const Launch &L, double *ext, const double *dcoef, int lv);
+void launch_ks_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt,
+                     const double *key, int lv);
+void launch_moddown_conv(const Launch &L, double *tmp, const double *acc, int lv);
+void launch_moddown_final(const Launch &L, double *out0, double *out1, const double *acc,
+                          const double *tmp, const double *base0, const double *base1, int lv);
+void launch_keygen_b(const Launch &L, double *b, const double *a, const double *e, const double *s,
+                     const double *sfrom, int digit);
+void launch_encrypt(const Launch &L, double *c0, const double *a, const double *e, const double *s,
+                    const double *m, int lv);
+void launch_decrypt(const Launch &L, double *m, const double *c0, const double *c1, const double *c2,
+                    const double *s, int lv);
+
+}  // namespace pfx

@@ -1,0 +1,760 @@
+// HIP kernels for gfx950 (MI355X) and their host launchers.
+//
+// Residues live in HBM as exact FP64 integers (every prime is below 2^50, see
+// modarith.h), limb-major: limb i of a polynomial is N contiguous doubles.
+// Ciphertexts stay in the NTT domain on the device.
+#include <algorithm>
+#include <cstdio>
+
+#include "internal.h"
+#include "modarith.h"
+
+namespace pfx {
+
+#define HIP_LAUNCH_CHECK()                                                     \
+    do {                                                                       \
+        hipError_t e_ = hipGetLastError();                                     \
+        if (e_ != hipSuccess) set_error(std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static inline unsigned grid_for(size_t total, unsigned threads = 256) {
+    size_t b = (total + threads - 1) / threads;
+    return (unsigned)std::min<size_t>(b, 1u << 20);
+}
+
+__device__ __forceinline__ unsigned brev_n(unsigned x, int logn) { return __brev(x) >> (32 - logn); }
+
+// ============================================================== NTT
+// Negacyclic NTT, output in the order NTT(a)[j] = a(psi^(2 bitrev(j) + 1)).
+// Stage s (0 <= s < log N) pairs j and j + N/2^(s+1); its twiddle is
+// tw[2^s + (j >> (log N - s))] = psi^bitrev(2^s + ...), as in the textbook
+// Cooley-Tukey (forward) / Gentleman-Sande (inverse) loops.
+//
+// A limb of N = 2^16 doubles (512 KiB) is larger than one CU's LDS, so the
+// transform runs as two passes of S_col + S_row = log N stages.  The column
+// pass does the first S_col stages on sub-transforms of stride 2^(log N -
+// S_col) (a tile = C consecutive columns, coalesced rows of C doubles); the
+// row pass does the last S_row stages on contiguous blocks of 2^S_row.  Each
+// pass splits its S stages into two register rounds (R1 = ceil(S/2) stages,
+// then R2) with one LDS exchange between them; a thread holds 2^R1 or 2^R2
+// elements and does their butterflies in registers.
+constexpr int kNttThreads = 256;
+constexpr int kNttTile = 4096;
+
+struct NttArgs {
+    double *dst;
+    const double *src;
+    const PrimeDev *primes;
+    int logn;
+    int C;
+    int tiles;
+    LimbMap map;
+};
+
+template <int S, bool ROW, bool INV>
+__global__ __launch_bounds__(kNttThreads) void k_ntt_pass(const NttArgs a) {
+    constexpr int R = 1 << S;
+    constexpr int R1 = (S + 1) / 2;
+    constexpr int R2 = S - R1;
+    constexpr int E1 = 1 << R1;
+    constexpr int E2 = 1 << R2;
+    __shared__ double lds[kNttTile + kNttTile / 16];
+
+    const int limb = blockIdx.x / a.tiles;
+    const int tile = blockIdx.x - limb * a.tiles;
+    const PrimeDev &P = a.primes[a.map.pid[limb]];
+    const double q = P.q;
+    const size_t loff = (size_t)a.map.off[limb] << a.logn;
+    double *__restrict__ dst = a.dst + loff;
+    const double *__restrict__ src = a.src + loff;
+    const int logn = a.logn;
+    const int C = a.C;
+    const int lo_bits = logn - S;
+    const int s0 = ROW ? logn - S : 0;
+    const int cbase = tile * C;
+    const double2 *__restrict__ tw = INV ? P.itw : P.tw;
+
+    auto gidx = [&](int c, int mid) -> int {
+        return ROW ? (((cbase + c) << S) | mid) : ((mid << lo_bits) | (cbase + c));
+    };
+    auto lidx = [&](int c, int mid) -> int {
+        return ROW ? (c * (R + R / 16) + mid + (mid >> 4)) : (mid * C + c);
+    };
+
+    if (ROW) {
+        for (int e = threadIdx.x; e < C * R; e += kNttThreads) {
+            const int c = e >> S, mid = e & (R - 1);
+            lds[lidx(c, mid)] = src[gidx(c, mid)];
+        }
+        __syncthreads();
+    }
+
+    if (!INV) {
+        // ---- round 1: local stages [0, R1), elements mid = (u << (S-R1)) | ml
+        const int n1 = C << (S - R1);
+        for (int g = threadIdx.x; g < n1; g += kNttThreads) {
+            int c, ml;
+            if (ROW) { ml = g & ((1 << (S - R1)) - 1); c = g >> (S - R1); }
+            else { c = g % C; ml = g / C; }
+            double v[E1];
+#pragma unroll
+            for (int u = 0; u < E1; ++u) {
+                const int mid = (u << (S - R1)) | ml;
+                v[u] = ROW ? lds[lidx(c, mid)] : src[gidx(c, mid)];
+            }
+#pragma unroll
+            for (int kk = 0; kk < R1; ++kk) {
+                const int s = s0 + kk;
+                const int h = 1 << (R1 - 1 - kk);
+#pragma unroll
+                for (int u = 0; u < E1; ++u) {
+                    if (u & h) continue;
+                    const int j = gidx(c, (u << (S - R1)) | ml);
+                    const double2 w = tw[(1 << s) + (j >> (logn - s))];
+                    const double V = mmulc(v[u + h], w.x, w.y, q);
+                    const double U = v[u];
+                    v[u] = madd(U, V, q);
+                    v[u + h] = msub(U, V, q);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < E1; ++u) lds[lidx(c, (u << (S - R1)) | ml)] = v[u];
+        }
+        __syncthreads();
+        // ---- round 2: local stages [R1, S), elements mid = (mh << R2) | u
+        const int n2 = C << R1;
+        for (int g = threadIdx.x; g < n2; g += kNttThreads) {
+            int c, mh;
+            if (ROW) { mh = g & (E1 - 1); c = g >> R1; }
+            else { c = g % C; mh = g / C; }
+            double v[E2];
+#pragma unroll
+            for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
+#pragma unroll
+            for (int kk = 0; kk < R2; ++kk) {
+                const int s = s0 + R1 + kk;
+                const int h = 1 << (R2 - 1 - kk);
+#pragma unroll
+                for (int u = 0; u < E2; ++u) {
+                    if (u & h) continue;
+                    const int j = gidx(c, (mh << R2) | u);
+                    const double2 w = tw[(1 << s) + (j >> (logn - s))];
+                    const double V = mmulc(v[u + h], w.x, w.y, q);
+                    const double U = v[u];
+                    v[u] = madd(U, V, q);
+                    v[u + h] = msub(U, V, q);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < E2; ++u) {
+                const int mid = (mh << R2) | u;
+                if (ROW) lds[lidx(c, mid)] = v[u];
+                else dst[gidx(c, mid)] = v[u];
+            }
+        }
+    } else {
+        // ---- round A: local stages S-1 .. R1 (descending), elements mid = (mh << R2) | u
+        const int n2 = C << R1;
+        for (int g = threadIdx.x; g < n2; g += kNttThreads) {
+            int c, mh;
+            if (ROW) { mh = g & (E1 - 1); c = g >> R1; }
+            else { c = g % C; mh = g / C; }
+            double v[E2];
+#pragma unroll
+            for (int u = 0; u < E2; ++u) {
+                const int mid = (mh << R2) | u;
+                v[u] = ROW ? lds[lidx(c, mid)] : src[gidx(c, mid)];
+            }
+#pragma unroll
+            for (int kk = R2 - 1; kk >= 0; --kk) {
+                const int s = s0 + R1 + kk;
+                const int h = 1 << (R2 - 1 - kk);
+#pragma unroll
+                for (int u = 0; u < E2; ++u) {
+                    if (u & h) continue;
+                    const int j = gidx(c, (mh << R2) | u);
+                    const double2 w = tw[(1 << s) + (j >> (logn - s))];
+                    const double U = v[u], V = v[u + h];
+                    v[u] = madd(U, V, q);
+                    v[u + h] = mmulc(msub(U, V, q), w.x, w.y, q);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
+        }
+        __syncthreads();
+        // ---- round B: local stages R1-1 .. 0, elements mid = (u << (S-R1)) | ml
+        const int n1 = C << (S - R1);
+        for (int g = threadIdx.x; g < n1; g += kNttThreads) {
+            int c, ml;
+            if (ROW) { ml = g & ((1 << (S - R1)) - 1); c = g >> (S - R1); }
+            else { c = g % C; ml = g / C; }
+            double v[E1];
+#pragma unroll
+            for (int u = 0; u < E1; ++u) v[u] = lds[lidx(c, (u << (S - R1)) | ml)];
+#pragma unroll
+            for (int kk = R1 - 1; kk >= 0; --kk) {
+                const int s = s0 + kk;
+                const int h = 1 << (R1 - 1 - kk);
+#pragma unroll
+                for (int u = 0; u < E1; ++u) {
+                    if (u & h) continue;
+                    const double U = v[u], V = v[u + h];
+                    if (!ROW && s == 0) {   // last stage: fold N^-1 into both outputs
+                        v[u] = mmulc(madd(U, V, q), P.ninv, P.ninv_q, q);
+                        v[u + h] = mmulc(msub(U, V, q), P.ninv_w1, P.ninv_w1_q, q);
+                    } else {
+                        const int j = gidx(c, (u << (S - R1)) | ml);
+                        const double2 w = tw[(1 << s) + (j >> (logn - s))];
+                        v[u] = madd(U, V, q);
+                        v[u + h] = mmulc(msub(U, V, q), w.x, w.y, q);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < E1; ++u) {
+                const int mid = (u << (S - R1)) | ml;
+                if (ROW) lds[lidx(c, mid)] = v[u];
+                else dst[gidx(c, mid)] = v[u];
+            }
+        }
+    }
+
+    if (ROW) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < C * R; e += kNttThreads) {
+            const int c = e >> S, mid = e & (R - 1);
+            dst[gidx(c, mid)] = lds[lidx(c, mid)];
+        }
+    }
+}
+
+template <bool ROW, bool INV>
+static void dispatch_pass(int S, dim3 grid, hipStream_t st, const NttArgs &a) {
+    switch (S) {
+#define PFX_CASE(s) case s: k_ntt_pass<s, ROW, INV><<<grid, kNttThreads, 0, st>>>(a); break;
+        PFX_CASE(2) PFX_CASE(3) PFX_CASE(4) PFX_CASE(5) PFX_CASE(6) PFX_CASE(7) PFX_CASE(8)
+#undef PFX_CASE
+        default: set_error("unsupported NTT pass size");
+    }
+}
+
+void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap &map, bool inverse) {
+    if (map.n <= 0) return;
+    pfx_ctx *ctx = L.ctx;
+    const int logn = ctx->logn;
+    const int Scol = logn / 2, Srow = logn - Scol;
+    NttArgs a;
+    a.dst = base;
+    a.primes = ctx->d_primes;
+    a.logn = logn;
+    a.map = map;
+    auto run = [&](int S, bool row, const double *from) {
+        const int R = 1 << S;
+        const int subs = 1 << (logn - S);
+        a.C = std::min(kNttTile / R, subs);
+        a.tiles = subs / a.C;
+        a.src = from;
+        dim3 grid(map.n * a.tiles);
+        hipEvent_t ev;
+        const char *nm = inverse ? (row ? "intt_row" : "intt_col") : (row ? "ntt_row" : "ntt_col");
+        prof_begin(L, nm, &ev);
+        if (row) { if (inverse) dispatch_pass<true, true>(S, grid, L.st, a); else dispatch_pass<true, false>(S, grid, L.st, a); }
+        else { if (inverse) dispatch_pass<false, true>(S, grid, L.st, a); else dispatch_pass<false, false>(S, grid, L.st, a); }
+        HIP_LAUNCH_CHECK();
+        prof_end(L, nm, ev);
+    };
+    const double *first = src ? src : base;
+    if (!inverse) { run(Scol, false, first); run(Srow, true, base); }
+    else { run(Srow, true, first); run(Scol, false, base); }
+}
+
+// ============================================================== conversions
+__global__ void k_u64_to_f64(double *out, const uint64_t *in, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (double)in[i];
+}
+__global__ void k_f64_to_u64(uint64_t *out, const double *in, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (uint64_t)in[i];
+}
+// out[i][c] = in[c] mod prime i  (|in| < 2^50)
+__global__ void k_int_to_rns(double *out, const int64_t *in, int n_limbs, int logn, const PrimeDev *pr) {
+    const size_t total = (size_t)n_limbs << logn;
+    const size_t mask = ((size_t)1 << logn) - 1;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i >> logn);
+        const double q = pr[l].q;
+        const int64_t v = in[i & mask];
+        const uint64_t m = (uint64_t)q;
+        const uint64_t r = v >= 0 ? (uint64_t)v % m : (m - ((uint64_t)(-v) % m)) % m;
+        out[i] = (double)r;
+    }
+}
+__global__ void k_s8_to_rns(double *out, const int8_t *in, int n_limbs, int logn, const PrimeDev *pr) {
+    const size_t total = (size_t)n_limbs << logn;
+    const size_t mask = ((size_t)1 << logn) - 1;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i >> logn);
+        const int v = in[i & mask];
+        out[i] = v >= 0 ? (double)v : pr[l].q + (double)v;
+    }
+}
+
+void launch_u64_to_f64(const Launch &L, double *out, const uint64_t *in, size_t n) {
+    k_u64_to_f64<<<grid_for(n), 256, 0, L.st>>>(out, in, n);
+    HIP_LAUNCH_CHECK();
+}
+void launch_f64_to_u64(const Launch &L, uint64_t *out, const double *in, size_t n) {
+    k_f64_to_u64<<<grid_for(n), 256, 0, L.st>>>(out, in, n);
+    HIP_LAUNCH_CHECK();
+}
+void launch_int_to_rns(const Launch &L, double *out, const int64_t *in, int n_limbs, int, int, int) {
+    size_t total = (size_t)n_limbs << L.ctx->logn;
+    k_int_to_rns<<<grid_for(total), 256, 0, L.st>>>(out, in, n_limbs, L.ctx->logn, L.ctx->d_primes);
+    HIP_LAUNCH_CHECK();
+}
+void launch_s8_to_rns(const Launch &L, double *out, const int8_t *in, int n_limbs) {
+    size_t total = (size_t)n_limbs << L.ctx->logn;
+    k_s8_to_rns<<<grid_for(total), 256, 0, L.st>>>(out, in, n_limbs, L.ctx->logn, L.ctx->d_primes);
+    HIP_LAUNCH_CHECK();
+}
+
+// ============================================================== elementwise
+template <int OP>
+__global__ void k_ew(double *out, const double *a, const double *b, size_t so, size_t sa, size_t sb, int npoly,
+                     int nl, int logn, const PrimeDev *pr) {
+    const size_t total = ((size_t)npoly * nl) << logn;
+    const size_t mask = ((size_t)1 << logn) - 1;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = idx & mask;
+        const size_t li = idx >> logn;
+        const int i = (int)(li % nl);
+        const int k = (int)(li / nl);
+        const size_t off = ((size_t)i << logn) + c;
+        const double q = pr[i].q;
+        const double x = a[k * sa + off];
+        double r;
+        if (OP == EW_ADD) r = madd(x, b[k * sb + off], q);
+        else if (OP == EW_SUB) r = msub(x, b[k * sb + off], q);
+        else if (OP == EW_MUL) r = mmul(x, b[k * sb + off], q, pr[i].qinv);
+        else if (OP == EW_NEG) r = mneg(x, q);
+        else r = x;
+        out[k * so + off] = r;
+    }
+}
+
+void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const double *b, size_t so, size_t sa,
+               size_t sb, int npoly, int nl) {
+    const int logn = L.ctx->logn;
+    const size_t total = ((size_t)npoly * nl) << logn;
+    if (!total) return;
+    const unsigned g = grid_for(total);
+    const PrimeDev *pr = L.ctx->d_primes;
+    hipEvent_t ev;
+    prof_begin(L, "elementwise", &ev);
+    switch (op) {
+        case EW_ADD: k_ew<EW_ADD><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
+        case EW_SUB: k_ew<EW_SUB><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
+        case EW_MUL: k_ew<EW_MUL><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
+        case EW_NEG: k_ew<EW_NEG><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
+        default: k_ew<EW_COPY><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
+    }
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "elementwise", ev);
+}
+
+struct LimbConsts {
+    double w[PFX_MAX_PRIMES];
+    double wq[PFX_MAX_PRIMES];
+};
+
+__global__ void k_mulconst(double *out, const double *a, size_t so, size_t sa, int npoly, int nl, int logn,
+                           const PrimeDev *pr, const LimbConsts k) {
+    const size_t total = ((size_t)npoly * nl) << logn;
+    const size_t mask = ((size_t)1 << logn) - 1;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = idx & mask;
+        const size_t li = idx >> logn;
+        const int i = (int)(li % nl);
+        const int kp = (int)(li / nl);
+        const size_t off = ((size_t)i << logn) + c;
+        out[kp * so + off] = mmulc(a[kp * sa + off], k.w[i], k.wq[i], pr[i].q);
+    }
+}
+
+void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, size_t sa, int npoly, int nl,
+                     const uint64_t *cst) {
+    LimbConsts k;
+    for (int i = 0; i < nl; ++i) {
+        k.w[i] = (double)cst[i];
+        k.wq[i] = (double)cst[i] / (double)L.ctx->primes[i];
+    }
+    const size_t total = ((size_t)npoly * nl) << L.ctx->logn;
+    hipEvent_t ev;
+    prof_begin(L, "mulconst", &ev);
+    k_mulconst<<<grid_for(total), 256, 0, L.st>>>(out, a, so, sa, npoly, nl, L.ctx->logn, L.ctx->d_primes, k);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "mulconst", ev);
+}
+
+// Tensor product in the NTT domain (Sec. 2.4.2): d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.
+__global__ void k_tensor(double *d0, double *d1, double *d2, const double *a0, const double *a1, const double *b0,
+                         const double *b1, int nl, int logn, const PrimeDev *pr) {
+    const size_t total = (size_t)nl << logn;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx >> logn);
+        const double q = pr[i].q, qi = pr[i].qinv;
+        const double x0 = a0[idx], x1 = a1[idx], y0 = b0[idx], y1 = b1[idx];
+        d0[idx] = mmul(x0, y0, q, qi);
+        d1[idx] = madd(mmul(x0, y1, q, qi), mmul(x1, y0, q, qi), q);
+        d2[idx] = mmul(x1, y1, q, qi);
+    }
+}
+
+void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const double *a0, const double *a1,
+                   const double *b0, const double *b1, int nl) {
+    const size_t total = (size_t)nl << L.ctx->logn;
+    hipEvent_t ev;
+    prof_begin(L, "tensor", &ev);
+    k_tensor<<<grid_for(total), 256, 0, L.st>>>(d0, d1, d2, a0, a1, b0, b1, nl, L.ctx->logn, L.ctx->d_primes);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "tensor", ev);
+}
+
+// ============================================================== automorphism
+// phi_g in the NTT domain is a permutation: slot j holds a(psi^e), e = 2 bitrev(j) + 1,
+// and phi_g(a)(psi^e) = a(psi^(g e)), so out[j] = in[j'] with 2 bitrev(j') + 1 = g e mod 2N.
+__global__ void k_automorph(double *out, const double *in, size_t so, size_t si, int npoly, int nl, int logn,
+                            uint32_t g) {
+    const size_t total = ((size_t)npoly * nl) << logn;
+    const uint32_t mask = (1u << logn) - 1;
+    const uint32_t mask2 = (2u << logn) - 1;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t j = (uint32_t)(idx & mask);
+        const size_t li = idx >> logn;
+        const int i = (int)(li % nl);
+        const int k = (int)(li / nl);
+        const uint32_t e = 2u * brev_n(j, logn) + 1u;
+        const uint32_t e2 = (uint32_t)(((uint64_t)e * g) & mask2);
+        const uint32_t j2 = brev_n((e2 - 1u) >> 1, logn);
+        out[k * so + ((size_t)i << logn) + j] = in[k * si + ((size_t)i << logn) + j2];
+    }
+}
+
+void launch_automorph(const Launch &L, double *out, const double *in, size_t so, size_t si, int npoly, int nl,
+                      uint32_t g) {
+    const size_t total = ((size_t)npoly * nl) << L.ctx->logn;
+    hipEvent_t ev;
+    prof_begin(L, "automorph", &ev);
+    k_automorph<<<grid_for(total), 256, 0, L.st>>>(out, in, so, si, npoly, nl, L.ctx->logn, g);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "automorph", ev);
+}
+
+// ============================================================== rescale (Sec. 2.5)
+// c'_i = (c_i + h - [c_last + h]_{q_last}) * q_last^-1 mod q_i, h = floor(q_last/2):
+// round-half-up division of the [0, Q) lift by the last prime.  h is added to
+// every coefficient, so it joins the correction t_i = [c_last + h]_{q_last} - h
+// in the coefficient domain; the NTT-domain update is then c'_i = (c_i - NTT(t)_i) q_last^-1.
+__global__ void k_rescale_spread(double *tmp, const double *lastc, int npoly, int lv, int logn, const PrimeDev *pr,
+                                 const RescaleConst *rc) {
+    const int nout = lv - 1;
+    const size_t total = ((size_t)npoly * nout) << logn;
+    const size_t mask = ((size_t)1 << logn) - 1;
+    const double ql = pr[lv - 1].q;
+    const double h = __builtin_floor(ql * 0.5);
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = idx & mask;
+        const size_t li = idx >> logn;
+        const int i = (int)(li % nout);
+        const int k = (int)(li / nout);
+        const double x = madd(lastc[((size_t)k << logn) + c], h, ql);
+        const double qi = pr[i].q;
+        tmp[idx] = msub(mred(x, qi, pr[i].qinv), rc[(lv - 1) * PFX_MAX_PRIMES + i].half, qi);
+    }
+}
+
+__global__ void k_rescale_final(double *out, const double *in, const double *tmp, size_t so, size_t si, int npoly,
+                                int lv, int logn, const PrimeDev *pr, const RescaleConst *rc) {
+    const int nout = lv - 1;
+    const size_t total = ((size_t)npoly * nout) << logn;
+    const size_t mask = ((size_t)1 << logn) - 1;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = idx & mask;
+        const size_t li = idx >> logn;
+        const int i = (int)(li % nout);
+        const int k = (int)(li / nout);
+        const double q = pr[i].q;
+        const RescaleConst r = rc[(lv - 1) * PFX_MAX_PRIMES + i];
+        const double x = msub(in[k * si + ((size_t)i << logn) + c], tmp[idx], q);
+        out[k * so + ((size_t)i << logn) + c] = mmulc(x, r.inv.x, r.inv.y, q);
+    }
+}
+
+void launch_rescale_spread(const Launch &L, double *tmp, const double *lastc, int npoly, int lv) {
+    const size_t total = ((size_t)npoly * (lv - 1)) << L.ctx->logn;
+    hipEvent_t ev;
+    prof_begin(L, "rescale_spread", &ev);
+    k_rescale_spread<<<grid_for(total), 256, 0, L.st>>>(tmp, lastc, npoly, lv, L.ctx->logn, L.ctx->d_primes,
+                                                        L.ctx->d_rescale);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "rescale_spread", ev);
+}
+
+void launch_rescale_final(const Launch &L, double *out, const double *in, const double *tmp, size_t so, size_t si,
+                          int npoly, int lv) {
+    const size_t total = ((size_t)npoly * (lv - 1)) << L.ctx->logn;
+    hipEvent_t ev;
+    prof_begin(L, "rescale_final", &ev);
+    k_rescale_final<<<grid_for(total), 256, 0, L.st>>>(out, in, tmp, so, si, npoly, lv, L.ctx->logn,
+                                                       L.ctx->d_primes, L.ctx->d_rescale);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "rescale_final", ev);
+}
+
+// ============================================================== key switching (Sec. 2.4.1)
+// Workspace layouts at level lv (E = lv + K limbs per extended polynomial):
+//   ext[j][t][c]  digit j's fast conversion to the E - sz_j primes outside the
+//                 digit, t in the order: q's below the digit, q's above, p's;
+//   acc[u][m][c]  u in {0, 1}, m < E: q_0..q_{lv-1} then p_0..p_{K-1}.
+__device__ __forceinline__ int ext_prime(int t, int j0, int sz, int lv, int L) {
+    if (t < j0) return t;
+    if (t < lv - sz) return t + sz;
+    return L + (t - (lv - sz));
+}
+
+__global__ void k_modup(double *ext, const double *dcoef, int lv, int logn, int L, int K, int alpha,
+                        const PrimeDev *pr, const ModUpConst *mc) {
+    const int j = blockIdx.y;
+    const int j0 = j * alpha;
+    const int sz = min(alpha, lv - j0);
+    const ModUpConst &cst = mc[j * alpha + (sz - 1)];
+    const int E = lv + K;
+    const size_t N = (size_t)1 << logn;
+    const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    double y[kMaxAlpha];
+#pragma unroll
+    for (int i = 0; i < kMaxAlpha; ++i) {
+        if (i < sz) y[i] = mmulc(dcoef[((size_t)(j0 + i) << logn) + c], cst.inv[i].x, cst.inv[i].y, pr[j0 + i].q);
+    }
+    double *out = ext + (size_t)j * E * N;
+    for (int t = 0; t < E - sz; ++t) {
+        const int m = ext_prime(t, j0, sz, lv, L);
+        const double qm = pr[m].q;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMaxAlpha; ++i) {
+            if (i < sz) acc = madd(acc, mmulc(y[i], cst.hat[i][m].x, cst.hat[i][m].y, qm), qm);
+        }
+        out[((size_t)t << logn) + c] = acc;
+    }
+}
+
+void launch_modup(const Launch &L, double *ext, const double *dcoef, int lv) {
+    pfx_ctx *ctx = L.ctx;
+    const int beta = (lv + ctx->alpha - 1) / ctx->alpha;
+    dim3 grid((ctx->N + 255) / 256, beta);
+    hipEvent_t ev;
+    prof_begin(L, "modup", &ev);
+    k_modup<<<grid, 256, 0, L.st>>>(ext, dcoef, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha, ctx->d_primes,
+                                    ctx->d_modup);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "modup", ev);
+}
+
+// acc_u[m] = sum_j dtilde_j[m] * swk_{j,u}[m]   (NTT domain)
+__global__ void k_ks_inner(double *acc, const double *ext, const double *d_ntt, const double *key, int lv, int logn,
+                           int L, int K, int alpha, const PrimeDev *pr) {
+    const int m = blockIdx.y;
+    const size_t N = (size_t)1 << logn;
+    const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    const int E = lv + K;
+    const int beta = (lv + alpha - 1) / alpha;
+    const int pid = m < lv ? m : L + (m - lv);
+    const int km = pid;
+    const double q = pr[pid].q, qi = pr[pid].qinv;
+    const size_t kstride = (size_t)(L + K) * N;
+    double a0 = 0.0, a1 = 0.0;
+    for (int j = 0; j < beta; ++j) {
+        const int j0 = j * alpha;
+        const int sz = min(alpha, lv - j0);
+        double x;
+        if (m >= j0 && m < j0 + sz) {
+            x = d_ntt[((size_t)m << logn) + c];
+        } else {
+            const int t = m < j0 ? m : m - sz;
+            x = ext[((size_t)j * E + t) * N + c];
+        }
+        const double k0 = key[(size_t)(2 * j) * kstride + ((size_t)km << logn) + c];
+        const double k1 = key[(size_t)(2 * j + 1) * kstride + ((size_t)km << logn) + c];
+        a0 = madd(a0, mmul(x, k0, q, qi), q);
+        a1 = madd(a1, mmul(x, k1, q, qi), q);
+    }
+    acc[((size_t)m << logn) + c] = a0;
+    acc[((size_t)(E + m) << logn) + c] = a1;
+}
+
+void launch_ks_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt, const double *key, int lv) {
+    pfx_ctx *ctx = L.ctx;
+    dim3 grid((ctx->N + 255) / 256, lv + ctx->K);
+    hipEvent_t ev;
+    prof_begin(L, "ks_inner", &ev);
+    k_ks_inner<<<grid, 256, 0, L.st>>>(acc, ext, d_ntt, key, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha,
+                                       ctx->d_primes);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "ks_inner", ev);
+}
+
+// ModDown, first half: r_k = [acc_u(p_k) + floor(P/2)]_{p_k} (coefficient domain);
+// tmp_u[i] = sum_k [r_k (P/p_k)^-1]_{p_k} (P/p_k) - floor(P/2) mod q_i.
+__global__ void k_moddown_conv(double *tmp, const double *acc, int lv, int logn, int L, int K, const PrimeDev *pr,
+                               const ModDownConst *md) {
+    const int u = blockIdx.y;
+    const size_t N = (size_t)1 << logn;
+    const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    const int E = lv + K;
+    double z[kMaxSpecial];   // K <= kMaxSpecial, fully unrolled so z stays in registers
+#pragma unroll
+    for (int k = 0; k < kMaxSpecial; ++k) {
+        if (k < K) {
+            const double pk = pr[L + k].q;
+            const double r = madd(acc[((size_t)(u * E + lv + k) << logn) + c], md->half[L + k], pk);
+            z[k] = mmulc(r, md->phat_inv[k].x, md->phat_inv[k].y, pk);
+        }
+    }
+    for (int i = 0; i < lv; ++i) {
+        const double q = pr[i].q;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMaxSpecial; ++k)
+            if (k < K) s = madd(s, mmulc(z[k], md->phat[k][i].x, md->phat[k][i].y, q), q);
+        // floor(P/2) sits on every coefficient of y = x + floor(P/2); the Q limbs
+        // of x are in the NTT domain, so it is taken out of the correction here,
+        // in the coefficient domain, before the correction's forward NTT.
+        tmp[((size_t)(u * lv + i) << logn) + c] = msub(s, md->half[i], q);
+    }
+}
+
+// out_u[i] = (acc_u[i] - NTT(tmp_u)[i]) * P^-1 (+ base_u[i])
+__global__ void k_moddown_final(double *out0, double *out1, const double *acc, const double *tmp,
+                                const double *base0, const double *base1, int lv, int logn, int K,
+                                const PrimeDev *pr, const ModDownConst *md) {
+    const size_t N = (size_t)1 << logn;
+    const size_t total = (size_t)2 * lv * N;
+    const int E = lv + K;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = idx & (N - 1);
+        const size_t li = idx >> logn;
+        const int i = (int)(li % lv);
+        const int u = (int)(li / lv);
+        const double q = pr[i].q;
+        double x = msub(acc[((size_t)(u * E + i) << logn) + c], tmp[idx], q);
+        x = mmulc(x, md->pinv[i].x, md->pinv[i].y, q);
+        const double *base = u ? base1 : base0;
+        if (base) x = madd(x, base[((size_t)i << logn) + c], q);
+        double *out = u ? out1 : out0;
+        out[((size_t)i << logn) + c] = x;
+    }
+}
+
+void launch_moddown_conv(const Launch &L, double *tmp, const double *acc, int lv) {
+    pfx_ctx *ctx = L.ctx;
+    dim3 grid((ctx->N + 255) / 256, 2);
+    hipEvent_t ev;
+    prof_begin(L, "moddown_conv", &ev);
+    k_moddown_conv<<<grid, 256, 0, L.st>>>(tmp, acc, lv, ctx->logn, ctx->L, ctx->K, ctx->d_primes, ctx->d_moddown);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "moddown_conv", ev);
+}
+
+void launch_moddown_final(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
+                          const double *base0, const double *base1, int lv) {
+    pfx_ctx *ctx = L.ctx;
+    const size_t total = (size_t)2 * lv * ctx->N;
+    hipEvent_t ev;
+    prof_begin(L, "moddown_final", &ev);
+    k_moddown_final<<<grid_for(total), 256, 0, L.st>>>(out0, out1, acc, tmp, base0, base1, lv, ctx->logn, ctx->K,
+                                                       ctx->d_primes, ctx->d_moddown);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "moddown_final", ev);
+}
+
+// ============================================================== keys, encryption
+// b[m] = -a[m] s[m] + e[m] + g_m sfrom[m] over all L + K primes (NTT domain);
+// g_m = [P]_{q_m} for the primes of digit `digit`, 0 elsewhere (P w_j reduced).
+__global__ void k_keygen_b(double *b, const double *a, const double *e, const double *s, const double *sfrom,
+                           int digit, int alpha, int L, int K, int logn, const PrimeDev *pr, const ModDownConst *md) {
+    const size_t total = (size_t)(L + K) << logn;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int m = (int)(idx >> logn);
+        const double q = pr[m].q, qi = pr[m].qinv;
+        double x = msub(e[idx], mmul(a[idx], s[idx], q, qi), q);
+        if (m < L && m >= digit * alpha && m < digit * alpha + alpha)
+            x = madd(x, mmulc(sfrom[idx], md->pmod[m].x, md->pmod[m].y, q), q);
+        b[idx] = x;
+    }
+}
+
+void launch_keygen_b(const Launch &L, double *b, const double *a, const double *e, const double *s,
+                     const double *sfrom, int digit) {
+    pfx_ctx *ctx = L.ctx;
+    const size_t total = (size_t)(ctx->L + ctx->K) << ctx->logn;
+    k_keygen_b<<<grid_for(total), 256, 0, L.st>>>(b, a, e, s, sfrom, digit, ctx->alpha, ctx->L, ctx->K, ctx->logn,
+                                                  ctx->d_primes, ctx->d_moddown);
+    HIP_LAUNCH_CHECK();
+}
+
+// c0 = -a s + e + m  (NTT domain, lv limbs)
+__global__ void k_encrypt(double *c0, const double *a, const double *e, const double *s, const double *m, int lv,
+                          int logn, const PrimeDev *pr) {
+    const size_t total = (size_t)lv << logn;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx >> logn);
+        const double q = pr[i].q, qi = pr[i].qinv;
+        c0[idx] = madd(msub(e[idx], mmul(a[idx], s[idx], q, qi), q), m[idx], q);
+    }
+}
+
+void launch_encrypt(const Launch &L, double *c0, const double *a, const double *e, const double *s, const double *m,
+                    int lv) {
+    const size_t total = (size_t)lv << L.ctx->logn;
+    k_encrypt<<<grid_for(total), 256, 0, L.st>>>(c0, a, e, s, m, lv, L.ctx->logn, L.ctx->d_primes);
+    HIP_LAUNCH_CHECK();
+}
+
+// m = c0 + c1 s (+ c2 s^2)
+__global__ void k_decrypt(double *m, const double *c0, const double *c1, const double *c2, const double *s, int lv,
+                          int logn, const PrimeDev *pr) {
+    const size_t total = (size_t)lv << logn;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx >> logn);
+        const double q = pr[i].q, qi = pr[i].qinv;
+        const double sv = s[idx];
+        double x = madd(c0[idx], mmul(c1[idx], sv, q, qi), q);
+        if (c2) x = madd(x, mmul(mmul(c2[idx], sv, q, qi), sv, q, qi), q);
+        m[idx] = x;
+    }
+}
+
+void launch_decrypt(const Launch &L, double *m, const double *c0, const double *c1, const double *c2, const double *s,
+                    int lv) {
+    const size_t total = (size_t)lv << L.ctx->logn;
+    k_decrypt<<<grid_for(total), 256, 0, L.st>>>(m, c0, c1, c2, s, lv, L.ctx->logn, L.ctx->d_primes);
+    HIP_LAUNCH_CHECK();
+}
+
+}  // namespace pfx

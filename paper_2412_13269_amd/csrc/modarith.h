@@ -1,0 +1,66 @@
+// Modular arithmetic on FP64 for primes below 2^50.
+//
+// Residues are exact integers held in doubles.  CDNA4 runs FP64 FMA at the
+// full vector rate, while a 64x64->128-bit integer product needs several
+// quarter-rate 32-bit multiplies, so the products below take the
+// error-free-transformation route:
+//
+//   a*b = h + l exactly, with h = fl(a*b) and l = fma(a, b, -h);
+//   c   = round-to-nearest of an estimate of a*b/q, off by at most 0.875;
+//   r   = fma(-c, q, h) + l = a*b - c*q exactly (|r| < q, an integer < 2^53);
+//   r   += q if negative.
+//
+// Bounds, for a < 2^50 and b < q < 2^50: |h - a*b| <= 2^46, so h - c*q and
+// r are integers below 2^51 in magnitude and every step above is exact.  The
+// estimate c uses either fl(fl(a*b) * fl(1/q)) (three roundings, error at most
+// 2^50 * 3 * 2^-53 = 0.375) or, for a constant b with bq = fl(b/q) prepared in
+// advance, fl(a * bq) (two roundings, error at most 0.25).  Either way
+// |a*b/q - c| < 1, so one conditional add of q lands r in [0, q).
+//
+// The first operand may be any integer below 2^50 (it need not be reduced
+// modulo q); the second must be below q.  Compiled with -ffp-contract=off so
+// that no multiply-add is fused other than the explicit fma calls.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace pfx {
+
+__device__ __forceinline__ double madd(double a, double b, double q) {
+    double s = a + b;
+    return s >= q ? s - q : s;
+}
+
+__device__ __forceinline__ double msub(double a, double b, double q) {
+    double s = a - b;
+    return s < 0.0 ? s + q : s;
+}
+
+__device__ __forceinline__ double mneg(double a, double q) { return a == 0.0 ? 0.0 : q - a; }
+
+// a * b mod q, both operands variable; qinv = fl(1/q).
+__device__ __forceinline__ double mmul(double a, double b, double q, double qinv) {
+    double h = a * b;
+    double l = __builtin_fma(a, b, -h);
+    double c = __builtin_rint(h * qinv);
+    double r = __builtin_fma(-c, q, h) + l;
+    return r < 0.0 ? r + q : r;
+}
+
+// a * w mod q for a constant w < q with wq = fl(w / q).
+__device__ __forceinline__ double mmulc(double a, double w, double wq, double q) {
+    double h = a * w;
+    double l = __builtin_fma(a, w, -h);
+    double c = __builtin_rint(a * wq);
+    double r = __builtin_fma(-c, q, h) + l;
+    return r < 0.0 ? r + q : r;
+}
+
+// x mod q for an integer 0 <= x < 2^50 (x may exceed q by any factor).
+__device__ __forceinline__ double mred(double x, double q, double qinv) {
+    double c = __builtin_floor(x * qinv);
+    double r = __builtin_fma(-c, q, x);
+    r = r < 0.0 ? r + q : r;
+    return r >= q ? r - q : r;
+}
+
+}  // namespace pfx

@@ -1,0 +1,443 @@
+"""Python binding of libpfx.so (ctypes): the C-ABI of include/pfx.h under the
+same names, with argument marshalling only.  Every step of the evaluation
+runs in the library's HIP kernels; nothing here computes on the data.
+
+Importing this module loads the in-tree ``libpfx.so`` and raises
+``ImportError`` if it is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpfx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libpfx.so is not built at {LIB_PATH}; run __graft_entry__.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+PFX_OK, PFX_EINVAL, PFX_EPARAM, PFX_ELEVEL, PFX_ESCALE = 0, -1, -2, -3, -4
+PFX_ENOKEY, PFX_ENOMEM, PFX_EBUSY, PFX_EDEVICE = -5, -6, -7, -8
+MAX_PRIMES = 64
+
+
+class PfxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pfx error {status}: {msg}")
+        self.status = status
+
+
+class pfx_params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32),
+                ("q_bits", ctypes.c_uint32 * MAX_PRIMES), ("n_p", ctypes.c_uint32),
+                ("p_bits", ctypes.c_uint32 * MAX_PRIMES), ("alpha", ctypes.c_uint32),
+                ("mod_log2", ctypes.c_uint32)]
+
+
+class pfx_info(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_limbs", ctypes.c_uint32),
+                ("degree", ctypes.c_uint32), ("scale", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i8p = ctypes.POINTER(ctypes.c_int8)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_u32, _i32, _sz, _i64 = ctypes.c_uint32, ctypes.c_int32, ctypes.c_size_t, ctypes.c_int64
+_PP = ctypes.POINTER(pfx_params)
+_IP = ctypes.POINTER(pfx_info)
+_VPP = ctypes.POINTER(ctypes.c_void_p)
+
+_SIGS = {
+    "pfx_status_str": (ctypes.c_char_p, [_i32]),
+    "pfx_last_error": (ctypes.c_char_p, []),
+    "pfx_params_primes": (_i32, [_PP, _u64p, _u64p, _u64p]),
+    "pfx_encode_words": (_i32, [_PP, _f64p, _f64p, _sz, _u32, ctypes.c_double, _u64p]),
+    "pfx_decode_words": (_i32, [_PP, _u64p, _u32, ctypes.c_double, _f64p, _f64p, _sz]),
+    "pfx_ctx_create": (_i32, [_PP, ctypes.c_int, _VPP]),
+    "pfx_ctx_destroy": (None, [_vp]),
+    "pfx_ctx_moduli": (_i32, [_vp, _u64p, _u64p, _u64p]),
+    "pfx_sync": (_i32, [_vp, _vp]),
+    "pfx_sk_create": (_i32, [_vp, _i8p, _VPP]),
+    "pfx_sk_destroy": (None, [_vp]),
+    "pfx_swk_create": (_i32, [_vp, _vp, _u32, _u64p, _i64p, _VPP]),
+    "pfx_swk_export": (_i32, [_vp, _vp, _u64p, _sz]),
+    "pfx_swk_galois": (_u32, [_vp]),
+    "pfx_swk_destroy": (None, [_vp]),
+    "pfx_encode": (_i32, [_vp, _f64p, _f64p, _sz, _u32, ctypes.c_double, _VPP]),
+    "pfx_decode": (_i32, [_vp, _vp, _f64p, _f64p, _sz]),
+    "pfx_pt_import": (_i32, [_vp, _u64p, _u32, ctypes.c_double, _VPP]),
+    "pfx_encrypt": (_i32, [_vp, _vp, _vp, _u64p, _i64p, _vp, _vp]),
+    "pfx_decrypt": (_i32, [_vp, _vp, _vp, _VPP, _vp]),
+    "pfx_ct_create": (_i32, [_vp, _u32, _u32, _VPP]),
+    "pfx_ct_destroy": (None, [_vp]),
+    "pfx_ct_info": (_i32, [_vp, _IP]),
+    "pfx_ct_set_scale": (_i32, [_vp, ctypes.c_double]),
+    "pfx_ct_import": (_i32, [_vp, _u64p, _u32, _u32, ctypes.c_double, _vp, _vp]),
+    "pfx_ct_export": (_i32, [_vp, _vp, _u64p, _sz, _IP, _vp]),
+    "pfx_ct_copy": (_i32, [_vp, _vp, _vp, _vp]),
+    "pfx_add": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_sub": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_neg": (_i32, [_vp, _vp, _vp, _vp]),
+    "pfx_add_plain": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_mul_plain": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_mul_int": (_i32, [_vp, _vp, _i64, _vp, _vp]),
+    "pfx_mul": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_relinearize": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_mul_relin": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pfx_rescale": (_i32, [_vp, _vp, _vp, _vp]),
+    "pfx_drop_level": (_i32, [_vp, _vp, _u32, _vp, _vp]),
+    "pfx_key_switch": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_apply_galois": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_rotate": (_i32, [_vp, _vp, _i32, _VPP, _sz, _vp, _vp]),
+    "pfx_conjugate": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp]),
+    "pfx_rotate_sum": (_i32, [_vp, _vp, _u32, _VPP, _sz, _vp, _vp]),
+    "pfx_ntt": (_i32, [_vp, _vp, _u32, _u32, _sz, ctypes.c_int, _vp]),
+    "pfx_dev_alloc": (_i32, [_vp, _sz, _VPP]),
+    "pfx_dev_free": (_i32, [_vp, _vp]),
+    "pfx_memcpy_htod": (_i32, [_vp, _vp, _vp, _sz, _vp]),
+    "pfx_memcpy_dtoh": (_i32, [_vp, _vp, _vp, _sz, _vp]),
+    "pfx_stream_create": (_i32, [_vp, _VPP]),
+    "pfx_stream_destroy": (_i32, [_vp, _vp]),
+    "pfx_profile_enable": (_i32, [_vp, ctypes.c_int]),
+    "pfx_profile_get": (_i32, [_vp, ctypes.c_char_p, _u64p, _f64p]),
+    "pfx_profile_names": (_i32, [_vp, ctypes.c_char_p, _sz]),
+    "pfx_profile_reset": (_i32, [_vp]),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(st: int):
+    if st != PFX_OK:
+        raise PfxError(st, _lib.pfx_last_error().decode())
+
+
+def _u64(a):
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return a, a.ctypes.data_as(_u64p)
+
+
+def _i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(_i64p)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_f64p)
+
+
+def _stream(s):
+    return None if s is None else ctypes.c_void_p(int(s))
+
+
+def _keys(keys):
+    arr = (ctypes.c_void_p * max(1, len(keys)))(*[k for k in keys])
+    return arr, len(keys)
+
+
+def make_params(log_n, q_bits, p_bits, alpha, mod_log2=0) -> pfx_params:
+    p = pfx_params()
+    p.log_n, p.n_q, p.n_p, p.alpha, p.mod_log2 = log_n, len(q_bits), len(p_bits), alpha, mod_log2
+    for i, b in enumerate(q_bits):
+        p.q_bits[i] = b
+    for i, b in enumerate(p_bits):
+        p.p_bits[i] = b
+    return p
+
+
+# ---------------------------------------------------------------- host only
+def pfx_status_str(st: int) -> str:
+    return _lib.pfx_status_str(st).decode()
+
+
+def pfx_params_primes(prm: pfx_params):
+    q = np.zeros(prm.n_q, np.uint64)
+    p = np.zeros(prm.n_p, np.uint64)
+    psi = np.zeros(prm.n_q + prm.n_p, np.uint64)
+    _check(_lib.pfx_params_primes(ctypes.byref(prm), _u64(q)[1], _u64(p)[1], _u64(psi)[1]))
+    return q, p, psi
+
+
+def pfx_encode_words(prm: pfx_params, re, im, n_limbs: int, scale: float) -> np.ndarray:
+    re_a, re_p = _f64(re)
+    im_a, im_p = (None, None) if im is None else _f64(im)
+    out = np.zeros((n_limbs, 1 << prm.log_n), np.uint64)
+    _check(_lib.pfx_encode_words(ctypes.byref(prm), re_p, im_p, len(re_a), n_limbs, scale, _u64(out)[1]))
+    return out
+
+
+def pfx_decode_words(prm: pfx_params, words, scale: float, n_slots: int) -> np.ndarray:
+    w, wp = _u64(words)
+    re = np.zeros(n_slots)
+    im = np.zeros(n_slots)
+    _check(_lib.pfx_decode_words(ctypes.byref(prm), wp, w.shape[0], scale, _f64(re)[1], _f64(im)[1], n_slots))
+    return re + 1j * im
+
+
+# ---------------------------------------------------------------- context and keys
+def pfx_ctx_create(prm: pfx_params, device: int = 0):
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_ctx_create(ctypes.byref(prm), device, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_ctx_destroy(ctx):
+    _lib.pfx_ctx_destroy(ctx)
+
+
+def pfx_ctx_moduli(ctx, n_q: int, n_p: int):
+    q = np.zeros(n_q, np.uint64)
+    p = np.zeros(n_p, np.uint64)
+    psi = np.zeros(n_q + n_p, np.uint64)
+    _check(_lib.pfx_ctx_moduli(ctx, _u64(q)[1], _u64(p)[1], _u64(psi)[1]))
+    return q, p, psi
+
+
+def pfx_sync(ctx, stream=None):
+    _check(_lib.pfx_sync(ctx, _stream(stream)))
+
+
+def pfx_sk_create(ctx, s):
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_sk_create(ctx, s.ctypes.data_as(_i8p), ctypes.byref(h)))
+    return h.value
+
+
+def pfx_sk_destroy(sk):
+    _lib.pfx_sk_destroy(sk)
+
+
+def pfx_swk_create(ctx, sk, galois: int, a, e):
+    a_, ap = _u64(a)
+    e_, ep = _i64(e)
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_swk_create(ctx, sk, galois, ap, ep, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_swk_export(ctx, k, beta: int, n_primes: int, n: int) -> np.ndarray:
+    out = np.zeros((beta, 2, n_primes, n), np.uint64)
+    _check(_lib.pfx_swk_export(ctx, k, _u64(out)[1], out.size))
+    return out
+
+
+def pfx_swk_galois(k) -> int:
+    return _lib.pfx_swk_galois(k)
+
+
+def pfx_swk_destroy(k):
+    _lib.pfx_swk_destroy(k)
+
+
+# ---------------------------------------------------------------- plaintexts, encryption
+def pfx_encode(ctx, re, im, n_limbs: int, scale: float):
+    re_a, re_p = _f64(re)
+    im_a, im_p = (None, None) if im is None else _f64(im)
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_encode(ctx, re_p, im_p, len(re_a), n_limbs, scale, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_decode(ctx, pt, n_slots: int) -> np.ndarray:
+    re = np.zeros(n_slots)
+    im = np.zeros(n_slots)
+    _check(_lib.pfx_decode(ctx, pt, _f64(re)[1], _f64(im)[1], n_slots))
+    return re + 1j * im
+
+
+def pfx_pt_import(ctx, words, scale: float):
+    w, wp = _u64(words)
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_pt_import(ctx, wp, w.shape[0], scale, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_encrypt(ctx, sk, pt, a, e, out, stream=None):
+    a_, ap = _u64(a)
+    e_, ep = _i64(e)
+    _check(_lib.pfx_encrypt(ctx, sk, pt, ap, ep, out, _stream(stream)))
+
+
+def pfx_decrypt(ctx, sk, ct, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_decrypt(ctx, sk, ct, ctypes.byref(h), _stream(stream)))
+    return h.value
+
+
+# ---------------------------------------------------------------- ciphertexts
+def pfx_ct_create(ctx, cap_limbs: int, cap_degree: int = 1):
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_ct_create(ctx, cap_limbs, cap_degree, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_ct_destroy(ct):
+    _lib.pfx_ct_destroy(ct)
+
+
+def pfx_ct_info(ct) -> pfx_info:
+    info = pfx_info()
+    _check(_lib.pfx_ct_info(ct, ctypes.byref(info)))
+    return info
+
+
+def pfx_ct_set_scale(ct, scale: float):
+    _check(_lib.pfx_ct_set_scale(ct, scale))
+
+
+def pfx_ct_import(ctx, words, scale: float, out, stream=None):
+    w, wp = _u64(words)
+    assert w.ndim == 3
+    _check(_lib.pfx_ct_import(ctx, wp, w.shape[1], w.shape[0] - 1, scale, out, _stream(stream)))
+
+
+def pfx_ct_export(ctx, ct, n: int, stream=None) -> np.ndarray:
+    info = pfx_ct_info(ct)
+    out = np.zeros((info.degree + 1, info.n_limbs, n), np.uint64)
+    _check(_lib.pfx_ct_export(ctx, ct, _u64(out)[1], out.size, None, _stream(stream)))
+    return out
+
+
+def pfx_ct_copy(ctx, src, dst, stream=None):
+    _check(_lib.pfx_ct_copy(ctx, src, dst, _stream(stream)))
+
+
+# ---------------------------------------------------------------- evaluation
+def pfx_add(ctx, a, b, out, stream=None):
+    _check(_lib.pfx_add(ctx, a, b, out, _stream(stream)))
+
+
+def pfx_sub(ctx, a, b, out, stream=None):
+    _check(_lib.pfx_sub(ctx, a, b, out, _stream(stream)))
+
+
+def pfx_neg(ctx, a, out, stream=None):
+    _check(_lib.pfx_neg(ctx, a, out, _stream(stream)))
+
+
+def pfx_add_plain(ctx, a, m, out, stream=None):
+    _check(_lib.pfx_add_plain(ctx, a, m, out, _stream(stream)))
+
+
+def pfx_mul_plain(ctx, a, m, out, stream=None):
+    _check(_lib.pfx_mul_plain(ctx, a, m, out, _stream(stream)))
+
+
+def pfx_mul_int(ctx, a, k: int, out, stream=None):
+    _check(_lib.pfx_mul_int(ctx, a, k, out, _stream(stream)))
+
+
+def pfx_mul(ctx, a, b, out, stream=None):
+    _check(_lib.pfx_mul(ctx, a, b, out, _stream(stream)))
+
+
+def pfx_relinearize(ctx, a, rlk, out, stream=None):
+    _check(_lib.pfx_relinearize(ctx, a, rlk, out, _stream(stream)))
+
+
+def pfx_mul_relin(ctx, a, b, rlk, out, stream=None):
+    _check(_lib.pfx_mul_relin(ctx, a, b, rlk, out, _stream(stream)))
+
+
+def pfx_rescale(ctx, a, out, stream=None):
+    _check(_lib.pfx_rescale(ctx, a, out, _stream(stream)))
+
+
+def pfx_drop_level(ctx, a, n_limbs: int, out, stream=None):
+    _check(_lib.pfx_drop_level(ctx, a, n_limbs, out, _stream(stream)))
+
+
+def pfx_key_switch(ctx, d, k, out, stream=None):
+    _check(_lib.pfx_key_switch(ctx, d, k, out, _stream(stream)))
+
+
+def pfx_apply_galois(ctx, a, gk, out, stream=None):
+    _check(_lib.pfx_apply_galois(ctx, a, gk, out, _stream(stream)))
+
+
+def pfx_rotate(ctx, a, step: int, keys, out, stream=None):
+    arr, n = _keys(keys)
+    _check(_lib.pfx_rotate(ctx, a, step, arr, n, out, _stream(stream)))
+
+
+def pfx_conjugate(ctx, a, keys, out, stream=None):
+    arr, n = _keys(keys)
+    _check(_lib.pfx_conjugate(ctx, a, arr, n, out, _stream(stream)))
+
+
+def pfx_rotate_sum(ctx, a, log_steps: int, keys, out, stream=None):
+    arr, n = _keys(keys)
+    _check(_lib.pfx_rotate_sum(ctx, a, log_steps, arr, n, out, _stream(stream)))
+
+
+def pfx_ntt(ctx, d_words_ptr: int, first_prime: int, n_limbs: int, batch: int, inverse: bool, stream=None):
+    _check(_lib.pfx_ntt(ctx, ctypes.c_void_p(d_words_ptr), first_prime, n_limbs, batch, int(inverse),
+                        _stream(stream)))
+
+
+# ---------------------------------------------------------------- plumbing
+def pfx_dev_alloc(ctx, nbytes: int) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_dev_alloc(ctx, nbytes, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_dev_free(ctx, ptr: int):
+    _check(_lib.pfx_dev_free(ctx, ctypes.c_void_p(ptr)))
+
+
+def pfx_memcpy_htod(ctx, dst: int, arr: np.ndarray, stream=None):
+    arr = np.ascontiguousarray(arr)
+    _check(_lib.pfx_memcpy_htod(ctx, ctypes.c_void_p(dst), arr.ctypes.data_as(_vp), arr.nbytes, _stream(stream)))
+
+
+def pfx_memcpy_dtoh(ctx, arr: np.ndarray, src: int, stream=None):
+    assert arr.flags["C_CONTIGUOUS"]
+    _check(_lib.pfx_memcpy_dtoh(ctx, arr.ctypes.data_as(_vp), ctypes.c_void_p(src), arr.nbytes, _stream(stream)))
+
+
+def pfx_stream_create(ctx) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_stream_create(ctx, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_stream_destroy(ctx, stream: int):
+    _check(_lib.pfx_stream_destroy(ctx, ctypes.c_void_p(stream)))
+
+
+# ---------------------------------------------------------------- profiling
+def pfx_profile_enable(ctx, on: bool = True):
+    _check(_lib.pfx_profile_enable(ctx, int(on)))
+
+
+def pfx_profile_get(ctx, kernel: str):
+    n = ctypes.c_uint64()
+    ms = ctypes.c_double()
+    _check(_lib.pfx_profile_get(ctx, kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def pfx_profile_names(ctx):
+    buf = ctypes.create_string_buffer(8192)
+    _check(_lib.pfx_profile_names(ctx, buf, len(buf)))
+    return [s for s in buf.value.decode().split("\n") if s]
+
+
+def pfx_profile_reset(ctx):
+    _check(_lib.pfx_profile_reset(ctx))

@@ -1,0 +1,302 @@
+"""GPU parity: every call of the C-ABI against the CPU oracle, word for word.
+
+Both sides take the same seeded inputs (secret, uniform `a`, errors, encoded
+plaintext words from the oracle) and must produce identical canonical
+coefficient-domain words.  Decrypted values are also checked against FP64.
+"""
+import numpy as np
+import pytest
+
+from oracle import ckks as O
+from paper_2412_13269_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_2412_13269_amd import pfx   # fails loudly if libpfx.so is missing
+    return pfx
+
+
+class Pair:
+    """Oracle and library contexts on one parameter set, with shared inputs."""
+
+    def __init__(self, X, logn, qb, pb, alpha, ml=0, h=None, seed=1, scale=2.0 ** 45):
+        self.X = X
+        self.P = O.Params(logn, qb, pb, alpha=alpha, mod_log2=ml)
+        self.prm = X.make_params(logn, qb, pb, alpha, ml)
+        self.ctx = X.pfx_ctx_create(self.prm, 0)
+        self.N = self.P.N
+        self.scale = scale
+        self.s = I.ternary_secret(self.N, h, seed)
+        self.sk = X.pfx_sk_create(self.ctx, self.s)
+        self.ko, self.kx = {}, {}
+        self.seed = seed * 1000
+        self.handles = []
+
+    def _next(self):
+        self.seed += 7
+        return self.seed
+
+    def key(self, g):
+        if g not in self.ko:
+            ext = self.P.ext_mods(self.P.L)
+            a = I.uniform_residues(ext, self.N, self._next(), lead=(self.P.beta,))
+            e = I.gaussian_error((self.P.beta, self.N), self._next())
+            self.ko[g] = O.relin_key(self.P, self.s, a, e) if g == 0 else O.galois_key(self.P, self.s, g, a, e)
+            self.kx[g] = self.X.pfx_swk_create(self.ctx, self.sk, g, a, e)
+        return self.ko[g], self.kx[g]
+
+    def ct(self, lv, cap=None, deg=2):
+        h = self.X.pfx_ct_create(self.ctx, cap or self.P.L, deg)
+        self.handles.append(h)
+        return h
+
+    def enc(self, lv, seed=None, z=None):
+        z = I.uniform_slots(self.N // 2, seed or self._next()) if z is None else z
+        m = O.encode(self.P, z, self.scale, lv)
+        a = I.uniform_residues(self.P.mods(lv), self.N, self._next())
+        e = I.gaussian_error(self.N, self._next())
+        co = O.encrypt(self.P, self.s, m, a, e, self.scale)
+        pt = self.X.pfx_pt_import(self.ctx, m, self.scale)
+        self.handles.append(pt)
+        cx = self.ct(lv)
+        self.X.pfx_encrypt(self.ctx, self.sk, pt, a, e, cx)
+        return co, cx, z
+
+    def words(self, cx):
+        return self.X.pfx_ct_export(self.ctx, cx, self.N)
+
+    def same(self, co, cx):
+        w = self.words(cx)
+        assert w.shape == co.c.shape, (w.shape, co.c.shape)
+        assert np.array_equal(w, co.c)
+        info = self.X.pfx_ct_info(cx)
+        assert info.scale == pytest.approx(co.scale, rel=1e-15)
+
+    def close(self):
+        for h in self.handles:
+            self.X.pfx_ct_destroy(h)
+        for k in self.kx.values():
+            self.X.pfx_swk_destroy(k)
+        self.X.pfx_sk_destroy(self.sk)
+        self.X.pfx_ctx_destroy(self.ctx)
+
+
+CONFIGS = {
+    # config 1: N = 2^12, three 50-bit primes, one special prime, digits of one prime
+    "c1": dict(logn=12, qb=[50, 50, 50], pb=[50], alpha=1, ml=0, h=None, scale=2.0 ** 40),
+    # config-2 chain shape at N = 2^13 with 9 limbs: a partial last digit (9 = 4 + 4 + 1)
+    "c2s": dict(logn=13, qb=[50] + [45] * 8, pb=[50] * 4, alpha=4, ml=17, h=192, scale=2.0 ** 45),
+}
+
+
+@pytest.fixture(scope="module", params=list(CONFIGS))
+def pair(request, X):
+    cfg = CONFIGS[request.param]
+    p = Pair(X, cfg["logn"], cfg["qb"], cfg["pb"], cfg["alpha"], cfg["ml"], cfg["h"], seed=11,
+             scale=cfg["scale"])
+    yield p
+    p.close()
+
+
+# ------------------------------------------------------------------ transforms and plumbing
+def test_moduli_match(pair, X):
+    q, p, psi = X.pfx_ctx_moduli(pair.ctx, pair.P.L, pair.P.K)
+    assert [int(v) for v in q] == pair.P.q and [int(v) for v in p] == pair.P.p
+    assert [int(v) for v in psi] == pair.P.psi_q + pair.P.psi_p
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+def test_standalone_ntt(pair, X, inverse):
+    P = pair.P
+    nl = P.L + P.K
+    batch = 2
+    words = I.uniform_residues(P.q + P.p, P.N, 5, lead=(batch,))
+    dev = X.pfx_dev_alloc(pair.ctx, words.nbytes)
+    X.pfx_memcpy_htod(pair.ctx, dev, words)
+    X.pfx_ntt(pair.ctx, dev, 0, nl, batch, inverse)
+    got = np.empty_like(words)
+    X.pfx_memcpy_dtoh(pair.ctx, got, dev)
+    X.pfx_dev_free(pair.ctx, dev)
+    fn = O.intt if inverse else O.ntt
+    for b in range(batch):
+        assert np.array_equal(got[b], fn(words[b], P.q + P.p, P.psi_q + P.psi_p, P.logn))
+
+
+def test_import_export_roundtrip(pair, X):
+    P = pair.P
+    w = I.uniform_residues(P.mods(P.L), P.N, 6, lead=(3,))
+    cx = pair.ct(P.L)
+    X.pfx_ct_import(pair.ctx, w, 3.0, cx)
+    assert np.array_equal(pair.words(cx), w)
+
+
+def test_keygen_parity(pair, X):
+    P = pair.P
+    for g in (0, O.galois_element(P, 1), 2 * P.N - 1):
+        ko, kx = pair.key(g)
+        got = X.pfx_swk_export(pair.ctx, kx, P.beta, P.L + P.K, P.N)
+        assert np.array_equal(got[:, 0], ko.b)
+        assert np.array_equal(got[:, 1], ko.a)
+
+
+def test_encrypt_decrypt_parity(pair, X):
+    P = pair.P
+    co, cx, z = pair.enc(P.L)
+    pair.same(co, cx)
+    mx = X.pfx_decrypt(pair.ctx, pair.sk, cx)
+    pair.handles.append(mx)
+    assert np.array_equal(pair.words(mx)[0], O.decrypt(P, pair.s, co))
+    got = X.pfx_decode(pair.ctx, mx, P.N // 2)
+    assert np.max(np.abs(got - z)) < 2.0 ** -20
+
+
+# ------------------------------------------------------------------ arithmetic
+def test_elementwise_ops(pair, X):
+    P = pair.P
+    lv = P.L
+    c1o, c1x, z1 = pair.enc(lv)
+    c2o, c2x, z2 = pair.enc(lv - 1)          # mixed levels: drops to lv - 1
+    out = pair.ct(lv)
+    X.pfx_add(pair.ctx, c1x, c2x, out)
+    pair.same(O.ct_add(P, c1o, c2o), out)
+    X.pfx_sub(pair.ctx, c1x, c2x, out)
+    pair.same(O.ct_sub(P, c1o, c2o), out)
+    X.pfx_neg(pair.ctx, c1x, out)
+    pair.same(O.Ct(np.stack([O.neg(c, P.mods(lv)) for c in c1o.c]), c1o.scale), out)
+    for k in (3, -5, 0, 1 << 40):
+        X.pfx_mul_int(pair.ctx, c1x, k, out)
+        pair.same(O.ct_mul_int(P, c1o, k), out)
+    m = O.encode(P, I.uniform_slots(P.N // 2, 40), pair.scale, lv)
+    pt = X.pfx_pt_import(pair.ctx, m, pair.scale)
+    pair.handles.append(pt)
+    X.pfx_mul_plain(pair.ctx, c1x, pt, out)
+    pair.same(O.ct_mul_plain(P, c1o, m, pair.scale), out)
+    X.pfx_add_plain(pair.ctx, c1x, pt, out)
+    pair.same(O.ct_add_plain(P, c1o, m), out)
+    # in place
+    X.pfx_add(pair.ctx, c1x, c1x, c1x)
+    pair.same(O.ct_add(P, c1o, c1o), c1x)
+
+
+def test_tensor_relinearize(pair, X):
+    P = pair.P
+    ko, kx = pair.key(0)
+    c1o, c1x, z1 = pair.enc(P.L)
+    c2o, c2x, z2 = pair.enc(P.L)
+    t = pair.ct(P.L)
+    X.pfx_mul(pair.ctx, c1x, c2x, t)
+    to = O.tensor(P, c1o, c2o)
+    pair.same(to, t)
+    r = pair.ct(P.L)
+    X.pfx_relinearize(pair.ctx, t, kx, r)
+    ro = O.relinearize(P, to, ko)
+    pair.same(ro, r)
+    X.pfx_mul_relin(pair.ctx, c1x, c2x, kx, c1x)     # output aliases an input
+    pair.same(ro, c1x)
+    dec = X.pfx_decrypt(pair.ctx, pair.sk, c1x)
+    pair.handles.append(dec)
+    assert np.max(np.abs(X.pfx_decode(pair.ctx, dec, P.N // 2) - z1 * z2)) < 2.0 ** -20
+
+
+def test_rescale_every_level(pair, X):
+    P = pair.P
+    co, cx, z = pair.enc(P.L)
+    for lv in range(P.L, 1, -1):
+        X.pfx_rescale(pair.ctx, cx, cx)
+        co = O.rescale(P, co)
+        pair.same(co, cx)
+    with pytest.raises(X.PfxError) as e:
+        X.pfx_rescale(pair.ctx, cx, cx)
+    assert e.value.status == X.PFX_ELEVEL
+
+
+def test_key_switch_at_partial_levels(pair, X):
+    P = pair.P
+    ko, kx = pair.key(0)
+    for lv in sorted({1, 2, 3, min(5, P.L), P.L}):
+        d = I.uniform_residues(P.mods(lv), P.N, 100 + lv)
+        dx = pair.ct(lv)
+        X.pfx_ct_import(pair.ctx, d[None], 1.0, dx)
+        out = pair.ct(lv)
+        X.pfx_key_switch(pair.ctx, dx, kx, out)
+        k0, k1 = O.key_switch(P, d, ko)
+        w = pair.words(out)
+        assert np.array_equal(w[0], k0) and np.array_equal(w[1], k1), lv
+
+
+def test_rotations_and_conjugation(pair, X):
+    P = pair.P
+    co, cx, z = pair.enc(P.L)
+    out = pair.ct(P.L)
+    keys = []
+    for step in (1, 7, -1):
+        g = O.galois_element(P, step)
+        ko, kx = pair.key(g)
+        keys.append(kx)
+        X.pfx_rotate(pair.ctx, cx, step, keys, out)
+        ro = O.rotate(P, co, step, {g: ko})
+        pair.same(ro, out)
+    gc = 2 * P.N - 1
+    ko, kx = pair.key(gc)
+    X.pfx_conjugate(pair.ctx, cx, [kx], out)
+    pair.same(O.conjugate(P, co, {gc: ko}), out)
+    with pytest.raises(X.PfxError) as e:
+        X.pfx_rotate(pair.ctx, cx, 3, keys, out)
+    assert e.value.status == X.PFX_ENOKEY
+
+
+def test_rotate_sum(pair, X):
+    P = pair.P
+    co, cx, z = pair.enc(P.L)
+    keys_o, keys_x = {}, []
+    for k in range(3):
+        g = O.galois_element(P, 1 << k)
+        ko, kx = pair.key(g)
+        keys_o[g] = ko
+        keys_x.append(kx)
+    out = pair.ct(P.L)
+    X.pfx_rotate_sum(pair.ctx, cx, 3, keys_x, out)
+    pair.same(O.rotate_sum(P, co, 3, keys_o), out)
+
+
+def test_scale_mismatch_is_rejected(pair, X):
+    P = pair.P
+    c1o, c1x, _ = pair.enc(P.L)
+    c2o, c2x, _ = pair.enc(P.L)
+    X.pfx_ct_set_scale(c2x, pair.scale * 1.01)
+    with pytest.raises(X.PfxError) as e:
+        X.pfx_add(pair.ctx, c1x, c2x, c1x)
+    assert e.value.status == X.PFX_ESCALE
+
+
+# ------------------------------------------------------------------ full size (N = 2^16, L = 24)
+@pytest.fixture(scope="module")
+def full(X):
+    p = Pair(X, 16, [50] + [45] * 23, [50] * 4, 4, 17, h=192, seed=201)
+    yield p
+    p.close()
+
+
+def test_full_size_mul_relin_rescale_rotate(full, X):
+    P = full.P
+    ko, kx = full.key(0)
+    g = O.galois_element(P, 1)
+    go, gx = full.key(g)
+    c1o, c1x, z1 = full.enc(24)
+    c2o, c2x, z2 = full.enc(24)
+    X.pfx_mul_relin(full.ctx, c1x, c2x, kx, c1x)
+    c1o = O.mul_relin(P, c1o, c2o, ko)
+    full.same(c1o, c1x)
+    X.pfx_rescale(full.ctx, c1x, c1x)
+    c1o = O.rescale(P, c1o)
+    full.same(c1o, c1x)
+    out = full.ct(24)
+    X.pfx_rotate(full.ctx, c1x, 1, [gx], out)
+    full.same(O.rotate(P, c1o, 1, {g: go}), out)
+    dec = X.pfx_decrypt(full.ctx, full.sk, out)
+    full.handles.append(dec)
+    got = X.pfx_decode(full.ctx, dec, P.N // 2)
+    assert np.max(np.abs(got - np.roll(z1 * z2, -1))) < 2.0 ** -20
