@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Key-switching throughput of the RNS-CKKS path on one MI355X.
+
+Workload (single-ciphertext kernel bench): N = 2^16, L = 24 ciphertext primes
+(one 50-bit, 23 near 2^45), K = 4 special primes of 50 bits, digits of 4
+primes (dnum = 6), scale 2^45, secret with 192 non-zeros, 2^15 real slots
+uniform in [-1, 1].  One step runs every operation of the path once on device-
+resident inputs: forward and inverse NTT of all limbs of a ciphertext, HMult +
+relinearisation, rescale 24 -> 23, and rotations by 2^k for k = 0..14 (15
+distinct Galois keys).  HMult + relin and the rotations are the 16 key
+switches of a step; `value` is key switches per second over the timed steps.
+
+Prints one JSON line.  `roofline` is for the kernel with the largest device
+time in the timed region, from HIP events the library records around each of
+its launches on the stream it launches on; `achieved` is the kernel's
+algorithmic bytes (each launch's minimal operand reads and writes) over its
+device time.  `cpu_baseline` times the CPU oracle on one HMult + relin and one
+rotation of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+LOGN = 16
+Q_BITS = [50] + [45] * 23
+P_BITS = [50] * 4
+ALPHA = 4
+MOD_LOG2 = 17
+SCALE = 2.0 ** 45
+H = 192
+ROT_STEPS = [1 << k for k in range(15)]
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def key_inputs(moduli, n, beta, seed):
+    from paper_2412_13269_amd import inputs as I
+    return (I.uniform_residues(moduli, n, seed, lead=(beta,)),
+            I.gaussian_error((beta, n), seed + 1))
+
+
+def cpu_baseline(q, p):
+    """The oracle on one HMult + relin and one rotation (same seeds)."""
+    from oracle import ckks as O
+    from paper_2412_13269_amd import inputs as I
+    P = O.Params(LOGN, Q_BITS, P_BITS, alpha=ALPHA, mod_log2=MOD_LOG2)
+    assert [int(v) for v in q] == P.q and [int(v) for v in p] == P.p
+    N, ext = P.N, P.ext_mods(P.L)
+    s = I.ternary_secret(N, H, 2001)
+    rlk = O.relin_key(P, s, *key_inputs(ext, N, P.beta, 2002))
+    g = O.galois_element(P, 1)
+    gk = O.galois_key(P, s, g, *key_inputs(ext, N, P.beta, 3000))
+    cts = []
+    for seed in (201, 202):
+        m = O.encode(P, I.uniform_slots(N // 2, seed), SCALE, P.L)
+        cts.append(O.encrypt(P, s, m, I.uniform_residues(P.q, N, seed + 10), I.gaussian_error(N, seed + 20), SCALE))
+    t0 = time.perf_counter()
+    O.mul_relin(P, cts[0], cts[1], rlk)
+    O.rotate(P, cts[0], 1, {g: gk})
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 2.0 / dt, "unit": "KS ops/s", "cores": cores, "kind": "oracle",
+            "sample": "1 HMult+relin + 1 rotation at N=2^16, L=24 (oracle C loops, OpenMP over limbs)",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2412_13269_amd import inputs as I
+    from paper_2412_13269_amd import pfx as X
+
+    prm = X.make_params(LOGN, Q_BITS, P_BITS, ALPHA, MOD_LOG2)
+    ctx = X.pfx_ctx_create(prm, 0)
+    N, L, K = 1 << LOGN, len(Q_BITS), len(P_BITS)
+    beta = -(-L // ALPHA)
+    q, p, _ = X.pfx_ctx_moduli(ctx, L, K)
+    ext = [int(v) for v in q] + [int(v) for v in p]
+    st = X.pfx_stream_create(ctx)
+
+    log("keygen ...")
+    s = I.ternary_secret(N, H, 2001)
+    sk = X.pfx_sk_create(ctx, s)
+    rlk = X.pfx_swk_create(ctx, sk, 0, *key_inputs(ext, N, beta, 2002))
+    gks = []
+    for k, step in enumerate(ROT_STEPS):
+        g = pow(5, step, 2 * N)
+        gks.append(X.pfx_swk_create(ctx, sk, g, *key_inputs(ext, N, beta, 3000 + 10 * k)))
+    cts, pts = [], []
+    for seed in (201, 202):
+        pt = X.pfx_encode(ctx, I.uniform_slots(N // 2, seed), None, L, SCALE)
+        ct = X.pfx_ct_create(ctx, L, 1)
+        X.pfx_encrypt(ctx, sk, pt, I.uniform_residues(q, N, seed + 10), I.gaussian_error(N, seed + 20), ct, st)
+        cts.append(ct)
+        pts.append(pt)
+    prod = X.pfx_ct_create(ctx, L, 1)
+    rot = X.pfx_ct_create(ctx, L, 1)
+    words = I.uniform_residues(q, N, 7, lead=(2,))          # one ciphertext: 2 x 24 limbs
+    dbuf = X.pfx_dev_alloc(ctx, words.nbytes)
+    X.pfx_memcpy_htod(ctx, dbuf, words, st)
+
+    def step():
+        X.pfx_ntt(ctx, dbuf, 0, L, 2, False, st)
+        X.pfx_ntt(ctx, dbuf, 0, L, 2, True, st)
+        X.pfx_mul_relin(ctx, cts[0], cts[1], rlk, prod, st)
+        X.pfx_rescale(ctx, prod, prod, st)
+        for r in ROT_STEPS:
+            X.pfx_rotate(ctx, cts[0], r, gks, rot, st)
+
+    log("warmup ...")
+    for _ in range(args.warmup):
+        step()
+    X.pfx_sync(ctx, st)
+
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    X.pfx_sync(ctx, st)
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    # the same steps again with the library's per-launch HIP events on
+    X.pfx_profile_reset(ctx)
+    X.pfx_profile_enable(ctx, True)
+    p0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    X.pfx_sync(ctx, st)
+    p_elapsed = time.perf_counter() - p0
+    X.pfx_profile_enable(ctx, False)
+    ks_per_step = 1 + len(ROT_STEPS)
+    kern = {}
+    for name in X.pfx_profile_names(ctx):
+        n, ms, by = X.pfx_profile_get(ctx, name)
+        kern[name] = {"launches": n, "ms": ms, "bytes": by}
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    d = kern[dom]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    log(f"timed {1e3 * elapsed / args.steps:.3f} ms/step, profiled {1e3 * p_elapsed / args.steps:.3f} ms/step")
+    log("kernels (profiled region):")
+    for name, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"]):
+        log(f"  {name:16s} launches={v['launches']:6d} avg_us={1e3 * v['ms'] / max(1, v['launches']):9.2f} "
+            f"GB/s={v['bytes'] / max(1e-12, v['ms'] * 1e-3) / 1e9:8.1f} share={v['ms'] / (1e3 * p_elapsed):.3f}")
+
+    # per-operation device latency, outside the timed region
+    per_op = {}
+
+    def op_time(fn, reps=10):
+        X.pfx_sync(ctx, st)
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        X.pfx_sync(ctx, st)
+        return 1e6 * (time.perf_counter() - a) / reps
+
+    per_op["ntt_fwd_ct_us"] = op_time(lambda: X.pfx_ntt(ctx, dbuf, 0, L, 2, False, st))
+    per_op["mul_relin_us"] = op_time(lambda: X.pfx_mul_relin(ctx, cts[0], cts[1], rlk, prod, st))
+    per_op["rotate_us"] = op_time(lambda: X.pfx_rotate(ctx, cts[0], 1, gks, rot, st))
+
+    def resc():
+        X.pfx_mul_relin(ctx, cts[0], cts[1], rlk, prod, st)
+        X.pfx_rescale(ctx, prod, prod, st)
+    per_op["rescale_us"] = op_time(resc) - per_op["mul_relin_us"]
+
+    out = {
+        "metric": "key-switch (HMult+relin/rotate) ops/s at N=2^16,L=24",
+        "value": ks_per_step * args.steps / elapsed,
+        "unit": "KS ops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single-ciphertext kernel bench: N=2^16, L=24 (+4 special primes, dnum=6), "
+                               "scale 2^45; per step NTT+INTT of a ciphertext, HMult+relin, rescale, "
+                               "rotations by 2^0..2^14",
+                   "N": N, "L": L, "K": K, "dnum": beta, "ks_ops_per_step": ks_per_step},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e3 * d["ms"] / d["launches"],
+                     "algorithmic_bytes_per_launch": d["bytes"] / d["launches"]},
+        "per_op_us": per_op,
+        "profiled_ms_per_step": 1e3 * p_elapsed / args.steps,
+        "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(1, v["launches"]),
+                        "GBps": v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9} for k, v in kern.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(q, p)
+    else:
+        out["cpu_baseline"] = None
+    for h in cts + pts + [prod, rot]:
+        X.pfx_ct_destroy(h)
+    for k in gks + [rlk]:
+        X.pfx_swk_destroy(k)
+    X.pfx_sk_destroy(sk)
+    X.pfx_dev_free(ctx, dbuf)
+    X.pfx_stream_destroy(ctx, st)
+    X.pfx_ctx_destroy(ctx)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -235,9 +235,12 @@ pfx_status pfx_stream_destroy(pfx_ctx *ctx, void *stream);
 /* When on, the library brackets each kernel launch with HIP events on the
  * stream it launches on and accumulates per-kernel device time. */
 pfx_status pfx_profile_enable(pfx_ctx *ctx, int on);
-/* Completed launches and their summed device time (ms) for a kernel name
- * (see pfx_profile_names); synchronises pending events. */
-pfx_status pfx_profile_get(pfx_ctx *ctx, const char *kernel, uint64_t *launches, double *total_ms);
+/* Completed launches, their summed device time (ms) and summed algorithmic
+ * HBM bytes (each launch's minimal reads + writes of its operands, no
+ * re-reads, no twiddle or constant tables) for a kernel name (see
+ * pfx_profile_names); synchronises pending events. */
+pfx_status pfx_profile_get(pfx_ctx *ctx, const char *kernel, uint64_t *launches, double *total_ms,
+                           double *bytes);
 /* Newline-separated kernel names seen so far. */
 pfx_status pfx_profile_names(pfx_ctx *ctx, char *buf, size_t cap);
 pfx_status pfx_profile_reset(pfx_ctx *ctx);

@@ -411,6 +411,7 @@ void pfx_ctx_destroy(pfx_ctx *c) {
         hipEventDestroy(e.start);
         hipEventDestroy(e.stop);
     }
+    for (auto e : c->prof_pool) hipEventDestroy(e);
     hipFree(c->d_tw);
     hipFree(c->d_primes);
     hipFree(c->d_modup);
@@ -1132,22 +1133,25 @@ static void prof_drain(pfx_ctx *c) {
         hipEventSynchronize(e.stop);
         float ms = 0.f;
         hipEventElapsedTime(&ms, e.start, e.stop);
-        auto &slot = c->prof_done[e.name];
-        slot.first += 1;
-        slot.second += ms;
-        hipEventDestroy(e.start);
-        hipEventDestroy(e.stop);
+        ProfTotal &t = c->prof_done[e.name];
+        t.launches += 1;
+        t.ms += ms;
+        t.bytes += e.bytes;
+        c->prof_pool.push_back(e.start);
+        c->prof_pool.push_back(e.stop);
     }
     c->prof_pending.clear();
 }
 
-pfx_status pfx_profile_get(pfx_ctx *c, const char *kernel, uint64_t *launches, double *total_ms) {
+pfx_status pfx_profile_get(pfx_ctx *c, const char *kernel, uint64_t *launches, double *total_ms, double *bytes) {
     REQUIRE(c && kernel, PFX_EINVAL, "null argument");
     std::lock_guard<std::mutex> g(c->mu);
     prof_drain(c);
     auto it = c->prof_done.find(kernel);
-    if (launches) *launches = it == c->prof_done.end() ? 0 : it->second.first;
-    if (total_ms) *total_ms = it == c->prof_done.end() ? 0.0 : it->second.second;
+    const bool have = it != c->prof_done.end();
+    if (launches) *launches = have ? it->second.launches : 0;
+    if (total_ms) *total_ms = have ? it->second.ms : 0.0;
+    if (bytes) *bytes = have ? it->second.bytes : 0.0;
     return PFX_OK;
 }
 
@@ -1174,20 +1178,31 @@ pfx_status pfx_profile_reset(pfx_ctx *c) {
 
 namespace pfx {
 
+static hipEvent_t pool_event(pfx_ctx *c) {
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->prof_pool.empty()) {
+        hipEvent_t e = c->prof_pool.back();
+        c->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
 void prof_begin(const Launch &L, const char *, hipEvent_t *ev) {
     *ev = nullptr;
     if (!L.ctx->prof_on) return;
-    hipEventCreate(ev);
+    *ev = pool_event(L.ctx);
     hipEventRecord(*ev, L.st);
 }
 
-void prof_end(const Launch &L, const char *name, hipEvent_t ev) {
+void prof_end(const Launch &L, const char *name, hipEvent_t ev, double bytes) {
     if (!L.ctx->prof_on || !ev) return;
-    hipEvent_t stop;
-    hipEventCreate(&stop);
+    hipEvent_t stop = pool_event(L.ctx);
     hipEventRecord(stop, L.st);
     std::lock_guard<std::mutex> g(L.ctx->mu);
-    L.ctx->prof_pending.push_back(ProfEntry{ev, stop, name});
+    L.ctx->prof_pending.push_back(ProfEntry{ev, stop, name, bytes});
 }
 
 }  // namespace pfx

@@ -65,6 +65,13 @@ struct Workspace {
 struct ProfEntry {
     hipEvent_t start, stop;
     std::string name;
+    double bytes;   // algorithmic HBM bytes of the launch
+};
+
+struct ProfTotal {
+    uint64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
 };
 
 }  // namespace pfx
@@ -89,7 +96,8 @@ struct pfx_ctx {
 
     bool prof_on = false;
     std::vector<pfx::ProfEntry> prof_pending;
-    std::map<std::string, std::pair<uint64_t, double>> prof_done;
+    std::map<std::string, pfx::ProfTotal> prof_done;
+    std::vector<hipEvent_t> prof_pool;
 };
 
 struct pfx_sk {
@@ -138,7 +146,7 @@ struct Launch {
 };
 
 void prof_begin(const Launch &L, const char *name, hipEvent_t *ev);
-void prof_end(const Launch &L, const char *name, hipEvent_t ev);
+void prof_end(const Launch &L, const char *name, hipEvent_t ev, double bytes);
 
 // Batched NTT over the limbs of `map`; src == nullptr means in place.
 void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap &map, bool inverse);

@@ -257,12 +257,14 @@ void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap 
         a.src = from;
         dim3 grid(map.n * a.tiles);
         hipEvent_t ev;
-        const char *nm = inverse ? (row ? "intt_row" : "intt_col") : (row ? "ntt_row" : "ntt_col");
+        char nm[32];
+        std::snprintf(nm, sizeof nm, "%s/%d", inverse ? (row ? "intt_row" : "intt_col") : (row ? "ntt_row" : "ntt_col"),
+                      map.n);
         prof_begin(L, nm, &ev);
         if (row) { if (inverse) dispatch_pass<true, true>(S, grid, L.st, a); else dispatch_pass<true, false>(S, grid, L.st, a); }
         else { if (inverse) dispatch_pass<false, true>(S, grid, L.st, a); else dispatch_pass<false, false>(S, grid, L.st, a); }
         HIP_LAUNCH_CHECK();
-        prof_end(L, nm, ev);
+        prof_end(L, nm, ev, 16.0 * (double)ctx->N * map.n);
     };
     const double *first = src ? src : base;
     if (!inverse) { run(Scol, false, first); run(Srow, true, base); }
@@ -362,7 +364,7 @@ void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const dou
         default: k_ew<EW_COPY><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
     }
     HIP_LAUNCH_CHECK();
-    prof_end(L, "elementwise", ev);
+    prof_end(L, "elementwise", ev, 8.0 * (double)total * ((op == EW_NEG || op == EW_COPY) ? 2 : 3));
 }
 
 struct LimbConsts {
@@ -397,7 +399,7 @@ void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, s
     prof_begin(L, "mulconst", &ev);
     k_mulconst<<<grid_for(total), 256, 0, L.st>>>(out, a, so, sa, npoly, nl, L.ctx->logn, L.ctx->d_primes, k);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "mulconst", ev);
+    prof_end(L, "mulconst", ev, 16.0 * (double)total);
 }
 
 // Tensor product in the NTT domain (Sec. 2.4.2): d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.
@@ -422,7 +424,7 @@ void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const do
     prof_begin(L, "tensor", &ev);
     k_tensor<<<grid_for(total), 256, 0, L.st>>>(d0, d1, d2, a0, a1, b0, b1, nl, L.ctx->logn, L.ctx->d_primes);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "tensor", ev);
+    prof_end(L, "tensor", ev, 56.0 * (double)total);
 }
 
 // ============================================================== automorphism
@@ -453,7 +455,7 @@ void launch_automorph(const Launch &L, double *out, const double *in, size_t so,
     prof_begin(L, "automorph", &ev);
     k_automorph<<<grid_for(total), 256, 0, L.st>>>(out, in, so, si, npoly, nl, L.ctx->logn, g);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "automorph", ev);
+    prof_end(L, "automorph", ev, 16.0 * (double)total);
 }
 
 // ============================================================== rescale (Sec. 2.5)
@@ -505,7 +507,7 @@ void launch_rescale_spread(const Launch &L, double *tmp, const double *lastc, in
     k_rescale_spread<<<grid_for(total), 256, 0, L.st>>>(tmp, lastc, npoly, lv, L.ctx->logn, L.ctx->d_primes,
                                                         L.ctx->d_rescale);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "rescale_spread", ev);
+    prof_end(L, "rescale_spread", ev, 8.0 * (double)L.ctx->N * npoly * lv);
 }
 
 void launch_rescale_final(const Launch &L, double *out, const double *in, const double *tmp, size_t so, size_t si,
@@ -516,7 +518,7 @@ void launch_rescale_final(const Launch &L, double *out, const double *in, const 
     k_rescale_final<<<grid_for(total), 256, 0, L.st>>>(out, in, tmp, so, si, npoly, lv, L.ctx->logn,
                                                        L.ctx->d_primes, L.ctx->d_rescale);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "rescale_final", ev);
+    prof_end(L, "rescale_final", ev, 24.0 * (double)total);
 }
 
 // ============================================================== key switching (Sec. 2.4.1)
@@ -567,7 +569,7 @@ void launch_modup(const Launch &L, double *ext, const double *dcoef, int lv) {
     k_modup<<<grid, 256, 0, L.st>>>(ext, dcoef, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha, ctx->d_primes,
                                     ctx->d_modup);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "modup", ev);
+    prof_end(L, "modup", ev, 8.0 * (double)ctx->N * beta * (lv + ctx->K));
 }
 
 // acc_u[m] = sum_j dtilde_j[m] * swk_{j,u}[m]   (NTT domain)
@@ -611,7 +613,7 @@ void launch_ks_inner(const Launch &L, double *acc, const double *ext, const doub
     k_ks_inner<<<grid, 256, 0, L.st>>>(acc, ext, d_ntt, key, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha,
                                        ctx->d_primes);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "ks_inner", ev);
+    prof_end(L, "ks_inner", ev, 8.0 * (double)ctx->N * (lv + ctx->K) * (3.0 * ((lv + ctx->alpha - 1) / ctx->alpha) + 2.0));
 }
 
 // ModDown, first half: r_k = [acc_u(p_k) + floor(P/2)]_{p_k} (coefficient domain);
@@ -675,7 +677,7 @@ void launch_moddown_conv(const Launch &L, double *tmp, const double *acc, int lv
     prof_begin(L, "moddown_conv", &ev);
     k_moddown_conv<<<grid, 256, 0, L.st>>>(tmp, acc, lv, ctx->logn, ctx->L, ctx->K, ctx->d_primes, ctx->d_moddown);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "moddown_conv", ev);
+    prof_end(L, "moddown_conv", ev, 8.0 * (double)ctx->N * (2.0 * ctx->K + 2.0 * lv));
 }
 
 void launch_moddown_final(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
@@ -687,7 +689,7 @@ void launch_moddown_final(const Launch &L, double *out0, double *out1, const dou
     k_moddown_final<<<grid_for(total), 256, 0, L.st>>>(out0, out1, acc, tmp, base0, base1, lv, ctx->logn, ctx->K,
                                                        ctx->d_primes, ctx->d_moddown);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "moddown_final", ev);
+    prof_end(L, "moddown_final", ev, 8.0 * (double)ctx->N * lv * (6.0 + (base0 ? 1 : 0) + (base1 ? 1 : 0)));
 }
 
 // ============================================================== keys, encryption

@@ -105,7 +105,7 @@ _SIGS = {
     "pfx_stream_create": (_i32, [_vp, _VPP]),
     "pfx_stream_destroy": (_i32, [_vp, _vp]),
     "pfx_profile_enable": (_i32, [_vp, ctypes.c_int]),
-    "pfx_profile_get": (_i32, [_vp, ctypes.c_char_p, _u64p, _f64p]),
+    "pfx_profile_get": (_i32, [_vp, ctypes.c_char_p, _u64p, _f64p, _f64p]),
     "pfx_profile_names": (_i32, [_vp, ctypes.c_char_p, _sz]),
     "pfx_profile_reset": (_i32, [_vp]),
 }
@@ -427,10 +427,12 @@ def pfx_profile_enable(ctx, on: bool = True):
 
 
 def pfx_profile_get(ctx, kernel: str):
+    """(launches, total device ms, total algorithmic bytes) of one kernel name."""
     n = ctypes.c_uint64()
     ms = ctypes.c_double()
-    _check(_lib.pfx_profile_get(ctx, kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
-    return n.value, ms.value
+    by = ctypes.c_double()
+    _check(_lib.pfx_profile_get(ctx, kernel.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
 
 
 def pfx_profile_names(ctx):
