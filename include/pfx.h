@@ -62,7 +62,8 @@ typedef int32_t pfx_status;
  * 1 mod 2^mod_log2 (0 means log_n + 1); a prime of 50 bits is the next unused
  * prime below 2^50, a smaller one the next unused prime nearest 2^bits
  * (offsets 0, +1, -1, +2, ... multiples of 2^mod_log2); q's are chosen first,
- * in order, then p's.  Bit sizes must lie in [20, 50].  alpha = primes per
+ * in order, then p's.  Bit sizes must lie in [20, 50]; at most 7 special primes
+ * (device contexts).  alpha (<= 8) = primes per
  * key-switching digit; digit j holds primes [alpha*j, alpha*j + alpha).
  */
 typedef struct pfx_params {

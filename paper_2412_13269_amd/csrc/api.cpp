@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -132,42 +133,37 @@ pfx_status check_out(const pfx_ct *o, uint32_t lv, uint32_t deg) {
 }
 
 // Key switching of the lv-limb NTT-domain polynomial d (Sec. 2.4.1):
-// out_u = ModDown(sum_j ModUp_j(d) * swk_{j,u}) (+ base_u).
+// out_u = ModDown(sum_j ModUp_j(d) * swk_{j,u}) (+ base_u).  Six launches, see
+// keyswitch.hip.
 void ks_core(pfx_ctx *c, const Launch &L, const Ws &w, const double *d, int lv, const pfx_swk *key, double *out0,
              double *out1, const double *base0, const double *base1) {
     const int E = lv + c->K;
-    const int beta = (lv + c->alpha - 1) / c->alpha;
     double *dcoef = w.at(w.lay.dcoef), *ext = w.at(w.lay.ext), *acc = w.at(w.lay.acc), *tmp = w.at(w.lay.mdtmp);
-    launch_ntt(L, dcoef, d, contiguous_map(lv, 0), true);
-    launch_modup(L, ext, dcoef, lv);
-    LimbMap m;
-    m.n = 0;
-    for (int j = 0; j < beta; ++j) {
-        const int sz = std::min(c->alpha, lv - j * c->alpha);
-        for (int t = 0; t < E - sz; ++t) {
-            int pid = t < j * c->alpha ? t : (t < lv - sz ? t + sz : c->L + (t - (lv - sz)));
-            m.off[m.n] = j * E + t;
-            m.pid[m.n] = (int16_t)pid;
-            ++m.n;
-            if (m.n == kMaxMapLimbs) {
-                launch_ntt(L, ext, nullptr, m, false);
-                m.n = 0;
+    launch_intt_scale(L, dcoef, d, lv);
+    launch_modup_col(L, ext, dcoef, lv);
+    if (c->ks_variant == 1) {
+        launch_row_inner(L, acc, ext, d, key->d_k, lv);
+    } else {
+        const int beta = (lv + c->alpha - 1) / c->alpha;
+        LimbMap m;
+        m.n = 0;
+        for (int j = 0; j < beta; ++j) {
+            const int sz = std::min(c->alpha, lv - j * c->alpha);
+            for (int t = 0; t < E - sz; ++t) {
+                m.off[m.n] = j * E + t;
+                m.pid[m.n] = (int16_t)(t < j * c->alpha ? t : (t < lv - sz ? t + sz : c->L + (t - (lv - sz))));
+                if (++m.n == kMaxMapLimbs) {
+                    launch_ntt_pass(L, ext, nullptr, m, true, false);
+                    m.n = 0;
+                }
             }
         }
+        launch_ntt_pass(L, ext, nullptr, m, true, false);
+        launch_ks_inner(L, acc, ext, d, key->d_k, lv);
     }
-    launch_ntt(L, ext, nullptr, m, false);
-    launch_ks_inner(L, acc, ext, d, key->d_k, lv);
-    LimbMap pm;
-    pm.n = 2 * c->K;
-    for (int u = 0; u < 2; ++u)
-        for (int k = 0; k < c->K; ++k) {
-            pm.off[u * c->K + k] = u * E + lv + k;
-            pm.pid[u * c->K + k] = (int16_t)(c->L + k);
-        }
-    launch_ntt(L, acc, nullptr, pm, true);
-    launch_moddown_conv(L, tmp, acc, lv);
-    launch_ntt(L, tmp, nullptr, poly_map(2, lv, lv), false);
-    launch_moddown_final(L, out0, out1, acc, tmp, base0, base1, lv);
+    launch_intt_special(L, acc, lv);
+    launch_moddown_col(L, tmp, acc, lv);
+    launch_row_moddown(L, out0, out1, acc, tmp, base0, base1, lv);
 }
 
 pfx_swk *find_key(pfx_ctx *c, uint32_t g, const pfx_swk *const *keys, size_t n) {
@@ -263,7 +259,7 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
     std::vector<uint64_t> q, p, psi;
     std::string err;
     if (!build_primes(prm, q, p, psi, err)) return fail(PFX_EPARAM, err);
-    REQUIRE(prm->n_p <= 8, PFX_EPARAM, "at most 8 special primes");
+    REQUIRE(prm->n_p <= 7, PFX_EPARAM, "at most 7 special primes");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0)
         return fail(PFX_EDEVICE, "no such HIP device");
@@ -282,6 +278,7 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
     c->alpha = prm->alpha;
     c->beta = (c->L + c->alpha - 1) / c->alpha;
     c->mod_log2 = prm->mod_log2 ? prm->mod_log2 : prm->log_n + 1;
+    if (const char *v = std::getenv("PFX_KS_VARIANT")) c->ks_variant = std::atoi(v) == 1 ? 1 : 0;
     c->primes = q;
     c->primes.insert(c->primes.end(), p.begin(), p.end());
     c->psi = psi;
@@ -307,6 +304,21 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
     }
     HIPCHECK(hipMalloc(&c->d_tw, tw.size() * sizeof(double2)));
     HIPCHECK(hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
+    // row-pass generated twiddles (see PrimeDev)
+    const int Srow = c->logn - c->logn / 2, R2 = Srow - (Srow + 1) / 2, T = c->logn - R2;
+    const size_t nT = (size_t)1 << T;
+    std::vector<double> rtw((size_t)2 * NP * nT);
+    for (int m = 0; m < NP; ++m) {
+        const uint64_t qq = c->primes[m];
+        const uint64_t ps = psi[m], ips = invmod_u64(ps, qq);
+        for (size_t P = 0; P < nT; ++P) {
+            const uint64_t e = 2ull * bitrev((unsigned)P, T);
+            rtw[(2 * (size_t)m) * nT + P] = (double)powmod_u64(ps, e, qq);
+            rtw[(2 * (size_t)m + 1) * nT + P] = (double)powmod_u64(ips, e, qq);
+        }
+    }
+    HIPCHECK(hipMalloc(&c->d_rtw, rtw.size() * sizeof(double)));
+    HIPCHECK(hipMemcpy(c->d_rtw, rtw.data(), rtw.size() * sizeof(double), hipMemcpyHostToDevice));
     c->h_primes.resize(NP);
     for (int m = 0; m < NP; ++m) {
         const uint64_t qq = c->primes[m];
@@ -321,6 +333,17 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
         d.ninv_w1_q = (double)w1 / (double)qq;
         d.tw = c->d_tw + (2 * (size_t)m) * N;
         d.itw = c->d_tw + (2 * (size_t)m + 1) * N;
+        d.rtw = c->d_rtw + (2 * (size_t)m) * nT;
+        d.irtw = c->d_rtw + (2 * (size_t)m + 1) * nT;
+        std::memset(d.rc, 0, sizeof d.rc);
+        std::memset(d.irc, 0, sizeof d.irc);
+        const uint64_t ips = invmod_u64(psi[m], qq);
+        for (int k = 0; k < R2; ++k)
+            for (int x = 0; x < (1 << k); ++x) {
+                const uint64_t e = (1ull << (c->logn - 1 - T - k)) + (uint64_t)bitrev((unsigned)x, k) * (1ull << (c->logn - k));
+                d.rc[(1 << k) - 1 + x] = (double)powmod_u64(psi[m], e, qq);
+                d.irc[(1 << k) - 1 + x] = (double)powmod_u64(ips, e, qq);
+            }
     }
     HIPCHECK(hipMalloc(&c->d_primes, NP * sizeof(PrimeDev)));
     HIPCHECK(hipMemcpy(c->d_primes, c->h_primes.data(), NP * sizeof(PrimeDev), hipMemcpyHostToDevice));
@@ -413,6 +436,7 @@ void pfx_ctx_destroy(pfx_ctx *c) {
     }
     for (auto e : c->prof_pool) hipEventDestroy(e);
     hipFree(c->d_tw);
+    hipFree(c->d_rtw);
     hipFree(c->d_primes);
     hipFree(c->d_modup);
     hipFree(c->d_moddown);

@@ -23,6 +23,13 @@ struct PrimeDev {
     double ninv_w1, ninv_w1_q;   // N^-1 * psi^-(N/2), the last inverse stage folded with N^-1
     const double2 *tw;           // tw[k]  = {psi^bitrev(k),  fl(./q)}, k < N
     const double2 *itw;          // itw[k] = {psi^-bitrev(k), fl(./q)}, k < N
+    // On-the-fly twiddles of the last R2 stages of the row pass (T = log N - R2):
+    // stage T + k, twiddle for j = (P << R2) | u is rc[2^k - 1 + x] * B_k with
+    // x = u >> (R2 - k), B_{R2-1} = rtw[P] = psi^(2 bitrev_T(P)), B_{k-1} = B_k^2.
+    const double *rtw;           // 2^T entries
+    const double *irtw;          // same with psi^-1
+    double rc[16];
+    double irc[16];
 };
 
 // Limbs of one batched NTT launch: limb b sits at base + off[b] * N and uses prime pid[b].
@@ -86,6 +93,7 @@ struct pfx_ctx {
 
     pfx::PrimeDev *d_primes = nullptr;
     double2 *d_tw = nullptr;
+    double *d_rtw = nullptr;
     pfx::ModUpConst *d_modup = nullptr;     // [beta][alpha] variants (j, sz-1)
     pfx::ModDownConst *d_moddown = nullptr;
     pfx::RescaleConst *d_rescale = nullptr; // [L][L]
@@ -93,6 +101,11 @@ struct pfx_ctx {
 
     std::mutex mu;
     std::map<hipStream_t, pfx::Workspace *> ws;
+
+    // Key-switch inner-product schedule: 0 = row pass of the ModUp limbs, then
+    // a streaming inner product; 1 = row pass fused with the inner product
+    // (accumulators in registers).  Chosen at context creation (PFX_KS_VARIANT).
+    int ks_variant = 0;
 
     bool prof_on = false;
     std::vector<pfx::ProfEntry> prof_pending;
@@ -150,6 +163,8 @@ void prof_end(const Launch &L, const char *name, hipEvent_t ev, double bytes);
 
 // Batched NTT over the limbs of `map`; src == nullptr means in place.
 void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap &map, bool inverse);
+// One pass (column: the first log N / 2 stages; row: the rest) of the same transform.
+void launch_ntt_pass(const Launch &L, double *base, const double *src, const LimbMap &map, bool row, bool inverse);
 void launch_u64_to_f64(const Launch &L, double *out, const uint64_t *in, size_t n);
 void launch_f64_to_u64(const Launch &L, uint64_t *out, const double *in, size_t n);
 void launch_int_to_rns(const Launch &L, double *out, const int64_t *in, int n_limbs, int pid0,
@@ -176,6 +191,15 @@ void launch_ks_inner(const Launch &L, double *acc, const double *ext, const doub
 void launch_moddown_conv(const Launch &L, double *tmp, const double *acc, int lv);
 void launch_moddown_final(const Launch &L, double *out0, double *out1, const double *acc,
                           const double *tmp, const double *base0, const double *base1, int lv);
+// Fused key-switching steps (keyswitch.hip).
+void launch_intt_scale(const Launch &L, double *dcoef, const double *d, int lv);
+void launch_modup_col(const Launch &L, double *ext, const double *dcoef, int lv);
+void launch_row_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt, const double *key,
+                      int lv);
+void launch_intt_special(const Launch &L, double *acc, int lv);
+void launch_moddown_col(const Launch &L, double *tmp, const double *acc, int lv);
+void launch_row_moddown(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
+                        const double *base0, const double *base1, int lv);
 void launch_keygen_b(const Launch &L, double *b, const double *a, const double *e, const double *s,
                      const double *sfrom, int digit);
 void launch_encrypt(const Launch &L, double *c0, const double *a, const double *e, const double *s,

@@ -8,6 +8,7 @@
 
 #include "internal.h"
 #include "modarith.h"
+#include "ntt_core.h"
 
 namespace pfx {
 
@@ -25,22 +26,9 @@ static inline unsigned grid_for(size_t total, unsigned threads = 256) {
 __device__ __forceinline__ unsigned brev_n(unsigned x, int logn) { return __brev(x) >> (32 - logn); }
 
 // ============================================================== NTT
-// Negacyclic NTT, output in the order NTT(a)[j] = a(psi^(2 bitrev(j) + 1)).
-// Stage s (0 <= s < log N) pairs j and j + N/2^(s+1); its twiddle is
-// tw[2^s + (j >> (log N - s))] = psi^bitrev(2^s + ...), as in the textbook
-// Cooley-Tukey (forward) / Gentleman-Sande (inverse) loops.
-//
-// A limb of N = 2^16 doubles (512 KiB) is larger than one CU's LDS, so the
-// transform runs as two passes of S_col + S_row = log N stages.  The column
-// pass does the first S_col stages on sub-transforms of stride 2^(log N -
-// S_col) (a tile = C consecutive columns, coalesced rows of C doubles); the
-// row pass does the last S_row stages on contiguous blocks of 2^S_row.  Each
-// pass splits its S stages into two register rounds (R1 = ceil(S/2) stages,
-// then R2) with one LDS exchange between them; a thread holds 2^R1 or 2^R2
-// elements and does their butterflies in registers.
-constexpr int kNttThreads = 256;
-constexpr int kNttTile = 4096;
-
+// Plain batched NTT over a LimbMap: both passes of ntt_core.h with ordinary
+// global loads and stores.  Workgroups are remapped so that the tiles of one
+// limb (one prime's twiddle table) stay on one XCD.
 struct NttArgs {
     double *dst;
     const double *src;
@@ -48,185 +36,25 @@ struct NttArgs {
     int logn;
     int C;
     int tiles;
+    int nblk;
     LimbMap map;
 };
 
 template <int S, bool ROW, bool INV>
 __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(const NttArgs a) {
-    constexpr int R = 1 << S;
-    constexpr int R1 = (S + 1) / 2;
-    constexpr int R2 = S - R1;
-    constexpr int E1 = 1 << R1;
-    constexpr int E2 = 1 << R2;
-    __shared__ double lds[kNttTile + kNttTile / 16];
-
-    const int limb = blockIdx.x / a.tiles;
-    const int tile = blockIdx.x - limb * a.tiles;
+    __shared__ double lds[kNttLds];
+    const int id = xcd_slot(a.nblk);
+    if (id >= a.nblk) return;
+    const int limb = id / a.tiles;
+    const int tile = id - limb * a.tiles;
     const PrimeDev &P = a.primes[a.map.pid[limb]];
-    const double q = P.q;
     const size_t loff = (size_t)a.map.off[limb] << a.logn;
-    double *__restrict__ dst = a.dst + loff;
-    const double *__restrict__ src = a.src + loff;
-    const int logn = a.logn;
-    const int C = a.C;
-    const int lo_bits = logn - S;
-    const int s0 = ROW ? logn - S : 0;
-    const int cbase = tile * C;
-    const double2 *__restrict__ tw = INV ? P.itw : P.tw;
-
-    auto gidx = [&](int c, int mid) -> int {
-        return ROW ? (((cbase + c) << S) | mid) : ((mid << lo_bits) | (cbase + c));
-    };
-    auto lidx = [&](int c, int mid) -> int {
-        return ROW ? (c * (R + R / 16) + mid + (mid >> 4)) : (mid * C + c);
-    };
-
-    if (ROW) {
-        for (int e = threadIdx.x; e < C * R; e += kNttThreads) {
-            const int c = e >> S, mid = e & (R - 1);
-            lds[lidx(c, mid)] = src[gidx(c, mid)];
-        }
-        __syncthreads();
-    }
-
-    if (!INV) {
-        // ---- round 1: local stages [0, R1), elements mid = (u << (S-R1)) | ml
-        const int n1 = C << (S - R1);
-        for (int g = threadIdx.x; g < n1; g += kNttThreads) {
-            int c, ml;
-            if (ROW) { ml = g & ((1 << (S - R1)) - 1); c = g >> (S - R1); }
-            else { c = g % C; ml = g / C; }
-            double v[E1];
-#pragma unroll
-            for (int u = 0; u < E1; ++u) {
-                const int mid = (u << (S - R1)) | ml;
-                v[u] = ROW ? lds[lidx(c, mid)] : src[gidx(c, mid)];
-            }
-#pragma unroll
-            for (int kk = 0; kk < R1; ++kk) {
-                const int s = s0 + kk;
-                const int h = 1 << (R1 - 1 - kk);
-#pragma unroll
-                for (int u = 0; u < E1; ++u) {
-                    if (u & h) continue;
-                    const int j = gidx(c, (u << (S - R1)) | ml);
-                    const double2 w = tw[(1 << s) + (j >> (logn - s))];
-                    const double V = mmulc(v[u + h], w.x, w.y, q);
-                    const double U = v[u];
-                    v[u] = madd(U, V, q);
-                    v[u + h] = msub(U, V, q);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < E1; ++u) lds[lidx(c, (u << (S - R1)) | ml)] = v[u];
-        }
-        __syncthreads();
-        // ---- round 2: local stages [R1, S), elements mid = (mh << R2) | u
-        const int n2 = C << R1;
-        for (int g = threadIdx.x; g < n2; g += kNttThreads) {
-            int c, mh;
-            if (ROW) { mh = g & (E1 - 1); c = g >> R1; }
-            else { c = g % C; mh = g / C; }
-            double v[E2];
-#pragma unroll
-            for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
-#pragma unroll
-            for (int kk = 0; kk < R2; ++kk) {
-                const int s = s0 + R1 + kk;
-                const int h = 1 << (R2 - 1 - kk);
-#pragma unroll
-                for (int u = 0; u < E2; ++u) {
-                    if (u & h) continue;
-                    const int j = gidx(c, (mh << R2) | u);
-                    const double2 w = tw[(1 << s) + (j >> (logn - s))];
-                    const double V = mmulc(v[u + h], w.x, w.y, q);
-                    const double U = v[u];
-                    v[u] = madd(U, V, q);
-                    v[u + h] = msub(U, V, q);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < E2; ++u) {
-                const int mid = (mh << R2) | u;
-                if (ROW) lds[lidx(c, mid)] = v[u];
-                else dst[gidx(c, mid)] = v[u];
-            }
-        }
-    } else {
-        // ---- round A: local stages S-1 .. R1 (descending), elements mid = (mh << R2) | u
-        const int n2 = C << R1;
-        for (int g = threadIdx.x; g < n2; g += kNttThreads) {
-            int c, mh;
-            if (ROW) { mh = g & (E1 - 1); c = g >> R1; }
-            else { c = g % C; mh = g / C; }
-            double v[E2];
-#pragma unroll
-            for (int u = 0; u < E2; ++u) {
-                const int mid = (mh << R2) | u;
-                v[u] = ROW ? lds[lidx(c, mid)] : src[gidx(c, mid)];
-            }
-#pragma unroll
-            for (int kk = R2 - 1; kk >= 0; --kk) {
-                const int s = s0 + R1 + kk;
-                const int h = 1 << (R2 - 1 - kk);
-#pragma unroll
-                for (int u = 0; u < E2; ++u) {
-                    if (u & h) continue;
-                    const int j = gidx(c, (mh << R2) | u);
-                    const double2 w = tw[(1 << s) + (j >> (logn - s))];
-                    const double U = v[u], V = v[u + h];
-                    v[u] = madd(U, V, q);
-                    v[u + h] = mmulc(msub(U, V, q), w.x, w.y, q);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
-        }
-        __syncthreads();
-        // ---- round B: local stages R1-1 .. 0, elements mid = (u << (S-R1)) | ml
-        const int n1 = C << (S - R1);
-        for (int g = threadIdx.x; g < n1; g += kNttThreads) {
-            int c, ml;
-            if (ROW) { ml = g & ((1 << (S - R1)) - 1); c = g >> (S - R1); }
-            else { c = g % C; ml = g / C; }
-            double v[E1];
-#pragma unroll
-            for (int u = 0; u < E1; ++u) v[u] = lds[lidx(c, (u << (S - R1)) | ml)];
-#pragma unroll
-            for (int kk = R1 - 1; kk >= 0; --kk) {
-                const int s = s0 + kk;
-                const int h = 1 << (R1 - 1 - kk);
-#pragma unroll
-                for (int u = 0; u < E1; ++u) {
-                    if (u & h) continue;
-                    const double U = v[u], V = v[u + h];
-                    if (!ROW && s == 0) {   // last stage: fold N^-1 into both outputs
-                        v[u] = mmulc(madd(U, V, q), P.ninv, P.ninv_q, q);
-                        v[u + h] = mmulc(msub(U, V, q), P.ninv_w1, P.ninv_w1_q, q);
-                    } else {
-                        const int j = gidx(c, (u << (S - R1)) | ml);
-                        const double2 w = tw[(1 << s) + (j >> (logn - s))];
-                        v[u] = madd(U, V, q);
-                        v[u + h] = mmulc(msub(U, V, q), w.x, w.y, q);
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < E1; ++u) {
-                const int mid = (u << (S - R1)) | ml;
-                if (ROW) lds[lidx(c, mid)] = v[u];
-                else dst[gidx(c, mid)] = v[u];
-            }
-        }
-    }
-
-    if (ROW) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < C * R; e += kNttThreads) {
-            const int c = e >> S, mid = e & (R - 1);
-            dst[gidx(c, mid)] = lds[lidx(c, mid)];
-        }
-    }
+    double *dst = a.dst + loff;
+    const double *src = a.src + loff;
+    auto ld = [&](int j, int) { return src[j]; };
+    auto st = [&](int j, double v, int) { dst[j] = v; };
+    if (ROW) row_pass<S, INV>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+    else col_pass<S, INV>(P, a.logn, a.C, tile * a.C, lds, ld, st);
 }
 
 template <bool ROW, bool INV>
@@ -239,36 +67,47 @@ static void dispatch_pass(int S, dim3 grid, hipStream_t st, const NttArgs &a) {
     }
 }
 
-void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap &map, bool inverse) {
+void launch_ntt_pass(const Launch &L, double *base, const double *src, const LimbMap &map, bool row, bool inverse) {
     if (map.n <= 0) return;
     pfx_ctx *ctx = L.ctx;
     const int logn = ctx->logn;
-    const int Scol = logn / 2, Srow = logn - Scol;
     NttArgs a;
     a.dst = base;
     a.primes = ctx->d_primes;
     a.logn = logn;
     a.map = map;
-    auto run = [&](int S, bool row, const double *from) {
-        const int R = 1 << S;
-        const int subs = 1 << (logn - S);
-        a.C = std::min(kNttTile / R, subs);
-        a.tiles = subs / a.C;
-        a.src = from;
-        dim3 grid(map.n * a.tiles);
-        hipEvent_t ev;
-        char nm[32];
-        std::snprintf(nm, sizeof nm, "%s/%d", inverse ? (row ? "intt_row" : "intt_col") : (row ? "ntt_row" : "ntt_col"),
-                      map.n);
-        prof_begin(L, nm, &ev);
-        if (row) { if (inverse) dispatch_pass<true, true>(S, grid, L.st, a); else dispatch_pass<true, false>(S, grid, L.st, a); }
-        else { if (inverse) dispatch_pass<false, true>(S, grid, L.st, a); else dispatch_pass<false, false>(S, grid, L.st, a); }
-        HIP_LAUNCH_CHECK();
-        prof_end(L, nm, ev, 16.0 * (double)ctx->N * map.n);
-    };
-    const double *first = src ? src : base;
-    if (!inverse) { run(Scol, false, first); run(Srow, true, base); }
-    else { run(Srow, true, first); run(Scol, false, base); }
+    PassShape ps = row ? row_shape(logn) : col_shape(logn);
+    // small batches: narrower tiles so that the launch still covers the CUs
+    // (column tiles stay >= 8 columns = 64-byte rows)
+    const int minC = row ? 1 : 8;
+    while (map.n * ps.tiles < 1024 && ps.C / 2 >= minC) {
+        ps.C /= 2;
+        ps.tiles *= 2;
+    }
+    a.C = ps.C;
+    a.tiles = ps.tiles;
+    a.nblk = map.n * ps.tiles;
+    a.src = src ? src : base;
+    dim3 grid(xcd_grid(a.nblk));
+    hipEvent_t ev;
+    char nm[32];
+    std::snprintf(nm, sizeof nm, "%s/%d", inverse ? (row ? "intt_row" : "intt_col") : (row ? "ntt_row" : "ntt_col"),
+                  map.n);
+    prof_begin(L, nm, &ev);
+    if (row) { if (inverse) dispatch_pass<true, true>(ps.S, grid, L.st, a); else dispatch_pass<true, false>(ps.S, grid, L.st, a); }
+    else { if (inverse) dispatch_pass<false, true>(ps.S, grid, L.st, a); else dispatch_pass<false, false>(ps.S, grid, L.st, a); }
+    HIP_LAUNCH_CHECK();
+    prof_end(L, nm, ev, 16.0 * (double)ctx->N * map.n);
+}
+
+void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap &map, bool inverse) {
+    if (!inverse) {
+        launch_ntt_pass(L, base, src, map, false, false);
+        launch_ntt_pass(L, base, nullptr, map, true, false);
+    } else {
+        launch_ntt_pass(L, base, src, map, true, true);
+        launch_ntt_pass(L, base, nullptr, map, false, true);
+    }
 }
 
 // ============================================================== conversions

@@ -63,4 +63,27 @@ __device__ __forceinline__ double mred(double x, double q, double qinv) {
     return r >= q ? r - q : r;
 }
 
+// ---- signed lazy forms (used inside transforms) ---------------------------
+// a*w mod q up to a multiple of q: r = a*w - c*q with |r| <= q, for |a| <= 2^51,
+// 0 <= w < q < 2^50, wq = fl(w/q).  Same steps as mmulc without the final
+// correction: |h - a*w| <= 2^47 and |c - a*w/q| <= 1, so h - c*q and r are
+// integers below 2^52 and exact.  For |a| <= q the bound is |r| <= 0.75 q.
+__device__ __forceinline__ double mmulc_lazy(double a, double w, double wq, double q) {
+    double h = a * w;
+    double l = __builtin_fma(a, w, -h);
+    double c = __builtin_rint(a * wq);
+    return __builtin_fma(-c, q, h) + l;
+}
+
+// x mod q into [-q/2, q/2] (up to a rounding tie) for an integer |x| < 2^53.
+__device__ __forceinline__ double mred_signed(double x, double q, double qinv) {
+    return __builtin_fma(-__builtin_rint(x * qinv), q, x);
+}
+
+// [0, q) from an integer |x| <= q.
+__device__ __forceinline__ double mcanon(double x, double q) {
+    x = x < 0.0 ? x + q : x;
+    return x >= q ? x - q : x;
+}
+
 }  // namespace pfx

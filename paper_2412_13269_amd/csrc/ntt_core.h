@@ -1,0 +1,388 @@
+// Device building blocks of the negacyclic NTT (gfx950).
+//
+// Order: NTT(a)[j] = a(psi^(2 bitrev(j) + 1)).  Stage s (0 <= s < log N)
+// pairs index j with j + N/2^(s+1); its twiddle is tw[2^s + (j >> (log N - s))]
+// with tw[k] = psi^bitrev(k) (forward, Cooley-Tukey butterfly) or
+// psi^-bitrev(k) (inverse, Gentleman-Sande butterfly).
+//
+// A limb of N = 2^16 doubles (512 KiB) does not fit one CU's LDS, so a
+// transform is two passes over the limb:
+//   column pass: global stages [0, S_col), sub-transforms of stride
+//                2^(log N - S_col); a tile is C consecutive columns, so every
+//                row of the tile is C contiguous doubles;
+//   row pass:    global stages [S_col, log N), contiguous blocks of
+//                2^S_row; a tile is C consecutive blocks.
+// Inside a pass the S stages run as two register rounds (R1 = ceil(S/2), then
+// R2 = S - R1 stages) with one LDS exchange between them.  The first round
+// reads its operands through a caller-supplied `load(global_index, slot)`
+// and the last round hands results to `store(global_index, value, slot)`,
+// so a pass can be fused with what produces its input (a basis conversion)
+// or consumes its output (a key inner product).  `slot` in [0, 16) numbers
+// the elements a thread owns in that round; for a full tile of 4096 elements
+// and 256 threads it is a compile-time index, so per-element accumulators of a
+// fused consumer stay in registers.
+//
+// Element/thread layouts (chosen for coalesced global access):
+//   column pass: thread group (c, m') with c fastest; row r of the tile is C
+//                consecutive doubles, read/written by consecutive threads;
+//   row pass, forward round 1 / inverse round B: (c, m_lo) with m_lo fastest
+//                (consecutive threads touch consecutive doubles);
+//   row pass, forward output / inverse input: through LDS, element e of the
+//                tile to thread e mod 256 (consecutive threads, consecutive
+//                doubles).
+#pragma once
+#include "internal.h"
+#include "modarith.h"
+
+namespace pfx {
+
+constexpr int kNttThreads = 256;
+constexpr int kNttTile = 4096;
+constexpr int kNttLds = kNttTile + kNttTile / 16;
+constexpr int kSlots = kNttTile / kNttThreads;   // elements per thread per round
+
+// Arithmetic inside a transform is signed and lazy: a twiddle product returns
+// a representative in [-q, q] (mmulc_lazy), sums and differences are left
+// unreduced, and every value is brought back to [-q/2, q/2] (mred_signed) after
+// every second forward stage and after every inverse stage's sum.  Bounds (q <
+// 2^50, inputs |x| <= q): forward, two stages take |x| <= 0.51q to at most
+// 2.75q before the reduction; inverse sums stay below 2q and differences below
+// 2q before their product.  Every intermediate is an integer below 2^52 in
+// magnitude, so each step is exact.  Group outputs are reduced to
+// [-q/2, q/2]; the last pass of a transform canonicalises to [0, q).
+
+// Forward butterflies of NST consecutive stages on the E = 2^NST elements of
+// one register group; gidx(u) is the global index of element u; stage kk of the
+// group is global stage s0 + kk.
+template <int NST, class Gidx>
+__device__ __forceinline__ void fwd_group(double *v, int s0, int logn, const double2 *__restrict__ tw, double q,
+                                          double qinv, Gidx &&gidx) {
+    constexpr int E = 1 << NST;
+#pragma unroll
+    for (int kk = 0; kk < NST; ++kk) {
+        const int s = s0 + kk;
+        const int h = 1 << (NST - 1 - kk);
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u & h) continue;
+            const double2 w = tw[(1 << s) + (gidx(u) >> (logn - s))];
+            const double T = mmulc_lazy(v[u + h], w.x, w.y, q);
+            const double U = v[u];
+            v[u] = U + T;
+            v[u + h] = U - T;
+        }
+        if ((kk & 1) || kk == NST - 1) {
+#pragma unroll
+            for (int u = 0; u < E; ++u) v[u] = mred_signed(v[u], q, qinv);
+        }
+    }
+}
+
+// Inverse butterflies, stages s0 + NST - 1 down to s0.  If `last` is set the
+// group contains global stage 0 and N^-1 is folded into that stage's outputs.
+template <int NST, class Gidx>
+__device__ __forceinline__ void inv_group(double *v, int s0, int logn, const double2 *__restrict__ tw,
+                                          const PrimeDev &P, bool last, Gidx &&gidx) {
+    constexpr int E = 1 << NST;
+    const double q = P.q, qinv = P.qinv;
+#pragma unroll
+    for (int kk = NST - 1; kk >= 0; --kk) {
+        const int s = s0 + kk;
+        const int h = 1 << (NST - 1 - kk);
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u & h) continue;
+            const double U = v[u], V = v[u + h];
+            if (last && s == 0) {
+                v[u] = mmulc_lazy(U + V, P.ninv, P.ninv_q, q);
+                v[u + h] = mmulc_lazy(U - V, P.ninv_w1, P.ninv_w1_q, q);
+            } else {
+                const double2 w = tw[(1 << s) + (gidx(u) >> (logn - s))];
+                v[u] = mred_signed(U + V, q, qinv);
+                v[u + h] = mmulc_lazy(U - V, w.x, w.y, q);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < E; ++u) v[u] = mred_signed(v[u], q, qinv);
+}
+
+// The last R2 stages of the row pass with twiddles generated in registers
+// instead of read from the 2^logn-entry table (which would cost as many bytes
+// as the data).  For the thread's group j = (P << R2) | u the stage-(T + k)
+// twiddle is rc[2^k - 1 + x] * B_k, x = u >> (R2 - k), with B_{R2-1} =
+// rtw[P] and B_{k-1} = B_k^2: 2^R2 - 1 + R2 - 1 modular products per group.
+// Generated twiddles come with wq = fl(w * fl(1/q)), so a lazy product is
+// within 1.25 q (|a| <= 2^51) or 0.875 q (|a| <= q); the two-stage growth
+// stays below 3.2 q < 2^52.
+template <int NST>
+__device__ __forceinline__ void row_twiddle_bases(double *B, const double *__restrict__ rtw, int P, double q,
+                                                  double qinv) {
+    B[NST - 1] = rtw[P];
+#pragma unroll
+    for (int k = NST - 1; k > 0; --k) B[k - 1] = mmul(B[k], B[k], q, qinv);
+}
+
+template <int NST>
+__device__ __forceinline__ void fwd_group_gen(double *v, const double *B, const double *rc, double q, double qinv) {
+    constexpr int E = 1 << NST;
+#pragma unroll
+    for (int kk = 0; kk < NST; ++kk) {
+        const int h = 1 << (NST - 1 - kk);
+#pragma unroll
+        for (int x = 0; x < (1 << kk); ++x) {
+            const double w = mmul(rc[(1 << kk) - 1 + x], B[kk], q, qinv);
+            const double wq = w * qinv;
+#pragma unroll
+            for (int lo = 0; lo < h; ++lo) {
+                const int u = (x << (NST - kk)) | lo;
+                const double T = mmulc_lazy(v[u + h], w, wq, q);
+                const double U = v[u];
+                v[u] = U + T;
+                v[u + h] = U - T;
+            }
+        }
+        if ((kk & 1) || kk == NST - 1) {
+#pragma unroll
+            for (int u = 0; u < E; ++u) v[u] = mred_signed(v[u], q, qinv);
+        }
+    }
+}
+
+template <int NST>
+__device__ __forceinline__ void inv_group_gen(double *v, const double *B, const double *rc, double q, double qinv) {
+    constexpr int E = 1 << NST;
+#pragma unroll
+    for (int kk = NST - 1; kk >= 0; --kk) {
+        const int h = 1 << (NST - 1 - kk);
+#pragma unroll
+        for (int x = 0; x < (1 << kk); ++x) {
+            const double w = mmul(rc[(1 << kk) - 1 + x], B[kk], q, qinv);
+            const double wq = w * qinv;
+#pragma unroll
+            for (int lo = 0; lo < h; ++lo) {
+                const int u = (x << (NST - kk)) | lo;
+                const double U = v[u], V = v[u + h];
+                v[u] = mred_signed(U + V, q, qinv);
+                v[u + h] = mmulc_lazy(U - V, w, wq, q);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < E; ++u) v[u] = mred_signed(v[u], q, qinv);
+}
+
+// Column pass: global stages [0, S) on the tile of columns [cbase, cbase + C).
+// Inputs |x| <= q.  Forward: the first pass of a transform, outputs in
+// [-q/2, q/2] for the row pass.  Inverse: the last pass, outputs in [0, q).
+template <int S, bool INV, class Load, class Store>
+__device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int cbase, double *lds, Load &&load,
+                                         Store &&store) {
+    constexpr int R1 = (S + 1) / 2, R2 = S - R1, E1 = 1 << R1, E2 = 1 << R2;
+    constexpr int IT1 = kSlots / E1, IT2 = kSlots / E2;
+    const int lo = logn - S;
+    const double q = P.q;
+    const double2 *__restrict__ tw = INV ? P.itw : P.tw;
+    const int n1 = C << (S - R1), n2 = C << R1;
+    auto gidx = [&](int c, int mid) { return (mid << lo) | (cbase + c); };
+    if (!INV) {
+#pragma unroll
+        for (int gi = 0; gi < IT1; ++gi) {
+            const int g = threadIdx.x + gi * kNttThreads;
+            if (g < n1) {
+                const int c = g % C, ml = g / C;
+                auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
+                double v[E1];
+#pragma unroll
+                for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
+                fwd_group<R1>(v, 0, logn, tw, q, P.qinv, gu);
+#pragma unroll
+                for (int u = 0; u < E1; ++u) lds[((u << (S - R1)) | ml) * C + c] = v[u];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int gi = 0; gi < IT2; ++gi) {
+            const int g = threadIdx.x + gi * kNttThreads;
+            if (g < n2) {
+                const int c = g % C, mh = g / C;
+                auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
+                double v[E2];
+#pragma unroll
+                for (int u = 0; u < E2; ++u) v[u] = lds[((mh << R2) | u) * C + c];
+                fwd_group<R2>(v, R1, logn, tw, q, P.qinv, gu);
+#pragma unroll
+                for (int u = 0; u < E2; ++u) store(gu(u), v[u], gi * E2 + u);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int gi = 0; gi < IT2; ++gi) {
+            const int g = threadIdx.x + gi * kNttThreads;
+            if (g < n2) {
+                const int c = g % C, mh = g / C;
+                auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
+                double v[E2];
+#pragma unroll
+                for (int u = 0; u < E2; ++u) v[u] = load(gu(u), gi * E2 + u);
+                inv_group<R2>(v, R1, logn, tw, P, false, gu);
+#pragma unroll
+                for (int u = 0; u < E2; ++u) lds[((mh << R2) | u) * C + c] = v[u];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int gi = 0; gi < IT1; ++gi) {
+            const int g = threadIdx.x + gi * kNttThreads;
+            if (g < n1) {
+                const int c = g % C, ml = g / C;
+                auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
+                double v[E1];
+#pragma unroll
+                for (int u = 0; u < E1; ++u) v[u] = lds[((u << (S - R1)) | ml) * C + c];
+                inv_group<R1>(v, 0, logn, tw, P, true, gu);
+#pragma unroll
+                for (int u = 0; u < E1; ++u) store(gu(u), mcanon(v[u], q), gi * E1 + u);
+            }
+        }
+    }
+}
+
+// Row pass: global stages [logn - S, logn) on the tile of blocks [cbase, cbase + C).
+// Inputs |x| <= q.  Forward: the last pass, outputs in [0, q).  Inverse: the
+// first pass, outputs in [-q/2, q/2] for the column pass.
+// The tile is C * 2^S contiguous doubles; the side of the pass that would own
+// 2^R2 consecutive doubles per thread (forward output, inverse input) goes
+// through LDS in coalesced order instead: element e of the tile belongs to
+// thread e mod 256 as slot e / 256.
+template <int S, bool INV, class Load, class Store>
+__device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int cbase, double *lds, Load &&load,
+                                         Store &&store) {
+    constexpr int R = 1 << S;
+    constexpr int R1 = (S + 1) / 2, R2 = S - R1, E1 = 1 << R1, E2 = 1 << R2;
+    constexpr int IT1 = kSlots / E1, IT2 = kSlots / E2;
+    constexpr int PAD = R + R / 16;
+    const int s0 = logn - S;
+    const double q = P.q;
+    const double2 *__restrict__ tw = INV ? P.itw : P.tw;
+    const int n1 = C << (S - R1), n2 = C << R1;
+    const int tot = C * R;
+    const int base = cbase << S;
+    auto gidx = [&](int c, int mid) { return ((cbase + c) << S) | mid; };
+    auto lidx = [&](int c, int mid) { return c * PAD + mid + (mid >> 4); };
+    if (!INV) {
+#pragma unroll
+        for (int gi = 0; gi < IT1; ++gi) {
+            const int g = threadIdx.x + gi * kNttThreads;
+            if (g < n1) {
+                const int ml = g & ((1 << (S - R1)) - 1), c = g >> (S - R1);
+                auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
+                double v[E1];
+#pragma unroll
+                for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
+                fwd_group<R1>(v, s0, logn, tw, q, P.qinv, gu);
+#pragma unroll
+                for (int u = 0; u < E1; ++u) lds[lidx(c, (u << (S - R1)) | ml)] = v[u];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int gi = 0; gi < IT2; ++gi) {
+            const int g = threadIdx.x + gi * kNttThreads;
+            if (g < n2) {
+                const int mh = g & (E1 - 1), c = g >> R1;
+                double v[E2], B[R2];
+#pragma unroll
+                for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
+                row_twiddle_bases<R2>(B, P.rtw, ((cbase + c) << R1) | mh, q, P.qinv);
+                fwd_group_gen<R2>(v, B, P.rc, q, P.qinv);
+#pragma unroll
+                for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const int e = threadIdx.x + k * kNttThreads;
+            if (e < tot) store(base + e, mcanon(lds[lidx(e >> S, e & (R - 1))], q), k);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const int e = threadIdx.x + k * kNttThreads;
+            if (e < tot) lds[lidx(e >> S, e & (R - 1))] = load(base + e, k);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int gi = 0; gi < IT2; ++gi) {
+            const int g = threadIdx.x + gi * kNttThreads;
+            if (g < n2) {
+                const int mh = g & (E1 - 1), c = g >> R1;
+                double v[E2], B[R2];
+#pragma unroll
+                for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
+                row_twiddle_bases<R2>(B, P.irtw, ((cbase + c) << R1) | mh, q, P.qinv);
+                inv_group_gen<R2>(v, B, P.irc, q, P.qinv);
+#pragma unroll
+                for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int gi = 0; gi < IT1; ++gi) {
+            const int g = threadIdx.x + gi * kNttThreads;
+            if (g < n1) {
+                const int ml = g & ((1 << (S - R1)) - 1), c = g >> (S - R1);
+                auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
+                double v[E1];
+#pragma unroll
+                for (int u = 0; u < E1; ++u) v[u] = lds[lidx(c, (u << (S - R1)) | ml)];
+                inv_group<R1>(v, s0, logn, tw, P, false, gu);
+#pragma unroll
+                for (int u = 0; u < E1; ++u) store(gu(u), v[u], gi * E1 + u);
+            }
+        }
+    }
+}
+
+// Pass geometry shared by host launchers and kernels.
+struct PassShape {
+    int S;       // stages in the pass
+    int C;       // sub-transforms per tile
+    int tiles;   // tiles per limb
+};
+
+inline PassShape col_shape(int logn) {
+    PassShape p;
+    p.S = logn / 2;
+    const int subs = 1 << (logn - p.S);
+    p.C = std::min(kNttTile >> p.S, subs);
+    p.tiles = subs / p.C;
+    return p;
+}
+
+inline PassShape row_shape(int logn) {
+    PassShape p;
+    p.S = logn - logn / 2;
+    const int subs = 1 << (logn - p.S);
+    p.C = std::min(kNttTile >> p.S, subs);
+    p.tiles = subs / p.C;
+    return p;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b mod 8).  xcd_slot() turns the hardware id into a logical id such that
+// each XCD works through a contiguous range of logical ids, so logical
+// neighbours (tiles of one limb, targets of one digit) share that XCD's L2.
+// The grid is padded to a multiple of 8; ids >= `n` exit.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_slot(int n) {
+    const int per = (n + kXcds - 1) / kXcds;
+    const int b = blockIdx.x;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+inline unsigned xcd_grid(int n) { return (unsigned)(((n + kXcds - 1) / kXcds) * kXcds); }
+
+}  // namespace pfx
