@@ -1,0 +1,126 @@
+"""Oracle of the private-query circuit (TEST INFRASTRUCTURE ONLY).
+
+The circuit follows the paper's private threshold and count (Alg. 2, lines
+12-15; Sec. 5.3 "Private Threshold Functions"), with the slot-domain linear
+score of the query in place of the paper's coefficient-encoded PFE phase:
+
+  per record block b (2^(logN-1) records in the slots):
+    S   = rescale( sum_a W[a] * X[b][a] )                    linear score
+    Y_k = powers of S up to degree D by the binary tree
+          Y2 = Y1 Y1, Y3 = Y2 Y1, Y4 = Y2 Y2, Y5 = Y4 Y1, Y6 = Y4 Y2, Y7 = Y4 Y3
+    Z   = sum_{k=1..D} rescale(relin(C[k] Y_k)) + C[0]       polynomial p(S)
+    U   = rescale(relin((Z - T) H))                          normalised threshold input
+    3 times (composite sign, degree-7 stage f7(x) = (35x - 35x^3 + 21x^5 - 5x^7)/16):
+        X2 = X X, X4 = X2 X2, X6 = X4 X2                     (relin + rescale each)
+        P  = (-35) X2 + 21 X4 + (-5) X6 + 35                 integer products, constant add
+        X' = rescale(X * round(q / 16))  (constant at the scale of the prime q that the
+                                          rescale drops, so X' keeps X's scale)
+        U  = rescale(relin(X' P))
+    step_b = (U + 1) with the scale doubled                  step = (sign + 1) / 2
+  W   = step_0 + step_1 + ...
+  OUT = rotate-and-sum over all slots (InnerSum)
+
+Additions take the scale of their first operand (the rule of the library).
+Every ct x ct product is relinearised and rescaled.
+
+Readings: the paper's [15,15,15] minimax composite coefficients are not
+printed (Tab. 2); f7 is the closed-form odd polynomial with f7(+-1) = +-1 and
+f7'(+-1) = 0, and the degree-7 score polynomial and the attribute count come
+from the query configuration (N = 2^16, 2^17 records x 8 attributes).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import ckks as O
+
+F7 = (35, -35, 21, -5)   # coefficients of x, x^3, x^5, x^7 over 16
+
+
+def f7(x):
+    return (35 * x - 35 * x ** 3 + 21 * x ** 5 - 5 * x ** 7) / 16.0
+
+
+def fp64_query(x, w, c, t, eta, stages=3):
+    """The circuit in plain FP64 on the records x (records, attributes)."""
+    s = x @ w
+    z = sum(c[k] * s ** k for k in range(len(c)))
+    u = (z - t) * eta
+    for _ in range(stages):
+        u = f7(u)
+    step = (u + 1.0) / 2.0
+    return step, float(step.sum())
+
+
+def _mr(P, a, b, rlk):
+    return O.rescale(P, O.mul_relin(P, a, b, rlk))
+
+
+def _powers(P, y1, D, rlk):
+    Y = {1: y1}
+    if D >= 2:
+        Y[2] = _mr(P, Y[1], Y[1], rlk)
+    if D >= 3:
+        Y[3] = _mr(P, Y[2], Y[1], rlk)
+    if D >= 4:
+        Y[4] = _mr(P, Y[2], Y[2], rlk)
+    if D >= 5:
+        Y[5] = _mr(P, Y[4], Y[1], rlk)
+    if D >= 6:
+        Y[6] = _mr(P, Y[4], Y[2], rlk)
+    if D >= 7:
+        Y[7] = _mr(P, Y[4], Y[3], rlk)
+    assert D <= 7
+    return Y
+
+
+def add_const(P, x: O.Ct, value: float) -> O.Ct:
+    """x + value, the constant encoded at x's scale: round(value * scale) on
+    coefficient 0 (App. A.1: a constant has a single coefficient)."""
+    k = int(O.round_half_away(np.array([value * x.scale]))[0])
+    c = x.c.copy()
+    for i, q in enumerate(P.mods(x.level)):
+        c[0, i, 0] = (int(c[0, i, 0]) + k) % q
+    return O.Ct(c, x.scale)
+
+
+def mul_const_next(P, x: O.Ct, value: float) -> O.Ct:
+    """x times the constant `value` encoded at the scale of x's last prime."""
+    q = P.q[x.level - 1]
+    k = int(O.round_half_away(np.array([value * q]))[0])
+    return O.Ct(O.ct_mul_int(P, x, k).c, x.scale * q)
+
+
+def sign_stage(P, x: O.Ct, rlk) -> O.Ct:
+    x2 = _mr(P, x, x, rlk)
+    x4 = _mr(P, x2, x2, rlk)
+    x6 = _mr(P, x4, x2, rlk)
+    p = O.ct_mul_int(P, x2, -35)
+    p = O.ct_add(P, p, O.ct_mul_int(P, x4, 21))
+    p = O.ct_add(P, p, O.ct_mul_int(P, x6, -5))
+    p = add_const(P, p, 35.0)
+    xs = O.rescale(P, mul_const_next(P, x, 1.0 / 16.0))
+    return _mr(P, xs, p, rlk)
+
+
+def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None):
+    """X[b][a]: plaintext words at scale x_scale; W[a], C[k], T, H: oracle ciphertexts."""
+    D = len(C) - 1
+    total = None
+    for b in range(len(X)):
+        s = O.ct_mul_plain(P, W[0], X[b][0], x_scale)
+        for a in range(1, len(W)):
+            s = O.ct_add(P, s, O.ct_mul_plain(P, W[a], X[b][a], x_scale))
+        s = O.rescale(P, s)
+        Y = _powers(P, s, D, rlk)
+        z = _mr(P, C[1], Y[1], rlk)
+        for k in range(2, D + 1):
+            z = O.ct_add(P, z, _mr(P, C[k], Y[k], rlk))
+        z = O.ct_add(P, z, C[0])
+        u = _mr(P, O.ct_sub(P, z, T), H, rlk)
+        for _ in range(stages):
+            u = sign_stage(P, u, rlk)
+        step = add_const(P, u, 1.0)
+        step = O.Ct(step.c, step.scale * 2.0)
+        total = step if total is None else O.ct_add(P, total, step)
+    return O.rotate_sum(P, total, log_slots if log_slots is not None else P.logn - 1, gks)

@@ -65,3 +65,15 @@ def synthetic_database(records: int, attributes: int, seed: int):
     x = g.normal(mu, sd, size=(records, attributes))
     x = np.clip(x, 0.0, np.nextafter(2.0, 0.0))
     return x - 1.0
+
+
+def query_parameters(attributes: int, degree: int, seed: int):
+    """Encrypted query parameters of the private query: weights w ~ U[-1,1]/A,
+    score-polynomial coefficients c ~ U[-1,1] scaled to sum |c_k| = 1,
+    threshold t ~ U[-0.5, 0.5], normalisation eta = 1/2."""
+    g = rng(seed)
+    w = g.uniform(-1.0, 1.0, size=attributes) / attributes
+    c = g.uniform(-1.0, 1.0, size=degree + 1)
+    c = c / np.abs(c).sum()
+    t = float(g.uniform(-0.5, 0.5))
+    return w, c, t, 0.5
