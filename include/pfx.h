@@ -212,12 +212,75 @@ pfx_status pfx_conjugate(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *const *ke
 pfx_status pfx_rotate_sum(pfx_ctx *ctx, const pfx_ct *a, uint32_t log_steps,
                           const pfx_swk *const *keys, size_t n_keys, pfx_ct *out, void *stream);
 
+/* x + value in every slot: the constant polynomial round(value * scale_x)
+ * (App. A.1: a constant has only coefficient 0) added to c0. */
+pfx_status pfx_add_const(pfx_ctx *ctx, const pfx_ct *a, double value, pfx_ct *out, void *stream);
+/* x times the constant round(value * cscale) (every slot times value); the
+ * scale multiplies by cscale.  cscale <= 0 takes the last prime of x, so that
+ * a following rescale returns x's scale. */
+pfx_status pfx_mul_const(pfx_ctx *ctx, const pfx_ct *a, double value, double cscale, pfx_ct *out,
+                         void *stream);
+
 /* Standalone negacyclic NTT on device words (canonical residues), in place:
  * d_words holds `batch` blocks of n_limbs limbs of N words; limb i of every
  * block uses prime first_prime + i (prime index: q's then p's).  Output order
  * is NTT(a)[j] = sum_k a_k psi^(k (2 bitrev(j) + 1)); inverse = 1 undoes it. */
 pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32_t n_limbs,
                    size_t batch, int inverse, void *stream);
+
+/* ------------------------------------------------------------ circuits */
+/*
+ * Op-list executor: a query circuit (e.g. Alg. 2's threshold and count) as a
+ * list of register operations run natively, optionally captured once into a
+ * HIP graph and replayed.  Registers are caller-created ciphertexts (capacity
+ * n_q limbs, degree 2); registers [0, n_inputs) are read-only inputs.
+ * Plaintexts are the database operands.  `gks` holds the Galois keys that
+ * ROTATE / ROTATE_SUM need; `rlk` the relinearisation key.
+ *   op            effect                                         operands
+ *   COPY          dst = a
+ *   ADD, SUB      dst = a +- b (scale of a)                      b register
+ *   MUL_PLAIN     dst = a * pts[b]                               b plaintext
+ *   ADD_PLAIN     dst = a + pts[b]                               b plaintext
+ *   MUL_INT       dst = a * k                                    k
+ *   MUL_RELIN     dst = relin(a * b)                             b register
+ *   RESCALE       dst = rescale(a)
+ *   ADD_CONST     dst = a + value (pfx_add_const)                value
+ *   MUL_CONST     dst = a * value at the last prime's scale      value
+ *   SCALE_MUL     dst = a with scale * value (value / factor)    value
+ *   ROTATE        dst = rotate(a, k)                             k
+ *   ROTATE_SUM    dst = InnerSum(a) over 2^k slots               k
+ * use_graph != 0 (non-NULL stream required): the first call for a given op
+ * list, register set, plaintexts and keys is captured into a HIP graph and
+ * launched; later calls replay it.  Register metadata (limbs, scale) after a
+ * replay equals that of the captured run.
+ */
+#define PFX_OP_COPY 0
+#define PFX_OP_ADD 1
+#define PFX_OP_SUB 2
+#define PFX_OP_MUL_PLAIN 3
+#define PFX_OP_ADD_PLAIN 4
+#define PFX_OP_MUL_INT 5
+#define PFX_OP_MUL_RELIN 6
+#define PFX_OP_RESCALE 7
+#define PFX_OP_ADD_CONST 8
+#define PFX_OP_MUL_CONST 9
+#define PFX_OP_SCALE_MUL 10
+#define PFX_OP_ROTATE 11
+#define PFX_OP_ROTATE_SUM 12
+
+typedef struct pfx_op {
+    int32_t code;
+    int32_t dst;
+    int32_t a;
+    int32_t b;
+    int64_t k;
+    double value;
+} pfx_op;
+
+pfx_status pfx_run_circuit(pfx_ctx *ctx, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs,
+                           size_t n_regs, size_t n_inputs, const pfx_pt *const *pts, size_t n_pts,
+                           const pfx_swk *rlk, const pfx_swk *const *gks, size_t n_gks, int use_graph,
+                           void *stream);
 
 /* ------------------------------------------------------------ plumbing */
 /* Device memory and streams for callers that hold raw words (pfx_ntt).  The

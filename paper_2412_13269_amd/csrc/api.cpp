@@ -51,7 +51,7 @@ hipStream_t S(void *stream) { return (hipStream_t)stream; }
 
 // Scratch of one stream, sized for the top level.
 struct WsLayout {
-    size_t dcoef, ext, acc, mdtmp, t3, rs_last, rs_tmp, xport, total;
+    size_t dcoef, ext, acc, mdtmp, t3, rs_last, rs_tmp, xport, rot, total;
 };
 
 WsLayout ws_layout(const pfx_ctx *c) {
@@ -66,6 +66,7 @@ WsLayout ws_layout(const pfx_ctx *c) {
     w.rs_last = o; o += 3 * N;
     w.rs_tmp = o; o += 3 * L * N;
     w.xport = o; o += std::max<size_t>(3 * L, (size_t)E) * N;   // u64 staging (same word size)
+    w.rot = o; o += 2 * L * N;                                   // rotate-sum temporary ciphertext
     w.total = o;
     return w;
 }
@@ -435,6 +436,7 @@ void pfx_ctx_destroy(pfx_ctx *c) {
         hipEventDestroy(e.stop);
     }
     for (auto e : c->prof_pool) hipEventDestroy(e);
+    for (auto &kv : c->graphs) hipGraphExecDestroy(kv.second.exec);
     hipFree(c->d_tw);
     hipFree(c->d_rtw);
     hipFree(c->d_primes);
@@ -1048,17 +1050,59 @@ pfx_status pfx_rotate_sum(pfx_ctx *c, const pfx_ct *a, uint32_t log_steps, const
         ks[k] = find_key(c, rot_element(c, 1ll << k), keys, n);
         if (!ks[k]) return fail(PFX_ENOKEY, "no Galois key for rotation step " + std::to_string(1 << k));
     }
-    pfx_ct *tmp = nullptr;
-    r = pfx_ct_create(c, a->n_limbs, 1, &tmp);
+    Ws w;
+    r = get_ws(c, S(stream), w);
     if (r) return r;
+    pfx_ct tmp;                       // a view of the workspace, no allocation
+    tmp.ctx = c;
+    tmp.cap_limbs = c->L;
+    tmp.cap_degree = 1;
+    tmp.d = w.at(w.lay.rot);
     r = pfx_ct_copy(c, a, out, stream);
     for (uint32_t k = 0; k < log_steps && !r; ++k) {
-        r = galois_apply(c, out, ks[k], tmp, S(stream));
-        if (!r) r = pfx_add(c, out, tmp, out, stream);
+        r = galois_apply(c, out, ks[k], &tmp, S(stream));
+        if (!r) r = pfx_add(c, out, &tmp, out, stream);
     }
-    hipStreamSynchronize(S(stream));
-    pfx_ct_destroy(tmp);
     return r;
+}
+
+pfx_status pfx_add_const(pfx_ctx *c, const pfx_ct *a, double value, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_out(out, a->n_limbs, a->degree);
+    if (r) return r;
+    const double v = value * a->scale;
+    REQUIRE(std::isfinite(v) && std::fabs(v) < 9.0e18, PFX_EINVAL, "constant times scale out of range");
+    const int64_t k = (int64_t)(v < 0 ? -std::floor(-v + 0.5) : std::floor(v + 0.5));   // half away from zero
+    std::vector<uint64_t> cst(a->n_limbs);
+    for (uint32_t i = 0; i < a->n_limbs; ++i) {
+        const uint64_t q = c->primes[i];
+        const uint64_t mag = (uint64_t)(k < 0 ? -k : k) % q;
+        cst[i] = k < 0 ? (q - mag) % q : mag;
+    }
+    Launch L{c, S(stream)};
+    launch_addconst(L, out->poly(0), a->poly(0), a->n_limbs, cst.data());
+    if (out != a && a->degree >= 1)
+        launch_ew(L, EW_COPY, out->poly(1), a->poly(1), nullptr, out->cap_limbs * (size_t)c->N,
+                  a->cap_limbs * (size_t)c->N, 0, a->degree, a->n_limbs);
+    out->n_limbs = a->n_limbs;
+    out->degree = a->degree;
+    out->scale = a->scale;
+    return PFX_OK;
+}
+
+pfx_status pfx_mul_const(pfx_ctx *c, const pfx_ct *a, double value, double cscale, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    if (cscale <= 0) cscale = (double)c->primes[a->n_limbs - 1];
+    const double v = value * cscale;
+    REQUIRE(std::isfinite(v) && std::fabs(v) < 9.0e18, PFX_EINVAL, "constant times scale out of range");
+    const int64_t k = (int64_t)(v < 0 ? -std::floor(-v + 0.5) : std::floor(v + 0.5));
+    const double sc = a->scale * cscale;
+    r = pfx_mul_int(c, a, k, out, stream);
+    if (r) return r;
+    out->scale = sc;
+    return PFX_OK;
 }
 
 pfx_status pfx_ntt(pfx_ctx *c, uint64_t *d_words, uint32_t first_prime, uint32_t n_limbs, size_t batch, int inverse,
@@ -1089,6 +1133,103 @@ pfx_status pfx_ntt(pfx_ctx *c, uint64_t *d_words, uint32_t first_prime, uint32_t
         }
         launch_f64_to_u64(L, d_words + l0 * N, buf, nl * N);
     }
+    return PFX_OK;
+}
+
+// ------------------------------------------------------------------ circuits
+static pfx_status run_ops(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
+                          size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
+                          const pfx_swk *const *gks, size_t n_gks, void *stream) {
+    auto R = [&](int32_t k) -> pfx_ct * { return (k >= 0 && (size_t)k < n_regs) ? regs[k] : nullptr; };
+    for (size_t i = 0; i < n_ops; ++i) {
+        const pfx_op &o = ops[i];
+        pfx_ct *d = R(o.dst), *A = R(o.a);
+        const std::string at = "op " + std::to_string(i) + ": ";
+        if (!d || !A) return fail(PFX_EINVAL, at + "register index out of range");
+        if ((size_t)o.dst < n_inputs) return fail(PFX_EINVAL, at + "writes an input register");
+        const pfx_pt *pt = (o.b >= 0 && (size_t)o.b < n_pts) ? pts[o.b] : nullptr;
+        pfx_status r;
+        switch (o.code) {
+            case PFX_OP_COPY: r = pfx_ct_copy(c, A, d, stream); break;
+            case PFX_OP_ADD: r = pfx_add(c, A, R(o.b), d, stream); break;
+            case PFX_OP_SUB: r = pfx_sub(c, A, R(o.b), d, stream); break;
+            case PFX_OP_MUL_PLAIN: r = pfx_mul_plain(c, A, pt, d, stream); break;
+            case PFX_OP_ADD_PLAIN: r = pfx_add_plain(c, A, pt, d, stream); break;
+            case PFX_OP_MUL_INT: r = pfx_mul_int(c, A, o.k, d, stream); break;
+            case PFX_OP_MUL_RELIN: r = pfx_mul_relin(c, A, R(o.b), rlk, d, stream); break;
+            case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
+            case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
+            case PFX_OP_MUL_CONST: r = pfx_mul_const(c, A, o.value, 0.0, d, stream); break;
+            case PFX_OP_SCALE_MUL: {
+                const double sc = A->scale * o.value;
+                r = pfx_ct_copy(c, A, d, stream);
+                if (!r) d->scale = sc;
+                break;
+            }
+            case PFX_OP_ROTATE: r = pfx_rotate(c, A, (int32_t)o.k, gks, n_gks, d, stream); break;
+            case PFX_OP_ROTATE_SUM: r = pfx_rotate_sum(c, A, (uint32_t)o.k, gks, n_gks, d, stream); break;
+            default: return fail(PFX_EINVAL, at + "unknown op code");
+        }
+        if (r) return fail(r, at + g_err);
+    }
+    return PFX_OK;
+}
+
+pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
+                           size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
+                           const pfx_swk *const *gks, size_t n_gks, int use_graph, void *stream) {
+    REQUIRE(c && ops && regs, PFX_EINVAL, "null argument");
+    REQUIRE(n_inputs <= n_regs, PFX_EINVAL, "n_inputs > n_regs");
+    for (size_t i = 0; i < n_regs; ++i) REQUIRE(regs[i] && regs[i]->ctx == c, PFX_EINVAL, "bad register");
+    if (!use_graph) return run_ops(c, ops, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream);
+    REQUIRE(stream != nullptr, PFX_EINVAL, "graph capture needs a non-default stream");
+    // the graph is valid for this op list, these objects and these input shapes
+    std::string key((const char *)ops, n_ops * sizeof(pfx_op));
+    auto put = [&](const void *p, size_t n) { key.append((const char *)p, n); };
+    for (size_t i = 0; i < n_regs; ++i) put(&regs[i]->d, sizeof(double *));
+    for (size_t i = 0; i < n_inputs; ++i) {
+        put(&regs[i]->n_limbs, sizeof(uint32_t));
+        put(&regs[i]->degree, sizeof(uint32_t));
+        put(&regs[i]->scale, sizeof(double));
+    }
+    for (size_t i = 0; i < n_pts; ++i) put(&pts[i]->d, sizeof(double *));
+    for (size_t i = 0; i < n_gks; ++i) put(&gks[i]->d_k, sizeof(double *));
+    if (rlk) put(&rlk->d_k, sizeof(double *));
+    put(&stream, sizeof(void *));
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        Ws w;
+        pfx_status r = get_ws(c, S(stream), w);   // allocate scratch before capturing
+        if (r) return r;
+        const bool prof = c->prof_on;
+        c->prof_on = false;
+        c->capturing = true;
+        HIPCHECK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal));
+        r = run_ops(c, ops, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(S(stream), &g);
+        c->capturing = false;
+        c->prof_on = prof;
+        if (r) {
+            if (g) hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        pfx_ctx::GraphEntry ent;
+        e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        for (size_t i = 0; i < n_regs; ++i)
+            ent.meta.push_back({regs[i]->n_limbs | (regs[i]->degree << 16), regs[i]->scale});
+        it = c->graphs.emplace(key, ent).first;
+    } else {
+        for (size_t i = n_inputs; i < n_regs; ++i) {
+            regs[i]->n_limbs = it->second.meta[i].first & 0xffff;
+            regs[i]->degree = it->second.meta[i].first >> 16;
+            regs[i]->scale = it->second.meta[i].second;
+        }
+    }
+    HIPCHECK(hipGraphLaunch(it->second.exec, S(stream)));
     return PFX_OK;
 }
 

@@ -107,6 +107,14 @@ struct pfx_ctx {
     // (accumulators in registers).  Chosen at context creation (PFX_KS_VARIANT).
     int ks_variant = 0;
 
+    // captured op lists (pfx_run_circuit with use_graph)
+    struct GraphEntry {
+        hipGraphExec_t exec;
+        std::vector<std::pair<uint32_t, double>> meta;   // (n_limbs | degree << 16, scale) per register
+    };
+    std::map<std::string, GraphEntry> graphs;
+    bool capturing = false;
+
     bool prof_on = false;
     std::vector<pfx::ProfEntry> prof_pending;
     std::map<std::string, pfx::ProfTotal> prof_done;
@@ -178,6 +186,7 @@ void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const dou
 // out[k][i] = a[k][i] * cst_i (+ 0) with per-limb constant words.
 void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, size_t sa, int npoly,
                      int nl, const uint64_t *cst);
+void launch_addconst(const Launch &L, double *out, const double *a, int nl, const uint64_t *cst);
 void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const double *a0,
                    const double *a1, const double *b0, const double *b1, int nl);
 void launch_automorph(const Launch &L, double *out, const double *in, size_t so, size_t si, int npoly,

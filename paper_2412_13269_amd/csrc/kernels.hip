@@ -241,6 +241,28 @@ void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, s
     prof_end(L, "mulconst", ev, 16.0 * (double)total);
 }
 
+// out[i][c] = a[i][c] + cst_i: a constant polynomial (coefficient 0 only) is the
+// same value at every NTT slot.
+__global__ void k_addconst(double *out, const double *a, int nl, int logn, const PrimeDev *pr, const LimbConsts k) {
+    const size_t total = (size_t)nl << logn;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx >> logn);
+        out[idx] = madd(a[idx], k.w[i], pr[i].q);
+    }
+}
+
+void launch_addconst(const Launch &L, double *out, const double *a, int nl, const uint64_t *cst) {
+    LimbConsts k;
+    for (int i = 0; i < nl; ++i) k.w[i] = (double)cst[i];
+    const size_t total = (size_t)nl << L.ctx->logn;
+    hipEvent_t ev;
+    prof_begin(L, "addconst", &ev);
+    k_addconst<<<grid_for(total), 256, 0, L.st>>>(out, a, nl, L.ctx->logn, L.ctx->d_primes, k);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "addconst", ev, 16.0 * (double)total);
+}
+
 // Tensor product in the NTT domain (Sec. 2.4.2): d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.
 __global__ void k_tensor(double *d0, double *d1, double *d2, const double *a0, const double *a1, const double *b0,
                          const double *b1, int nl, int logn, const PrimeDev *pr) {

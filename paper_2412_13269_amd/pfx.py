@@ -38,6 +38,15 @@ class pfx_params(ctypes.Structure):
                 ("mod_log2", ctypes.c_uint32)]
 
 
+class pfx_op(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("dst", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("k", ctypes.c_int64), ("value", ctypes.c_double)]
+
+
+OP_COPY, OP_ADD, OP_SUB, OP_MUL_PLAIN, OP_ADD_PLAIN, OP_MUL_INT, OP_MUL_RELIN = 0, 1, 2, 3, 4, 5, 6
+OP_RESCALE, OP_ADD_CONST, OP_MUL_CONST, OP_SCALE_MUL, OP_ROTATE, OP_ROTATE_SUM = 7, 8, 9, 10, 11, 12
+
+
 class pfx_info(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_limbs", ctypes.c_uint32),
                 ("degree", ctypes.c_uint32), ("scale", ctypes.c_double)]
@@ -98,6 +107,10 @@ _SIGS = {
     "pfx_conjugate": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp]),
     "pfx_rotate_sum": (_i32, [_vp, _vp, _u32, _VPP, _sz, _vp, _vp]),
     "pfx_ntt": (_i32, [_vp, _vp, _u32, _u32, _sz, ctypes.c_int, _vp]),
+    "pfx_add_const": (_i32, [_vp, _vp, ctypes.c_double, _vp, _vp]),
+    "pfx_mul_const": (_i32, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
+    "pfx_run_circuit": (_i32, [_vp, ctypes.POINTER(pfx_op), _sz, _VPP, _sz, _sz, _VPP, _sz, _vp, _VPP, _sz,
+                               ctypes.c_int, _vp]),
     "pfx_dev_alloc": (_i32, [_vp, _sz, _VPP]),
     "pfx_dev_free": (_i32, [_vp, _vp]),
     "pfx_memcpy_htod": (_i32, [_vp, _vp, _vp, _sz, _vp]),
@@ -388,6 +401,24 @@ def pfx_rotate_sum(ctx, a, log_steps: int, keys, out, stream=None):
 def pfx_ntt(ctx, d_words_ptr: int, first_prime: int, n_limbs: int, batch: int, inverse: bool, stream=None):
     _check(_lib.pfx_ntt(ctx, ctypes.c_void_p(d_words_ptr), first_prime, n_limbs, batch, int(inverse),
                         _stream(stream)))
+
+
+def pfx_add_const(ctx, a, value: float, out, stream=None):
+    _check(_lib.pfx_add_const(ctx, a, value, out, _stream(stream)))
+
+
+def pfx_mul_const(ctx, a, value: float, cscale: float, out, stream=None):
+    _check(_lib.pfx_mul_const(ctx, a, value, cscale, out, _stream(stream)))
+
+
+def pfx_run_circuit(ctx, ops, regs, n_inputs: int, pts, rlk, gks, use_graph: bool = False, stream=None):
+    """ops: a sequence of (code, dst, a, b, k, value)."""
+    arr = (pfx_op * max(1, len(ops)))(*[pfx_op(*o) for o in ops])
+    R = (ctypes.c_void_p * max(1, len(regs)))(*regs)
+    Pt = (ctypes.c_void_p * max(1, len(pts)))(*pts)
+    G = (ctypes.c_void_p * max(1, len(gks)))(*gks)
+    _check(_lib.pfx_run_circuit(ctx, arr, len(ops), R, len(regs), n_inputs, Pt, len(pts), rlk, G, len(gks),
+                                int(use_graph), _stream(stream)))
 
 
 # ---------------------------------------------------------------- plumbing

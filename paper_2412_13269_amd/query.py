@@ -1,0 +1,133 @@
+"""The private query as a native op list (pfx_run_circuit).
+
+Circuit (the threshold-and-count phase of the paper's Alg. 2, with a
+slot-domain linear score): for each block b of 2^(logN-1) records
+
+    S   = rescale(sum_a W[a] * X[b][a])
+    Y_k = S^k by the binary power tree (Y2 = Y1 Y1, Y3 = Y2 Y1, Y4 = Y2 Y2,
+          Y5 = Y4 Y1, Y6 = Y4 Y2, Y7 = Y4 Y3; each relinearised and rescaled)
+    Z   = sum_{k=1..D} rescale(relin(C[k] Y_k)) + C[0]
+    U   = rescale(relin((Z - T) H))
+    3 stages of f7(x) = (35x - 35x^3 + 21x^5 - 5x^7)/16:
+        X2 = X^2, X4 = X2^2, X6 = X4 X2
+        P  = (-35) X2 + 21 X4 + (-5) X6 + 35
+        U  = rescale(relin(rescale(X * round(q/16)) * P))
+    step_b = (U + 1) with the scale doubled
+  OUT = InnerSum(step_0 + step_1 + ...)
+
+Inputs (registers, read-only): W[0..A), C[0..D], T, H.  Plaintexts: X[b][a]
+at index b * A + a.  The op list and the register allocation are built here;
+the library executes them (eagerly, or captured once into a HIP graph).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+from . import pfx as X
+
+
+@dataclass
+class QueryPlan:
+    n_blocks: int
+    attributes: int = 8
+    degree: int = 7
+    stages: int = 3
+    log_slots: int = 15
+    ops: list = field(default_factory=list)
+    n_regs: int = 0
+    out: int = -1
+
+    def __post_init__(self):
+        A, D = self.attributes, self.degree
+        assert 1 <= D <= 7 and A >= 1 and self.n_blocks >= 1
+        self.W = list(range(A))
+        self.C = list(range(A, A + D + 1))
+        self.T = A + D + 1
+        self.H = A + D + 2
+        self.n_inputs = A + D + 3
+        self._free: list[int] = []
+        self._next = self.n_inputs
+        self._build()
+        self.n_regs = self._next
+
+    # register allocation
+    def _new(self) -> int:
+        if self._free:
+            return self._free.pop()
+        r = self._next
+        self._next += 1
+        return r
+
+    def _drop(self, *regs):
+        for r in regs:
+            if r >= self.n_inputs:
+                self._free.append(r)
+
+    def _op(self, code, dst, a, b=-1, k=0, value=0.0):
+        self.ops.append((code, dst, a, b, k, value))
+
+    def _mr(self, dst, a, b):
+        self._op(X.OP_MUL_RELIN, dst, a, b)
+        self._op(X.OP_RESCALE, dst, dst)
+
+    def _block(self, b: int) -> int:
+        A, D = self.attributes, self.degree
+        s = self._new()
+        self._op(X.OP_MUL_PLAIN, s, self.W[0], b * A)
+        t = self._new()
+        for a in range(1, A):
+            self._op(X.OP_MUL_PLAIN, t, self.W[a], b * A + a)
+            self._op(X.OP_ADD, s, s, t)
+        self._op(X.OP_RESCALE, s, s)
+        Y = {1: s}
+        tree = {2: (1, 1), 3: (2, 1), 4: (2, 2), 5: (4, 1), 6: (4, 2), 7: (4, 3)}
+        for k in range(2, D + 1):
+            Y[k] = self._new()
+            self._mr(Y[k], Y[tree[k][0]], Y[tree[k][1]])
+        z = self._new()
+        self._mr(z, self.C[1], Y[1])
+        for k in range(2, D + 1):
+            self._mr(t, self.C[k], Y[k])
+            self._op(X.OP_ADD, z, z, t)
+        self._op(X.OP_ADD, z, z, self.C[0])
+        self._drop(*Y.values())
+        u = self._new()
+        self._op(X.OP_SUB, u, z, self.T)
+        self._mr(u, u, self.H)
+        self._drop(z)
+        for _ in range(self.stages):
+            x2, x4, x6, p = self._new(), self._new(), self._new(), self._new()
+            self._mr(x2, u, u)
+            self._mr(x4, x2, x2)
+            self._mr(x6, x4, x2)
+            self._op(X.OP_MUL_INT, p, x2, k=-35)
+            self._op(X.OP_MUL_INT, t, x4, k=21)
+            self._op(X.OP_ADD, p, p, t)
+            self._op(X.OP_MUL_INT, t, x6, k=-5)
+            self._op(X.OP_ADD, p, p, t)
+            self._op(X.OP_ADD_CONST, p, p, value=35.0)
+            self._op(X.OP_MUL_CONST, x2, u, value=1.0 / 16.0)
+            self._op(X.OP_RESCALE, x2, x2)
+            self._mr(u, x2, p)
+            self._drop(x2, x4, x6, p)
+        self._op(X.OP_ADD_CONST, u, u, value=1.0)
+        self._op(X.OP_SCALE_MUL, u, u, value=2.0)
+        self._drop(t)
+        return u
+
+    def _build(self):
+        total = None
+        for b in range(self.n_blocks):
+            u = self._block(b)
+            if total is None:
+                total = u
+            else:
+                self._op(X.OP_ADD, total, total, u)
+                self._drop(u)
+        self.out = self._new()
+        self._op(X.OP_ROTATE_SUM, self.out, total, k=self.log_slots)
+        self._drop(total)
+
+    @property
+    def key_switches(self) -> int:
+        return sum(1 for o in self.ops if o[0] == X.OP_MUL_RELIN) + self.log_slots

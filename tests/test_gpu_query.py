@@ -1,0 +1,180 @@
+"""The private query on the GPU (op list, eager and HIP-graph replay) against
+the oracle circuit word for word, and at full size against FP64."""
+import numpy as np
+import pytest
+
+from oracle import ckks as O
+from oracle import query as Q
+from paper_2412_13269_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+QB, PB, ALPHA, ML = [50] + [45] * 23, [50] * 4, 4, 17
+DELTA = 2.0 ** 45
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_2412_13269_amd import pfx
+    return pfx
+
+
+def spread(x, w):
+    s = x @ w
+    t = float(np.median(s))
+    c = np.zeros(8)
+    c[1] = 1.0
+    return c, t, 0.9 / float(np.max(np.abs(s - t)))
+
+
+def gap_records(x, w, c, t, eta, gap, seed):
+    """Keep records whose threshold input u satisfies gap <= |u| <= 0.95,
+    drawing more from the same distribution until there are len(x) of them."""
+    want, A = len(x), x.shape[1]
+    keep, it = [], 0
+    pool = x
+    while sum(len(k) for k in keep) < want:
+        s = pool @ w
+        u = (sum(c[k] * s ** k for k in range(len(c))) - t) * eta
+        keep.append(pool[(np.abs(u) >= gap) & (np.abs(u) <= 0.95)])
+        it += 1
+        pool = I.synthetic_database(4 * want, A, seed + 1000 + it)
+    return np.concatenate(keep)[:want]
+
+
+class Setup:
+    """Library objects for one query; oracle twins built only when asked."""
+
+    def __init__(self, X, logn, n_blocks, seed, gap=None, with_oracle=False):
+        from paper_2412_13269_amd.query import QueryPlan
+        self.X = X
+        self.logn, self.N, self.n = logn, 1 << logn, 1 << (logn - 1)
+        A, D = 8, 7
+        self.x = I.synthetic_database(self.n * n_blocks, A, seed)
+        w, c, t, eta = I.query_parameters(A, D, seed + 1)
+        if gap is not None:
+            c, t, eta = spread(self.x, w)
+            self.x = gap_records(self.x, w, c, t, eta, gap, seed)
+        self.params = (w, c, t, eta)
+        self.plan = QueryPlan(n_blocks, A, D, 3, logn - 1)
+        prm = X.make_params(logn, QB, PB, ALPHA, ML)
+        self.ctx = X.pfx_ctx_create(prm, 0)
+        q, p, _ = X.pfx_ctx_moduli(self.ctx, len(QB), len(PB))
+        self.q = [int(v) for v in q]
+        ext = self.q + [int(v) for v in p]
+        beta = -(-len(QB) // ALPHA)
+        N = self.N
+        self.s = I.ternary_secret(N, 192, seed + 2)
+        self.sk = X.pfx_sk_create(self.ctx, self.s)
+        self.key_in = {0: (I.uniform_residues(ext, N, seed + 3, lead=(beta,)), I.gaussian_error((beta, N), seed + 4))}
+        for k in range(logn - 1):
+            g = pow(5, 1 << k, 2 * N)
+            self.key_in[g] = (I.uniform_residues(ext, N, seed + 10 + 2 * k, lead=(beta,)),
+                              I.gaussian_error((beta, N), seed + 11 + 2 * k))
+        self.rlk = X.pfx_swk_create(self.ctx, self.sk, 0, *self.key_in[0])
+        self.gks = [X.pfx_swk_create(self.ctx, self.sk, g, *v) for g, v in self.key_in.items() if g]
+        # encrypted parameters (broadcast) and database plaintexts: oracle-encoded words
+        self.P = O.Params(logn, QB, PB, alpha=ALPHA, mod_log2=ML) if with_oracle else None
+        if with_oracle:       # words fed to both sides come from the oracle's encoder
+            assert self.P.q == self.q
+            encode = lambda z: O.encode(self.P, z, DELTA, len(QB))
+        else:
+            encode = lambda z: X.pfx_encode_words(prm, z, None, len(QB), DELTA)
+        enc_words = [encode(np.full(self.n, v)) for v in list(w) + list(c) + [t, eta]]
+        self.enc_in = []
+        self.regs = [X.pfx_ct_create(self.ctx, len(QB), 1) for _ in range(self.plan.n_regs)]
+        self.pts = []
+        for i, m in enumerate(enc_words):
+            a = I.uniform_residues(self.q, N, seed + 500 + 2 * i)
+            e = I.gaussian_error(N, seed + 501 + 2 * i)
+            self.enc_in.append((m, a, e))
+            pt = X.pfx_pt_import(self.ctx, m, DELTA)
+            X.pfx_encrypt(self.ctx, self.sk, pt, a, e, self.regs[i])
+            X.pfx_ct_destroy(pt)
+        self.db_words = []
+        for b in range(n_blocks):
+            for a in range(A):
+                m = encode(self.x[b * self.n:(b + 1) * self.n, a])
+                self.db_words.append(m)
+                self.pts.append(X.pfx_pt_import(self.ctx, m, DELTA))
+        self.stream = X.pfx_stream_create(self.ctx)
+
+    def run(self, graph=False):
+        X = self.X
+        X.pfx_run_circuit(self.ctx, self.plan.ops, self.regs, self.plan.n_inputs, self.pts, self.rlk, self.gks,
+                          graph, self.stream)
+        X.pfx_sync(self.ctx, self.stream)
+        return self.regs[self.plan.out]
+
+    def count(self, ct):
+        X = self.X
+        m = X.pfx_decrypt(self.ctx, self.sk, ct)
+        z = X.pfx_decode(self.ctx, m, self.n)
+        X.pfx_ct_destroy(m)
+        return z.real
+
+    def oracle_out(self):
+        P = self.P
+        ct = lambda m, a, e: O.encrypt(P, self.s, m, a, e, DELTA)
+        cts = [ct(*v) for v in self.enc_in]
+        A, D = 8, 7
+        W, C, T, H = cts[:A], cts[A:A + D + 1], cts[A + D + 1], cts[A + D + 2]
+        rlk = O.relin_key(P, self.s, *self.key_in[0])
+        gks = {g: O.galois_key(P, self.s, g, *v) for g, v in self.key_in.items() if g}
+        Xw = [[self.db_words[b * A + a] for a in range(A)] for b in range(len(self.db_words) // A)]
+        return Q.query_circuit(P, Xw, DELTA, W, C, T, H, rlk, gks)
+
+    def close(self):
+        X = self.X
+        for h in self.regs + self.pts:
+            X.pfx_ct_destroy(h)
+        for k in self.gks + [self.rlk]:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(self.sk)
+        X.pfx_stream_destroy(self.ctx, self.stream)
+        X.pfx_ctx_destroy(self.ctx)
+
+
+def test_query_words_match_oracle_eager_and_graph(X):
+    S = Setup(X, 12, 2, 31, with_oracle=True)
+    try:
+        want = S.oracle_out()
+        out = S.run(graph=False)
+        got = X.pfx_ct_export(S.ctx, out, S.N)
+        assert got.shape == want.c.shape
+        assert np.array_equal(got, want.c)
+        assert X.pfx_ct_info(out).scale == want.scale
+        # graph: captured once, replayed; eager runs in between; every replay checked
+        for rep in range(3):
+            out = S.run(graph=True)
+            assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), want.c), rep
+            out = S.run(graph=False)
+            assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), want.c), rep
+        step, count = Q.fp64_query(S.x, *S.params)
+        assert abs(S.count(out)[0] - count) < 0.25
+    finally:
+        S.close()
+
+
+def test_full_size_query_count(X):
+    # 2^17 records x 8 attributes at N = 2^16 (4 blocks of 2^15 slots)
+    S = Setup(X, 16, 4, 41)
+    try:
+        out = S.run(graph=True)
+        got = S.count(out)
+        step, count = Q.fp64_query(S.x, *S.params)
+        assert abs(got[0] - count) < 0.25
+        assert np.max(np.abs(got - got[0])) < 1e-3
+    finally:
+        S.close()
+
+
+def test_full_size_query_exact_count_on_gap_data(X):
+    S = Setup(X, 16, 4, 43, gap=0.4)
+    try:
+        got = S.count(S.run(graph=False))
+        step, count = Q.fp64_query(S.x, *S.params)
+        exact = int(np.sum(step > 0.5))
+        assert int(round(got[0])) == exact
+    finally:
+        S.close()

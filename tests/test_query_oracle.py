@@ -29,6 +29,21 @@ def spread_parameters(x, w):
     return c, t, 0.9 / float(np.max(np.abs(s - t)))
 
 
+def gap_records(x, w, c, t, eta, gap, seed):
+    """Keep records whose threshold input u satisfies gap <= |u| <= 0.95,
+    drawing more from the same distribution until there are len(x) of them."""
+    want, A = len(x), x.shape[1]
+    keep, it = [], 0
+    pool = x
+    while sum(len(k) for k in keep) < want:
+        s = pool @ w
+        u = (sum(c[k] * s ** k for k in range(len(c))) - t) * eta
+        keep.append(pool[(np.abs(u) >= gap) & (np.abs(u) <= 0.95)])
+        it += 1
+        pool = I.synthetic_database(4 * want, A, seed + 1000 + it)
+    return np.concatenate(keep)[:want]
+
+
 def build(logn, n_blocks, seed, gap=None):
     P = O.Params(logn, [50] + [45] * 23, [50] * 4, alpha=4, mod_log2=17)
     N, n = P.N, P.N // 2
@@ -37,15 +52,8 @@ def build(logn, n_blocks, seed, gap=None):
     w, c, t, eta = I.query_parameters(A, D, seed + 1)
     if gap is not None:
         c, t, eta = spread_parameters(x, w)
-    if gap is not None:       # redraw records whose threshold input is within the gap
-        for it in range(50):
-            s = x @ w
-            u = (sum(c[k] * s ** k for k in range(D + 1)) - t) * eta
-            bad = np.abs(u) < gap
-            if not bad.any():
-                break
-            x[bad] = I.synthetic_database(int(bad.sum()), A, seed + 100 + it)
-        assert not bad.any()
+    if gap is not None:
+        x = gap_records(x, w, c, t, eta, gap, seed)
     s_ = I.ternary_secret(N, 192, seed + 2)
     ext = P.ext_mods(P.L)
     ki = lambda sd: (I.uniform_residues(ext, N, sd, lead=(P.beta,)), I.gaussian_error((P.beta, N), sd + 1))
