@@ -182,6 +182,47 @@ def main():
         X.pfx_rescale(ctx, prod, prod, st)
     per_op["rescale_us"] = op_time(resc) - per_op["mul_relin_us"]
 
+    # ---- private query: 2^17 records x 8 attributes, degree-7 score polynomial,
+    # (7,7,7) composite sign, InnerSum count; keys as above (resident)
+    from paper_2412_13269_amd.query import QueryPlan
+    n_blocks, A, D = 4, 8, 7
+    plan = QueryPlan(n_blocks, A, D, 3, LOGN - 1)
+    x = I.synthetic_database(n_blocks * (N // 2), A, 301)
+    w, c, t, eta = I.query_parameters(A, D, 302)
+    regs = [X.pfx_ct_create(ctx, L, 1) for _ in range(plan.n_regs)]
+    for i, v in enumerate(list(w) + list(c) + [t, eta]):
+        pt = X.pfx_encode(ctx, np.full(N // 2, v), None, L, SCALE)
+        X.pfx_encrypt(ctx, sk, pt, I.uniform_residues(q, N, 400 + 2 * i), I.gaussian_error(N, 401 + 2 * i),
+                      regs[i], st)
+        X.pfx_ct_destroy(pt)
+    db = [X.pfx_encode(ctx, x[b * (N // 2):(b + 1) * (N // 2), a], None, L, SCALE)
+          for b in range(n_blocks) for a in range(A)]
+
+    def query(graph):
+        X.pfx_run_circuit(ctx, plan.ops, regs, plan.n_inputs, db, rlk, gks, graph, st)
+
+    query(True)                              # capture
+    query(False)
+    X.pfx_sync(ctx, st)
+    reps = max(3, args.steps // 4)
+    res = {}
+    for mode in (True, False):
+        a0 = time.perf_counter()
+        for _ in range(reps):
+            query(mode)
+        X.pfx_sync(ctx, st)
+        res[mode] = (time.perf_counter() - a0) / reps
+    records = n_blocks * (N // 2)
+    query_out = {"records": records, "attributes": A, "degree": D, "sign_stages": 3,
+                 "key_switches": plan.key_switches, "reps": reps,
+                 "ms_per_query_graph": 1e3 * res[True], "ms_per_query_eager": 1e3 * res[False],
+                 "us_per_record": 1e6 * res[True] / records,
+                 "paper_context_us_per_record_1thread_cpu": 1941.0}
+    log(f"query: {1e3 * res[True]:.2f} ms (graph), {1e3 * res[False]:.2f} ms (eager), "
+        f"{1e6 * res[True] / records:.3f} us/record, {plan.key_switches} key switches")
+    for h in regs + db:
+        X.pfx_ct_destroy(h)
+
     out = {
         "metric": "key-switch (HMult+relin/rotate) ops/s at N=2^16,L=24",
         "value": ks_per_step * args.steps / elapsed,
@@ -204,6 +245,7 @@ def main():
                      "avg_launch_us": 1e3 * d["ms"] / d["launches"],
                      "algorithmic_bytes_per_launch": d["bytes"] / d["launches"]},
         "per_op_us": per_op,
+        "query": query_out,
         "profiled_ms_per_step": 1e3 * p_elapsed / args.steps,
         "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(1, v["launches"]),
                         "GBps": v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9} for k, v in kern.items()},
