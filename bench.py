@@ -77,6 +77,63 @@ def cpu_baseline(q, p):
             "seconds": dt}
 
 
+def batched_form(X, I, ctx16, rlk16, st, args):
+    """256 HMult + relin + rescale of uneven shape: per-ciphertext launches vs
+    concurrent lanes vs one HIP graph.  Inputs are random residues (valid
+    ciphertexts of random messages) cut from one ciphertext per ring degree."""
+    rng = np.random.default_rng(401)
+    ctxs, rlks, base, sks = {16: ctx16}, {16: rlk16}, {}, []
+    for ln in (14, 15):
+        ctxs[ln] = X.pfx_ctx_create(X.make_params(ln, Q_BITS, P_BITS, ALPHA, MOD_LOG2), 0)
+        n = 1 << ln
+        q, p, _ = X.pfx_ctx_moduli(ctxs[ln], len(Q_BITS), len(P_BITS))
+        sk = X.pfx_sk_create(ctxs[ln], I.ternary_secret(n, H, 2100 + ln))
+        sks.append(sk)
+        rlks[ln] = X.pfx_swk_create(ctxs[ln], sk, 0, *key_inputs([int(v) for v in q] + [int(v) for v in p], n,
+                                                                    -(-len(Q_BITS) // ALPHA), 2200 + ln))
+    L = len(Q_BITS)
+    for ln, c in ctxs.items():
+        q, _, _ = X.pfx_ctx_moduli(c, L, len(P_BITS))
+        for k in range(2):
+            h = X.pfx_ct_create(c, L, 1)
+            X.pfx_ct_import(c, I.uniform_residues(q, 1 << ln, 2300 + 10 * ln + k, lead=(2,)), SCALE, h)
+            base[(ln, k)] = h
+    shapes = [(int(rng.choice([14, 15, 16])), int(rng.integers(3, 25))) for _ in range(256)]
+    cut = {}
+    for ln, lv in set(shapes):
+        for k in range(2):
+            h = X.pfx_ct_create(ctxs[ln], lv, 1)
+            X.pfx_drop_level(ctxs[ln], base[(ln, k)], lv, h, st)
+            cut[(ln, lv, k)] = h
+    outs = [X.pfx_ct_create(ctxs[ln], lv, 1) for ln, lv in shapes]
+    bargs = ([ctxs[ln] for ln, _ in shapes], [cut[(ln, lv, 0)] for ln, lv in shapes],
+             [cut[(ln, lv, 1)] for ln, lv in shapes], [rlks[ln] for ln, _ in shapes], outs)
+    res = {}
+    reps = max(2, args.steps // 10)
+    for mode in (0, 1, 2):
+        X.pfx_batch_mul_relin_rescale(*bargs, mode, st)      # warm (and capture for mode 2)
+        X.pfx_sync(ctx16, st)
+        a0 = time.perf_counter()
+        for _ in range(reps):
+            X.pfx_batch_mul_relin_rescale(*bargs, mode, st)
+        X.pfx_sync(ctx16, st)
+        res[mode] = (time.perf_counter() - a0) / reps
+    log(f"batched 256: per-ct {1e3 * res[0]:.2f} ms, lanes {1e3 * res[1]:.2f} ms, graph {1e3 * res[2]:.2f} ms")
+    for h in outs + list(cut.values()) + list(base.values()):
+        X.pfx_ct_destroy(h)
+    for ln in (14, 15):
+        X.pfx_swk_destroy(rlks[ln])
+    for sk in sks:
+        X.pfx_sk_destroy(sk)
+    for ln in (14, 15):
+        X.pfx_ctx_destroy(ctxs[ln])
+    return {"ciphertexts": 256, "op": "HMult+relin+rescale", "ring_degrees": [2 ** 14, 2 ** 15, 2 ** 16],
+            "levels": [3, 24], "reps": reps,
+            "ms_per_ct_launch_path": 1e3 * res[0], "ms_lanes": 1e3 * res[1], "ms_graph": 1e3 * res[2],
+            "us_per_ct_launch_path": 1e6 * res[0] / 256, "us_per_ct_graph": 1e6 * res[2] / 256,
+            "speedup_graph_vs_launch_path": res[0] / res[2]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +280,9 @@ def main():
     for h in regs + db:
         X.pfx_ct_destroy(h)
 
+    # ---- batched form: 256 ciphertexts, ring degree in {2^14, 2^15, 2^16}, 3..24 limbs
+    batch_out = batched_form(X, I, ctx, rlk, st, args)
+
     out = {
         "metric": "key-switch (HMult+relin/rotate) ops/s at N=2^16,L=24",
         "value": ks_per_step * args.steps / elapsed,
@@ -246,6 +306,7 @@ def main():
                      "algorithmic_bytes_per_launch": d["bytes"] / d["launches"]},
         "per_op_us": per_op,
         "query": query_out,
+        "batched": batch_out,
         "profiled_ms_per_step": 1e3 * p_elapsed / args.steps,
         "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(1, v["launches"]),
                         "GBps": v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9} for k, v in kern.items()},

@@ -282,6 +282,22 @@ pfx_status pfx_run_circuit(pfx_ctx *ctx, const pfx_op *ops, size_t n_ops, pfx_ct
                            const pfx_swk *rlk, const pfx_swk *const *gks, size_t n_gks, int use_graph,
                            void *stream);
 
+/*
+ * Batched HMult + relinearisation + rescale over ciphertexts of uneven ring
+ * degree and level: out[i] = rescale(relin(a[i] * b[i])) under ctxs[i]
+ * (one context per ring degree; rlk[i] its relinearisation key).
+ *   mode 0: one ciphertext after the other on `stream` (the per-ciphertext path)
+ *   mode 1: spread over the library's lane streams, forked from and joined back
+ *           to `stream` with events, so that the launches of different
+ *           ciphertexts overlap on the device (lanes balanced by estimated work)
+ *   mode 2: mode 1 captured once into a HIP graph (non-NULL stream) and replayed
+ * Results are identical in every mode.  Outputs must not alias inputs of other
+ * batch entries.
+ */
+pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const *a,
+                                       const pfx_ct *const *b, const pfx_swk *const *rlk,
+                                       pfx_ct *const *out, size_t n, int mode, void *stream);
+
 /* ------------------------------------------------------------ plumbing */
 /* Device memory and streams for callers that hold raw words (pfx_ntt).  The
  * library links the system HIP runtime; a process should not load a second

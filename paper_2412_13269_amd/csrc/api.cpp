@@ -437,6 +437,8 @@ void pfx_ctx_destroy(pfx_ctx *c) {
     }
     for (auto e : c->prof_pool) hipEventDestroy(e);
     for (auto &kv : c->graphs) hipGraphExecDestroy(kv.second.exec);
+    for (auto st : c->lanes) hipStreamDestroy(st);
+    for (auto e : c->lane_events) hipEventDestroy(e);
     hipFree(c->d_tw);
     hipFree(c->d_rtw);
     hipFree(c->d_primes);
@@ -1233,6 +1235,133 @@ pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *
     return PFX_OK;
 }
 
+// ------------------------------------------------------------------ batched form
+static constexpr int kLanes = 8;
+
+static pfx_status ensure_lanes(pfx_ctx *c) {
+    if ((int)c->lanes.size() == kLanes) return PFX_OK;
+    HIPCHECK(hipSetDevice(c->device));
+    for (int i = (int)c->lanes.size(); i < kLanes; ++i) {
+        hipStream_t st;
+        HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        c->lanes.push_back(st);
+    }
+    for (int i = 0; i < kLanes + 1; ++i) {
+        hipEvent_t e;
+        HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->lane_events.push_back(e);
+    }
+    return PFX_OK;
+}
+
+static pfx_status batch_ops(pfx_ctx *const *ctxs, const pfx_ct *const *a, const pfx_ct *const *b,
+                            const pfx_swk *const *rlk, pfx_ct *const *out, size_t n, bool lanes, void *stream) {
+    pfx_ctx *c0 = ctxs[0];
+    if (!lanes) {
+        for (size_t i = 0; i < n; ++i) {
+            pfx_status r = pfx_mul_relin(ctxs[i], a[i], b[i], rlk[i], out[i], stream);
+            if (!r) r = pfx_rescale(ctxs[i], out[i], out[i], stream);
+            if (r) return r;
+        }
+        return PFX_OK;
+    }
+    // greedy assignment by estimated work (limbs x ring degree), largest first
+    std::vector<size_t> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = i;
+    auto work = [&](size_t i) { return (double)std::min(a[i]->n_limbs, b[i]->n_limbs) * ctxs[i]->N; };
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
+    std::vector<double> load(kLanes, 0.0);
+    std::vector<int> lane_of(n);
+    for (size_t i : order) {
+        int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lane_of[i] = best;
+        load[best] += work(i);
+    }
+    HIPCHECK(hipEventRecord(c0->lane_events[kLanes], S(stream)));
+    for (int l = 0; l < kLanes; ++l) HIPCHECK(hipStreamWaitEvent(c0->lanes[l], c0->lane_events[kLanes], 0));
+    for (size_t i : order) {
+        hipStream_t st = c0->lanes[lane_of[i]];
+        pfx_status r = pfx_mul_relin(ctxs[i], a[i], b[i], rlk[i], out[i], st);
+        if (!r) r = pfx_rescale(ctxs[i], out[i], out[i], st);
+        if (r) return r;
+    }
+    for (int l = 0; l < kLanes; ++l) {
+        HIPCHECK(hipEventRecord(c0->lane_events[l], c0->lanes[l]));
+        HIPCHECK(hipStreamWaitEvent(S(stream), c0->lane_events[l], 0));
+    }
+    return PFX_OK;
+}
+
+pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const *a, const pfx_ct *const *b,
+                                       const pfx_swk *const *rlk, pfx_ct *const *out, size_t n, int mode,
+                                       void *stream) {
+    REQUIRE(ctxs && a && b && rlk && out, PFX_EINVAL, "null argument");
+    REQUIRE(mode >= 0 && mode <= 2, PFX_EINVAL, "mode must be 0, 1 or 2");
+    if (n == 0) return PFX_OK;
+    for (size_t i = 0; i < n; ++i) {
+        pfx_ctx *c = ctxs[i];
+        REQUIRE(c && a[i] && b[i] && rlk[i] && out[i], PFX_EINVAL, "null batch entry");
+        REQUIRE(a[i]->ctx == c && b[i]->ctx == c && rlk[i]->ctx == c && out[i]->ctx == c, PFX_EINVAL,
+                "batch entry mixes contexts");
+        REQUIRE(c->device == ctxs[0]->device, PFX_EINVAL, "batch spans devices");
+        REQUIRE(std::min(a[i]->n_limbs, b[i]->n_limbs) >= 2, PFX_ELEVEL, "batch entry below 2 limbs");
+    }
+    if (mode == 0) return batch_ops(ctxs, a, b, rlk, out, n, false, stream);
+    pfx_ctx *c0 = ctxs[0];
+    pfx_status r = ensure_lanes(c0);
+    if (r) return r;
+    for (size_t i = 0; i < n; ++i)        // scratch for every (context, lane) before any capture
+        for (int l = 0; l < kLanes; ++l) {
+            Ws w;
+            r = get_ws(ctxs[i], c0->lanes[l], w);
+            if (r) return r;
+        }
+    if (mode == 1) return batch_ops(ctxs, a, b, rlk, out, n, true, stream);
+    REQUIRE(stream != nullptr, PFX_EINVAL, "graph capture needs a non-default stream");
+    std::string key = "batch";
+    auto put = [&](const void *p, size_t k) { key.append((const char *)p, k); };
+    for (size_t i = 0; i < n; ++i) {
+        put(&ctxs[i], sizeof(void *));
+        put(&a[i]->d, sizeof(void *));
+        put(&b[i]->d, sizeof(void *));
+        put(&out[i]->d, sizeof(void *));
+        put(&rlk[i]->d_k, sizeof(void *));
+        put(&a[i]->n_limbs, sizeof(uint32_t));
+        put(&b[i]->n_limbs, sizeof(uint32_t));
+        put(&a[i]->scale, sizeof(double));
+        put(&b[i]->scale, sizeof(double));
+    }
+    put(&stream, sizeof(void *));
+    auto it = c0->graphs.find(key);
+    if (it == c0->graphs.end()) {
+        for (size_t i = 0; i < n; ++i) ctxs[i]->capturing = true;
+        HIPCHECK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal));
+        r = batch_ops(ctxs, a, b, rlk, out, n, true, stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(S(stream), &g);
+        for (size_t i = 0; i < n; ++i) ctxs[i]->capturing = false;
+        if (r) {
+            if (g) hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("batch capture: ") + hipGetErrorString(e));
+        pfx_ctx::GraphEntry ent;
+        e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        for (size_t i = 0; i < n; ++i) ent.meta.push_back({out[i]->n_limbs | (out[i]->degree << 16), out[i]->scale});
+        it = c0->graphs.emplace(key, ent).first;
+    } else {
+        for (size_t i = 0; i < n; ++i) {
+            out[i]->n_limbs = it->second.meta[i].first & 0xffff;
+            out[i]->degree = it->second.meta[i].first >> 16;
+            out[i]->scale = it->second.meta[i].second;
+        }
+    }
+    HIPCHECK(hipGraphLaunch(it->second.exec, S(stream)));
+    return PFX_OK;
+}
+
 // ------------------------------------------------------------------ plumbing
 pfx_status pfx_dev_alloc(pfx_ctx *c, size_t bytes, void **out) {
     REQUIRE(c && out, PFX_EINVAL, "null argument");
@@ -1357,13 +1486,13 @@ static hipEvent_t pool_event(pfx_ctx *c) {
 
 void prof_begin(const Launch &L, const char *, hipEvent_t *ev) {
     *ev = nullptr;
-    if (!L.ctx->prof_on) return;
+    if (!L.ctx->prof_on || L.ctx->capturing) return;
     *ev = pool_event(L.ctx);
     hipEventRecord(*ev, L.st);
 }
 
 void prof_end(const Launch &L, const char *name, hipEvent_t ev, double bytes) {
-    if (!L.ctx->prof_on || !ev) return;
+    if (!L.ctx->prof_on || L.ctx->capturing || !ev) return;
     hipEvent_t stop = pool_event(L.ctx);
     hipEventRecord(stop, L.st);
     std::lock_guard<std::mutex> g(L.ctx->mu);

@@ -113,6 +113,8 @@ struct pfx_ctx {
         std::vector<std::pair<uint32_t, double>> meta;   // (n_limbs | degree << 16, scale) per register
     };
     std::map<std::string, GraphEntry> graphs;
+    std::vector<hipStream_t> lanes;       // batch lanes (default priority)
+    std::vector<hipEvent_t> lane_events;
     bool capturing = false;
 
     bool prof_on = false;

@@ -111,6 +111,7 @@ _SIGS = {
     "pfx_mul_const": (_i32, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "pfx_run_circuit": (_i32, [_vp, ctypes.POINTER(pfx_op), _sz, _VPP, _sz, _sz, _VPP, _sz, _vp, _VPP, _sz,
                                ctypes.c_int, _vp]),
+    "pfx_batch_mul_relin_rescale": (_i32, [_VPP, _VPP, _VPP, _VPP, _VPP, _sz, ctypes.c_int, _vp]),
     "pfx_dev_alloc": (_i32, [_vp, _sz, _VPP]),
     "pfx_dev_free": (_i32, [_vp, _vp]),
     "pfx_memcpy_htod": (_i32, [_vp, _vp, _vp, _sz, _vp]),
@@ -419,6 +420,13 @@ def pfx_run_circuit(ctx, ops, regs, n_inputs: int, pts, rlk, gks, use_graph: boo
     G = (ctypes.c_void_p * max(1, len(gks)))(*gks)
     _check(_lib.pfx_run_circuit(ctx, arr, len(ops), R, len(regs), n_inputs, Pt, len(pts), rlk, G, len(gks),
                                 int(use_graph), _stream(stream)))
+
+
+def pfx_batch_mul_relin_rescale(ctxs, a, b, rlks, outs, mode: int, stream=None):
+    n = len(a)
+    arr = lambda xs: (ctypes.c_void_p * max(1, n))(*xs)
+    _check(_lib.pfx_batch_mul_relin_rescale(arr(ctxs), arr(a), arr(b), arr(rlks), arr(outs), n, mode,
+                                            _stream(stream)))
 
 
 # ---------------------------------------------------------------- plumbing

@@ -1,0 +1,82 @@
+"""Batched HMult + relin + rescale over ciphertexts of uneven ring degree and
+level: every mode (per-ciphertext launches, concurrent lanes, HIP-graph
+replay) gives the same words, and sampled entries match the oracle."""
+import numpy as np
+import pytest
+
+from oracle import ckks as O
+from paper_2412_13269_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+QB, PB, ALPHA, ML = [50] + [45] * 23, [50] * 4, 4, 17
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_2412_13269_amd import pfx
+    return pfx
+
+
+def test_batch_modes_agree_and_match_oracle(X):
+    lognums = (12, 13, 14)
+    rng = np.random.default_rng(401)
+    ctxs, P, sks, rlks, keyin, secrets = {}, {}, {}, {}, {}, {}
+    for ln in lognums:
+        prm = X.make_params(ln, QB, PB, ALPHA, ML)
+        ctxs[ln] = X.pfx_ctx_create(prm, 0)
+        P[ln] = O.Params(ln, QB, PB, alpha=ALPHA, mod_log2=ML)
+        N = 1 << ln
+        secrets[ln] = I.ternary_secret(N, 192, ln)
+        sks[ln] = X.pfx_sk_create(ctxs[ln], secrets[ln])
+        ext = P[ln].ext_mods(P[ln].L)
+        keyin[ln] = (I.uniform_residues(ext, N, 50 + ln, lead=(P[ln].beta,)),
+                     I.gaussian_error((P[ln].beta, N), 60 + ln))
+        rlks[ln] = X.pfx_swk_create(ctxs[ln], sks[ln], 0, *keyin[ln])
+    stream = X.pfx_stream_create(ctxs[12])
+    entries = []
+    handles = []
+    for i in range(24):
+        ln = int(rng.choice(lognums))
+        lv = int(rng.integers(3, 25))
+        N = 1 << ln
+        words = [I.uniform_residues(P[ln].mods(lv), N, 1000 + 10 * i + k, lead=(2,)) for k in range(2)]
+        cts = []
+        for w in words:
+            h = X.pfx_ct_create(ctxs[ln], lv, 1)
+            X.pfx_ct_import(ctxs[ln], w, 2.0 ** 45, h)
+            cts.append(h)
+        out = X.pfx_ct_create(ctxs[ln], lv, 1)
+        handles += cts + [out]
+        entries.append((ln, lv, words, cts, out))
+    args = ([ctxs[e[0]] for e in entries], [e[3][0] for e in entries], [e[3][1] for e in entries],
+            [rlks[e[0]] for e in entries], [e[4] for e in entries])
+    try:
+        X.pfx_batch_mul_relin_rescale(*args, 0, stream)
+        X.pfx_sync(ctxs[12], stream)
+        ref = [X.pfx_ct_export(ctxs[e[0]], e[4], 1 << e[0]) for e in entries]
+        for mode in (1, 2, 2, 1, 2):
+            for e in entries:        # clobber outputs between runs
+                X.pfx_ct_import(ctxs[e[0]], np.zeros((2, e[1] - 1, 1 << e[0]), np.uint64), 1.0, e[4])
+            X.pfx_batch_mul_relin_rescale(*args, mode, stream)
+            X.pfx_sync(ctxs[12], stream)
+            for e, r in zip(entries, ref):
+                assert np.array_equal(X.pfx_ct_export(ctxs[e[0]], e[4], 1 << e[0]), r), mode
+        # oracle parity on one entry of each ring degree
+        for ln in lognums:
+            e = next(x for x in entries if x[0] == ln)
+            Pl = P[ln]
+            rlk_o = O.relin_key(Pl, secrets[ln], *keyin[ln])
+            a, b = (O.Ct(w, 2.0 ** 45) for w in e[2])
+            want = O.rescale(Pl, O.mul_relin(Pl, a, b, rlk_o))
+            got = ref[entries.index(e)]
+            assert np.array_equal(got, want.c), ln
+    finally:
+        for h in handles:
+            X.pfx_ct_destroy(h)
+        for ln in lognums:
+            X.pfx_swk_destroy(rlks[ln])
+            X.pfx_sk_destroy(sks[ln])
+        X.pfx_stream_destroy(ctxs[12], stream)
+        for ln in lognums:
+            X.pfx_ctx_destroy(ctxs[ln])
