@@ -134,6 +134,116 @@ def batched_form(X, I, ctx16, rlk16, st, args):
             "speedup_graph_vs_launch_path": res[0] / res[2]}
 
 
+def served_form(X, I, ctx, sk, q, rlk, gks, st, args):
+    """A Poisson stream of private queries through the library's request
+    server.  Database size 2^k records, k uniform over 14..19 (a half block of
+    2^14 sparse slots up to 16 blocks of 2^15), score degree uniform over
+    3..15, (7,7,7) composite sign and InnerSum count per query.  The database
+    (16 blocks + the half block) and the encrypted query parameters stay
+    resident; arrivals at 0.8 x the capacity measured closed-loop first."""
+    from paper_2412_13269_amd.query import QueryPlan
+    N, L, A, MAXD = 1 << LOGN, len(Q_BITS), 8, 15
+    n = N // 2
+    w, c, t, eta = I.query_parameters(A, MAXD, 502)
+    inputs = []
+    for i, v in enumerate(list(w) + list(c) + [t, eta]):
+        pt = X.pfx_encode(ctx, np.full(n, v), None, L, SCALE)
+        h = X.pfx_ct_create(ctx, L, 1)
+        X.pfx_encrypt(ctx, sk, pt, I.uniform_residues(q, N, 600 + 2 * i), I.gaussian_error(N, 601 + 2 * i), h, st)
+        X.pfx_ct_destroy(pt)
+        inputs.append(h)
+    x = I.synthetic_database(16 * n, A, 503)
+    xh = I.synthetic_database(n // 2, A, 504)
+    db = [X.pfx_encode(ctx, x[b * n:(b + 1) * n, a], None, L, SCALE) for b in range(16) for a in range(A)]
+    dbh = [X.pfx_encode(ctx, xh[:, a], None, L, SCALE) for a in range(A)]
+    plans = {}
+
+    def request(k, D):
+        blocks = 1 << (k - 15) if k >= 15 else 0
+        if (k, D) not in plans:
+            plans[(k, D)] = QueryPlan(max(1, blocks), A, D, 3, LOGN - 1 if blocks else LOGN - 2)
+        plan = plans[(k, D)]
+        ins = inputs[:A] + inputs[A:A + D + 1] + inputs[A + MAXD + 1:]
+        return plan, ins, (db[:blocks * A] if blocks else dbh)
+
+    slots = 4
+    scratch_probe = X.pfx_server_create(ctx, 1 << 31, 1, rlk, gks)
+    scratch = X.pfx_server_stats_get(scratch_probe)["scratch_bytes"]
+    X.pfx_server_destroy(scratch_probe)
+    budget = slots * scratch + (2 << 30)
+    srv = X.pfx_server_create(ctx, budget, slots, rlk, gks)
+    free_outs = [X.pfx_ct_create(ctx, 8, 1) for _ in range(64)]
+    all_outs = list(free_outs)
+    pending = {}
+
+    def reap(block=False):
+        for tk in list(pending):
+            info = X.pfx_server_poll(srv, tk, wait=block)
+            if info is None:
+                continue
+            assert info.status == 0, info.error.decode()
+            out, rec = pending.pop(tk)
+            free_outs.append(out)
+            done.append((info.latency_s, info.queued_s, rec))
+
+    def submit(k, D):
+        plan, ins, pts = request(k, D)
+        while not free_outs:
+            reap()
+        out = free_outs.pop()
+        tk = X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out)
+        pending[tk] = (out, 1 << k)
+
+    rng = np.random.default_rng(501)
+    # capacity: 24 queries of the same mix submitted at once
+    done = []
+    cap_mix = [(int(rng.integers(14, 20)), int(rng.integers(3, 16))) for _ in range(24)]
+    submit(14, 3)                                  # warm the slots
+    reap(True)
+    done = []
+    a0 = time.perf_counter()
+    for k, D in cap_mix:
+        submit(k, D)
+    reap(True)
+    cap_s = time.perf_counter() - a0
+    capacity = len(cap_mix) / cap_s
+    lam = 0.8 * capacity
+    n_q = 200
+    mix = [(int(rng.integers(14, 20)), int(rng.integers(3, 16))) for _ in range(n_q)]
+    gaps = rng.exponential(1.0 / lam, size=n_q)
+    log(f"served: capacity {capacity:.2f} queries/s, arrivals at {lam:.2f}/s, {n_q} queries ...")
+    done = []
+    t_start = time.perf_counter()
+    t_next = t_start
+    for (k, D), g in zip(mix, gaps):
+        t_next += g
+        while True:
+            now = time.perf_counter()
+            if now >= t_next:
+                break
+            reap()
+            time.sleep(min(0.002, max(0.0, t_next - time.perf_counter())))
+        submit(k, D)
+    reap(True)
+    wall = time.perf_counter() - t_start
+    stats = X.pfx_server_stats_get(srv)
+    X.pfx_server_destroy(srv)
+    lat = np.array([d[0] for d in done])
+    qd = np.array([d[1] for d in done])
+    records = sum(d[2] for d in done)
+    for h in all_outs + inputs + db + dbh:
+        X.pfx_ct_destroy(h)
+    out = {"queries": n_q, "arrival": "Poisson", "rate_per_s": lam, "capacity_queries_per_s": capacity,
+           "records_per_query": "2^k, k uniform in 14..19", "degree": "uniform in 3..15", "sign_stages": 3,
+           "slots": slots, "hbm_budget_bytes": budget, "arena_bytes": stats["arena_bytes"],
+           "peak_bytes": stats["peak_bytes"], "peak_running": stats["peak_running"],
+           "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+           "mean_queue_ms": 1e3 * float(qd.mean()), "records_per_s": records / wall, "wall_s": wall}
+    log(f"served: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, {out['records_per_s']:.3g} records/s, "
+        f"peak {stats['peak_running']} running")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +393,9 @@ def main():
     # ---- batched form: 256 ciphertexts, ring degree in {2^14, 2^15, 2^16}, 3..24 limbs
     batch_out = batched_form(X, I, ctx, rlk, st, args)
 
+    # ---- served form: Poisson stream of queries through the request server
+    served_out = served_form(X, I, ctx, sk, q, rlk, gks, st, args)
+
     out = {
         "metric": "key-switch (HMult+relin/rotate) ops/s at N=2^16,L=24",
         "value": ks_per_step * args.steps / elapsed,
@@ -307,6 +420,7 @@ def main():
         "per_op_us": per_op,
         "query": query_out,
         "batched": batch_out,
+        "served": served_out,
         "profiled_ms_per_step": 1e3 * p_elapsed / args.steps,
         "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(1, v["launches"]),
                         "GBps": v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9} for k, v in kern.items()},

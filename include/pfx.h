@@ -298,6 +298,80 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
                                        const pfx_ct *const *b, const pfx_swk *const *rlk,
                                        pfx_ct *const *out, size_t n, int mode, void *stream);
 
+/* ------------------------------------------------------------ served form */
+/*
+ * A query server over one context: the database owner's side of the private
+ * query (Sec. 5 and Alg. 2 of the paper) run as a service.  Requests are op
+ * lists (the pfx_op codes above) that arrive at any time; the server admits
+ * them first-come first-served whenever one of its `slots` streams is free and
+ * the request's footprint fits in what is left of the HBM budget, and runs
+ * every admitted request on its own stream, so that requests overlap on the
+ * device (continuous batching at request granularity: a finishing request
+ * frees its slot and memory, which admits the next one at once).
+ *
+ * Memory.  At creation the server takes `hbm_budget` bytes: each slot's
+ * key-switching scratch (fixed), and the rest as one arena from which each
+ * admitted request's work registers are carved.  A request's footprint is
+ * (n_regs - n_inputs) ciphertexts of degree 1 at the largest level among its
+ * inputs: 2 * max(inputs' n_limbs) * N * 8 bytes each.  The evaluation keys
+ * (rlk, gks: resident, shared by every request), the input ciphertexts and the
+ * plaintexts are the caller's and are not counted.
+ *
+ * Ownership.  rlk and gks must outlive the server.  A request's inputs, pts
+ * and out are borrowed until pfx_server_poll reports the ticket finished; the
+ * server copies the request's op list and pointer arrays at submit.  Inputs
+ * are registers 0..n_inputs-1 and are only read; out receives a copy of
+ * register out_reg (its capacity must hold that register's limbs).
+ *
+ * Results are identical to pfx_run_circuit of the same op list on the same
+ * inputs, whatever else runs beside them.  A server launches from a thread of
+ * its own; calls on the same context from other threads may run meanwhile.
+ */
+typedef struct pfx_server pfx_server;
+
+typedef struct pfx_request {
+    const pfx_op *ops;
+    size_t n_ops;
+    size_t n_regs;                 /* registers of the op list */
+    size_t n_inputs;               /* registers 0..n_inputs-1 are inputs[...] */
+    const pfx_ct *const *inputs;
+    const pfx_pt *const *pts;      /* plaintext operands, by op field b */
+    size_t n_pts;
+    int32_t out_reg;               /* in [n_inputs, n_regs) */
+    pfx_ct *out;
+} pfx_request;
+
+typedef struct pfx_request_info {
+    pfx_status status;             /* of the evaluation (PFX_OK, or the failing op's error) */
+    int32_t slot;                  /* stream slot it ran on */
+    size_t footprint;              /* arena bytes it held while running */
+    double queued_s;               /* submit -> admission, seconds */
+    double latency_s;              /* submit -> the end of its last launch, seconds */
+    char error[160];               /* message of a failed evaluation */
+} pfx_request_info;
+
+typedef struct pfx_server_stats {
+    uint64_t submitted, completed, queued, running;
+    size_t budget, scratch_bytes, arena_bytes, bytes_in_use, peak_bytes;
+    uint32_t slots, peak_running;
+} pfx_server_stats;
+
+/* PFX_ENOMEM if the budget does not cover the slots' scratch; slots in [1, 16]. */
+pfx_status pfx_server_create(pfx_ctx *ctx, size_t hbm_budget, uint32_t slots, const pfx_swk *rlk,
+                             const pfx_swk *const *gks, size_t n_gks, pfx_server **out);
+/* Queues a request and returns its ticket.  PFX_EINVAL for a malformed request
+ * (registers out of range, an input of another context), PFX_ENOMEM if its
+ * footprint exceeds the whole arena (it could never be admitted). */
+pfx_status pfx_server_submit(pfx_server *s, const pfx_request *rq, uint64_t *ticket);
+/* PFX_OK once the ticket has finished (info filled, the ticket released),
+ * PFX_EBUSY while it is queued or running and wait == 0 (wait != 0 blocks until
+ * it finishes), PFX_EINVAL for an unknown or already released ticket. */
+pfx_status pfx_server_poll(pfx_server *s, uint64_t ticket, int wait, pfx_request_info *info);
+pfx_status pfx_server_stats_get(pfx_server *s, pfx_server_stats *st);
+/* Waits for the running requests, drops the queued ones, frees the arena and
+ * the slots. */
+void pfx_server_destroy(pfx_server *s);
+
 /* ------------------------------------------------------------ plumbing */
 /* Device memory and streams for callers that hold raw words (pfx_ntt).  The
  * library links the system HIP runtime; a process should not load a second

@@ -6,8 +6,9 @@ score of the query in place of the paper's coefficient-encoded PFE phase:
 
   per record block b (2^(logN-1) records in the slots):
     S   = rescale( sum_a W[a] * X[b][a] )                    linear score
-    Y_k = powers of S up to degree D by the binary tree
-          Y2 = Y1 Y1, Y3 = Y2 Y1, Y4 = Y2 Y2, Y5 = Y4 Y1, Y6 = Y4 Y2, Y7 = Y4 Y3
+    Y_k = powers of S up to degree D <= 15 by the binary tree
+          Y2 = Y1 Y1, Y3 = Y2 Y1, Y4 = Y2 Y2, Y5 = Y4 Y1, Y6 = Y4 Y2, Y7 = Y4 Y3,
+          Y8 = Y4 Y4, Y(8+i) = Y8 Yi
     Z   = sum_{k=1..D} rescale(relin(C[k] Y_k)) + C[0]       polynomial p(S)
     U   = rescale(relin((Z - T) H))                          normalised threshold input
     3 times (composite sign, degree-7 stage f7(x) = (35x - 35x^3 + 21x^5 - 5x^7)/16):
@@ -56,21 +57,29 @@ def _mr(P, a, b, rlk):
     return O.rescale(P, O.mul_relin(P, a, b, rlk))
 
 
+def _factors(k):
+    """The two lower powers whose product gives y^k in the power tree."""
+    if k == 2:
+        return 1, 1
+    if k == 3:
+        return 2, 1
+    if k == 4:
+        return 2, 2
+    if k <= 7:
+        return 4, k - 4
+    if k == 8:
+        return 4, 4
+    return 8, k - 8
+
+
 def _powers(P, y1, D, rlk):
+    """y^k for k <= D <= 15: y^2 = y y, y^3 = y^2 y, y^4 = y^2 y^2, y^5 = y^4 y,
+    y^6 = y^4 y^2, y^7 = y^4 y^3, y^8 = y^4 y^4, and y^(8+i) = y^8 y^i."""
+    assert 1 <= D <= 15
     Y = {1: y1}
-    if D >= 2:
-        Y[2] = _mr(P, Y[1], Y[1], rlk)
-    if D >= 3:
-        Y[3] = _mr(P, Y[2], Y[1], rlk)
-    if D >= 4:
-        Y[4] = _mr(P, Y[2], Y[2], rlk)
-    if D >= 5:
-        Y[5] = _mr(P, Y[4], Y[1], rlk)
-    if D >= 6:
-        Y[6] = _mr(P, Y[4], Y[2], rlk)
-    if D >= 7:
-        Y[7] = _mr(P, Y[4], Y[3], rlk)
-    assert D <= 7
+    for k in range(2, D + 1):
+        a, b = _factors(k)
+        Y[k] = _mr(P, Y[a], Y[b], rlk)
     return Y
 
 

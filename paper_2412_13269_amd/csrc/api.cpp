@@ -196,6 +196,55 @@ uint32_t rot_element(const pfx_ctx *c, int64_t step) {
 
 }  // namespace
 
+namespace pfx {
+
+size_t ws_bytes(const pfx_ctx *c) { return ws_layout(c).total * sizeof(double); }
+
+pfx_status ws_reserve(pfx_ctx *c, hipStream_t st) {
+    Ws w;
+    return get_ws(c, st, w);
+}
+
+pfx_status run_ops(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
+                   size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
+                   const pfx_swk *const *gks, size_t n_gks, void *stream) {
+    auto R = [&](int32_t k) -> pfx_ct * { return (k >= 0 && (size_t)k < n_regs) ? regs[k] : nullptr; };
+    for (size_t i = 0; i < n_ops; ++i) {
+        const pfx_op &o = ops[i];
+        pfx_ct *d = R(o.dst), *A = R(o.a);
+        const std::string at = "op " + std::to_string(i) + ": ";
+        if (!d || !A) return fail(PFX_EINVAL, at + "register index out of range");
+        if ((size_t)o.dst < n_inputs) return fail(PFX_EINVAL, at + "writes an input register");
+        const pfx_pt *pt = (o.b >= 0 && (size_t)o.b < n_pts) ? pts[o.b] : nullptr;
+        pfx_status r;
+        switch (o.code) {
+            case PFX_OP_COPY: r = pfx_ct_copy(c, A, d, stream); break;
+            case PFX_OP_ADD: r = pfx_add(c, A, R(o.b), d, stream); break;
+            case PFX_OP_SUB: r = pfx_sub(c, A, R(o.b), d, stream); break;
+            case PFX_OP_MUL_PLAIN: r = pfx_mul_plain(c, A, pt, d, stream); break;
+            case PFX_OP_ADD_PLAIN: r = pfx_add_plain(c, A, pt, d, stream); break;
+            case PFX_OP_MUL_INT: r = pfx_mul_int(c, A, o.k, d, stream); break;
+            case PFX_OP_MUL_RELIN: r = pfx_mul_relin(c, A, R(o.b), rlk, d, stream); break;
+            case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
+            case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
+            case PFX_OP_MUL_CONST: r = pfx_mul_const(c, A, o.value, 0.0, d, stream); break;
+            case PFX_OP_SCALE_MUL: {
+                const double sc = A->scale * o.value;
+                r = pfx_ct_copy(c, A, d, stream);
+                if (!r) d->scale = sc;
+                break;
+            }
+            case PFX_OP_ROTATE: r = pfx_rotate(c, A, (int32_t)o.k, gks, n_gks, d, stream); break;
+            case PFX_OP_ROTATE_SUM: r = pfx_rotate_sum(c, A, (uint32_t)o.k, gks, n_gks, d, stream); break;
+            default: return fail(PFX_EINVAL, at + "unknown op code");
+        }
+        if (r) return fail(r, at + g_err);
+    }
+    return PFX_OK;
+}
+
+}  // namespace pfx
+
 // ======================================================================= API
 extern "C" {
 
@@ -585,7 +634,7 @@ pfx_status pfx_ct_create(pfx_ctx *c, uint32_t cap_limbs, uint32_t cap_degree, pf
 
 void pfx_ct_destroy(pfx_ct *x) {
     if (!x) return;
-    hipFree(x->d);
+    if (x->owns) hipFree(x->d);
     delete x;
 }
 
@@ -1134,45 +1183,6 @@ pfx_status pfx_ntt(pfx_ctx *c, uint64_t *d_words, uint32_t first_prime, uint32_t
             launch_ntt(L, buf, nullptr, m, inverse != 0);
         }
         launch_f64_to_u64(L, d_words + l0 * N, buf, nl * N);
-    }
-    return PFX_OK;
-}
-
-// ------------------------------------------------------------------ circuits
-static pfx_status run_ops(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
-                          size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
-                          const pfx_swk *const *gks, size_t n_gks, void *stream) {
-    auto R = [&](int32_t k) -> pfx_ct * { return (k >= 0 && (size_t)k < n_regs) ? regs[k] : nullptr; };
-    for (size_t i = 0; i < n_ops; ++i) {
-        const pfx_op &o = ops[i];
-        pfx_ct *d = R(o.dst), *A = R(o.a);
-        const std::string at = "op " + std::to_string(i) + ": ";
-        if (!d || !A) return fail(PFX_EINVAL, at + "register index out of range");
-        if ((size_t)o.dst < n_inputs) return fail(PFX_EINVAL, at + "writes an input register");
-        const pfx_pt *pt = (o.b >= 0 && (size_t)o.b < n_pts) ? pts[o.b] : nullptr;
-        pfx_status r;
-        switch (o.code) {
-            case PFX_OP_COPY: r = pfx_ct_copy(c, A, d, stream); break;
-            case PFX_OP_ADD: r = pfx_add(c, A, R(o.b), d, stream); break;
-            case PFX_OP_SUB: r = pfx_sub(c, A, R(o.b), d, stream); break;
-            case PFX_OP_MUL_PLAIN: r = pfx_mul_plain(c, A, pt, d, stream); break;
-            case PFX_OP_ADD_PLAIN: r = pfx_add_plain(c, A, pt, d, stream); break;
-            case PFX_OP_MUL_INT: r = pfx_mul_int(c, A, o.k, d, stream); break;
-            case PFX_OP_MUL_RELIN: r = pfx_mul_relin(c, A, R(o.b), rlk, d, stream); break;
-            case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
-            case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
-            case PFX_OP_MUL_CONST: r = pfx_mul_const(c, A, o.value, 0.0, d, stream); break;
-            case PFX_OP_SCALE_MUL: {
-                const double sc = A->scale * o.value;
-                r = pfx_ct_copy(c, A, d, stream);
-                if (!r) d->scale = sc;
-                break;
-            }
-            case PFX_OP_ROTATE: r = pfx_rotate(c, A, (int32_t)o.k, gks, n_gks, d, stream); break;
-            case PFX_OP_ROTATE_SUM: r = pfx_rotate_sum(c, A, (uint32_t)o.k, gks, n_gks, d, stream); break;
-            default: return fail(PFX_EINVAL, at + "unknown op code");
-        }
-        if (r) return fail(r, at + g_err);
     }
     return PFX_OK;
 }

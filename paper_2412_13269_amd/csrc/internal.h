@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -115,9 +116,9 @@ struct pfx_ctx {
     std::map<std::string, GraphEntry> graphs;
     std::vector<hipStream_t> lanes;       // batch lanes (default priority)
     std::vector<hipEvent_t> lane_events;
-    bool capturing = false;
+    std::atomic<bool> capturing{false};
 
-    bool prof_on = false;
+    std::atomic<bool> prof_on{false};
     std::vector<pfx::ProfEntry> prof_pending;
     std::map<std::string, pfx::ProfTotal> prof_done;
     std::vector<hipEvent_t> prof_pool;
@@ -141,6 +142,7 @@ struct pfx_ct {
     uint32_t n_limbs = 0, degree = 0;
     double scale = 1.0;
     double *d = nullptr;  // poly k, limb i at d + (k * cap_limbs + i) * N
+    bool owns = true;     // false for views into memory the library manages elsewhere (server arena)
     double *poly(uint32_t k) const { return d + (size_t)k * cap_limbs * (size_t)ctx->N; }
 };
 
@@ -161,6 +163,15 @@ bool encode_coeffs(int logn, const double *re, const double *im, size_t n, doubl
                    const std::vector<uint64_t> &mods, std::vector<uint64_t> &words, std::string &err);
 void decode_words(int logn, const uint64_t *words, int n_limbs, const std::vector<uint64_t> &mods,
                   double scale, size_t n, double *re, double *im);
+
+// Op-list interpreter behind pfx_run_circuit (api.cpp): registers 0..n_inputs-1
+// are read-only, every op is launched on `stream`.
+pfx_status run_ops(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
+                   size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
+                   const pfx_swk *const *gks, size_t n_gks, void *stream);
+// Bytes of the per-stream scratch, and its allocation for one stream.
+size_t ws_bytes(const pfx_ctx *c);
+pfx_status ws_reserve(pfx_ctx *c, hipStream_t st);
 
 // ---------------------------------------------------------------- launchers
 struct Launch {

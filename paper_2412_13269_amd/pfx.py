@@ -52,6 +52,25 @@ class pfx_info(ctypes.Structure):
                 ("degree", ctypes.c_uint32), ("scale", ctypes.c_double)]
 
 
+class pfx_request(ctypes.Structure):
+    _fields_ = [("ops", ctypes.POINTER(pfx_op)), ("n_ops", ctypes.c_size_t), ("n_regs", ctypes.c_size_t),
+                ("n_inputs", ctypes.c_size_t), ("inputs", ctypes.POINTER(ctypes.c_void_p)),
+                ("pts", ctypes.POINTER(ctypes.c_void_p)), ("n_pts", ctypes.c_size_t),
+                ("out_reg", ctypes.c_int32), ("out", ctypes.c_void_p)]
+
+
+class pfx_request_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("footprint", ctypes.c_size_t),
+                ("queued_s", ctypes.c_double), ("latency_s", ctypes.c_double), ("error", ctypes.c_char * 160)]
+
+
+class pfx_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "queued", "running")] + \
+               [(n, ctypes.c_size_t) for n in ("budget", "scratch_bytes", "arena_bytes", "bytes_in_use",
+                                               "peak_bytes")] + \
+               [("slots", ctypes.c_uint32), ("peak_running", ctypes.c_uint32)]
+
+
 _vp = ctypes.c_void_p
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -112,6 +131,11 @@ _SIGS = {
     "pfx_run_circuit": (_i32, [_vp, ctypes.POINTER(pfx_op), _sz, _VPP, _sz, _sz, _VPP, _sz, _vp, _VPP, _sz,
                                ctypes.c_int, _vp]),
     "pfx_batch_mul_relin_rescale": (_i32, [_VPP, _VPP, _VPP, _VPP, _VPP, _sz, ctypes.c_int, _vp]),
+    "pfx_server_create": (_i32, [_vp, _sz, _u32, _vp, _VPP, _sz, _VPP]),
+    "pfx_server_submit": (_i32, [_vp, ctypes.POINTER(pfx_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "pfx_server_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(pfx_request_info)]),
+    "pfx_server_stats_get": (_i32, [_vp, ctypes.POINTER(pfx_server_stats)]),
+    "pfx_server_destroy": (None, [_vp]),
     "pfx_dev_alloc": (_i32, [_vp, _sz, _VPP]),
     "pfx_dev_free": (_i32, [_vp, _vp]),
     "pfx_memcpy_htod": (_i32, [_vp, _vp, _vp, _sz, _vp]),
@@ -427,6 +451,45 @@ def pfx_batch_mul_relin_rescale(ctxs, a, b, rlks, outs, mode: int, stream=None):
     arr = lambda xs: (ctypes.c_void_p * max(1, n))(*xs)
     _check(_lib.pfx_batch_mul_relin_rescale(arr(ctxs), arr(a), arr(b), arr(rlks), arr(outs), n, mode,
                                             _stream(stream)))
+
+
+# ---------------------------------------------------------------- served form
+def pfx_server_create(ctx, hbm_budget: int, slots: int, rlk, gks):
+    G = (ctypes.c_void_p * max(1, len(gks)))(*gks)
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_server_create(ctx, hbm_budget, slots, rlk, G, len(gks), ctypes.byref(h)))
+    return h.value
+
+
+def pfx_server_submit(srv, ops, n_regs: int, inputs, pts, out_reg: int, out) -> int:
+    """ops: a sequence of (code, dst, a, b, k, value); inputs are registers 0..len(inputs)-1."""
+    arr = (pfx_op * max(1, len(ops)))(*[pfx_op(*o) for o in ops])
+    I = (ctypes.c_void_p * max(1, len(inputs)))(*inputs)
+    Pt = (ctypes.c_void_p * max(1, len(pts)))(*pts)
+    rq = pfx_request(arr, len(ops), n_regs, len(inputs), I, Pt, len(pts), out_reg, out)
+    t = ctypes.c_uint64()
+    _check(_lib.pfx_server_submit(srv, ctypes.byref(rq), ctypes.byref(t)))
+    return t.value
+
+
+def pfx_server_poll(srv, ticket: int, wait: bool = False):
+    """The finished request's pfx_request_info, or None while it is queued or running."""
+    info = pfx_request_info()
+    st = _lib.pfx_server_poll(srv, ticket, int(wait), ctypes.byref(info))
+    if st == PFX_EBUSY:
+        return None
+    _check(st)
+    return info
+
+
+def pfx_server_stats_get(srv) -> dict:
+    st = pfx_server_stats()
+    _check(_lib.pfx_server_stats_get(srv, ctypes.byref(st)))
+    return {n: getattr(st, n) for n, _ in pfx_server_stats._fields_}
+
+
+def pfx_server_destroy(srv):
+    _lib.pfx_server_destroy(srv)
 
 
 # ---------------------------------------------------------------- plumbing

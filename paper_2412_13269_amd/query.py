@@ -5,7 +5,8 @@ slot-domain linear score): for each block b of 2^(logN-1) records
 
     S   = rescale(sum_a W[a] * X[b][a])
     Y_k = S^k by the binary power tree (Y2 = Y1 Y1, Y3 = Y2 Y1, Y4 = Y2 Y2,
-          Y5 = Y4 Y1, Y6 = Y4 Y2, Y7 = Y4 Y3; each relinearised and rescaled)
+          Y5 = Y4 Y1, Y6 = Y4 Y2, Y7 = Y4 Y3, Y8 = Y4 Y4, Y(8+i) = Y8 Yi;
+          each relinearised and rescaled), degree D <= 15
     Z   = sum_{k=1..D} rescale(relin(C[k] Y_k)) + C[0]
     U   = rescale(relin((Z - T) H))
     3 stages of f7(x) = (35x - 35x^3 + 21x^5 - 5x^7)/16:
@@ -39,7 +40,7 @@ class QueryPlan:
 
     def __post_init__(self):
         A, D = self.attributes, self.degree
-        assert 1 <= D <= 7 and A >= 1 and self.n_blocks >= 1
+        assert 1 <= D <= 15 and A >= 1 and self.n_blocks >= 1
         self.W = list(range(A))
         self.C = list(range(A, A + D + 1))
         self.T = A + D + 1
@@ -80,7 +81,8 @@ class QueryPlan:
             self._op(X.OP_ADD, s, s, t)
         self._op(X.OP_RESCALE, s, s)
         Y = {1: s}
-        tree = {2: (1, 1), 3: (2, 1), 4: (2, 2), 5: (4, 1), 6: (4, 2), 7: (4, 3)}
+        tree = {2: (1, 1), 3: (2, 1), 4: (2, 2), 5: (4, 1), 6: (4, 2), 7: (4, 3), 8: (4, 4)}
+        tree.update({8 + i: (8, i) for i in range(1, 8)})
         for k in range(2, D + 1):
             Y[k] = self._new()
             self._mr(Y[k], Y[tree[k][0]], Y[tree[k][1]])

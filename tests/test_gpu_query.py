@@ -45,15 +45,17 @@ def gap_records(x, w, c, t, eta, gap, seed):
 class Setup:
     """Library objects for one query; oracle twins built only when asked."""
 
-    def __init__(self, X, logn, n_blocks, seed, gap=None, with_oracle=False):
+    def __init__(self, X, logn, n_blocks, seed, gap=None, with_oracle=False, degree=7):
         from paper_2412_13269_amd.query import QueryPlan
         self.X = X
         self.logn, self.N, self.n = logn, 1 << logn, 1 << (logn - 1)
-        A, D = 8, 7
+        A, D = 8, degree
+        self.D = D
         self.x = I.synthetic_database(self.n * n_blocks, A, seed)
         w, c, t, eta = I.query_parameters(A, D, seed + 1)
         if gap is not None:
             c, t, eta = spread(self.x, w)
+            c = np.concatenate([c, np.zeros(max(0, D + 1 - len(c)))])[:D + 1]
             self.x = gap_records(self.x, w, c, t, eta, gap, seed)
         self.params = (w, c, t, eta)
         self.plan = QueryPlan(n_blocks, A, D, 3, logn - 1)
@@ -117,7 +119,7 @@ class Setup:
         P = self.P
         ct = lambda m, a, e: O.encrypt(P, self.s, m, a, e, DELTA)
         cts = [ct(*v) for v in self.enc_in]
-        A, D = 8, 7
+        A, D = 8, self.D
         W, C, T, H = cts[:A], cts[A:A + D + 1], cts[A + D + 1], cts[A + D + 2]
         rlk = O.relin_key(P, self.s, *self.key_in[0])
         gks = {g: O.galois_key(P, self.s, g, *v) for g, v in self.key_in.items() if g}
@@ -152,6 +154,19 @@ def test_query_words_match_oracle_eager_and_graph(X):
             assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), want.c), rep
         step, count = Q.fp64_query(S.x, *S.params)
         assert abs(S.count(out)[0] - count) < 0.25
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("degree", [3, 15])
+def test_query_degrees_match_oracle(X, degree):
+    S = Setup(X, 12, 1, 33 + degree, with_oracle=True, degree=degree)
+    try:
+        want = S.oracle_out()
+        for graph in (False, True, True):
+            out = S.run(graph=graph)
+            assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), want.c), graph
+        assert X.pfx_ct_info(out).scale == want.scale
     finally:
         S.close()
 

@@ -44,14 +44,15 @@ def gap_records(x, w, c, t, eta, gap, seed):
     return np.concatenate(keep)[:want]
 
 
-def build(logn, n_blocks, seed, gap=None):
+def build(logn, n_blocks, seed, gap=None, degree=7):
     P = O.Params(logn, [50] + [45] * 23, [50] * 4, alpha=4, mod_log2=17)
     N, n = P.N, P.N // 2
-    A, D, delta = 8, 7, 2.0 ** 45
+    A, D, delta = 8, degree, 2.0 ** 45
     x = I.synthetic_database(n * n_blocks, A, seed)
     w, c, t, eta = I.query_parameters(A, D, seed + 1)
     if gap is not None:
         c, t, eta = spread_parameters(x, w)
+        c = np.concatenate([c, np.zeros(max(0, D + 1 - len(c)))])[:D + 1]
     if gap is not None:
         x = gap_records(x, w, c, t, eta, gap, seed)
     s_ = I.ternary_secret(N, 192, seed + 2)
@@ -108,3 +109,13 @@ def test_query_exact_count_on_gap_data():
     exact = int(np.sum(step > 0.5))
     assert abs(count - exact) < 1e-3
     assert int(round(got[0])) == exact
+
+
+def test_query_circuit_degrees_3_and_15():
+    for D, depth in ((3, 17), (15, 19)):
+        P, s_, x, (w, c, t, eta), X, delta, W, C, T, H, rlk, gks = build(9, 1, 13, degree=D)
+        out = Q.query_circuit(P, X, delta, W, C, T, H, rlk, gks)
+        assert out.level == P.L - depth
+        got = O.decode(P, O.decrypt(P, s_, out), out.scale, P.N // 2).real
+        step, count = Q.fp64_query(x, w, c, t, eta)
+        assert abs(got[0] - count) < 0.25, D
