@@ -135,36 +135,35 @@ pfx_status check_out(const pfx_ct *o, uint32_t lv, uint32_t deg) {
 
 // Key switching of the lv-limb NTT-domain polynomial d (Sec. 2.4.1):
 // out_u = ModDown(sum_j ModUp_j(d) * swk_{j,u}) (+ base_u).  Six launches, see
-// keyswitch.hip.
+// keyswitch.hip.  galois != 0 switches phi_galois(d) instead of d, and adds
+// phi_galois(base0): both are read through the automorphism's permutation, so
+// out0 must not alias base0 then (other workgroups still read base0 while
+// out0 is written).
 void ks_core(pfx_ctx *c, const Launch &L, const Ws &w, const double *d, int lv, const pfx_swk *key, double *out0,
-             double *out1, const double *base0, const double *base1) {
+             double *out1, const double *base0, const double *base1, uint32_t galois = 0) {
     const int E = lv + c->K;
     double *dcoef = w.at(w.lay.dcoef), *ext = w.at(w.lay.ext), *acc = w.at(w.lay.acc), *tmp = w.at(w.lay.mdtmp);
-    launch_intt_scale(L, dcoef, d, lv);
+    launch_intt_scale(L, dcoef, d, lv, galois);
     launch_modup_col(L, ext, dcoef, lv);
-    if (c->ks_variant == 1) {
-        launch_row_inner(L, acc, ext, d, key->d_k, lv);
-    } else {
-        const int beta = (lv + c->alpha - 1) / c->alpha;
-        LimbMap m;
-        m.n = 0;
-        for (int j = 0; j < beta; ++j) {
-            const int sz = std::min(c->alpha, lv - j * c->alpha);
-            for (int t = 0; t < E - sz; ++t) {
-                m.off[m.n] = j * E + t;
-                m.pid[m.n] = (int16_t)(t < j * c->alpha ? t : (t < lv - sz ? t + sz : c->L + (t - (lv - sz))));
-                if (++m.n == kMaxMapLimbs) {
-                    launch_ntt_pass(L, ext, nullptr, m, true, false);
-                    m.n = 0;
-                }
+    const int beta = (lv + c->alpha - 1) / c->alpha;
+    LimbMap m;
+    m.n = 0;
+    for (int j = 0; j < beta; ++j) {
+        const int sz = std::min(c->alpha, lv - j * c->alpha);
+        for (int t = 0; t < E - sz; ++t) {
+            m.off[m.n] = j * E + t;
+            m.pid[m.n] = (int16_t)(t < j * c->alpha ? t : (t < lv - sz ? t + sz : c->L + (t - (lv - sz))));
+            if (++m.n == kMaxMapLimbs) {
+                launch_ntt_pass(L, ext, nullptr, m, true, false);
+                m.n = 0;
             }
         }
-        launch_ntt_pass(L, ext, nullptr, m, true, false);
-        launch_ks_inner(L, acc, ext, d, key->d_k, lv);
     }
+    launch_ntt_pass(L, ext, nullptr, m, true, false);
+    launch_ks_inner(L, acc, ext, d, key->d_k, lv, galois);
     launch_intt_special(L, acc, lv);
     launch_moddown_col(L, tmp, acc, lv);
-    launch_row_moddown(L, out0, out1, acc, tmp, base0, base1, lv);
+    launch_row_moddown(L, out0, out1, acc, tmp, base0, base1, lv, galois);
 }
 
 pfx_swk *find_key(pfx_ctx *c, uint32_t g, const pfx_swk *const *keys, size_t n) {
@@ -179,9 +178,15 @@ pfx_status galois_apply(pfx_ctx *c, const pfx_ct *a, const pfx_swk *gk, pfx_ct *
     if (r) return r;
     const int lv = a->n_limbs;
     Launch L{c, st};
-    double *t0 = w.at(w.lay.t3), *t1 = t0 + (size_t)c->L * c->N;
-    launch_automorph(L, t0, a->poly(0), (size_t)c->L * c->N, (size_t)a->cap_limbs * c->N, 2, lv, gk->galois);
-    ks_core(c, L, w, t1, lv, gk, out->poly(0), out->poly(1), t0, nullptr);
+    if (out->d == a->d) {
+        // in place: c0 is read through the permutation while out0 is written,
+        // so it is read from a copy (c1 is only written by the last launch)
+        double *t0 = w.at(w.lay.t3);
+        launch_ew(L, EW_COPY, t0, a->poly(0), nullptr, (size_t)c->L * c->N, (size_t)a->cap_limbs * c->N, 0, 1, lv);
+        ks_core(c, L, w, a->poly(1), lv, gk, out->poly(0), out->poly(1), t0, nullptr, gk->galois);
+    } else {
+        ks_core(c, L, w, a->poly(1), lv, gk, out->poly(0), out->poly(1), a->poly(0), nullptr, gk->galois);
+    }
     out->n_limbs = lv;
     out->degree = 1;
     out->scale = a->scale;
@@ -328,7 +333,6 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
     c->alpha = prm->alpha;
     c->beta = (c->L + c->alpha - 1) / c->alpha;
     c->mod_log2 = prm->mod_log2 ? prm->mod_log2 : prm->log_n + 1;
-    if (const char *v = std::getenv("PFX_KS_VARIANT")) c->ks_variant = std::atoi(v) == 1 ? 1 : 0;
     c->primes = q;
     c->primes.insert(c->primes.end(), p.begin(), p.end());
     c->psi = psi;

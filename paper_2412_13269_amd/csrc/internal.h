@@ -103,11 +103,6 @@ struct pfx_ctx {
     std::mutex mu;
     std::map<hipStream_t, pfx::Workspace *> ws;
 
-    // Key-switch inner-product schedule: 0 = row pass of the ModUp limbs, then
-    // a streaming inner product; 1 = row pass fused with the inner product
-    // (accumulators in registers).  Chosen at context creation (PFX_KS_VARIANT).
-    int ks_variant = 0;
-
     // captured op lists (pfx_run_circuit with use_graph)
     struct GraphEntry {
         hipGraphExec_t exec;
@@ -207,21 +202,16 @@ void launch_automorph(const Launch &L, double *out, const double *in, size_t so,
 void launch_rescale_spread(const Launch &L, double *tmp, const double *lastc, int npoly, int lv);
 void launch_rescale_final(const Launch &L, double *out, const double *in, const double *tmp, size_t so,
                           size_t si, int npoly, int lv);
-void launch_modup(const Launch &L, double *ext, const double *dcoef, int lv);
+// galois != 0: d_ntt is read through the NTT-domain permutation of phi_galois.
 void launch_ks_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt,
-                     const double *key, int lv);
-void launch_moddown_conv(const Launch &L, double *tmp, const double *acc, int lv);
-void launch_moddown_final(const Launch &L, double *out0, double *out1, const double *acc,
-                          const double *tmp, const double *base0, const double *base1, int lv);
+                     const double *key, int lv, uint32_t galois);
 // Fused key-switching steps (keyswitch.hip).
-void launch_intt_scale(const Launch &L, double *dcoef, const double *d, int lv);
+void launch_intt_scale(const Launch &L, double *dcoef, const double *d, int lv, uint32_t galois);
 void launch_modup_col(const Launch &L, double *ext, const double *dcoef, int lv);
-void launch_row_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt, const double *key,
-                      int lv);
 void launch_intt_special(const Launch &L, double *acc, int lv);
 void launch_moddown_col(const Launch &L, double *tmp, const double *acc, int lv);
 void launch_row_moddown(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
-                        const double *base0, const double *base1, int lv);
+                        const double *base0, const double *base1, int lv, uint32_t galois);
 void launch_keygen_b(const Launch &L, double *b, const double *a, const double *e, const double *s,
                      const double *sfrom, int digit);
 void launch_encrypt(const Launch &L, double *c0, const double *a, const double *e, const double *s,

@@ -23,7 +23,6 @@ static inline unsigned grid_for(size_t total, unsigned threads = 256) {
     return (unsigned)std::min<size_t>(b, 1u << 20);
 }
 
-__device__ __forceinline__ unsigned brev_n(unsigned x, int logn) { return __brev(x) >> (32 - logn); }
 
 // ============================================================== NTT
 // Plain batched NTT over a LimbMap: both passes of ntt_core.h with ordinary
@@ -40,9 +39,9 @@ struct NttArgs {
     LimbMap map;
 };
 
-template <int S, bool ROW, bool INV>
-__global__ __launch_bounds__(kNttThreads) void k_ntt_pass(const NttArgs a) {
-    __shared__ double lds[kNttLds];
+template <int S, bool ROW, bool INV, int TH>
+__global__ __launch_bounds__(TH) void k_ntt_pass(const NttArgs a) {
+    __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.nblk);
     if (id >= a.nblk) return;
     const int limb = id / a.tiles;
@@ -53,17 +52,28 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(const NttArgs a) {
     const double *src = a.src + loff;
     auto ld = [&](int j, int) { return src[j]; };
     auto st = [&](int j, double v, int) { dst[j] = v; };
-    if (ROW) row_pass<S, INV>(P, a.logn, a.C, tile * a.C, lds, ld, st);
-    else col_pass<S, INV>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+    if (ROW) row_pass<S, INV, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+    else col_pass<S, INV, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
 }
 
-template <bool ROW, bool INV>
+template <bool ROW, bool INV, int TH>
 static void dispatch_pass(int S, dim3 grid, hipStream_t st, const NttArgs &a) {
     switch (S) {
-#define PFX_CASE(s) case s: k_ntt_pass<s, ROW, INV><<<grid, kNttThreads, 0, st>>>(a); break;
+#define PFX_CASE(s) case s: k_ntt_pass<s, ROW, INV, TH><<<grid, TH, 0, st>>>(a); break;
         PFX_CASE(2) PFX_CASE(3) PFX_CASE(4) PFX_CASE(5) PFX_CASE(6) PFX_CASE(7) PFX_CASE(8)
 #undef PFX_CASE
         default: set_error("unsupported NTT pass size");
+    }
+}
+
+template <int TH>
+static void dispatch_th(bool row, bool inverse, int S, dim3 grid, hipStream_t st, const NttArgs &a) {
+    if (row) {
+        if (inverse) dispatch_pass<true, true, TH>(S, grid, st, a);
+        else dispatch_pass<true, false, TH>(S, grid, st, a);
+    } else {
+        if (inverse) dispatch_pass<false, true, TH>(S, grid, st, a);
+        else dispatch_pass<false, false, TH>(S, grid, st, a);
     }
 }
 
@@ -76,9 +86,10 @@ void launch_ntt_pass(const Launch &L, double *base, const double *src, const Lim
     a.primes = ctx->d_primes;
     a.logn = logn;
     a.map = map;
-    PassShape ps = row ? row_shape(logn) : col_shape(logn);
-    // small batches: narrower tiles so that the launch still covers the CUs
-    // (column tiles stay >= 8 columns = 64-byte rows)
+    const int th = pass_threads(logn, map.n, row);
+    PassShape ps = row ? row_shape(logn, th * kSlots) : col_shape(logn, th * kSlots);
+    // very small batches: narrower tiles (idle threads) so that the launch
+    // still covers the CUs (column tiles stay >= 8 columns = 64-byte rows)
     const int minC = row ? 1 : 8;
     while (map.n * ps.tiles < 1024 && ps.C / 2 >= minC) {
         ps.C /= 2;
@@ -94,8 +105,7 @@ void launch_ntt_pass(const Launch &L, double *base, const double *src, const Lim
     std::snprintf(nm, sizeof nm, "%s/%d", inverse ? (row ? "intt_row" : "intt_col") : (row ? "ntt_row" : "ntt_col"),
                   map.n);
     prof_begin(L, nm, &ev);
-    if (row) { if (inverse) dispatch_pass<true, true>(ps.S, grid, L.st, a); else dispatch_pass<true, false>(ps.S, grid, L.st, a); }
-    else { if (inverse) dispatch_pass<false, true>(ps.S, grid, L.st, a); else dispatch_pass<false, false>(ps.S, grid, L.st, a); }
+    PFX_SWITCH_TH(th, (dispatch_th<TH>(row, inverse, ps.S, grid, L.st, a)));
     HIP_LAUNCH_CHECK();
     prof_end(L, nm, ev, 16.0 * (double)ctx->N * map.n);
 }
@@ -289,23 +299,20 @@ void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const do
 }
 
 // ============================================================== automorphism
-// phi_g in the NTT domain is a permutation: slot j holds a(psi^e), e = 2 bitrev(j) + 1,
-// and phi_g(a)(psi^e) = a(psi^(g e)), so out[j] = in[j'] with 2 bitrev(j') + 1 = g e mod 2N.
+// phi_g in the NTT domain is the permutation galois_src (ntt_core.h).  Key
+// switching reads its operand through the same map instead (no copy); this
+// kernel serves callers that want the permuted polynomial itself.
 __global__ void k_automorph(double *out, const double *in, size_t so, size_t si, int npoly, int nl, int logn,
                             uint32_t g) {
     const size_t total = ((size_t)npoly * nl) << logn;
     const uint32_t mask = (1u << logn) - 1;
-    const uint32_t mask2 = (2u << logn) - 1;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         const uint32_t j = (uint32_t)(idx & mask);
         const size_t li = idx >> logn;
         const int i = (int)(li % nl);
         const int k = (int)(li / nl);
-        const uint32_t e = 2u * brev_n(j, logn) + 1u;
-        const uint32_t e2 = (uint32_t)(((uint64_t)e * g) & mask2);
-        const uint32_t j2 = brev_n((e2 - 1u) >> 1, logn);
-        out[k * so + ((size_t)i << logn) + j] = in[k * si + ((size_t)i << logn) + j2];
+        out[k * so + ((size_t)i << logn) + j] = in[k * si + ((size_t)i << logn) + galois_src(j, logn, g)];
     }
 }
 
@@ -387,55 +394,11 @@ void launch_rescale_final(const Launch &L, double *out, const double *in, const 
 //   ext[j][t][c]  digit j's fast conversion to the E - sz_j primes outside the
 //                 digit, t in the order: q's below the digit, q's above, p's;
 //   acc[u][m][c]  u in {0, 1}, m < E: q_0..q_{lv-1} then p_0..p_{K-1}.
-__device__ __forceinline__ int ext_prime(int t, int j0, int sz, int lv, int L) {
-    if (t < j0) return t;
-    if (t < lv - sz) return t + sz;
-    return L + (t - (lv - sz));
-}
-
-__global__ void k_modup(double *ext, const double *dcoef, int lv, int logn, int L, int K, int alpha,
-                        const PrimeDev *pr, const ModUpConst *mc) {
-    const int j = blockIdx.y;
-    const int j0 = j * alpha;
-    const int sz = min(alpha, lv - j0);
-    const ModUpConst &cst = mc[j * alpha + (sz - 1)];
-    const int E = lv + K;
-    const size_t N = (size_t)1 << logn;
-    const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (c >= N) return;
-    double y[kMaxAlpha];
-#pragma unroll
-    for (int i = 0; i < kMaxAlpha; ++i) {
-        if (i < sz) y[i] = mmulc(dcoef[((size_t)(j0 + i) << logn) + c], cst.inv[i].x, cst.inv[i].y, pr[j0 + i].q);
-    }
-    double *out = ext + (size_t)j * E * N;
-    for (int t = 0; t < E - sz; ++t) {
-        const int m = ext_prime(t, j0, sz, lv, L);
-        const double qm = pr[m].q;
-        double acc = 0.0;
-#pragma unroll
-        for (int i = 0; i < kMaxAlpha; ++i) {
-            if (i < sz) acc = madd(acc, mmulc(y[i], cst.hat[i][m].x, cst.hat[i][m].y, qm), qm);
-        }
-        out[((size_t)t << logn) + c] = acc;
-    }
-}
-
-void launch_modup(const Launch &L, double *ext, const double *dcoef, int lv) {
-    pfx_ctx *ctx = L.ctx;
-    const int beta = (lv + ctx->alpha - 1) / ctx->alpha;
-    dim3 grid((ctx->N + 255) / 256, beta);
-    hipEvent_t ev;
-    prof_begin(L, "modup", &ev);
-    k_modup<<<grid, 256, 0, L.st>>>(ext, dcoef, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha, ctx->d_primes,
-                                    ctx->d_modup);
-    HIP_LAUNCH_CHECK();
-    prof_end(L, "modup", ev, 8.0 * (double)ctx->N * beta * (lv + ctx->K));
-}
-
-// acc_u[m] = sum_j dtilde_j[m] * swk_{j,u}[m]   (NTT domain)
+// acc_u[m] = sum_j dtilde_j[m] * swk_{j,u}[m]   (NTT domain).  The digit's own
+// primes take d itself; with GAL, d is phi_g(d_in) read through galois_src.
+template <bool GAL>
 __global__ void k_ks_inner(double *acc, const double *ext, const double *d_ntt, const double *key, int lv, int logn,
-                           int L, int K, int alpha, const PrimeDev *pr) {
+                           int L, int K, int alpha, const PrimeDev *pr, uint32_t g) {
     const int m = blockIdx.y;
     const size_t N = (size_t)1 << logn;
     const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -452,7 +415,8 @@ __global__ void k_ks_inner(double *acc, const double *ext, const double *d_ntt, 
         const int sz = min(alpha, lv - j0);
         double x;
         if (m >= j0 && m < j0 + sz) {
-            x = d_ntt[((size_t)m << logn) + c];
+            const size_t cs = GAL ? galois_src((uint32_t)c, logn, g) : c;
+            x = d_ntt[((size_t)m << logn) + cs];
         } else {
             const int t = m < j0 ? m : m - sz;
             x = ext[((size_t)j * E + t) * N + c];
@@ -466,91 +430,20 @@ __global__ void k_ks_inner(double *acc, const double *ext, const double *d_ntt, 
     acc[((size_t)(E + m) << logn) + c] = a1;
 }
 
-void launch_ks_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt, const double *key, int lv) {
+void launch_ks_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt, const double *key, int lv,
+                     uint32_t galois) {
     pfx_ctx *ctx = L.ctx;
     dim3 grid((ctx->N + 255) / 256, lv + ctx->K);
     hipEvent_t ev;
     prof_begin(L, "ks_inner", &ev);
-    k_ks_inner<<<grid, 256, 0, L.st>>>(acc, ext, d_ntt, key, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha,
-                                       ctx->d_primes);
+    if (galois)
+        k_ks_inner<true><<<grid, 256, 0, L.st>>>(acc, ext, d_ntt, key, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha,
+                                                 ctx->d_primes, galois);
+    else
+        k_ks_inner<false><<<grid, 256, 0, L.st>>>(acc, ext, d_ntt, key, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha,
+                                                  ctx->d_primes, 0);
     HIP_LAUNCH_CHECK();
     prof_end(L, "ks_inner", ev, 8.0 * (double)ctx->N * (lv + ctx->K) * (3.0 * ((lv + ctx->alpha - 1) / ctx->alpha) + 2.0));
-}
-
-// ModDown, first half: r_k = [acc_u(p_k) + floor(P/2)]_{p_k} (coefficient domain);
-// tmp_u[i] = sum_k [r_k (P/p_k)^-1]_{p_k} (P/p_k) - floor(P/2) mod q_i.
-__global__ void k_moddown_conv(double *tmp, const double *acc, int lv, int logn, int L, int K, const PrimeDev *pr,
-                               const ModDownConst *md) {
-    const int u = blockIdx.y;
-    const size_t N = (size_t)1 << logn;
-    const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (c >= N) return;
-    const int E = lv + K;
-    double z[kMaxSpecial];   // K <= kMaxSpecial, fully unrolled so z stays in registers
-#pragma unroll
-    for (int k = 0; k < kMaxSpecial; ++k) {
-        if (k < K) {
-            const double pk = pr[L + k].q;
-            const double r = madd(acc[((size_t)(u * E + lv + k) << logn) + c], md->half[L + k], pk);
-            z[k] = mmulc(r, md->phat_inv[k].x, md->phat_inv[k].y, pk);
-        }
-    }
-    for (int i = 0; i < lv; ++i) {
-        const double q = pr[i].q;
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < kMaxSpecial; ++k)
-            if (k < K) s = madd(s, mmulc(z[k], md->phat[k][i].x, md->phat[k][i].y, q), q);
-        // floor(P/2) sits on every coefficient of y = x + floor(P/2); the Q limbs
-        // of x are in the NTT domain, so it is taken out of the correction here,
-        // in the coefficient domain, before the correction's forward NTT.
-        tmp[((size_t)(u * lv + i) << logn) + c] = msub(s, md->half[i], q);
-    }
-}
-
-// out_u[i] = (acc_u[i] - NTT(tmp_u)[i]) * P^-1 (+ base_u[i])
-__global__ void k_moddown_final(double *out0, double *out1, const double *acc, const double *tmp,
-                                const double *base0, const double *base1, int lv, int logn, int K,
-                                const PrimeDev *pr, const ModDownConst *md) {
-    const size_t N = (size_t)1 << logn;
-    const size_t total = (size_t)2 * lv * N;
-    const int E = lv + K;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t c = idx & (N - 1);
-        const size_t li = idx >> logn;
-        const int i = (int)(li % lv);
-        const int u = (int)(li / lv);
-        const double q = pr[i].q;
-        double x = msub(acc[((size_t)(u * E + i) << logn) + c], tmp[idx], q);
-        x = mmulc(x, md->pinv[i].x, md->pinv[i].y, q);
-        const double *base = u ? base1 : base0;
-        if (base) x = madd(x, base[((size_t)i << logn) + c], q);
-        double *out = u ? out1 : out0;
-        out[((size_t)i << logn) + c] = x;
-    }
-}
-
-void launch_moddown_conv(const Launch &L, double *tmp, const double *acc, int lv) {
-    pfx_ctx *ctx = L.ctx;
-    dim3 grid((ctx->N + 255) / 256, 2);
-    hipEvent_t ev;
-    prof_begin(L, "moddown_conv", &ev);
-    k_moddown_conv<<<grid, 256, 0, L.st>>>(tmp, acc, lv, ctx->logn, ctx->L, ctx->K, ctx->d_primes, ctx->d_moddown);
-    HIP_LAUNCH_CHECK();
-    prof_end(L, "moddown_conv", ev, 8.0 * (double)ctx->N * (2.0 * ctx->K + 2.0 * lv));
-}
-
-void launch_moddown_final(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
-                          const double *base0, const double *base1, int lv) {
-    pfx_ctx *ctx = L.ctx;
-    const size_t total = (size_t)2 * lv * ctx->N;
-    hipEvent_t ev;
-    prof_begin(L, "moddown_final", &ev);
-    k_moddown_final<<<grid_for(total), 256, 0, L.st>>>(out0, out1, acc, tmp, base0, base1, lv, ctx->logn, ctx->K,
-                                                       ctx->d_primes, ctx->d_moddown);
-    HIP_LAUNCH_CHECK();
-    prof_end(L, "moddown_final", ev, 8.0 * (double)ctx->N * lv * (6.0 + (base0 ? 1 : 0) + (base1 ? 1 : 0)));
 }
 
 // ============================================================== keys, encryption

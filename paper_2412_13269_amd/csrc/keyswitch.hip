@@ -7,9 +7,9 @@
 //                     on the way out: y_i = [d_i (Q'_j/q_i)^-1]_{q_i}  -> dcoef (lv limbs)
 //   2. k_modup_col:   fast basis conversion sum_i y_i [Q'_j/q_i]_m, fed straight
 //                     into the column pass of the forward NTT   -> ext     (one limb per (j, m))
-//   3. k_row_inner:   row pass of ext_j[m] for every digit j, each result
-//                     multiplied by swk_{j,0}[m], swk_{j,1}[m] and summed in
-//                     registers (the digit's own primes take d itself) -> acc (2E limbs)
+//   3. row pass of ext (plain NTT pass), then k_ks_inner: acc_u[m] =
+//                     sum_j ext_j[m] swk_{j,u}[m] (the digit's own primes take
+//                     d itself)                                  -> acc (2E limbs)
 //   4. k_intt_special: INTT of the 2K special-prime limbs of acc, the last store
 //                     giving z_k = [(x_k + floor(P/2)) (P/p_k)^-1]_{p_k}  (in place)
 //   5. k_moddown_col: sum_k z_k [P/p_k]_{q_i} - floor(P/2), fed into the
@@ -18,8 +18,10 @@
 //                     the key switch is added to)                -> out
 //
 // The fusions remove the coefficient-domain ModUp output (beta * E limbs written
-// and read back), the NTT-domain ModUp output (the same again) and the
-// coefficient-domain ModDown conversion.  Workgroup ids are remapped so that
+// and read back) and the coefficient-domain ModDown conversion.  For a
+// rotation the automorphism is fused too: steps 1 and 3 read d through the
+// NTT-domain permutation of phi_g, and step 6 reads the polynomial it adds
+// (c0) through it, so no permuted copy is made.  Workgroup ids are remapped so that
 // blocks sharing input tiles (step 2, 5) or a prime's twiddle table (3, 6) run
 // on one XCD (see xcd_slot in ntt_core.h).
 #include <algorithm>
@@ -43,6 +45,7 @@ struct KsArgs {
     int logn, lv, L, K, alpha, beta, E;
     int C, tiles;   // pass geometry (column or row, per kernel)
     int n;          // logical blocks
+    uint32_t galois;   // != 0: the key-switched polynomial is phi_galois of the one passed in
 };
 
 __device__ __forceinline__ int ks_ext_prime(int t, int j0, int sz, int lv, int L) {
@@ -52,117 +55,66 @@ __device__ __forceinline__ int ks_ext_prime(int t, int j0, int sz, int lv, int L
 }
 
 // ---- step 2: ModUp conversion into the forward column pass
-template <int S>
-__global__ __launch_bounds__(kNttThreads) void k_modup_col(const KsArgs a, double *__restrict__ ext,
+// NT is the digit size rounded up to a power of two; the terms of a shorter
+// digit (the last one at some levels) beyond its size get weight 0 and read
+// the digit's first limb again, so the sum has no data-dependent branches.
+// Blocks: every (digit j, tile, target t) with t < E - sz_j, t fastest.
+template <int S, int NT, int TH>
+__global__ __launch_bounds__(TH) void k_modup_col(const KsArgs a, double *__restrict__ ext,
                                                            const double *__restrict__ dcoef) {
-    __shared__ double lds[kNttLds];
+    __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
-    const int Tmax = a.E - 1;
-    const int t = id % Tmax;
-    const int pair = id / Tmax;
-    const int tile = pair % a.tiles;
-    const int j = pair / a.tiles;
+    const int Tf = a.E - a.alpha;                       // targets of a full digit
+    const int full = (a.beta - 1) * Tf * a.tiles;
+    int j, rem, T;
+    if (id < full) {
+        T = Tf;
+        j = id / (Tf * a.tiles);
+        rem = id - j * Tf * a.tiles;
+    } else {
+        j = a.beta - 1;
+        T = a.E - (a.lv - j * a.alpha);
+        rem = id - full;
+    }
+    const int t = rem % T;
+    const int tile = rem / T;
     const int j0 = j * a.alpha;
     const int sz = min(a.alpha, a.lv - j0);
-    if (t >= a.E - sz) return;
     const int m = ks_ext_prime(t, j0, sz, a.lv, a.L);
     const PrimeDev &P = a.primes[m];
     const double qm = P.q;
     const ModUpConst &cst = a.mu[j * a.alpha + (sz - 1)];
-    double w[kMaxAlpha], wq[kMaxAlpha];
-#pragma unroll
-    for (int i = 0; i < kMaxAlpha; ++i) {
-        if (i < sz) {
-            w[i] = cst.hat[i][m].x;
-            wq[i] = cst.hat[i][m].y;
-        }
-    }
     const size_t N = (size_t)1 << a.logn;
     const double *src = dcoef + (size_t)j0 * N;
+    const double *sp[NT];
+    double w[NT], wq[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const bool on = i < sz;
+        sp[i] = on ? src + (size_t)i * N : src;
+        w[i] = on ? cst.hat[i][m].x : 0.0;
+        wq[i] = on ? cst.hat[i][m].y : 0.0;
+    }
     double *dst = ext + ((size_t)j * a.E + t) * N;
     auto ld = [&](int g, int) {
-        // |each term| <= q_m < 2^50 (inputs below 2^50), at most alpha = 8 terms: < 2^53
-        double acc = 0.0;
+        // |each term| <= q_m < 2^50 (inputs below 2^50), at most 8 terms: < 2^53
+        const unsigned ug = (unsigned)g;
+        double acc = mmulc_lazy(sp[0][ug], w[0], wq[0], qm);
 #pragma unroll
-        for (int i = 0; i < kMaxAlpha; ++i)
-            if (i < sz) acc += mmulc_lazy(src[(size_t)i * N + g], w[i], wq[i], qm);
+        for (int i = 1; i < NT; ++i) acc += mmulc_lazy(sp[i][ug], w[i], wq[i], qm);
         return mred_signed(acc, qm, P.qinv);
     };
-    auto st = [&](int g, double v, int) { dst[g] = v; };
-    col_pass<S, false>(P, a.logn, a.C, tile * a.C, lds, ld, st);
-}
-
-// global index of slot `slot` in the output layout of the forward row pass
-// (coalesced: element e = thread + 256 * slot of the tile)
-template <int S>
-__device__ __forceinline__ bool row_fwd_out(int slot, int C, int cbase, int &gidx) {
-    const int e = threadIdx.x + slot * kNttThreads;
-    if (e >= (C << S)) return false;
-    gidx = (cbase << S) + e;
-    return true;
-}
-
-// ---- step 3: forward row pass of every digit's limb m, times the key, summed
-template <int S>
-__global__ __launch_bounds__(kNttThreads) void k_row_inner(const KsArgs a, double *__restrict__ acc,
-                                                           const double *__restrict__ ext,
-                                                           const double *__restrict__ d_ntt,
-                                                           const double *__restrict__ key) {
-    __shared__ double lds[kNttLds];
-    const int id = xcd_slot(a.n);
-    if (id >= a.n) return;
-    const int m = id / a.tiles;
-    const int tile = id - m * a.tiles;
-    const int pid = m < a.lv ? m : a.L + (m - a.lv);
-    const PrimeDev &P = a.primes[pid];
-    const double q = P.q, qinv = P.qinv;
-    const size_t N = (size_t)1 << a.logn;
-    const size_t kstride = (size_t)(a.L + a.K) * N;
-    const int cbase = tile * a.C;
-    double a0[kSlots], a1[kSlots];
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) a0[k] = a1[k] = 0.0;
-    for (int j = 0; j < a.beta; ++j) {
-        const int j0 = j * a.alpha;
-        const int sz = min(a.alpha, a.lv - j0);
-        const double *k0 = key + (size_t)(2 * j) * kstride + (size_t)pid * N;
-        const double *k1 = k0 + kstride;
-        auto mac = [&](int g, double x, int slot) {
-            a0[slot] = madd(a0[slot], mmul(x, k0[g], q, qinv), q);
-            a1[slot] = madd(a1[slot], mmul(x, k1[g], q, qinv), q);
-        };
-        if (m >= j0 && m < j0 + sz) {
-            const double *x = d_ntt + (size_t)m * N;
-#pragma unroll
-            for (int slot = 0; slot < kSlots; ++slot) {
-                int g;
-                if (row_fwd_out<S>(slot, a.C, cbase, g)) mac(g, x[g], slot);
-            }
-        } else {
-            const int t = m < j0 ? m : m - sz;
-            const double *src = ext + ((size_t)j * a.E + t) * N;
-            auto ld = [&](int g, int) { return src[g]; };
-            row_pass<S, false>(P, a.logn, a.C, cbase, lds, ld, mac);
-            __syncthreads();
-        }
-    }
-    double *o0 = acc + (size_t)m * N, *o1 = acc + (size_t)(a.E + m) * N;
-#pragma unroll
-    for (int slot = 0; slot < kSlots; ++slot) {
-        int g;
-        if (row_fwd_out<S>(slot, a.C, cbase, g)) {
-            o0[g] = a0[slot];
-            o1[g] = a1[slot];
-        }
-    }
+    auto st = [&](int g, double v, int) { dst[(unsigned)g] = v; };
+    col_pass<S, false, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
 }
 
 // ---- step 5: ModDown conversion into the forward column pass
-template <int S>
-__global__ __launch_bounds__(kNttThreads) void k_moddown_col(const KsArgs a, double *__restrict__ tmp,
+// NT is K rounded up to a power of two (terms beyond K: weight 0, limb 0 again).
+template <int S, int NT, int TH>
+__global__ __launch_bounds__(TH) void k_moddown_col(const KsArgs a, double *__restrict__ tmp,
                                                              const double *__restrict__ acc) {
-    __shared__ double lds[kNttLds];
+    __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
     const int i = id % a.lv;
@@ -173,37 +125,38 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_col(const KsArgs a, dou
     const double q = P.q;
     const ModDownConst *md = a.md;
     const size_t N = (size_t)1 << a.logn;
-    double w[kMaxSpecial], wq[kMaxSpecial];
+    const double *src = acc + ((size_t)u * a.E + a.lv) * N;
+    const double *sp[NT];
+    double w[NT], wq[NT];
 #pragma unroll
-    for (int k = 0; k < kMaxSpecial; ++k) {
-        if (k < a.K) {
-            w[k] = md->phat[k][i].x;
-            wq[k] = md->phat[k][i].y;
-        }
+    for (int k = 0; k < NT; ++k) {
+        const bool on = k < a.K;
+        sp[k] = on ? src + (size_t)k * N : src;
+        w[k] = on ? md->phat[k][i].x : 0.0;
+        wq[k] = on ? md->phat[k][i].y : 0.0;
     }
     const double hi = md->half[i];
-    const double *src = acc + ((size_t)u * a.E + a.lv) * N;
     double *dst = tmp + ((size_t)u * a.lv + i) * N;
     auto ld = [&](int g, int) {
         // src holds z_k = [(x_k + floor(P/2)) (P/p_k)^-1]_{p_k} (step 4).
-        // |each term| <= q_i < 2^50, K <= 7 terms plus floor(P/2) mod q_i: < 2^53
+        // |each term| <= q_i < 2^50, at most 8 terms plus floor(P/2) mod q_i: < 2^53
+        const unsigned ug = (unsigned)g;
         double s = -hi;
 #pragma unroll
-        for (int k = 0; k < kMaxSpecial; ++k)
-            if (k < a.K) s += mmulc_lazy(src[(size_t)k * N + g], w[k], wq[k], q);
+        for (int k = 0; k < NT; ++k) s += mmulc_lazy(sp[k][ug], w[k], wq[k], q);
         return mred_signed(s, q, P.qinv);
     };
-    auto st = [&](int g, double v, int) { dst[g] = v; };
-    col_pass<S, false>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+    auto st = [&](int g, double v, int) { dst[(unsigned)g] = v; };
+    col_pass<S, false, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
 }
 
 // ---- step 6: forward row pass of the conversion, then (acc_Q - x) P^-1 (+ base)
-template <int S>
-__global__ __launch_bounds__(kNttThreads) void k_row_moddown(const KsArgs a, double *out0, double *out1,
+template <int S, bool GAL, int TH>
+__global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, double *out0, double *out1,
                                                              const double *__restrict__ acc,
                                                              const double *__restrict__ tmp, const double *base0,
                                                              const double *base1) {
-    __shared__ double lds[kNttLds];
+    __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
     const int tile = id % a.tiles;
@@ -220,19 +173,20 @@ __global__ __launch_bounds__(kNttThreads) void k_row_moddown(const KsArgs a, dou
     double *out = (u ? out1 : out0) + (size_t)i * N;
     const double *bs = base ? base + (size_t)i * N : nullptr;
     auto ld = [&](int g, int) { return src[g]; };
+    // with GAL the base of output 0 (c0 of the rotated ciphertext) is read through phi_g
     auto st = [&](int g, double v, int) {
         double x = mmulc(msub(ax[g], v, q), pinv.x, pinv.y, q);
-        if (bs) x = madd(x, bs[g], q);
+        if (bs) x = madd(x, bs[GAL && u == 0 ? galois_src((uint32_t)g, a.logn, a.galois) : (uint32_t)g], q);
         out[g] = x;
     };
-    row_pass<S, false>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+    row_pass<S, false, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
 }
 
 // ---- step 1: INTT of d with the ModUp scaling folded into the last stage's store
-template <int S, bool ROW>
-__global__ __launch_bounds__(kNttThreads) void k_intt_scale(const KsArgs a, double *__restrict__ dst,
+template <int S, bool ROW, bool GAL, int TH>
+__global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__restrict__ dst,
                                                             const double *__restrict__ src) {
-    __shared__ double lds[kNttLds];
+    __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
     const int i = id / a.tiles;
@@ -241,24 +195,24 @@ __global__ __launch_bounds__(kNttThreads) void k_intt_scale(const KsArgs a, doub
     const size_t N = (size_t)1 << a.logn;
     const double *s = src + (size_t)i * N;
     double *d = dst + (size_t)i * N;
-    auto ld = [&](int g, int) { return s[g]; };
+    auto ld = [&](int g, int) { return s[GAL ? galois_src((uint32_t)g, a.logn, a.galois) : (uint32_t)g]; };
     if (ROW) {
         auto st = [&](int g, double v, int) { d[g] = v; };
-        row_pass<S, true>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+        row_pass<S, true, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
     } else {
         const int j = i / a.alpha;
         const int sz = min(a.alpha, a.lv - j * a.alpha);
         const double2 inv = a.mu[j * a.alpha + (sz - 1)].inv[i - j * a.alpha];
         auto st = [&](int g, double v, int) { d[g] = mmulc(v, inv.x, inv.y, P.q); };
-        col_pass<S, true>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+        col_pass<S, true, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
     }
 }
 
 // ---- step 4: INTT of the special-prime limbs of acc_0, acc_1 (in place); the
 // last store adds floor(P/2) and multiplies by (P/p_k)^-1, so step 5 only sums.
-template <int S, bool ROW>
-__global__ __launch_bounds__(kNttThreads) void k_intt_special(const KsArgs a, double *__restrict__ acc) {
-    __shared__ double lds[kNttLds];
+template <int S, bool ROW, int TH>
+__global__ __launch_bounds__(TH) void k_intt_special(const KsArgs a, double *__restrict__ acc) {
+    __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
     const int limb = id / a.tiles;          // u * K + k
@@ -270,12 +224,12 @@ __global__ __launch_bounds__(kNttThreads) void k_intt_special(const KsArgs a, do
     auto ld = [&](int g, int) { return x[g]; };
     if (ROW) {
         auto st = [&](int g, double v, int) { x[g] = v; };
-        row_pass<S, true>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+        row_pass<S, true, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
     } else {
         const double h = a.md->half[a.L + k];
         const double2 iv = a.md->phat_inv[k];
         auto st = [&](int g, double v, int) { x[g] = mmulc(madd(v, h, P.q), iv.x, iv.y, P.q); };
-        col_pass<S, true>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+        col_pass<S, true, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
     }
 }
 
@@ -292,6 +246,15 @@ __global__ __launch_bounds__(kNttThreads) void k_intt_special(const KsArgs a, do
         default: set_error("unsupported NTT pass size"); break;  \
     }
 
+// Term count of a conversion kernel: n rounded up to 1, 2, 4 or 8.
+#define PFX_SWITCH_NT(n_, CALL)                                          \
+    switch ((n_) <= 1 ? 1 : (n_) <= 2 ? 2 : (n_) <= 4 ? 4 : 8) {         \
+        case 1: { constexpr int NT = 1; CALL; } break;                  \
+        case 2: { constexpr int NT = 2; CALL; } break;                  \
+        case 4: { constexpr int NT = 4; CALL; } break;                  \
+        default: { constexpr int NT = 8; CALL; } break;                 \
+    }
+
 static KsArgs ks_args(pfx_ctx *c, int lv) {
     KsArgs a;
     a.primes = c->d_primes;
@@ -304,103 +267,120 @@ static KsArgs ks_args(pfx_ctx *c, int lv) {
     a.alpha = c->alpha;
     a.beta = (lv + c->alpha - 1) / c->alpha;
     a.E = lv + c->K;
+    a.galois = 0;
     return a;
 }
 
-void launch_intt_scale(const Launch &L, double *dcoef, const double *d, int lv) {
+// Narrower tiles (idle threads) until a launch over `limbs` limbs has at least
+// 1024 workgroups: the transforms of the special-prime limbs (2K of them) are
+// too small to fill the chip even with 128-thread groups.  Column tiles keep
+// 8 columns (64-byte rows).
+static void widen_grid(PassShape &pr, PassShape &pc, int limbs) {
+    while (limbs * pr.tiles < 1024 && pr.C > 1) { pr.C /= 2; pr.tiles *= 2; }
+    while (limbs * pc.tiles < 1024 && pc.C / 2 >= 8) { pc.C /= 2; pc.tiles *= 2; }
+}
+
+void launch_intt_scale(const Launch &L, double *dcoef, const double *d, int lv, uint32_t galois) {
     KsArgs a = ks_args(L.ctx, lv);
-    const PassShape pr = row_shape(a.logn), pc = col_shape(a.logn);
+    a.galois = galois;
+    const int th = pass_threads(a.logn, lv, true), tc = pass_threads(a.logn, lv, false);
+    const PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
     hipEvent_t ev;
     a.C = pr.C;
     a.tiles = pr.tiles;
     a.n = lv * a.tiles;
     prof_begin(L, "ks_intt_row", &ev);
-    PFX_SWITCH_S(pr.S, (k_intt_scale<SS, true><<<xcd_grid(a.n), kNttThreads, 0, L.st>>>(a, dcoef, d)));
+    PFX_SWITCH_TH(th, {
+        if (galois) {
+            PFX_SWITCH_S(pr.S, (k_intt_scale<SS, true, true, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, dcoef, d)));
+        } else {
+            PFX_SWITCH_S(pr.S, (k_intt_scale<SS, true, false, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, dcoef, d)));
+        }
+    });
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_intt_row", ev, 16.0 * (double)L.ctx->N * lv);
     a.C = pc.C;
     a.tiles = pc.tiles;
     a.n = lv * a.tiles;
     prof_begin(L, "ks_intt_col", &ev);
-    PFX_SWITCH_S(pc.S, (k_intt_scale<SS, false><<<xcd_grid(a.n), kNttThreads, 0, L.st>>>(a, dcoef, dcoef)));
+    PFX_SWITCH_TH(tc, PFX_SWITCH_S(pc.S, (k_intt_scale<SS, false, false, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(
+                                              a, dcoef, dcoef))));
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_intt_col", ev, 16.0 * (double)L.ctx->N * lv);
 }
 
 void launch_modup_col(const Launch &L, double *ext, const double *dcoef, int lv) {
     KsArgs a = ks_args(L.ctx, lv);
-    const PassShape ps = col_shape(a.logn);
+    const int th = pass_threads(a.logn, a.beta * a.E - lv, false);
+    const PassShape ps = col_shape(a.logn, th * kSlots);
     a.C = ps.C;
     a.tiles = ps.tiles;
-    a.n = a.beta * a.tiles * (a.E - 1);
+    a.n = (a.beta * a.E - lv) * a.tiles;      // sum over digits of E - sz_j targets
     hipEvent_t ev;
     prof_begin(L, "ks_modup_col", &ev);
-    PFX_SWITCH_S(ps.S, (k_modup_col<SS><<<xcd_grid(a.n), kNttThreads, 0, L.st>>>(a, ext, dcoef)));
+    PFX_SWITCH_TH(th, PFX_SWITCH_NT(a.alpha, PFX_SWITCH_S(ps.S, (k_modup_col<SS, NT, TH><<<xcd_grid(a.n), TH, 0,
+                                                                                           L.st>>>(a, ext, dcoef)))));
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_modup_col", ev, 8.0 * (double)L.ctx->N * a.beta * a.E);
 }
 
-void launch_row_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt, const double *key,
-                      int lv) {
-    KsArgs a = ks_args(L.ctx, lv);
-    const PassShape ps = row_shape(a.logn);
-    a.C = ps.C;
-    a.tiles = ps.tiles;
-    a.n = a.E * a.tiles;
-    hipEvent_t ev;
-    prof_begin(L, "ks_row_inner", &ev);
-    PFX_SWITCH_S(ps.S, (k_row_inner<SS><<<xcd_grid(a.n), kNttThreads, 0, L.st>>>(a, acc, ext, d_ntt, key)));
-    HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_row_inner", ev, 8.0 * (double)L.ctx->N * a.E * (3.0 * a.beta + 2.0));
-}
-
 void launch_intt_special(const Launch &L, double *acc, int lv) {
     KsArgs a = ks_args(L.ctx, lv);
-    PassShape pr = row_shape(a.logn), pc = col_shape(a.logn);
-    // 2K limbs only: narrower tiles for more workgroups
-    while (2 * a.K * pr.tiles < 1024 && pr.C > 1) { pr.C /= 2; pr.tiles *= 2; }
-    while (2 * a.K * pc.tiles < 1024 && pc.C / 2 >= 8) { pc.C /= 2; pc.tiles *= 2; }
+    constexpr int th = 128, tc = 256;
+    PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
+    widen_grid(pr, pc, 2 * a.K);
     hipEvent_t ev;
     a.C = pr.C;
     a.tiles = pr.tiles;
     a.n = 2 * a.K * a.tiles;
     prof_begin(L, "ks_intt_special_row", &ev);
-    PFX_SWITCH_S(pr.S, (k_intt_special<SS, true><<<xcd_grid(a.n), kNttThreads, 0, L.st>>>(a, acc)));
+    PFX_SWITCH_S(pr.S, (k_intt_special<SS, true, th><<<xcd_grid(a.n), th, 0, L.st>>>(a, acc)));
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_intt_special_row", ev, 16.0 * (double)L.ctx->N * 2 * a.K);
     a.C = pc.C;
     a.tiles = pc.tiles;
     a.n = 2 * a.K * a.tiles;
     prof_begin(L, "ks_intt_special_col", &ev);
-    PFX_SWITCH_S(pc.S, (k_intt_special<SS, false><<<xcd_grid(a.n), kNttThreads, 0, L.st>>>(a, acc)));
+    PFX_SWITCH_S(pc.S, (k_intt_special<SS, false, tc><<<xcd_grid(a.n), tc, 0, L.st>>>(a, acc)));
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_intt_special_col", ev, 16.0 * (double)L.ctx->N * 2 * a.K);
 }
 
 void launch_moddown_col(const Launch &L, double *tmp, const double *acc, int lv) {
     KsArgs a = ks_args(L.ctx, lv);
-    const PassShape ps = col_shape(a.logn);
+    const int th = pass_threads(a.logn, 2 * lv, false);
+    const PassShape ps = col_shape(a.logn, th * kSlots);
     a.C = ps.C;
     a.tiles = ps.tiles;
     a.n = 2 * a.tiles * lv;
     hipEvent_t ev;
     prof_begin(L, "ks_moddown_col", &ev);
-    PFX_SWITCH_S(ps.S, (k_moddown_col<SS><<<xcd_grid(a.n), kNttThreads, 0, L.st>>>(a, tmp, acc)));
+    PFX_SWITCH_TH(th, PFX_SWITCH_NT(a.K, PFX_SWITCH_S(ps.S, (k_moddown_col<SS, NT, TH><<<xcd_grid(a.n), TH, 0,
+                                                                                       L.st>>>(a, tmp, acc)))));
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_moddown_col", ev, 8.0 * (double)L.ctx->N * (2.0 * a.K + 2.0 * lv));
 }
 
 void launch_row_moddown(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
-                        const double *base0, const double *base1, int lv) {
+                        const double *base0, const double *base1, int lv, uint32_t galois) {
     KsArgs a = ks_args(L.ctx, lv);
-    const PassShape ps = row_shape(a.logn);
+    a.galois = galois;
+    const int th = pass_threads(a.logn, 2 * lv, true);
+    const PassShape ps = row_shape(a.logn, th * kSlots);
     a.C = ps.C;
     a.tiles = ps.tiles;
     a.n = 2 * lv * a.tiles;
     hipEvent_t ev;
     prof_begin(L, "ks_row_moddown", &ev);
-    PFX_SWITCH_S(ps.S, (k_row_moddown<SS><<<xcd_grid(a.n), kNttThreads, 0, L.st>>>(a, out0, out1, acc, tmp, base0,
-                                                                                     base1)));
+    PFX_SWITCH_TH(th, {
+        if (galois) {
+            PFX_SWITCH_S(ps.S, (k_row_moddown<SS, true, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, out0, out1, acc, tmp,
+                                                                                          base0, base1)));
+        } else {
+            PFX_SWITCH_S(ps.S, (k_row_moddown<SS, false, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, out0, out1, acc, tmp,
+                                                                                           base0, base1)));
+        }
+    });
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_row_moddown", ev,
              8.0 * (double)L.ctx->N * lv * (6.0 + (base0 ? 1 : 0) + (base1 ? 1 : 0)));

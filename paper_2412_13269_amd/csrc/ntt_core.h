@@ -36,10 +36,28 @@
 
 namespace pfx {
 
+// A workgroup of TH threads (256 or 128) works on a tile of TH * kSlots
+// elements, kSlots per thread in each register round, through an LDS buffer of
+// the tile plus 1/16 padding.  Launches over few limbs take 128-thread groups
+// so that they still spread over every CU.
 constexpr int kNttThreads = 256;
-constexpr int kNttTile = 4096;
-constexpr int kNttLds = kNttTile + kNttTile / 16;
-constexpr int kSlots = kNttTile / kNttThreads;   // elements per thread per round
+constexpr int kSlots = 16;                       // elements per thread per round
+constexpr int kNttTile = kNttThreads * kSlots;
+template <int TH>
+struct NttTile {
+    static constexpr int n = TH * kSlots;
+    static constexpr int lds = n + n / 16;
+};
+constexpr int kNttLds = NttTile<kNttThreads>::lds;
+
+// Automorphism phi_g: X -> X^g (g odd) in the NTT domain.  Slot j holds
+// a(psi^e) with e = 2 bitrev(j) + 1, and phi_g(a)(psi^e) = a(psi^(g e)), so
+// phi_g(a)[j] = a[galois_src(j)] with 2 bitrev(galois_src(j)) + 1 = g e mod 2N.
+__device__ __forceinline__ uint32_t galois_src(uint32_t j, int logn, uint32_t g) {
+    const uint32_t e = 2u * (__brev(j) >> (32 - logn)) + 1u;
+    const uint32_t e2 = (e * g) & ((2u << logn) - 1u);
+    return __brev((e2 - 1u) >> 1) >> (32 - logn);
+}
 
 // Arithmetic inside a transform is signed and lazy: a twiddle product returns
 // a representative in [-q, q] (mmulc_lazy), sums and differences are left
@@ -172,10 +190,11 @@ __device__ __forceinline__ void inv_group_gen(double *v, const double *B, const 
     for (int u = 0; u < E; ++u) v[u] = mred_signed(v[u], q, qinv);
 }
 
-// Column pass: global stages [0, S) on the tile of columns [cbase, cbase + C).
+// Column pass: global stages [0, S) on the tile of columns [cbase, cbase + C),
+// run by TH threads.
 // Inputs |x| <= q.  Forward: the first pass of a transform, outputs in
 // [-q/2, q/2] for the row pass.  Inverse: the last pass, outputs in [0, q).
-template <int S, bool INV, class Load, class Store>
+template <int S, bool INV, int TH, class Load, class Store>
 __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int cbase, double *lds, Load &&load,
                                          Store &&store) {
     constexpr int R1 = (S + 1) / 2, R2 = S - R1, E1 = 1 << R1, E2 = 1 << R2;
@@ -188,7 +207,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
     if (!INV) {
 #pragma unroll
         for (int gi = 0; gi < IT1; ++gi) {
-            const int g = threadIdx.x + gi * kNttThreads;
+            const int g = threadIdx.x + gi * TH;
             if (g < n1) {
                 const int c = g % C, ml = g / C;
                 auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
@@ -203,7 +222,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
         __syncthreads();
 #pragma unroll
         for (int gi = 0; gi < IT2; ++gi) {
-            const int g = threadIdx.x + gi * kNttThreads;
+            const int g = threadIdx.x + gi * TH;
             if (g < n2) {
                 const int c = g % C, mh = g / C;
                 auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
@@ -218,7 +237,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
     } else {
 #pragma unroll
         for (int gi = 0; gi < IT2; ++gi) {
-            const int g = threadIdx.x + gi * kNttThreads;
+            const int g = threadIdx.x + gi * TH;
             if (g < n2) {
                 const int c = g % C, mh = g / C;
                 auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
@@ -233,7 +252,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
         __syncthreads();
 #pragma unroll
         for (int gi = 0; gi < IT1; ++gi) {
-            const int g = threadIdx.x + gi * kNttThreads;
+            const int g = threadIdx.x + gi * TH;
             if (g < n1) {
                 const int c = g % C, ml = g / C;
                 auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
@@ -254,8 +273,8 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
 // The tile is C * 2^S contiguous doubles; the side of the pass that would own
 // 2^R2 consecutive doubles per thread (forward output, inverse input) goes
 // through LDS in coalesced order instead: element e of the tile belongs to
-// thread e mod 256 as slot e / 256.
-template <int S, bool INV, class Load, class Store>
+// thread e mod TH as slot e / TH.
+template <int S, bool INV, int TH, class Load, class Store>
 __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int cbase, double *lds, Load &&load,
                                          Store &&store) {
     constexpr int R = 1 << S;
@@ -273,7 +292,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
     if (!INV) {
 #pragma unroll
         for (int gi = 0; gi < IT1; ++gi) {
-            const int g = threadIdx.x + gi * kNttThreads;
+            const int g = threadIdx.x + gi * TH;
             if (g < n1) {
                 const int ml = g & ((1 << (S - R1)) - 1), c = g >> (S - R1);
                 auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
@@ -288,7 +307,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
         __syncthreads();
 #pragma unroll
         for (int gi = 0; gi < IT2; ++gi) {
-            const int g = threadIdx.x + gi * kNttThreads;
+            const int g = threadIdx.x + gi * TH;
             if (g < n2) {
                 const int mh = g & (E1 - 1), c = g >> R1;
                 double v[E2], B[R2];
@@ -303,19 +322,19 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
-            const int e = threadIdx.x + k * kNttThreads;
+            const int e = threadIdx.x + k * TH;
             if (e < tot) store(base + e, mcanon(lds[lidx(e >> S, e & (R - 1))], q), k);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
-            const int e = threadIdx.x + k * kNttThreads;
+            const int e = threadIdx.x + k * TH;
             if (e < tot) lds[lidx(e >> S, e & (R - 1))] = load(base + e, k);
         }
         __syncthreads();
 #pragma unroll
         for (int gi = 0; gi < IT2; ++gi) {
-            const int g = threadIdx.x + gi * kNttThreads;
+            const int g = threadIdx.x + gi * TH;
             if (g < n2) {
                 const int mh = g & (E1 - 1), c = g >> R1;
                 double v[E2], B[R2];
@@ -330,7 +349,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
         __syncthreads();
 #pragma unroll
         for (int gi = 0; gi < IT1; ++gi) {
-            const int g = threadIdx.x + gi * kNttThreads;
+            const int g = threadIdx.x + gi * TH;
             if (g < n1) {
                 const int ml = g & ((1 << (S - R1)) - 1), c = g >> (S - R1);
                 auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
@@ -352,23 +371,36 @@ struct PassShape {
     int tiles;   // tiles per limb
 };
 
-inline PassShape col_shape(int logn) {
+inline PassShape col_shape(int logn, int tile = kNttTile) {
     PassShape p;
     p.S = logn / 2;
     const int subs = 1 << (logn - p.S);
-    p.C = std::min(kNttTile >> p.S, subs);
+    p.C = std::min(tile >> p.S, subs);
     p.tiles = subs / p.C;
     return p;
 }
 
-inline PassShape row_shape(int logn) {
+inline PassShape row_shape(int logn, int tile = kNttTile) {
     PassShape p;
     p.S = logn - logn / 2;
     const int subs = 1 << (logn - p.S);
-    p.C = std::min(kNttTile >> p.S, subs);
+    p.C = std::min(tile >> p.S, subs);
     p.tiles = subs / p.C;
     return p;
 }
+
+// Workgroup size of a pass launch over `limbs` limbs: a row pass takes 128
+// threads when 256 would make fewer than 2048 workgroups (eight per CU); a
+// column pass keeps 256, whose 16-column tiles read whole 128-byte rows.
+inline int pass_threads(int logn, int limbs, bool row) {
+    return (!row || limbs * col_shape(logn).tiles >= 2048) ? 256 : 128;
+}
+
+#define PFX_SWITCH_TH(th_, CALL)                                   \
+    switch (th_) {                                                 \
+        case 128: { constexpr int TH = 128; CALL; } break;         \
+        default: { constexpr int TH = 256; CALL; } break;          \
+    }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
 // XCD b mod 8).  xcd_slot() turns the hardware id into a logical id such that

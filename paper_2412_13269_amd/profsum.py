@@ -1,7 +1,10 @@
-"""Summarise a rocprofv3 kernel trace (CSV, `--kernel-trace --output-format csv`)
-by kernel and grid size: launches, average and total duration.
+"""Summarise rocprofv3 CSV output by kernel and grid size.
 
     python -m paper_2412_13269_amd.profsum <..._kernel_trace.csv> [--top N]
+        launches, average and total duration (`--kernel-trace --output-format csv`)
+    python -m paper_2412_13269_amd.profsum --pmc <..._counter_collection.csv> [--match REGEX]
+        per-dispatch average of every collected counter (`--pmc ...`), with the
+        kernel's VGPR/SGPR counts and LDS block size
 """
 from __future__ import annotations
 
@@ -29,7 +32,38 @@ def summarise(path: str, top: int = 25) -> str:
     return "\n".join(out)
 
 
+def summarise_pmc(path: str, match: str | None = None) -> str:
+    import re
+    vals = defaultdict(lambda: defaultdict(list))
+    meta = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = (row.get("Kernel_Name") or "?").split("(")[0].replace("void ", "")
+            if match and not re.search(match, name):
+                continue
+            grid = row.get("Grid_Size") or row.get("Grid_Size_X") or "?"
+            key = (name, grid)
+            vals[key][row["Counter_Name"]].append(float(row["Counter_Value"]))
+            meta[key] = (row.get("VGPR_Count", "?"), row.get("Accum_VGPR_Count", "?"), row.get("SGPR_Count", "?"),
+                         row.get("LDS_Block_Size", "?"))
+    counters = sorted({c for v in vals.values() for c in v})
+    out = ["| kernel | grid (threads) | dispatches | vgpr/agpr/sgpr | lds | " + " | ".join(counters) + " |",
+           "|---|---|---|---|---|" + "---|" * len(counters)]
+    for key in sorted(vals):
+        v = vals[key]
+        n = max(len(x) for x in v.values())
+        cells = [f"{sum(v[c]) / len(v[c]):.4g}" if v.get(c) else "" for c in counters]
+        m = meta[key]
+        out.append(f"| `{key[0]}` | {key[1]} | {n} | {m[0]}/{m[1]}/{m[2]} | {m[3]} | " + " | ".join(cells) + " |")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
+    if "--pmc" in sys.argv:
+        i = sys.argv.index("--pmc")
+        m = sys.argv[sys.argv.index("--match") + 1] if "--match" in sys.argv else None
+        print(summarise_pmc(sys.argv[i + 1], m))
+        sys.exit(0)
     top = 25
     if "--top" in sys.argv:
         top = int(sys.argv[sys.argv.index("--top") + 1])

@@ -1,0 +1,133 @@
+"""The single-ciphertext key-switching workload, shared by bench.py and the
+profiler runs.
+
+N = 2^16, L = 24 ciphertext primes (one 50-bit, 23 near 2^45), K = 4 special
+primes of 50 bits, digits of 4 primes (dnum = 6), scale 2^45, a secret with
+192 non-zeros, 2^15 real slots uniform in [-1, 1].  One step runs every
+operation of the path once on device-resident inputs: forward and inverse NTT
+of all limbs of a ciphertext, HMult + relinearisation, rescale 24 -> 23, and
+rotations by 2^k for k = 0..14 (15 distinct Galois keys): 16 key switches.
+
+    python -m paper_2412_13269_amd.workload --steps 20 [--calibrate]
+
+runs the step `--steps` times after one warm-up step, the command that
+rocprofv3 wraps for kernel traces and counters.  `--calibrate` first runs the
+library's plain word-to-double copy (k_u64_to_f64) over one ciphertext, 2 x 24
+limbs = 24 MiB read and 24 MiB written per launch, five times: the reference
+against which HBM counters are scaled.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+LOGN = 16
+Q_BITS = [50] + [45] * 23
+P_BITS = [50] * 4
+ALPHA = 4
+MOD_LOG2 = 17
+SCALE = 2.0 ** 45
+H = 192
+ROT_STEPS = [1 << k for k in range(15)]
+KS_PER_STEP = 1 + len(ROT_STEPS)
+
+
+def key_inputs(moduli, n, beta, seed):
+    from . import inputs as I
+    return (I.uniform_residues(moduli, n, seed, lead=(beta,)),
+            I.gaussian_error((beta, n), seed + 1))
+
+
+class KsWorkload:
+    """Context, keys and operands of the workload, all resident on the device."""
+
+    def __init__(self, log=lambda *a: None):
+        from . import inputs as I
+        from . import pfx as X
+        self.X = X
+        prm = X.make_params(LOGN, Q_BITS, P_BITS, ALPHA, MOD_LOG2)
+        self.ctx = ctx = X.pfx_ctx_create(prm, 0)
+        self.N, self.L, self.K = N, L, K = 1 << LOGN, len(Q_BITS), len(P_BITS)
+        self.beta = beta = -(-L // ALPHA)
+        q, p, _ = X.pfx_ctx_moduli(ctx, L, K)
+        self.q, self.p = q, p
+        ext = [int(v) for v in q] + [int(v) for v in p]
+        self.st = st = X.pfx_stream_create(ctx)
+        log("keygen ...")
+        self.s = I.ternary_secret(N, H, 2001)
+        self.sk = X.pfx_sk_create(ctx, self.s)
+        self.rlk = X.pfx_swk_create(ctx, self.sk, 0, *key_inputs(ext, N, beta, 2002))
+        self.gks = []
+        for k, step in enumerate(ROT_STEPS):
+            g = pow(5, step, 2 * N)
+            self.gks.append(X.pfx_swk_create(ctx, self.sk, g, *key_inputs(ext, N, beta, 3000 + 10 * k)))
+        self.cts, self.pts = [], []
+        for seed in (201, 202):
+            pt = X.pfx_encode(ctx, I.uniform_slots(N // 2, seed), None, L, SCALE)
+            ct = X.pfx_ct_create(ctx, L, 1)
+            X.pfx_encrypt(ctx, self.sk, pt, I.uniform_residues(q, N, seed + 10), I.gaussian_error(N, seed + 20),
+                          ct, st)
+            self.cts.append(ct)
+            self.pts.append(pt)
+        self.prod = X.pfx_ct_create(ctx, L, 1)
+        self.rot = X.pfx_ct_create(ctx, L, 1)
+        self.words = I.uniform_residues(q, N, 7, lead=(2,))          # one ciphertext: 2 x 24 limbs
+        self.dbuf = X.pfx_dev_alloc(ctx, self.words.nbytes)
+        X.pfx_memcpy_htod(ctx, self.dbuf, self.words, st)
+
+    def step(self):
+        X, ctx, st, L = self.X, self.ctx, self.st, self.L
+        X.pfx_ntt(ctx, self.dbuf, 0, L, 2, False, st)
+        X.pfx_ntt(ctx, self.dbuf, 0, L, 2, True, st)
+        X.pfx_mul_relin(ctx, self.cts[0], self.cts[1], self.rlk, self.prod, st)
+        X.pfx_rescale(ctx, self.prod, self.prod, st)
+        for r in ROT_STEPS:
+            X.pfx_rotate(ctx, self.cts[0], r, self.gks, self.rot, st)
+
+    def calibrate_copy(self, reps=5):
+        """k_u64_to_f64 over 2 x 24 limbs (24 MiB in, 24 MiB out) per launch."""
+        X = self.X
+        for _ in range(reps):
+            X.pfx_ct_import(self.ctx, self.words, SCALE, self.rot, self.st)
+        X.pfx_sync(self.ctx, self.st)
+
+    def sync(self):
+        self.X.pfx_sync(self.ctx, self.st)
+
+    def close(self):
+        X = self.X
+        for h in self.cts + self.pts + [self.prod, self.rot]:
+            X.pfx_ct_destroy(h)
+        for k in self.gks + [self.rlk]:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(self.sk)
+        X.pfx_dev_free(self.ctx, self.dbuf)
+        X.pfx_stream_destroy(self.ctx, self.st)
+        X.pfx_ctx_destroy(self.ctx)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--calibrate", action="store_true")
+    args = ap.parse_args()
+    w = KsWorkload(log=lambda *a: print(*a, flush=True))
+    if args.calibrate:
+        w.calibrate_copy()
+        print("copy calibration done", flush=True)
+    w.step()
+    w.sync()
+    for _ in range(args.steps):
+        w.step()
+    w.sync()
+    print(f"{args.steps} steps done ({KS_PER_STEP * args.steps} key switches)", flush=True)
+    w.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -246,6 +246,14 @@ def test_rotations_and_conjugation(pair, X):
     with pytest.raises(X.PfxError) as e:
         X.pfx_rotate(pair.ctx, cx, 3, keys, out)
     assert e.value.status == X.PFX_ENOKEY
+    # in place (output aliases the input), and below the top level
+    g = O.galois_element(P, 7)
+    X.pfx_rotate(pair.ctx, cx, 7, keys, cx)
+    pair.same(O.rotate(P, co, 7, {g: pair.key(g)[0]}), cx)
+    lo_o, lo_x, _ = pair.enc(P.L - 1)
+    X.pfx_rotate(pair.ctx, lo_x, -1, keys, out)
+    g = O.galois_element(P, -1)
+    pair.same(O.rotate(P, lo_o, -1, {g: pair.key(g)[0]}), out)
 
 
 def test_rotate_sum(pair, X):
