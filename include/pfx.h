@@ -249,11 +249,28 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
  *   SCALE_MUL     dst = a with scale * value (value / factor)    value
  *   ROTATE        dst = rotate(a, k)                             k
  *   ROTATE_SUM    dst = InnerSum(a) over 2^k slots               k
- * use_graph != 0 (non-NULL stream required): the first call for a given op
- * list, register set, plaintexts and keys is captured into a HIP graph and
- * launched; later calls replay it.  Register metadata (limbs, scale) after a
- * replay equals that of the captured run.
+ * `mode` is a combination of
+ *   PFX_RUN_GRAPH (non-NULL stream required): the first call for a given op
+ *     list, register set, plaintexts and keys is captured into a HIP graph and
+ *     launched; later calls replay it.  Register metadata (limbs, scale) after
+ *     a replay equals that of the captured run.
+ *   PFX_RUN_LANES: LANE markers in the list are honoured.  The first marker
+ *     LANE k (0 <= k < 8) of a fork records an event on `stream` that all of
+ *     the library's lane streams wait for, and the ops after LANE k run on
+ *     lane k; LANE -1 (or the end of the list) joins every lane back into
+ *     `stream`.  Ops on different lanes of one fork run concurrently (e.g. the
+ *     record blocks of a query), so none of them may depend on another's
+ *     registers (read-after-write, write-after-read, write-after-write):
+ *     the list is checked before anything is launched (PFX_EINVAL).  With
+ *     PFX_RUN_GRAPH the forks are captured into one multi-stream graph.
+ *     Without PFX_RUN_LANES the markers are ignored and the list runs in
+ *     program order on `stream`.
+ * Results are identical in every mode.
+ *   LANE          switch lane (see PFX_RUN_LANES)                k
  */
+#define PFX_RUN_EAGER 0
+#define PFX_RUN_GRAPH 1
+#define PFX_RUN_LANES 2
 #define PFX_OP_COPY 0
 #define PFX_OP_ADD 1
 #define PFX_OP_SUB 2
@@ -267,6 +284,7 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
 #define PFX_OP_SCALE_MUL 10
 #define PFX_OP_ROTATE 11
 #define PFX_OP_ROTATE_SUM 12
+#define PFX_OP_LANE 13
 
 typedef struct pfx_op {
     int32_t code;
@@ -279,7 +297,7 @@ typedef struct pfx_op {
 
 pfx_status pfx_run_circuit(pfx_ctx *ctx, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs,
                            size_t n_regs, size_t n_inputs, const pfx_pt *const *pts, size_t n_pts,
-                           const pfx_swk *rlk, const pfx_swk *const *gks, size_t n_gks, int use_graph,
+                           const pfx_swk *rlk, const pfx_swk *const *gks, size_t n_gks, int mode,
                            void *stream);
 
 /*

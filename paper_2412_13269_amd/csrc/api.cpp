@@ -210,40 +210,49 @@ pfx_status ws_reserve(pfx_ctx *c, hipStream_t st) {
     return get_ws(c, st, w);
 }
 
+// One op of an op list on `stream`.
+static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *regs, size_t n_regs, size_t n_inputs,
+                         const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk, const pfx_swk *const *gks,
+                         size_t n_gks, void *stream) {
+    if (o.code == PFX_OP_LANE) return PFX_OK;
+    auto R = [&](int32_t k) -> pfx_ct * { return (k >= 0 && (size_t)k < n_regs) ? regs[k] : nullptr; };
+    pfx_ct *d = R(o.dst), *A = R(o.a);
+    const std::string at = "op " + std::to_string(i) + ": ";
+    if (!d || !A) return fail(PFX_EINVAL, at + "register index out of range");
+    if ((size_t)o.dst < n_inputs) return fail(PFX_EINVAL, at + "writes an input register");
+    const pfx_pt *pt = (o.b >= 0 && (size_t)o.b < n_pts) ? pts[o.b] : nullptr;
+    pfx_status r;
+    switch (o.code) {
+        case PFX_OP_COPY: r = pfx_ct_copy(c, A, d, stream); break;
+        case PFX_OP_ADD: r = pfx_add(c, A, R(o.b), d, stream); break;
+        case PFX_OP_SUB: r = pfx_sub(c, A, R(o.b), d, stream); break;
+        case PFX_OP_MUL_PLAIN: r = pfx_mul_plain(c, A, pt, d, stream); break;
+        case PFX_OP_ADD_PLAIN: r = pfx_add_plain(c, A, pt, d, stream); break;
+        case PFX_OP_MUL_INT: r = pfx_mul_int(c, A, o.k, d, stream); break;
+        case PFX_OP_MUL_RELIN: r = pfx_mul_relin(c, A, R(o.b), rlk, d, stream); break;
+        case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
+        case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
+        case PFX_OP_MUL_CONST: r = pfx_mul_const(c, A, o.value, 0.0, d, stream); break;
+        case PFX_OP_SCALE_MUL: {
+            const double sc = A->scale * o.value;
+            r = pfx_ct_copy(c, A, d, stream);
+            if (!r) d->scale = sc;
+            break;
+        }
+        case PFX_OP_ROTATE: r = pfx_rotate(c, A, (int32_t)o.k, gks, n_gks, d, stream); break;
+        case PFX_OP_ROTATE_SUM: r = pfx_rotate_sum(c, A, (uint32_t)o.k, gks, n_gks, d, stream); break;
+        default: return fail(PFX_EINVAL, at + "unknown op code");
+    }
+    if (r) return fail(r, at + g_err);
+    return PFX_OK;
+}
+
 pfx_status run_ops(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
                    size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
                    const pfx_swk *const *gks, size_t n_gks, void *stream) {
-    auto R = [&](int32_t k) -> pfx_ct * { return (k >= 0 && (size_t)k < n_regs) ? regs[k] : nullptr; };
     for (size_t i = 0; i < n_ops; ++i) {
-        const pfx_op &o = ops[i];
-        pfx_ct *d = R(o.dst), *A = R(o.a);
-        const std::string at = "op " + std::to_string(i) + ": ";
-        if (!d || !A) return fail(PFX_EINVAL, at + "register index out of range");
-        if ((size_t)o.dst < n_inputs) return fail(PFX_EINVAL, at + "writes an input register");
-        const pfx_pt *pt = (o.b >= 0 && (size_t)o.b < n_pts) ? pts[o.b] : nullptr;
-        pfx_status r;
-        switch (o.code) {
-            case PFX_OP_COPY: r = pfx_ct_copy(c, A, d, stream); break;
-            case PFX_OP_ADD: r = pfx_add(c, A, R(o.b), d, stream); break;
-            case PFX_OP_SUB: r = pfx_sub(c, A, R(o.b), d, stream); break;
-            case PFX_OP_MUL_PLAIN: r = pfx_mul_plain(c, A, pt, d, stream); break;
-            case PFX_OP_ADD_PLAIN: r = pfx_add_plain(c, A, pt, d, stream); break;
-            case PFX_OP_MUL_INT: r = pfx_mul_int(c, A, o.k, d, stream); break;
-            case PFX_OP_MUL_RELIN: r = pfx_mul_relin(c, A, R(o.b), rlk, d, stream); break;
-            case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
-            case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
-            case PFX_OP_MUL_CONST: r = pfx_mul_const(c, A, o.value, 0.0, d, stream); break;
-            case PFX_OP_SCALE_MUL: {
-                const double sc = A->scale * o.value;
-                r = pfx_ct_copy(c, A, d, stream);
-                if (!r) d->scale = sc;
-                break;
-            }
-            case PFX_OP_ROTATE: r = pfx_rotate(c, A, (int32_t)o.k, gks, n_gks, d, stream); break;
-            case PFX_OP_ROTATE_SUM: r = pfx_rotate_sum(c, A, (uint32_t)o.k, gks, n_gks, d, stream); break;
-            default: return fail(PFX_EINVAL, at + "unknown op code");
-        }
-        if (r) return fail(r, at + g_err);
+        pfx_status r = run_op(c, i, ops[i], regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream);
+        if (r) return r;
     }
     return PFX_OK;
 }
@@ -1191,13 +1200,131 @@ pfx_status pfx_ntt(pfx_ctx *c, uint64_t *d_words, uint32_t first_prime, uint32_t
     return PFX_OK;
 }
 
+static constexpr int kLanes = 8;
+
+static pfx_status ensure_lanes(pfx_ctx *c) {
+    if ((int)c->lanes.size() == kLanes) return PFX_OK;
+    HIPCHECK(hipSetDevice(c->device));
+    for (int i = (int)c->lanes.size(); i < kLanes; ++i) {
+        hipStream_t st;
+        HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        c->lanes.push_back(st);
+    }
+    for (int i = 0; i < kLanes + 1; ++i) {
+        hipEvent_t e;
+        HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->lane_events.push_back(e);
+    }
+    return PFX_OK;
+}
+
+// Lane structure of an op list (PFX_OP_LANE markers): the caller declares which
+// ops may run concurrently.  Before any op is launched, every dependency
+// (read-after-write, write-after-read, write-after-write on registers) of an op
+// inside a fork is checked to lie on its own lane or before the fork, so that
+// the fork/join events alone order the list.
+static bool reads_b_register(int32_t code) {
+    return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN;
+}
+
+static pfx_status check_lanes(const pfx_op *ops, size_t n_ops, size_t n_regs) {
+    struct Tag {
+        int epoch = -1, lane = -1;   // fork epoch and lane of an access; lane -1 = caller stream
+    };
+    std::vector<Tag> writer(n_regs);
+    std::vector<std::vector<Tag>> readers(n_regs);
+    int epoch = 0, lane = -1;
+    auto ok = [&](const Tag &t) { return t.epoch < epoch || t.lane == -1 || t.lane == lane; };
+    for (size_t i = 0; i < n_ops; ++i) {
+        const pfx_op &o = ops[i];
+        if (o.code == PFX_OP_LANE) {
+            if (o.k < -1 || o.k >= kLanes) return fail(PFX_EINVAL, "op " + std::to_string(i) + ": lane out of range");
+            if (o.k == -1) {
+                if (lane != -1) ++epoch;
+                lane = -1;
+            } else {
+                lane = (int)o.k;
+            }
+            continue;
+        }
+        auto in_range = [&](int32_t k) { return k >= 0 && (size_t)k < n_regs; };
+        if (!in_range(o.dst) || !in_range(o.a)) continue;   // run_op reports it
+        const bool rb = reads_b_register(o.code) && in_range(o.b);
+        bool good = ok(writer[o.a]) && (!rb || ok(writer[o.b])) && ok(writer[o.dst]);
+        for (const Tag &t : readers[o.dst]) good = good && ok(t);
+        if (!good)
+            return fail(PFX_EINVAL, "op " + std::to_string(i) + " depends on an op of another lane of the same fork");
+        const Tag me{epoch, lane};
+        readers[o.a].push_back(me);
+        if (rb) readers[o.b].push_back(me);
+        writer[o.dst] = me;
+        readers[o.dst].clear();
+    }
+    return PFX_OK;
+}
+
+// The op list with its lane markers honoured: the first marker of a fork
+// records an event on `stream` that every lane waits for; LANE -1 (and the end
+// of the list) joins every lane back into `stream`.
+static pfx_status run_ops_lanes(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
+                                size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
+                                const pfx_swk *const *gks, size_t n_gks, void *stream) {
+    pfx_status r = check_lanes(ops, n_ops, n_regs);
+    if (!r) r = ensure_lanes(c);
+    for (int l = 0; l < kLanes && !r; ++l) {      // scratch of every lane before anything is enqueued or captured
+        Ws w;
+        r = get_ws(c, c->lanes[l], w);
+    }
+    if (r) return r;
+    bool forked = false;
+    void *cur = stream;
+    auto join = [&]() -> pfx_status {
+        for (int l = 0; l < kLanes; ++l) {
+            HIPCHECK(hipEventRecord(c->lane_events[l], c->lanes[l]));
+            HIPCHECK(hipStreamWaitEvent(S(stream), c->lane_events[l], 0));
+        }
+        forked = false;
+        cur = stream;
+        return PFX_OK;
+    };
+    pfx_status res = PFX_OK;
+    for (size_t i = 0; i < n_ops && !res; ++i) {
+        const pfx_op &o = ops[i];
+        if (o.code != PFX_OP_LANE) {
+            res = run_op(c, i, o, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, cur);
+            continue;
+        }
+        if (o.k == -1) {
+            if (forked) res = join();
+            continue;
+        }
+        if (!forked) {
+            HIPCHECK(hipEventRecord(c->lane_events[kLanes], S(stream)));
+            for (int l = 0; l < kLanes; ++l) HIPCHECK(hipStreamWaitEvent(c->lanes[l], c->lane_events[kLanes], 0));
+            forked = true;
+        }
+        cur = c->lanes[o.k];
+    }
+    if (forked) {            // also after a failed op
+        pfx_status rj = join();
+        if (!res) res = rj;
+    }
+    return res;
+}
+
 pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
                            size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
-                           const pfx_swk *const *gks, size_t n_gks, int use_graph, void *stream) {
+                           const pfx_swk *const *gks, size_t n_gks, int mode, void *stream) {
     REQUIRE(c && ops && regs, PFX_EINVAL, "null argument");
     REQUIRE(n_inputs <= n_regs, PFX_EINVAL, "n_inputs > n_regs");
+    REQUIRE((mode & ~(PFX_RUN_GRAPH | PFX_RUN_LANES)) == 0, PFX_EINVAL, "unknown mode bits");
     for (size_t i = 0; i < n_regs; ++i) REQUIRE(regs[i] && regs[i]->ctx == c, PFX_EINVAL, "bad register");
-    if (!use_graph) return run_ops(c, ops, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream);
+    const bool lanes = (mode & PFX_RUN_LANES) != 0;
+    auto exec = [&]() {
+        return lanes ? run_ops_lanes(c, ops, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream)
+                     : run_ops(c, ops, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream);
+    };
+    if (!(mode & PFX_RUN_GRAPH)) return exec();
     REQUIRE(stream != nullptr, PFX_EINVAL, "graph capture needs a non-default stream");
     // the graph is valid for this op list, these objects and these input shapes
     std::string key((const char *)ops, n_ops * sizeof(pfx_op));
@@ -1212,16 +1339,22 @@ pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *
     for (size_t i = 0; i < n_gks; ++i) put(&gks[i]->d_k, sizeof(double *));
     if (rlk) put(&rlk->d_k, sizeof(double *));
     put(&stream, sizeof(void *));
+    put(&mode, sizeof(int));
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         Ws w;
         pfx_status r = get_ws(c, S(stream), w);   // allocate scratch before capturing
         if (r) return r;
+        if (lanes) {
+            r = ensure_lanes(c);
+            for (int l = 0; l < kLanes && !r; ++l) r = get_ws(c, c->lanes[l], w);
+            if (r) return r;
+        }
         const bool prof = c->prof_on;
         c->prof_on = false;
         c->capturing = true;
         HIPCHECK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal));
-        r = run_ops(c, ops, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream);
+        r = exec();
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(S(stream), &g);
         c->capturing = false;
@@ -1250,24 +1383,6 @@ pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *
 }
 
 // ------------------------------------------------------------------ batched form
-static constexpr int kLanes = 8;
-
-static pfx_status ensure_lanes(pfx_ctx *c) {
-    if ((int)c->lanes.size() == kLanes) return PFX_OK;
-    HIPCHECK(hipSetDevice(c->device));
-    for (int i = (int)c->lanes.size(); i < kLanes; ++i) {
-        hipStream_t st;
-        HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        c->lanes.push_back(st);
-    }
-    for (int i = 0; i < kLanes + 1; ++i) {
-        hipEvent_t e;
-        HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        c->lane_events.push_back(e);
-    }
-    return PFX_OK;
-}
-
 static pfx_status batch_ops(pfx_ctx *const *ctxs, const pfx_ct *const *a, const pfx_ct *const *b,
                             const pfx_swk *const *rlk, pfx_ct *const *out, size_t n, bool lanes, void *stream) {
     pfx_ctx *c0 = ctxs[0];

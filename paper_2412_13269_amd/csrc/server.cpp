@@ -301,6 +301,7 @@ pfx_status pfx_server_submit(pfx_server *s, const pfx_request *rq, uint64_t *tic
     r->ops.assign(rq->ops, rq->ops + rq->n_ops);
     for (size_t i = 0; i < rq->n_ops; ++i) {
         const pfx_op &o = rq->ops[i];
+        if (o.code == PFX_OP_LANE) continue;     // run on the slot's stream, markers ignored
         REQUIRE(o.dst >= (int32_t)rq->n_inputs && (size_t)o.dst < rq->n_regs, PFX_EINVAL,
                 "op " + std::to_string(i) + ": destination is not a work register");
         REQUIRE(o.a >= 0 && (size_t)o.a < rq->n_regs, PFX_EINVAL,

@@ -45,6 +45,7 @@ class pfx_op(ctypes.Structure):
 
 OP_COPY, OP_ADD, OP_SUB, OP_MUL_PLAIN, OP_ADD_PLAIN, OP_MUL_INT, OP_MUL_RELIN = 0, 1, 2, 3, 4, 5, 6
 OP_RESCALE, OP_ADD_CONST, OP_MUL_CONST, OP_SCALE_MUL, OP_ROTATE, OP_ROTATE_SUM = 7, 8, 9, 10, 11, 12
+OP_LANE = 13
 
 
 class pfx_info(ctypes.Structure):
@@ -436,14 +437,18 @@ def pfx_mul_const(ctx, a, value: float, cscale: float, out, stream=None):
     _check(_lib.pfx_mul_const(ctx, a, value, cscale, out, _stream(stream)))
 
 
-def pfx_run_circuit(ctx, ops, regs, n_inputs: int, pts, rlk, gks, use_graph: bool = False, stream=None):
-    """ops: a sequence of (code, dst, a, b, k, value)."""
+RUN_EAGER, RUN_GRAPH, RUN_LANES = 0, 1, 2
+
+
+def pfx_run_circuit(ctx, ops, regs, n_inputs: int, pts, rlk, gks, mode: int = RUN_EAGER, stream=None):
+    """ops: a sequence of (code, dst, a, b, k, value); mode: RUN_* flags (a bool
+    selects RUN_GRAPH or RUN_EAGER)."""
     arr = (pfx_op * max(1, len(ops)))(*[pfx_op(*o) for o in ops])
     R = (ctypes.c_void_p * max(1, len(regs)))(*regs)
     Pt = (ctypes.c_void_p * max(1, len(pts)))(*pts)
     G = (ctypes.c_void_p * max(1, len(gks)))(*gks)
     _check(_lib.pfx_run_circuit(ctx, arr, len(ops), R, len(regs), n_inputs, Pt, len(pts), rlk, G, len(gks),
-                                int(use_graph), _stream(stream)))
+                                int(mode), _stream(stream)))
 
 
 def pfx_batch_mul_relin_rescale(ctxs, a, b, rlks, outs, mode: int, stream=None):

@@ -18,7 +18,17 @@ slot-domain linear score): for each block b of 2^(logN-1) records
 
 Inputs (registers, read-only): W[0..A), C[0..D], T, H.  Plaintexts: X[b][a]
 at index b * A + a.  The op list and the register allocation are built here;
-the library executes them (eagerly, or captured once into a HIP graph).
+the library executes them (eagerly, or captured once into a HIP graph; on one
+stream, or scheduled over its lane streams by register dependencies).
+
+Register allocation: temporaries are recycled through a free list.  With
+parallel=False one list serves the whole circuit (fewest registers: the
+smallest HBM footprint, the natural choice on one stream).  With
+parallel=True every record block recycles only its own registers, block b is
+preceded by a LANE (b mod lanes) marker and the sum of the blocks by LANE -1,
+so that with PFX_RUN_LANES the blocks run concurrently on the library's lane
+streams (more registers, more concurrency); without it the markers are
+ignored.
 """
 from __future__ import annotations
 
@@ -34,6 +44,8 @@ class QueryPlan:
     degree: int = 7
     stages: int = 3
     log_slots: int = 15
+    parallel: bool = False
+    lanes: int = 4
     ops: list = field(default_factory=list)
     n_regs: int = 0
     out: int = -1
@@ -50,6 +62,8 @@ class QueryPlan:
         self._next = self.n_inputs
         self._build()
         self.n_regs = self._next
+
+
 
     # register allocation
     def _new(self) -> int:
@@ -118,14 +132,26 @@ class QueryPlan:
         return u
 
     def _build(self):
-        total = None
-        for b in range(self.n_blocks):
-            u = self._block(b)
-            if total is None:
-                total = u
-            else:
+        if self.parallel:
+            us = []
+            for b in range(self.n_blocks):
+                self._free = []     # every block recycles only its own registers
+                self._op(X.OP_LANE, 0, 0, k=b % self.lanes)
+                us.append(self._block(b))
+            self._op(X.OP_LANE, 0, 0, k=-1)
+            self._free = []
+            total = us[0]
+            for u in us[1:]:
                 self._op(X.OP_ADD, total, total, u)
-                self._drop(u)
+        else:
+            total = None
+            for b in range(self.n_blocks):
+                u = self._block(b)
+                if total is None:
+                    total = u
+                else:
+                    self._op(X.OP_ADD, total, total, u)
+                    self._drop(u)
         self.out = self._new()
         self._op(X.OP_ROTATE_SUM, self.out, total, k=self.log_slots)
         self._drop(total)

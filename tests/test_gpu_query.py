@@ -45,7 +45,7 @@ def gap_records(x, w, c, t, eta, gap, seed):
 class Setup:
     """Library objects for one query; oracle twins built only when asked."""
 
-    def __init__(self, X, logn, n_blocks, seed, gap=None, with_oracle=False, degree=7):
+    def __init__(self, X, logn, n_blocks, seed, gap=None, with_oracle=False, degree=7, parallel=False):
         from paper_2412_13269_amd.query import QueryPlan
         self.X = X
         self.logn, self.N, self.n = logn, 1 << logn, 1 << (logn - 1)
@@ -58,7 +58,7 @@ class Setup:
             c = np.concatenate([c, np.zeros(max(0, D + 1 - len(c)))])[:D + 1]
             self.x = gap_records(self.x, w, c, t, eta, gap, seed)
         self.params = (w, c, t, eta)
-        self.plan = QueryPlan(n_blocks, A, D, 3, logn - 1)
+        self.plan = QueryPlan(n_blocks, A, D, 3, logn - 1, parallel=parallel)
         prm = X.make_params(logn, QB, PB, ALPHA, ML)
         self.ctx = X.pfx_ctx_create(prm, 0)
         q, p, _ = X.pfx_ctx_moduli(self.ctx, len(QB), len(PB))
@@ -101,10 +101,11 @@ class Setup:
                 self.pts.append(X.pfx_pt_import(self.ctx, m, DELTA))
         self.stream = X.pfx_stream_create(self.ctx)
 
-    def run(self, graph=False):
+    def run(self, graph=False, lanes=False):
         X = self.X
+        mode = (X.RUN_GRAPH if graph else 0) | (X.RUN_LANES if lanes else 0)
         X.pfx_run_circuit(self.ctx, self.plan.ops, self.regs, self.plan.n_inputs, self.pts, self.rlk, self.gks,
-                          graph, self.stream)
+                          mode, self.stream)
         X.pfx_sync(self.ctx, self.stream)
         return self.regs[self.plan.out]
 
@@ -158,6 +159,37 @@ def test_query_words_match_oracle_eager_and_graph(X):
         S.close()
 
 
+def test_query_on_lanes_matches_oracle(X):
+    # parallel plan (one lane per record block, fork/join), eager and one
+    # captured multi-stream graph, replays checked between eager runs
+    S = Setup(X, 12, 3, 37, with_oracle=True, parallel=True)
+    try:
+        want = S.oracle_out()
+        for graph, lanes in ((False, True), (True, True), (False, False), (True, True), (False, True), (True, True)):
+            out = S.run(graph=graph, lanes=lanes)
+            assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), want.c), (graph, lanes)
+            assert X.pfx_ct_info(out).scale == want.scale
+    finally:
+        S.close()
+
+
+def test_lane_markers_with_cross_lane_dependency_are_rejected(X):
+    S = Setup(X, 12, 1, 39)
+    try:
+        w0, t0, t1 = 0, S.plan.n_inputs, S.plan.n_inputs + 1
+        bad = [(X.OP_LANE, 0, 0, -1, 0, 0.0), (X.OP_MUL_PLAIN, t0, w0, 0, 0, 0.0),
+               (X.OP_LANE, 0, 0, -1, 1, 0.0), (X.OP_ADD, t1, t0, t0, 0, 0.0)]
+        with pytest.raises(X.PfxError) as e:
+            X.pfx_run_circuit(S.ctx, bad, S.regs, S.plan.n_inputs, S.pts, S.rlk, S.gks, X.RUN_LANES, S.stream)
+        assert e.value.status == X.PFX_EINVAL
+        good = bad[:2] + [(X.OP_LANE, 0, 0, -1, -1, 0.0)] + bad[3:]      # join first: fine
+        X.pfx_run_circuit(S.ctx, good, S.regs, S.plan.n_inputs, S.pts, S.rlk, S.gks, X.RUN_LANES, S.stream)
+        X.pfx_run_circuit(S.ctx, good, S.regs, S.plan.n_inputs, S.pts, S.rlk, S.gks, X.RUN_EAGER, S.stream)
+        X.pfx_sync(S.ctx, S.stream)
+    finally:
+        S.close()
+
+
 @pytest.mark.parametrize("degree", [3, 15])
 def test_query_degrees_match_oracle(X, degree):
     S = Setup(X, 12, 1, 33 + degree, with_oracle=True, degree=degree)
@@ -173,9 +205,11 @@ def test_query_degrees_match_oracle(X, degree):
 
 def test_full_size_query_count(X):
     # 2^17 records x 8 attributes at N = 2^16 (4 blocks of 2^15 slots)
-    S = Setup(X, 16, 4, 41)
+    S = Setup(X, 16, 4, 41, parallel=True)
     try:
-        out = S.run(graph=True)
+        ref = X.pfx_ct_export(S.ctx, S.run(graph=False), S.N)
+        out = S.run(graph=True, lanes=True)
+        assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), ref)
         got = S.count(out)
         step, count = Q.fp64_query(S.x, *S.params)
         assert abs(got[0] - count) < 0.25
