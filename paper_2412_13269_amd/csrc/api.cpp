@@ -1011,19 +1011,9 @@ pfx_status pfx_rescale(pfx_ctx *c, const pfx_ct *a, pfx_ct *out, void *stream) {
     const size_t N = c->N;
     const int np = a->degree + 1;
     double *last = w.at(w.lay.rs_last), *tmp = w.at(w.lay.rs_tmp);
-    // INTT of the last limbs, written compactly into `last` (out-of-place)
-    for (int k = 0; k < np; ++k) {
-        LimbMap one;
-        one.n = 1;
-        one.off[0] = 0;
-        one.pid[0] = (int16_t)(lv - 1);
-        launch_ntt(L, last + (size_t)k * N, a->poly(k) + (size_t)(lv - 1) * N, one, true);
-    }
-    launch_rescale_spread(L, tmp, last, np, lv);
-    launch_ntt(L, tmp, nullptr, poly_map(np, lv - 1, lv - 1), false);
     const double sc = a->scale / (double)c->primes[lv - 1];
     const uint32_t deg = a->degree;
-    launch_rescale_final(L, out->d, a->d, tmp, out->cap_limbs * N, a->cap_limbs * N, np, lv);
+    launch_rescale(L, out->d, out->cap_limbs * N, a->d, a->cap_limbs * N, np, lv, last, tmp);
     out->n_limbs = lv - 1;
     out->degree = deg;
     out->scale = sc;

@@ -199,12 +199,13 @@ void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const do
                    const double *a1, const double *b0, const double *b1, int nl);
 void launch_automorph(const Launch &L, double *out, const double *in, size_t so, size_t si, int npoly,
                       int nl, uint32_t g);
-void launch_rescale_spread(const Launch &L, double *tmp, const double *lastc, int npoly, int lv);
-void launch_rescale_final(const Launch &L, double *out, const double *in, const double *tmp, size_t so,
-                          size_t si, int npoly, int lv);
 // galois != 0: d_ntt is read through the NTT-domain permutation of phi_galois.
 void launch_ks_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt,
                      const double *key, int lv, uint32_t galois);
+// Rescale of np polynomials of lv limbs (rescale.hip): in/out poly strides in
+// doubles, `last` (np limbs) and `tmp` (np (lv - 1) limbs) scratch.
+void launch_rescale(const Launch &L, double *out, size_t so, const double *in, size_t si, int np, int lv,
+                    double *last, double *tmp);
 // Fused key-switching steps (keyswitch.hip).
 void launch_intt_scale(const Launch &L, double *dcoef, const double *d, int lv, uint32_t galois);
 void launch_modup_col(const Launch &L, double *ext, const double *dcoef, int lv);

@@ -326,69 +326,6 @@ void launch_automorph(const Launch &L, double *out, const double *in, size_t so,
     prof_end(L, "automorph", ev, 16.0 * (double)total);
 }
 
-// ============================================================== rescale (Sec. 2.5)
-// c'_i = (c_i + h - [c_last + h]_{q_last}) * q_last^-1 mod q_i, h = floor(q_last/2):
-// round-half-up division of the [0, Q) lift by the last prime.  h is added to
-// every coefficient, so it joins the correction t_i = [c_last + h]_{q_last} - h
-// in the coefficient domain; the NTT-domain update is then c'_i = (c_i - NTT(t)_i) q_last^-1.
-__global__ void k_rescale_spread(double *tmp, const double *lastc, int npoly, int lv, int logn, const PrimeDev *pr,
-                                 const RescaleConst *rc) {
-    const int nout = lv - 1;
-    const size_t total = ((size_t)npoly * nout) << logn;
-    const size_t mask = ((size_t)1 << logn) - 1;
-    const double ql = pr[lv - 1].q;
-    const double h = __builtin_floor(ql * 0.5);
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t c = idx & mask;
-        const size_t li = idx >> logn;
-        const int i = (int)(li % nout);
-        const int k = (int)(li / nout);
-        const double x = madd(lastc[((size_t)k << logn) + c], h, ql);
-        const double qi = pr[i].q;
-        tmp[idx] = msub(mred(x, qi, pr[i].qinv), rc[(lv - 1) * PFX_MAX_PRIMES + i].half, qi);
-    }
-}
-
-__global__ void k_rescale_final(double *out, const double *in, const double *tmp, size_t so, size_t si, int npoly,
-                                int lv, int logn, const PrimeDev *pr, const RescaleConst *rc) {
-    const int nout = lv - 1;
-    const size_t total = ((size_t)npoly * nout) << logn;
-    const size_t mask = ((size_t)1 << logn) - 1;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t c = idx & mask;
-        const size_t li = idx >> logn;
-        const int i = (int)(li % nout);
-        const int k = (int)(li / nout);
-        const double q = pr[i].q;
-        const RescaleConst r = rc[(lv - 1) * PFX_MAX_PRIMES + i];
-        const double x = msub(in[k * si + ((size_t)i << logn) + c], tmp[idx], q);
-        out[k * so + ((size_t)i << logn) + c] = mmulc(x, r.inv.x, r.inv.y, q);
-    }
-}
-
-void launch_rescale_spread(const Launch &L, double *tmp, const double *lastc, int npoly, int lv) {
-    const size_t total = ((size_t)npoly * (lv - 1)) << L.ctx->logn;
-    hipEvent_t ev;
-    prof_begin(L, "rescale_spread", &ev);
-    k_rescale_spread<<<grid_for(total), 256, 0, L.st>>>(tmp, lastc, npoly, lv, L.ctx->logn, L.ctx->d_primes,
-                                                        L.ctx->d_rescale);
-    HIP_LAUNCH_CHECK();
-    prof_end(L, "rescale_spread", ev, 8.0 * (double)L.ctx->N * npoly * lv);
-}
-
-void launch_rescale_final(const Launch &L, double *out, const double *in, const double *tmp, size_t so, size_t si,
-                          int npoly, int lv) {
-    const size_t total = ((size_t)npoly * (lv - 1)) << L.ctx->logn;
-    hipEvent_t ev;
-    prof_begin(L, "rescale_final", &ev);
-    k_rescale_final<<<grid_for(total), 256, 0, L.st>>>(out, in, tmp, so, si, npoly, lv, L.ctx->logn,
-                                                       L.ctx->d_primes, L.ctx->d_rescale);
-    HIP_LAUNCH_CHECK();
-    prof_end(L, "rescale_final", ev, 24.0 * (double)total);
-}
-
 // ============================================================== key switching (Sec. 2.4.1)
 // Workspace layouts at level lv (E = lv + K limbs per extended polynomial):
 //   ext[j][t][c]  digit j's fast conversion to the E - sz_j primes outside the

@@ -234,18 +234,6 @@ __global__ __launch_bounds__(TH) void k_intt_special(const KsArgs a, double *__r
 }
 
 // ----------------------------------------------------------------- launchers
-#define PFX_SWITCH_S(S_, CALL)                                   \
-    switch (S_) {                                                \
-        case 2: { constexpr int SS = 2; CALL; } break;           \
-        case 3: { constexpr int SS = 3; CALL; } break;           \
-        case 4: { constexpr int SS = 4; CALL; } break;           \
-        case 5: { constexpr int SS = 5; CALL; } break;           \
-        case 6: { constexpr int SS = 6; CALL; } break;           \
-        case 7: { constexpr int SS = 7; CALL; } break;           \
-        case 8: { constexpr int SS = 8; CALL; } break;           \
-        default: set_error("unsupported NTT pass size"); break;  \
-    }
-
 // Term count of a conversion kernel: n rounded up to 1, 2, 4 or 8.
 #define PFX_SWITCH_NT(n_, CALL)                                          \
     switch ((n_) <= 1 ? 1 : (n_) <= 2 ? 2 : (n_) <= 4 ? 4 : 8) {         \

@@ -396,6 +396,19 @@ inline int pass_threads(int logn, int limbs, bool row) {
     return (!row || limbs * col_shape(logn).tiles >= 2048) ? 256 : 128;
 }
 
+// Stages of a pass (log N / 2 or the rest) as a compile-time constant SS.
+#define PFX_SWITCH_S(S_, CALL)                                   \
+    switch (S_) {                                                \
+        case 2: { constexpr int SS = 2; CALL; } break;           \
+        case 3: { constexpr int SS = 3; CALL; } break;           \
+        case 4: { constexpr int SS = 4; CALL; } break;           \
+        case 5: { constexpr int SS = 5; CALL; } break;           \
+        case 6: { constexpr int SS = 6; CALL; } break;           \
+        case 7: { constexpr int SS = 7; CALL; } break;           \
+        case 8: { constexpr int SS = 8; CALL; } break;           \
+        default: set_error("unsupported NTT pass size"); break;  \
+    }
+
 #define PFX_SWITCH_TH(th_, CALL)                                   \
     switch (th_) {                                                 \
         case 128: { constexpr int TH = 128; CALL; } break;         \
