@@ -58,7 +58,7 @@ def cpu_baseline(q, p):
         cts.append(O.encrypt(P, s, m, I.uniform_residues(P.q, N, seed + 10), I.gaussian_error(N, seed + 20), SCALE))
     t0 = time.perf_counter()
     ops = 0
-    while ops == 0 or time.perf_counter() - t0 < 8.0:    # whole (HMult+relin, rotation) pairs, ~8-10 s
+    while ops == 0 or time.perf_counter() - t0 < 10.0:   # whole (HMult+relin, rotation) pairs, ~10-12 s
         O.mul_relin(P, cts[0], cts[1], rlk)
         O.rotate(P, cts[0], 1, {g: gk})
         ops += 2
@@ -311,6 +311,12 @@ def main():
         X.pfx_mul_relin(ctx, cts[0], cts[1], rlk, prod, st)
         X.pfx_rescale(ctx, prod, prod, st)
     per_op["rescale_us"] = op_time(resc) - per_op["mul_relin_us"]
+    # the boundary's host interchange (PCIe-inclusive): canonical words of one
+    # ciphertext, 2 x 24 limbs = 24 MiB, host -> device and back
+    words = I.uniform_residues(q, N, 9, lead=(2,))
+    per_op["ct_import_host_us"] = op_time(lambda: X.pfx_ct_import(ctx, words, SCALE, rot, st), reps=5)
+    per_op["ct_export_host_us"] = op_time(lambda: X.pfx_ct_export(ctx, rot, N, st), reps=5)
+    per_op["ct_interchange_bytes"] = int(words.nbytes)
 
     # ---- private query: 2^17 records x 8 attributes, degree-7 score polynomial,
     # (7,7,7) composite sign, InnerSum count; keys as above (resident)

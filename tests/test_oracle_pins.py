@@ -410,3 +410,30 @@ def test_homomorphic_ops_track_fp64():
     mp = O.ct_mul_plain(P, c1, pm, delta)
     assert np.max(np.abs(dec(mp) - z1 * z2)) < 2 ** -20
     assert np.max(np.abs(dec(O.ct_mul_int(P, c1, -3)) - (-3 * z1))) < 2 ** -20
+
+
+def test_prime_rule_reproduces_the_parameter_sets_of_tab1():
+    """tests/golden/tab1_parameter_sets.json: Tab. 1 prints log(QP) and its split
+    into prime sizes; the chain rule must give distinct NTT-friendly primes whose
+    sizes add up to the printed total, and the secret generator the printed h."""
+    import json
+    import math
+    import os
+    from paper_2412_13269_amd import inputs as I
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tab1_parameter_sets.json")))
+    for st in g["sets"]:
+        n = 1 << st["log_n"]
+        assert sum(st["q_bits"]) + sum(st["p_bits"]) == st["log_qp"], st["name"]
+        q, p = O.gen_primes(st["log_n"] + 1, st["q_bits"], st["p_bits"])
+        chain = q + p
+        assert len(set(chain)) == len(chain)
+        for c, b in zip(chain, st["q_bits"] + st["p_bits"]):
+            assert O.is_prime(c) and (c - 1) % (2 * n) == 0
+            assert abs(math.log2(c) - b) < 0.01, (st["name"], b, c)
+        assert abs(sum(math.log2(c) for c in chain) - st["log_qp"]) < 0.5
+        s = I.ternary_secret(n, None if st["h"] == "2N/3" else st["h"], 7)
+        nz = int(np.count_nonzero(s))
+        if st["h"] == "2N/3":
+            assert abs(nz - 2 * n / 3) < 4 * math.sqrt(n)
+        else:
+            assert nz == st["h"]
