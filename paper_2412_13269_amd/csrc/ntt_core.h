@@ -50,6 +50,18 @@ struct NttTile {
 };
 constexpr int kNttLds = NttTile<kNttThreads>::lds;
 
+// Twiddle tables live in device global memory; their pointers are read from
+// the PrimeDev records, so without this the compiler would emit generic (flat)
+// loads for them.
+typedef const __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ const gdouble *as_global(const double *p) { return (const gdouble *)p; }
+// A table of (w, fl(w/q)) pairs in global memory.
+struct GTw {
+    const gdouble *p;
+    __device__ __forceinline__ double2 operator[](int i) const { return make_double2(p[2 * i], p[2 * i + 1]); }
+};
+__device__ __forceinline__ GTw as_global(const double2 *p) { return GTw{(const gdouble *)p}; }
+
 // Automorphism phi_g: X -> X^g (g odd) in the NTT domain.  Slot j holds
 // a(psi^e) with e = 2 bitrev(j) + 1, and phi_g(a)(psi^e) = a(psi^(g e)), so
 // phi_g(a)[j] = a[galois_src(j)] with 2 bitrev(galois_src(j)) + 1 = g e mod 2N.
@@ -70,24 +82,28 @@ __device__ __forceinline__ uint32_t galois_src(uint32_t j, int logn, uint32_t g)
 // [-q/2, q/2]; the last pass of a transform canonicalises to [0, q).
 
 // Forward butterflies of NST consecutive stages on the E = 2^NST elements of
-// one register group; gidx(u) is the global index of element u; stage kk of the
-// group is global stage s0 + kk.
-template <int NST, class Gidx>
-__device__ __forceinline__ void fwd_group(double *v, int s0, int logn, const double2 *__restrict__ tw, double q,
-                                          double qinv, Gidx &&gidx) {
+// one register group.  At stage kk of the group the butterflies come in 2^kk
+// runs x = u >> (NST - kk) that share one twiddle; twf(kk, x) returns it (w,
+// fl(w/q)), each exactly once per group.  The pass code below gives twf in
+// closed form (for the first round of a column pass the index is a
+// compile-time constant, so the twiddles are uniform scalar loads).
+template <int NST, class Twf>
+__device__ __forceinline__ void fwd_group(double *v, double q, double qinv, Twf &&twf) {
     constexpr int E = 1 << NST;
 #pragma unroll
     for (int kk = 0; kk < NST; ++kk) {
-        const int s = s0 + kk;
         const int h = 1 << (NST - 1 - kk);
 #pragma unroll
-        for (int u = 0; u < E; ++u) {
-            if (u & h) continue;
-            const double2 w = tw[(1 << s) + (gidx(u) >> (logn - s))];
-            const double T = mmulc_lazy(v[u + h], w.x, w.y, q);
-            const double U = v[u];
-            v[u] = U + T;
-            v[u + h] = U - T;
+        for (int x = 0; x < (1 << kk); ++x) {
+            const double2 w = twf(kk, x);
+#pragma unroll
+            for (int lo = 0; lo < h; ++lo) {
+                const int u = (x << (NST - kk)) | lo;
+                const double T = mmulc_lazy(v[u + h], w.x, w.y, q);
+                const double U = v[u];
+                v[u] = U + T;
+                v[u + h] = U - T;
+            }
         }
         if ((kk & 1) || kk == NST - 1) {
 #pragma unroll
@@ -96,28 +112,30 @@ __device__ __forceinline__ void fwd_group(double *v, int s0, int logn, const dou
     }
 }
 
-// Inverse butterflies, stages s0 + NST - 1 down to s0.  If `last` is set the
-// group contains global stage 0 and N^-1 is folded into that stage's outputs.
-template <int NST, class Gidx>
-__device__ __forceinline__ void inv_group(double *v, int s0, int logn, const double2 *__restrict__ tw,
-                                          const PrimeDev &P, bool last, Gidx &&gidx) {
+// Inverse butterflies, group stages NST - 1 down to 0 (twiddles as above).
+// With `last` the group's stage 0 is global stage 0 and N^-1 is folded into it.
+template <int NST, class Twf>
+__device__ __forceinline__ void inv_group(double *v, const PrimeDev &P, bool last, Twf &&twf) {
     constexpr int E = 1 << NST;
     const double q = P.q, qinv = P.qinv;
 #pragma unroll
     for (int kk = NST - 1; kk >= 0; --kk) {
-        const int s = s0 + kk;
         const int h = 1 << (NST - 1 - kk);
 #pragma unroll
-        for (int u = 0; u < E; ++u) {
-            if (u & h) continue;
-            const double U = v[u], V = v[u + h];
-            if (last && s == 0) {
-                v[u] = mmulc_lazy(U + V, P.ninv, P.ninv_q, q);
-                v[u + h] = mmulc_lazy(U - V, P.ninv_w1, P.ninv_w1_q, q);
-            } else {
-                const double2 w = tw[(1 << s) + (gidx(u) >> (logn - s))];
-                v[u] = mred_signed(U + V, q, qinv);
-                v[u + h] = mmulc_lazy(U - V, w.x, w.y, q);
+        for (int x = 0; x < (1 << kk); ++x) {
+            double2 w = make_double2(0.0, 0.0);
+            if (!(last && kk == 0)) w = twf(kk, x);
+#pragma unroll
+            for (int lo = 0; lo < h; ++lo) {
+                const int u = (x << (NST - kk)) | lo;
+                const double U = v[u], V = v[u + h];
+                if (last && kk == 0) {
+                    v[u] = mmulc_lazy(U + V, P.ninv, P.ninv_q, q);
+                    v[u + h] = mmulc_lazy(U - V, P.ninv_w1, P.ninv_w1_q, q);
+                } else {
+                    v[u] = mred_signed(U + V, q, qinv);
+                    v[u + h] = mmulc_lazy(U - V, w.x, w.y, q);
+                }
             }
         }
     }
@@ -134,7 +152,7 @@ __device__ __forceinline__ void inv_group(double *v, int s0, int logn, const dou
 // within 1.25 q (|a| <= 2^51) or 0.875 q (|a| <= q); the two-stage growth
 // stays below 3.2 q < 2^52.
 template <int NST>
-__device__ __forceinline__ void row_twiddle_bases(double *B, const double *__restrict__ rtw, int P, double q,
+__device__ __forceinline__ void row_twiddle_bases(double *B, const gdouble *__restrict__ rtw, int P, double q,
                                                   double qinv) {
     B[NST - 1] = rtw[P];
 #pragma unroll
@@ -201,7 +219,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
     constexpr int IT1 = kSlots / E1, IT2 = kSlots / E2;
     const int lo = logn - S;
     const double q = P.q;
-    const double2 *__restrict__ tw = INV ? P.itw : P.tw;
+    const GTw tw = as_global(INV ? P.itw : P.tw);
     const int n1 = C << (S - R1), n2 = C << R1;
     auto gidx = [&](int c, int mid) { return (mid << lo) | (cbase + c); };
     if (!INV) {
@@ -214,7 +232,8 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
                 double v[E1];
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
-                fwd_group<R1>(v, 0, logn, tw, q, P.qinv, gu);
+                // stage kk < R1: index 2^kk + (mid >> (S - kk)) = 2^kk + x (ml shifts out)
+                fwd_group<R1>(v, q, P.qinv, [&](int kk, int x) { return tw[(1 << kk) + x]; });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) lds[((u << (S - R1)) | ml) * C + c] = v[u];
             }
@@ -229,7 +248,8 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
                 double v[E2];
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = lds[((mh << R2) | u) * C + c];
-                fwd_group<R2>(v, R1, logn, tw, q, P.qinv, gu);
+                // stage R1 + kk: mid >> (R2 - kk) = (mh << kk) | x
+                fwd_group<R2>(v, q, P.qinv, [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
 #pragma unroll
                 for (int u = 0; u < E2; ++u) store(gu(u), v[u], gi * E2 + u);
             }
@@ -244,7 +264,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
                 double v[E2];
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = load(gu(u), gi * E2 + u);
-                inv_group<R2>(v, R1, logn, tw, P, false, gu);
+                inv_group<R2>(v, P, false, [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
 #pragma unroll
                 for (int u = 0; u < E2; ++u) lds[((mh << R2) | u) * C + c] = v[u];
             }
@@ -259,7 +279,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
                 double v[E1];
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = lds[((u << (S - R1)) | ml) * C + c];
-                inv_group<R1>(v, 0, logn, tw, P, true, gu);
+                inv_group<R1>(v, P, true, [&](int kk, int x) { return tw[(1 << kk) + x]; });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) store(gu(u), mcanon(v[u], q), gi * E1 + u);
             }
@@ -283,7 +303,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
     constexpr int PAD = R + R / 16;
     const int s0 = logn - S;
     const double q = P.q;
-    const double2 *__restrict__ tw = INV ? P.itw : P.tw;
+    const GTw tw = as_global(INV ? P.itw : P.tw);
     const int n1 = C << (S - R1), n2 = C << R1;
     const int tot = C * R;
     const int base = cbase << S;
@@ -299,7 +319,9 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
                 double v[E1];
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
-                fwd_group<R1>(v, s0, logn, tw, q, P.qinv, gu);
+                // stage s0 + kk: gidx >> (S - kk) = ((cbase + c) << kk) | x
+                fwd_group<R1>(v, q, P.qinv,
+                              [&](int kk, int x) { return tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)]; });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) lds[lidx(c, (u << (S - R1)) | ml)] = v[u];
             }
@@ -313,7 +335,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
                 double v[E2], B[R2];
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
-                row_twiddle_bases<R2>(B, P.rtw, ((cbase + c) << R1) | mh, q, P.qinv);
+                row_twiddle_bases<R2>(B, as_global(P.rtw), ((cbase + c) << R1) | mh, q, P.qinv);
                 fwd_group_gen<R2>(v, B, P.rc, q, P.qinv);
 #pragma unroll
                 for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
@@ -340,7 +362,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
                 double v[E2], B[R2];
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
-                row_twiddle_bases<R2>(B, P.irtw, ((cbase + c) << R1) | mh, q, P.qinv);
+                row_twiddle_bases<R2>(B, as_global(P.irtw), ((cbase + c) << R1) | mh, q, P.qinv);
                 inv_group_gen<R2>(v, B, P.irc, q, P.qinv);
 #pragma unroll
                 for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
@@ -356,7 +378,8 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
                 double v[E1];
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = lds[lidx(c, (u << (S - R1)) | ml)];
-                inv_group<R1>(v, s0, logn, tw, P, false, gu);
+                inv_group<R1>(v, P, false,
+                              [&](int kk, int x) { return tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)]; });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) store(gu(u), v[u], gi * E1 + u);
             }
