@@ -334,8 +334,10 @@ void launch_automorph(const Launch &L, double *out, const double *in, size_t so,
 // acc_u[m] = sum_j dtilde_j[m] * swk_{j,u}[m]   (NTT domain).  The digit's own
 // primes take d itself; with GAL, d is phi_g(d_in) read through galois_src.
 template <bool GAL>
-__global__ void k_ks_inner(double *acc, const double *ext, const double *d_ntt, const double *key, int lv, int logn,
-                           int L, int K, int alpha, const PrimeDev *pr, uint32_t g) {
+__global__ __launch_bounds__(256) void k_ks_inner(double *acc, const double *ext, const double *d_ntt,
+                                                  const double *key, int lv, int logn, int L, int K, int alpha,
+                                                  const PrimeDev *pr, uint32_t g) {
+    constexpr int kChunk = 4;   // digits whose 3 loads are all in flight before any product
     const int m = blockIdx.y;
     const size_t N = (size_t)1 << logn;
     const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -343,25 +345,40 @@ __global__ void k_ks_inner(double *acc, const double *ext, const double *d_ntt, 
     const int E = lv + K;
     const int beta = (lv + alpha - 1) / alpha;
     const int pid = m < lv ? m : L + (m - lv);
-    const int km = pid;
     const double q = pr[pid].q, qi = pr[pid].qinv;
     const size_t kstride = (size_t)(L + K) * N;
+    const double *k0 = key + ((size_t)pid << logn) + c;
+    const double *dm = d_ntt + ((size_t)m << logn) + (GAL ? galois_src((uint32_t)c, logn, g) : c);
+    // products in [0, q) summed lazily; a chunk leaves a < q + 4q < 2^53, which
+    // mred reduces exactly (its quotient estimate is off by at most one there)
     double a0 = 0.0, a1 = 0.0;
-    for (int j = 0; j < beta; ++j) {
-        const int j0 = j * alpha;
-        const int sz = min(alpha, lv - j0);
-        double x;
-        if (m >= j0 && m < j0 + sz) {
-            const size_t cs = GAL ? galois_src((uint32_t)c, logn, g) : c;
-            x = d_ntt[((size_t)m << logn) + cs];
-        } else {
-            const int t = m < j0 ? m : m - sz;
-            x = ext[((size_t)j * E + t) * N + c];
+    for (int jb = 0; jb < beta; jb += kChunk) {
+        double x[kChunk], w0[kChunk], w1[kChunk];
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) {
+            const int j = jb + t;
+            if (j < beta) {
+                const int j0 = j * alpha;
+                const int sz = min(alpha, lv - j0);
+                if (m >= j0 && m < j0 + sz) {
+                    x[t] = *dm;
+                } else {
+                    const int tt = m < j0 ? m : m - sz;
+                    x[t] = ext[((size_t)j * E + tt) * N + c];
+                }
+                w0[t] = k0[(size_t)(2 * j) * kstride];
+                w1[t] = k0[(size_t)(2 * j + 1) * kstride];
+            }
         }
-        const double k0 = key[(size_t)(2 * j) * kstride + ((size_t)km << logn) + c];
-        const double k1 = key[(size_t)(2 * j + 1) * kstride + ((size_t)km << logn) + c];
-        a0 = madd(a0, mmul(x, k0, q, qi), q);
-        a1 = madd(a1, mmul(x, k1, q, qi), q);
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) {
+            if (jb + t < beta) {
+                a0 += mmul(x[t], w0[t], q, qi);
+                a1 += mmul(x[t], w1[t], q, qi);
+            }
+        }
+        a0 = mred(a0, q, qi);
+        a1 = mred(a1, q, qi);
     }
     acc[((size_t)m << logn) + c] = a0;
     acc[((size_t)(E + m) << logn) + c] = a1;

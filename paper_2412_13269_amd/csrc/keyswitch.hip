@@ -314,7 +314,8 @@ void launch_modup_col(const Launch &L, double *ext, const double *dcoef, int lv)
 
 void launch_intt_special(const Launch &L, double *acc, int lv) {
     KsArgs a = ks_args(L.ctx, lv);
-    constexpr int th = 128, tc = 256;
+    const int th = pass_threads(a.logn, 2 * a.K, true);
+    constexpr int tc = 256;
     PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
     widen_grid(pr, pc, 2 * a.K);
     hipEvent_t ev;
@@ -322,7 +323,7 @@ void launch_intt_special(const Launch &L, double *acc, int lv) {
     a.tiles = pr.tiles;
     a.n = 2 * a.K * a.tiles;
     prof_begin(L, "ks_intt_special_row", &ev);
-    PFX_SWITCH_S(pr.S, (k_intt_special<SS, true, th><<<xcd_grid(a.n), th, 0, L.st>>>(a, acc)));
+    PFX_SWITCH_TH(th, PFX_SWITCH_S(pr.S, (k_intt_special<SS, true, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, acc))));
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_intt_special_row", ev, 16.0 * (double)L.ctx->N * 2 * a.K);
     a.C = pc.C;

@@ -55,7 +55,10 @@ __device__ __forceinline__ double mmulc(double a, double w, double wq, double q)
     return r < 0.0 ? r + q : r;
 }
 
-// x mod q for an integer 0 <= x < 2^50 (x may exceed q by any factor).
+// x mod q for an integer 0 <= x < 2^50 (x may exceed q by any factor), and for
+// 0 <= x < 8q < 2^53: fl(x * qinv) is then within 2^-50 of x/q < 8, so the floor
+// is off by at most one, fma(-c, q, x) is an exact small integer, and the two
+// corrections land it in [0, q).
 __device__ __forceinline__ double mred(double x, double q, double qinv) {
     double c = __builtin_floor(x * qinv);
     double r = __builtin_fma(-c, q, x);
