@@ -14,7 +14,9 @@ Prints one JSON line.  `roofline` is for the kernel with the largest device
 time in the timed region, from HIP events the library records around each of
 its launches on the stream it launches on; `achieved` is the kernel's
 algorithmic bytes (each launch's minimal operand reads and writes) over its
-device time.  `cpu_baseline` times the CPU oracle on HMult + relin and rotation pairs
+device time; `traffic` is its measured HBM bytes per launch (rocprofv3
+FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy kernel) from the committed
+summary under profiles/, null if the kernel's sources changed since.  `cpu_baseline` times the CPU oracle on HMult + relin and rotation pairs
 of the same workload for about ten seconds.
 """
 from __future__ import annotations
@@ -39,6 +41,30 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# sources that define a profiled kernel (their hash ties a committed counter
+# measurement to the code it was taken on)
+_KERNEL_SOURCES = {"ks_inner": ["kernels.hip", "modarith.h", "ntt_core.h", "internal.h"]}
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (profiles/<kernel>_n16_l24_hbm_traffic.md), or None when
+    there is none or the kernel's sources have changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_n16_l24_hbm_traffic.md")
+    if kernel not in _KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    m = re.search(r"traffic_bytes_per_launch: (\d+) kernel: (\S+) sources_sha256: ([0-9a-f]{64})", open(path).read())
+    if not m or m.group(2) != kernel:
+        return None
+    h = hashlib.sha256()
+    for f in _KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2412_13269_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(m.group(1)) if h.hexdigest() == m.group(3) else None
 
 
 def cpu_baseline(q, p):
@@ -386,7 +412,7 @@ def main():
                                "rotations by 2^0..2^14",
                    "N": N, "L": L, "K": K, "dnum": beta, "ks_ops_per_step": ks_per_step},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "avg_launch_us": 1e3 * d["ms"] / d["launches"],
                      "algorithmic_bytes_per_launch": d["bytes"] / d["launches"]},
         "per_op_us": per_op,
