@@ -133,17 +133,18 @@ pfx_status check_out(const pfx_ct *o, uint32_t lv, uint32_t deg) {
     return PFX_OK;
 }
 
-// Key switching of the lv-limb NTT-domain polynomial d (Sec. 2.4.1):
-// out_u = ModDown(sum_j ModUp_j(d) * swk_{j,u}) (+ base_u).  Six launches, see
-// keyswitch.hip.  galois != 0 switches phi_galois(d) instead of d, and adds
-// phi_galois(base0): both are read through the automorphism's permutation, so
-// out0 must not alias base0 then (other workgroups still read base0 while
-// out0 is written).
-void ks_core(pfx_ctx *c, const Launch &L, const Ws &w, const double *d, int lv, const pfx_swk *key, double *out0,
-             double *out1, const double *base0, const double *base1, uint32_t galois = 0) {
+// Key switching (Sec. 2.4.1): out_u = ModDown(sum_j ModUp_j(d) * swk_{j,u}) +
+// base_u, with d and the bases as the operand describes them (KsOperand:
+// plain, read through an automorphism, or formed from a ciphertext product).
+// Six kernels and one row-pass launch, see keyswitch.hip.  The last kernel
+// reads the bases while it writes out0 / out1 from other workgroups, so the
+// outputs must not alias a permuted base (KS_GALOIS) or a product operand
+// (KS_PRODUCT); callers copy or fall back first.
+void ks_core(pfx_ctx *c, const Launch &L, const Ws &w, const KsOperand &op, int lv, const pfx_swk *key,
+             double *out0, double *out1) {
     const int E = lv + c->K;
     double *dcoef = w.at(w.lay.dcoef), *ext = w.at(w.lay.ext), *acc = w.at(w.lay.acc), *tmp = w.at(w.lay.mdtmp);
-    launch_intt_scale(L, dcoef, d, lv, galois);
+    launch_intt_scale(L, dcoef, op, lv);
     launch_modup_col(L, ext, dcoef, lv);
     const int beta = (lv + c->alpha - 1) / c->alpha;
     LimbMap m;
@@ -160,10 +161,19 @@ void ks_core(pfx_ctx *c, const Launch &L, const Ws &w, const double *d, int lv, 
         }
     }
     launch_ntt_pass(L, ext, nullptr, m, true, false);
-    launch_ks_inner(L, acc, ext, d, key->d_k, lv, galois);
+    launch_ks_inner(L, acc, ext, op, key->d_k, lv);
     launch_intt_special(L, acc, lv);
     launch_moddown_col(L, tmp, acc, lv);
-    launch_row_moddown(L, out0, out1, acc, tmp, base0, base1, lv, galois);
+    launch_row_moddown(L, out0, out1, acc, tmp, op, lv);
+}
+
+KsOperand ks_plain(const double *d, const double *base0, const double *base1) {
+    KsOperand op;
+    op.mode = KS_PLAIN;
+    op.d = d;
+    op.base0 = base0;
+    op.base1 = base1;
+    return op;
 }
 
 pfx_swk *find_key(pfx_ctx *c, uint32_t g, const pfx_swk *const *keys, size_t n) {
@@ -178,15 +188,19 @@ pfx_status galois_apply(pfx_ctx *c, const pfx_ct *a, const pfx_swk *gk, pfx_ct *
     if (r) return r;
     const int lv = a->n_limbs;
     Launch L{c, st};
+    KsOperand op;
+    op.mode = KS_GALOIS;
+    op.d = a->poly(1);
+    op.base0 = a->poly(0);
+    op.galois = gk->galois;
     if (out->d == a->d) {
         // in place: c0 is read through the permutation while out0 is written,
         // so it is read from a copy (c1 is only written by the last launch)
         double *t0 = w.at(w.lay.t3);
         launch_ew(L, EW_COPY, t0, a->poly(0), nullptr, (size_t)c->L * c->N, (size_t)a->cap_limbs * c->N, 0, 1, lv);
-        ks_core(c, L, w, a->poly(1), lv, gk, out->poly(0), out->poly(1), t0, nullptr, gk->galois);
-    } else {
-        ks_core(c, L, w, a->poly(1), lv, gk, out->poly(0), out->poly(1), a->poly(0), nullptr, gk->galois);
+        op.base0 = t0;
     }
+    ks_core(c, L, w, op, lv, gk, out->poly(0), out->poly(1));
     out->n_limbs = lv;
     out->degree = 1;
     out->scale = a->scale;
@@ -963,7 +977,7 @@ pfx_status pfx_relinearize(pfx_ctx *c, const pfx_ct *a, const pfx_swk *rlk, pfx_
     Launch L{c, S(stream)};
     const double sc = a->scale;
     const uint32_t lv = a->n_limbs;
-    ks_core(c, L, w, a->poly(2), lv, rlk, out->poly(0), out->poly(1), a->poly(0), a->poly(1));
+    ks_core(c, L, w, ks_plain(a->poly(2), a->poly(0), a->poly(1)), lv, rlk, out->poly(0), out->poly(1));
     out->n_limbs = lv;
     out->degree = 1;
     out->scale = sc;
@@ -987,10 +1001,23 @@ pfx_status pfx_mul_relin(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx
     if (r) return r;
     Launch L{c, S(stream)};
     const double sc = a->scale * b->scale;
-    const size_t PL = (size_t)c->L * c->N;
-    double *t0 = w.at(w.lay.t3), *t1 = t0 + PL, *t2 = t1 + PL;
-    launch_tensor(L, t0, t1, t2, a->poly(0), a->poly(1), b->poly(0), b->poly(1), lv);
-    ks_core(c, L, w, t2, lv, rlk, out->poly(0), out->poly(1), t0, t1);
+    if (out->d != a->d && out->d != b->d) {
+        // the tensor product is formed inside the key switch, never stored
+        KsOperand op;
+        op.mode = KS_PRODUCT;
+        op.a0 = a->poly(0);
+        op.a1 = a->poly(1);
+        op.b0 = b->poly(0);
+        op.b1 = b->poly(1);
+        ks_core(c, L, w, op, lv, rlk, out->poly(0), out->poly(1));
+    } else {
+        // the output overwrites an operand that other workgroups of the last
+        // launch still read: take the tensor product into scratch first
+        const size_t PL = (size_t)c->L * c->N;
+        double *t0 = w.at(w.lay.t3), *t1 = t0 + PL, *t2 = t1 + PL;
+        launch_tensor(L, t0, t1, t2, a->poly(0), a->poly(1), b->poly(0), b->poly(1), lv);
+        ks_core(c, L, w, ks_plain(t2, t0, t1), lv, rlk, out->poly(0), out->poly(1));
+    }
     out->n_limbs = lv;
     out->degree = 1;
     out->scale = sc;
@@ -1048,7 +1075,7 @@ pfx_status pfx_key_switch(pfx_ctx *c, const pfx_ct *d, const pfx_swk *k, pfx_ct 
     r = get_ws(c, S(stream), w);
     if (r) return r;
     Launch L{c, S(stream)};
-    ks_core(c, L, w, d->poly(0), d->n_limbs, k, out->poly(0), out->poly(1), nullptr, nullptr);
+    ks_core(c, L, w, ks_plain(d->poly(0), nullptr, nullptr), d->n_limbs, k, out->poly(0), out->poly(1));
     out->n_limbs = d->n_limbs;
     out->degree = 1;
     out->scale = d->scale;

@@ -199,20 +199,30 @@ void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const do
                    const double *a1, const double *b0, const double *b1, int nl);
 void launch_automorph(const Launch &L, double *out, const double *in, size_t so, size_t si, int npoly,
                       int nl, uint32_t g);
-// galois != 0: d_ntt is read through the NTT-domain permutation of phi_galois.
-void launch_ks_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt,
-                     const double *key, int lv, uint32_t galois);
+// The operand of a key switch and what it adds (keyswitch.hip):
+//   KS_PLAIN:   switch d, add base0 / base1 (either may be null)
+//   KS_GALOIS:  switch phi_galois(d), add phi_galois(base0) (base1 null)
+//   KS_PRODUCT: switch a1 b1, add a0 b0 and a0 b1 + a1 b0 (HMult + relin)
+enum KsMode { KS_PLAIN = 0, KS_GALOIS = 1, KS_PRODUCT = 2 };
+struct KsOperand {
+    int mode = KS_PLAIN;
+    const double *d = nullptr;
+    const double *base0 = nullptr, *base1 = nullptr;
+    uint32_t galois = 0;
+    const double *a0 = nullptr, *a1 = nullptr, *b0 = nullptr, *b1 = nullptr;
+};
+void launch_ks_inner(const Launch &L, double *acc, const double *ext, const KsOperand &op, const double *key, int lv);
 // Rescale of np polynomials of lv limbs (rescale.hip): in/out poly strides in
 // doubles, `last` (np limbs) and `tmp` (np (lv - 1) limbs) scratch.
 void launch_rescale(const Launch &L, double *out, size_t so, const double *in, size_t si, int np, int lv,
                     double *last, double *tmp);
 // Fused key-switching steps (keyswitch.hip).
-void launch_intt_scale(const Launch &L, double *dcoef, const double *d, int lv, uint32_t galois);
+void launch_intt_scale(const Launch &L, double *dcoef, const KsOperand &op, int lv);
 void launch_modup_col(const Launch &L, double *ext, const double *dcoef, int lv);
 void launch_intt_special(const Launch &L, double *acc, int lv);
 void launch_moddown_col(const Launch &L, double *tmp, const double *acc, int lv);
 void launch_row_moddown(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
-                        const double *base0, const double *base1, int lv, uint32_t galois);
+                        const KsOperand &op, int lv);
 void launch_keygen_b(const Launch &L, double *b, const double *a, const double *e, const double *s,
                      const double *sfrom, int digit);
 void launch_encrypt(const Launch &L, double *c0, const double *a, const double *e, const double *s,

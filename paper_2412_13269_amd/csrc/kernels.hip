@@ -332,11 +332,12 @@ void launch_automorph(const Launch &L, double *out, const double *in, size_t so,
 //                 digit, t in the order: q's below the digit, q's above, p's;
 //   acc[u][m][c]  u in {0, 1}, m < E: q_0..q_{lv-1} then p_0..p_{K-1}.
 // acc_u[m] = sum_j dtilde_j[m] * swk_{j,u}[m]   (NTT domain).  The digit's own
-// primes take d itself; with GAL, d is phi_g(d_in) read through galois_src.
-template <bool GAL>
+// primes take d itself: phi_g(d_in) read through galois_src (KS_GALOIS), or
+// a1 b1 formed from the product's operands (KS_PRODUCT, d_ntt = a1, d2 = b1).
+template <int MODE>
 __global__ __launch_bounds__(256) void k_ks_inner(double *acc, const double *ext, const double *d_ntt,
-                                                  const double *key, int lv, int logn, int L, int K, int alpha,
-                                                  const PrimeDev *pr, uint32_t g) {
+                                                  const double *d2, const double *key, int lv, int logn, int L,
+                                                  int K, int alpha, const PrimeDev *pr, uint32_t g) {
     constexpr int kChunk = 4;   // digits whose 3 loads are all in flight before any product
     const int m = blockIdx.y;
     const size_t N = (size_t)1 << logn;
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) void k_ks_inner(double *acc, const double *ext
     const double q = pr[pid].q, qi = pr[pid].qinv;
     const size_t kstride = (size_t)(L + K) * N;
     const double *k0 = key + ((size_t)pid << logn) + c;
-    const double *dm = d_ntt + ((size_t)m << logn) + (GAL ? galois_src((uint32_t)c, logn, g) : c);
+    const size_t dof = ((size_t)m << logn) + (MODE == KS_GALOIS ? galois_src((uint32_t)c, logn, g) : c);
     // products in [0, q) summed lazily; a chunk leaves a < q + 4q < 2^53, which
     // mred reduces exactly (its quotient estimate is off by at most one there)
     double a0 = 0.0, a1 = 0.0;
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(256) void k_ks_inner(double *acc, const double *ext
                 const int j0 = j * alpha;
                 const int sz = min(alpha, lv - j0);
                 if (m >= j0 && m < j0 + sz) {
-                    x[t] = *dm;
+                    x[t] = MODE == KS_PRODUCT ? mmul(d_ntt[dof], d2[dof], q, qi) : d_ntt[dof];
                 } else {
                     const int tt = m < j0 ? m : m - sz;
                     x[t] = ext[((size_t)j * E + tt) * N + c];
@@ -384,18 +385,19 @@ __global__ __launch_bounds__(256) void k_ks_inner(double *acc, const double *ext
     acc[((size_t)(E + m) << logn) + c] = a1;
 }
 
-void launch_ks_inner(const Launch &L, double *acc, const double *ext, const double *d_ntt, const double *key, int lv,
-                     uint32_t galois) {
+void launch_ks_inner(const Launch &L, double *acc, const double *ext, const KsOperand &op, const double *key, int lv) {
     pfx_ctx *ctx = L.ctx;
     dim3 grid((ctx->N + 255) / 256, lv + ctx->K);
+    const double *d1 = op.mode == KS_PRODUCT ? op.a1 : op.d, *d2 = op.mode == KS_PRODUCT ? op.b1 : nullptr;
     hipEvent_t ev;
     prof_begin(L, "ks_inner", &ev);
-    if (galois)
-        k_ks_inner<true><<<grid, 256, 0, L.st>>>(acc, ext, d_ntt, key, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha,
-                                                 ctx->d_primes, galois);
-    else
-        k_ks_inner<false><<<grid, 256, 0, L.st>>>(acc, ext, d_ntt, key, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha,
-                                                  ctx->d_primes, 0);
+#define PFX_KS_INNER(MD)                                                                                         \
+    k_ks_inner<MD><<<grid, 256, 0, L.st>>>(acc, ext, d1, d2, key, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha,       \
+                                           ctx->d_primes, op.galois)
+    if (op.mode == KS_GALOIS) PFX_KS_INNER(KS_GALOIS);
+    else if (op.mode == KS_PRODUCT) PFX_KS_INNER(KS_PRODUCT);
+    else PFX_KS_INNER(KS_PLAIN);
+#undef PFX_KS_INNER
     HIP_LAUNCH_CHECK();
     prof_end(L, "ks_inner", ev, 8.0 * (double)ctx->N * (lv + ctx->K) * (3.0 * ((lv + ctx->alpha - 1) / ctx->alpha) + 2.0));
 }

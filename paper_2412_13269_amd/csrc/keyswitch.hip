@@ -18,10 +18,12 @@
 //                     the key switch is added to)                -> out
 //
 // The fusions remove the coefficient-domain ModUp output (beta * E limbs written
-// and read back) and the coefficient-domain ModDown conversion.  For a
-// rotation the automorphism is fused too: steps 1 and 3 read d through the
-// NTT-domain permutation of phi_g, and step 6 reads the polynomial it adds
-// (c0) through it, so no permuted copy is made.  Workgroup ids are remapped so that
+// and read back) and the coefficient-domain ModDown conversion.  The operand
+// is read where it is needed (KsMode): for a rotation steps 1 and 3 read d
+// through the NTT-domain permutation of phi_g and step 6 reads the polynomial
+// it adds (c0) through it, so no permuted copy is made; for HMult + relin the
+// tensor product is never stored: steps 1 and 3 form d2 = a1 b1 and step 6
+// the bases d0 = a0 b0, d1 = a0 b1 + a1 b0 from the input ciphertexts.  Workgroup ids are remapped so that
 // blocks sharing input tiles (step 2, 5) or a prime's twiddle table (3, 6) run
 // on one XCD (see xcd_slot in ntt_core.h).
 #include <algorithm>
@@ -45,7 +47,10 @@ struct KsArgs {
     int logn, lv, L, K, alpha, beta, E;
     int C, tiles;   // pass geometry (column or row, per kernel)
     int n;          // logical blocks
-    uint32_t galois;   // != 0: the key-switched polynomial is phi_galois of the one passed in
+    uint32_t galois;   // KS_GALOIS: the key-switched polynomial is phi_galois of the one passed in
+    // KS_PRODUCT: the operands of a ciphertext product (a0, a1) x (b0, b1):
+    // d = a1 b1 and the bases a0 b0, a0 b1 + a1 b0 are formed where they are read
+    const double *a0, *a1, *b0, *b1;
 };
 
 __device__ __forceinline__ int ks_ext_prime(int t, int j0, int sz, int lv, int L) {
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(TH) void k_moddown_col(const KsArgs a, double *__re
 }
 
 // ---- step 6: forward row pass of the conversion, then (acc_Q - x) P^-1 (+ base)
-template <int S, bool GAL, int TH>
+template <int S, int MODE, int TH>
 __global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, double *out0, double *out1,
                                                              const double *__restrict__ acc,
                                                              const double *__restrict__ tmp, const double *base0,
@@ -172,18 +177,28 @@ __global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, double *out0
     const double *base = u ? base1 : base0;
     double *out = (u ? out1 : out0) + (size_t)i * N;
     const double *bs = base ? base + (size_t)i * N : nullptr;
+    const size_t li = (size_t)i * N;
     auto ld = [&](int g, int) { return src[g]; };
-    // with GAL the base of output 0 (c0 of the rotated ciphertext) is read through phi_g
+    // KS_GALOIS: the base of output 0 (c0 of the rotated ciphertext) is read
+    // through phi_g; KS_PRODUCT: the bases are the tensor terms of the inputs
     auto st = [&](int g, double v, int) {
         double x = mmulc(msub(ax[g], v, q), pinv.x, pinv.y, q);
-        if (bs) x = madd(x, bs[GAL && u == 0 ? galois_src((uint32_t)g, a.logn, a.galois) : (uint32_t)g], q);
+        if (MODE == KS_PRODUCT) {
+            const unsigned e = (unsigned)g;
+            const double t = u == 0 ? mmul(a.a0[li + e], a.b0[li + e], q, P.qinv)
+                                    : madd(mmul(a.a0[li + e], a.b1[li + e], q, P.qinv),
+                                           mmul(a.a1[li + e], a.b0[li + e], q, P.qinv), q);
+            x = madd(x, t, q);
+        } else if (bs) {
+            x = madd(x, bs[MODE == KS_GALOIS && u == 0 ? galois_src((uint32_t)g, a.logn, a.galois) : (uint32_t)g], q);
+        }
         out[g] = x;
     };
     row_pass<S, false, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
 }
 
 // ---- step 1: INTT of d with the ModUp scaling folded into the last stage's store
-template <int S, bool ROW, bool GAL, int TH>
+template <int S, bool ROW, int MODE, int TH>
 __global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__restrict__ dst,
                                                             const double *__restrict__ src) {
     __shared__ double lds[NttTile<TH>::lds];
@@ -195,7 +210,12 @@ __global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__res
     const size_t N = (size_t)1 << a.logn;
     const double *s = src + (size_t)i * N;
     double *d = dst + (size_t)i * N;
-    auto ld = [&](int g, int) { return s[GAL ? galois_src((uint32_t)g, a.logn, a.galois) : (uint32_t)g]; };
+    const size_t li = (size_t)i * N;
+    auto ld = [&](int g, int) {
+        const unsigned e = (unsigned)g;
+        if (MODE == KS_PRODUCT) return mmul(a.a1[li + e], a.b1[li + e], P.q, P.qinv);
+        return s[MODE == KS_GALOIS ? galois_src(e, a.logn, a.galois) : e];
+    };
     if (ROW) {
         auto st = [&](int g, double v, int) { d[g] = v; };
         row_pass<S, true, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
@@ -243,7 +263,14 @@ __global__ __launch_bounds__(TH) void k_intt_special(const KsArgs a, double *__r
         default: { constexpr int NT = 8; CALL; } break;                 \
     }
 
-static KsArgs ks_args(pfx_ctx *c, int lv) {
+#define PFX_SWITCH_KS(m_, CALL)                                        \
+    switch (m_) {                                                      \
+        case KS_GALOIS: { constexpr int MD = KS_GALOIS; CALL; } break;  \
+        case KS_PRODUCT: { constexpr int MD = KS_PRODUCT; CALL; } break; \
+        default: { constexpr int MD = KS_PLAIN; CALL; } break;          \
+    }
+
+static KsArgs ks_args(pfx_ctx *c, int lv, const KsOperand &op = KsOperand{}) {
     KsArgs a;
     a.primes = c->d_primes;
     a.mu = c->d_modup;
@@ -255,7 +282,11 @@ static KsArgs ks_args(pfx_ctx *c, int lv) {
     a.alpha = c->alpha;
     a.beta = (lv + c->alpha - 1) / c->alpha;
     a.E = lv + c->K;
-    a.galois = 0;
+    a.galois = op.galois;
+    a.a0 = op.a0;
+    a.a1 = op.a1;
+    a.b0 = op.b0;
+    a.b1 = op.b1;
     return a;
 }
 
@@ -268,9 +299,9 @@ static void widen_grid(PassShape &pr, PassShape &pc, int limbs) {
     while (limbs * pc.tiles < 1024 && pc.C / 2 >= 8) { pc.C /= 2; pc.tiles *= 2; }
 }
 
-void launch_intt_scale(const Launch &L, double *dcoef, const double *d, int lv, uint32_t galois) {
-    KsArgs a = ks_args(L.ctx, lv);
-    a.galois = galois;
+void launch_intt_scale(const Launch &L, double *dcoef, const KsOperand &op, int lv) {
+    KsArgs a = ks_args(L.ctx, lv, op);
+    const double *d = op.d;
     const int th = pass_threads(a.logn, lv, true), tc = pass_threads(a.logn, lv, false);
     const PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
     hipEvent_t ev;
@@ -278,20 +309,15 @@ void launch_intt_scale(const Launch &L, double *dcoef, const double *d, int lv, 
     a.tiles = pr.tiles;
     a.n = lv * a.tiles;
     prof_begin(L, "ks_intt_row", &ev);
-    PFX_SWITCH_TH(th, {
-        if (galois) {
-            PFX_SWITCH_S(pr.S, (k_intt_scale<SS, true, true, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, dcoef, d)));
-        } else {
-            PFX_SWITCH_S(pr.S, (k_intt_scale<SS, true, false, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, dcoef, d)));
-        }
-    });
+    PFX_SWITCH_TH(th, PFX_SWITCH_KS(op.mode, PFX_SWITCH_S(pr.S, (k_intt_scale<SS, true, MD, TH><<<xcd_grid(a.n), TH, 0,
+                                                                                             L.st>>>(a, dcoef, d)))));
     HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_intt_row", ev, 16.0 * (double)L.ctx->N * lv);
+    prof_end(L, "ks_intt_row", ev, (op.mode == KS_PRODUCT ? 24.0 : 16.0) * (double)L.ctx->N * lv);
     a.C = pc.C;
     a.tiles = pc.tiles;
     a.n = lv * a.tiles;
     prof_begin(L, "ks_intt_col", &ev);
-    PFX_SWITCH_TH(tc, PFX_SWITCH_S(pc.S, (k_intt_scale<SS, false, false, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(
+    PFX_SWITCH_TH(tc, PFX_SWITCH_S(pc.S, (k_intt_scale<SS, false, KS_PLAIN, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(
                                               a, dcoef, dcoef))));
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_intt_col", ev, 16.0 * (double)L.ctx->N * lv);
@@ -351,9 +377,9 @@ void launch_moddown_col(const Launch &L, double *tmp, const double *acc, int lv)
 }
 
 void launch_row_moddown(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
-                        const double *base0, const double *base1, int lv, uint32_t galois) {
-    KsArgs a = ks_args(L.ctx, lv);
-    a.galois = galois;
+                        const KsOperand &op, int lv) {
+    KsArgs a = ks_args(L.ctx, lv, op);
+    const double *base0 = op.base0, *base1 = op.base1;
     const int th = pass_threads(a.logn, 2 * lv, true);
     const PassShape ps = row_shape(a.logn, th * kSlots);
     a.C = ps.C;
@@ -361,18 +387,12 @@ void launch_row_moddown(const Launch &L, double *out0, double *out1, const doubl
     a.n = 2 * lv * a.tiles;
     hipEvent_t ev;
     prof_begin(L, "ks_row_moddown", &ev);
-    PFX_SWITCH_TH(th, {
-        if (galois) {
-            PFX_SWITCH_S(ps.S, (k_row_moddown<SS, true, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, out0, out1, acc, tmp,
-                                                                                          base0, base1)));
-        } else {
-            PFX_SWITCH_S(ps.S, (k_row_moddown<SS, false, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, out0, out1, acc, tmp,
-                                                                                           base0, base1)));
-        }
-    });
+    PFX_SWITCH_TH(th, PFX_SWITCH_KS(op.mode, PFX_SWITCH_S(ps.S, (k_row_moddown<SS, MD, TH><<<xcd_grid(a.n), TH, 0,
+                                                                                          L.st>>>(a, out0, out1, acc,
+                                                                                                  tmp, base0, base1)))));
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_row_moddown", ev,
-             8.0 * (double)L.ctx->N * lv * (6.0 + (base0 ? 1 : 0) + (base1 ? 1 : 0)));
+             8.0 * (double)L.ctx->N * lv * (op.mode == KS_PRODUCT ? 10.0 : 6.0 + (base0 ? 1 : 0) + (base1 ? 1 : 0)));
 }
 
 }  // namespace pfx

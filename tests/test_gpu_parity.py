@@ -194,11 +194,21 @@ def test_tensor_relinearize(pair, X):
     X.pfx_relinearize(pair.ctx, t, kx, r)
     ro = O.relinearize(P, to, ko)
     pair.same(ro, r)
-    X.pfx_mul_relin(pair.ctx, c1x, c2x, kx, c1x)     # output aliases an input
-    pair.same(ro, c1x)
-    dec = X.pfx_decrypt(pair.ctx, pair.sk, c1x)
+    m = pair.ct(P.L)
+    X.pfx_mul_relin(pair.ctx, c1x, c2x, kx, m)        # product formed inside the key switch
+    pair.same(ro, m)
+    dec = X.pfx_decrypt(pair.ctx, pair.sk, m)
     pair.handles.append(dec)
     assert np.max(np.abs(X.pfx_decode(pair.ctx, dec, P.N // 2) - z1 * z2)) < 2.0 ** -20
+    c3o, c3x, _ = pair.enc(P.L - 1)                  # operands at different levels
+    X.pfx_mul_relin(pair.ctx, c3x, c2x, kx, m)
+    pair.same(O.mul_relin(P, c3o, c2o, ko), m)
+    X.pfx_mul_relin(pair.ctx, c3x, c3x, kx, m)        # squaring
+    pair.same(O.mul_relin(P, c3o, c3o, ko), m)
+    X.pfx_mul_relin(pair.ctx, c1x, c2x, kx, c2x)     # output aliases the second input
+    pair.same(ro, c2x)
+    X.pfx_mul_relin(pair.ctx, c1x, c1x, kx, c1x)     # output aliases both
+    pair.same(O.mul_relin(P, c1o, c1o, ko), c1x)
 
 
 def test_rescale_every_level(pair, X):
