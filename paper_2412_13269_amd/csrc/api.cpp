@@ -501,26 +501,26 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
 
 void pfx_ctx_destroy(pfx_ctx *c) {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
     for (auto &kv : c->ws) {
-        hipFree(kv.second->buf);
+        (void)hipFree(kv.second->buf);
         delete kv.second;
     }
     for (auto &e : c->prof_pending) {
-        hipEventDestroy(e.start);
-        hipEventDestroy(e.stop);
+        (void)hipEventDestroy(e.start);
+        (void)hipEventDestroy(e.stop);
     }
-    for (auto e : c->prof_pool) hipEventDestroy(e);
-    for (auto &kv : c->graphs) hipGraphExecDestroy(kv.second.exec);
-    for (auto st : c->lanes) hipStreamDestroy(st);
-    for (auto e : c->lane_events) hipEventDestroy(e);
-    hipFree(c->d_tw);
-    hipFree(c->d_rtw);
-    hipFree(c->d_primes);
-    hipFree(c->d_modup);
-    hipFree(c->d_moddown);
-    hipFree(c->d_rescale);
+    for (auto e : c->prof_pool) (void)(void)hipEventDestroy(e);
+    for (auto &kv : c->graphs) (void)(void)hipGraphExecDestroy(kv.second.exec);
+    for (auto st : c->lanes) (void)(void)hipStreamDestroy(st);
+    for (auto e : c->lane_events) (void)(void)hipEventDestroy(e);
+    (void)hipFree(c->d_tw);
+    (void)hipFree(c->d_rtw);
+    (void)hipFree(c->d_primes);
+    (void)hipFree(c->d_modup);
+    (void)hipFree(c->d_moddown);
+    (void)hipFree(c->d_rescale);
     delete c;
 }
 
@@ -555,14 +555,14 @@ pfx_status pfx_sk_create(pfx_ctx *c, const int8_t *s, pfx_sk **out) {
     launch_s8_to_rns(L, k->d_s, tmp, NP);
     launch_ntt(L, k->d_s, nullptr, contiguous_map(NP, 0), false);
     HIPCHECK(hipStreamSynchronize(nullptr));
-    hipFree(tmp);
+    (void)hipFree(tmp);
     *out = k.release();
     return PFX_OK;
 }
 
 void pfx_sk_destroy(pfx_sk *k) {
     if (!k) return;
-    hipFree(k->d_s);
+    (void)hipFree(k->d_s);
     delete k;
 }
 
@@ -606,10 +606,10 @@ pfx_status pfx_swk_create(pfx_ctx *c, const pfx_sk *sk, uint32_t galois, const u
         launch_keygen_b(L, b, aa, etmp, sk->d_s, sfrom, j);
         HIPCHECK(hipStreamSynchronize(nullptr));
     }
-    hipFree(sfrom);
-    hipFree(etmp);
-    hipFree(stage);
-    hipFree(edev);
+    (void)hipFree(sfrom);
+    (void)hipFree(etmp);
+    (void)hipFree(stage);
+    (void)hipFree(edev);
     *out = k.release();
     return PFX_OK;
 }
@@ -630,8 +630,8 @@ pfx_status pfx_swk_export(pfx_ctx *c, const pfx_swk *k, uint64_t *words, size_t 
         launch_f64_to_u64(L, u, tmp, per);
         HIPCHECK(hipMemcpy(words + (size_t)p * per, u, per * sizeof(uint64_t), hipMemcpyDeviceToHost));
     }
-    hipFree(tmp);
-    hipFree(u);
+    (void)hipFree(tmp);
+    (void)hipFree(u);
     return PFX_OK;
 }
 
@@ -639,7 +639,7 @@ uint32_t pfx_swk_galois(const pfx_swk *k) { return k ? k->galois : 0; }
 
 void pfx_swk_destroy(pfx_swk *k) {
     if (!k) return;
-    hipFree(k->d_k);
+    (void)hipFree(k->d_k);
     delete k;
 }
 
@@ -661,7 +661,7 @@ pfx_status pfx_ct_create(pfx_ctx *c, uint32_t cap_limbs, uint32_t cap_degree, pf
 
 void pfx_ct_destroy(pfx_ct *x) {
     if (!x) return;
-    if (x->owns) hipFree(x->d);
+    if (x->owns) (void)hipFree(x->d);
     delete x;
 }
 
@@ -1377,13 +1377,13 @@ pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *
         c->capturing = false;
         c->prof_on = prof;
         if (r) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return r;
         }
         if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
         pfx_ctx::GraphEntry ent;
         e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         for (size_t i = 0; i < n_regs; ++i)
             ent.meta.push_back({regs[i]->n_limbs | (regs[i]->degree << 16), regs[i]->scale});
@@ -1487,13 +1487,13 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
         hipError_t e = hipStreamEndCapture(S(stream), &g);
         for (size_t i = 0; i < n; ++i) ctxs[i]->capturing = false;
         if (r) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return r;
         }
         if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("batch capture: ") + hipGetErrorString(e));
         pfx_ctx::GraphEntry ent;
         e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         for (size_t i = 0; i < n; ++i) ent.meta.push_back({out[i]->n_limbs | (out[i]->degree << 16), out[i]->scale});
         it = c0->graphs.emplace(key, ent).first;
@@ -1552,7 +1552,7 @@ pfx_status pfx_stream_destroy(pfx_ctx *c, void *stream) {
         std::lock_guard<std::mutex> g(c->mu);
         auto it = c->ws.find(S(stream));
         if (it != c->ws.end()) {
-            hipFree(it->second->buf);
+            (void)hipFree(it->second->buf);
             delete it->second;
             c->ws.erase(it);
         }
@@ -1570,9 +1570,9 @@ pfx_status pfx_profile_enable(pfx_ctx *c, int on) {
 
 static void prof_drain(pfx_ctx *c) {
     for (auto &e : c->prof_pending) {
-        hipEventSynchronize(e.stop);
+        (void)hipEventSynchronize(e.stop);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e.start, e.stop);
+        (void)hipEventElapsedTime(&ms, e.start, e.stop);
         ProfTotal &t = c->prof_done[e.name];
         t.launches += 1;
         t.ms += ms;
@@ -1626,7 +1626,7 @@ static hipEvent_t pool_event(pfx_ctx *c) {
         return e;
     }
     hipEvent_t e = nullptr;
-    hipEventCreate(&e);
+    (void)hipEventCreate(&e);
     return e;
 }
 
@@ -1634,13 +1634,13 @@ void prof_begin(const Launch &L, const char *, hipEvent_t *ev) {
     *ev = nullptr;
     if (!L.ctx->prof_on || L.ctx->capturing) return;
     *ev = pool_event(L.ctx);
-    hipEventRecord(*ev, L.st);
+    (void)hipEventRecord(*ev, L.st);
 }
 
 void prof_end(const Launch &L, const char *name, hipEvent_t ev, double bytes) {
     if (!L.ctx->prof_on || L.ctx->capturing || !ev) return;
     hipEvent_t stop = pool_event(L.ctx);
-    hipEventRecord(stop, L.st);
+    (void)hipEventRecord(stop, L.st);
     std::lock_guard<std::mutex> g(L.ctx->mu);
     L.ctx->prof_pending.push_back(ProfEntry{ev, stop, name, bytes});
 }

@@ -178,21 +178,32 @@ __global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, double *out0
     double *out = (u ? out1 : out0) + (size_t)i * N;
     const double *bs = base ? base + (size_t)i * N : nullptr;
     const size_t li = (size_t)i * N;
-    auto ld = [&](int g, int) { return src[g]; };
+    // The operands of the combination are loaded before the transform, so
+    // their latency hides under it: slot k of this thread is element
+    // tid + k * TH of the tile (the row pass's output order).
     // KS_GALOIS: the base of output 0 (c0 of the rotated ciphertext) is read
-    // through phi_g; KS_PRODUCT: the bases are the tensor terms of the inputs
-    auto st = [&](int g, double v, int) {
-        double x = mmulc(msub(ax[g], v, q), pinv.x, pinv.y, q);
-        if (MODE == KS_PRODUCT) {
-            const unsigned e = (unsigned)g;
-            const double t = u == 0 ? mmul(a.a0[li + e], a.b0[li + e], q, P.qinv)
-                                    : madd(mmul(a.a0[li + e], a.b1[li + e], q, P.qinv),
-                                           mmul(a.a1[li + e], a.b0[li + e], q, P.qinv), q);
-            x = madd(x, t, q);
-        } else if (bs) {
-            x = madd(x, bs[MODE == KS_GALOIS && u == 0 ? galois_src((uint32_t)g, a.logn, a.galois) : (uint32_t)g], q);
+    // through phi_g; KS_PRODUCT: the bases are the tensor terms of the inputs.
+    const int g0 = (tile * a.C) << S, tot = a.C << S;
+    double xa[kSlots], xb[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+        const int e = threadIdx.x + k * TH;
+        xa[k] = xb[k] = 0.0;
+        if (e < tot) {
+            const unsigned g = (unsigned)(g0 + e);
+            xa[k] = ax[g];
+            if (MODE == KS_PRODUCT) {
+                xb[k] = u == 0 ? mmul(a.a0[li + g], a.b0[li + g], q, P.qinv)
+                               : madd(mmul(a.a0[li + g], a.b1[li + g], q, P.qinv),
+                                      mmul(a.a1[li + g], a.b0[li + g], q, P.qinv), q);
+            } else if (bs) {
+                xb[k] = bs[MODE == KS_GALOIS && u == 0 ? galois_src(g, a.logn, a.galois) : g];
+            }
         }
-        out[g] = x;
+    }
+    auto ld = [&](int g, int) { return src[g]; };
+    auto st = [&](int g, double v, int k) {
+        out[g] = madd(mmulc(msub(xa[k], v, q), pinv.x, pinv.y, q), xb[k], q);
     };
     row_pass<S, false, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
 }

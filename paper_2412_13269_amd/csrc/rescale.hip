@@ -96,9 +96,19 @@ __global__ __launch_bounds__(TH) void k_rs_row(const RsArgs a, double *out, cons
     const double *src = tmp + ((size_t)k * nout + i) * N;
     const double *c = in + k * a.si + (size_t)i * N;
     double *o = out + k * a.so + (size_t)i * N;
+    // c is loaded before the transform (its latency hides under it); slot k of
+    // this thread is element tid + k * TH of the tile, the row pass's output
+    // order.  out may alias in: each element is read and then written by the
+    // same thread.
+    const int g0 = (tile * a.C) << S, tot = a.C << S;
+    double xc[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+        const int e = threadIdx.x + k * TH;
+        xc[k] = e < tot ? c[(unsigned)(g0 + e)] : 0.0;
+    }
     auto ld = [&](int g, int) { return src[(unsigned)g]; };
-    // out may alias in: each element is read and then written by the same thread
-    auto st = [&](int g, double v, int) { o[(unsigned)g] = mmulc(msub(c[(unsigned)g], v, P.q), inv.x, inv.y, P.q); };
+    auto st = [&](int g, double v, int k) { o[(unsigned)g] = mmulc(msub(xc[k], v, P.q), inv.x, inv.y, P.q); };
     row_pass<S, false, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
 }
 

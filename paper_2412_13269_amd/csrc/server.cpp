@@ -193,7 +193,7 @@ void launch(pfx_server *s, Request *r) {
     }
     Callback *cb = &s->callbacks[r->slot];
     if (hipLaunchHostFunc((hipStream_t)st, on_complete, cb) != hipSuccess) {
-        hipStreamSynchronize((hipStream_t)st);   // no hook: retire after the stream has drained
+        (void)hipStreamSynchronize((hipStream_t)st);   // no hook: retire after the stream has drained
         on_complete(cb);
     }
 }
@@ -213,7 +213,7 @@ void retire(pfx_server *s, int slot, Clock::time_point t) {
 }
 
 void scheduler(pfx_server *s) {
-    hipSetDevice(s->ctx->device);
+    (void)hipSetDevice(s->ctx->device);   // launches below report their own errors
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         for (auto &f : s->finished) retire(s, f.first, f.second);
@@ -278,7 +278,7 @@ pfx_status pfx_server_create(pfx_ctx *c, size_t hbm_budget, uint32_t slots, cons
         }
         if (r) {
             for (void *x : s->streams) pfx_stream_destroy(c, x);
-            hipFree(s->arena_mem);
+            (void)hipFree(s->arena_mem);
             return r;
         }
         s->callbacks[i] = Callback{s.get(), (int)i};
@@ -386,7 +386,7 @@ void pfx_server_destroy(pfx_server *s) {
     s->worker.join();
     for (void *st : s->streams) pfx_stream_destroy(s->ctx, st);   // also waits for the host functions
     for (auto &kv : s->tickets) delete kv.second;                 // queued, finished and unpolled
-    hipFree(s->arena_mem);
+    (void)hipFree(s->arena_mem);
     delete s;
 }
 

@@ -82,8 +82,14 @@ class QueryPlan:
         self.ops.append((code, dst, a, b, k, value))
 
     def _mr(self, dst, a, b):
-        self._op(X.OP_MUL_RELIN, dst, a, b)
-        self._op(X.OP_RESCALE, dst, dst)
+        if dst in (a, b):      # the product goes to a temporary: the library then
+            t = self._new()    # never stores the tensor product (its output may
+            self._op(X.OP_MUL_RELIN, t, a, b)   # not alias an operand for that)
+            self._op(X.OP_RESCALE, dst, t)
+            self._drop(t)
+        else:
+            self._op(X.OP_MUL_RELIN, dst, a, b)
+            self._op(X.OP_RESCALE, dst, dst)
 
     def _block(self, b: int) -> int:
         A, D = self.attributes, self.degree
