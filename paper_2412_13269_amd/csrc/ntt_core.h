@@ -152,11 +152,20 @@ __device__ __forceinline__ void inv_group(double *v, const PrimeDev &P, bool las
 // within 1.25 q (|a| <= 2^51) or 0.875 q (|a| <= q); the two-stage growth
 // stays below 3.2 q < 2^52.
 template <int NST>
-__device__ __forceinline__ void row_twiddle_bases(double *B, const gdouble *__restrict__ rtw, int P, double q,
-                                                  double qinv) {
-    B[NST - 1] = rtw[P];
+__device__ __forceinline__ void row_twiddle_bases(double *B, double top, double q, double qinv) {
+    B[NST - 1] = top;
 #pragma unroll
     for (int k = NST - 1; k > 0; --k) B[k - 1] = mmul(B[k], B[k], q, qinv);
+}
+
+// The 2^NST - 1 table twiddles of one register group, loaded ahead of the
+// group (index of stage kk, run x: base(kk) + x, kept at W[2^kk - 1 + x]).
+template <int NST, class Idx>
+__device__ __forceinline__ void prefetch_twiddles(double2 *W, const GTw &tw, Idx &&idx) {
+#pragma unroll
+    for (int kk = 0; kk < NST; ++kk)
+#pragma unroll
+        for (int x = 0; x < (1 << kk); ++x) W[(1 << kk) - 1 + x] = tw[idx(kk, x)];
 }
 
 template <int NST>
@@ -309,6 +318,12 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
     const int base = cbase << S;
     auto gidx = [&](int c, int mid) { return ((cbase + c) << S) | mid; };
     auto lidx = [&](int c, int mid) { return c * PAD + mid + (mid >> 4); };
+    // Twiddle operands of the rounds after the first barrier are loaded before
+    // it when each thread owns one group per round (IT == 1, the 2^16 shape),
+    // so that their latency hides under the first round.
+    const gdouble *rt = as_global(INV ? P.irtw : P.rtw);
+    double rtop = 0.0;
+    if (IT2 == 1 && (int)threadIdx.x < n2) rtop = rt[((cbase + ((int)threadIdx.x >> R1)) << R1) | ((int)threadIdx.x & (E1 - 1))];
     if (!INV) {
 #pragma unroll
         for (int gi = 0; gi < IT1; ++gi) {
@@ -335,7 +350,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
                 double v[E2], B[R2];
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
-                row_twiddle_bases<R2>(B, as_global(P.rtw), ((cbase + c) << R1) | mh, q, P.qinv);
+                row_twiddle_bases<R2>(B, IT2 == 1 ? rtop : rt[((cbase + c) << R1) | mh], q, P.qinv);
                 fwd_group_gen<R2>(v, B, P.rc, q, P.qinv);
 #pragma unroll
                 for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
@@ -348,6 +363,11 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
             if (e < tot) store(base + e, mcanon(lds[lidx(e >> S, e & (R - 1))], q), k);
         }
     } else {
+        double2 W1[E1 - 1];
+        if (IT1 == 1 && (int)threadIdx.x < n1) {
+            const int c1 = (int)threadIdx.x >> (S - R1);
+            prefetch_twiddles<R1>(W1, tw, [&](int kk, int x) { return (1 << (s0 + kk)) + (((cbase + c1) << kk) | x); });
+        }
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
             const int e = threadIdx.x + k * TH;
@@ -362,7 +382,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
                 double v[E2], B[R2];
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
-                row_twiddle_bases<R2>(B, as_global(P.irtw), ((cbase + c) << R1) | mh, q, P.qinv);
+                row_twiddle_bases<R2>(B, IT2 == 1 ? rtop : rt[((cbase + c) << R1) | mh], q, P.qinv);
                 inv_group_gen<R2>(v, B, P.irc, q, P.qinv);
 #pragma unroll
                 for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
@@ -378,8 +398,9 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
                 double v[E1];
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = lds[lidx(c, (u << (S - R1)) | ml)];
-                inv_group<R1>(v, P, false,
-                              [&](int kk, int x) { return tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)]; });
+                inv_group<R1>(v, P, false, [&](int kk, int x) {
+                    return IT1 == 1 ? W1[(1 << kk) - 1 + x] : tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)];
+                });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) store(gu(u), v[u], gi * E1 + u);
             }
