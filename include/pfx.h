@@ -188,9 +188,25 @@ pfx_status pfx_relinearize(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *rlk, pf
 /* HMult + relinearisation in one call. */
 pfx_status pfx_mul_relin(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk,
                          pfx_ct *out, void *stream);
+/* HMult + relinearisation of n pairs under one context and key: out[i] =
+ * relin(a[i] * b[i]), word for word what n calls of pfx_mul_relin give.  Pairs
+ * of the same level (min of the operands' levels) share the launches of one
+ * batched key switch, up to 8 pairs per launch: the key residues are read once
+ * for all of them.  Outputs must be distinct and alias no operand of any pair
+ * (PFX_EINVAL); the call validates every pair before it launches anything.
+ * Scratch for the batch is kept with the stream and grows on first use. */
+pfx_status pfx_mul_relin_batch(pfx_ctx *ctx, const pfx_ct *const *a, const pfx_ct *const *b, size_t n,
+                               const pfx_swk *rlk, pfx_ct *const *out, void *stream);
 /* Rescale (Sec. 2.5): round(c / q_last) with round-half-up of the [0, Q)
  * lift; one limb fewer; scale / q_last.  PFX_ELEVEL below 2 limbs. */
 pfx_status pfx_rescale(pfx_ctx *ctx, const pfx_ct *a, pfx_ct *out, void *stream);
+/* Rescale of n ciphertexts: out[i] = rescale(a[i]), word for word what n calls
+ * of pfx_rescale give.  Ciphertexts of the same level and degree share the
+ * four launches of one batched rescale (up to 8 per launch).  out[i] may be
+ * a[i] (in place); it must not alias another entry's input or output
+ * (PFX_EINVAL).  Every entry is validated before anything is launched.
+ * Scratch: the stream's batch region (as pfx_mul_relin_batch). */
+pfx_status pfx_rescale_batch(pfx_ctx *ctx, const pfx_ct *const *a, size_t n, pfx_ct *const *out, void *stream);
 /* Keep the first n_limbs limbs (exact modulus switch to Q_{n_limbs}). */
 pfx_status pfx_drop_level(pfx_ctx *ctx, const pfx_ct *a, uint32_t n_limbs, pfx_ct *out,
                           void *stream);

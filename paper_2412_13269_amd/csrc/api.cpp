@@ -77,6 +77,39 @@ struct Ws {
     double *at(size_t off) const { return base + off; }
 };
 
+// Key-switch scratch of nb batch entries on one stream (dcoef, ext, acc, tmp per
+// entry, sized for the top level), grown on demand and kept with the stream's
+// workspace.
+pfx_status get_batch_ws(pfx_ctx *c, hipStream_t st, int nb, KsBatch &kb) {
+    const size_t N = c->N, L = c->L, K = c->K, E = L + K;
+    const size_t sdc = L * N, sext = (size_t)c->beta * E * N, sacc = 2 * E * N, stmp = 2 * L * N;
+    const size_t per = sdc + sext + sacc + stmp;
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->ws.find(st);
+    if (it == c->ws.end()) return fail(PFX_EINVAL, "stream has no workspace");
+    Workspace *w = it->second;
+    if (w->bcap < nb) {
+        if (c->capturing) return fail(PFX_EINVAL, "batch workspace must be reserved before graph capture");
+        (void)hipStreamSynchronize(st);   // the old region may still be in use on this stream
+        (void)hipFree(w->bbuf);
+        w->bbuf = nullptr;
+        w->bcap = 0;
+        if (hipMalloc(&w->bbuf, (size_t)nb * per * sizeof(double)) != hipSuccess)
+            return fail(PFX_ENOMEM, "batch workspace allocation failed");
+        w->bcap = nb;
+    }
+    double *base = w->bbuf;
+    kb.dcoef = base;
+    kb.ext = base + (size_t)nb * sdc;
+    kb.acc = kb.ext + (size_t)nb * sext;
+    kb.tmp = kb.acc + (size_t)nb * sacc;
+    kb.sdc = sdc;
+    kb.sext = sext;
+    kb.sacc = sacc;
+    kb.stmp = stmp;
+    return PFX_OK;
+}
+
 pfx_status get_ws(pfx_ctx *c, hipStream_t st, Ws &out) {
     std::lock_guard<std::mutex> g(c->mu);
     auto it = c->ws.find(st);
@@ -133,19 +166,19 @@ pfx_status check_out(const pfx_ct *o, uint32_t lv, uint32_t deg) {
     return PFX_OK;
 }
 
-// Key switching (Sec. 2.4.1): out_u = ModDown(sum_j ModUp_j(d) * swk_{j,u}) +
-// base_u, with d and the bases as the operand describes them (KsOperand:
-// plain, read through an automorphism, or formed from a ciphertext product).
-// Six kernels and one row-pass launch, see keyswitch.hip.  The last kernel
-// reads the bases while it writes out0 / out1 from other workgroups, so the
-// outputs must not alias a permuted base (KS_GALOIS) or a product operand
-// (KS_PRODUCT); callers copy or fall back first.
-void ks_core(pfx_ctx *c, const Launch &L, const Ws &w, const KsOperand &op, int lv, const pfx_swk *key,
-             double *out0, double *out1) {
+// Key switching (Sec. 2.4.1) of a batch: for every entry b, out_u = ModDown(
+// sum_j ModUp_j(d) * swk_{j,u}) + base_u, with d and the bases as the
+// operand describes them (KsOperand: plain, read through an automorphism, or
+// formed from a ciphertext product).  Six kernels and one row-pass launch,
+// each covering the whole batch (keyswitch.hip).  The last kernel reads the
+// bases while other workgroups write the outputs, so no output may alias a
+// permuted base (KS_GALOIS) or a product operand (KS_PRODUCT) of any entry;
+// callers copy or fall back first.
+void ks_run(const Launch &L, const KsBatch &kb, int lv, const pfx_swk *key) {
+    pfx_ctx *c = L.ctx;
     const int E = lv + c->K;
-    double *dcoef = w.at(w.lay.dcoef), *ext = w.at(w.lay.ext), *acc = w.at(w.lay.acc), *tmp = w.at(w.lay.mdtmp);
-    launch_intt_scale(L, dcoef, op, lv);
-    launch_modup_col(L, ext, dcoef, lv);
+    launch_intt_scale(L, kb, lv);
+    launch_modup_col(L, kb, lv);
     const int beta = (lv + c->alpha - 1) / c->alpha;
     LimbMap m;
     m.n = 0;
@@ -155,16 +188,33 @@ void ks_core(pfx_ctx *c, const Launch &L, const Ws &w, const KsOperand &op, int 
             m.off[m.n] = j * E + t;
             m.pid[m.n] = (int16_t)(t < j * c->alpha ? t : (t < lv - sz ? t + sz : c->L + (t - (lv - sz))));
             if (++m.n == kMaxMapLimbs) {
-                launch_ntt_pass(L, ext, nullptr, m, true, false);
+                launch_ntt_pass(L, kb.ext, nullptr, m, true, false, kb.nb, kb.sext);
                 m.n = 0;
             }
         }
     }
-    launch_ntt_pass(L, ext, nullptr, m, true, false);
-    launch_ks_inner(L, acc, ext, op, key->d_k, lv);
-    launch_intt_special(L, acc, lv);
-    launch_moddown_col(L, tmp, acc, lv);
-    launch_row_moddown(L, out0, out1, acc, tmp, op, lv);
+    launch_ntt_pass(L, kb.ext, nullptr, m, true, false, kb.nb, kb.sext);
+    launch_ks_inner(L, kb, key->d_k, lv);
+    launch_intt_special(L, kb, lv);
+    launch_moddown_col(L, kb, lv);
+    launch_row_moddown(L, kb, lv);
+}
+
+// One key switch in the stream's scratch.
+void ks_core(pfx_ctx *c, const Launch &L, const Ws &w, const KsOperand &op, int lv, const pfx_swk *key,
+             double *out0, double *out1) {
+    (void)c;
+    KsBatch kb;
+    kb.nb = 1;
+    kb.mode = op.mode;
+    kb.op[0] = op;
+    kb.out0[0] = out0;
+    kb.out1[0] = out1;
+    kb.dcoef = w.at(w.lay.dcoef);
+    kb.ext = w.at(w.lay.ext);
+    kb.acc = w.at(w.lay.acc);
+    kb.tmp = w.at(w.lay.mdtmp);
+    ks_run(L, kb, lv, key);
 }
 
 KsOperand ks_plain(const double *d, const double *base0, const double *base1) {
@@ -261,14 +311,91 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
     return PFX_OK;
 }
 
-pfx_status run_ops(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
-                   size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
-                   const pfx_swk *const *gks, size_t n_gks, void *stream) {
-    for (size_t i = 0; i < n_ops; ++i) {
+// Length of the run of ops starting at ops[i] that one batched launch sequence
+// may take: consecutive HMult + relin ops (or consecutive rescales), at most
+// max_batch, outputs distinct and none of them an operand of another op of the
+// run, so the ops are independent.  An HMult + relin output must not alias its
+// own operands either (the batched key switch reads them while it writes); a
+// rescale may work in place.  1 if ops[i] alone; 0 for any other op.
+size_t mr_run(const pfx_op *ops, size_t n_ops, size_t i, int max_batch) {
+    const int32_t code = ops[i].code;
+    if (code != PFX_OP_MUL_RELIN && code != PFX_OP_RESCALE) return 0;
+    const bool mr = code == PFX_OP_MUL_RELIN;
+    auto reads = [&](const pfx_op &o, int32_t r) { return o.a == r || (mr && o.b == r); };
+    const pfx_op &f = ops[i];
+    if (mr && reads(f, f.dst)) return 1;
+    size_t j = i + 1;
+    for (; j < n_ops && j - i < (size_t)max_batch && ops[j].code == code; ++j) {
+        const pfx_op &o = ops[j];
+        bool ok = !(mr && reads(o, o.dst));
+        for (size_t k = i; k < j && ok; ++k) {
+            const pfx_op &p = ops[k];
+            ok = o.dst != p.dst && !reads(p, o.dst) && !reads(o, p.dst);
+        }
+        if (!ok) break;
+    }
+    return j - i;
+}
+
+// Largest batch that run_span will hand to one batched call.
+size_t max_mr_run(const pfx_op *ops, size_t n_ops, int max_batch) {
+    size_t m = 0;
+    for (size_t i = 0; i < n_ops;) {
+        const size_t r = mr_run(ops, n_ops, i, max_batch);
+        m = std::max(m, r);
+        i += r ? r : 1;
+    }
+    return m;
+}
+
+// ops[lo, hi) on one stream; runs of independent HMult + relin ops or
+// rescales (mr_run) go to pfx_mul_relin_batch / pfx_rescale_batch when
+// max_batch > 1.
+pfx_status run_span(pfx_ctx *c, const pfx_op *ops, size_t lo, size_t hi, pfx_ct *const *regs, size_t n_regs,
+                    size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
+                    const pfx_swk *const *gks, size_t n_gks, void *stream, int max_batch) {
+    for (size_t i = lo; i < hi;) {
+        const size_t run = max_batch > 1 ? mr_run(ops, hi, i, max_batch) : 0;
+        if (run > 1) {
+            const bool mr = ops[i].code == PFX_OP_MUL_RELIN;
+            const pfx_ct *a[kMaxBatch], *b[kMaxBatch];
+            pfx_ct *out[kMaxBatch];
+            bool distinct = true;       // distinct registers may still name one ciphertext
+            for (size_t k = 0; k < run; ++k) {
+                const pfx_op &o = ops[i + k];
+                auto R = [&](int32_t x) -> pfx_ct * { return (x >= 0 && (size_t)x < n_regs) ? regs[x] : nullptr; };
+                a[k] = R(o.a);
+                b[k] = mr ? R(o.b) : a[k];
+                out[k] = R(o.dst);
+                if (!a[k] || !b[k] || !out[k] || (size_t)o.dst < n_inputs) {
+                    distinct = false;   // run_op reports the error
+                    break;
+                }
+            }
+            for (size_t k = 0; k < run && distinct; ++k)
+                for (size_t m = 0; m < run && distinct; ++m) {
+                    if (k != m) distinct = out[k]->d != a[m]->d && out[k]->d != b[m]->d && out[k]->d != out[m]->d;
+                    else if (mr) distinct = out[k]->d != a[k]->d && out[k]->d != b[k]->d;
+                }
+            if (distinct) {
+                pfx_status r = mr ? pfx_mul_relin_batch(c, a, b, run, rlk, out, stream)
+                                  : pfx_rescale_batch(c, a, run, out, stream);
+                if (r) return fail(r, "ops " + std::to_string(i) + ".." + std::to_string(i + run - 1) + ": " + g_err);
+                i += run;
+                continue;
+            }
+        }
         pfx_status r = run_op(c, i, ops[i], regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream);
         if (r) return r;
+        ++i;
     }
     return PFX_OK;
+}
+
+pfx_status run_ops(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
+                   size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
+                   const pfx_swk *const *gks, size_t n_gks, void *stream, int max_batch) {
+    return run_span(c, ops, 0, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream, max_batch);
 }
 
 }  // namespace pfx
@@ -505,6 +632,7 @@ void pfx_ctx_destroy(pfx_ctx *c) {
     (void)hipDeviceSynchronize();
     for (auto &kv : c->ws) {
         (void)hipFree(kv.second->buf);
+        (void)hipFree(kv.second->bbuf);
         delete kv.second;
     }
     for (auto &e : c->prof_pending) {
@@ -1024,6 +1152,77 @@ pfx_status pfx_mul_relin(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx
     return PFX_OK;
 }
 
+// Batched HMult + relinearisation: entries of one level share every launch
+// of the key switch (the key residues are read once per launch for all of
+// them), at most kMaxBatch entries per launch.
+pfx_status mul_relin_group(pfx_ctx *c, const Launch &L, const pfx_ct *const *a, const pfx_ct *const *b,
+                           pfx_ct *const *out, const int *idx, int nb, int lv, const pfx_swk *rlk) {
+    KsBatch kb;
+    pfx_status r = get_batch_ws(c, L.st, nb, kb);
+    if (r) return r;
+    kb.nb = nb;
+    kb.mode = KS_PRODUCT;
+    for (int e = 0; e < nb; ++e) {
+        const int i = idx[e];
+        KsOperand &op = kb.op[e];
+        op.mode = KS_PRODUCT;
+        op.a0 = a[i]->poly(0);
+        op.a1 = a[i]->poly(1);
+        op.b0 = b[i]->poly(0);
+        op.b1 = b[i]->poly(1);
+        kb.out0[e] = out[i]->poly(0);
+        kb.out1[e] = out[i]->poly(1);
+    }
+    ks_run(L, kb, lv, rlk);
+    return PFX_OK;
+}
+
+pfx_status pfx_mul_relin_batch(pfx_ctx *c, const pfx_ct *const *a, const pfx_ct *const *b, size_t n,
+                               const pfx_swk *rlk, pfx_ct *const *out, void *stream) {
+    REQUIRE(c && (n == 0 || (a && b && out)), PFX_EINVAL, "null argument");
+    REQUIRE(rlk && rlk->ctx == c, PFX_EINVAL, "bad relinearisation key");
+    REQUIRE(rlk->galois == 0, PFX_ENOKEY, "key is not a relinearisation key");
+    std::vector<uint32_t> lvs(n);
+    for (size_t i = 0; i < n; ++i) {
+        pfx_status r = check_ct(c, a[i], "a");
+        if (r) return r;
+        r = check_ct(c, b[i], "b");
+        if (r) return r;
+        REQUIRE(a[i]->degree == 1 && b[i]->degree == 1, PFX_EINVAL, "mul_relin needs two degree-1 ciphertexts");
+        lvs[i] = std::min(a[i]->n_limbs, b[i]->n_limbs);
+        r = check_out(out[i], lvs[i], 1);
+        if (r) return r;
+    }
+    for (size_t i = 0; i < n; ++i)           // the last launch reads operands while writing outputs
+        for (size_t j = 0; j < n; ++j) {
+            REQUIRE(out[i]->d != a[j]->d && out[i]->d != b[j]->d, PFX_EINVAL,
+                    "batched mul_relin output aliases an operand");
+            REQUIRE(i == j || out[i]->d != out[j]->d, PFX_EINVAL, "batched mul_relin outputs alias");
+        }
+    if (n == 0) return PFX_OK;
+    Ws w;
+    pfx_status r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    std::vector<int> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return lvs[x] > lvs[y]; });
+    for (size_t s0 = 0; s0 < n;) {
+        size_t s1 = s0;
+        while (s1 < n && s1 - s0 < (size_t)kMaxBatch && lvs[order[s1]] == lvs[order[s0]]) ++s1;
+        r = mul_relin_group(c, L, a, b, out, &order[s0], (int)(s1 - s0), (int)lvs[order[s0]], rlk);
+        if (r) return r;
+        s0 = s1;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        const double sc = a[i]->scale * b[i]->scale;
+        out[i]->n_limbs = lvs[i];
+        out[i]->degree = 1;
+        out[i]->scale = sc;
+    }
+    return PFX_OK;
+}
+
 pfx_status pfx_rescale(pfx_ctx *c, const pfx_ct *a, pfx_ct *out, void *stream) {
     pfx_status r = check_ct(c, a, "a");
     if (r) return r;
@@ -1040,10 +1239,76 @@ pfx_status pfx_rescale(pfx_ctx *c, const pfx_ct *a, pfx_ct *out, void *stream) {
     double *last = w.at(w.lay.rs_last), *tmp = w.at(w.lay.rs_tmp);
     const double sc = a->scale / (double)c->primes[lv - 1];
     const uint32_t deg = a->degree;
-    launch_rescale(L, out->d, out->cap_limbs * N, a->d, a->cap_limbs * N, np, lv, last, tmp);
+    RsEntry e;
+    e.in = a->d;
+    e.out = out->d;
+    e.si = a->cap_limbs * N;
+    e.so = out->cap_limbs * N;
+    launch_rescale(L, &e, 1, np, lv, last, tmp);
     out->n_limbs = lv - 1;
     out->degree = deg;
     out->scale = sc;
+    return PFX_OK;
+}
+
+pfx_status pfx_rescale_batch(pfx_ctx *c, const pfx_ct *const *a, size_t n, pfx_ct *const *out, void *stream) {
+    REQUIRE(c && (n == 0 || (a && out)), PFX_EINVAL, "null argument");
+    for (size_t i = 0; i < n; ++i) {
+        pfx_status r = check_ct(c, a[i], "a");
+        if (r) return r;
+        REQUIRE(a[i]->n_limbs >= 2, PFX_ELEVEL, "rescale needs at least 2 limbs");
+        r = check_out(out[i], a[i]->n_limbs - 1, a[i]->degree);
+        if (r) return r;
+    }
+    for (size_t i = 0; i < n; ++i)        // an entry may rescale in place, never into another's input
+        for (size_t j = 0; j < n; ++j)
+            if (i != j) {
+                REQUIRE(out[i]->d != a[j]->d, PFX_EINVAL, "batched rescale output aliases another input");
+                REQUIRE(out[i]->d != out[j]->d, PFX_EINVAL, "batched rescale outputs alias");
+            }
+    if (n == 0) return PFX_OK;
+    Ws w;
+    pfx_status r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    std::vector<int> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = (int)i;
+    auto shape = [&](int i) { return a[i]->n_limbs * 4 + a[i]->degree; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return shape(x) > shape(y); });
+    std::vector<double> sc(n);
+    std::vector<uint32_t> deg(n), lvs(n);
+    for (size_t i = 0; i < n; ++i) {
+        lvs[i] = a[i]->n_limbs;
+        deg[i] = a[i]->degree;
+        sc[i] = a[i]->scale / (double)c->primes[lvs[i] - 1];
+    }
+    for (size_t s0 = 0; s0 < n;) {
+        size_t s1 = s0;
+        while (s1 < n && s1 - s0 < (size_t)kMaxBatch && shape(order[s1]) == shape(order[s0])) ++s1;
+        const int nb = (int)(s1 - s0), lv = (int)lvs[order[s0]], np = (int)deg[order[s0]] + 1;
+        // scratch: the batch key-switch region, used flat (np lv limbs per entry fit
+        // in its dcoef + tmp share of 3 L limbs)
+        KsBatch kb;
+        r = get_batch_ws(c, S(stream), nb, kb);
+        if (r) return r;
+        double *last = kb.dcoef, *tmp = last + (size_t)nb * np * N;
+        RsEntry ents[kMaxBatch];
+        for (int e = 0; e < nb; ++e) {
+            const int i = order[s0 + e];
+            ents[e].in = a[i]->d;
+            ents[e].out = out[i]->d;
+            ents[e].si = a[i]->cap_limbs * N;
+            ents[e].so = out[i]->cap_limbs * N;
+        }
+        launch_rescale(L, ents, nb, np, lv, last, tmp);
+        s0 = s1;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        out[i]->n_limbs = lvs[i] - 1;
+        out[i]->degree = deg[i];
+        out[i]->scale = sc[i];
+    }
     return PFX_OK;
 }
 
@@ -1308,7 +1573,10 @@ static pfx_status run_ops_lanes(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx
     for (size_t i = 0; i < n_ops && !res; ++i) {
         const pfx_op &o = ops[i];
         if (o.code != PFX_OP_LANE) {
-            res = run_op(c, i, o, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, cur);
+            size_t j = i + 1;
+            while (j < n_ops && ops[j].code != PFX_OP_LANE) ++j;
+            res = run_span(c, ops, i, j, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, cur, kMaxBatch);
+            i = j - 1;
             continue;
         }
         if (o.k == -1) {
@@ -1339,7 +1607,8 @@ pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *
     const bool lanes = (mode & PFX_RUN_LANES) != 0;
     auto exec = [&]() {
         return lanes ? run_ops_lanes(c, ops, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream)
-                     : run_ops(c, ops, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream);
+                     : run_ops(c, ops, n_ops, regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream,
+                               kMaxBatch);
     };
     if (!(mode & PFX_RUN_GRAPH)) return exec();
     REQUIRE(stream != nullptr, PFX_EINVAL, "graph capture needs a non-default stream");
@@ -1362,9 +1631,16 @@ pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *
         Ws w;
         pfx_status r = get_ws(c, S(stream), w);   // allocate scratch before capturing
         if (r) return r;
+        const int nb = (int)max_mr_run(ops, n_ops, kMaxBatch);
+        KsBatch kb;
+        if (nb > 1 && !lanes) r = get_batch_ws(c, S(stream), nb, kb);
+        if (r) return r;
         if (lanes) {
             r = ensure_lanes(c);
-            for (int l = 0; l < kLanes && !r; ++l) r = get_ws(c, c->lanes[l], w);
+            for (int l = 0; l < kLanes && !r; ++l) {
+                r = get_ws(c, c->lanes[l], w);
+                if (!r && nb > 1) r = get_batch_ws(c, c->lanes[l], nb, kb);
+            }
             if (r) return r;
         }
         const bool prof = c->prof_on;
@@ -1553,6 +1829,7 @@ pfx_status pfx_stream_destroy(pfx_ctx *c, void *stream) {
         auto it = c->ws.find(S(stream));
         if (it != c->ws.end()) {
             (void)hipFree(it->second->buf);
+            (void)hipFree(it->second->bbuf);
             delete it->second;
             c->ws.erase(it);
         }

@@ -68,6 +68,8 @@ struct Workspace {
     hipStream_t stream = nullptr;
     double *buf = nullptr;
     size_t doubles = 0;
+    double *bbuf = nullptr;   // batched key-switch scratch (bcap entries), on demand
+    int bcap = 0;
 };
 
 struct ProfEntry {
@@ -160,10 +162,12 @@ void decode_words(int logn, const uint64_t *words, int n_limbs, const std::vecto
                   double scale, size_t n, double *re, double *im);
 
 // Op-list interpreter behind pfx_run_circuit (api.cpp): registers 0..n_inputs-1
-// are read-only, every op is launched on `stream`.
+// are read-only, every op is launched on `stream`.  With max_batch > 1, runs of
+// up to max_batch independent HMult + relin ops share one batched key switch
+// (its scratch grows with the stream's workspace); 1 runs every op alone.
 pfx_status run_ops(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
                    size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
-                   const pfx_swk *const *gks, size_t n_gks, void *stream);
+                   const pfx_swk *const *gks, size_t n_gks, void *stream, int max_batch);
 // Bytes of the per-stream scratch, and its allocation for one stream.
 size_t ws_bytes(const pfx_ctx *c);
 pfx_status ws_reserve(pfx_ctx *c, hipStream_t st);
@@ -179,8 +183,10 @@ void prof_end(const Launch &L, const char *name, hipEvent_t ev, double bytes);
 
 // Batched NTT over the limbs of `map`; src == nullptr means in place.
 void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap &map, bool inverse);
-// One pass (column: the first log N / 2 stages; row: the rest) of the same transform.
-void launch_ntt_pass(const Launch &L, double *base, const double *src, const LimbMap &map, bool row, bool inverse);
+// One pass (column: the first log N / 2 stages; row: the rest) of the same transform;
+// nb copies of the map at base + b * bstride (doubles).
+void launch_ntt_pass(const Launch &L, double *base, const double *src, const LimbMap &map, bool row, bool inverse,
+                     int nb = 1, size_t bstride = 0);
 void launch_u64_to_f64(const Launch &L, double *out, const uint64_t *in, size_t n);
 void launch_f64_to_u64(const Launch &L, uint64_t *out, const double *in, size_t n);
 void launch_int_to_rns(const Launch &L, double *out, const int64_t *in, int n_limbs, int pid0,
@@ -211,18 +217,36 @@ struct KsOperand {
     uint32_t galois = 0;
     const double *a0 = nullptr, *a1 = nullptr, *b0 = nullptr, *b1 = nullptr;
 };
-void launch_ks_inner(const Launch &L, double *acc, const double *ext, const KsOperand &op, const double *key, int lv);
-// Rescale of np polynomials of lv limbs (rescale.hip): in/out poly strides in
-// doubles, `last` (np limbs) and `tmp` (np (lv - 1) limbs) scratch.
-void launch_rescale(const Launch &L, double *out, size_t so, const double *in, size_t si, int np, int lv,
-                    double *last, double *tmp);
+// A batch of key switches at one level with one key and one mode: entry b
+// switches op[b] into (out0[b], out1[b]); its scratch regions sit at entry 0's
+// (dcoef, ext, acc, tmp) plus b times the strides, in doubles.  Every kernel of
+// the key switch covers the whole batch in one launch, and the inner product
+// reads each key residue once for all entries.
+constexpr int kMaxBatch = 8;
+struct KsBatch {
+    int nb = 1, mode = KS_PLAIN;
+    KsOperand op[kMaxBatch];
+    double *out0[kMaxBatch] = {}, *out1[kMaxBatch] = {};
+    double *dcoef = nullptr, *ext = nullptr, *acc = nullptr, *tmp = nullptr;
+    size_t sdc = 0, sext = 0, sacc = 0, stmp = 0;
+};
+void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int lv);
+// Rescale of nb ciphertexts of np polynomials at lv limbs (rescale.hip): entry
+// b reads ents[b].in and writes ents[b].out (which may equal in), polynomials
+// si / so doubles apart; scratch `last` (nb np limbs) and `tmp` (nb np (lv - 1)
+// limbs).
+struct RsEntry {
+    const double *in = nullptr;
+    double *out = nullptr;
+    size_t si = 0, so = 0;
+};
+void launch_rescale(const Launch &L, const RsEntry *ents, int nb, int np, int lv, double *last, double *tmp);
 // Fused key-switching steps (keyswitch.hip).
-void launch_intt_scale(const Launch &L, double *dcoef, const KsOperand &op, int lv);
-void launch_modup_col(const Launch &L, double *ext, const double *dcoef, int lv);
-void launch_intt_special(const Launch &L, double *acc, int lv);
-void launch_moddown_col(const Launch &L, double *tmp, const double *acc, int lv);
-void launch_row_moddown(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
-                        const KsOperand &op, int lv);
+void launch_intt_scale(const Launch &L, const KsBatch &kb, int lv);
+void launch_modup_col(const Launch &L, const KsBatch &kb, int lv);
+void launch_intt_special(const Launch &L, const KsBatch &kb, int lv);
+void launch_moddown_col(const Launch &L, const KsBatch &kb, int lv);
+void launch_row_moddown(const Launch &L, const KsBatch &kb, int lv);
 void launch_keygen_b(const Launch &L, double *b, const double *a, const double *e, const double *s,
                      const double *sfrom, int digit);
 void launch_encrypt(const Launch &L, double *c0, const double *a, const double *e, const double *s,

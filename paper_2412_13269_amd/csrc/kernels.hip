@@ -36,6 +36,7 @@ struct NttArgs {
     int C;
     int tiles;
     int nblk;
+    size_t bstride;   // batch copies of the map, this many doubles apart
     LimbMap map;
 };
 
@@ -44,10 +45,11 @@ __global__ __launch_bounds__(TH) void k_ntt_pass(const NttArgs a) {
     __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.nblk);
     if (id >= a.nblk) return;
-    const int limb = id / a.tiles;
-    const int tile = id - limb * a.tiles;
+    const int bl = id / a.tiles;
+    const int tile = id - bl * a.tiles;
+    const int bi = bl / a.map.n, limb = bl - bi * a.map.n;
     const PrimeDev &P = a.primes[a.map.pid[limb]];
-    const size_t loff = (size_t)a.map.off[limb] << a.logn;
+    const size_t loff = ((size_t)a.map.off[limb] << a.logn) + bi * a.bstride;
     double *dst = a.dst + loff;
     const double *src = a.src + loff;
     auto ld = [&](int j, int) { return src[j]; };
@@ -77,8 +79,9 @@ static void dispatch_th(bool row, bool inverse, int S, dim3 grid, hipStream_t st
     }
 }
 
-void launch_ntt_pass(const Launch &L, double *base, const double *src, const LimbMap &map, bool row, bool inverse) {
-    if (map.n <= 0) return;
+void launch_ntt_pass(const Launch &L, double *base, const double *src, const LimbMap &map, bool row, bool inverse,
+                     int nb, size_t bstride) {
+    if (map.n <= 0 || nb <= 0) return;
     pfx_ctx *ctx = L.ctx;
     const int logn = ctx->logn;
     NttArgs a;
@@ -86,28 +89,29 @@ void launch_ntt_pass(const Launch &L, double *base, const double *src, const Lim
     a.primes = ctx->d_primes;
     a.logn = logn;
     a.map = map;
-    const int th = pass_threads(logn, map.n, row);
+    const int th = pass_threads(logn, nb * map.n, row);
     PassShape ps = row ? row_shape(logn, th * kSlots) : col_shape(logn, th * kSlots);
     // very small batches: narrower tiles (idle threads) so that the launch
     // still covers the CUs (column tiles stay >= 8 columns = 64-byte rows)
     const int minC = row ? 1 : 8;
-    while (map.n * ps.tiles < 1024 && ps.C / 2 >= minC) {
+    while (nb * map.n * ps.tiles < 1024 && ps.C / 2 >= minC) {
         ps.C /= 2;
         ps.tiles *= 2;
     }
     a.C = ps.C;
     a.tiles = ps.tiles;
-    a.nblk = map.n * ps.tiles;
+    a.nblk = nb * map.n * ps.tiles;
+    a.bstride = bstride;
     a.src = src ? src : base;
     dim3 grid(xcd_grid(a.nblk));
     hipEvent_t ev;
     char nm[32];
     std::snprintf(nm, sizeof nm, "%s/%d", inverse ? (row ? "intt_row" : "intt_col") : (row ? "ntt_row" : "ntt_col"),
-                  map.n);
+                  nb * map.n);
     prof_begin(L, nm, &ev);
     PFX_SWITCH_TH(th, (dispatch_th<TH>(row, inverse, ps.S, grid, L.st, a)));
     HIP_LAUNCH_CHECK();
-    prof_end(L, nm, ev, 16.0 * (double)ctx->N * map.n);
+    prof_end(L, nm, ev, 16.0 * (double)ctx->N * map.n * nb);
 }
 
 void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap &map, bool inverse) {
@@ -331,75 +335,109 @@ void launch_automorph(const Launch &L, double *out, const double *in, size_t so,
 //   ext[j][t][c]  digit j's fast conversion to the E - sz_j primes outside the
 //                 digit, t in the order: q's below the digit, q's above, p's;
 //   acc[u][m][c]  u in {0, 1}, m < E: q_0..q_{lv-1} then p_0..p_{K-1}.
-// acc_u[m] = sum_j dtilde_j[m] * swk_{j,u}[m]   (NTT domain).  The digit's own
-// primes take d itself: phi_g(d_in) read through galois_src (KS_GALOIS), or
-// a1 b1 formed from the product's operands (KS_PRODUCT, d_ntt = a1, d2 = b1).
+// acc_u[m] = sum_j dtilde_j[m] * swk_{j,u}[m]   (NTT domain), for every entry
+// of a key-switch batch: each key residue is loaded once and used by all
+// entries.  The digit's own primes take d itself: phi_g(d_in) read through
+// galois_src (KS_GALOIS), or a1 b1 formed from the product's operands
+// (KS_PRODUCT).
+struct InnerArgs {
+    const double *ext, *key;
+    double *acc;
+    size_t sext, sacc;
+    int nb, lv, logn, L, K, alpha;
+    const PrimeDev *pr;
+    const double *d[kMaxBatch], *d2[kMaxBatch];
+    uint32_t g[kMaxBatch];
+};
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_ks_inner(double *acc, const double *ext, const double *d_ntt,
-                                                  const double *d2, const double *key, int lv, int logn, int L,
-                                                  int K, int alpha, const PrimeDev *pr, uint32_t g) {
-    constexpr int kChunk = 4;   // digits whose 3 loads are all in flight before any product
+__global__ __launch_bounds__(256) void k_ks_inner(const InnerArgs a) {
     const int m = blockIdx.y;
+    const int logn = a.logn;
     const size_t N = (size_t)1 << logn;
     const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (c >= N) return;
-    const int E = lv + K;
+    const int lv = a.lv, E = lv + a.K, alpha = a.alpha;
     const int beta = (lv + alpha - 1) / alpha;
-    const int pid = m < lv ? m : L + (m - lv);
-    const double q = pr[pid].q, qi = pr[pid].qinv;
-    const size_t kstride = (size_t)(L + K) * N;
-    const double *k0 = key + ((size_t)pid << logn) + c;
-    const size_t dof = ((size_t)m << logn) + (MODE == KS_GALOIS ? galois_src((uint32_t)c, logn, g) : c);
-    // products in [0, q) summed lazily; a chunk leaves a < q + 4q < 2^53, which
-    // mred reduces exactly (its quotient estimate is off by at most one there)
-    double a0 = 0.0, a1 = 0.0;
-    for (int jb = 0; jb < beta; jb += kChunk) {
-        double x[kChunk], w0[kChunk], w1[kChunk];
+    const int pid = m < lv ? m : a.L + (m - lv);
+    const double q = a.pr[pid].q, qi = a.pr[pid].qinv;
+    const size_t kstride = (size_t)(a.L + a.K) * N;
+    const double *k0 = a.key + ((size_t)pid << logn) + c;
+    const size_t lm = (size_t)m << logn;
+    // products in [0, q) summed lazily; every digit is followed by a reduction
+    // once more than four products have accumulated (< 5q < 2^53, which mred
+    // reduces exactly: its quotient estimate is off by at most one there)
+    double a0[kMaxBatch], a1[kMaxBatch];
 #pragma unroll
-        for (int t = 0; t < kChunk; ++t) {
-            const int j = jb + t;
-            if (j < beta) {
-                const int j0 = j * alpha;
-                const int sz = min(alpha, lv - j0);
-                if (m >= j0 && m < j0 + sz) {
-                    x[t] = MODE == KS_PRODUCT ? mmul(d_ntt[dof], d2[dof], q, qi) : d_ntt[dof];
+    for (int b = 0; b < kMaxBatch; ++b) a0[b] = a1[b] = 0.0;
+    for (int j = 0; j < beta; ++j) {
+        const int j0 = j * alpha;
+        const int sz = min(alpha, lv - j0);
+        const bool own = m >= j0 && m < j0 + sz;
+        const int tt = m < j0 ? m : m - sz;
+        const double w0 = k0[(size_t)(2 * j) * kstride];
+        const double w1 = k0[(size_t)(2 * j + 1) * kstride];
+#pragma unroll
+        for (int b = 0; b < kMaxBatch; ++b) {
+            if (b < a.nb) {
+                double x;
+                if (own) {
+                    if (MODE == KS_GALOIS) x = a.d[b][lm + galois_src((uint32_t)c, logn, a.g[b])];
+                    else if (MODE == KS_PRODUCT) x = mmul(a.d[b][lm + c], a.d2[b][lm + c], q, qi);
+                    else x = a.d[b][lm + c];
                 } else {
-                    const int tt = m < j0 ? m : m - sz;
-                    x[t] = ext[((size_t)j * E + tt) * N + c];
+                    x = a.ext[b * a.sext + ((size_t)j * E + tt) * N + c];
                 }
-                w0[t] = k0[(size_t)(2 * j) * kstride];
-                w1[t] = k0[(size_t)(2 * j + 1) * kstride];
+                a0[b] += mmul(x, w0, q, qi);
+                a1[b] += mmul(x, w1, q, qi);
+                if ((j & 3) == 3) {
+                    a0[b] = mred(a0[b], q, qi);
+                    a1[b] = mred(a1[b], q, qi);
+                }
             }
         }
-#pragma unroll
-        for (int t = 0; t < kChunk; ++t) {
-            if (jb + t < beta) {
-                a0 += mmul(x[t], w0[t], q, qi);
-                a1 += mmul(x[t], w1[t], q, qi);
-            }
-        }
-        a0 = mred(a0, q, qi);
-        a1 = mred(a1, q, qi);
     }
-    acc[((size_t)m << logn) + c] = a0;
-    acc[((size_t)(E + m) << logn) + c] = a1;
+#pragma unroll
+    for (int b = 0; b < kMaxBatch; ++b) {
+        if (b < a.nb) {
+            a.acc[b * a.sacc + lm + c] = mred(a0[b], q, qi);
+            a.acc[b * a.sacc + ((size_t)(E + m) << logn) + c] = mred(a1[b], q, qi);
+        }
+    }
 }
 
-void launch_ks_inner(const Launch &L, double *acc, const double *ext, const KsOperand &op, const double *key, int lv) {
+void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int lv) {
     pfx_ctx *ctx = L.ctx;
+    InnerArgs a;
+    a.ext = kb.ext;
+    a.key = key;
+    a.acc = kb.acc;
+    a.sext = kb.sext;
+    a.sacc = kb.sacc;
+    a.nb = kb.nb;
+    a.lv = lv;
+    a.logn = ctx->logn;
+    a.L = ctx->L;
+    a.K = ctx->K;
+    a.alpha = ctx->alpha;
+    a.pr = ctx->d_primes;
+    for (int b = 0; b < kMaxBatch; ++b) {
+        const KsOperand &o = kb.op[b];
+        const bool on = b < kb.nb;
+        a.d[b] = on ? (kb.mode == KS_PRODUCT ? o.a1 : o.d) : nullptr;
+        a.d2[b] = on && kb.mode == KS_PRODUCT ? o.b1 : nullptr;
+        a.g[b] = on ? o.galois : 0;
+    }
     dim3 grid((ctx->N + 255) / 256, lv + ctx->K);
-    const double *d1 = op.mode == KS_PRODUCT ? op.a1 : op.d, *d2 = op.mode == KS_PRODUCT ? op.b1 : nullptr;
     hipEvent_t ev;
     prof_begin(L, "ks_inner", &ev);
-#define PFX_KS_INNER(MD)                                                                                         \
-    k_ks_inner<MD><<<grid, 256, 0, L.st>>>(acc, ext, d1, d2, key, lv, ctx->logn, ctx->L, ctx->K, ctx->alpha,       \
-                                           ctx->d_primes, op.galois)
-    if (op.mode == KS_GALOIS) PFX_KS_INNER(KS_GALOIS);
-    else if (op.mode == KS_PRODUCT) PFX_KS_INNER(KS_PRODUCT);
-    else PFX_KS_INNER(KS_PLAIN);
-#undef PFX_KS_INNER
+    if (kb.mode == KS_GALOIS) k_ks_inner<KS_GALOIS><<<grid, 256, 0, L.st>>>(a);
+    else if (kb.mode == KS_PRODUCT) k_ks_inner<KS_PRODUCT><<<grid, 256, 0, L.st>>>(a);
+    else k_ks_inner<KS_PLAIN><<<grid, 256, 0, L.st>>>(a);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "ks_inner", ev, 8.0 * (double)ctx->N * (lv + ctx->K) * (3.0 * ((lv + ctx->alpha - 1) / ctx->alpha) + 2.0));
+    // per entry: ext / d and the accumulators; the key once for the batch
+    const int beta = (lv + ctx->alpha - 1) / ctx->alpha;
+    prof_end(L, "ks_inner", ev, 8.0 * (double)ctx->N * (lv + ctx->K) * ((beta + 2.0) * kb.nb + 2.0 * beta));
 }
 
 // ============================================================== keys, encryption

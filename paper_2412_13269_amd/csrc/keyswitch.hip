@@ -40,6 +40,19 @@ namespace pfx {
         if (e_ != hipSuccess) set_error(std::string("kernel launch: ") + hipGetErrorString(e_)); \
     } while (0)
 
+// One batch entry: its operand (KsOperand) and outputs, as plain pointers.
+//   KS_GALOIS: the key-switched polynomial is phi_galois of d;
+//   KS_PRODUCT: the operands of a ciphertext product (a0, a1) x (b0, b1):
+//   d = a1 b1 and the bases a0 b0, a0 b1 + a1 b0 are formed where they are read.
+struct KsEntry {
+    const double *d, *base0, *base1, *a0, *a1, *b0, *b1;
+    double *out0, *out1;
+    uint32_t galois;
+};
+
+// Kernel arguments.  A launch covers nb batch entries (same level, key and
+// mode): logical block id = entry * per + the entry's own block id, and the
+// entry's scratch regions sit at the given strides (in doubles) from entry 0's.
 struct KsArgs {
     const PrimeDev *primes;
     const ModUpConst *mu;
@@ -47,10 +60,9 @@ struct KsArgs {
     int logn, lv, L, K, alpha, beta, E;
     int C, tiles;   // pass geometry (column or row, per kernel)
     int n;          // logical blocks
-    uint32_t galois;   // KS_GALOIS: the key-switched polynomial is phi_galois of the one passed in
-    // KS_PRODUCT: the operands of a ciphertext product (a0, a1) x (b0, b1):
-    // d = a1 b1 and the bases a0 b0, a0 b1 + a1 b0 are formed where they are read
-    const double *a0, *a1, *b0, *b1;
+    int nb, per;    // batch entries, blocks per entry
+    size_t sdc, sext, sacc, stmp;
+    KsEntry op[kMaxBatch];
 };
 
 __device__ __forceinline__ int ks_ext_prime(int t, int j0, int sz, int lv, int L) {
@@ -68,8 +80,11 @@ template <int S, int NT, int TH>
 __global__ __launch_bounds__(TH) void k_modup_col(const KsArgs a, double *__restrict__ ext,
                                                            const double *__restrict__ dcoef) {
     __shared__ double lds[NttTile<TH>::lds];
-    const int id = xcd_slot(a.n);
-    if (id >= a.n) return;
+    const int gid = xcd_slot(a.n);
+    if (gid >= a.n) return;
+    const int bi = gid / a.per, id = gid - bi * a.per;
+    ext += bi * a.sext;
+    dcoef += bi * a.sdc;
     const int Tf = a.E - a.alpha;                       // targets of a full digit
     const int full = (a.beta - 1) * Tf * a.tiles;
     int j, rem, T;
@@ -120,8 +135,11 @@ template <int S, int NT, int TH>
 __global__ __launch_bounds__(TH) void k_moddown_col(const KsArgs a, double *__restrict__ tmp,
                                                              const double *__restrict__ acc) {
     __shared__ double lds[NttTile<TH>::lds];
-    const int id = xcd_slot(a.n);
-    if (id >= a.n) return;
+    const int gid = xcd_slot(a.n);
+    if (gid >= a.n) return;
+    const int bi = gid / a.per, id = gid - bi * a.per;
+    tmp += bi * a.stmp;
+    acc += bi * a.sacc;
     const int i = id % a.lv;
     const int rest = id / a.lv;
     const int tile = rest % a.tiles;
@@ -157,13 +175,17 @@ __global__ __launch_bounds__(TH) void k_moddown_col(const KsArgs a, double *__re
 
 // ---- step 6: forward row pass of the conversion, then (acc_Q - x) P^-1 (+ base)
 template <int S, int MODE, int TH>
-__global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, double *out0, double *out1,
-                                                             const double *__restrict__ acc,
-                                                             const double *__restrict__ tmp, const double *base0,
-                                                             const double *base1) {
+__global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, const double *__restrict__ acc,
+                                                    const double *__restrict__ tmp) {
     __shared__ double lds[NttTile<TH>::lds];
-    const int id = xcd_slot(a.n);
-    if (id >= a.n) return;
+    const int gid = xcd_slot(a.n);
+    if (gid >= a.n) return;
+    const int bi = gid / a.per, id = gid - bi * a.per;
+    const KsEntry &en = a.op[bi];
+    acc += bi * a.sacc;
+    tmp += bi * a.stmp;
+    double *out0 = en.out0, *out1 = en.out1;
+    const double *base0 = en.base0, *base1 = en.base1;
     const int tile = id % a.tiles;
     const int rest = id / a.tiles;
     const int u = rest % 2;
@@ -193,11 +215,11 @@ __global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, double *out0
             const unsigned g = (unsigned)(g0 + e);
             xa[k] = ax[g];
             if (MODE == KS_PRODUCT) {
-                xb[k] = u == 0 ? mmul(a.a0[li + g], a.b0[li + g], q, P.qinv)
-                               : madd(mmul(a.a0[li + g], a.b1[li + g], q, P.qinv),
-                                      mmul(a.a1[li + g], a.b0[li + g], q, P.qinv), q);
+                xb[k] = u == 0 ? mmul(en.a0[li + g], en.b0[li + g], q, P.qinv)
+                               : madd(mmul(en.a0[li + g], en.b1[li + g], q, P.qinv),
+                                      mmul(en.a1[li + g], en.b0[li + g], q, P.qinv), q);
             } else if (bs) {
-                xb[k] = bs[MODE == KS_GALOIS && u == 0 ? galois_src(g, a.logn, a.galois) : g];
+                xb[k] = bs[MODE == KS_GALOIS && u == 0 ? galois_src(g, a.logn, en.galois) : g];
             }
         }
     }
@@ -210,11 +232,15 @@ __global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, double *out0
 
 // ---- step 1: INTT of d with the ModUp scaling folded into the last stage's store
 template <int S, bool ROW, int MODE, int TH>
-__global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__restrict__ dst,
-                                                            const double *__restrict__ src) {
+__global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__restrict__ dst) {
     __shared__ double lds[NttTile<TH>::lds];
-    const int id = xcd_slot(a.n);
-    if (id >= a.n) return;
+    const int gid = xcd_slot(a.n);
+    if (gid >= a.n) return;
+    const int bi = gid / a.per, id = gid - bi * a.per;
+    const KsEntry &en = a.op[bi];
+    dst += bi * a.sdc;
+    // the row (first) pass reads the operand, the column pass dst in place
+    const double *src = ROW ? en.d : dst;
     const int i = id / a.tiles;
     const int tile = id - i * a.tiles;
     const PrimeDev &P = a.primes[i];
@@ -224,8 +250,8 @@ __global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__res
     const size_t li = (size_t)i * N;
     auto ld = [&](int g, int) {
         const unsigned e = (unsigned)g;
-        if (MODE == KS_PRODUCT) return mmul(a.a1[li + e], a.b1[li + e], P.q, P.qinv);
-        return s[MODE == KS_GALOIS ? galois_src(e, a.logn, a.galois) : e];
+        if (MODE == KS_PRODUCT) return mmul(en.a1[li + e], en.b1[li + e], P.q, P.qinv);
+        return s[MODE == KS_GALOIS ? galois_src(e, a.logn, en.galois) : e];
     };
     if (ROW) {
         auto st = [&](int g, double v, int) { d[g] = v; };
@@ -244,8 +270,10 @@ __global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__res
 template <int S, bool ROW, int TH>
 __global__ __launch_bounds__(TH) void k_intt_special(const KsArgs a, double *__restrict__ acc) {
     __shared__ double lds[NttTile<TH>::lds];
-    const int id = xcd_slot(a.n);
-    if (id >= a.n) return;
+    const int gid = xcd_slot(a.n);
+    if (gid >= a.n) return;
+    const int bi = gid / a.per, id = gid - bi * a.per;
+    acc += bi * a.sacc;
     const int limb = id / a.tiles;          // u * K + k
     const int tile = id - limb * a.tiles;
     const int u = limb / a.K, k = limb - u * a.K;
@@ -281,7 +309,7 @@ __global__ __launch_bounds__(TH) void k_intt_special(const KsArgs a, double *__r
         default: { constexpr int MD = KS_PLAIN; CALL; } break;          \
     }
 
-static KsArgs ks_args(pfx_ctx *c, int lv, const KsOperand &op = KsOperand{}) {
+static KsArgs ks_args(pfx_ctx *c, int lv, const KsBatch &kb) {
     KsArgs a;
     a.primes = c->d_primes;
     a.mu = c->d_modup;
@@ -293,12 +321,26 @@ static KsArgs ks_args(pfx_ctx *c, int lv, const KsOperand &op = KsOperand{}) {
     a.alpha = c->alpha;
     a.beta = (lv + c->alpha - 1) / c->alpha;
     a.E = lv + c->K;
-    a.galois = op.galois;
-    a.a0 = op.a0;
-    a.a1 = op.a1;
-    a.b0 = op.b0;
-    a.b1 = op.b1;
+    a.nb = kb.nb;
+    a.sdc = kb.sdc;
+    a.sext = kb.sext;
+    a.sacc = kb.sacc;
+    a.stmp = kb.stmp;
+    for (int b = 0; b < kMaxBatch; ++b) {
+        KsEntry &e = a.op[b];
+        if (b < kb.nb) {
+            const KsOperand &o = kb.op[b];
+            e = KsEntry{o.d, o.base0, o.base1, o.a0, o.a1, o.b0, o.b1, kb.out0[b], kb.out1[b], o.galois};
+        } else {
+            e = KsEntry{};
+        }
+    }
     return a;
+}
+
+static void set_blocks(KsArgs &a, int per) {
+    a.per = per;
+    a.n = a.nb * per;
 }
 
 // Narrower tiles (idle threads) until a launch over `limbs` limbs has at least
@@ -310,100 +352,105 @@ static void widen_grid(PassShape &pr, PassShape &pc, int limbs) {
     while (limbs * pc.tiles < 1024 && pc.C / 2 >= 8) { pc.C /= 2; pc.tiles *= 2; }
 }
 
-void launch_intt_scale(const Launch &L, double *dcoef, const KsOperand &op, int lv) {
-    KsArgs a = ks_args(L.ctx, lv, op);
-    const double *d = op.d;
-    const int th = pass_threads(a.logn, lv, true), tc = pass_threads(a.logn, lv, false);
+void launch_intt_scale(const Launch &L, const KsBatch &kb, int lv) {
+    KsArgs a = ks_args(L.ctx, lv, kb);
+    double *dcoef = kb.dcoef;
+    const int limbs = kb.nb * lv;
+    const int th = pass_threads(a.logn, limbs, true), tc = pass_threads(a.logn, limbs, false);
     const PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
     hipEvent_t ev;
     a.C = pr.C;
     a.tiles = pr.tiles;
-    a.n = lv * a.tiles;
+    set_blocks(a, lv * a.tiles);
     prof_begin(L, "ks_intt_row", &ev);
-    PFX_SWITCH_TH(th, PFX_SWITCH_KS(op.mode, PFX_SWITCH_S(pr.S, (k_intt_scale<SS, true, MD, TH><<<xcd_grid(a.n), TH, 0,
-                                                                                             L.st>>>(a, dcoef, d)))));
+    PFX_SWITCH_TH(th, PFX_SWITCH_KS(kb.mode, PFX_SWITCH_S(pr.S, (k_intt_scale<SS, true, MD, TH><<<xcd_grid(a.n), TH, 0,
+                                                                                             L.st>>>(a, dcoef)))));
     HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_intt_row", ev, (op.mode == KS_PRODUCT ? 24.0 : 16.0) * (double)L.ctx->N * lv);
+    prof_end(L, "ks_intt_row", ev, (kb.mode == KS_PRODUCT ? 24.0 : 16.0) * (double)L.ctx->N * limbs);
     a.C = pc.C;
     a.tiles = pc.tiles;
-    a.n = lv * a.tiles;
+    set_blocks(a, lv * a.tiles);
     prof_begin(L, "ks_intt_col", &ev);
     PFX_SWITCH_TH(tc, PFX_SWITCH_S(pc.S, (k_intt_scale<SS, false, KS_PLAIN, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(
-                                              a, dcoef, dcoef))));
+                                              a, dcoef))));
     HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_intt_col", ev, 16.0 * (double)L.ctx->N * lv);
+    prof_end(L, "ks_intt_col", ev, 16.0 * (double)L.ctx->N * limbs);
 }
 
-void launch_modup_col(const Launch &L, double *ext, const double *dcoef, int lv) {
-    KsArgs a = ks_args(L.ctx, lv);
-    const int th = pass_threads(a.logn, a.beta * a.E - lv, false);
+void launch_modup_col(const Launch &L, const KsBatch &kb, int lv) {
+    KsArgs a = ks_args(L.ctx, lv, kb);
+    const int th = pass_threads(a.logn, kb.nb * (a.beta * a.E - lv), false);
     const PassShape ps = col_shape(a.logn, th * kSlots);
     a.C = ps.C;
     a.tiles = ps.tiles;
-    a.n = (a.beta * a.E - lv) * a.tiles;      // sum over digits of E - sz_j targets
+    set_blocks(a, (a.beta * a.E - lv) * a.tiles);      // sum over digits of E - sz_j targets
+    double *ext = kb.ext;
+    const double *dcoef = kb.dcoef;
     hipEvent_t ev;
     prof_begin(L, "ks_modup_col", &ev);
     PFX_SWITCH_TH(th, PFX_SWITCH_NT(a.alpha, PFX_SWITCH_S(ps.S, (k_modup_col<SS, NT, TH><<<xcd_grid(a.n), TH, 0,
                                                                                            L.st>>>(a, ext, dcoef)))));
     HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_modup_col", ev, 8.0 * (double)L.ctx->N * a.beta * a.E);
+    prof_end(L, "ks_modup_col", ev, 8.0 * (double)L.ctx->N * a.beta * a.E * kb.nb);
 }
 
-void launch_intt_special(const Launch &L, double *acc, int lv) {
-    KsArgs a = ks_args(L.ctx, lv);
-    const int th = pass_threads(a.logn, 2 * a.K, true);
+void launch_intt_special(const Launch &L, const KsBatch &kb, int lv) {
+    KsArgs a = ks_args(L.ctx, lv, kb);
+    double *acc = kb.acc;
+    const int limbs = kb.nb * 2 * a.K;
+    const int th = pass_threads(a.logn, limbs, true);
     constexpr int tc = 256;
     PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
-    widen_grid(pr, pc, 2 * a.K);
+    widen_grid(pr, pc, limbs);
     hipEvent_t ev;
     a.C = pr.C;
     a.tiles = pr.tiles;
-    a.n = 2 * a.K * a.tiles;
+    set_blocks(a, 2 * a.K * a.tiles);
     prof_begin(L, "ks_intt_special_row", &ev);
     PFX_SWITCH_TH(th, PFX_SWITCH_S(pr.S, (k_intt_special<SS, true, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, acc))));
     HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_intt_special_row", ev, 16.0 * (double)L.ctx->N * 2 * a.K);
+    prof_end(L, "ks_intt_special_row", ev, 16.0 * (double)L.ctx->N * limbs);
     a.C = pc.C;
     a.tiles = pc.tiles;
-    a.n = 2 * a.K * a.tiles;
+    set_blocks(a, 2 * a.K * a.tiles);
     prof_begin(L, "ks_intt_special_col", &ev);
     PFX_SWITCH_S(pc.S, (k_intt_special<SS, false, tc><<<xcd_grid(a.n), tc, 0, L.st>>>(a, acc)));
     HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_intt_special_col", ev, 16.0 * (double)L.ctx->N * 2 * a.K);
+    prof_end(L, "ks_intt_special_col", ev, 16.0 * (double)L.ctx->N * limbs);
 }
 
-void launch_moddown_col(const Launch &L, double *tmp, const double *acc, int lv) {
-    KsArgs a = ks_args(L.ctx, lv);
-    const int th = pass_threads(a.logn, 2 * lv, false);
+void launch_moddown_col(const Launch &L, const KsBatch &kb, int lv) {
+    KsArgs a = ks_args(L.ctx, lv, kb);
+    const int th = pass_threads(a.logn, kb.nb * 2 * lv, false);
     const PassShape ps = col_shape(a.logn, th * kSlots);
     a.C = ps.C;
     a.tiles = ps.tiles;
-    a.n = 2 * a.tiles * lv;
+    set_blocks(a, 2 * a.tiles * lv);
+    double *tmp = kb.tmp;
+    const double *acc = kb.acc;
     hipEvent_t ev;
     prof_begin(L, "ks_moddown_col", &ev);
     PFX_SWITCH_TH(th, PFX_SWITCH_NT(a.K, PFX_SWITCH_S(ps.S, (k_moddown_col<SS, NT, TH><<<xcd_grid(a.n), TH, 0,
                                                                                        L.st>>>(a, tmp, acc)))));
     HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_moddown_col", ev, 8.0 * (double)L.ctx->N * (2.0 * a.K + 2.0 * lv));
+    prof_end(L, "ks_moddown_col", ev, 8.0 * (double)L.ctx->N * (2.0 * a.K + 2.0 * lv) * kb.nb);
 }
 
-void launch_row_moddown(const Launch &L, double *out0, double *out1, const double *acc, const double *tmp,
-                        const KsOperand &op, int lv) {
-    KsArgs a = ks_args(L.ctx, lv, op);
-    const double *base0 = op.base0, *base1 = op.base1;
-    const int th = pass_threads(a.logn, 2 * lv, true);
+void launch_row_moddown(const Launch &L, const KsBatch &kb, int lv) {
+    KsArgs a = ks_args(L.ctx, lv, kb);
+    const int th = pass_threads(a.logn, kb.nb * 2 * lv, true);
     const PassShape ps = row_shape(a.logn, th * kSlots);
     a.C = ps.C;
     a.tiles = ps.tiles;
-    a.n = 2 * lv * a.tiles;
+    set_blocks(a, 2 * lv * a.tiles);
+    const double *acc = kb.acc, *tmp = kb.tmp;
+    const int nbases = kb.mode == KS_PRODUCT ? 4 : (kb.op[0].base0 ? 1 : 0) + (kb.op[0].base1 ? 1 : 0);
     hipEvent_t ev;
     prof_begin(L, "ks_row_moddown", &ev);
-    PFX_SWITCH_TH(th, PFX_SWITCH_KS(op.mode, PFX_SWITCH_S(ps.S, (k_row_moddown<SS, MD, TH><<<xcd_grid(a.n), TH, 0,
-                                                                                          L.st>>>(a, out0, out1, acc,
-                                                                                                  tmp, base0, base1)))));
+    PFX_SWITCH_TH(th, PFX_SWITCH_KS(kb.mode, PFX_SWITCH_S(ps.S, (k_row_moddown<SS, MD, TH><<<xcd_grid(a.n), TH, 0,
+                                                                                          L.st>>>(a, acc, tmp)))));
     HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_row_moddown", ev,
-             8.0 * (double)L.ctx->N * lv * (op.mode == KS_PRODUCT ? 10.0 : 6.0 + (base0 ? 1 : 0) + (base1 ? 1 : 0)));
+    prof_end(L, "ks_row_moddown", ev, 8.0 * (double)L.ctx->N * lv * (6.0 + nbases) * kb.nb);
 }
 
 }  // namespace pfx

@@ -20,24 +20,36 @@
 
 namespace pfx {
 
+// A launch covers nb ciphertexts of one level and degree: polynomial index
+// k = entry * np + p runs over all of them; `last` and `tmp` hold every
+// polynomial's scratch back to back.
 struct RsArgs {
     const PrimeDev *primes;
     const RescaleConst *rc;
     int logn, lv, np;
     int C, tiles, n;
-    size_t si, so;   // doubles between the polynomials of the input and of the output
+    RsEntry e[kMaxBatch];
 };
 
+__device__ __forceinline__ const double *rs_in(const RsArgs &a, int k) {
+    const int b = k / a.np;
+    return a.e[b].in + (size_t)(k - b * a.np) * a.e[b].si;
+}
+
+__device__ __forceinline__ double *rs_out(const RsArgs &a, int k) {
+    const int b = k / a.np;
+    return a.e[b].out + (size_t)(k - b * a.np) * a.e[b].so;
+}
+
 template <int S, int TH>
-__global__ __launch_bounds__(TH) void k_rs_intt_row(const RsArgs a, double *__restrict__ last,
-                                                    const double *__restrict__ in) {
+__global__ __launch_bounds__(TH) void k_rs_intt_row(const RsArgs a, double *__restrict__ last) {
     __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
     const int k = id / a.tiles, tile = id - k * a.tiles;
     const PrimeDev &P = a.primes[a.lv - 1];
     const size_t N = (size_t)1 << a.logn;
-    const double *src = in + k * a.si + (size_t)(a.lv - 1) * N;
+    const double *src = rs_in(a, k) + (size_t)(a.lv - 1) * N;
     double *dst = last + (size_t)k * N;
     auto ld = [&](int g, int) { return src[(unsigned)g]; };
     auto st = [&](int g, double v, int) { dst[(unsigned)g] = v; };
@@ -82,8 +94,7 @@ __global__ __launch_bounds__(TH) void k_rs_col(const RsArgs a, double *__restric
 
 // blocks: (poly k, prime i, tile), tile fastest (one twiddle table per run of blocks)
 template <int S, int TH>
-__global__ __launch_bounds__(TH) void k_rs_row(const RsArgs a, double *out, const double *in,
-                                               const double *__restrict__ tmp) {
+__global__ __launch_bounds__(TH) void k_rs_row(const RsArgs a, const double *__restrict__ tmp) {
     __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
@@ -94,8 +105,8 @@ __global__ __launch_bounds__(TH) void k_rs_row(const RsArgs a, double *out, cons
     const double2 inv = a.rc[(a.lv - 1) * PFX_MAX_PRIMES + i].inv;
     const size_t N = (size_t)1 << a.logn;
     const double *src = tmp + ((size_t)k * nout + i) * N;
-    const double *c = in + k * a.si + (size_t)i * N;
-    double *o = out + k * a.so + (size_t)i * N;
+    const double *c = rs_in(a, k) + (size_t)i * N;
+    double *o = rs_out(a, k) + (size_t)i * N;
     // c is loaded before the transform (its latency hides under it); slot k of
     // this thread is element tid + k * TH of the tile, the row pass's output
     // order.  out may alias in: each element is read and then written by the
@@ -118,8 +129,7 @@ __global__ __launch_bounds__(TH) void k_rs_row(const RsArgs a, double *out, cons
         if (e_ != hipSuccess) set_error(std::string("kernel launch: ") + hipGetErrorString(e_)); \
     } while (0)
 
-void launch_rescale(const Launch &L, double *out, size_t so, const double *in, size_t si, int np, int lv,
-                    double *last, double *tmp) {
+void launch_rescale(const Launch &L, const RsEntry *ents, int nb, int np, int lv, double *last, double *tmp) {
     pfx_ctx *c = L.ctx;
     RsArgs a;
     a.primes = c->d_primes;
@@ -127,32 +137,32 @@ void launch_rescale(const Launch &L, double *out, size_t so, const double *in, s
     a.logn = c->logn;
     a.lv = lv;
     a.np = np;
-    a.si = si;
-    a.so = so;
+    for (int b = 0; b < kMaxBatch; ++b) a.e[b] = b < nb ? ents[b] : RsEntry{};
     const double N = (double)c->N;
+    const int polys = nb * np;
     hipEvent_t ev;
-    // 1-2: INTT of the np last limbs (narrow launches)
+    // 1-2: INTT of the last limbs (narrow launches)
     {
-        const int th = pass_threads(a.logn, np, true), tc = pass_threads(a.logn, np, false);
+        const int th = pass_threads(a.logn, polys, true), tc = pass_threads(a.logn, polys, false);
         PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
-        while (np * pr.tiles < 256 && pr.C > 1) { pr.C /= 2; pr.tiles *= 2; }
-        while (np * pc.tiles < 256 && pc.C / 2 >= 8) { pc.C /= 2; pc.tiles *= 2; }
+        while (polys * pr.tiles < 256 && pr.C > 1) { pr.C /= 2; pr.tiles *= 2; }
+        while (polys * pc.tiles < 256 && pc.C / 2 >= 8) { pc.C /= 2; pc.tiles *= 2; }
         a.C = pr.C;
         a.tiles = pr.tiles;
-        a.n = np * pr.tiles;
+        a.n = polys * pr.tiles;
         prof_begin(L, "rs_intt_row", &ev);
-        PFX_SWITCH_TH(th, PFX_SWITCH_S(pr.S, (k_rs_intt_row<SS, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, last, in))));
+        PFX_SWITCH_TH(th, PFX_SWITCH_S(pr.S, (k_rs_intt_row<SS, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, last))));
         HIP_LAUNCH_CHECK_RS();
-        prof_end(L, "rs_intt_row", ev, 16.0 * N * np);
+        prof_end(L, "rs_intt_row", ev, 16.0 * N * polys);
         a.C = pc.C;
         a.tiles = pc.tiles;
-        a.n = np * pc.tiles;
+        a.n = polys * pc.tiles;
         prof_begin(L, "rs_intt_col", &ev);
         PFX_SWITCH_TH(tc, PFX_SWITCH_S(pc.S, (k_rs_intt_col<SS, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, last))));
         HIP_LAUNCH_CHECK_RS();
-        prof_end(L, "rs_intt_col", ev, 16.0 * N * np);
+        prof_end(L, "rs_intt_col", ev, 16.0 * N * polys);
     }
-    const int limbs = np * (lv - 1);
+    const int limbs = polys * (lv - 1);
     {
         const int tc = pass_threads(a.logn, limbs, false);
         const PassShape pc = col_shape(a.logn, tc * kSlots);
@@ -162,7 +172,7 @@ void launch_rescale(const Launch &L, double *out, size_t so, const double *in, s
         prof_begin(L, "rs_col", &ev);
         PFX_SWITCH_TH(tc, PFX_SWITCH_S(pc.S, (k_rs_col<SS, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, tmp, last))));
         HIP_LAUNCH_CHECK_RS();
-        prof_end(L, "rs_col", ev, 8.0 * N * (np + limbs));
+        prof_end(L, "rs_col", ev, 8.0 * N * (polys + limbs));
     }
     {
         const int th = pass_threads(a.logn, limbs, true);
@@ -171,7 +181,7 @@ void launch_rescale(const Launch &L, double *out, size_t so, const double *in, s
         a.tiles = pr.tiles;
         a.n = limbs * pr.tiles;
         prof_begin(L, "rs_row", &ev);
-        PFX_SWITCH_TH(th, PFX_SWITCH_S(pr.S, (k_rs_row<SS, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, out, in, tmp))));
+        PFX_SWITCH_TH(th, PFX_SWITCH_S(pr.S, (k_rs_row<SS, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, tmp))));
         HIP_LAUNCH_CHECK_RS();
         prof_end(L, "rs_row", ev, 24.0 * N * limbs);
     }

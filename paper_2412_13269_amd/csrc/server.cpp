@@ -180,7 +180,8 @@ void launch(pfx_server *s, Request *r) {
     pfx_ctx *c = s->ctx;
     void *st = s->streams[r->slot];
     pfx_status st_run = run_ops(c, r->ops.data(), r->ops.size(), r->regs.data(), r->n_regs, r->n_inputs,
-                                r->pts.data(), r->pts.size(), s->rlk, s->gks.data(), s->gks.size(), st);
+                                r->pts.data(), r->pts.size(), s->rlk, s->gks.data(), s->gks.size(), st,
+                                1);   // one key switch at a time: the slot's scratch is what was budgeted
     std::string err = st_run ? pfx_last_error() : "";
     if (!st_run) {
         st_run = pfx_ct_copy(c, r->regs[r->out_reg], r->out, st);

@@ -119,7 +119,9 @@ _SIGS = {
     "pfx_mul": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_relinearize": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_mul_relin": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pfx_mul_relin_batch": (_i32, [_vp, _VPP, _VPP, _sz, _vp, _VPP, _vp]),
     "pfx_rescale": (_i32, [_vp, _vp, _vp, _vp]),
+    "pfx_rescale_batch": (_i32, [_vp, _VPP, _sz, _VPP, _vp]),
     "pfx_drop_level": (_i32, [_vp, _vp, _u32, _vp, _vp]),
     "pfx_key_switch": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_apply_galois": (_i32, [_vp, _vp, _vp, _vp, _vp]),
@@ -393,8 +395,22 @@ def pfx_mul_relin(ctx, a, b, rlk, out, stream=None):
     _check(_lib.pfx_mul_relin(ctx, a, b, rlk, out, _stream(stream)))
 
 
+def pfx_mul_relin_batch(ctx, a, b, rlk, outs, stream=None):
+    n = len(a)
+    assert len(b) == n and len(outs) == n
+    arr = lambda xs: (ctypes.c_void_p * max(1, n))(*xs)
+    _check(_lib.pfx_mul_relin_batch(ctx, arr(a), arr(b), n, rlk, arr(outs), _stream(stream)))
+
+
 def pfx_rescale(ctx, a, out, stream=None):
     _check(_lib.pfx_rescale(ctx, a, out, _stream(stream)))
+
+
+def pfx_rescale_batch(ctx, a, outs, stream=None):
+    n = len(a)
+    assert len(outs) == n
+    arr = lambda xs: (ctypes.c_void_p * max(1, n))(*xs)
+    _check(_lib.pfx_rescale_batch(ctx, arr(a), n, arr(outs), _stream(stream)))
 
 
 def pfx_drop_level(ctx, a, n_limbs: int, out, stream=None):

@@ -22,13 +22,18 @@ the library executes them (eagerly, or captured once into a HIP graph; on one
 stream, or scheduled over its lane streams by register dependencies).
 
 Register allocation: temporaries are recycled through a free list.  With
-parallel=False one list serves the whole circuit (fewest registers: the
-smallest HBM footprint, the natural choice on one stream).  With
-parallel=True every record block recycles only its own registers, block b is
-preceded by a LANE (b mod lanes) marker and the sum of the blocks by LANE -1,
-so that with PFX_RUN_LANES the blocks run concurrently on the library's lane
-streams (more registers, more concurrency); without it the markers are
-ignored.
+parallel=False and interleave=False one list serves the whole circuit (fewest
+registers: the smallest HBM footprint, the natural choice on one stream).
+Otherwise every record block recycles only its own registers (more registers):
+  parallel=True   the blocks of lane l (b mod lanes == l) follow a LANE l marker
+                  and the sum of the blocks a LANE -1 marker, so that with
+                  PFX_RUN_LANES the lanes run concurrently on the library's lane
+                  streams; without it the markers are ignored;
+  interleave=True the op lists of the blocks of one lane (of the whole circuit
+                  without parallel) are interleaved op by op: the blocks' i-th
+                  ops sit side by side, so their HMult + relin ops form runs of
+                  independent ops that the library executes as one batched key
+                  switch.
 """
 from __future__ import annotations
 
@@ -46,6 +51,7 @@ class QueryPlan:
     log_slots: int = 15
     parallel: bool = False
     lanes: int = 4
+    interleave: bool = False
     ops: list = field(default_factory=list)
     n_regs: int = 0
     out: int = -1
@@ -138,13 +144,31 @@ class QueryPlan:
         return u
 
     def _build(self):
-        if self.parallel:
+        if self.parallel or self.interleave:
+            lanes = self.lanes if self.parallel else 1
             us = []
-            for b in range(self.n_blocks):
-                self._free = []     # every block recycles only its own registers
-                self._op(X.OP_LANE, 0, 0, k=b % self.lanes)
-                us.append(self._block(b))
-            self._op(X.OP_LANE, 0, 0, k=-1)
+            for lane in range(lanes):
+                blocks = [b for b in range(self.n_blocks) if b % lanes == lane]
+                if not blocks:
+                    continue
+                if self.parallel:
+                    self._op(X.OP_LANE, 0, 0, k=lane)
+                lists = []
+                for b in blocks:
+                    self._free = []     # every block recycles only its own registers
+                    start = len(self.ops)
+                    us.append(self._block(b))
+                    lists.append(self.ops[start:])
+                    del self.ops[start:]
+                if self.interleave:
+                    assert len({len(ops) for ops in lists}) == 1
+                    for step in zip(*lists):
+                        self.ops.extend(step)
+                else:
+                    for ops in lists:
+                        self.ops.extend(ops)
+            if self.parallel:
+                self._op(X.OP_LANE, 0, 0, k=-1)
             self._free = []
             total = us[0]
             for u in us[1:]:

@@ -211,6 +211,72 @@ def test_tensor_relinearize(pair, X):
     pair.same(O.mul_relin(P, c1o, c1o, ko), c1x)
 
 
+def test_mul_relin_batch(pair, X):
+    """Batched HMult + relin: 11 pairs over three levels (more than one launch
+    of 8 at the top level), word for word the per-pair results, and the first
+    pairs against the oracle."""
+    P = pair.P
+    ko, kx = pair.key(0)
+    levels = [P.L, P.L, P.L - 1, P.L, 2, P.L, P.L - 1, P.L, P.L, P.L, P.L]
+    cts = [pair.enc(lv) for lv in levels]
+    a = [cts[i][1] for i in range(11)]
+    b = [cts[(i + 3) % 11][1] for i in range(11)]
+    b[5] = a[5]                                       # a squaring inside the batch
+    outs = [pair.ct(P.L) for _ in range(11)]
+    X.pfx_mul_relin_batch(pair.ctx, a, b, kx, outs)
+    one = pair.ct(P.L)
+    for i in range(11):
+        X.pfx_mul_relin(pair.ctx, a[i], b[i], kx, one)
+        assert np.array_equal(pair.words(outs[i]), pair.words(one)), i
+        assert X.pfx_ct_info(outs[i]).scale == X.pfx_ct_info(one).scale
+        assert X.pfx_ct_info(outs[i]).n_limbs == min(levels[i], levels[(i + 3) % 11])
+    for i in (0, 2, 4):
+        pair.same(O.mul_relin(P, cts[i][0], cts[(i + 3) % 11][0], ko), outs[i])
+    with pytest.raises(X.PfxError) as e:              # output aliases another pair's operand
+        X.pfx_mul_relin_batch(pair.ctx, a[:2], b[:2], kx, [outs[0], a[1]])
+    assert e.value.status == X.PFX_EINVAL
+    with pytest.raises(X.PfxError) as e:              # two pairs write one output
+        X.pfx_mul_relin_batch(pair.ctx, a[:2], b[:2], kx, [outs[0], outs[0]])
+    assert e.value.status == X.PFX_EINVAL
+    X.pfx_mul_relin_batch(pair.ctx, [], [], kx, [])   # empty batch
+
+
+def test_rescale_batch(pair, X):
+    """Batched rescale: ten ciphertexts over two levels and degrees 1 and 2,
+    some in place, word for word the single rescales (themselves pinned to the
+    oracle below)."""
+    P = pair.P
+    cts = [pair.enc(P.L if i % 3 else P.L - 1) for i in range(8)]
+    src = [c[1] for c in cts]
+    for i in (0, 1):                                 # two degree-2 tensor products
+        t = pair.ct(P.L)
+        X.pfx_mul(pair.ctx, cts[2 + i][1], cts[4 + i][1], t)
+        src.append(t)
+    want = []
+    for h in src:
+        o = pair.ct(P.L)
+        X.pfx_rescale(pair.ctx, h, o)
+        want.append((pair.words(o), X.pfx_ct_info(o)))
+    copies = []
+    for h in src:                                    # in-place entries work on copies
+        c = pair.ct(P.L)
+        X.pfx_ct_copy(pair.ctx, h, c)
+        copies.append(c)
+    ins = [copies[i] if i % 2 else src[i] for i in range(10)]
+    outs = [copies[i] if i % 2 else pair.ct(P.L) for i in range(10)]
+    X.pfx_rescale_batch(pair.ctx, ins, outs)
+    for i in range(10):
+        w, info = want[i]
+        assert np.array_equal(pair.words(outs[i]), w), i
+        got = X.pfx_ct_info(outs[i])
+        assert (got.n_limbs, got.degree, got.scale) == (info.n_limbs, info.degree, info.scale), i
+    pair.same(O.rescale(P, cts[0][0]), outs[0])
+    with pytest.raises(X.PfxError) as e:             # writes another entry's input
+        X.pfx_rescale_batch(pair.ctx, [src[0], src[2]], [outs[0], src[0]])
+    assert e.value.status == X.PFX_EINVAL
+    X.pfx_rescale_batch(pair.ctx, [], [])
+
+
 def test_rescale_every_level(pair, X):
     P = pair.P
     co, cx, z = pair.enc(P.L)
@@ -318,3 +384,16 @@ def test_full_size_mul_relin_rescale_rotate(full, X):
     full.handles.append(dec)
     got = X.pfx_decode(full.ctx, dec, P.N // 2)
     assert np.max(np.abs(got - np.roll(z1 * z2, -1))) < 2.0 ** -20
+
+
+def test_full_size_mul_relin_batch(full, X):
+    """Four full-size pairs in one batched key switch equal four single calls."""
+    P = full.P
+    _, kx = full.key(0)
+    cts = [full.enc(24)[1] for _ in range(5)]
+    outs = [full.ct(24) for _ in range(4)]
+    X.pfx_mul_relin_batch(full.ctx, cts[:4], cts[1:5], kx, outs)
+    one = full.ct(24)
+    for i in range(4):
+        X.pfx_mul_relin(full.ctx, cts[i], cts[i + 1], kx, one)
+        assert np.array_equal(full.words(outs[i]), full.words(one)), i

@@ -45,7 +45,7 @@ def gap_records(x, w, c, t, eta, gap, seed):
 class Setup:
     """Library objects for one query; oracle twins built only when asked."""
 
-    def __init__(self, X, logn, n_blocks, seed, gap=None, with_oracle=False, degree=7, parallel=False):
+    def __init__(self, X, logn, n_blocks, seed, gap=None, with_oracle=False, degree=7, **plan_kw):
         from paper_2412_13269_amd.query import QueryPlan
         self.X = X
         self.logn, self.N, self.n = logn, 1 << logn, 1 << (logn - 1)
@@ -58,7 +58,7 @@ class Setup:
             c = np.concatenate([c, np.zeros(max(0, D + 1 - len(c)))])[:D + 1]
             self.x = gap_records(self.x, w, c, t, eta, gap, seed)
         self.params = (w, c, t, eta)
-        self.plan = QueryPlan(n_blocks, A, D, 3, logn - 1, parallel=parallel)
+        self.plan = QueryPlan(n_blocks, A, D, 3, logn - 1, **plan_kw)
         prm = X.make_params(logn, QB, PB, ALPHA, ML)
         self.ctx = X.pfx_ctx_create(prm, 0)
         q, p, _ = X.pfx_ctx_moduli(self.ctx, len(QB), len(PB))
@@ -173,6 +173,23 @@ def test_query_on_lanes_matches_oracle(X):
         S.close()
 
 
+@pytest.mark.parametrize("plan_kw", [dict(interleave=True), dict(parallel=True, lanes=2, interleave=True)],
+                         ids=["interleave", "lanes2-interleave"])
+def test_interleaved_query_matches_oracle(X, plan_kw):
+    # the blocks' products run as batched key switches (3 blocks: runs of 3,
+    # or of 2 and 1 on two lanes), eagerly and from replayed graphs
+    S = Setup(X, 12, 3, 47, with_oracle=True, **plan_kw)
+    try:
+        want = S.oracle_out()
+        for graph, lanes in ((False, False), (True, False), (False, True), (True, True), (True, False),
+                             (False, False), (True, True)):
+            out = S.run(graph=graph, lanes=lanes)
+            assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), want.c), (graph, lanes)
+            assert X.pfx_ct_info(out).scale == want.scale
+    finally:
+        S.close()
+
+
 def test_lane_markers_with_cross_lane_dependency_are_rejected(X):
     S = Setup(X, 12, 1, 39)
     try:
@@ -210,6 +227,15 @@ def test_full_size_query_count(X):
         ref = X.pfx_ct_export(S.ctx, S.run(graph=False), S.N)
         out = S.run(graph=True, lanes=True)
         assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), ref)
+        from paper_2412_13269_amd.query import QueryPlan
+        plan = S.plan
+        for kw in (dict(interleave=True), dict(parallel=True, lanes=2, interleave=True)):
+            S.plan = QueryPlan(4, 8, 7, 3, 15, **kw)        # same registers: every plan fits in 55
+            assert S.plan.n_regs <= len(S.regs)
+            for graph in (False, True):
+                out = S.run(graph=graph, lanes=kw.get("parallel", False))
+                assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), ref), (kw, graph)
+        S.plan = plan
         got = S.count(out)
         step, count = Q.fp64_query(S.x, *S.params)
         assert abs(got[0] - count) < 0.25

@@ -1,0 +1,103 @@
+"""Host-side checks of the query op lists (no GPU): every plan variant
+computes the query's function, and the interleaved variants put the record
+blocks' HMult + relin ops side by side as runs of independent ops.
+
+The op lists run here through a slot-value interpreter: a register holds the
+slot vector its ciphertext would decrypt to (rescale and relinearisation do
+not change it), so a wrong register (a temporary reused while live, a wrong
+operand) changes the result, which must equal the plain FP64 query."""
+import numpy as np
+import pytest
+
+from oracle import query as Q
+from paper_2412_13269_amd import inputs as I
+from paper_2412_13269_amd import pfx as X
+from paper_2412_13269_amd.query import QueryPlan
+
+VARIANTS = [dict(), dict(parallel=True), dict(interleave=True), dict(parallel=True, lanes=2, interleave=True),
+            dict(parallel=True, lanes=3, interleave=True)]
+
+
+def interpret(plan, inputs, pts):
+    reg = {i: np.asarray(v, dtype=np.float64) for i, v in enumerate(inputs)}
+    for code, dst, a, b, k, value in plan.ops:
+        if code == X.OP_LANE:
+            continue
+        A = reg[a]
+        if code == X.OP_ADD:
+            r = A + reg[b]
+        elif code == X.OP_SUB:
+            r = A - reg[b]
+        elif code == X.OP_MUL_PLAIN:
+            r = A * pts[b]
+        elif code == X.OP_MUL_RELIN:
+            r = A * reg[b]
+        elif code == X.OP_RESCALE:
+            r = A
+        elif code == X.OP_MUL_INT:
+            r = A * k
+        elif code == X.OP_ADD_CONST:
+            r = A + value
+        elif code == X.OP_MUL_CONST:
+            r = A * value
+        elif code == X.OP_SCALE_MUL:
+            r = A / value
+        elif code == X.OP_ROTATE_SUM:
+            r = np.full_like(A, A.sum())
+        else:
+            raise AssertionError(f"op {code} not used by the query")
+        assert dst >= plan.n_inputs
+        reg[dst] = np.broadcast_to(r, A.shape).copy() if np.ndim(r) else r
+    return reg[plan.out]
+
+
+@pytest.mark.parametrize("kw", VARIANTS, ids=lambda kw: "-".join(f"{k}{v}" for k, v in kw.items()) or "plain")
+@pytest.mark.parametrize("degree", [3, 7, 15])
+def test_plan_computes_the_query(kw, degree):
+    n, A, blocks = 64, 8, 5
+    x = I.synthetic_database(n * blocks, A, 11 + degree)
+    w, c, t, eta = I.query_parameters(A, degree, 12 + degree)
+    plan = QueryPlan(blocks, A, degree, 3, 6, **kw)
+    inputs = [np.full(n, v) for v in list(w) + list(c) + [t, eta]]
+    pts = [x[b * n:(b + 1) * n, a] for b in range(blocks) for a in range(A)]
+    got = interpret(plan, inputs, pts)
+    _, count = Q.fp64_query(x, w, c, t, eta)
+    assert np.allclose(got, count, rtol=1e-9, atol=1e-9)
+
+
+def _runs(ops):
+    """Maximal runs of consecutive independent HMult + relin ops (the rule the
+    library's executor applies before it batches them)."""
+    runs, cur = [], []
+    for o in ops:
+        if o[0] == X.OP_MUL_RELIN:
+            dst, a, b = o[1], o[2], o[3]
+            ok = dst not in (a, b) and all(dst not in (p[1], p[2], p[3]) and p[1] not in (a, b) for p in cur)
+            if ok and cur:
+                cur.append(o)
+                continue
+            if cur:
+                runs.append(len(cur))
+            cur = [o] if dst not in (a, b) else []
+            if not cur:
+                runs.append(1)
+        else:
+            if cur:
+                runs.append(len(cur))
+            cur = []
+    if cur:
+        runs.append(len(cur))
+    return runs
+
+
+def test_interleaved_plan_batches_every_product_across_blocks():
+    blocks = 4
+    seq = QueryPlan(blocks, 8, 7, 3, 15)
+    inter = QueryPlan(blocks, 8, 7, 3, 15, interleave=True)
+    two = QueryPlan(blocks, 8, 7, 3, 15, parallel=True, lanes=2, interleave=True)
+    n_mr = sum(1 for o in seq.ops if o[0] == X.OP_MUL_RELIN)
+    assert sorted(o[0] for o in inter.ops) == sorted(o[0] for o in seq.ops)
+    assert _runs(seq.ops) == [1] * n_mr
+    assert _runs(inter.ops) == [blocks] * (n_mr // blocks)
+    assert _runs(two.ops) == [2] * (n_mr // 2)
+    assert inter.key_switches == seq.key_switches == two.key_switches
