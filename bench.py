@@ -130,15 +130,16 @@ def batched_form(X, I, ctx16, rlk16, st, args):
              [cut[(ln, lv, 1)] for ln, lv in shapes], [rlks[ln] for ln, _ in shapes], outs)
     res = {}
     reps = max(2, args.steps // 10)
-    for mode in (0, 1, 2):
-        X.pfx_batch_mul_relin_rescale(*bargs, mode, st)      # warm (and capture for mode 2)
+    for mode in (0, 1, 2, 3, 4):
+        X.pfx_batch_mul_relin_rescale(*bargs, mode, st)      # warm (and capture for modes 2, 4)
         X.pfx_sync(ctx16, st)
         a0 = time.perf_counter()
         for _ in range(reps):
             X.pfx_batch_mul_relin_rescale(*bargs, mode, st)
         X.pfx_sync(ctx16, st)
         res[mode] = (time.perf_counter() - a0) / reps
-    log(f"batched 256: per-ct {1e3 * res[0]:.2f} ms, lanes {1e3 * res[1]:.2f} ms, graph {1e3 * res[2]:.2f} ms")
+    log(f"batched 256: per-ct {1e3 * res[0]:.2f} ms, lanes {1e3 * res[1]:.2f} ms, graph {1e3 * res[2]:.2f} ms, "
+        f"grouped lanes {1e3 * res[3]:.2f} ms, grouped graph {1e3 * res[4]:.2f} ms")
     for h in outs + list(cut.values()) + list(base.values()):
         X.pfx_ct_destroy(h)
     for ln in (14, 15):
@@ -150,8 +151,10 @@ def batched_form(X, I, ctx16, rlk16, st, args):
     return {"ciphertexts": 256, "op": "HMult+relin+rescale", "ring_degrees": [2 ** 14, 2 ** 15, 2 ** 16],
             "levels": [3, 24], "reps": reps,
             "ms_per_ct_launch_path": 1e3 * res[0], "ms_lanes": 1e3 * res[1], "ms_graph": 1e3 * res[2],
-            "us_per_ct_launch_path": 1e6 * res[0] / 256, "us_per_ct_graph": 1e6 * res[2] / 256,
-            "speedup_graph_vs_launch_path": res[0] / res[2]}
+            "ms_grouped_lanes": 1e3 * res[3], "ms_grouped_graph": 1e3 * res[4],
+            "shape_groups": len(set(shapes)),
+            "us_per_ct_launch_path": 1e6 * res[0] / 256, "us_per_ct_best": 1e6 * min(res.values()) / 256,
+            "speedup_best_vs_launch_path": res[0] / min(res.values())}
 
 
 def served_form(X, I, ctx, sk, q, rlk, gks, st, args):
@@ -348,10 +351,14 @@ def main():
     # (7,7,7) composite sign, InnerSum count; keys as above (resident)
     from paper_2412_13269_amd.query import QueryPlan
     n_blocks, A, D = 4, 8, 7
-    plan = QueryPlan(n_blocks, A, D, 3, LOGN - 1, parallel=True)
+    plans = {"blocks_on_lanes": QueryPlan(n_blocks, A, D, 3, LOGN - 1, parallel=True),
+             "interleaved": QueryPlan(n_blocks, A, D, 3, LOGN - 1, interleave=True),
+             "interleaved_2_lanes": QueryPlan(n_blocks, A, D, 3, LOGN - 1, parallel=True, lanes=2,
+                                              interleave=True)}
+    plan = plans["blocks_on_lanes"]
     x = I.synthetic_database(n_blocks * (N // 2), A, 301)
     w, c, t, eta = I.query_parameters(A, D, 302)
-    regs = [X.pfx_ct_create(ctx, L, 1) for _ in range(plan.n_regs)]
+    regs = [X.pfx_ct_create(ctx, L, 1) for _ in range(max(p.n_regs for p in plans.values()))]
     for i, v in enumerate(list(w) + list(c) + [t, eta]):
         pt = X.pfx_encode(ctx, np.full(N // 2, v), None, L, SCALE)
         X.pfx_encrypt(ctx, sk, pt, I.uniform_residues(q, N, 400 + 2 * i), I.gaussian_error(N, 401 + 2 * i),
@@ -360,30 +367,36 @@ def main():
     db = [X.pfx_encode(ctx, x[b * (N // 2):(b + 1) * (N // 2), a], None, L, SCALE)
           for b in range(n_blocks) for a in range(A)]
 
-    def query(mode):
-        X.pfx_run_circuit(ctx, plan.ops, regs, plan.n_inputs, db, rlk, gks, mode, st)
+    def query(pl, mode):
+        X.pfx_run_circuit(ctx, pl.ops, regs, pl.n_inputs, db, rlk, gks, mode, st)
 
     modes = {"eager": X.RUN_EAGER, "graph": X.RUN_GRAPH, "lanes": X.RUN_LANES,
              "lanes_graph": X.RUN_LANES | X.RUN_GRAPH}
-    for m in modes.values():                 # warm, and capture the graphs
-        query(m)
-    X.pfx_sync(ctx, st)
+    runs = {f"{pn}/{mn}": (pl, m) for pn, pl in plans.items() for mn, m in modes.items()
+            if pl.parallel or not m & X.RUN_LANES}
+    words = {}
+    for name, (pl, m) in runs.items():       # warm, capture the graphs, and compare the results
+        query(pl, m)
+        X.pfx_sync(ctx, st)
+        words[name] = X.pfx_ct_export(ctx, regs[pl.out], N)
+    first = next(iter(words.values()))
+    assert all(np.array_equal(v, first) for v in words.values()), "query variants disagree"
     reps = max(3, args.steps // 4)
     res = {}
-    for name, m in modes.items():
+    for name, (pl, m) in runs.items():
         a0 = time.perf_counter()
         for _ in range(reps):
-            query(m)
+            query(pl, m)
         X.pfx_sync(ctx, st)
         res[name] = (time.perf_counter() - a0) / reps
     records = n_blocks * (N // 2)
     best = min(res, key=res.get)
     query_out = {"records": records, "attributes": A, "degree": D, "sign_stages": 3,
-                 "key_switches": plan.key_switches, "reps": reps,
-                 **{f"ms_per_query_{k}": 1e3 * v for k, v in res.items()},
-                 "best_mode": best, "us_per_record": 1e6 * res[best] / records,
+                 "key_switches": plan.key_switches, "reps": reps, "variants_identical": True,
+                 "ms_per_query": {k: 1e3 * v for k, v in res.items()},
+                 "best": best, "ms_best": 1e3 * res[best], "us_per_record": 1e6 * res[best] / records,
                  "paper_context_us_per_record_1thread_cpu": 1941.0}
-    log("query: " + ", ".join(f"{k} {1e3 * v:.2f} ms" for k, v in res.items()) +
+    log("query: " + ", ".join(f"{k} {1e3 * v:.2f} ms" for k, v in res.items()) + "\n      " +
         f"; {1e6 * res[best] / records:.3f} us/record ({best}), {plan.key_switches} key switches")
     for h in regs + db:
         X.pfx_ct_destroy(h)

@@ -325,6 +325,11 @@ pfx_status pfx_run_circuit(pfx_ctx *ctx, const pfx_op *ops, size_t n_ops, pfx_ct
  *           to `stream` with events, so that the launches of different
  *           ciphertexts overlap on the device (lanes balanced by estimated work)
  *   mode 2: mode 1 captured once into a HIP graph (non-NULL stream) and replayed
+ *   mode 3: mode 1 with entries of the same context and level grouped (up to 8)
+ *           into batched key switches and rescales (pfx_mul_relin_batch,
+ *           pfx_rescale_batch); an entry whose output aliases its own operand
+ *           runs alone
+ *   mode 4: mode 3 captured once into a HIP graph and replayed
  * Results are identical in every mode.  Outputs must not alias inputs of other
  * batch entries.
  */

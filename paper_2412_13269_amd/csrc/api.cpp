@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -1676,49 +1677,100 @@ pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *
 }
 
 // ------------------------------------------------------------------ batched form
+// Entries grouped for batched key switches: same context and level, at most
+// kMaxBatch per group, no output aliasing an operand of its own entry (those
+// run alone, as pfx_mul_relin handles them); one entry per group otherwise.
+static std::vector<std::vector<size_t>> batch_groups(pfx_ctx *const *ctxs, const pfx_ct *const *a,
+                                                     const pfx_ct *const *b, pfx_ct *const *out, size_t n,
+                                                     bool group) {
+    std::vector<std::vector<size_t>> gs;
+    std::map<std::pair<const pfx_ctx *, uint32_t>, size_t> open;   // (context, level) -> group being filled
+    for (size_t i = 0; i < n; ++i) {
+        const bool self_alias = out[i]->d == a[i]->d || out[i]->d == b[i]->d;
+        if (!group || self_alias) {
+            gs.push_back({i});
+            continue;
+        }
+        const auto key = std::make_pair((const pfx_ctx *)ctxs[i], std::min(a[i]->n_limbs, b[i]->n_limbs));
+        auto it = open.find(key);
+        if (it == open.end() || gs[it->second].size() == (size_t)kMaxBatch) {
+            open[key] = gs.size();
+            gs.push_back({i});
+        } else {
+            gs[it->second].push_back(i);
+        }
+    }
+    return gs;
+}
+
+static pfx_status batch_group_run(pfx_ctx *const *ctxs, const pfx_ct *const *a, const pfx_ct *const *b,
+                                  const pfx_swk *const *rlk, pfx_ct *const *out, const std::vector<size_t> &g,
+                                  void *st) {
+    if (g.size() == 1) {
+        const size_t i = g[0];
+        pfx_status r = pfx_mul_relin(ctxs[i], a[i], b[i], rlk[i], out[i], st);
+        if (!r) r = pfx_rescale(ctxs[i], out[i], out[i], st);
+        return r;
+    }
+    const pfx_ct *ga[kMaxBatch], *gb[kMaxBatch];
+    pfx_ct *go[kMaxBatch];
+    for (size_t k = 0; k < g.size(); ++k) {
+        ga[k] = a[g[k]];
+        gb[k] = b[g[k]];
+        go[k] = out[g[k]];
+    }
+    pfx_ctx *c = ctxs[g[0]];
+    pfx_status r = pfx_mul_relin_batch(c, ga, gb, g.size(), rlk[g[0]], go, st);
+    if (!r) r = pfx_rescale_batch(c, go, g.size(), go, st);
+    return r;
+}
+
 static pfx_status batch_ops(pfx_ctx *const *ctxs, const pfx_ct *const *a, const pfx_ct *const *b,
-                            const pfx_swk *const *rlk, pfx_ct *const *out, size_t n, bool lanes, void *stream) {
+                            const pfx_swk *const *rlk, pfx_ct *const *out, size_t n, bool lanes, bool group,
+                            void *stream) {
     pfx_ctx *c0 = ctxs[0];
+    const auto gs = batch_groups(ctxs, a, b, out, n, group);
     if (!lanes) {
-        for (size_t i = 0; i < n; ++i) {
-            pfx_status r = pfx_mul_relin(ctxs[i], a[i], b[i], rlk[i], out[i], stream);
-            if (!r) r = pfx_rescale(ctxs[i], out[i], out[i], stream);
+        for (const auto &g : gs) {
+            pfx_status r = batch_group_run(ctxs, a, b, rlk, out, g, stream);
             if (r) return r;
         }
         return PFX_OK;
     }
     // greedy assignment by estimated work (limbs x ring degree), largest first
-    std::vector<size_t> order(n);
-    for (size_t i = 0; i < n; ++i) order[i] = i;
-    auto work = [&](size_t i) { return (double)std::min(a[i]->n_limbs, b[i]->n_limbs) * ctxs[i]->N; };
+    std::vector<size_t> order(gs.size());
+    for (size_t i = 0; i < gs.size(); ++i) order[i] = i;
+    auto work = [&](size_t k) {
+        const size_t i = gs[k][0];
+        return (double)std::min(a[i]->n_limbs, b[i]->n_limbs) * ctxs[i]->N * gs[k].size();
+    };
     std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
     std::vector<double> load(kLanes, 0.0);
-    std::vector<int> lane_of(n);
-    for (size_t i : order) {
+    std::vector<int> lane_of(gs.size());
+    for (size_t k : order) {
         int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        lane_of[i] = best;
-        load[best] += work(i);
+        lane_of[k] = best;
+        load[best] += work(k);
     }
     HIPCHECK(hipEventRecord(c0->lane_events[kLanes], S(stream)));
     for (int l = 0; l < kLanes; ++l) HIPCHECK(hipStreamWaitEvent(c0->lanes[l], c0->lane_events[kLanes], 0));
-    for (size_t i : order) {
-        hipStream_t st = c0->lanes[lane_of[i]];
-        pfx_status r = pfx_mul_relin(ctxs[i], a[i], b[i], rlk[i], out[i], st);
-        if (!r) r = pfx_rescale(ctxs[i], out[i], out[i], st);
-        if (r) return r;
+    pfx_status res = PFX_OK;
+    for (size_t k : order) {
+        res = batch_group_run(ctxs, a, b, rlk, out, gs[k], c0->lanes[lane_of[k]]);
+        if (res) break;
     }
-    for (int l = 0; l < kLanes; ++l) {
+    for (int l = 0; l < kLanes; ++l) {        // joined also after a failure
         HIPCHECK(hipEventRecord(c0->lane_events[l], c0->lanes[l]));
         HIPCHECK(hipStreamWaitEvent(S(stream), c0->lane_events[l], 0));
     }
-    return PFX_OK;
+    return res;
 }
 
 pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const *a, const pfx_ct *const *b,
                                        const pfx_swk *const *rlk, pfx_ct *const *out, size_t n, int mode,
                                        void *stream) {
     REQUIRE(ctxs && a && b && rlk && out, PFX_EINVAL, "null argument");
-    REQUIRE(mode >= 0 && mode <= 2, PFX_EINVAL, "mode must be 0, 1 or 2");
+    REQUIRE(mode >= 0 && mode <= 4, PFX_EINVAL, "mode must be 0 to 4");
     if (n == 0) return PFX_OK;
     for (size_t i = 0; i < n; ++i) {
         pfx_ctx *c = ctxs[i];
@@ -1728,17 +1780,23 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
         REQUIRE(c->device == ctxs[0]->device, PFX_EINVAL, "batch spans devices");
         REQUIRE(std::min(a[i]->n_limbs, b[i]->n_limbs) >= 2, PFX_ELEVEL, "batch entry below 2 limbs");
     }
-    if (mode == 0) return batch_ops(ctxs, a, b, rlk, out, n, false, stream);
+    const bool group = mode >= 3;
+    if (mode == 0) return batch_ops(ctxs, a, b, rlk, out, n, false, false, stream);
     pfx_ctx *c0 = ctxs[0];
     pfx_status r = ensure_lanes(c0);
     if (r) return r;
+    size_t gmax = 1;
+    if (group)
+        for (const auto &g : batch_groups(ctxs, a, b, out, n, true)) gmax = std::max(gmax, g.size());
     for (size_t i = 0; i < n; ++i)        // scratch for every (context, lane) before any capture
         for (int l = 0; l < kLanes; ++l) {
             Ws w;
             r = get_ws(ctxs[i], c0->lanes[l], w);
+            KsBatch kb;
+            if (!r && gmax > 1) r = get_batch_ws(ctxs[i], c0->lanes[l], (int)gmax, kb);
             if (r) return r;
         }
-    if (mode == 1) return batch_ops(ctxs, a, b, rlk, out, n, true, stream);
+    if (mode == 1 || mode == 3) return batch_ops(ctxs, a, b, rlk, out, n, true, group, stream);
     REQUIRE(stream != nullptr, PFX_EINVAL, "graph capture needs a non-default stream");
     std::string key = "batch";
     auto put = [&](const void *p, size_t k) { key.append((const char *)p, k); };
@@ -1754,11 +1812,12 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
         put(&b[i]->scale, sizeof(double));
     }
     put(&stream, sizeof(void *));
+    put(&mode, sizeof(int));
     auto it = c0->graphs.find(key);
     if (it == c0->graphs.end()) {
         for (size_t i = 0; i < n; ++i) ctxs[i]->capturing = true;
         HIPCHECK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal));
-        r = batch_ops(ctxs, a, b, rlk, out, n, true, stream);
+        r = batch_ops(ctxs, a, b, rlk, out, n, true, group, stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(S(stream), &g);
         for (size_t i = 0; i < n; ++i) ctxs[i]->capturing = false;

@@ -350,8 +350,11 @@ struct InnerArgs {
     uint32_t g[kMaxBatch];
 };
 
-template <int MODE>
+template <int MODE, int NB>
 __global__ __launch_bounds__(256) void k_ks_inner(const InnerArgs a) {
+    // digits whose loads are all in flight before any product: NB entries'
+    // limbs plus two key residues per digit
+    constexpr int kChunk = NB >= 4 ? 1 : 4 / NB;
     const int m = blockIdx.y;
     const int logn = a.logn;
     const size_t N = (size_t)1 << logn;
@@ -364,41 +367,63 @@ __global__ __launch_bounds__(256) void k_ks_inner(const InnerArgs a) {
     const size_t kstride = (size_t)(a.L + a.K) * N;
     const double *k0 = a.key + ((size_t)pid << logn) + c;
     const size_t lm = (size_t)m << logn;
-    // products in [0, q) summed lazily; every digit is followed by a reduction
-    // once more than four products have accumulated (< 5q < 2^53, which mred
-    // reduces exactly: its quotient estimate is off by at most one there)
-    double a0[kMaxBatch], a1[kMaxBatch];
+    // products in [0, q) summed lazily, reduced once four digits have
+    // accumulated: below q + 4q < 2^53, which mred reduces exactly (its
+    // quotient estimate is off by at most one there)
+    double a0[NB], a1[NB];
 #pragma unroll
-    for (int b = 0; b < kMaxBatch; ++b) a0[b] = a1[b] = 0.0;
-    for (int j = 0; j < beta; ++j) {
-        const int j0 = j * alpha;
-        const int sz = min(alpha, lv - j0);
-        const bool own = m >= j0 && m < j0 + sz;
-        const int tt = m < j0 ? m : m - sz;
-        const double w0 = k0[(size_t)(2 * j) * kstride];
-        const double w1 = k0[(size_t)(2 * j + 1) * kstride];
+    for (int b = 0; b < NB; ++b) a0[b] = a1[b] = 0.0;
+    int pend = 0;
+    for (int jb = 0; jb < beta; jb += kChunk) {
+        double x[kChunk][NB], w0[kChunk], w1[kChunk];
 #pragma unroll
-        for (int b = 0; b < kMaxBatch; ++b) {
-            if (b < a.nb) {
-                double x;
-                if (own) {
-                    if (MODE == KS_GALOIS) x = a.d[b][lm + galois_src((uint32_t)c, logn, a.g[b])];
-                    else if (MODE == KS_PRODUCT) x = mmul(a.d[b][lm + c], a.d2[b][lm + c], q, qi);
-                    else x = a.d[b][lm + c];
-                } else {
-                    x = a.ext[b * a.sext + ((size_t)j * E + tt) * N + c];
-                }
-                a0[b] += mmul(x, w0, q, qi);
-                a1[b] += mmul(x, w1, q, qi);
-                if ((j & 3) == 3) {
-                    a0[b] = mred(a0[b], q, qi);
-                    a1[b] = mred(a1[b], q, qi);
+        for (int t = 0; t < kChunk; ++t) {
+            const int j = jb + t;
+            if (j < beta) {
+                const int j0 = j * alpha;
+                const int sz = min(alpha, lv - j0);
+                const bool own = m >= j0 && m < j0 + sz;
+                const int tt = m < j0 ? m : m - sz;
+                w0[t] = k0[(size_t)(2 * j) * kstride];
+                w1[t] = k0[(size_t)(2 * j + 1) * kstride];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (b < a.nb) {
+                        if (own) {
+                            if (MODE == KS_GALOIS) x[t][b] = a.d[b][lm + galois_src((uint32_t)c, logn, a.g[b])];
+                            else if (MODE == KS_PRODUCT) x[t][b] = mmul(a.d[b][lm + c], a.d2[b][lm + c], q, qi);
+                            else x[t][b] = a.d[b][lm + c];
+                        } else {
+                            x[t][b] = a.ext[b * a.sext + ((size_t)j * E + tt) * N + c];
+                        }
+                    }
                 }
             }
         }
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) {
+            if (jb + t < beta) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (b < a.nb) {
+                        a0[b] += mmul(x[t][b], w0[t], q, qi);
+                        a1[b] += mmul(x[t][b], w1[t], q, qi);
+                    }
+                }
+            }
+        }
+        pend += kChunk;
+        if (pend >= 4) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                a0[b] = mred(a0[b], q, qi);
+                a1[b] = mred(a1[b], q, qi);
+            }
+            pend = 0;
+        }
     }
 #pragma unroll
-    for (int b = 0; b < kMaxBatch; ++b) {
+    for (int b = 0; b < NB; ++b) {
         if (b < a.nb) {
             a.acc[b * a.sacc + lm + c] = mred(a0[b], q, qi);
             a.acc[b * a.sacc + ((size_t)(E + m) << logn) + c] = mred(a1[b], q, qi);
@@ -431,9 +456,17 @@ void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int 
     dim3 grid((ctx->N + 255) / 256, lv + ctx->K);
     hipEvent_t ev;
     prof_begin(L, "ks_inner", &ev);
-    if (kb.mode == KS_GALOIS) k_ks_inner<KS_GALOIS><<<grid, 256, 0, L.st>>>(a);
-    else if (kb.mode == KS_PRODUCT) k_ks_inner<KS_PRODUCT><<<grid, 256, 0, L.st>>>(a);
-    else k_ks_inner<KS_PLAIN><<<grid, 256, 0, L.st>>>(a);
+#define PFX_KS_INNER(NB_)                                                                        \
+    do {                                                                                          \
+        if (kb.mode == KS_GALOIS) k_ks_inner<KS_GALOIS, NB_><<<grid, 256, 0, L.st>>>(a);          \
+        else if (kb.mode == KS_PRODUCT) k_ks_inner<KS_PRODUCT, NB_><<<grid, 256, 0, L.st>>>(a);   \
+        else k_ks_inner<KS_PLAIN, NB_><<<grid, 256, 0, L.st>>>(a);                                \
+    } while (0)
+    if (kb.nb <= 1) PFX_KS_INNER(1);
+    else if (kb.nb <= 2) PFX_KS_INNER(2);
+    else if (kb.nb <= 4) PFX_KS_INNER(4);
+    else PFX_KS_INNER(kMaxBatch);
+#undef PFX_KS_INNER
     HIP_LAUNCH_CHECK();
     // per entry: ext / d and the accumulators; the key once for the batch
     const int beta = (lv + ctx->alpha - 1) / ctx->alpha;

@@ -1,6 +1,7 @@
 """Batched HMult + relin + rescale over ciphertexts of uneven ring degree and
-level: every mode (per-ciphertext launches, concurrent lanes, HIP-graph
-replay) gives the same words, and sampled entries match the oracle."""
+level: every mode (per-ciphertext launches, concurrent lanes, batched key
+switches grouped by shape, HIP-graph replay) gives the same words, and
+sampled entries match the oracle."""
 import numpy as np
 import pytest
 
@@ -36,9 +37,11 @@ def test_batch_modes_agree_and_match_oracle(X):
     stream = X.pfx_stream_create(ctxs[12])
     entries = []
     handles = []
-    for i in range(24):
-        ln = int(rng.choice(lognums))
-        lv = int(rng.integers(3, 25))
+    # 24 entries of random shape, then 20 over few shapes (groups of up to 8 for
+    # the batched modes, one of 10 split in two), two of them in place
+    shapes = [(int(rng.choice(lognums)), int(rng.integers(3, 25))) for _ in range(24)]
+    shapes += [(13, 24)] * 10 + [(12, 7)] * 6 + [(14, 7)] * 4
+    for i, (ln, lv) in enumerate(shapes):
         N = 1 << ln
         words = [I.uniform_residues(P[ln].mods(lv), N, 1000 + 10 * i + k, lead=(2,)) for k in range(2)]
         cts = []
@@ -46,18 +49,24 @@ def test_batch_modes_agree_and_match_oracle(X):
             h = X.pfx_ct_create(ctxs[ln], lv, 1)
             X.pfx_ct_import(ctxs[ln], w, 2.0 ** 45, h)
             cts.append(h)
-        out = X.pfx_ct_create(ctxs[ln], lv, 1)
-        handles += cts + [out]
+        out = cts[0] if i in (30, 41) else X.pfx_ct_create(ctxs[ln], lv, 1)
+        handles += cts + ([] if out is cts[0] else [out])
         entries.append((ln, lv, words, cts, out))
     args = ([ctxs[e[0]] for e in entries], [e[3][0] for e in entries], [e[3][1] for e in entries],
             [rlks[e[0]] for e in entries], [e[4] for e in entries])
+    def reset():
+        for e in entries:            # clobber outputs, restore in-place inputs
+            if e[4] is e[3][0]:
+                X.pfx_ct_import(ctxs[e[0]], e[2][0], 2.0 ** 45, e[4])
+            else:
+                X.pfx_ct_import(ctxs[e[0]], np.zeros((2, e[1] - 1, 1 << e[0]), np.uint64), 1.0, e[4])
+
     try:
         X.pfx_batch_mul_relin_rescale(*args, 0, stream)
         X.pfx_sync(ctxs[12], stream)
         ref = [X.pfx_ct_export(ctxs[e[0]], e[4], 1 << e[0]) for e in entries]
-        for mode in (1, 2, 2, 1, 2):
-            for e in entries:        # clobber outputs between runs
-                X.pfx_ct_import(ctxs[e[0]], np.zeros((2, e[1] - 1, 1 << e[0]), np.uint64), 1.0, e[4])
+        for mode in (1, 2, 3, 4, 2, 4, 3, 1, 4):
+            reset()
             X.pfx_batch_mul_relin_rescale(*args, mode, stream)
             X.pfx_sync(ctxs[12], stream)
             for e, r in zip(entries, ref):
