@@ -5,6 +5,11 @@
     python -m paper_2412_13269_amd.profsum --pmc <..._counter_collection.csv> [--match REGEX]
         per-dispatch average of every collected counter (`--pmc ...`), with the
         kernel's VGPR/SGPR counts and LDS block size
+    python -m paper_2412_13269_amd.profsum --traffic <FETCH_SIZE csv> <WRITE_SIZE csv>
+            --kernel REGEX --copy REGEX:GRID:KIB
+        HBM bytes per dispatch of the kernels matching --kernel (all their
+        dispatches), each counter scaled by what it reads for the copy kernel
+        of known size (dispatches of that name and grid; KIB read = KIB written)
 """
 from __future__ import annotations
 
@@ -58,7 +63,45 @@ def summarise_pmc(path: str, match: str | None = None) -> str:
     return "\n".join(out)
 
 
+def _per_dispatch(path: str, counter: str, match: str, grid: str | None = None) -> list:
+    import re
+    per = defaultdict(float)
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            name = (row.get("Kernel_Name") or "?").split("(")[0].replace("void ", "")
+            if not re.search(match, name) or (grid is not None and row.get("Grid_Size") != grid):
+                continue
+            per[row["Dispatch_Id"]] += float(row["Counter_Value"])    # summed over instances
+    return list(per.values())
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy: str) -> str:
+    cname, cgrid, ckib = copy.rsplit(":", 2)
+    out = []
+    total = 0.0
+    for path, ctr in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        cal = _per_dispatch(path, ctr, cname, cgrid)
+        k = _per_dispatch(path, ctr, kernel)
+        if not cal or not k:
+            raise SystemExit(f"{ctr}: no dispatches of the copy or of the kernel")
+        c_avg, k_avg = sum(cal) / len(cal), sum(k) / len(k)
+        scale = float(ckib) / c_avg
+        nbytes = k_avg * 1024.0 * scale
+        total += nbytes
+        out.append(f"{ctr}: copy {c_avg:.2f} KiB over {len(cal)} dispatches -> scale {scale:.5f}; "
+                   f"kernel {k_avg:.2f} KiB over {len(k)} dispatches -> {nbytes:.0f} bytes")
+    out.append(f"total bytes per dispatch: {total:.0f}")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
+    if "--traffic" in sys.argv:
+        i = sys.argv.index("--traffic")
+        print(traffic(sys.argv[i + 1], sys.argv[i + 2], sys.argv[sys.argv.index("--kernel") + 1],
+                      sys.argv[sys.argv.index("--copy") + 1]))
+        sys.exit(0)
     if "--pmc" in sys.argv:
         i = sys.argv.index("--pmc")
         m = sys.argv[sys.argv.index("--match") + 1] if "--match" in sys.argv else None
