@@ -157,13 +157,18 @@ def batched_form(X, I, ctx16, rlk16, st, args):
             "speedup_best_vs_launch_path": res[0] / min(res.values())}
 
 
+BATCH = 4   # served form: blocks interleaved in groups of 4, batched launches of up to 4 inside a request
+
+
 def served_form(X, I, ctx, sk, q, rlk, gks, st, args):
     """A Poisson stream of private queries through the library's request
     server.  Database size 2^k records, k uniform over 14..19 (a half block of
     2^14 sparse slots up to 16 blocks of 2^15), score degree uniform over
     3..15, (7,7,7) composite sign and InnerSum count per query.  The database
     (16 blocks + the half block) and the encrypted query parameters stay
-    resident; arrivals at 0.8 x the capacity measured closed-loop first."""
+    resident; arrivals at 0.8 x the capacity measured closed-loop first.
+    Queries of two or more blocks interleave their blocks in groups of BATCH,
+    and the server batches their key switches and rescales (max_batch)."""
     from paper_2412_13269_amd.query import QueryPlan
     N, L, A, MAXD = 1 << LOGN, len(Q_BITS), 8, 15
     n = N // 2
@@ -184,17 +189,18 @@ def served_form(X, I, ctx, sk, q, rlk, gks, st, args):
     def request(k, D):
         blocks = 1 << (k - 15) if k >= 15 else 0
         if (k, D) not in plans:
-            plans[(k, D)] = QueryPlan(max(1, blocks), A, D, 3, LOGN - 1 if blocks else LOGN - 2)
+            plans[(k, D)] = QueryPlan(max(1, blocks), A, D, 3, LOGN - 1 if blocks else LOGN - 2,
+                                      interleave=BATCH if blocks >= 2 else False)
         plan = plans[(k, D)]
         ins = inputs[:A] + inputs[A:A + D + 1] + inputs[A + MAXD + 1:]
         return plan, ins, (db[:blocks * A] if blocks else dbh)
 
     slots = 4
-    scratch_probe = X.pfx_server_create(ctx, 1 << 31, 1, rlk, gks)
+    scratch_probe = X.pfx_server_create(ctx, 1 << 33, 1, rlk, gks, BATCH)
     scratch = X.pfx_server_stats_get(scratch_probe)["scratch_bytes"]
     X.pfx_server_destroy(scratch_probe)
-    budget = slots * scratch + (2 << 30)
-    srv = X.pfx_server_create(ctx, budget, slots, rlk, gks)
+    budget = slots * scratch + (8 << 30)
+    srv = X.pfx_server_create(ctx, budget, slots, rlk, gks, BATCH)
     free_outs = [X.pfx_ct_create(ctx, 8, 1) for _ in range(64)]
     all_outs = list(free_outs)
     pending = {}
@@ -258,7 +264,7 @@ def served_form(X, I, ctx, sk, q, rlk, gks, st, args):
         X.pfx_ct_destroy(h)
     out = {"queries": n_q, "arrival": "Poisson", "rate_per_s": lam, "capacity_queries_per_s": capacity,
            "records_per_query": "2^k, k uniform in 14..19", "degree": "uniform in 3..15", "sign_stages": 3,
-           "slots": slots, "hbm_budget_bytes": budget, "arena_bytes": stats["arena_bytes"],
+           "slots": slots, "max_batch": BATCH, "hbm_budget_bytes": budget, "arena_bytes": stats["arena_bytes"],
            "peak_bytes": stats["peak_bytes"], "peak_running": stats["peak_running"],
            "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
            "mean_queue_ms": 1e3 * float(qd.mean()), "records_per_s": records / wall, "wall_s": wall}

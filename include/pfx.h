@@ -348,8 +348,14 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
  * device (continuous batching at request granularity: a finishing request
  * frees its slot and memory, which admits the next one at once).
  *
+ * Batching inside a request.  With max_batch > 1 a request's runs of
+ * independent HMult + relin ops or rescales (as pfx_run_circuit batches them,
+ * e.g. the record blocks of an interleaved query plan) share batched launches
+ * of up to max_batch (at most 8) entries; 1 runs every op alone.
+ *
  * Memory.  At creation the server takes `hbm_budget` bytes: each slot's
- * key-switching scratch (fixed), and the rest as one arena from which each
+ * key-switching scratch (fixed; with max_batch > 1 it includes the batch
+ * region for max_batch entries), and the rest as one arena from which each
  * admitted request's work registers are carved.  A request's footprint is
  * (n_regs - n_inputs) ciphertexts of degree 1 at the largest level among its
  * inputs: 2 * max(inputs' n_limbs) * N * 8 bytes each.  The evaluation keys
@@ -395,9 +401,10 @@ typedef struct pfx_server_stats {
     uint32_t slots, peak_running;
 } pfx_server_stats;
 
-/* PFX_ENOMEM if the budget does not cover the slots' scratch; slots in [1, 16]. */
-pfx_status pfx_server_create(pfx_ctx *ctx, size_t hbm_budget, uint32_t slots, const pfx_swk *rlk,
-                             const pfx_swk *const *gks, size_t n_gks, pfx_server **out);
+/* PFX_ENOMEM if the budget does not cover the slots' scratch; slots in [1, 16],
+ * max_batch in [1, 8] (PFX_EINVAL otherwise). */
+pfx_status pfx_server_create(pfx_ctx *ctx, size_t hbm_budget, uint32_t slots, uint32_t max_batch,
+                             const pfx_swk *rlk, const pfx_swk *const *gks, size_t n_gks, pfx_server **out);
 /* Queues a request and returns its ticket.  PFX_EINVAL for a malformed request
  * (registers out of range, an input of another context), PFX_ENOMEM if its
  * footprint exceeds the whole arena (it could never be admitted). */

@@ -81,10 +81,15 @@ struct Ws {
 // Key-switch scratch of nb batch entries on one stream (dcoef, ext, acc, tmp per
 // entry, sized for the top level), grown on demand and kept with the stream's
 // workspace.
+size_t batch_entry_doubles(const pfx_ctx *c) {
+    const size_t N = c->N, L = c->L, K = c->K, E = L + K;
+    return L * N + (size_t)c->beta * E * N + 2 * E * N + 2 * L * N;
+}
+
 pfx_status get_batch_ws(pfx_ctx *c, hipStream_t st, int nb, KsBatch &kb) {
     const size_t N = c->N, L = c->L, K = c->K, E = L + K;
     const size_t sdc = L * N, sext = (size_t)c->beta * E * N, sacc = 2 * E * N, stmp = 2 * L * N;
-    const size_t per = sdc + sext + sacc + stmp;
+    const size_t per = batch_entry_doubles(c);
     std::lock_guard<std::mutex> g(c->mu);
     auto it = c->ws.find(st);
     if (it == c->ws.end()) return fail(PFX_EINVAL, "stream has no workspace");
@@ -269,6 +274,13 @@ uint32_t rot_element(const pfx_ctx *c, int64_t step) {
 namespace pfx {
 
 size_t ws_bytes(const pfx_ctx *c) { return ws_layout(c).total * sizeof(double); }
+
+size_t batch_ws_bytes(const pfx_ctx *c, int nb) { return (size_t)nb * batch_entry_doubles(c) * sizeof(double); }
+
+pfx_status batch_ws_reserve(pfx_ctx *c, hipStream_t st, int nb) {
+    KsBatch kb;
+    return get_batch_ws(c, st, nb, kb);
+}
 
 pfx_status ws_reserve(pfx_ctx *c, hipStream_t st) {
     Ws w;

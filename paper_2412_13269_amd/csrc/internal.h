@@ -168,9 +168,12 @@ void decode_words(int logn, const uint64_t *words, int n_limbs, const std::vecto
 pfx_status run_ops(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *const *regs, size_t n_regs,
                    size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
                    const pfx_swk *const *gks, size_t n_gks, void *stream, int max_batch);
-// Bytes of the per-stream scratch, and its allocation for one stream.
+// Bytes of the per-stream scratch, and its allocation for one stream; the same
+// for the stream's batch region of nb entries (batched key switch / rescale).
 size_t ws_bytes(const pfx_ctx *c);
 pfx_status ws_reserve(pfx_ctx *c, hipStream_t st);
+size_t batch_ws_bytes(const pfx_ctx *c, int nb);
+pfx_status batch_ws_reserve(pfx_ctx *c, hipStream_t st, int nb);
 
 // ---------------------------------------------------------------- launchers
 struct Launch {

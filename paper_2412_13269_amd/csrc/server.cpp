@@ -112,6 +112,7 @@ struct pfx_server {
     const pfx_swk *rlk = nullptr;
     std::vector<const pfx_swk *> gks;
     size_t budget = 0, scratch = 0;
+    int max_batch = 1;                   // largest batched launch inside a request
     void *arena_mem = nullptr;
     Arena arena;
     std::vector<void *> streams;
@@ -181,7 +182,7 @@ void launch(pfx_server *s, Request *r) {
     void *st = s->streams[r->slot];
     pfx_status st_run = run_ops(c, r->ops.data(), r->ops.size(), r->regs.data(), r->n_regs, r->n_inputs,
                                 r->pts.data(), r->pts.size(), s->rlk, s->gks.data(), s->gks.size(), st,
-                                1);   // one key switch at a time: the slot's scratch is what was budgeted
+                                s->max_batch);   // the slot's batch region was reserved for this size
     std::string err = st_run ? pfx_last_error() : "";
     if (!st_run) {
         st_run = pfx_ct_copy(c, r->regs[r->out_reg], r->out, st);
@@ -247,13 +248,15 @@ double seconds(Clock::time_point a, Clock::time_point b) { return std::chrono::d
 
 extern "C" {
 
-pfx_status pfx_server_create(pfx_ctx *c, size_t hbm_budget, uint32_t slots, const pfx_swk *rlk,
-                             const pfx_swk *const *gks, size_t n_gks, pfx_server **out) {
+pfx_status pfx_server_create(pfx_ctx *c, size_t hbm_budget, uint32_t slots, uint32_t max_batch,
+                             const pfx_swk *rlk, const pfx_swk *const *gks, size_t n_gks, pfx_server **out) {
     REQUIRE(c && out, PFX_EINVAL, "null argument");
     REQUIRE(slots >= 1 && slots <= kMaxSlots, PFX_EINVAL, "slots must be in [1, 16]");
+    REQUIRE(max_batch >= 1 && max_batch <= (uint32_t)kMaxBatch, PFX_EINVAL, "max_batch must be in [1, 8]");
     REQUIRE(!rlk || rlk->ctx == c, PFX_EINVAL, "relinearisation key of another context");
     for (size_t i = 0; i < n_gks; ++i) REQUIRE(gks[i] && gks[i]->ctx == c, PFX_EINVAL, "bad Galois key");
-    const size_t scratch = (size_t)slots * Arena::round(ws_bytes(c));
+    const size_t per_slot = Arena::round(ws_bytes(c)) + (max_batch > 1 ? Arena::round(batch_ws_bytes(c, max_batch)) : 0);
+    const size_t scratch = (size_t)slots * per_slot;
     REQUIRE(hbm_budget > scratch, PFX_ENOMEM,
             "budget of " + std::to_string(hbm_budget) + " bytes does not cover the slots' scratch (" +
                 std::to_string(scratch) + " bytes)");
@@ -264,6 +267,7 @@ pfx_status pfx_server_create(pfx_ctx *c, size_t hbm_budget, uint32_t slots, cons
     s->gks.assign(gks, gks + n_gks);
     s->budget = hbm_budget;
     s->scratch = scratch;
+    s->max_batch = (int)max_batch;
     const size_t arena_bytes = (hbm_budget - scratch) / kAlign * kAlign;
     if (arena_bytes && hipMalloc(&s->arena_mem, arena_bytes) != hipSuccess)
         return fail(PFX_ENOMEM, "arena allocation of " + std::to_string(arena_bytes) + " bytes failed");
@@ -276,6 +280,7 @@ pfx_status pfx_server_create(pfx_ctx *c, size_t hbm_budget, uint32_t slots, cons
         if (!r) {
             s->streams.push_back(st);
             r = ws_reserve(c, (hipStream_t)st);
+            if (!r && max_batch > 1) r = batch_ws_reserve(c, (hipStream_t)st, (int)max_batch);
         }
         if (r) {
             for (void *x : s->streams) pfx_stream_destroy(c, x);

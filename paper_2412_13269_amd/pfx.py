@@ -134,7 +134,7 @@ _SIGS = {
     "pfx_run_circuit": (_i32, [_vp, ctypes.POINTER(pfx_op), _sz, _VPP, _sz, _sz, _VPP, _sz, _vp, _VPP, _sz,
                                ctypes.c_int, _vp]),
     "pfx_batch_mul_relin_rescale": (_i32, [_VPP, _VPP, _VPP, _VPP, _VPP, _sz, ctypes.c_int, _vp]),
-    "pfx_server_create": (_i32, [_vp, _sz, _u32, _vp, _VPP, _sz, _VPP]),
+    "pfx_server_create": (_i32, [_vp, _sz, _u32, _u32, _vp, _VPP, _sz, _VPP]),
     "pfx_server_submit": (_i32, [_vp, ctypes.POINTER(pfx_request), ctypes.POINTER(ctypes.c_uint64)]),
     "pfx_server_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(pfx_request_info)]),
     "pfx_server_stats_get": (_i32, [_vp, ctypes.POINTER(pfx_server_stats)]),
@@ -475,10 +475,10 @@ def pfx_batch_mul_relin_rescale(ctxs, a, b, rlks, outs, mode: int, stream=None):
 
 
 # ---------------------------------------------------------------- served form
-def pfx_server_create(ctx, hbm_budget: int, slots: int, rlk, gks):
+def pfx_server_create(ctx, hbm_budget: int, slots: int, rlk, gks, max_batch: int = 1):
     G = (ctypes.c_void_p * max(1, len(gks)))(*gks)
     h = ctypes.c_void_p()
-    _check(_lib.pfx_server_create(ctx, hbm_budget, slots, rlk, G, len(gks), ctypes.byref(h)))
+    _check(_lib.pfx_server_create(ctx, hbm_budget, slots, max_batch, rlk, G, len(gks), ctypes.byref(h)))
     return h.value
 
 

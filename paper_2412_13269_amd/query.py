@@ -33,7 +33,11 @@ Otherwise every record block recycles only its own registers (more registers):
                   without parallel) are interleaved op by op: the blocks' i-th
                   ops sit side by side, so their HMult + relin ops form runs of
                   independent ops that the library executes as one batched key
-                  switch.
+                  switch;
+  interleave=G    (an int >= 2, without parallel) the blocks are interleaved in
+                  groups of G, one group after the other; block i of a group
+                  reuses the registers of block i of the previous group, so the
+                  footprint is that of G blocks whatever the database size.
 """
 from __future__ import annotations
 
@@ -51,7 +55,7 @@ class QueryPlan:
     log_slots: int = 15
     parallel: bool = False
     lanes: int = 4
-    interleave: bool = False
+    interleave: bool | int = False
     ops: list = field(default_factory=list)
     n_regs: int = 0
     out: int = -1
@@ -144,7 +148,7 @@ class QueryPlan:
         return u
 
     def _build(self):
-        if self.parallel or self.interleave:
+        if self.parallel or self.interleave is True:
             lanes = self.lanes if self.parallel else 1
             us = []
             for lane in range(lanes):
@@ -173,6 +177,28 @@ class QueryPlan:
             total = us[0]
             for u in us[1:]:
                 self._op(X.OP_ADD, total, total, u)
+        elif self.interleave is not False and int(self.interleave) >= 2:
+            G = int(self.interleave)
+            pools = [[] for _ in range(G)]          # block i of every group recycles pools[i]
+            total = None
+            for g0 in range(0, self.n_blocks, G):
+                lists, us = [], []
+                for i, b in enumerate(range(g0, min(g0 + G, self.n_blocks))):
+                    self._free = pools[i]
+                    start = len(self.ops)
+                    us.append(self._block(b))
+                    lists.append(self.ops[start:])
+                    del self.ops[start:]
+                assert len({len(ops) for ops in lists}) == 1
+                for step in zip(*lists):
+                    self.ops.extend(step)
+                for i, u in enumerate(us):
+                    if total is None:
+                        total = u
+                    else:
+                        self._op(X.OP_ADD, total, total, u)
+                        pools[i].append(u)
+            self._free = [r for pool in pools for r in pool]
         else:
             total = None
             for b in range(self.n_blocks):

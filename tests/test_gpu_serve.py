@@ -68,12 +68,12 @@ class Bench:
         self.stream = X.pfx_stream_create(self.ctx)
         self.owned = []
 
-    def query(self, degree, blocks):
+    def query(self, degree, blocks, interleave=False):
         """(plan, inputs, pts) of a query over `blocks` full blocks, or over the
         half block when blocks == 0."""
         from paper_2412_13269_amd.query import QueryPlan
         log_slots = LOGN - 1 if blocks else LOGN - 2
-        plan = QueryPlan(max(1, blocks), A, degree, 3, log_slots)
+        plan = QueryPlan(max(1, blocks), A, degree, 3, log_slots, interleave=interleave)
         ins = self.inputs[:A] + self.inputs[A:A + degree + 1] + self.inputs[A + MAXD + 1:A + MAXD + 3]
         pts = self.pt_full[:blocks * A] if blocks else self.pt_half
         return plan, ins, pts
@@ -122,12 +122,12 @@ def solo(B):
     return {q: B.solo(*q) for q in set(MIX)}
 
 
-def _serve(X, B, budget, slots, mix):
-    srv = X.pfx_server_create(B.ctx, budget, slots, B.rlk, B.gks)
+def _serve(X, B, budget, slots, mix, max_batch=1):
+    srv = X.pfx_server_create(B.ctx, budget, slots, B.rlk, B.gks, max_batch)
     try:
         tickets = []
         for q in mix:
-            plan, ins, pts = B.query(*q)
+            plan, ins, pts = B.query(*q, interleave=max_batch > 1)
             out = B.new_out()
             t = X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out)
             tickets.append((q, t, out))
@@ -144,8 +144,8 @@ def _serve(X, B, budget, slots, mix):
         X.pfx_server_destroy(srv)
 
 
-def _footprint(B, q):
-    plan, ins, _ = B.query(*q)
+def _footprint(B, q, interleave=False):
+    plan, ins, _ = B.query(*q, interleave=interleave)
     return (plan.n_regs - plan.n_inputs) * 2 * len(QB) * B.N * 8
 
 
@@ -163,13 +163,29 @@ def test_mix_equals_solo_with_requests_in_flight(X, B, solo):
     assert stats["bytes_in_use"] == 0
 
 
-def _scratch(X, B):
+def _scratch(X, B, max_batch=1):
     """Scratch bytes of one slot, read back from a one-slot server's stats."""
-    srv = X.pfx_server_create(B.ctx, 1 << 30, 1, B.rlk, B.gks)
+    srv = X.pfx_server_create(B.ctx, 1 << 30, 1, B.rlk, B.gks, max_batch)
     try:
         return X.pfx_server_stats_get(srv)["scratch_bytes"]
     finally:
         X.pfx_server_destroy(srv)
+
+
+def test_batched_launches_inside_requests(X, B, solo):
+    # interleaved plans: the blocks of a request share batched key switches
+    # and rescales; every result is still the solo one
+    one, four = _scratch(X, B), _scratch(X, B, 4)
+    assert four > one
+    budget = 3 * four + 16 * max(_footprint(B, q, True) for q in MIX)
+    infos, stats = _serve(X, B, budget, 3, MIX, max_batch=4)
+    for q, out, info in infos:
+        assert np.array_equal(X.pfx_ct_export(B.ctx, out, B.N), solo[q][0]), q
+        assert info.footprint == _footprint(B, q, True)
+    assert stats["scratch_bytes"] == 3 * four
+    with pytest.raises(X.PfxError) as e:
+        X.pfx_server_create(B.ctx, budget, 1, B.rlk, B.gks, 9)
+    assert e.value.status == X.PFX_EINVAL
 
 
 @pytest.mark.parametrize("slots", [3, 1])

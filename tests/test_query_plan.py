@@ -15,7 +15,7 @@ from paper_2412_13269_amd import pfx as X
 from paper_2412_13269_amd.query import QueryPlan
 
 VARIANTS = [dict(), dict(parallel=True), dict(interleave=True), dict(parallel=True, lanes=2, interleave=True),
-            dict(parallel=True, lanes=3, interleave=True)]
+            dict(parallel=True, lanes=3, interleave=True), dict(interleave=2), dict(interleave=3)]
 
 
 def interpret(plan, inputs, pts):
@@ -101,3 +101,15 @@ def test_interleaved_plan_batches_every_product_across_blocks():
     assert _runs(inter.ops) == [blocks] * (n_mr // blocks)
     assert _runs(two.ops) == [2] * (n_mr // 2)
     assert inter.key_switches == seq.key_switches == two.key_switches
+
+
+def test_grouped_interleave_bounds_the_registers():
+    seq = QueryPlan(1, 8, 7, 3, 15)
+    per_block = seq.n_regs - seq.n_inputs
+    for blocks in (4, 9, 16):
+        g = QueryPlan(blocks, 8, 7, 3, 15, interleave=4)
+        n_mr = sum(1 for o in g.ops if o[0] == X.OP_MUL_RELIN)
+        assert g.n_regs - g.n_inputs <= 4 * per_block + 1
+        runs = _runs(g.ops)
+        assert sum(runs) == n_mr and max(runs) == 4
+        assert runs.count(4) == (blocks // 4) * (n_mr // blocks)
