@@ -82,6 +82,7 @@ def cpu_baseline(q, p):
     for seed in (201, 202):
         m = O.encode(P, I.uniform_slots(N // 2, seed), SCALE, P.L)
         cts.append(O.encrypt(P, s, m, I.uniform_residues(P.q, N, seed + 10), I.gaussian_error(N, seed + 20), SCALE))
+    cores = O.threads()
     t0 = time.perf_counter()
     ops = 0
     while ops == 0 or time.perf_counter() - t0 < 10.0:   # whole (HMult+relin, rotation) pairs, ~10-12 s
@@ -89,12 +90,19 @@ def cpu_baseline(q, p):
         O.rotate(P, cts[0], 1, {g: gk})
         ops += 2
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one HMult + relin on one thread (about 20 s on a current server core)
+    O.set_threads(1)
+    t1 = time.perf_counter()
+    O.mul_relin(P, cts[0], cts[1], rlk)
+    dt1 = time.perf_counter() - t1
+    O.set_threads(cores)
     return {"value": ops / dt, "unit": "KS ops/s", "cores": cores, "kind": "oracle",
             "sample": f"{ops // 2} x (HMult+relin, rotation by 1) at N=2^16, L=24 on the same seeded inputs "
                       "(oracle C loops, OpenMP over limbs; key generation not timed)",
             "key_switches": ops,
-            "seconds": dt}
+            "seconds": dt,
+            "single_thread": {"value": 1.0 / dt1, "unit": "KS ops/s", "cores": 1,
+                              "sample": "1 x HMult+relin at N=2^16, L=24, same inputs", "seconds": dt1}}
 
 
 def batched_form(X, I, ctx16, rlk16, st, args):
@@ -327,10 +335,40 @@ def main():
         log(f"  {name:16s} launches={v['launches']:6d} avg_us={1e3 * v['ms'] / max(1, v['launches']):9.2f} "
             f"GB/s={v['bytes'] / max(1e-12, v['ms'] * 1e-3) / 1e9:8.1f} share={v['ms'] / (1e3 * p_elapsed):.3f}")
 
-    # per-operation device latency, outside the timed region
+    # per-operation device latency, outside the timed region: HIP events on the
+    # caller's stream around each call, 5 warm-up calls, 50 timed, median and
+    # p10 / p90 (each call also waits for the previous one's events)
     per_op = {}
+    ev0, ev1 = X.pfx_event_create(ctx), X.pfx_event_create(ctx)
 
-    def op_time(fn, reps=10):
+    def op_time(name, fn, prep=None, warm=5, reps=50):
+        ts = []
+        for r in range(warm + reps):
+            if prep:
+                prep()
+            X.pfx_event_record(ctx, ev0, st)
+            fn()
+            X.pfx_event_record(ctx, ev1, st)
+            t = X.pfx_event_elapsed(ctx, ev0, ev1)
+            if r >= warm:
+                ts.append(1e3 * t)
+        per_op[name] = float(np.median(ts))
+        per_op[name.replace("_us", "_p10_us")] = float(np.percentile(ts, 10))
+        per_op[name.replace("_us", "_p90_us")] = float(np.percentile(ts, 90))
+
+    op_time("ntt_fwd_ct_us", lambda: X.pfx_ntt(ctx, dbuf, 0, L, 2, False, st))
+    op_time("intt_ct_us", lambda: X.pfx_ntt(ctx, dbuf, 0, L, 2, True, st))
+    op_time("mul_relin_us", lambda: X.pfx_mul_relin(ctx, cts[0], cts[1], rlk, prod, st))
+    op_time("rotate_us", lambda: X.pfx_rotate(ctx, cts[0], 1, gks, rot, st))
+    op_time("rotate_2_14_us", lambda: X.pfx_rotate(ctx, cts[0], 1 << 14, gks, rot, st))
+    op_time("rescale_us", lambda: X.pfx_rescale(ctx, prod, rot, st),
+            prep=lambda: X.pfx_mul_relin(ctx, cts[0], cts[1], rlk, prod, st))
+    X.pfx_event_destroy(ctx, ev0)
+    X.pfx_event_destroy(ctx, ev1)
+    # the boundary's host interchange (PCIe-inclusive): canonical words of one
+    # ciphertext, 2 x 24 limbs = 24 MiB, host -> device and back
+    words = I.uniform_residues(q, N, 9, lead=(2,))
+    def host_time(fn, reps=5):
         X.pfx_sync(ctx, st)
         a = time.perf_counter()
         for _ in range(reps):
@@ -338,19 +376,8 @@ def main():
         X.pfx_sync(ctx, st)
         return 1e6 * (time.perf_counter() - a) / reps
 
-    per_op["ntt_fwd_ct_us"] = op_time(lambda: X.pfx_ntt(ctx, dbuf, 0, L, 2, False, st))
-    per_op["mul_relin_us"] = op_time(lambda: X.pfx_mul_relin(ctx, cts[0], cts[1], rlk, prod, st))
-    per_op["rotate_us"] = op_time(lambda: X.pfx_rotate(ctx, cts[0], 1, gks, rot, st))
-
-    def resc():
-        X.pfx_mul_relin(ctx, cts[0], cts[1], rlk, prod, st)
-        X.pfx_rescale(ctx, prod, prod, st)
-    per_op["rescale_us"] = op_time(resc) - per_op["mul_relin_us"]
-    # the boundary's host interchange (PCIe-inclusive): canonical words of one
-    # ciphertext, 2 x 24 limbs = 24 MiB, host -> device and back
-    words = I.uniform_residues(q, N, 9, lead=(2,))
-    per_op["ct_import_host_us"] = op_time(lambda: X.pfx_ct_import(ctx, words, SCALE, rot, st), reps=5)
-    per_op["ct_export_host_us"] = op_time(lambda: X.pfx_ct_export(ctx, rot, N, st), reps=5)
+    per_op["ct_import_host_us"] = host_time(lambda: X.pfx_ct_import(ctx, words, SCALE, rot, st))
+    per_op["ct_export_host_us"] = host_time(lambda: X.pfx_ct_export(ctx, rot, N, st))
     per_op["ct_interchange_bytes"] = int(words.nbytes)
 
     # ---- private query: 2^17 records x 8 attributes, degree-7 score polynomial,

@@ -430,6 +430,13 @@ pfx_status pfx_memcpy_dtoh(pfx_ctx *ctx, void *dst, const void *src, size_t byte
 /* Streams at the default priority. */
 pfx_status pfx_stream_create(pfx_ctx *ctx, void **out);
 pfx_status pfx_stream_destroy(pfx_ctx *ctx, void *stream);
+/* Timing events on a stream, for callers that time calls on the device: record
+ * one before and one after a call on the stream it runs on; pfx_event_elapsed
+ * waits for `end` and gives the device time between the two (ms). */
+pfx_status pfx_event_create(pfx_ctx *ctx, void **out);
+pfx_status pfx_event_record(pfx_ctx *ctx, void *event, void *stream);
+pfx_status pfx_event_elapsed(pfx_ctx *ctx, void *start, void *end, float *ms);
+pfx_status pfx_event_destroy(pfx_ctx *ctx, void *event);
 
 /* ------------------------------------------------------------ profiling */
 /* When on, the library brackets each kernel launch with HIP events on the

@@ -80,8 +80,19 @@ def lib():
         L.pfo_smul_rns.argtypes = [i, _u64p, sz, _u64p, _u64p, _u64p]
         L.pfo_bconv.argtypes = [sz, i, _u64p, _u64p, _u64p, i, _u64p, _u64p, _u64p]
         L.pfo_automorphism.argtypes = [i, _u64p, i, u, _u64p, _u64p]
+        L.pfo_threads.restype = i
+        L.pfo_set_threads.argtypes = [i]
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """Threads the oracle's OpenMP loops use (results do not depend on it)."""
+    return int(lib().pfo_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().pfo_set_threads(int(n))
 
 
 def _p(a: np.ndarray):

@@ -19,6 +19,7 @@
  *     the test suite pins (schoolbook convolution, O(N^2) transform, big-integer
  *     CRT).
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -219,3 +220,8 @@ void pfo_automorphism(int nl, const u64 *q, int logn, u64 g, const u64 *a, u64 *
             else out[l * n + (e - n)] = (v == 0) ? 0 : q[l] - v;
         }
 }
+
+/* Threads of the OpenMP loops above (plumbing for timing runs: the results
+ * do not depend on it). */
+int pfo_threads(void) { return omp_get_max_threads(); }
+void pfo_set_threads(int n) { omp_set_num_threads(n); }

@@ -1469,28 +1469,15 @@ pfx_status pfx_ntt(pfx_ctx *c, uint64_t *d_words, uint32_t first_prime, uint32_t
     REQUIRE(c && d_words, PFX_EINVAL, "null argument");
     REQUIRE(n_limbs >= 1 && first_prime + n_limbs <= (uint32_t)(c->L + c->K), PFX_EINVAL, "prime range out of bounds");
     REQUIRE(batch >= 1, PFX_EINVAL, "empty batch");
-    Ws w;
-    pfx_status r = get_ws(c, S(stream), w);
-    if (r) return r;
     Launch L{c, S(stream)};
-    const size_t N = c->N;
-    // convert to FP64 residues in the workspace in chunks of at most ext-sized limb counts
-    const size_t cap_limbs = (w.lay.acc - w.lay.ext) / N;
-    double *buf = w.at(w.lay.ext);
+    // two launches in place: words are converted as the first pass loads them
+    // and written back canonical by the last pass; launches of at most 2^20
+    // limbs keep the block count within int
     const size_t total_limbs = batch * n_limbs;
-    for (size_t l0 = 0; l0 < total_limbs; l0 += cap_limbs) {
-        const size_t nl = std::min(cap_limbs, total_limbs - l0);
-        launch_u64_to_f64(L, buf, d_words + l0 * N, nl * N);
-        for (size_t b0 = 0; b0 < nl; b0 += kMaxMapLimbs) {
-            LimbMap m;
-            m.n = (int)std::min<size_t>(kMaxMapLimbs, nl - b0);
-            for (int i = 0; i < m.n; ++i) {
-                m.off[i] = (int32_t)(b0 + i);
-                m.pid[i] = (int16_t)(first_prime + (l0 + b0 + i) % n_limbs);
-            }
-            launch_ntt(L, buf, nullptr, m, inverse != 0);
-        }
-        launch_f64_to_u64(L, d_words + l0 * N, buf, nl * N);
+    const size_t chunk = (size_t)n_limbs << (20 - std::min(20, (int)std::ceil(std::log2((double)n_limbs))));
+    for (size_t l0 = 0; l0 < total_limbs; l0 += chunk) {
+        const size_t nl = std::min(chunk, total_limbs - l0);
+        launch_ntt_words(L, d_words + l0 * c->N, nl, (int)first_prime, (int)n_limbs, inverse != 0);
     }
     return PFX_OK;
 }
@@ -1889,6 +1876,34 @@ pfx_status pfx_stream_create(pfx_ctx *c, void **out) {
     hipStream_t st;
     HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     *out = st;
+    return PFX_OK;
+}
+
+pfx_status pfx_event_create(pfx_ctx *c, void **out) {
+    REQUIRE(c && out, PFX_EINVAL, "null argument");
+    HIPCHECK(hipSetDevice(c->device));
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    *out = e;
+    return PFX_OK;
+}
+
+pfx_status pfx_event_record(pfx_ctx *c, void *event, void *stream) {
+    REQUIRE(c && event, PFX_EINVAL, "null argument");
+    HIPCHECK(hipEventRecord((hipEvent_t)event, S(stream)));
+    return PFX_OK;
+}
+
+pfx_status pfx_event_elapsed(pfx_ctx *c, void *start, void *end, float *ms) {
+    REQUIRE(c && start && end && ms, PFX_EINVAL, "null argument");
+    HIPCHECK(hipEventSynchronize((hipEvent_t)end));
+    HIPCHECK(hipEventElapsedTime(ms, (hipEvent_t)start, (hipEvent_t)end));
+    return PFX_OK;
+}
+
+pfx_status pfx_event_destroy(pfx_ctx *c, void *event) {
+    REQUIRE(c && event, PFX_EINVAL, "null argument");
+    HIPCHECK(hipEventDestroy((hipEvent_t)event));
     return PFX_OK;
 }
 

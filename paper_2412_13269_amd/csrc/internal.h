@@ -190,6 +190,9 @@ void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap 
 // nb copies of the map at base + b * bstride (doubles).
 void launch_ntt_pass(const Launch &L, double *base, const double *src, const LimbMap &map, bool row, bool inverse,
                      int nb = 1, size_t bstride = 0);
+// NTT / INTT of `limbs` limbs of canonical uint64 words in place (kernels.hip);
+// limb l uses prime first + l % nl.
+void launch_ntt_words(const Launch &L, uint64_t *words, size_t limbs, int first, int nl, bool inverse);
 void launch_u64_to_f64(const Launch &L, double *out, const uint64_t *in, size_t n);
 void launch_f64_to_u64(const Launch &L, uint64_t *out, const double *in, size_t n);
 void launch_int_to_rns(const Launch &L, double *out, const int64_t *in, int n_limbs, int pid0,

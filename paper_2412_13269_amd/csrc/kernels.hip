@@ -91,9 +91,10 @@ void launch_ntt_pass(const Launch &L, double *base, const double *src, const Lim
     a.map = map;
     const int th = pass_threads(logn, nb * map.n, row);
     PassShape ps = row ? row_shape(logn, th * kSlots) : col_shape(logn, th * kSlots);
-    // very small batches: narrower tiles (idle threads) so that the launch
-    // still covers the CUs (column tiles stay >= 8 columns = 64-byte rows)
-    const int minC = row ? 1 : 8;
+    // very small batches: narrower row tiles (idle threads) so that the launch
+    // still covers the CUs; column tiles stay >= 16 columns (128-byte rows:
+    // 8-column tiles measured 17.0 us against 11.0 us for a 48-limb pass)
+    const int minC = row ? 1 : 16;
     while (nb * map.n * ps.tiles < 1024 && ps.C / 2 >= minC) {
         ps.C /= 2;
         ps.tiles *= 2;
@@ -112,6 +113,57 @@ void launch_ntt_pass(const Launch &L, double *base, const double *src, const Lim
     PFX_SWITCH_TH(th, (dispatch_th<TH>(row, inverse, ps.S, grid, L.st, a)));
     HIP_LAUNCH_CHECK();
     prof_end(L, nm, ev, 16.0 * (double)ctx->N * map.n * nb);
+}
+
+// Transform of canonical uint64 words in place (the standalone entry point):
+// the first pass reads words and converts them as it loads, the last pass
+// stores canonical words; the intermediate is FP64 residues in the same
+// memory (8 bytes per element either way; every block reads its whole tile
+// before it writes it).  Limb l of the launch uses prime first + l % nl.
+template <int S, bool ROW, bool INV, int TH, bool IN_WORDS, bool OUT_WORDS>
+__global__ __launch_bounds__(TH) void k_ntt_words(uint64_t *words, const PrimeDev *primes, int logn, int C,
+                                                  int tiles, int nblk, int first, int nl) {
+    __shared__ double lds[NttTile<TH>::lds];
+    const int id = xcd_slot(nblk);
+    if (id >= nblk) return;
+    const int limb = id / tiles;
+    const int tile = id - limb * tiles;
+    const PrimeDev &P = primes[first + limb % nl];
+    uint64_t *wl = words + ((size_t)limb << logn);
+    double *dl = reinterpret_cast<double *>(wl);
+    auto ld = [&](int j, int) { return IN_WORDS ? (double)wl[(unsigned)j] : dl[(unsigned)j]; };
+    auto st = [&](int j, double v, int) {
+        if (OUT_WORDS) wl[(unsigned)j] = (uint64_t)v;
+        else dl[(unsigned)j] = v;
+    };
+    if (ROW) row_pass<S, INV, TH>(P, logn, C, tile * C, lds, ld, st);
+    else col_pass<S, INV, TH>(P, logn, C, tile * C, lds, ld, st);
+}
+
+template <bool ROW, bool INV, bool IW, bool OW>
+static void words_pass(uint64_t *words, pfx_ctx *ctx, size_t limbs, int first, int nl, hipStream_t st,
+                       const char *name, const Launch &L) {
+    const int logn = ctx->logn;
+    const int th = pass_threads(logn, (int)limbs, ROW);
+    const PassShape ps = ROW ? row_shape(logn, th * kSlots) : col_shape(logn, th * kSlots);
+    const int nblk = (int)limbs * ps.tiles;
+    hipEvent_t ev;
+    prof_begin(L, name, &ev);
+    PFX_SWITCH_TH(th, PFX_SWITCH_S(ps.S, (k_ntt_words<SS, ROW, INV, TH, IW, OW><<<xcd_grid(nblk), TH, 0, st>>>(
+                                           words, ctx->d_primes, logn, ps.C, ps.tiles, nblk, first, nl))));
+    HIP_LAUNCH_CHECK();
+    prof_end(L, name, ev, 16.0 * (double)ctx->N * (double)limbs);
+}
+
+void launch_ntt_words(const Launch &L, uint64_t *words, size_t limbs, int first, int nl, bool inverse) {
+    if (limbs == 0) return;
+    if (!inverse) {
+        words_pass<false, false, true, false>(words, L.ctx, limbs, first, nl, L.st, "ntt_words_col", L);
+        words_pass<true, false, false, true>(words, L.ctx, limbs, first, nl, L.st, "ntt_words_row", L);
+    } else {
+        words_pass<true, true, true, false>(words, L.ctx, limbs, first, nl, L.st, "intt_words_row", L);
+        words_pass<false, true, false, true>(words, L.ctx, limbs, first, nl, L.st, "intt_words_col", L);
+    }
 }
 
 void launch_ntt(const Launch &L, double *base, const double *src, const LimbMap &map, bool inverse) {

@@ -145,6 +145,10 @@ _SIGS = {
     "pfx_memcpy_dtoh": (_i32, [_vp, _vp, _vp, _sz, _vp]),
     "pfx_stream_create": (_i32, [_vp, _VPP]),
     "pfx_stream_destroy": (_i32, [_vp, _vp]),
+    "pfx_event_create": (_i32, [_vp, _VPP]),
+    "pfx_event_record": (_i32, [_vp, _vp, _vp]),
+    "pfx_event_elapsed": (_i32, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)]),
+    "pfx_event_destroy": (_i32, [_vp, _vp]),
     "pfx_profile_enable": (_i32, [_vp, ctypes.c_int]),
     "pfx_profile_get": (_i32, [_vp, ctypes.c_char_p, _u64p, _f64p, _f64p]),
     "pfx_profile_names": (_i32, [_vp, ctypes.c_char_p, _sz]),
@@ -542,6 +546,26 @@ def pfx_stream_create(ctx) -> int:
 
 def pfx_stream_destroy(ctx, stream: int):
     _check(_lib.pfx_stream_destroy(ctx, ctypes.c_void_p(stream)))
+
+
+def pfx_event_create(ctx) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_event_create(ctx, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_event_record(ctx, event: int, stream=None):
+    _check(_lib.pfx_event_record(ctx, ctypes.c_void_p(event), _stream(stream)))
+
+
+def pfx_event_elapsed(ctx, start: int, end: int) -> float:
+    ms = ctypes.c_float()
+    _check(_lib.pfx_event_elapsed(ctx, ctypes.c_void_p(start), ctypes.c_void_p(end), ctypes.byref(ms)))
+    return ms.value
+
+
+def pfx_event_destroy(ctx, event: int):
+    _check(_lib.pfx_event_destroy(ctx, ctypes.c_void_p(event)))
 
 
 # ---------------------------------------------------------------- profiling

@@ -397,3 +397,22 @@ def test_full_size_mul_relin_batch(full, X):
     for i in range(4):
         X.pfx_mul_relin(full.ctx, cts[i], cts[i + 1], kx, one)
         assert np.array_equal(full.words(outs[i]), full.words(one)), i
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+def test_full_size_standalone_ntt_offset_primes(full, X, inverse):
+    """N = 2^16: three blocks of 5 limbs on primes 3..7 (limb l of a block on
+    prime 3 + l), against the oracle's transform."""
+    P = full.P
+    mods = (P.q + P.p)[3:8]
+    psis = (P.psi_q + P.psi_p)[3:8]
+    words = I.uniform_residues(mods, P.N, 17, lead=(3,))
+    dev = X.pfx_dev_alloc(full.ctx, words.nbytes)
+    X.pfx_memcpy_htod(full.ctx, dev, words)
+    X.pfx_ntt(full.ctx, dev, 3, 5, 3, inverse)
+    got = np.empty_like(words)
+    X.pfx_memcpy_dtoh(full.ctx, got, dev)
+    X.pfx_dev_free(full.ctx, dev)
+    fn = O.intt if inverse else O.ntt
+    for b in range(3):
+        assert np.array_equal(got[b], fn(words[b], mods, psis, P.logn)), b
