@@ -228,7 +228,7 @@ def served_form(X, I, ctx, sk, q, rlk, gks, st, args):
         while not free_outs:
             reap()
         out = free_outs.pop()
-        tk = X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out)
+        tk = X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out, plan.reg_degree)
         pending[tk] = (out, 1 << k)
 
     rng = np.random.default_rng(501)
@@ -391,7 +391,8 @@ def main():
     plan = plans["blocks_on_lanes"]
     x = I.synthetic_database(n_blocks * (N // 2), A, 301)
     w, c, t, eta = I.query_parameters(A, D, 302)
-    regs = [X.pfx_ct_create(ctx, L, 1) for _ in range(max(p.n_regs for p in plans.values()))]
+    regs = [X.pfx_ct_create(ctx, L, max(p.reg_degree[i] if i < p.n_regs else 1 for p in plans.values()))
+            for i in range(max(p.n_regs for p in plans.values()))]
     for i, v in enumerate(list(w) + list(c) + [t, eta]):
         pt = X.pfx_encode(ctx, np.full(N // 2, v), None, L, SCALE)
         X.pfx_encrypt(ctx, sk, pt, I.uniform_residues(q, N, 400 + 2 * i), I.gaussian_error(N, 401 + 2 * i),

@@ -185,6 +185,12 @@ pfx_status pfx_mul(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, 
 /* Relinearisation (App. A.2): (d0, d1) + SwitchKey(d2, swk_{s^2 -> s}). */
 pfx_status pfx_relinearize(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *rlk, pfx_ct *out,
                            void *stream);
+/* Relinearisation of n degree-2 ciphertexts: out[i] = relin(a[i]), word for
+ * word n calls of pfx_relinearize; those of one level share batched key-switch
+ * launches (up to 8).  out[i] may be a[i]; it must not alias another entry's
+ * input or output (PFX_EINVAL).  Scratch as pfx_mul_relin_batch. */
+pfx_status pfx_relinearize_batch(pfx_ctx *ctx, const pfx_ct *const *a, size_t n, const pfx_swk *rlk,
+                                 pfx_ct *const *out, void *stream);
 /* HMult + relinearisation in one call. */
 pfx_status pfx_mul_relin(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk,
                          pfx_ct *out, void *stream);
@@ -259,6 +265,9 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
  *   ADD_PLAIN     dst = a + pts[b]                               b plaintext
  *   MUL_INT       dst = a * k                                    k
  *   MUL_RELIN     dst = relin(a * b)                             b register
+ *   MUL           dst = a * b, degree 2 (pfx_mul; dst needs     b register
+ *                 capacity for degree 2)
+ *   RELIN         dst = relin(a), a of degree 2
  *   RESCALE       dst = rescale(a)
  *   ADD_CONST     dst = a + value (pfx_add_const)                value
  *   MUL_CONST     dst = a * value at the last prime's scale      value
@@ -301,6 +310,8 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
 #define PFX_OP_ROTATE 11
 #define PFX_OP_ROTATE_SUM 12
 #define PFX_OP_LANE 13
+#define PFX_OP_MUL 14
+#define PFX_OP_RELIN 15
 
 typedef struct pfx_op {
     int32_t code;
@@ -357,8 +368,9 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
  * key-switching scratch (fixed; with max_batch > 1 it includes the batch
  * region for max_batch entries), and the rest as one arena from which each
  * admitted request's work registers are carved.  A request's footprint is
- * (n_regs - n_inputs) ciphertexts of degree 1 at the largest level among its
- * inputs: 2 * max(inputs' n_limbs) * N * 8 bytes each.  The evaluation keys
+ * its work registers at the largest level among its inputs: (degree + 1) *
+ * max(inputs' n_limbs) * N * 8 bytes each, degree from reg_degree (1 when
+ * NULL).  The evaluation keys
  * (rlk, gks: resident, shared by every request), the input ciphertexts and the
  * plaintexts are the caller's and are not counted.
  *
@@ -384,6 +396,8 @@ typedef struct pfx_request {
     size_t n_pts;
     int32_t out_reg;               /* in [n_inputs, n_regs) */
     pfx_ct *out;
+    const uint8_t *reg_degree;     /* per register: capacity degree (1 or 2) of a work
+                                      register; NULL: every work register degree 1 */
 } pfx_request;
 
 typedef struct pfx_request_info {

@@ -9,7 +9,9 @@ score of the query in place of the paper's coefficient-encoded PFE phase:
     Y_k = powers of S up to degree D <= 15 by the binary tree
           Y2 = Y1 Y1, Y3 = Y2 Y1, Y4 = Y2 Y2, Y5 = Y4 Y1, Y6 = Y4 Y2, Y7 = Y4 Y3,
           Y8 = Y4 Y4, Y(8+i) = Y8 Yi
-    Z   = sum_{k=1..D} rescale(relin(C[k] Y_k)) + C[0]       polynomial p(S)
+    Z   = rescale(relin(sum_{k=1..D} C[k] (x) Y_k)) + C[0]   polynomial p(S): the
+          tensor products (degree 2) are summed, at the level of the deepest
+          Y_k, and relinearised and rescaled once
     U   = rescale(relin((Z - T) H))                          normalised threshold input
     3 times (composite sign, degree-7 stage f7(x) = (35x - 35x^3 + 21x^5 - 5x^7)/16):
         X2 = X X, X4 = X2 X2, X6 = X4 X2                     (relin + rescale each)
@@ -122,10 +124,10 @@ def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None)
             s = O.ct_add(P, s, O.ct_mul_plain(P, W[a], X[b][a], x_scale))
         s = O.rescale(P, s)
         Y = _powers(P, s, D, rlk)
-        z = _mr(P, C[1], Y[1], rlk)
+        z2 = O.tensor(P, C[1], Y[1])
         for k in range(2, D + 1):
-            z = O.ct_add(P, z, _mr(P, C[k], Y[k], rlk))
-        z = O.ct_add(P, z, C[0])
+            z2 = O.ct_add(P, z2, O.tensor(P, C[k], Y[k]))
+        z = O.ct_add(P, O.rescale(P, O.relinearize(P, z2, rlk)), C[0])
         u = _mr(P, O.ct_sub(P, z, T), H, rlk)
         for _ in range(stages):
             u = sign_stage(P, u, rlk)

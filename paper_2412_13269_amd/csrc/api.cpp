@@ -307,6 +307,8 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
         case PFX_OP_ADD_PLAIN: r = pfx_add_plain(c, A, pt, d, stream); break;
         case PFX_OP_MUL_INT: r = pfx_mul_int(c, A, o.k, d, stream); break;
         case PFX_OP_MUL_RELIN: r = pfx_mul_relin(c, A, R(o.b), rlk, d, stream); break;
+        case PFX_OP_MUL: r = pfx_mul(c, A, R(o.b), d, stream); break;
+        case PFX_OP_RELIN: r = pfx_relinearize(c, A, rlk, d, stream); break;
         case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
         case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
         case PFX_OP_MUL_CONST: r = pfx_mul_const(c, A, o.value, 0.0, d, stream); break;
@@ -325,14 +327,15 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
 }
 
 // Length of the run of ops starting at ops[i] that one batched launch sequence
-// may take: consecutive HMult + relin ops (or consecutive rescales), at most
-// max_batch, outputs distinct and none of them an operand of another op of the
-// run, so the ops are independent.  An HMult + relin output must not alias its
-// own operands either (the batched key switch reads them while it writes); a
-// rescale may work in place.  1 if ops[i] alone; 0 for any other op.
+// may take: consecutive HMult + relin ops (or consecutive relinearisations, or
+// rescales), at most max_batch, outputs distinct and none of them an operand of
+// another op of the run, so the ops are independent.  An HMult + relin output
+// must not alias its own operands either (the batched key switch reads them
+// while it writes); a relinearisation or a rescale may work in place.  1 if
+// ops[i] alone; 0 for any other op.
 size_t mr_run(const pfx_op *ops, size_t n_ops, size_t i, int max_batch) {
     const int32_t code = ops[i].code;
-    if (code != PFX_OP_MUL_RELIN && code != PFX_OP_RESCALE) return 0;
+    if (code != PFX_OP_MUL_RELIN && code != PFX_OP_RESCALE && code != PFX_OP_RELIN) return 0;
     const bool mr = code == PFX_OP_MUL_RELIN;
     auto reads = [&](const pfx_op &o, int32_t r) { return o.a == r || (mr && o.b == r); };
     const pfx_op &f = ops[i];
@@ -361,9 +364,9 @@ size_t max_mr_run(const pfx_op *ops, size_t n_ops, int max_batch) {
     return m;
 }
 
-// ops[lo, hi) on one stream; runs of independent HMult + relin ops or
-// rescales (mr_run) go to pfx_mul_relin_batch / pfx_rescale_batch when
-// max_batch > 1.
+// ops[lo, hi) on one stream; runs of independent HMult + relin ops,
+// relinearisations or rescales (mr_run) go to pfx_mul_relin_batch /
+// pfx_relinearize_batch / pfx_rescale_batch when max_batch > 1.
 pfx_status run_span(pfx_ctx *c, const pfx_op *ops, size_t lo, size_t hi, pfx_ct *const *regs, size_t n_regs,
                     size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
                     const pfx_swk *const *gks, size_t n_gks, void *stream, int max_batch) {
@@ -392,7 +395,8 @@ pfx_status run_span(pfx_ctx *c, const pfx_op *ops, size_t lo, size_t hi, pfx_ct 
                 }
             if (distinct) {
                 pfx_status r = mr ? pfx_mul_relin_batch(c, a, b, run, rlk, out, stream)
-                                  : pfx_rescale_batch(c, a, run, out, stream);
+                               : ops[i].code == PFX_OP_RELIN ? pfx_relinearize_batch(c, a, run, rlk, out, stream)
+                                                             : pfx_rescale_batch(c, a, run, out, stream);
                 if (r) return fail(r, "ops " + std::to_string(i) + ".." + std::to_string(i + run - 1) + ": " + g_err);
                 i += run;
                 continue;
@@ -1236,6 +1240,63 @@ pfx_status pfx_mul_relin_batch(pfx_ctx *c, const pfx_ct *const *a, const pfx_ct 
     return PFX_OK;
 }
 
+pfx_status pfx_relinearize_batch(pfx_ctx *c, const pfx_ct *const *a, size_t n, const pfx_swk *rlk,
+                                 pfx_ct *const *out, void *stream) {
+    REQUIRE(c && (n == 0 || (a && out)), PFX_EINVAL, "null argument");
+    REQUIRE(rlk && rlk->ctx == c, PFX_EINVAL, "bad relinearisation key");
+    REQUIRE(rlk->galois == 0, PFX_ENOKEY, "key is not a relinearisation key");
+    for (size_t i = 0; i < n; ++i) {
+        pfx_status r = check_ct(c, a[i], "a");
+        if (r) return r;
+        REQUIRE(a[i]->degree == 2, PFX_EINVAL, "relinearize needs a degree-2 ciphertext");
+        r = check_out(out[i], a[i]->n_limbs, 1);
+        if (r) return r;
+    }
+    for (size_t i = 0; i < n; ++i)        // in place allowed; never into another entry
+        for (size_t j = 0; j < n; ++j)
+            if (i != j) {
+                REQUIRE(out[i]->d != a[j]->d, PFX_EINVAL, "batched relinearize output aliases another input");
+                REQUIRE(out[i]->d != out[j]->d, PFX_EINVAL, "batched relinearize outputs alias");
+            }
+    if (n == 0) return PFX_OK;
+    Ws w;
+    pfx_status r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    std::vector<int> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return a[x]->n_limbs > a[y]->n_limbs; });
+    std::vector<double> sc(n);
+    std::vector<uint32_t> lvs(n);
+    for (size_t i = 0; i < n; ++i) {
+        sc[i] = a[i]->scale;
+        lvs[i] = a[i]->n_limbs;
+    }
+    for (size_t s0 = 0; s0 < n;) {
+        size_t s1 = s0;
+        while (s1 < n && s1 - s0 < (size_t)kMaxBatch && lvs[order[s1]] == lvs[order[s0]]) ++s1;
+        KsBatch kb;
+        r = get_batch_ws(c, L.st, (int)(s1 - s0), kb);
+        if (r) return r;
+        kb.nb = (int)(s1 - s0);
+        kb.mode = KS_PLAIN;
+        for (int e = 0; e < kb.nb; ++e) {
+            const int i = order[s0 + e];
+            kb.op[e] = ks_plain(a[i]->poly(2), a[i]->poly(0), a[i]->poly(1));
+            kb.out0[e] = out[i]->poly(0);
+            kb.out1[e] = out[i]->poly(1);
+        }
+        ks_run(L, kb, (int)lvs[order[s0]], rlk);
+        s0 = s1;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        out[i]->n_limbs = lvs[i];
+        out[i]->degree = 1;
+        out[i]->scale = sc[i];
+    }
+    return PFX_OK;
+}
+
 pfx_status pfx_rescale(pfx_ctx *c, const pfx_ct *a, pfx_ct *out, void *stream) {
     pfx_status r = check_ct(c, a, "a");
     if (r) return r;
@@ -1506,7 +1567,7 @@ static pfx_status ensure_lanes(pfx_ctx *c) {
 // inside a fork is checked to lie on its own lane or before the fork, so that
 // the fork/join events alone order the list.
 static bool reads_b_register(int32_t code) {
-    return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN;
+    return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN || code == PFX_OP_MUL;
 }
 
 static pfx_status check_lanes(const pfx_op *ops, size_t n_ops, size_t n_regs) {

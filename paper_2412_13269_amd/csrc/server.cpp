@@ -91,6 +91,7 @@ struct Request {
     int32_t out_reg = -1;
     pfx_ct *out = nullptr;
     uint32_t reg_limbs = 0;
+    std::vector<uint8_t> reg_degree;     // capacity degree of each work register
     size_t footprint = 0;
     size_t arena_off = 0;
     int slot = -1;
@@ -159,15 +160,16 @@ void admit(pfx_server *s, Request *r, int slot) {
     r->slot = slot;
     r->state = State::Running;
     r->t_admit = Clock::now();
-    const size_t ct_doubles = 2 * (size_t)r->reg_limbs * c->N;
-    double *base = reinterpret_cast<double *>(s->arena.base + r->arena_off);
+    const size_t poly_doubles = (size_t)r->reg_limbs * c->N;
+    double *next = reinterpret_cast<double *>(s->arena.base + r->arena_off);
     for (size_t i = r->n_inputs; i < r->n_regs; ++i) {
         pfx_ct *v = new pfx_ct;
         v->ctx = c;
         v->cap_limbs = r->reg_limbs;
-        v->cap_degree = 1;
-        v->d = base + (i - r->n_inputs) * ct_doubles;
+        v->cap_degree = r->reg_degree[i];
+        v->d = next;
         v->owns = false;
+        next += (v->cap_degree + 1) * poly_doubles;
         r->regs[i] = v;
     }
     s->running[slot] = r;
@@ -327,7 +329,17 @@ pfx_status pfx_server_submit(pfx_server *s, const pfx_request *rq, uint64_t *tic
     r->pts.assign(rq->pts, rq->pts + rq->n_pts);
     r->out_reg = rq->out_reg;
     r->out = rq->out;
-    r->footprint = (rq->n_regs - rq->n_inputs) * 2 * (size_t)r->reg_limbs * s->ctx->N * sizeof(double);
+    r->reg_degree.assign(rq->n_regs, 1);
+    size_t polys = 0;
+    for (size_t i = rq->n_inputs; i < rq->n_regs; ++i) {
+        if (rq->reg_degree) {
+            REQUIRE(rq->reg_degree[i] == 1 || rq->reg_degree[i] == 2, PFX_EINVAL,
+                    "register " + std::to_string(i) + ": degree must be 1 or 2");
+            r->reg_degree[i] = rq->reg_degree[i];
+        }
+        polys += r->reg_degree[i] + 1;
+    }
+    r->footprint = polys * (size_t)r->reg_limbs * s->ctx->N * sizeof(double);
     REQUIRE(Arena::round(r->footprint) <= s->arena.size, PFX_ENOMEM,
             "footprint of " + std::to_string(r->footprint) + " bytes exceeds the arena (" +
                 std::to_string(s->arena.size) + " bytes)");

@@ -45,7 +45,7 @@ class pfx_op(ctypes.Structure):
 
 OP_COPY, OP_ADD, OP_SUB, OP_MUL_PLAIN, OP_ADD_PLAIN, OP_MUL_INT, OP_MUL_RELIN = 0, 1, 2, 3, 4, 5, 6
 OP_RESCALE, OP_ADD_CONST, OP_MUL_CONST, OP_SCALE_MUL, OP_ROTATE, OP_ROTATE_SUM = 7, 8, 9, 10, 11, 12
-OP_LANE = 13
+OP_LANE, OP_MUL, OP_RELIN = 13, 14, 15
 
 
 class pfx_info(ctypes.Structure):
@@ -57,7 +57,8 @@ class pfx_request(ctypes.Structure):
     _fields_ = [("ops", ctypes.POINTER(pfx_op)), ("n_ops", ctypes.c_size_t), ("n_regs", ctypes.c_size_t),
                 ("n_inputs", ctypes.c_size_t), ("inputs", ctypes.POINTER(ctypes.c_void_p)),
                 ("pts", ctypes.POINTER(ctypes.c_void_p)), ("n_pts", ctypes.c_size_t),
-                ("out_reg", ctypes.c_int32), ("out", ctypes.c_void_p)]
+                ("out_reg", ctypes.c_int32), ("out", ctypes.c_void_p),
+                ("reg_degree", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class pfx_request_info(ctypes.Structure):
@@ -122,6 +123,7 @@ _SIGS = {
     "pfx_mul_relin_batch": (_i32, [_vp, _VPP, _VPP, _sz, _vp, _VPP, _vp]),
     "pfx_rescale": (_i32, [_vp, _vp, _vp, _vp]),
     "pfx_rescale_batch": (_i32, [_vp, _VPP, _sz, _VPP, _vp]),
+    "pfx_relinearize_batch": (_i32, [_vp, _VPP, _sz, _vp, _VPP, _vp]),
     "pfx_drop_level": (_i32, [_vp, _vp, _u32, _vp, _vp]),
     "pfx_key_switch": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_apply_galois": (_i32, [_vp, _vp, _vp, _vp, _vp]),
@@ -410,6 +412,13 @@ def pfx_rescale(ctx, a, out, stream=None):
     _check(_lib.pfx_rescale(ctx, a, out, _stream(stream)))
 
 
+def pfx_relinearize_batch(ctx, a, rlk, outs, stream=None):
+    n = len(a)
+    assert len(outs) == n
+    arr = lambda xs: (ctypes.c_void_p * max(1, n))(*xs)
+    _check(_lib.pfx_relinearize_batch(ctx, arr(a), n, rlk, arr(outs), _stream(stream)))
+
+
 def pfx_rescale_batch(ctx, a, outs, stream=None):
     n = len(a)
     assert len(outs) == n
@@ -486,12 +495,18 @@ def pfx_server_create(ctx, hbm_budget: int, slots: int, rlk, gks, max_batch: int
     return h.value
 
 
-def pfx_server_submit(srv, ops, n_regs: int, inputs, pts, out_reg: int, out) -> int:
-    """ops: a sequence of (code, dst, a, b, k, value); inputs are registers 0..len(inputs)-1."""
+def pfx_server_submit(srv, ops, n_regs: int, inputs, pts, out_reg: int, out, reg_degree=None) -> int:
+    """ops: a sequence of (code, dst, a, b, k, value); inputs are registers 0..len(inputs)-1;
+    reg_degree: capacity degree (1 or 2) per register, None for all 1."""
     arr = (pfx_op * max(1, len(ops)))(*[pfx_op(*o) for o in ops])
     I = (ctypes.c_void_p * max(1, len(inputs)))(*inputs)
     Pt = (ctypes.c_void_p * max(1, len(pts)))(*pts)
-    rq = pfx_request(arr, len(ops), n_regs, len(inputs), I, Pt, len(pts), out_reg, out)
+    D = None
+    if reg_degree is not None:
+        assert len(reg_degree) == n_regs
+        D = (ctypes.c_uint8 * max(1, n_regs))(*reg_degree)
+    rq = pfx_request(arr, len(ops), n_regs, len(inputs), I, Pt, len(pts), out_reg, out,
+                     ctypes.cast(D, ctypes.POINTER(ctypes.c_uint8)) if D is not None else None)
     t = ctypes.c_uint64()
     _check(_lib.pfx_server_submit(srv, ctypes.byref(rq), ctypes.byref(t)))
     return t.value

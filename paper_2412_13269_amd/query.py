@@ -7,7 +7,8 @@ slot-domain linear score): for each block b of 2^(logN-1) records
     Y_k = S^k by the binary power tree (Y2 = Y1 Y1, Y3 = Y2 Y1, Y4 = Y2 Y2,
           Y5 = Y4 Y1, Y6 = Y4 Y2, Y7 = Y4 Y3, Y8 = Y4 Y4, Y(8+i) = Y8 Yi;
           each relinearised and rescaled), degree D <= 15
-    Z   = sum_{k=1..D} rescale(relin(C[k] Y_k)) + C[0]
+    Z   = rescale(relin(sum_{k=1..D} C[k] (x) Y_k)) + C[0]   (tensor products
+          summed at degree 2, one relinearisation)
     U   = rescale(relin((Z - T) H))
     3 stages of f7(x) = (35x - 35x^3 + 21x^5 - 5x^7)/16:
         X2 = X^2, X4 = X2^2, X6 = X4 X2
@@ -19,7 +20,9 @@ slot-domain linear score): for each block b of 2^(logN-1) records
 Inputs (registers, read-only): W[0..A), C[0..D], T, H.  Plaintexts: X[b][a]
 at index b * A + a.  The op list and the register allocation are built here;
 the library executes them (eagerly, or captured once into a HIP graph; on one
-stream, or scheduled over its lane streams by register dependencies).
+stream, or scheduled over its lane streams by register dependencies).  The
+registers that hold the degree-2 sum need capacity for degree 2: reg_degree
+gives the capacity degree of every register (1 or 2).
 
 Register allocation: temporaries are recycled through a free list.  With
 parallel=False and interleave=False one list serves the whole circuit (fewest
@@ -68,25 +71,29 @@ class QueryPlan:
         self.T = A + D + 1
         self.H = A + D + 2
         self.n_inputs = A + D + 3
-        self._free: list[int] = []
+        self._free: dict = {1: [], 2: []}
         self._next = self.n_inputs
+        self._deg2: set = set()
         self._build()
         self.n_regs = self._next
+        self.reg_degree = [2 if r in self._deg2 else 1 for r in range(self.n_regs)]
 
 
 
-    # register allocation
-    def _new(self) -> int:
-        if self._free:
-            return self._free.pop()
+    # register allocation: free lists by capacity degree
+    def _new(self, degree: int = 1) -> int:
+        if self._free[degree]:
+            return self._free[degree].pop()
         r = self._next
         self._next += 1
+        if degree == 2:
+            self._deg2.add(r)
         return r
 
     def _drop(self, *regs):
         for r in regs:
             if r >= self.n_inputs:
-                self._free.append(r)
+                self._free[2 if r in self._deg2 else 1].append(r)
 
     def _op(self, code, dst, a, b=-1, k=0, value=0.0):
         self.ops.append((code, dst, a, b, k, value))
@@ -116,11 +123,15 @@ class QueryPlan:
         for k in range(2, D + 1):
             Y[k] = self._new()
             self._mr(Y[k], Y[tree[k][0]], Y[tree[k][1]])
-        z = self._new()
-        self._mr(z, self.C[1], Y[1])
+        z2, t2 = self._new(2), self._new(2)
+        self._op(X.OP_MUL, z2, self.C[1], Y[1])
         for k in range(2, D + 1):
-            self._mr(t, self.C[k], Y[k])
-            self._op(X.OP_ADD, z, z, t)
+            self._op(X.OP_MUL, t2, self.C[k], Y[k])
+            self._op(X.OP_ADD, z2, z2, t2)
+        z = self._new()
+        self._op(X.OP_RELIN, z, z2)
+        self._op(X.OP_RESCALE, z, z)
+        self._drop(z2, t2)
         self._op(X.OP_ADD, z, z, self.C[0])
         self._drop(*Y.values())
         u = self._new()
@@ -159,7 +170,7 @@ class QueryPlan:
                     self._op(X.OP_LANE, 0, 0, k=lane)
                 lists = []
                 for b in blocks:
-                    self._free = []     # every block recycles only its own registers
+                    self._free = {1: [], 2: []}     # every block recycles only its own registers
                     start = len(self.ops)
                     us.append(self._block(b))
                     lists.append(self.ops[start:])
@@ -173,13 +184,13 @@ class QueryPlan:
                         self.ops.extend(ops)
             if self.parallel:
                 self._op(X.OP_LANE, 0, 0, k=-1)
-            self._free = []
+            self._free = {1: [], 2: []}
             total = us[0]
             for u in us[1:]:
                 self._op(X.OP_ADD, total, total, u)
         elif self.interleave is not False and int(self.interleave) >= 2:
             G = int(self.interleave)
-            pools = [[] for _ in range(G)]          # block i of every group recycles pools[i]
+            pools = [{1: [], 2: []} for _ in range(G)]   # block i of every group recycles pools[i]
             total = None
             for g0 in range(0, self.n_blocks, G):
                 lists, us = [], []
@@ -197,8 +208,8 @@ class QueryPlan:
                         total = u
                     else:
                         self._op(X.OP_ADD, total, total, u)
-                        pools[i].append(u)
-            self._free = [r for pool in pools for r in pool]
+                        pools[i][1].append(u)
+            self._free = {d: [r for pool in pools for r in pool[d]] for d in (1, 2)}
         else:
             total = None
             for b in range(self.n_blocks):
@@ -214,4 +225,4 @@ class QueryPlan:
 
     @property
     def key_switches(self) -> int:
-        return sum(1 for o in self.ops if o[0] == X.OP_MUL_RELIN) + self.log_slots
+        return sum(1 for o in self.ops if o[0] in (X.OP_MUL_RELIN, X.OP_RELIN)) + self.log_slots

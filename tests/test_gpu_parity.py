@@ -277,6 +277,34 @@ def test_rescale_batch(pair, X):
     X.pfx_rescale_batch(pair.ctx, [], [])
 
 
+def test_relinearize_batch(pair, X):
+    """Batched relinearisation: five tensor products over two levels, two of
+    them in place, word for word the single calls; the first against the
+    oracle."""
+    P = pair.P
+    ko, kx = pair.key(0)
+    cts = [pair.enc(P.L if i % 2 else P.L - 1) for i in range(6)]
+    tens = []
+    for i in range(5):
+        t = pair.ct(P.L)
+        X.pfx_mul(pair.ctx, cts[i][1], cts[i + 1][1], t)
+        tens.append(t)
+    want = []
+    for t in tens:
+        o = pair.ct(P.L)
+        X.pfx_relinearize(pair.ctx, t, kx, o)
+        want.append(pair.words(o))
+    outs = [t if i in (1, 3) else pair.ct(P.L) for i, t in enumerate(tens)]
+    X.pfx_relinearize_batch(pair.ctx, tens, kx, outs)
+    for i in range(5):
+        assert np.array_equal(pair.words(outs[i]), want[i]), i
+        assert X.pfx_ct_info(outs[i]).degree == 1
+    pair.same(O.relinearize(P, O.tensor(P, cts[0][0], cts[1][0]), ko), outs[0])
+    with pytest.raises(X.PfxError) as e:             # degree-1 input
+        X.pfx_relinearize_batch(pair.ctx, [outs[0]], kx, [pair.ct(P.L)])
+    assert e.value.status == X.PFX_EINVAL
+
+
 def test_rescale_every_level(pair, X):
     P = pair.P
     co, cx, z = pair.enc(P.L)

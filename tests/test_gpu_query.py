@@ -84,7 +84,7 @@ class Setup:
             encode = lambda z: X.pfx_encode_words(prm, z, None, len(QB), DELTA)
         enc_words = [encode(np.full(self.n, v)) for v in list(w) + list(c) + [t, eta]]
         self.enc_in = []
-        self.regs = [X.pfx_ct_create(self.ctx, len(QB), 1) for _ in range(self.plan.n_regs)]
+        self.regs = [X.pfx_ct_create(self.ctx, len(QB), self.plan.reg_degree[i]) for i in range(self.plan.n_regs)]
         self.pts = []
         for i, m in enumerate(enc_words):
             a = I.uniform_residues(self.q, N, seed + 500 + 2 * i)
@@ -100,6 +100,16 @@ class Setup:
                 self.db_words.append(m)
                 self.pts.append(X.pfx_pt_import(self.ctx, m, DELTA))
         self.stream = X.pfx_stream_create(self.ctx)
+
+    def use_plan(self, plan):
+        """Another op list over the same inputs: fresh work registers for it."""
+        X = self.X
+        assert plan.n_inputs == self.plan.n_inputs
+        for h in self.regs[plan.n_inputs:]:
+            X.pfx_ct_destroy(h)
+        self.regs = self.regs[:plan.n_inputs] + [X.pfx_ct_create(self.ctx, len(QB), plan.reg_degree[i])
+                                                 for i in range(plan.n_inputs, plan.n_regs)]
+        self.plan = plan
 
     def run(self, graph=False, lanes=False):
         X = self.X
@@ -228,14 +238,11 @@ def test_full_size_query_count(X):
         out = S.run(graph=True, lanes=True)
         assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), ref)
         from paper_2412_13269_amd.query import QueryPlan
-        plan = S.plan
         for kw in (dict(interleave=True), dict(parallel=True, lanes=2, interleave=True)):
-            S.plan = QueryPlan(4, 8, 7, 3, 15, **kw)        # same registers: every plan fits in 55
-            assert S.plan.n_regs <= len(S.regs)
+            S.use_plan(QueryPlan(4, 8, 7, 3, 15, **kw))
             for graph in (False, True):
                 out = S.run(graph=graph, lanes=kw.get("parallel", False))
                 assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), ref), (kw, graph)
-        S.plan = plan
         got = S.count(out)
         step, count = Q.fp64_query(S.x, *S.params)
         assert abs(got[0] - count) < 0.25

@@ -81,7 +81,7 @@ class Bench:
     def solo(self, degree, blocks):
         X = self.X
         plan, ins, pts = self.query(degree, blocks)
-        regs = ins + [X.pfx_ct_create(self.ctx, len(QB), 1) for _ in range(plan.n_regs - plan.n_inputs)]
+        regs = ins + [X.pfx_ct_create(self.ctx, len(QB), plan.reg_degree[i]) for i in range(plan.n_inputs, plan.n_regs)]
         try:
             X.pfx_run_circuit(self.ctx, plan.ops, regs, plan.n_inputs, pts, self.rlk, self.gks, False, self.stream)
             X.pfx_sync(self.ctx, self.stream)
@@ -129,7 +129,7 @@ def _serve(X, B, budget, slots, mix, max_batch=1):
         for q in mix:
             plan, ins, pts = B.query(*q, interleave=max_batch > 1)
             out = B.new_out()
-            t = X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out)
+            t = X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out, plan.reg_degree)
             tickets.append((q, t, out))
         infos = []
         for q, t, out in tickets:
@@ -146,7 +146,7 @@ def _serve(X, B, budget, slots, mix, max_batch=1):
 
 def _footprint(B, q, interleave=False):
     plan, ins, _ = B.query(*q, interleave=interleave)
-    return (plan.n_regs - plan.n_inputs) * 2 * len(QB) * B.N * 8
+    return sum(d + 1 for d in plan.reg_degree[plan.n_inputs:]) * len(QB) * B.N * 8
 
 
 def test_mix_equals_solo_with_requests_in_flight(X, B, solo):
@@ -211,10 +211,10 @@ def test_server_rejects_what_cannot_fit(X, B):
         plan, ins, pts = B.query(3, 1)
         out = B.new_out()
         with pytest.raises(X.PfxError) as e:
-            X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out)
+            X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out, plan.reg_degree)
         assert e.value.status == X.PFX_ENOMEM
         with pytest.raises(X.PfxError) as e:       # output register must be a work register
-            X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, 0, out)
+            X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, 0, out, plan.reg_degree)
         assert e.value.status == X.PFX_EINVAL
     finally:
         X.pfx_server_destroy(srv)
@@ -225,7 +225,8 @@ def test_failed_request_reports_its_error(X, B, solo):
     srv = X.pfx_server_create(B.ctx, 2 * _scratch(X, B) + 4 * _footprint(B, (3, 1)), 2, B.rlk, [])
     try:
         out = B.new_out()
-        t_bad = X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out)   # no Galois keys
+        t_bad = X.pfx_server_submit(srv, plan.ops, plan.n_regs, ins, pts, plan.out, out,
+                                    plan.reg_degree)   # no Galois keys
         info = X.pfx_server_poll(srv, t_bad, wait=True)
         assert info.status == X.PFX_ENOKEY and info.error
     finally:

@@ -30,8 +30,10 @@ def interpret(plan, inputs, pts):
             r = A - reg[b]
         elif code == X.OP_MUL_PLAIN:
             r = A * pts[b]
-        elif code == X.OP_MUL_RELIN:
+        elif code in (X.OP_MUL_RELIN, X.OP_MUL):
             r = A * reg[b]
+        elif code == X.OP_RELIN:
+            r = A
         elif code == X.OP_RESCALE:
             r = A
         elif code == X.OP_MUL_INT:
@@ -47,6 +49,8 @@ def interpret(plan, inputs, pts):
         else:
             raise AssertionError(f"op {code} not used by the query")
         assert dst >= plan.n_inputs
+        if code == X.OP_MUL:          # a tensor product needs a degree-2 register
+            assert plan.reg_degree[dst] == 2
         reg[dst] = np.broadcast_to(r, A.shape).copy() if np.ndim(r) else r
     return reg[plan.out]
 
@@ -113,3 +117,12 @@ def test_grouped_interleave_bounds_the_registers():
         runs = _runs(g.ops)
         assert sum(runs) == n_mr and max(runs) == 4
         assert runs.count(4) == (blocks // 4) * (n_mr // blocks)
+
+
+def test_one_relinearisation_for_the_score_polynomial():
+    # the D products C_k Y_k are summed at degree 2: D tensor products, one RELIN per block
+    for D in (3, 7, 15):
+        plan = QueryPlan(2, 8, D, 3, 15)
+        codes = [o[0] for o in plan.ops]
+        assert codes.count(X.OP_MUL) == 2 * D and codes.count(X.OP_RELIN) == 2
+        assert sum(plan.reg_degree) == plan.n_regs + 2          # two degree-2 registers
