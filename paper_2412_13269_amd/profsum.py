@@ -10,6 +10,11 @@
         HBM bytes per dispatch of the kernels matching --kernel (all their
         dispatches), each counter scaled by what it reads for the copy kernel
         of known size (dispatches of that name and grid; KIB read = KIB written)
+    python -m paper_2412_13269_amd.profsum --valu <SQ counters csv> <..._kernel_trace.csv> [--top N]
+        per kernel and grid: VALU wave instructions per dispatch (SQ_INSTS_VALU),
+        the average duration from the trace run, and the issue rate against
+        the chip's peak for full-rate FP64 VALU instructions: 256 CUs x 4 SIMDs
+        x 2.4 GHz / 4 cycles per wave64 instruction = 614.4 G/s
 """
 from __future__ import annotations
 
@@ -96,7 +101,50 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy: str) -> str:
     return "\n".join(out)
 
 
+VALU_PEAK = 256 * 4 * 2.4e9 / 4     # wave64 FP64 VALU instructions per second
+
+
+def valu(counters_csv: str, trace_csv: str, top: int = 16) -> str:
+    inst = defaultdict(lambda: defaultdict(float))     # (name, grid) -> dispatch -> SQ_INSTS_VALU
+    busy = defaultdict(lambda: defaultdict(float))
+    with open(counters_csv, newline="") as f:
+        for row in csv.DictReader(f):
+            name = (row.get("Kernel_Name") or "?").split("(")[0].replace("void ", "")
+            key = (name, row.get("Grid_Size") or "?")
+            if row["Counter_Name"] == "SQ_INSTS_VALU":
+                inst[key][row["Dispatch_Id"]] += float(row["Counter_Value"])
+            elif row["Counter_Name"] == "SQ_ACTIVE_INST_VALU":
+                busy[key][row["Dispatch_Id"]] += float(row["Counter_Value"])
+    dur = defaultdict(list)
+    with open(trace_csv, newline="") as f:
+        for row in csv.DictReader(f):
+            name = (row.get("Kernel_Name") or "?").split("(")[0].replace("void ", "")
+            grid = row.get("Grid_Size_X") or row.get("Grid_Size") or "?"
+            wg = row.get("Workgroup_Size_X") or row.get("Workgroup_Size") or "1"
+            # the counter csv's grid is in threads, the trace's in threads too
+            dur[(name, grid)].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1000.0)
+    rows = []
+    for key, d in inst.items():
+        if key not in dur:
+            continue
+        n = sum(d.values()) / len(d)
+        us = sum(dur[key]) / len(dur[key])
+        rate = n / (us * 1e-6)
+        rows.append((us * len(dur[key]), key, n, us, rate))
+    rows.sort(reverse=True)
+    out = ["| kernel | grid (threads) | VALU wave instr. per dispatch | avg us (trace) | G instr/s | of peak |",
+           "|---|---|---|---|---|---|"]
+    for _, (name, grid), n, us, rate in rows[:top]:
+        out.append(f"| `{name}` | {grid} | {n:.4g} | {us:.2f} | {rate / 1e9:.1f} | {rate / VALU_PEAK:.3f} |")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
+    if "--valu" in sys.argv:
+        i = sys.argv.index("--valu")
+        top = int(sys.argv[sys.argv.index("--top") + 1]) if "--top" in sys.argv else 16
+        print(valu(sys.argv[i + 1], sys.argv[i + 2], top))
+        sys.exit(0)
     if "--traffic" in sys.argv:
         i = sys.argv.index("--traffic")
         print(traffic(sys.argv[i + 1], sys.argv[i + 2], sys.argv[sys.argv.index("--kernel") + 1],

@@ -11,10 +11,10 @@ rotations by 2^k for k = 0..14 (15 distinct Galois keys): 16 key switches.
     python -m paper_2412_13269_amd.workload --steps 20 [--calibrate]
 
 runs the step `--steps` times after one warm-up step, the command that
-rocprofv3 wraps for kernel traces and counters.  `--calibrate` first runs the
-library's plain word-to-double copy (k_u64_to_f64) over one ciphertext, 2 x 24
-limbs = 24 MiB read and 24 MiB written per launch, five times: the reference
-against which HBM counters are scaled.
+rocprofv3 wraps for kernel traces and counters.  `--calibrate` first imports
+one ciphertext five times: the library's plain word-to-double copy
+(k_u64_to_f64) of one polynomial per launch, 24 limbs = 12 MiB read and 12 MiB
+written, the reference against which HBM counters are scaled.
 """
 from __future__ import annotations
 
@@ -90,7 +90,7 @@ class KsWorkload:
             X.pfx_rotate(ctx, self.cts[0], r, self.gks, self.rot, st)
 
     def calibrate_copy(self, reps=5):
-        """k_u64_to_f64 over 2 x 24 limbs (24 MiB in, 24 MiB out) per launch."""
+        """Two k_u64_to_f64 launches per import, 24 limbs (12 MiB in, 12 MiB out) each."""
         X = self.X
         for _ in range(reps):
             X.pfx_ct_import(self.ctx, self.words, SCALE, self.rot, self.st)
