@@ -182,6 +182,13 @@ pfx_status pfx_mul_plain(pfx_ctx *ctx, const pfx_ct *a, const pfx_pt *m, pfx_ct 
 pfx_status pfx_mul_int(pfx_ctx *ctx, const pfx_ct *a, int64_t k, pfx_ct *out, void *stream);
 /* Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1): degree-2 result. */
 pfx_status pfx_mul(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, void *stream);
+/* Accumulating products, one launch each: acc += a * b (tensor product; acc of
+ * degree 2) and acc += a * m (plaintext product; acc of a's degree).  The
+ * scale of acc is kept (it must be within 2^-10 of the product's, PFX_ESCALE
+ * otherwise); the level becomes the smallest of the operands'; acc must not
+ * alias an operand.  Word for word the product followed by pfx_add. */
+pfx_status pfx_mul_acc(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, pfx_ct *acc, void *stream);
+pfx_status pfx_mul_plain_acc(pfx_ctx *ctx, const pfx_ct *a, const pfx_pt *m, pfx_ct *acc, void *stream);
 /* Relinearisation (App. A.2): (d0, d1) + SwitchKey(d2, swk_{s^2 -> s}). */
 pfx_status pfx_relinearize(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *rlk, pfx_ct *out,
                            void *stream);
@@ -268,6 +275,8 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
  *   MUL           dst = a * b, degree 2 (pfx_mul; dst needs     b register
  *                 capacity for degree 2)
  *   RELIN         dst = relin(a), a of degree 2
+ *   MUL_ACC       dst = dst + a * b (dst of degree 2)            b register
+ *   MUL_PLAIN_ACC dst = dst + a * pts[b]                         b plaintext
  *   RESCALE       dst = rescale(a)
  *   ADD_CONST     dst = a + value (pfx_add_const)                value
  *   MUL_CONST     dst = a * value at the last prime's scale      value
@@ -312,6 +321,8 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
 #define PFX_OP_LANE 13
 #define PFX_OP_MUL 14
 #define PFX_OP_RELIN 15
+#define PFX_OP_MUL_ACC 16
+#define PFX_OP_MUL_PLAIN_ACC 17
 
 typedef struct pfx_op {
     int32_t code;

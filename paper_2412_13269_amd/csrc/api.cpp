@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <string>
@@ -308,6 +309,8 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
         case PFX_OP_MUL_INT: r = pfx_mul_int(c, A, o.k, d, stream); break;
         case PFX_OP_MUL_RELIN: r = pfx_mul_relin(c, A, R(o.b), rlk, d, stream); break;
         case PFX_OP_MUL: r = pfx_mul(c, A, R(o.b), d, stream); break;
+        case PFX_OP_MUL_ACC: r = pfx_mul_acc(c, A, R(o.b), d, stream); break;
+        case PFX_OP_MUL_PLAIN_ACC: r = pfx_mul_plain_acc(c, A, pt, d, stream); break;
         case PFX_OP_RELIN: r = pfx_relinearize(c, A, rlk, d, stream); break;
         case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
         case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
@@ -1108,6 +1111,43 @@ pfx_status pfx_mul(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, vo
     return PFX_OK;
 }
 
+pfx_status pfx_mul_acc(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, pfx_ct *acc, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_ct(c, b, "b");
+    if (r) return r;
+    r = check_ct(c, acc, "acc");
+    if (r) return r;
+    REQUIRE(a->degree == 1 && b->degree == 1, PFX_EINVAL, "tensor product needs two degree-1 ciphertexts");
+    REQUIRE(acc->degree == 2, PFX_EINVAL, "accumulator must be of degree 2");
+    REQUIRE(acc->d != a->d && acc->d != b->d, PFX_EINVAL, "accumulator aliases an operand");
+    if (!scale_close(acc->scale, a->scale * b->scale)) return fail(PFX_ESCALE, "operand scales differ");
+    const uint32_t lv = std::min({a->n_limbs, b->n_limbs, acc->n_limbs});
+    Launch L{c, S(stream)};
+    launch_tensor(L, acc->poly(0), acc->poly(1), acc->poly(2), a->poly(0), a->poly(1), b->poly(0), b->poly(1), lv,
+                  true);
+    acc->n_limbs = lv;
+    return PFX_OK;
+}
+
+pfx_status pfx_mul_plain_acc(pfx_ctx *c, const pfx_ct *a, const pfx_pt *m, pfx_ct *acc, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_ct(c, m, "plaintext");
+    if (r) return r;
+    r = check_ct(c, acc, "acc");
+    if (r) return r;
+    REQUIRE(acc->degree == a->degree, PFX_EINVAL, "accumulator and operand degrees differ");
+    REQUIRE(acc->d != a->d, PFX_EINVAL, "accumulator aliases the operand");
+    if (!scale_close(acc->scale, a->scale * m->scale)) return fail(PFX_ESCALE, "operand scales differ");
+    const uint32_t lv = std::min({a->n_limbs, m->n_limbs, acc->n_limbs});
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    launch_ew(L, EW_MAC, acc->d, a->d, m->d, acc->cap_limbs * N, a->cap_limbs * N, 0, a->degree + 1, lv);
+    acc->n_limbs = lv;
+    return PFX_OK;
+}
+
 pfx_status pfx_relinearize(pfx_ctx *c, const pfx_ct *a, const pfx_swk *rlk, pfx_ct *out, void *stream) {
     pfx_status r = check_ct(c, a, "a");
     if (r) return r;
@@ -1567,7 +1607,8 @@ static pfx_status ensure_lanes(pfx_ctx *c) {
 // inside a fork is checked to lie on its own lane or before the fork, so that
 // the fork/join events alone order the list.
 static bool reads_b_register(int32_t code) {
-    return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN || code == PFX_OP_MUL;
+    return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN || code == PFX_OP_MUL ||
+           code == PFX_OP_MUL_ACC;
 }
 
 static pfx_status check_lanes(const pfx_op *ops, size_t n_ops, size_t n_regs) {

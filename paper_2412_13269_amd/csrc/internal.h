@@ -199,7 +199,8 @@ void launch_int_to_rns(const Launch &L, double *out, const int64_t *in, int n_li
                        int pid_gap_at, int pid_gap);
 void launch_s8_to_rns(const Launch &L, double *out, const int8_t *in, int n_limbs);
 
-enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4 };
+// EW_MAC: out = out + a * b (out read and written by the same thread).
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4, EW_MAC = 5 };
 // out[k][i] = a[k][i] op b[k][i] over npoly polynomials of nl limbs (prime ids 0..nl-1).
 void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const double *b, size_t so,
                size_t sa, size_t sb, int npoly, int nl);
@@ -207,8 +208,9 @@ void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const dou
 void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, size_t sa, int npoly,
                      int nl, const uint64_t *cst);
 void launch_addconst(const Launch &L, double *out, const double *a, int nl, const uint64_t *cst);
+// acc: add the product to what d0, d1, d2 hold.
 void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const double *a0,
-                   const double *a1, const double *b0, const double *b1, int nl);
+                   const double *a1, const double *b0, const double *b1, int nl, bool acc = false);
 void launch_automorph(const Launch &L, double *out, const double *in, size_t so, size_t si, int npoly,
                       int nl, uint32_t g);
 // The operand of a key switch and what it adds (keyswitch.hip):

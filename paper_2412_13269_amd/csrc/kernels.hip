@@ -228,27 +228,34 @@ void launch_s8_to_rns(const Launch &L, double *out, const int8_t *in, int n_limb
 }
 
 // ============================================================== elementwise
+// Grid: x over the N slots of a limb (a few per thread), y over polynomial x
+// limb, so a block's prime and polynomial are uniform and no thread divides.
+static inline dim3 ew_grid(int logn, int rows) {
+    const int per_block = 256 * 4;
+    return dim3((unsigned)std::max(1, (1 << logn) / per_block), (unsigned)rows);
+}
+
 template <int OP>
-__global__ void k_ew(double *out, const double *a, const double *b, size_t so, size_t sa, size_t sb, int npoly,
-                     int nl, int logn, const PrimeDev *pr) {
-    const size_t total = ((size_t)npoly * nl) << logn;
-    const size_t mask = ((size_t)1 << logn) - 1;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t c = idx & mask;
-        const size_t li = idx >> logn;
-        const int i = (int)(li % nl);
-        const int k = (int)(li / nl);
-        const size_t off = ((size_t)i << logn) + c;
-        const double q = pr[i].q;
-        const double x = a[k * sa + off];
+__global__ __launch_bounds__(256) void k_ew(double *out, const double *a, const double *b, size_t so, size_t sa,
+                                            size_t sb, int nl, int logn, const PrimeDev *pr) {
+    const int row = blockIdx.y;                 // polynomial k, limb i
+    const int k = row / nl, i = row - k * nl;
+    const size_t off = (size_t)i << logn;
+    const double q = pr[i].q, qi = pr[i].qinv;
+    const double *ap = a + k * sa + off;
+    const double *bp = b + k * sb + off;
+    double *op = out + k * so + off;
+    const size_t N = (size_t)1 << logn;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const double x = ap[c];
         double r;
-        if (OP == EW_ADD) r = madd(x, b[k * sb + off], q);
-        else if (OP == EW_SUB) r = msub(x, b[k * sb + off], q);
-        else if (OP == EW_MUL) r = mmul(x, b[k * sb + off], q, pr[i].qinv);
+        if (OP == EW_ADD) r = madd(x, bp[c], q);
+        else if (OP == EW_SUB) r = msub(x, bp[c], q);
+        else if (OP == EW_MUL) r = mmul(x, bp[c], q, qi);
+        else if (OP == EW_MAC) r = madd(op[c], mmul(x, bp[c], q, qi), q);
         else if (OP == EW_NEG) r = mneg(x, q);
         else r = x;
-        out[k * so + off] = r;
+        op[c] = r;
     }
 }
 
@@ -257,19 +264,21 @@ void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const dou
     const int logn = L.ctx->logn;
     const size_t total = ((size_t)npoly * nl) << logn;
     if (!total) return;
-    const unsigned g = grid_for(total);
+    const dim3 g = ew_grid(logn, npoly * nl);
     const PrimeDev *pr = L.ctx->d_primes;
     hipEvent_t ev;
     prof_begin(L, "elementwise", &ev);
     switch (op) {
-        case EW_ADD: k_ew<EW_ADD><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
-        case EW_SUB: k_ew<EW_SUB><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
-        case EW_MUL: k_ew<EW_MUL><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
-        case EW_NEG: k_ew<EW_NEG><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
-        default: k_ew<EW_COPY><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, npoly, nl, logn, pr); break;
+        case EW_ADD: k_ew<EW_ADD><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, nl, logn, pr); break;
+        case EW_SUB: k_ew<EW_SUB><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, nl, logn, pr); break;
+        case EW_MUL: k_ew<EW_MUL><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, nl, logn, pr); break;
+        case EW_MAC: k_ew<EW_MAC><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, nl, logn, pr); break;
+        case EW_NEG: k_ew<EW_NEG><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, nl, logn, pr); break;
+        default: k_ew<EW_COPY><<<g, 256, 0, L.st>>>(out, a, b, so, sa, sb, nl, logn, pr); break;
     }
     HIP_LAUNCH_CHECK();
-    prof_end(L, "elementwise", ev, 8.0 * (double)total * ((op == EW_NEG || op == EW_COPY) ? 2 : 3));
+    const double words = (op == EW_NEG || op == EW_COPY) ? 2 : op == EW_MAC ? 4 : 3;
+    prof_end(L, "elementwise", ev, 8.0 * (double)total * words);
 }
 
 struct LimbConsts {
@@ -277,19 +286,17 @@ struct LimbConsts {
     double wq[PFX_MAX_PRIMES];
 };
 
-__global__ void k_mulconst(double *out, const double *a, size_t so, size_t sa, int npoly, int nl, int logn,
-                           const PrimeDev *pr, const LimbConsts k) {
-    const size_t total = ((size_t)npoly * nl) << logn;
-    const size_t mask = ((size_t)1 << logn) - 1;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t c = idx & mask;
-        const size_t li = idx >> logn;
-        const int i = (int)(li % nl);
-        const int kp = (int)(li / nl);
-        const size_t off = ((size_t)i << logn) + c;
-        out[kp * so + off] = mmulc(a[kp * sa + off], k.w[i], k.wq[i], pr[i].q);
-    }
+__global__ __launch_bounds__(256) void k_mulconst(double *out, const double *a, size_t so, size_t sa, int nl,
+                                                   int logn, const PrimeDev *pr, const LimbConsts k) {
+    const int row = blockIdx.y;
+    const int kp = row / nl, i = row - kp * nl;
+    const size_t off = (size_t)i << logn;
+    const double *ap = a + kp * sa + off;
+    double *op = out + kp * so + off;
+    const double w = k.w[i], wq = k.wq[i], q = pr[i].q;
+    const size_t N = (size_t)1 << logn;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x)
+        op[c] = mmulc(ap[c], w, wq, q);
 }
 
 void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, size_t sa, int npoly, int nl,
@@ -302,7 +309,8 @@ void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, s
     const size_t total = ((size_t)npoly * nl) << L.ctx->logn;
     hipEvent_t ev;
     prof_begin(L, "mulconst", &ev);
-    k_mulconst<<<grid_for(total), 256, 0, L.st>>>(out, a, so, sa, npoly, nl, L.ctx->logn, L.ctx->d_primes, k);
+    k_mulconst<<<ew_grid(L.ctx->logn, npoly * nl), 256, 0, L.st>>>(out, a, so, sa, nl, L.ctx->logn, L.ctx->d_primes,
+                                                                    k);
     HIP_LAUNCH_CHECK();
     prof_end(L, "mulconst", ev, 16.0 * (double)total);
 }
@@ -329,29 +337,42 @@ void launch_addconst(const Launch &L, double *out, const double *a, int nl, cons
     prof_end(L, "addconst", ev, 16.0 * (double)total);
 }
 
-// Tensor product in the NTT domain (Sec. 2.4.2): d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.
-__global__ void k_tensor(double *d0, double *d1, double *d2, const double *a0, const double *a1, const double *b0,
-                         const double *b1, int nl, int logn, const PrimeDev *pr) {
-    const size_t total = (size_t)nl << logn;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(idx >> logn);
-        const double q = pr[i].q, qi = pr[i].qinv;
+// Tensor product in the NTT domain (Sec. 2.4.2): d0 = a0 b0, d1 = a0 b1 + a1 b0,
+// d2 = a1 b1; ACC adds it to what d0, d1, d2 hold.
+template <bool ACC>
+__global__ __launch_bounds__(256) void k_tensor(double *d0, double *d1, double *d2, const double *a0, const double *a1,
+                                                const double *b0, const double *b1, int logn, const PrimeDev *pr) {
+    const int i = blockIdx.y;
+    const double q = pr[i].q, qi = pr[i].qinv;
+    const size_t N = (size_t)1 << logn;
+    const size_t off = (size_t)i << logn;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const size_t idx = off + c;
         const double x0 = a0[idx], x1 = a1[idx], y0 = b0[idx], y1 = b1[idx];
-        d0[idx] = mmul(x0, y0, q, qi);
-        d1[idx] = madd(mmul(x0, y1, q, qi), mmul(x1, y0, q, qi), q);
-        d2[idx] = mmul(x1, y1, q, qi);
+        double r0 = mmul(x0, y0, q, qi);
+        double r1 = madd(mmul(x0, y1, q, qi), mmul(x1, y0, q, qi), q);
+        double r2 = mmul(x1, y1, q, qi);
+        if (ACC) {
+            r0 = madd(d0[idx], r0, q);
+            r1 = madd(d1[idx], r1, q);
+            r2 = madd(d2[idx], r2, q);
+        }
+        d0[idx] = r0;
+        d1[idx] = r1;
+        d2[idx] = r2;
     }
 }
 
 void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const double *a0, const double *a1,
-                   const double *b0, const double *b1, int nl) {
+                   const double *b0, const double *b1, int nl, bool acc) {
     const size_t total = (size_t)nl << L.ctx->logn;
+    const dim3 g = ew_grid(L.ctx->logn, nl);
     hipEvent_t ev;
-    prof_begin(L, "tensor", &ev);
-    k_tensor<<<grid_for(total), 256, 0, L.st>>>(d0, d1, d2, a0, a1, b0, b1, nl, L.ctx->logn, L.ctx->d_primes);
+    prof_begin(L, acc ? "tensor_acc" : "tensor", &ev);
+    if (acc) k_tensor<true><<<g, 256, 0, L.st>>>(d0, d1, d2, a0, a1, b0, b1, L.ctx->logn, L.ctx->d_primes);
+    else k_tensor<false><<<g, 256, 0, L.st>>>(d0, d1, d2, a0, a1, b0, b1, L.ctx->logn, L.ctx->d_primes);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "tensor", ev, 56.0 * (double)total);
+    prof_end(L, acc ? "tensor_acc" : "tensor", ev, (acc ? 80.0 : 56.0) * (double)total);
 }
 
 // ============================================================== automorphism

@@ -3,7 +3,7 @@
 Circuit (the threshold-and-count phase of the paper's Alg. 2, with a
 slot-domain linear score): for each block b of 2^(logN-1) records
 
-    S   = rescale(sum_a W[a] * X[b][a])
+    S   = rescale(sum_a W[a] * X[b][a])     (products accumulated in place)
     Y_k = S^k by the binary power tree (Y2 = Y1 Y1, Y3 = Y2 Y1, Y4 = Y2 Y2,
           Y5 = Y4 Y1, Y6 = Y4 Y2, Y7 = Y4 Y3, Y8 = Y4 Y4, Y(8+i) = Y8 Yi;
           each relinearised and rescaled), degree D <= 15
@@ -114,8 +114,7 @@ class QueryPlan:
         self._op(X.OP_MUL_PLAIN, s, self.W[0], b * A)
         t = self._new()
         for a in range(1, A):
-            self._op(X.OP_MUL_PLAIN, t, self.W[a], b * A + a)
-            self._op(X.OP_ADD, s, s, t)
+            self._op(X.OP_MUL_PLAIN_ACC, s, self.W[a], b * A + a)
         self._op(X.OP_RESCALE, s, s)
         Y = {1: s}
         tree = {2: (1, 1), 3: (2, 1), 4: (2, 2), 5: (4, 1), 6: (4, 2), 7: (4, 3), 8: (4, 4)}
@@ -123,15 +122,14 @@ class QueryPlan:
         for k in range(2, D + 1):
             Y[k] = self._new()
             self._mr(Y[k], Y[tree[k][0]], Y[tree[k][1]])
-        z2, t2 = self._new(2), self._new(2)
+        z2 = self._new(2)
         self._op(X.OP_MUL, z2, self.C[1], Y[1])
         for k in range(2, D + 1):
-            self._op(X.OP_MUL, t2, self.C[k], Y[k])
-            self._op(X.OP_ADD, z2, z2, t2)
+            self._op(X.OP_MUL_ACC, z2, self.C[k], Y[k])
         z = self._new()
         self._op(X.OP_RELIN, z, z2)
         self._op(X.OP_RESCALE, z, z)
-        self._drop(z2, t2)
+        self._drop(z2)
         self._op(X.OP_ADD, z, z, self.C[0])
         self._drop(*Y.values())
         u = self._new()

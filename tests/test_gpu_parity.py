@@ -181,6 +181,39 @@ def test_elementwise_ops(pair, X):
     pair.same(O.ct_add(P, c1o, c1o), c1x)
 
 
+def test_accumulating_products(pair, X):
+    """acc += a * b (tensor) and acc += a * m (plaintext): the oracle's product
+    followed by its addition, word for word, including a level drop."""
+    P = pair.P
+    c1o, c1x, _ = pair.enc(P.L)
+    c2o, c2x, _ = pair.enc(P.L)
+    c3o, c3x, _ = pair.enc(P.L - 1)
+    acc = pair.ct(P.L)
+    X.pfx_mul(pair.ctx, c1x, c2x, acc)
+    X.pfx_mul_acc(pair.ctx, c3x, c2x, acc)          # drops to L - 1 limbs
+    want = O.ct_add(P, O.tensor(P, c1o, c2o), O.tensor(P, c3o, c2o))
+    pair.same(want, acc)
+    X.pfx_mul_acc(pair.ctx, c1x, c1x, acc)
+    pair.same(O.ct_add(P, want, O.tensor(P, c1o, c1o)), acc)
+    m1 = O.encode(P, I.uniform_slots(P.N // 2, 41), pair.scale, P.L)
+    m2 = O.encode(P, I.uniform_slots(P.N // 2, 42), pair.scale, P.L)
+    pt1, pt2 = X.pfx_pt_import(pair.ctx, m1, pair.scale), X.pfx_pt_import(pair.ctx, m2, pair.scale)
+    pair.handles += [pt1, pt2]
+    acc1 = pair.ct(P.L)
+    X.pfx_mul_plain(pair.ctx, c1x, pt1, acc1)
+    X.pfx_mul_plain_acc(pair.ctx, c2x, pt2, acc1)
+    X.pfx_mul_plain_acc(pair.ctx, c3x, pt1, acc1)   # drops to L - 1 limbs
+    want = O.ct_add(P, O.ct_add(P, O.ct_mul_plain(P, c1o, m1, pair.scale), O.ct_mul_plain(P, c2o, m2, pair.scale)),
+                    O.ct_mul_plain(P, c3o, m1, pair.scale))
+    pair.same(want, acc1)
+    with pytest.raises(X.PfxError) as e:             # a degree-1 accumulator for a tensor product
+        X.pfx_mul_acc(pair.ctx, c1x, c2x, acc1)
+    assert e.value.status == X.PFX_EINVAL
+    with pytest.raises(X.PfxError) as e:             # accumulator aliasing the operand
+        X.pfx_mul_plain_acc(pair.ctx, acc1, pt1, acc1)
+    assert e.value.status == X.PFX_EINVAL
+
+
 def test_tensor_relinearize(pair, X):
     P = pair.P
     ko, kx = pair.key(0)

@@ -32,6 +32,10 @@ def interpret(plan, inputs, pts):
             r = A * pts[b]
         elif code in (X.OP_MUL_RELIN, X.OP_MUL):
             r = A * reg[b]
+        elif code == X.OP_MUL_ACC:
+            r = reg[dst] + A * reg[b]
+        elif code == X.OP_MUL_PLAIN_ACC:
+            r = reg[dst] + A * pts[b]
         elif code == X.OP_RELIN:
             r = A
         elif code == X.OP_RESCALE:
@@ -49,7 +53,7 @@ def interpret(plan, inputs, pts):
         else:
             raise AssertionError(f"op {code} not used by the query")
         assert dst >= plan.n_inputs
-        if code == X.OP_MUL:          # a tensor product needs a degree-2 register
+        if code in (X.OP_MUL, X.OP_MUL_ACC):     # a tensor product needs a degree-2 register
             assert plan.reg_degree[dst] == 2
         reg[dst] = np.broadcast_to(r, A.shape).copy() if np.ndim(r) else r
     return reg[plan.out]
@@ -124,5 +128,7 @@ def test_one_relinearisation_for_the_score_polynomial():
     for D in (3, 7, 15):
         plan = QueryPlan(2, 8, D, 3, 15)
         codes = [o[0] for o in plan.ops]
-        assert codes.count(X.OP_MUL) == 2 * D and codes.count(X.OP_RELIN) == 2
-        assert sum(plan.reg_degree) == plan.n_regs + 2          # two degree-2 registers
+        assert codes.count(X.OP_MUL) == 2 and codes.count(X.OP_MUL_ACC) == 2 * (D - 1)
+        assert codes.count(X.OP_RELIN) == 2
+        assert codes.count(X.OP_MUL_PLAIN) == 2 and codes.count(X.OP_MUL_PLAIN_ACC) == 2 * 7
+        assert sum(plan.reg_degree) == plan.n_regs + 1          # one degree-2 register
