@@ -189,6 +189,8 @@ pfx_status pfx_mul(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, pfx_ct *out, 
  * alias an operand.  Word for word the product followed by pfx_add. */
 pfx_status pfx_mul_acc(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, pfx_ct *acc, void *stream);
 pfx_status pfx_mul_plain_acc(pfx_ctx *ctx, const pfx_ct *a, const pfx_pt *m, pfx_ct *acc, void *stream);
+/* acc += a * k for an integer k (acc of a's degree, scales within 2^-10). */
+pfx_status pfx_mul_int_acc(pfx_ctx *ctx, const pfx_ct *a, int64_t k, pfx_ct *acc, void *stream);
 /* Relinearisation (App. A.2): (d0, d1) + SwitchKey(d2, swk_{s^2 -> s}). */
 pfx_status pfx_relinearize(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *rlk, pfx_ct *out,
                            void *stream);
@@ -277,6 +279,7 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
  *   RELIN         dst = relin(a), a of degree 2
  *   MUL_ACC       dst = dst + a * b (dst of degree 2)            b register
  *   MUL_PLAIN_ACC dst = dst + a * pts[b]                         b plaintext
+ *   MUL_INT_ACC   dst = dst + a * k                              k
  *   RESCALE       dst = rescale(a)
  *   ADD_CONST     dst = a + value (pfx_add_const)                value
  *   MUL_CONST     dst = a * value at the last prime's scale      value
@@ -323,6 +326,7 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
 #define PFX_OP_RELIN 15
 #define PFX_OP_MUL_ACC 16
 #define PFX_OP_MUL_PLAIN_ACC 17
+#define PFX_OP_MUL_INT_ACC 18
 
 typedef struct pfx_op {
     int32_t code;

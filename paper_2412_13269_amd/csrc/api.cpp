@@ -311,6 +311,7 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
         case PFX_OP_MUL: r = pfx_mul(c, A, R(o.b), d, stream); break;
         case PFX_OP_MUL_ACC: r = pfx_mul_acc(c, A, R(o.b), d, stream); break;
         case PFX_OP_MUL_PLAIN_ACC: r = pfx_mul_plain_acc(c, A, pt, d, stream); break;
+        case PFX_OP_MUL_INT_ACC: r = pfx_mul_int_acc(c, A, o.k, d, stream); break;
         case PFX_OP_RELIN: r = pfx_relinearize(c, A, rlk, d, stream); break;
         case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
         case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
@@ -1073,17 +1074,40 @@ pfx_status pfx_mul_plain(pfx_ctx *c, const pfx_ct *a, const pfx_pt *m, pfx_ct *o
     return PFX_OK;
 }
 
+// [k]_{q_i} for the first n primes.
+static std::vector<uint64_t> int_residues(const pfx_ctx *c, int64_t k, uint32_t n) {
+    std::vector<uint64_t> cst(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t q = c->primes[i];
+        const uint64_t mag = (uint64_t)(k < 0 ? -(k + 1) + 1ull : (uint64_t)k) % q;
+        cst[i] = k < 0 ? (q - mag) % q : mag;
+    }
+    return cst;
+}
+
+pfx_status pfx_mul_int_acc(pfx_ctx *c, const pfx_ct *a, int64_t k, pfx_ct *acc, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_ct(c, acc, "acc");
+    if (r) return r;
+    REQUIRE(acc->degree == a->degree, PFX_EINVAL, "accumulator and operand degrees differ");
+    REQUIRE(acc->d != a->d, PFX_EINVAL, "accumulator aliases the operand");
+    if (!scale_close(acc->scale, a->scale)) return fail(PFX_ESCALE, "operand scales differ");
+    const uint32_t lv = std::min(a->n_limbs, acc->n_limbs);
+    const std::vector<uint64_t> cst = int_residues(c, k, lv);
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    launch_mulconst(L, acc->d, a->d, acc->cap_limbs * N, a->cap_limbs * N, a->degree + 1, lv, cst.data(), true);
+    acc->n_limbs = lv;
+    return PFX_OK;
+}
+
 pfx_status pfx_mul_int(pfx_ctx *c, const pfx_ct *a, int64_t k, pfx_ct *out, void *stream) {
     pfx_status r = check_ct(c, a, "a");
     if (r) return r;
     r = check_out(out, a->n_limbs, a->degree);
     if (r) return r;
-    std::vector<uint64_t> cst(a->n_limbs);
-    for (uint32_t i = 0; i < a->n_limbs; ++i) {
-        const uint64_t q = c->primes[i];
-        const uint64_t mag = (uint64_t)(k < 0 ? -(k + 1) + 1ull : (uint64_t)k) % q;
-        cst[i] = k < 0 ? (q - mag) % q : mag;
-    }
+    const std::vector<uint64_t> cst = int_residues(c, k, a->n_limbs);
     Launch L{c, S(stream)};
     const size_t N = c->N;
     launch_mulconst(L, out->d, a->d, out->cap_limbs * N, a->cap_limbs * N, a->degree + 1, a->n_limbs, cst.data());

@@ -205,8 +205,9 @@ enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4, EW_MAC 
 void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const double *b, size_t so,
                size_t sa, size_t sb, int npoly, int nl);
 // out[k][i] = a[k][i] * cst_i (+ 0) with per-limb constant words.
+// acc: out += a * cst (per limb constant) instead of out = a * cst.
 void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, size_t sa, int npoly,
-                     int nl, const uint64_t *cst);
+                     int nl, const uint64_t *cst, bool acc = false);
 void launch_addconst(const Launch &L, double *out, const double *a, int nl, const uint64_t *cst);
 // acc: add the product to what d0, d1, d2 hold.
 void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const double *a0,

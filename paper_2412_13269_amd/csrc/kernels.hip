@@ -286,6 +286,7 @@ struct LimbConsts {
     double wq[PFX_MAX_PRIMES];
 };
 
+template <bool ACC>
 __global__ __launch_bounds__(256) void k_mulconst(double *out, const double *a, size_t so, size_t sa, int nl,
                                                    int logn, const PrimeDev *pr, const LimbConsts k) {
     const int row = blockIdx.y;
@@ -295,12 +296,14 @@ __global__ __launch_bounds__(256) void k_mulconst(double *out, const double *a, 
     double *op = out + kp * so + off;
     const double w = k.w[i], wq = k.wq[i], q = pr[i].q;
     const size_t N = (size_t)1 << logn;
-    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x)
-        op[c] = mmulc(ap[c], w, wq, q);
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const double r = mmulc(ap[c], w, wq, q);
+        op[c] = ACC ? madd(op[c], r, q) : r;
+    }
 }
 
 void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, size_t sa, int npoly, int nl,
-                     const uint64_t *cst) {
+                     const uint64_t *cst, bool acc) {
     LimbConsts k;
     for (int i = 0; i < nl; ++i) {
         k.w[i] = (double)cst[i];
@@ -309,10 +312,11 @@ void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, s
     const size_t total = ((size_t)npoly * nl) << L.ctx->logn;
     hipEvent_t ev;
     prof_begin(L, "mulconst", &ev);
-    k_mulconst<<<ew_grid(L.ctx->logn, npoly * nl), 256, 0, L.st>>>(out, a, so, sa, nl, L.ctx->logn, L.ctx->d_primes,
-                                                                    k);
+    const dim3 g = ew_grid(L.ctx->logn, npoly * nl);
+    if (acc) k_mulconst<true><<<g, 256, 0, L.st>>>(out, a, so, sa, nl, L.ctx->logn, L.ctx->d_primes, k);
+    else k_mulconst<false><<<g, 256, 0, L.st>>>(out, a, so, sa, nl, L.ctx->logn, L.ctx->d_primes, k);
     HIP_LAUNCH_CHECK();
-    prof_end(L, "mulconst", ev, 16.0 * (double)total);
+    prof_end(L, "mulconst", ev, (acc ? 24.0 : 16.0) * (double)total);
 }
 
 // out[i][c] = a[i][c] + cst_i: a constant polynomial (coefficient 0 only) is the

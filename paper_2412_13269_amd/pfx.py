@@ -45,7 +45,7 @@ class pfx_op(ctypes.Structure):
 
 OP_COPY, OP_ADD, OP_SUB, OP_MUL_PLAIN, OP_ADD_PLAIN, OP_MUL_INT, OP_MUL_RELIN = 0, 1, 2, 3, 4, 5, 6
 OP_RESCALE, OP_ADD_CONST, OP_MUL_CONST, OP_SCALE_MUL, OP_ROTATE, OP_ROTATE_SUM = 7, 8, 9, 10, 11, 12
-OP_LANE, OP_MUL, OP_RELIN, OP_MUL_ACC, OP_MUL_PLAIN_ACC = 13, 14, 15, 16, 17
+OP_LANE, OP_MUL, OP_RELIN, OP_MUL_ACC, OP_MUL_PLAIN_ACC, OP_MUL_INT_ACC = 13, 14, 15, 16, 17, 18
 
 
 class pfx_info(ctypes.Structure):
@@ -120,6 +120,7 @@ _SIGS = {
     "pfx_mul": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_mul_acc": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_mul_plain_acc": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_mul_int_acc": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "pfx_relinearize": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_mul_relin": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "pfx_mul_relin_batch": (_i32, [_vp, _VPP, _VPP, _sz, _vp, _VPP, _vp]),
@@ -401,6 +402,10 @@ def pfx_mul_acc(ctx, a, b, acc, stream=None):
 
 def pfx_mul_plain_acc(ctx, a, m, acc, stream=None):
     _check(_lib.pfx_mul_plain_acc(ctx, a, m, acc, _stream(stream)))
+
+
+def pfx_mul_int_acc(ctx, a, k: int, acc, stream=None):
+    _check(_lib.pfx_mul_int_acc(ctx, a, k, acc, _stream(stream)))
 
 
 def pfx_relinearize(ctx, a, rlk, out, stream=None):

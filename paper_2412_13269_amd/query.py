@@ -112,7 +112,6 @@ class QueryPlan:
         A, D = self.attributes, self.degree
         s = self._new()
         self._op(X.OP_MUL_PLAIN, s, self.W[0], b * A)
-        t = self._new()
         for a in range(1, A):
             self._op(X.OP_MUL_PLAIN_ACC, s, self.W[a], b * A + a)
         self._op(X.OP_RESCALE, s, s)
@@ -142,10 +141,8 @@ class QueryPlan:
             self._mr(x4, x2, x2)
             self._mr(x6, x4, x2)
             self._op(X.OP_MUL_INT, p, x2, k=-35)
-            self._op(X.OP_MUL_INT, t, x4, k=21)
-            self._op(X.OP_ADD, p, p, t)
-            self._op(X.OP_MUL_INT, t, x6, k=-5)
-            self._op(X.OP_ADD, p, p, t)
+            self._op(X.OP_MUL_INT_ACC, p, x4, k=21)
+            self._op(X.OP_MUL_INT_ACC, p, x6, k=-5)
             self._op(X.OP_ADD_CONST, p, p, value=35.0)
             self._op(X.OP_MUL_CONST, x2, u, value=1.0 / 16.0)
             self._op(X.OP_RESCALE, x2, x2)
@@ -153,7 +150,6 @@ class QueryPlan:
             self._drop(x2, x4, x6, p)
         self._op(X.OP_ADD_CONST, u, u, value=1.0)
         self._op(X.OP_SCALE_MUL, u, u, value=2.0)
-        self._drop(t)
         return u
 
     def _build(self):

@@ -182,8 +182,9 @@ def test_elementwise_ops(pair, X):
 
 
 def test_accumulating_products(pair, X):
-    """acc += a * b (tensor) and acc += a * m (plaintext): the oracle's product
-    followed by its addition, word for word, including a level drop."""
+    """acc += a * b (tensor), acc += a * m (plaintext) and acc += a * k
+    (integer): the oracle's product followed by its addition, word for word,
+    including a level drop."""
     P = pair.P
     c1o, c1x, _ = pair.enc(P.L)
     c2o, c2x, _ = pair.enc(P.L)
@@ -206,6 +207,12 @@ def test_accumulating_products(pair, X):
     want = O.ct_add(P, O.ct_add(P, O.ct_mul_plain(P, c1o, m1, pair.scale), O.ct_mul_plain(P, c2o, m2, pair.scale)),
                     O.ct_mul_plain(P, c3o, m1, pair.scale))
     pair.same(want, acc1)
+    acc2 = pair.ct(P.L)
+    X.pfx_mul_int(pair.ctx, c1x, -35, acc2)
+    X.pfx_mul_int_acc(pair.ctx, c2x, 21, acc2)
+    X.pfx_mul_int_acc(pair.ctx, c3x, -5, acc2)     # drops to L - 1 limbs
+    want = O.ct_add(P, O.ct_add(P, O.ct_mul_int(P, c1o, -35), O.ct_mul_int(P, c2o, 21)), O.ct_mul_int(P, c3o, -5))
+    pair.same(want, acc2)
     with pytest.raises(X.PfxError) as e:             # a degree-1 accumulator for a tensor product
         X.pfx_mul_acc(pair.ctx, c1x, c2x, acc1)
     assert e.value.status == X.PFX_EINVAL

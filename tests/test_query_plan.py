@@ -36,6 +36,8 @@ def interpret(plan, inputs, pts):
             r = reg[dst] + A * reg[b]
         elif code == X.OP_MUL_PLAIN_ACC:
             r = reg[dst] + A * pts[b]
+        elif code == X.OP_MUL_INT_ACC:
+            r = reg[dst] + A * k
         elif code == X.OP_RELIN:
             r = A
         elif code == X.OP_RESCALE:
