@@ -357,6 +357,80 @@ size_t mr_run(const pfx_op *ops, size_t n_ops, size_t i, int max_batch) {
     return j - i;
 }
 
+// Elementwise ops (one or two elementwise, constant or tensor launches each,
+// no scratch): runs of independent ones are issued as collected launches.
+bool ew_code(int32_t code) {
+    switch (code) {
+        case PFX_OP_COPY: case PFX_OP_ADD: case PFX_OP_SUB: case PFX_OP_MUL_PLAIN: case PFX_OP_ADD_PLAIN:
+        case PFX_OP_MUL_INT: case PFX_OP_MUL: case PFX_OP_MUL_ACC: case PFX_OP_MUL_PLAIN_ACC:
+        case PFX_OP_MUL_INT_ACC: case PFX_OP_ADD_CONST: case PFX_OP_MUL_CONST: case PFX_OP_SCALE_MUL:
+            return true;
+        default:
+            return false;
+    }
+}
+
+bool accumulates(int32_t code) {
+    return code == PFX_OP_MUL_ACC || code == PFX_OP_MUL_PLAIN_ACC || code == PFX_OP_MUL_INT_ACC;
+}
+
+bool reads_b_reg(int32_t code) {
+    return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN || code == PFX_OP_MUL ||
+           code == PFX_OP_MUL_ACC;
+}
+
+// Registers an op reads (a, a register b, and an accumulator), as indices.
+int op_reads(const pfx_op &o, int32_t out[3]) {
+    int n = 0;
+    out[n++] = o.a;
+    if (reads_b_reg(o.code)) out[n++] = o.b;
+    if (accumulates(o.code)) out[n++] = o.dst;
+    return n;
+}
+
+// Run of consecutive ops with the same elementwise code from ops[i], at most
+// max_batch, none writing what another of the run reads or writes.
+size_t ew_run(const pfx_op *ops, size_t n_ops, size_t i, int max_batch) {
+    if (!ew_code(ops[i].code)) return 0;
+    size_t j = i + 1;
+    for (; j < n_ops && j - i < (size_t)max_batch && ops[j].code == ops[i].code; ++j) {
+        bool ok = true;
+        int32_t rj[3];
+        const int nj = op_reads(ops[j], rj);
+        for (size_t k = i; k < j && ok; ++k) {
+            int32_t rk[3];
+            const int nk = op_reads(ops[k], rk);
+            ok = ops[j].dst != ops[k].dst;
+            for (int x = 0; x < nk && ok; ++x) ok = rk[x] != ops[j].dst;
+            for (int x = 0; x < nj && ok; ++x) ok = rj[x] != ops[k].dst;
+        }
+        if (!ok) break;
+    }
+    return j - i;
+}
+
+// The same independence on the ciphertexts the registers name (two registers
+// may hold one ciphertext).
+bool ew_run_distinct(const pfx_op *ops, size_t i, size_t run, pfx_ct *const *regs, size_t n_regs) {
+    auto R = [&](int32_t x) -> const pfx_ct * { return (x >= 0 && (size_t)x < n_regs) ? regs[x] : nullptr; };
+    for (size_t k = 0; k < run; ++k) {
+        const pfx_ct *dk = R(ops[i + k].dst);
+        if (!dk) return false;
+        for (size_t m = 0; m < run; ++m) {
+            if (m == k) continue;
+            const pfx_ct *dm = R(ops[i + m].dst);
+            if (!dm || dm->d == dk->d) return false;
+            int32_t rm[3];
+            const int nm = op_reads(ops[i + m], rm);
+            for (int x = 0; x < nm; ++x) {
+                const pfx_ct *r = R(rm[x]);
+                if (!r || r->d == dk->d) return false;
+            }
+        }
+    }
+    return true;
+}
+
 // Largest batch that run_span will hand to one batched call.
 size_t max_mr_run(const pfx_op *ops, size_t n_ops, int max_batch) {
     size_t m = 0;
@@ -375,6 +449,18 @@ pfx_status run_span(pfx_ctx *c, const pfx_op *ops, size_t lo, size_t hi, pfx_ct 
                     size_t n_inputs, const pfx_pt *const *pts, size_t n_pts, const pfx_swk *rlk,
                     const pfx_swk *const *gks, size_t n_gks, void *stream, int max_batch) {
     for (size_t i = lo; i < hi;) {
+        const size_t ew = max_batch > 1 ? ew_run(ops, hi, i, kMaxBatch) : 0;
+        if (ew > 1 && ew_run_distinct(ops, i, ew, regs, n_regs)) {
+            const Launch L{c, S(stream)};
+            ew_collect_begin(L);
+            pfx_status r = PFX_OK;
+            for (size_t k = 0; k < ew && !r; ++k)
+                r = run_op(c, i + k, ops[i + k], regs, n_regs, n_inputs, pts, n_pts, rlk, gks, n_gks, stream);
+            ew_collect_end(L);      // what was recorded is issued, also after a failed op
+            if (r) return r;
+            i += ew;
+            continue;
+        }
         const size_t run = max_batch > 1 ? mr_run(ops, hi, i, max_batch) : 0;
         if (run > 1) {
             const bool mr = ops[i].code == PFX_OP_MUL_RELIN;

@@ -199,8 +199,16 @@ void launch_int_to_rns(const Launch &L, double *out, const int64_t *in, int n_li
                        int pid_gap_at, int pid_gap);
 void launch_s8_to_rns(const Launch &L, double *out, const int8_t *in, int n_limbs);
 
-// EW_MAC: out = out + a * b (out read and written by the same thread).
-enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4, EW_MAC = 5 };
+// EW_MAC: out = out + a * b (out read and written by the same thread).  The
+// last three are the per-limb constant forms of collected launches.
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4, EW_MAC = 5, EW_MULC = 6, EW_MULC_ACC = 7,
+            EW_ADDC = 8 };
+// Collection of independent elementwise / constant / tensor launches on one
+// stream by the calling thread (kernels.hip): between begin and end the
+// launchers record instead of launching; end issues one launch per kernel
+// variant over up to kMaxBatch records.
+void ew_collect_begin(const Launch &L);
+void ew_collect_end(const Launch &L);
 // out[k][i] = a[k][i] op b[k][i] over npoly polynomials of nl limbs (prime ids 0..nl-1).
 void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const double *b, size_t so,
                size_t sa, size_t sb, int npoly, int nl);

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cstdio>
 
+#include <cstring>
+
 #include "internal.h"
 #include "modarith.h"
 #include "ntt_core.h"
@@ -227,6 +229,88 @@ void launch_s8_to_rns(const Launch &L, double *out, const int8_t *in, int n_limb
     HIP_LAUNCH_CHECK();
 }
 
+struct LimbConsts {
+    double w[PFX_MAX_PRIMES];
+    double wq[PFX_MAX_PRIMES];
+};
+
+// ============================================================== collected launches
+// While a collector is active on the calling thread for a stream, the
+// elementwise, constant and tensor launchers above record their launches
+// instead of issuing them; ew_collect_end issues every record of one kernel
+// variant (same operation, same per-limb constants) as one launch over up to
+// kMaxBatch records (grid z).  The records of one collection must be
+// independent of each other (the op-list executor collects runs of
+// independent elementwise ops).
+struct EwRec {
+    double *out;
+    const double *a, *b;
+    size_t so, sa, sb;
+    int rows, nl;
+};
+struct TensorRec {
+    double *d0, *d1, *d2;
+    const double *a0, *a1, *b0, *b1;
+    int nl;
+};
+namespace {
+
+struct EwGroup {
+    int op;              // EwOp, or EW_MULC / EW_MULC_ACC / EW_ADDC
+    LimbConsts k;
+    int nk;              // constants in use (0: none)
+    std::vector<EwRec> recs;
+};
+
+struct Collector {
+    pfx_ctx *ctx = nullptr;
+    hipStream_t st = nullptr;
+    std::vector<EwGroup> ew;
+    std::vector<TensorRec> tensor[2];
+};
+
+thread_local Collector *t_collect = nullptr;
+
+Collector *collecting(const Launch &L) {
+    Collector *c = t_collect;
+    return (c && c->ctx == L.ctx && c->st == L.st) ? c : nullptr;
+}
+
+void collect_ew(Collector *c, int op, const EwRec &r, const LimbConsts *k, int nk) {
+    for (EwGroup &g : c->ew) {
+        if (g.op != op || g.nk != nk) continue;
+        if (nk && (std::memcmp(g.k.w, k->w, nk * sizeof(double)) || std::memcmp(g.k.wq, k->wq, nk * sizeof(double))))
+            continue;
+        g.recs.push_back(r);
+        return;
+    }
+    EwGroup g;
+    g.op = op;
+    g.nk = nk;
+    if (nk) g.k = *k;
+    g.recs.push_back(r);
+    c->ew.push_back(g);
+}
+
+}  // namespace
+
+// Records a launch when a collector is active for (ctx, stream); false if the
+// caller should launch it itself.
+static bool record_ew(const Launch &L, int op, double *out, const double *a, const double *b, size_t so, size_t sa,
+                      size_t sb, int rows, int nl, const LimbConsts *k, int nk) {
+    Collector *c = collecting(L);
+    if (!c) return false;
+    collect_ew(c, op, EwRec{out, a, b, so, sa, sb, rows, nl}, k, nk);
+    return true;
+}
+
+static bool record_tensor(const Launch &L, const TensorRec &r, bool acc) {
+    Collector *c = collecting(L);
+    if (!c) return false;
+    c->tensor[acc ? 1 : 0].push_back(r);
+    return true;
+}
+
 // ============================================================== elementwise
 // Grid: x over the N slots of a limb (a few per thread), y over polynomial x
 // limb, so a block's prime and polynomial are uniform and no thread divides.
@@ -264,6 +348,7 @@ void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const dou
     const int logn = L.ctx->logn;
     const size_t total = ((size_t)npoly * nl) << logn;
     if (!total) return;
+    if (record_ew(L, op, out, a, b, so, sa, sb, npoly * nl, nl, nullptr, 0)) return;
     const dim3 g = ew_grid(logn, npoly * nl);
     const PrimeDev *pr = L.ctx->d_primes;
     hipEvent_t ev;
@@ -280,11 +365,6 @@ void launch_ew(const Launch &L, EwOp op, double *out, const double *a, const dou
     const double words = (op == EW_NEG || op == EW_COPY) ? 2 : op == EW_MAC ? 4 : 3;
     prof_end(L, "elementwise", ev, 8.0 * (double)total * words);
 }
-
-struct LimbConsts {
-    double w[PFX_MAX_PRIMES];
-    double wq[PFX_MAX_PRIMES];
-};
 
 template <bool ACC>
 __global__ __launch_bounds__(256) void k_mulconst(double *out, const double *a, size_t so, size_t sa, int nl,
@@ -309,6 +389,7 @@ void launch_mulconst(const Launch &L, double *out, const double *a, size_t so, s
         k.w[i] = (double)cst[i];
         k.wq[i] = (double)cst[i] / (double)L.ctx->primes[i];
     }
+    if (record_ew(L, acc ? EW_MULC_ACC : EW_MULC, out, a, nullptr, so, sa, 0, npoly * nl, nl, &k, nl)) return;
     const size_t total = ((size_t)npoly * nl) << L.ctx->logn;
     hipEvent_t ev;
     prof_begin(L, "mulconst", &ev);
@@ -332,7 +413,11 @@ __global__ void k_addconst(double *out, const double *a, int nl, int logn, const
 
 void launch_addconst(const Launch &L, double *out, const double *a, int nl, const uint64_t *cst) {
     LimbConsts k;
-    for (int i = 0; i < nl; ++i) k.w[i] = (double)cst[i];
+    for (int i = 0; i < nl; ++i) {
+        k.w[i] = (double)cst[i];
+        k.wq[i] = 0.0;
+    }
+    if (record_ew(L, EW_ADDC, out, a, nullptr, 0, 0, 0, nl, nl, &k, nl)) return;
     const size_t total = (size_t)nl << L.ctx->logn;
     hipEvent_t ev;
     prof_begin(L, "addconst", &ev);
@@ -369,6 +454,7 @@ __global__ __launch_bounds__(256) void k_tensor(double *d0, double *d1, double *
 
 void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const double *a0, const double *a1,
                    const double *b0, const double *b1, int nl, bool acc) {
+    if (record_tensor(L, TensorRec{d0, d1, d2, a0, a1, b0, b1, nl}, acc)) return;
     const size_t total = (size_t)nl << L.ctx->logn;
     const dim3 g = ew_grid(L.ctx->logn, nl);
     hipEvent_t ev;
@@ -377,6 +463,146 @@ void launch_tensor(const Launch &L, double *d0, double *d1, double *d2, const do
     else k_tensor<false><<<g, 256, 0, L.st>>>(d0, d1, d2, a0, a1, b0, b1, L.ctx->logn, L.ctx->d_primes);
     HIP_LAUNCH_CHECK();
     prof_end(L, acc ? "tensor_acc" : "tensor", ev, (acc ? 80.0 : 56.0) * (double)total);
+}
+
+// ---- multi-record launches of a collection
+struct EwMultiArgs {
+    EwRec e[kMaxBatch];
+    int logn;
+    const PrimeDev *pr;
+};
+struct TensorMultiArgs {
+    TensorRec e[kMaxBatch];
+    int logn;
+    const PrimeDev *pr;
+};
+
+template <int OP>
+__global__ __launch_bounds__(256) void k_ew_multi(const EwMultiArgs m, const LimbConsts k) {
+    const EwRec &r = m.e[blockIdx.z];
+    const int row = blockIdx.y;
+    if (row >= r.rows) return;
+    const int kp = row / r.nl, i = row - kp * r.nl;
+    const int logn = m.logn;
+    const size_t off = (size_t)i << logn;
+    const double q = m.pr[i].q, qi = m.pr[i].qinv;
+    const double *ap = r.a + kp * r.sa + off;
+    const double *bp = r.b + kp * r.sb + off;
+    double *op = r.out + kp * r.so + off;
+    const size_t N = (size_t)1 << logn;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const double x = ap[c];
+        double v;
+        if (OP == EW_ADD) v = madd(x, bp[c], q);
+        else if (OP == EW_SUB) v = msub(x, bp[c], q);
+        else if (OP == EW_MUL) v = mmul(x, bp[c], q, qi);
+        else if (OP == EW_MAC) v = madd(op[c], mmul(x, bp[c], q, qi), q);
+        else if (OP == EW_NEG) v = mneg(x, q);
+        else if (OP == EW_MULC) v = mmulc(x, k.w[i], k.wq[i], q);
+        else if (OP == EW_MULC_ACC) v = madd(op[c], mmulc(x, k.w[i], k.wq[i], q), q);
+        else if (OP == EW_ADDC) v = madd(x, k.w[i], q);
+        else v = x;
+        op[c] = v;
+    }
+}
+
+template <bool ACC>
+__global__ __launch_bounds__(256) void k_tensor_multi(const TensorMultiArgs m) {
+    const TensorRec &r = m.e[blockIdx.z];
+    const int i = blockIdx.y;
+    if (i >= r.nl) return;
+    const double q = m.pr[i].q, qi = m.pr[i].qinv;
+    const size_t N = (size_t)1 << m.logn;
+    const size_t off = (size_t)i << m.logn;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const size_t idx = off + c;
+        const double x0 = r.a0[idx], x1 = r.a1[idx], y0 = r.b0[idx], y1 = r.b1[idx];
+        double r0 = mmul(x0, y0, q, qi);
+        double r1 = madd(mmul(x0, y1, q, qi), mmul(x1, y0, q, qi), q);
+        double r2 = mmul(x1, y1, q, qi);
+        if (ACC) {
+            r0 = madd(r.d0[idx], r0, q);
+            r1 = madd(r.d1[idx], r1, q);
+            r2 = madd(r.d2[idx], r2, q);
+        }
+        r.d0[idx] = r0;
+        r.d1[idx] = r1;
+        r.d2[idx] = r2;
+    }
+}
+
+
+void ew_collect_begin(const Launch &L) {
+    Collector *c = new Collector;
+    c->ctx = L.ctx;
+    c->st = L.st;
+    t_collect = c;
+}
+
+void ew_collect_end(const Launch &L) {
+    Collector *c = t_collect;
+    t_collect = nullptr;
+    if (!c) return;
+    const int logn = L.ctx->logn;
+    const PrimeDev *pr = L.ctx->d_primes;
+    hipEvent_t ev;
+    for (const EwGroup &g : c->ew) {
+        for (size_t s0 = 0; s0 < g.recs.size(); s0 += kMaxBatch) {
+            const int n = (int)std::min<size_t>(kMaxBatch, g.recs.size() - s0);
+            EwMultiArgs m;
+            int rows = 0;
+            double bytes = 0;
+            const double words = (g.op == EW_NEG || g.op == EW_COPY || g.op == EW_MULC || g.op == EW_ADDC) ? 2
+                                 : (g.op == EW_MAC) ? 4 : 3;
+            for (int e = 0; e < kMaxBatch; ++e) {
+                m.e[e] = e < n ? g.recs[s0 + e] : EwRec{};
+                if (e < n) {
+                    rows = std::max(rows, m.e[e].rows);
+                    bytes += 8.0 * words * ((double)m.e[e].rows * (double)L.ctx->N);
+                }
+            }
+            m.logn = logn;
+            m.pr = pr;
+            dim3 grid = ew_grid(logn, rows);
+            grid.z = (unsigned)n;
+            prof_begin(L, "elementwise_batch", &ev);
+            switch (g.op) {
+#define PFX_EWM(O) case O: k_ew_multi<O><<<grid, 256, 0, L.st>>>(m, g.k); break;
+                PFX_EWM(EW_ADD) PFX_EWM(EW_SUB) PFX_EWM(EW_MUL) PFX_EWM(EW_MAC) PFX_EWM(EW_NEG) PFX_EWM(EW_MULC)
+                PFX_EWM(EW_MULC_ACC) PFX_EWM(EW_ADDC)
+#undef PFX_EWM
+                default: k_ew_multi<EW_COPY><<<grid, 256, 0, L.st>>>(m, g.k); break;
+            }
+            HIP_LAUNCH_CHECK();
+            prof_end(L, "elementwise_batch", ev, bytes);
+        }
+    }
+    for (int acc = 0; acc < 2; ++acc) {
+        const std::vector<TensorRec> &v = c->tensor[acc];
+        for (size_t s0 = 0; s0 < v.size(); s0 += kMaxBatch) {
+            const int n = (int)std::min<size_t>(kMaxBatch, v.size() - s0);
+            TensorMultiArgs m;
+            int rows = 0;
+            double bytes = 0;
+            for (int e = 0; e < kMaxBatch; ++e) {
+                m.e[e] = e < n ? v[s0 + e] : TensorRec{};
+                if (e < n) {
+                    rows = std::max(rows, m.e[e].nl);
+                    bytes += (acc ? 80.0 : 56.0) * (double)m.e[e].nl * (double)L.ctx->N;
+                }
+            }
+            m.logn = logn;
+            m.pr = pr;
+            dim3 grid = ew_grid(logn, rows);
+            grid.z = (unsigned)n;
+            prof_begin(L, "tensor_batch", &ev);
+            if (acc) k_tensor_multi<true><<<grid, 256, 0, L.st>>>(m);
+            else k_tensor_multi<false><<<grid, 256, 0, L.st>>>(m);
+            HIP_LAUNCH_CHECK();
+            prof_end(L, "tensor_batch", ev, bytes);
+        }
+    }
+    delete c;
 }
 
 // ============================================================== automorphism
