@@ -260,3 +260,94 @@ def test_full_size_query_exact_count_on_gap_data(X):
         assert int(round(got[0])) == exact
     finally:
         S.close()
+
+
+def test_elementwise_runs_match_single_calls(X):
+    """Runs of independent elementwise ops (issued by the executor as collected
+    launches) give the words of the same ops called one at a time."""
+    logn, L = 12, 6
+    prm = X.make_params(logn, QB[:L], PB, ALPHA, ML)
+    ctx = X.pfx_ctx_create(prm, 0)
+    N = 1 << logn
+    q, _, _ = X.pfx_ctx_moduli(ctx, L, len(PB))
+    q = [int(v) for v in q]
+    handles = []
+    try:
+        ins = []
+        for i in range(4):                       # two ciphertexts at L limbs, two at L - 1
+            lv = L if i < 2 else L - 1
+            h = X.pfx_ct_create(ctx, L, 1)
+            X.pfx_ct_import(ctx, I.uniform_residues(q[:lv], N, 70 + i, lead=(2,)), DELTA, h)
+            ins.append(h)
+        pts = []
+        for i in range(2):
+            pts.append(X.pfx_pt_import(ctx, I.uniform_residues(q, N, 80 + i), DELTA))
+        handles += ins + pts
+        R = 4                                    # work registers 4..9 (degree 2 for 7..9)
+        codes = [                                # in an order that keeps the scales compatible
+            (X.OP_COPY, 0, 0.0), (X.OP_ADD, 1, 0.0), (X.OP_SUB, 1, 0.0), (X.OP_MUL_INT, -35, 0.0),
+            (X.OP_MUL_INT_ACC, 21, 0.0), (X.OP_ADD_CONST, 0, 0.5), (X.OP_MUL_CONST, 0, 0.25),
+            (X.OP_SCALE_MUL, 0, 2.0), (X.OP_MUL_PLAIN, 1, 0.0), (X.OP_MUL_PLAIN_ACC, 0, 0.0),
+            (X.OP_ADD_PLAIN, 0, 0.0),
+        ]
+        ops = []
+        for code, k, value in codes:             # one run of 3 per code, registers 4, 5, 6
+            for j in range(3):
+                b = (j + 1) % 2 if code in (X.OP_MUL_PLAIN, X.OP_ADD_PLAIN, X.OP_MUL_PLAIN_ACC) else (j + 1) % 4
+                src = j if code in (X.OP_COPY,) else R + j
+                if code in (X.OP_ADD, X.OP_SUB, X.OP_MUL_PLAIN, X.OP_ADD_PLAIN, X.OP_MUL_INT):
+                    src = j % 4
+                kk = k if code in (X.OP_MUL_INT, X.OP_MUL_INT_ACC) else 0
+                if code in (X.OP_MUL_INT_ACC, X.OP_MUL_PLAIN_ACC):
+                    ops.append((code, R + j, j + 1, b, kk, value))
+                else:
+                    ops.append((code, R + j, src, b, kk, value))
+        for j in range(3):                       # tensor products and accumulation into 7..9
+            ops.append((X.OP_MUL, 7 + j, j, (j + 1) % 4, 0, 0.0))
+        for j in range(3):
+            ops.append((X.OP_MUL_ACC, 7 + j, (j + 2) % 4, j, 0, 0.0))
+        degs = [1] * 7 + [2] * 3
+        regs = ins + [X.pfx_ct_create(ctx, L, degs[i]) for i in range(4, 10)]
+        handles += regs[4:]
+        X.pfx_run_circuit(ctx, ops, regs, 4, pts, None, [], X.RUN_EAGER, None)
+        got = [X.pfx_ct_export(ctx, regs[i], N) for i in range(4, 10)]
+        # the same ops one at a time
+        ref = ins + [X.pfx_ct_create(ctx, L, degs[i]) for i in range(4, 10)]
+        handles += ref[4:]
+        for code, dst, a, b, k, value in ops:
+            d, A = ref[dst], ref[a]
+            if code == X.OP_COPY:
+                X.pfx_ct_copy(ctx, A, d)
+            elif code == X.OP_ADD:
+                X.pfx_add(ctx, A, ref[b], d)
+            elif code == X.OP_SUB:
+                X.pfx_sub(ctx, A, ref[b], d)
+            elif code == X.OP_MUL_PLAIN:
+                X.pfx_mul_plain(ctx, A, pts[b], d)
+            elif code == X.OP_ADD_PLAIN:
+                X.pfx_add_plain(ctx, A, pts[b], d)
+            elif code == X.OP_MUL_INT:
+                X.pfx_mul_int(ctx, A, k, d)
+            elif code == X.OP_MUL_INT_ACC:
+                X.pfx_mul_int_acc(ctx, A, k, d)
+            elif code == X.OP_MUL_PLAIN_ACC:
+                X.pfx_mul_plain_acc(ctx, A, pts[b], d)
+            elif code == X.OP_ADD_CONST:
+                X.pfx_add_const(ctx, A, value, d)
+            elif code == X.OP_MUL_CONST:
+                X.pfx_mul_const(ctx, A, value, 0.0, d)
+            elif code == X.OP_SCALE_MUL:
+                sc = X.pfx_ct_info(A).scale * value
+                X.pfx_ct_copy(ctx, A, d)
+                X.pfx_ct_set_scale(d, sc)
+            elif code == X.OP_MUL:
+                X.pfx_mul(ctx, A, ref[b], d)
+            elif code == X.OP_MUL_ACC:
+                X.pfx_mul_acc(ctx, A, ref[b], d)
+        for i in range(4, 10):
+            assert np.array_equal(X.pfx_ct_export(ctx, ref[i], N), got[i - 4]), i
+            assert X.pfx_ct_info(ref[i]).scale == X.pfx_ct_info(regs[i]).scale, i
+    finally:
+        for h in handles:
+            X.pfx_ct_destroy(h)
+        X.pfx_ctx_destroy(ctx)
