@@ -280,6 +280,7 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
  *   MUL_ACC       dst = dst + a * b (dst of degree 2)            b register
  *   MUL_PLAIN_ACC dst = dst + a * pts[b]                         b plaintext
  *   MUL_INT_ACC   dst = dst + a * k                              k
+ *   DROP          dst = the first k limbs of a (pfx_drop_level)  k
  *   RESCALE       dst = rescale(a)
  *   ADD_CONST     dst = a + value (pfx_add_const)                value
  *   MUL_CONST     dst = a * value at the last prime's scale      value
@@ -327,6 +328,7 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
 #define PFX_OP_MUL_ACC 16
 #define PFX_OP_MUL_PLAIN_ACC 17
 #define PFX_OP_MUL_INT_ACC 18
+#define PFX_OP_DROP 19
 
 typedef struct pfx_op {
     int32_t code;

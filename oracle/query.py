@@ -21,7 +21,9 @@ score of the query in place of the paper's coefficient-encoded PFE phase:
         U  = rescale(relin(X' P))
     step_b = (U + 1) with the scale doubled                  step = (sign + 1) / 2
   W   = step_0 + step_1 + ...
-  OUT = rotate-and-sum over all slots (InnerSum)
+  OUT = rotate-and-sum over all slots (InnerSum), on the first FINAL_LIMBS
+        limbs of W only (dropping limbs is exact; Q_2 > 2^94 holds any count
+        below 2^17 at a scale near 2^46 with room to spare)
 
 Additions take the scale of their first operand (the rule of the library).
 Every ct x ct product is relinearised and rescaled.
@@ -114,7 +116,10 @@ def sign_stage(P, x: O.Ct, rlk) -> O.Ct:
     return _mr(P, xs, p, rlk)
 
 
-def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None):
+FINAL_LIMBS = 2   # limbs the InnerSum runs on
+
+
+def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None, final_limbs=FINAL_LIMBS):
     """X[b][a]: plaintext words at scale x_scale; W[a], C[k], T, H: oracle ciphertexts."""
     D = len(C) - 1
     total = None
@@ -134,4 +139,5 @@ def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None)
         step = add_const(P, u, 1.0)
         step = O.Ct(step.c, step.scale * 2.0)
         total = step if total is None else O.ct_add(P, total, step)
+    total = O.Ct(total.c[:, :min(final_limbs, total.level)], total.scale)
     return O.rotate_sum(P, total, log_slots if log_slots is not None else P.logn - 1, gks)

@@ -312,6 +312,10 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
         case PFX_OP_MUL_ACC: r = pfx_mul_acc(c, A, R(o.b), d, stream); break;
         case PFX_OP_MUL_PLAIN_ACC: r = pfx_mul_plain_acc(c, A, pt, d, stream); break;
         case PFX_OP_MUL_INT_ACC: r = pfx_mul_int_acc(c, A, o.k, d, stream); break;
+        case PFX_OP_DROP:
+            if (o.k < 1 || o.k > (int64_t)A->n_limbs) return fail(PFX_ELEVEL, at + "cannot drop to that many limbs");
+            r = pfx_drop_level(c, A, (uint32_t)o.k, d, stream);
+            break;
         case PFX_OP_RELIN: r = pfx_relinearize(c, A, rlk, d, stream); break;
         case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
         case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
@@ -364,6 +368,7 @@ bool ew_code(int32_t code) {
         case PFX_OP_COPY: case PFX_OP_ADD: case PFX_OP_SUB: case PFX_OP_MUL_PLAIN: case PFX_OP_ADD_PLAIN:
         case PFX_OP_MUL_INT: case PFX_OP_MUL: case PFX_OP_MUL_ACC: case PFX_OP_MUL_PLAIN_ACC:
         case PFX_OP_MUL_INT_ACC: case PFX_OP_ADD_CONST: case PFX_OP_MUL_CONST: case PFX_OP_SCALE_MUL:
+        case PFX_OP_DROP:
             return true;
         default:
             return false;

@@ -15,7 +15,7 @@ slot-domain linear score): for each block b of 2^(logN-1) records
         P  = (-35) X2 + 21 X4 + (-5) X6 + 35
         U  = rescale(relin(rescale(X * round(q/16)) * P))
     step_b = (U + 1) with the scale doubled
-  OUT = InnerSum(step_0 + step_1 + ...)
+  OUT = InnerSum(step_0 + step_1 + ...) on the first final_limbs limbs
 
 Inputs (registers, read-only): W[0..A), C[0..D], T, H.  Plaintexts: X[b][a]
 at index b * A + a.  The op list and the register allocation are built here;
@@ -59,6 +59,7 @@ class QueryPlan:
     parallel: bool = False
     lanes: int = 4
     interleave: bool | int = False
+    final_limbs: int = 2
     ops: list = field(default_factory=list)
     n_regs: int = 0
     out: int = -1
@@ -213,6 +214,7 @@ class QueryPlan:
                 else:
                     self._op(X.OP_ADD, total, total, u)
                     self._drop(u)
+        self._op(X.OP_DROP, total, total, k=self.final_limbs)   # InnerSum on the lowest limbs that hold the count
         self.out = self._new()
         self._op(X.OP_ROTATE_SUM, self.out, total, k=self.log_slots)
         self._drop(total)

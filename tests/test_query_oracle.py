@@ -93,8 +93,10 @@ def test_constant_add_and_product_are_slotwise():
 
 def test_query_circuit_tracks_fp64():
     P, s_, x, (w, c, t, eta), X, delta, W, C, T, H, rlk, gks = build(10, 2, 7)
+    out = Q.query_circuit(P, X, delta, W, C, T, H, rlk, gks, final_limbs=P.L)
+    assert out.level == P.L - 18                             # the circuit's depth
     out = Q.query_circuit(P, X, delta, W, C, T, H, rlk, gks)
-    assert out.level == P.L - 18
+    assert out.level == Q.FINAL_LIMBS                        # InnerSum on the first limbs
     got = O.decode(P, O.decrypt(P, s_, out), out.scale, P.N // 2).real
     step, count = Q.fp64_query(x, w, c, t, eta)
     assert np.max(np.abs(got - count)) < 0.25
@@ -114,7 +116,7 @@ def test_query_exact_count_on_gap_data():
 def test_query_circuit_degrees_3_and_15():
     for D, depth in ((3, 17), (15, 19)):
         P, s_, x, (w, c, t, eta), X, delta, W, C, T, H, rlk, gks = build(9, 1, 13, degree=D)
-        out = Q.query_circuit(P, X, delta, W, C, T, H, rlk, gks)
+        out = Q.query_circuit(P, X, delta, W, C, T, H, rlk, gks, final_limbs=P.L)
         assert out.level == P.L - depth
         got = O.decode(P, O.decrypt(P, s_, out), out.scale, P.N // 2).real
         step, count = Q.fp64_query(x, w, c, t, eta)

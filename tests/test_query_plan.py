@@ -38,6 +38,8 @@ def interpret(plan, inputs, pts):
             r = reg[dst] + A * pts[b]
         elif code == X.OP_MUL_INT_ACC:
             r = reg[dst] + A * k
+        elif code == X.OP_DROP:
+            r = A
         elif code == X.OP_RELIN:
             r = A
         elif code == X.OP_RESCALE:
