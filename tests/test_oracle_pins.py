@@ -74,7 +74,7 @@ def lucas_certificate(q):
     return False
 
 
-SMALL = O.Params(5, [50, 50, 50], [50], alpha=1, mod_log2=13)   # N = 32, config-1 primes
+SMALL = O.Params(5, [50, 50, 50], [50], alpha=1, mod_log2=13)   # N = 32, three 50-bit primes and one special
 SMALL4 = O.Params(4, [50, 45, 45, 45, 45], [50, 50], alpha=2, mod_log2=17)
 
 
