@@ -10,6 +10,11 @@
         HBM bytes per dispatch of the kernels matching --kernel (all their
         dispatches), each counter scaled by what it reads for the copy kernel
         of known size (dispatches of that name and grid; KIB read = KIB written)
+    python -m paper_2412_13269_amd.profsum --runs R <..._kernel_trace.csv> [--top N]
+        the kernels after the longest idle gap of the trace (the runs after
+        the setup: `workload --query` idles 0.5 s there), grouped by kernel
+        name, per run (divided by R), with the device's busy and idle time
+        over that span
     python -m paper_2412_13269_amd.profsum --valu <SQ counters csv> <..._kernel_trace.csv> [--top N]
         per kernel and grid: VALU wave instructions per dispatch (SQ_INSTS_VALU),
         the average duration from the trace run, and the issue rate against
@@ -101,6 +106,30 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy: str) -> str:
     return "\n".join(out)
 
 
+def per_run(path: str, runs: int, top: int = 20) -> str:
+    ks = []
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = (row.get("Kernel_Name") or "?").split("(")[0].replace("void ", "").split("<")[0]
+            ks.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"]), name))
+    ks.sort()
+    gaps = [(ks[i + 1][0] - ks[i][1], i) for i in range(len(ks) - 1)]
+    cut = max(gaps)[1] + 1 if gaps else 0
+    ks = ks[cut:]
+    span = (ks[-1][1] - ks[0][0]) / 1000.0
+    busy = sum(e - s for s, e, _ in ks) / 1000.0
+    groups = defaultdict(list)
+    for s_, e, n in ks:
+        groups[n].append((e - s_) / 1000.0)
+    out = [f"{len(ks) / runs:.0f} launches per run; per run {span / runs:.1f} us span, "
+           f"{busy / runs:.1f} us busy, {(span - busy) / runs:.1f} us idle between launches", "",
+           "| kernel | launches per run | avg us | us per run | share |", "|---|---|---|---|---|"]
+    for n, d in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        out.append(f"| `{n}` | {len(d) / runs:.0f} | {sum(d) / len(d):.2f} | {sum(d) / runs:.1f} | "
+                   f"{sum(d) / busy:.3f} |")
+    return "\n".join(out)
+
+
 VALU_PEAK = 256 * 4 * 2.4e9 / 4     # wave64 FP64 VALU instructions per second
 
 
@@ -140,6 +169,11 @@ def valu(counters_csv: str, trace_csv: str, top: int = 16) -> str:
 
 
 if __name__ == "__main__":
+    if "--runs" in sys.argv:
+        i = sys.argv.index("--runs")
+        top = int(sys.argv[sys.argv.index("--top") + 1]) if "--top" in sys.argv else 20
+        print(per_run(sys.argv[i + 2], int(sys.argv[i + 1]), top))
+        sys.exit(0)
     if "--valu" in sys.argv:
         i = sys.argv.index("--valu")
         top = int(sys.argv[sys.argv.index("--top") + 1]) if "--top" in sys.argv else 16

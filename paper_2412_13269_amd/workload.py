@@ -11,7 +11,10 @@ rotations by 2^k for k = 0..14 (15 distinct Galois keys): 16 key switches.
     python -m paper_2412_13269_amd.workload --steps 20 [--calibrate]
 
 runs the step `--steps` times after one warm-up step, the command that
-rocprofv3 wraps for kernel traces and counters.  `--calibrate` first imports
+rocprofv3 wraps for kernel traces and counters.  `--query` runs instead the
+private query on 2^17 records (4 blocks of 2^15, 8 attributes, degree-7 score,
+(7,7,7) sign, InnerSum), blocks interleaved on one stream, eagerly, `--steps`
+times after one warm-up run.  `--calibrate` first imports
 one ciphertext five times: the library's plain word-to-double copy
 (k_u64_to_f64) of one polynomial per launch, 24 limbs = 12 MiB read and 12 MiB
 written, the reference against which HBM counters are scaled.
@@ -111,12 +114,45 @@ class KsWorkload:
         X.pfx_ctx_destroy(self.ctx)
 
 
+def query_runs(w, steps):
+    """The interleaved 4-block query, eagerly, after one warm-up run."""
+    import numpy as np
+    from . import inputs as I
+    from .query import QueryPlan
+    X, ctx, st, N, L = w.X, w.ctx, w.st, w.N, w.L
+    plan = QueryPlan(4, 8, 7, 3, LOGN - 1, interleave=True)
+    x = I.synthetic_database(4 * (N // 2), 8, 301)
+    wt, c, t, eta = I.query_parameters(8, 7, 302)
+    regs = [X.pfx_ct_create(ctx, L, plan.reg_degree[i]) for i in range(plan.n_regs)]
+    for i, v in enumerate(list(wt) + list(c) + [t, eta]):
+        pt = X.pfx_encode(ctx, np.full(N // 2, v), None, L, SCALE)
+        X.pfx_encrypt(ctx, w.sk, pt, I.uniform_residues(w.q, N, 400 + 2 * i), I.gaussian_error(N, 401 + 2 * i),
+                      regs[i], st)
+        X.pfx_ct_destroy(pt)
+    db = [X.pfx_encode(ctx, x[b * (N // 2):(b + 1) * (N // 2), a], None, L, SCALE) for b in range(4) for a in range(8)]
+    X.pfx_sync(ctx, st)
+    import time
+    time.sleep(0.5)      # an idle gap that marks the end of the setup in kernel traces
+    for _ in range(steps + 1):
+        X.pfx_run_circuit(ctx, plan.ops, regs, plan.n_inputs, db, w.rlk, w.gks, X.RUN_EAGER, st)
+    X.pfx_sync(ctx, st)
+    for h in regs + db:
+        X.pfx_ct_destroy(h)
+    return plan
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--calibrate", action="store_true")
+    ap.add_argument("--query", action="store_true")
     args = ap.parse_args()
     w = KsWorkload(log=lambda *a: print(*a, flush=True))
+    if args.query:
+        plan = query_runs(w, args.steps)
+        print(f"{args.steps} queries done ({plan.key_switches} key switches each)", flush=True)
+        w.close()
+        return
     if args.calibrate:
         w.calibrate_copy()
         print("copy calibration done", flush=True)
