@@ -74,3 +74,37 @@ def test_cyclic_instead_of_negacyclic_is_caught(monkeypatch):
             g += 1
     monkeypatch.setattr(O, "find_psi", cyclic_root)
     _expect_fail(T.test_ntt_product_is_negacyclic_convolution, 3)
+
+
+# ---- lookup-table evaluation and ring repacking (oracle/repack.py)
+from oracle import repack as RP
+from tests import test_repack_oracle as TR
+
+
+def test_monomial_without_wrap_sign_is_caught(monkeypatch):
+    def unsigned(a, k, mods, N):
+        d = (np.arange(N) + k % (2 * N)) % N
+        out = np.empty_like(a)
+        out[:, d] = a
+        return out
+    monkeypatch.setattr(RP, "monomial", unsigned)
+    _expect_fail(TR.test_lookup_constant_coefficient_is_f_of_the_point)
+
+
+def test_repack_without_inverse_n_is_caught(monkeypatch):
+    monkeypatch.setattr(RP, "ct_mul_inv_n", lambda P, x: x)
+    _expect_fail(TR.test_repack_decrypts_to_the_constant_coefficients, 32)
+
+
+def test_repack_with_shifted_galois_order_is_caught(monkeypatch):
+    monkeypatch.setattr(RP, "repack_galois", lambda P, i: pow(5, 1 << i, 2 * P.N))
+    _expect_fail(TR.test_repack_decrypts_to_the_constant_coefficients, 32)
+
+
+def test_repack_with_wrong_sign_inside_the_automorphism_is_caught(monkeypatch):
+    orig_sub = O.ct_sub
+    monkeypatch.setattr(O, "ct_sub", lambda P, x, y: O.ct_add(P, x, y))
+    try:
+        _expect_fail(TR.test_repack_decrypts_to_the_constant_coefficients, 32)
+    finally:
+        monkeypatch.setattr(O, "ct_sub", orig_sub)
