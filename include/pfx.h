@@ -233,6 +233,19 @@ pfx_status pfx_key_switch(pfx_ctx *ctx, const pfx_ct *d, const pfx_swk *k, pfx_c
  * g is the key's Galois element. */
 pfx_status pfx_apply_galois(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *gk, pfx_ct *out,
                             void *stream);
+/* n automorphisms by the Galois element of gk: out[i] = phi_g(a[i]), word for
+ * word n calls of pfx_apply_galois; entries of one level share batched
+ * key-switch launches (up to 8; the key residues read once for them).
+ * Outputs must be distinct and alias no input of any entry (PFX_EINVAL). */
+pfx_status pfx_apply_galois_batch(pfx_ctx *ctx, const pfx_ct *const *a, size_t n, const pfx_swk *gk,
+                                  pfx_ct *const *out, void *stream);
+/* a * X^k in R_Q = Z_Q[X]/(X^N + 1) (k taken mod 2N; X^N = -1): the lookup of
+ * plaintext point k in an encrypted table (Sec. 3.4) and the X^t of ring
+ * repacking (Alg. 1).  Scale and level are kept; out may be a. */
+pfx_status pfx_mul_monomial(pfx_ctx *ctx, const pfx_ct *a, int64_t k, pfx_ct *out, void *stream);
+/* a * N^-1 mod Q (every residue times N^-1 mod q_i), the pre-multiplication
+ * of ring repacking (Alg. 1); the scale is kept.  out may be a. */
+pfx_status pfx_mul_inv_n(pfx_ctx *ctx, const pfx_ct *a, pfx_ct *out, void *stream);
 /* Rotate slots left by `step` (App. A.1); the key for 5^step mod 2N must be
  * among keys[0..n_keys) (PFX_ENOKEY otherwise). */
 pfx_status pfx_rotate(pfx_ctx *ctx, const pfx_ct *a, int32_t step, const pfx_swk *const *keys,
@@ -281,6 +294,10 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
  *   MUL_PLAIN_ACC dst = dst + a * pts[b]                         b plaintext
  *   MUL_INT_ACC   dst = dst + a * k                              k
  *   DROP          dst = the first k limbs of a (pfx_drop_level)  k
+ *   MONO          dst = a * X^k (pfx_mul_monomial)               k
+ *   INV_N         dst = a * N^-1 mod Q (pfx_mul_inv_n)
+ *   GALOIS        dst = phi_k(a) (pfx_apply_galois; the key of    k
+ *                 Galois element k among gks)
  *   RESCALE       dst = rescale(a)
  *   ADD_CONST     dst = a + value (pfx_add_const)                value
  *   MUL_CONST     dst = a * value at the last prime's scale      value
@@ -329,6 +346,9 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
 #define PFX_OP_MUL_PLAIN_ACC 17
 #define PFX_OP_MUL_INT_ACC 18
 #define PFX_OP_DROP 19
+#define PFX_OP_MONO 20
+#define PFX_OP_INV_N 21
+#define PFX_OP_GALOIS 22
 
 typedef struct pfx_op {
     int32_t code;

@@ -312,6 +312,14 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
         case PFX_OP_MUL_ACC: r = pfx_mul_acc(c, A, R(o.b), d, stream); break;
         case PFX_OP_MUL_PLAIN_ACC: r = pfx_mul_plain_acc(c, A, pt, d, stream); break;
         case PFX_OP_MUL_INT_ACC: r = pfx_mul_int_acc(c, A, o.k, d, stream); break;
+        case PFX_OP_MONO: r = pfx_mul_monomial(c, A, o.k, d, stream); break;
+        case PFX_OP_INV_N: r = pfx_mul_inv_n(c, A, d, stream); break;
+        case PFX_OP_GALOIS: {
+            pfx_swk *gk = (o.k > 0 && o.k < 2 * (int64_t)c->N) ? find_key(c, (uint32_t)o.k, gks, n_gks) : nullptr;
+            if (!gk) return fail(PFX_ENOKEY, at + "no Galois key for element " + std::to_string(o.k));
+            r = pfx_apply_galois(c, A, gk, d, stream);
+            break;
+        }
         case PFX_OP_DROP:
             if (o.k < 1 || o.k > (int64_t)A->n_limbs) return fail(PFX_ELEVEL, at + "cannot drop to that many limbs");
             r = pfx_drop_level(c, A, (uint32_t)o.k, d, stream);
@@ -335,23 +343,25 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
 }
 
 // Length of the run of ops starting at ops[i] that one batched launch sequence
-// may take: consecutive HMult + relin ops (or consecutive relinearisations, or
-// rescales), at most max_batch, outputs distinct and none of them an operand of
-// another op of the run, so the ops are independent.  An HMult + relin output
-// must not alias its own operands either (the batched key switch reads them
-// while it writes); a relinearisation or a rescale may work in place.  1 if
-// ops[i] alone; 0 for any other op.
+// may take: consecutive HMult + relin ops (or consecutive relinearisations,
+// rescales, or automorphisms by one Galois element), at most max_batch,
+// outputs distinct and none of them an operand of another op of the run, so
+// the ops are independent.  An HMult + relin or automorphism output must not
+// alias its own operands either (the batched key switch reads them while it
+// writes); a relinearisation or a rescale may work in place.  1 if ops[i]
+// alone; 0 for any other op.
 size_t mr_run(const pfx_op *ops, size_t n_ops, size_t i, int max_batch) {
     const int32_t code = ops[i].code;
-    if (code != PFX_OP_MUL_RELIN && code != PFX_OP_RESCALE && code != PFX_OP_RELIN) return 0;
-    const bool mr = code == PFX_OP_MUL_RELIN;
-    auto reads = [&](const pfx_op &o, int32_t r) { return o.a == r || (mr && o.b == r); };
+    if (code != PFX_OP_MUL_RELIN && code != PFX_OP_RESCALE && code != PFX_OP_RELIN && code != PFX_OP_GALOIS) return 0;
+    const bool rb = code == PFX_OP_MUL_RELIN;                      // b is a register
+    const bool no_self = rb || code == PFX_OP_GALOIS;              // no in-place output
+    auto reads = [&](const pfx_op &o, int32_t r) { return o.a == r || (rb && o.b == r); };
     const pfx_op &f = ops[i];
-    if (mr && reads(f, f.dst)) return 1;
+    if (no_self && reads(f, f.dst)) return 1;
     size_t j = i + 1;
     for (; j < n_ops && j - i < (size_t)max_batch && ops[j].code == code; ++j) {
         const pfx_op &o = ops[j];
-        bool ok = !(mr && reads(o, o.dst));
+        bool ok = !(no_self && reads(o, o.dst)) && (code != PFX_OP_GALOIS || o.k == f.k);
         for (size_t k = i; k < j && ok; ++k) {
             const pfx_op &p = ops[k];
             ok = o.dst != p.dst && !reads(p, o.dst) && !reads(o, p.dst);
@@ -368,7 +378,7 @@ bool ew_code(int32_t code) {
         case PFX_OP_COPY: case PFX_OP_ADD: case PFX_OP_SUB: case PFX_OP_MUL_PLAIN: case PFX_OP_ADD_PLAIN:
         case PFX_OP_MUL_INT: case PFX_OP_MUL: case PFX_OP_MUL_ACC: case PFX_OP_MUL_PLAIN_ACC:
         case PFX_OP_MUL_INT_ACC: case PFX_OP_ADD_CONST: case PFX_OP_MUL_CONST: case PFX_OP_SCALE_MUL:
-        case PFX_OP_DROP:
+        case PFX_OP_DROP: case PFX_OP_MONO: case PFX_OP_INV_N:
             return true;
         default:
             return false;
@@ -469,6 +479,7 @@ pfx_status run_span(pfx_ctx *c, const pfx_op *ops, size_t lo, size_t hi, pfx_ct 
         const size_t run = max_batch > 1 ? mr_run(ops, hi, i, max_batch) : 0;
         if (run > 1) {
             const bool mr = ops[i].code == PFX_OP_MUL_RELIN;
+            const bool gal = ops[i].code == PFX_OP_GALOIS;
             const pfx_ct *a[kMaxBatch], *b[kMaxBatch];
             pfx_ct *out[kMaxBatch];
             bool distinct = true;       // distinct registers may still name one ciphertext
@@ -486,10 +497,17 @@ pfx_status run_span(pfx_ctx *c, const pfx_op *ops, size_t lo, size_t hi, pfx_ct 
             for (size_t k = 0; k < run && distinct; ++k)
                 for (size_t m = 0; m < run && distinct; ++m) {
                     if (k != m) distinct = out[k]->d != a[m]->d && out[k]->d != b[m]->d && out[k]->d != out[m]->d;
-                    else if (mr) distinct = out[k]->d != a[k]->d && out[k]->d != b[k]->d;
+                    else if (mr || gal) distinct = out[k]->d != a[k]->d && out[k]->d != b[k]->d;
                 }
+            pfx_swk *gk = nullptr;
+            if (gal) {
+                const int64_t g = ops[i].k;
+                gk = (g > 0 && g < 2 * (int64_t)c->N) ? find_key(c, (uint32_t)g, gks, n_gks) : nullptr;
+                distinct = distinct && gk;     // a missing key: run_op reports it
+            }
             if (distinct) {
                 pfx_status r = mr ? pfx_mul_relin_batch(c, a, b, run, rlk, out, stream)
+                               : gal ? pfx_apply_galois_batch(c, a, run, gk, out, stream)
                                : ops[i].code == PFX_OP_RELIN ? pfx_relinearize_batch(c, a, run, rlk, out, stream)
                                                              : pfx_rescale_batch(c, a, run, out, stream);
                 if (r) return fail(r, "ops " + std::to_string(i) + ".." + std::to_string(i + run - 1) + ": " + g_err);
@@ -1584,6 +1602,101 @@ pfx_status pfx_apply_galois(pfx_ctx *c, const pfx_ct *a, const pfx_swk *gk, pfx_
     r = check_out(out, a->n_limbs, 1);
     if (r) return r;
     return galois_apply(c, a, gk, out, S(stream));
+}
+
+pfx_status pfx_apply_galois_batch(pfx_ctx *c, const pfx_ct *const *a, size_t n, const pfx_swk *gk,
+                                  pfx_ct *const *out, void *stream) {
+    REQUIRE(c && (n == 0 || (a && out)), PFX_EINVAL, "null argument");
+    REQUIRE(gk && gk->ctx == c && gk->galois != 0, PFX_ENOKEY, "not a Galois key");
+    for (size_t i = 0; i < n; ++i) {
+        pfx_status r = check_ct(c, a[i], "a");
+        if (r) return r;
+        REQUIRE(a[i]->degree == 1, PFX_EINVAL, "automorphism needs a degree-1 ciphertext");
+        r = check_out(out[i], a[i]->n_limbs, 1);
+        if (r) return r;
+    }
+    for (size_t i = 0; i < n; ++i)           // the last launch reads the inputs while writing outputs
+        for (size_t j = 0; j < n; ++j) {
+            REQUIRE(out[i]->d != a[j]->d, PFX_EINVAL, "batched automorphism output aliases an input");
+            REQUIRE(i == j || out[i]->d != out[j]->d, PFX_EINVAL, "batched automorphism outputs alias");
+        }
+    if (n == 0) return PFX_OK;
+    Ws w;
+    pfx_status r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    std::vector<int> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return a[x]->n_limbs > a[y]->n_limbs; });
+    std::vector<uint32_t> lvs(n);
+    std::vector<double> sc(n);
+    for (size_t i = 0; i < n; ++i) {
+        lvs[i] = a[i]->n_limbs;
+        sc[i] = a[i]->scale;
+    }
+    for (size_t s0 = 0; s0 < n;) {
+        size_t s1 = s0;
+        while (s1 < n && s1 - s0 < (size_t)kMaxBatch && lvs[order[s1]] == lvs[order[s0]]) ++s1;
+        KsBatch kb;
+        r = get_batch_ws(c, L.st, (int)(s1 - s0), kb);
+        if (r) return r;
+        kb.nb = (int)(s1 - s0);
+        kb.mode = KS_GALOIS;
+        for (int e = 0; e < kb.nb; ++e) {
+            const pfx_ct *x = a[order[s0 + e]];
+            KsOperand &op = kb.op[e];
+            op.mode = KS_GALOIS;
+            op.d = x->poly(1);
+            op.base0 = x->poly(0);
+            op.galois = gk->galois;
+            kb.out0[e] = out[order[s0 + e]]->poly(0);
+            kb.out1[e] = out[order[s0 + e]]->poly(1);
+        }
+        ks_run(L, kb, (int)lvs[order[s0]], gk);
+        s0 = s1;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        out[i]->n_limbs = lvs[i];
+        out[i]->degree = 1;
+        out[i]->scale = sc[i];
+    }
+    return PFX_OK;
+}
+
+pfx_status pfx_mul_monomial(pfx_ctx *c, const pfx_ct *a, int64_t k, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_out(out, a->n_limbs, a->degree);
+    if (r) return r;
+    const int64_t twoN = 2 * (int64_t)c->N;
+    const uint32_t e = (uint32_t)(((k % twoN) + twoN) % twoN);
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    const uint32_t lv = a->n_limbs, deg = a->degree;
+    const double sc = a->scale;
+    launch_monomial(L, out->d, a->d, out->cap_limbs * N, a->cap_limbs * N, (int)deg + 1, (int)lv, e);
+    out->n_limbs = lv;
+    out->degree = deg;
+    out->scale = sc;
+    return PFX_OK;
+}
+
+pfx_status pfx_mul_inv_n(pfx_ctx *c, const pfx_ct *a, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    r = check_out(out, a->n_limbs, a->degree);
+    if (r) return r;
+    std::vector<uint64_t> cst(a->n_limbs);
+    for (uint32_t i = 0; i < a->n_limbs; ++i) cst[i] = invmod_u64((uint64_t)c->N % c->primes[i], c->primes[i]);
+    Launch L{c, S(stream)};
+    const size_t N = c->N;
+    const uint32_t lv = a->n_limbs, deg = a->degree;
+    const double sc = a->scale;
+    launch_mulconst(L, out->d, a->d, out->cap_limbs * N, a->cap_limbs * N, (int)deg + 1, (int)lv, cst.data());
+    out->n_limbs = lv;
+    out->degree = deg;
+    out->scale = sc;
+    return PFX_OK;
 }
 
 pfx_status pfx_rotate(pfx_ctx *c, const pfx_ct *a, int32_t step, const pfx_swk *const *keys, size_t n, pfx_ct *out,

@@ -202,7 +202,11 @@ void launch_s8_to_rns(const Launch &L, double *out, const int8_t *in, int n_limb
 // EW_MAC: out = out + a * b (out read and written by the same thread).  The
 // last three are the per-limb constant forms of collected launches.
 enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4, EW_MAC = 5, EW_MULC = 6, EW_MULC_ACC = 7,
-            EW_ADDC = 8 };
+            EW_ADDC = 8, EW_MONO = 9 };
+// out = a * X^k (k in [0, 2N)) in the NTT domain, npoly polynomials of nl limbs
+// (kernels.hip): slot j is multiplied by psi^(k (2 bitrev(j) + 1)).
+void launch_monomial(const Launch &L, double *out, const double *a, size_t so, size_t sa, int npoly, int nl,
+                     uint32_t k);
 // Collection of independent elementwise / constant / tensor launches on one
 // stream by the calling thread (kernels.hip): between begin and end the
 // launchers record instead of launching; end issues one launch per kernel

@@ -247,6 +247,7 @@ struct EwRec {
     const double *a, *b;
     size_t so, sa, sb;
     int rows, nl;
+    uint32_t k;            // EW_MONO: the exponent
 };
 struct TensorRec {
     double *d0, *d1, *d2;
@@ -297,11 +298,23 @@ void collect_ew(Collector *c, int op, const EwRec &r, const LimbConsts *k, int n
 // Records a launch when a collector is active for (ctx, stream); false if the
 // caller should launch it itself.
 static bool record_ew(const Launch &L, int op, double *out, const double *a, const double *b, size_t so, size_t sa,
-                      size_t sb, int rows, int nl, const LimbConsts *k, int nk) {
+                      size_t sb, int rows, int nl, const LimbConsts *k, int nk, uint32_t e = 0) {
     Collector *c = collecting(L);
     if (!c) return false;
-    collect_ew(c, op, EwRec{out, a, b, so, sa, sb, rows, nl}, k, nk);
+    collect_ew(c, op, EwRec{out, a, b, so, sa, sb, rows, nl, e}, k, nk);
     return true;
+}
+
+// psi^(k (2 bitrev(j) + 1)) for slot j: the exponent mod 2N, psi^e from the
+// bit-reversed table (tw[bitrev(e)] = psi^e for e < N), negated for e >= N
+// (psi^N = -1).
+__device__ __forceinline__ double monomial_mul(double x, uint32_t j, uint32_t k, int logn, const PrimeDev &P) {
+    const uint32_t N = 1u << logn;
+    const uint32_t ej = 2u * (__brev(j) >> (32 - logn)) + 1u;
+    const uint32_t E = (uint32_t)(((uint64_t)k * ej) & (2ull * N - 1));
+    const double2 w = P.tw[__brev(E & (N - 1)) >> (32 - logn)];
+    const double r = mmulc(x, w.x, w.y, P.q);
+    return (E >= N && r != 0.0) ? P.q - r : r;
 }
 
 static bool record_tensor(const Launch &L, const TensorRec &r, bool acc) {
@@ -426,6 +439,33 @@ void launch_addconst(const Launch &L, double *out, const double *a, int nl, cons
     prof_end(L, "addconst", ev, 16.0 * (double)total);
 }
 
+// Monomial product (the lookup of a plaintext point, Sec. 3.4; the X^t of ring
+// repacking, Alg. 1): a * X^k.
+__global__ __launch_bounds__(256) void k_monomial(double *out, const double *a, size_t so, size_t sa, int nl,
+                                                  int logn, const PrimeDev *pr, uint32_t k) {
+    const int row = blockIdx.y;
+    const int kp = row / nl, i = row - kp * nl;
+    const size_t off = (size_t)i << logn;
+    const double *ap = a + kp * sa + off;
+    double *op = out + kp * so + off;
+    const PrimeDev &P = pr[i];
+    const size_t N = (size_t)1 << logn;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x)
+        op[c] = monomial_mul(ap[c], (uint32_t)c, k, logn, P);
+}
+
+void launch_monomial(const Launch &L, double *out, const double *a, size_t so, size_t sa, int npoly, int nl,
+                     uint32_t k) {
+    if (record_ew(L, EW_MONO, out, a, nullptr, so, sa, 0, npoly * nl, nl, nullptr, 0, k)) return;
+    const size_t total = ((size_t)npoly * nl) << L.ctx->logn;
+    hipEvent_t ev;
+    prof_begin(L, "monomial", &ev);
+    k_monomial<<<ew_grid(L.ctx->logn, npoly * nl), 256, 0, L.st>>>(out, a, so, sa, nl, L.ctx->logn, L.ctx->d_primes,
+                                                                     k);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "monomial", ev, 16.0 * (double)total);
+}
+
 // Tensor product in the NTT domain (Sec. 2.4.2): d0 = a0 b0, d1 = a0 b1 + a1 b0,
 // d2 = a1 b1; ACC adds it to what d0, d1, d2 hold.
 template <bool ACC>
@@ -501,6 +541,7 @@ __global__ __launch_bounds__(256) void k_ew_multi(const EwMultiArgs m, const Lim
         else if (OP == EW_MULC) v = mmulc(x, k.w[i], k.wq[i], q);
         else if (OP == EW_MULC_ACC) v = madd(op[c], mmulc(x, k.w[i], k.wq[i], q), q);
         else if (OP == EW_ADDC) v = madd(x, k.w[i], q);
+        else if (OP == EW_MONO) v = monomial_mul(x, (uint32_t)c, r.k, logn, m.pr[i]);
         else v = x;
         op[c] = v;
     }
@@ -552,7 +593,8 @@ void ew_collect_end(const Launch &L) {
             EwMultiArgs m;
             int rows = 0;
             double bytes = 0;
-            const double words = (g.op == EW_NEG || g.op == EW_COPY || g.op == EW_MULC || g.op == EW_ADDC) ? 2
+            const double words = (g.op == EW_NEG || g.op == EW_COPY || g.op == EW_MULC || g.op == EW_ADDC ||
+                                  g.op == EW_MONO) ? 2
                                  : (g.op == EW_MAC) ? 4 : 3;
             for (int e = 0; e < kMaxBatch; ++e) {
                 m.e[e] = e < n ? g.recs[s0 + e] : EwRec{};
@@ -569,7 +611,7 @@ void ew_collect_end(const Launch &L) {
             switch (g.op) {
 #define PFX_EWM(O) case O: k_ew_multi<O><<<grid, 256, 0, L.st>>>(m, g.k); break;
                 PFX_EWM(EW_ADD) PFX_EWM(EW_SUB) PFX_EWM(EW_MUL) PFX_EWM(EW_MAC) PFX_EWM(EW_NEG) PFX_EWM(EW_MULC)
-                PFX_EWM(EW_MULC_ACC) PFX_EWM(EW_ADDC)
+                PFX_EWM(EW_MULC_ACC) PFX_EWM(EW_ADDC) PFX_EWM(EW_MONO)
 #undef PFX_EWM
                 default: k_ew_multi<EW_COPY><<<grid, 256, 0, L.st>>>(m, g.k); break;
             }

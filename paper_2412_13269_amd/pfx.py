@@ -46,6 +46,7 @@ class pfx_op(ctypes.Structure):
 OP_COPY, OP_ADD, OP_SUB, OP_MUL_PLAIN, OP_ADD_PLAIN, OP_MUL_INT, OP_MUL_RELIN = 0, 1, 2, 3, 4, 5, 6
 OP_RESCALE, OP_ADD_CONST, OP_MUL_CONST, OP_SCALE_MUL, OP_ROTATE, OP_ROTATE_SUM = 7, 8, 9, 10, 11, 12
 OP_LANE, OP_MUL, OP_RELIN, OP_MUL_ACC, OP_MUL_PLAIN_ACC, OP_MUL_INT_ACC, OP_DROP = 13, 14, 15, 16, 17, 18, 19
+OP_MONO, OP_INV_N, OP_GALOIS = 20, 21, 22
 
 
 class pfx_info(ctypes.Structure):
@@ -130,6 +131,9 @@ _SIGS = {
     "pfx_drop_level": (_i32, [_vp, _vp, _u32, _vp, _vp]),
     "pfx_key_switch": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_apply_galois": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "pfx_apply_galois_batch": (_i32, [_vp, _VPP, _sz, _vp, _VPP, _vp]),
+    "pfx_mul_monomial": (_i32, [_vp, _vp, _i64, _vp, _vp]),
+    "pfx_mul_inv_n": (_i32, [_vp, _vp, _vp, _vp]),
     "pfx_rotate": (_i32, [_vp, _vp, _i32, _VPP, _sz, _vp, _vp]),
     "pfx_conjugate": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp]),
     "pfx_rotate_sum": (_i32, [_vp, _vp, _u32, _VPP, _sz, _vp, _vp]),
@@ -451,6 +455,21 @@ def pfx_key_switch(ctx, d, k, out, stream=None):
 
 def pfx_apply_galois(ctx, a, gk, out, stream=None):
     _check(_lib.pfx_apply_galois(ctx, a, gk, out, _stream(stream)))
+
+
+def pfx_apply_galois_batch(ctx, a, gk, outs, stream=None):
+    n = len(a)
+    assert len(outs) == n
+    arr = lambda xs: (ctypes.c_void_p * max(1, n))(*xs)
+    _check(_lib.pfx_apply_galois_batch(ctx, arr(a), n, gk, arr(outs), _stream(stream)))
+
+
+def pfx_mul_monomial(ctx, a, k: int, out, stream=None):
+    _check(_lib.pfx_mul_monomial(ctx, a, k, out, _stream(stream)))
+
+
+def pfx_mul_inv_n(ctx, a, out, stream=None):
+    _check(_lib.pfx_mul_inv_n(ctx, a, out, _stream(stream)))
 
 
 def pfx_rotate(ctx, a, step: int, keys, out, stream=None):

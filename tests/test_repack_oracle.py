@@ -84,3 +84,58 @@ def test_lookup_then_repack_gives_the_table_at_the_points():
     out = R.repack(P, R.evaluate(P, U, points), gks)
     got = R.packed_values(P, s, out, P.N)
     assert np.max(np.abs(got - f[points])) < 2 ** -16
+
+
+# ---- the library's op list (paper_2412_13269_amd/repack.py), run on plaintexts
+def _run_plan_on_plaintexts(plan, inputs, q, N):
+    """Registers hold integer polynomials mod q; the automorphism is the exact
+    map X -> X^g, so Lemma 1 holds without noise."""
+    from paper_2412_13269_amd import pfx as X
+    reg = {i: np.asarray(v, dtype=np.uint64) for i, v in enumerate(inputs)}
+    ninv = pow(N, -1, q)
+    for code, dst, a, b, k, value in plan.ops:
+        A = reg[a]
+        if code == X.OP_INV_N:
+            r = O.smul(A[None, :], [ninv], [q])[0]
+        elif code == X.OP_MONO:
+            r = R.monomial(A[None, :], int(k), [q], N)[0]
+        elif code == X.OP_SUB:
+            r = O.sub(A[None, :], reg[b][None, :], [q])[0]
+        elif code == X.OP_ADD:
+            r = O.add(A[None, :], reg[b][None, :], [q])[0]
+        elif code == X.OP_GALOIS:
+            r = O.automorphism(A[None, :], int(k), [q], int(np.log2(N)))[0]
+        else:
+            raise AssertionError(f"op {code} not in a repacking plan")
+        assert dst >= plan.n_inputs
+        reg[dst] = r
+    return reg[plan.out]
+
+
+@pytest.mark.parametrize("logn,n", [(5, 32), (5, 7), (6, 64), (6, 1), (6, 33)])
+def test_repack_plan_packs_the_constant_coefficients(logn, n):
+    from paper_2412_13269_amd.repack import RepackPlan, repack_keys_needed
+    N, q = 1 << logn, params(logn).q[0]
+    rng = np.random.default_rng(logn * 100 + n)
+    ms = [rng.integers(0, q, size=N, dtype=np.uint64) for _ in range(n)]
+    plan = RepackPlan(logn, n)
+    assert {o[4] for o in plan.ops if o[0] == 22} <= set(repack_keys_needed(logn))
+    got = _run_plan_on_plaintexts(plan, ms, q, N)
+    want = np.zeros(N, dtype=np.uint64)
+    want[:n] = [m[0] for m in ms]
+    assert np.array_equal(got, want)
+
+
+def test_lookup_plan_reads_the_table_at_the_points():
+    from paper_2412_13269_amd.repack import RepackPlan
+    logn = 6
+    N, q = 1 << logn, params(logn).q[0]
+    rng = np.random.default_rng(7)
+    table = rng.integers(0, q, size=N)
+    u = np.empty(N, dtype=np.uint64)                 # u_f = f(0) - sum_k f(N - k) X^k, mod q
+    u[0] = table[0]
+    u[1:] = (q - table[N - np.arange(1, N)]) % q
+    points = rng.integers(0, N, size=N)
+    plan = RepackPlan(logn, N, points=list(points))
+    got = _run_plan_on_plaintexts(plan, [u], q, N)
+    assert np.array_equal(got, table[points].astype(np.uint64))
