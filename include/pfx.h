@@ -246,6 +246,30 @@ pfx_status pfx_mul_monomial(pfx_ctx *ctx, const pfx_ct *a, int64_t k, pfx_ct *ou
 /* a * N^-1 mod Q (every residue times N^-1 mod q_i), the pre-multiplication
  * of ring repacking (Alg. 1); the scale is kept.  out may be a. */
 pfx_status pfx_mul_inv_n(pfx_ctx *ctx, const pfx_ct *a, pfx_ct *out, void *stream);
+/* Ring repacking (Sec. 3.2, Alg. 1) of in[0..n), degree-1 ciphertexts of one
+ * level and scale, in groups of N: out[g] (g < ceil(n / N)) encrypts
+ * sum_j m_(gN+j)[0] X^j, the constant coefficients of the group's inputs
+ * (Lemma 1).  Inputs are multiplied by N^-1, the last group is padded with
+ * zero ciphertexts, then round i < log N with t = N / 2^(i+1) and g = 2N - 1
+ * (i = 0) or 5^(2^(i-1)) mod 2N updates c_j <- c_j + X^t c_(j+t) +
+ * phi_g(c_j - X^t c_(j+t)) for j < t, every pair of every group of a round in
+ * batched key-switch launches.  The log N Galois keys must be among gks
+ * (PFX_ENOKEY).  Outputs keep the inputs' level and scale and alias no input
+ * (PFX_EINVAL).  The stream's repacking arrays (1.5 ceil(n/N) N ciphertexts)
+ * are allocated on first use, not under graph capture. */
+pfx_status pfx_repack(pfx_ctx *ctx, const pfx_ct *const *in, size_t n, const pfx_swk *const *gks, size_t n_gks,
+                      pfx_ct *const *out, void *stream);
+/* Private lookup-table evaluation with score aggregation, then ring repacking
+ * (Sec. 3.4, Sec. 4.2 "Encrypted Scoring Functions", Alg. 1): record r < n is
+ * the ciphertext sum_l tables[l] X^(exps[r m + l]) (tables[l] encrypts u_f of
+ * function l, Sec. 3.4, and its constant coefficient is then sum_l f_l(k_rl)),
+ * and out[g] encrypts the records g N .. g N + N - 1 in its coefficients, as
+ * pfx_repack of those records would (word for word).  exps: device memory,
+ * n * m int64 exponents, row-major by record, taken mod 2N; the records are
+ * formed directly in the repacking arrays.  tables: m degree-1 ciphertexts of
+ * one level and scale; out as for pfx_repack. */
+pfx_status pfx_pfe_repack(pfx_ctx *ctx, const pfx_ct *const *tables, size_t m, const int64_t *exps, size_t n,
+                          const pfx_swk *const *gks, size_t n_gks, pfx_ct *const *out, void *stream);
 /* Rotate slots left by `step` (App. A.1); the key for 5^step mod 2N must be
  * among keys[0..n_keys) (PFX_ENOKEY otherwise). */
 pfx_status pfx_rotate(pfx_ctx *ctx, const pfx_ct *a, int32_t step, const pfx_swk *const *keys,

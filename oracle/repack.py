@@ -11,6 +11,9 @@ Sec. 3.2 "Ring Repacking", Alg. 1), on coefficient-encoded RLWE ciphertexts of
                  scientist;
   evaluation     X^i * Enc(u_f) encrypts a polynomial whose constant
                  coefficient is f(i) (X^N = -1), for a plaintext point i;
+  aggregation    record r of a database: sum_l X^(k_(r,l)) * Enc(u_(f_l)), whose
+                 constant coefficient is sum_l f_l(k_(r,l)) (Sec. 4.2, the
+                 encrypted scoring functions summed over the attributes);
   repacking      N ciphertexts -> one encrypting sum_i m_i[0] X^i: every
                  input times N^-1 mod Q, then for i = 0 .. log N - 1 with
                  t = N / 2^(i+1), g = 2N - 1 for i = 0 and 5^(2^(i-1)) mod 2N
@@ -93,6 +96,22 @@ def lut_poly(f_values, delta: float) -> np.ndarray:
 def evaluate(P, U: O.Ct, points) -> list:
     """X^i * U for each point i: the lookup of f at i in the constant coefficient."""
     return [ct_monomial(P, U, int(i)) for i in points]
+
+
+def score_records(P, tables: list, exps) -> list:
+    """Record r: sum over the tables l of X^(exps[r][l]) * tables[l] (Sec. 4.2)."""
+    out = []
+    for row in np.asarray(exps, dtype=np.int64):
+        acc = ct_monomial(P, tables[0], int(row[0]))
+        for U, k in zip(tables[1:], row[1:]):
+            acc = O.ct_add(P, acc, ct_monomial(P, U, int(k)))
+        out.append(acc)
+    return out
+
+
+def repack_groups(P, cts: list, gks: dict) -> list:
+    """Alg. 1 on consecutive groups of N ciphertexts (the last one zero-padded)."""
+    return [repack(P, cts[g:g + P.N], gks) for g in range(0, len(cts), P.N)]
 
 
 def packed_values(P, s, ct: O.Ct, n: int) -> np.ndarray:

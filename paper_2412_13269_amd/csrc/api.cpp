@@ -201,7 +201,8 @@ void ks_run(const Launch &L, const KsBatch &kb, int lv, const pfx_swk *key) {
         }
     }
     launch_ntt_pass(L, kb.ext, nullptr, m, true, false, kb.nb, kb.sext);
-    launch_ks_inner(L, kb, key->d_k, lv);
+    if (kb.mode == KS_REPACK) launch_ks_inner_repack(L, kb, key->d_k, lv);
+    else launch_ks_inner(L, kb, key->d_k, lv);
     launch_intt_special(L, kb, lv);
     launch_moddown_col(L, kb, lv);
     launch_row_moddown(L, kb, lv);
@@ -763,6 +764,7 @@ void pfx_ctx_destroy(pfx_ctx *c) {
     for (auto &kv : c->ws) {
         (void)hipFree(kv.second->buf);
         (void)hipFree(kv.second->bbuf);
+        (void)hipFree(kv.second->rbuf);
         delete kv.second;
     }
     for (auto &e : c->prof_pending) {
@@ -1345,7 +1347,7 @@ pfx_status pfx_mul_relin(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx
 // Batched HMult + relinearisation: entries of one level share every launch
 // of the key switch (the key residues are read once per launch for all of
 // them), at most kMaxBatch entries per launch.
-pfx_status mul_relin_group(pfx_ctx *c, const Launch &L, const pfx_ct *const *a, const pfx_ct *const *b,
+static pfx_status mul_relin_group(pfx_ctx *c, const Launch &L, const pfx_ct *const *a, const pfx_ct *const *b,
                            pfx_ct *const *out, const int *idx, int nb, int lv, const pfx_swk *rlk) {
     KsBatch kb;
     pfx_status r = get_batch_ws(c, L.st, nb, kb);
@@ -1697,6 +1699,210 @@ pfx_status pfx_mul_inv_n(pfx_ctx *c, const pfx_ct *a, pfx_ct *out, void *stream)
     out->degree = deg;
     out->scale = sc;
     return PFX_OK;
+}
+
+// ------------------------------------------------------------ ring repacking
+}  // extern "C"
+
+namespace {
+
+// Ring-repacking arrays of one stream (doubles), grown on demand.
+pfx_status get_repack_ws(pfx_ctx *c, hipStream_t st, size_t doubles, double **out) {
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->ws.find(st);
+    if (it == c->ws.end()) return fail(PFX_EINVAL, "stream has no workspace");
+    Workspace *w = it->second;
+    if (w->rcap < doubles) {
+        if (c->capturing) return fail(PFX_EINVAL, "repacking workspace must be reserved before graph capture");
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(w->rbuf);
+        w->rbuf = nullptr;
+        w->rcap = 0;
+        if (hipMalloc(&w->rbuf, doubles * sizeof(double)) != hipSuccess)
+            return fail(PFX_ENOMEM, "repacking workspace allocation failed");
+        w->rcap = doubles;
+    }
+    *out = w->rbuf;
+    return PFX_OK;
+}
+
+uint32_t repack_galois(const pfx_ctx *c, int i) {
+    const uint64_t two_n = 2 * (uint64_t)c->N;
+    if (i == 0) return (uint32_t)(two_n - 1);
+    uint64_t g = 5;                                  // 5^(2^(i-1)) mod 2N
+    for (int k = 1; k < i; ++k) g = g * g % two_n;
+    return (uint32_t)g;
+}
+
+// Key-switch entries per repacking launch: the per-entry scratch of a batch
+// stays within 512 MiB.
+int repack_chunk(const pfx_ctx *c) {
+    const size_t per = batch_entry_doubles(c) * sizeof(double);
+    return (int)std::max<size_t>(1, std::min<size_t>(4096, ((size_t)512 << 20) / per));
+}
+
+// Alg. 1 over G groups of N ciphertexts (2 polynomials of lv limbs each, cs =
+// 2 lv N doubles apart) already multiplied by N^-1 in A (group stride N cs);
+// B holds N/2 ciphertexts per group.  Round i reads one array and writes the
+// other; the result of group g is slot 0 of group g of *res (group stride
+// *res_gs).
+pfx_status repack_rounds(pfx_ctx *c, const Launch &L, double *A, double *B, int G, int lv,
+                         const pfx_swk *const *gks, size_t n_gks, const double **res, size_t *res_gs) {
+    const size_t N = c->N, cs = 2 * (size_t)lv * N;
+    const double *in = A;
+    double *out = B;
+    size_t in_gs = N * cs, out_gs = (N / 2) * cs;
+    const int chunk = repack_chunk(c);
+    for (int i = 0; i < c->logn; ++i) {
+        const int tlog = c->logn - 1 - i;
+        const uint32_t g = repack_galois(c, i);
+        const pfx_swk *gk = find_key(c, g, gks, n_gks);
+        REQUIRE(gk, PFX_ENOKEY, "no key for a Galois element of ring repacking");
+        const int total = G << tlog;
+        for (int e0 = 0; e0 < total; e0 += chunk) {
+            KsBatch kb;
+            const int nb = std::min(chunk, total - e0);
+            pfx_status r = get_batch_ws(c, L.st, nb, kb);
+            if (r) return r;
+            kb.nb = nb;
+            kb.mode = KS_REPACK;
+            kb.rp.in = in;
+            kb.rp.out = out;
+            kb.rp.in_gs = in_gs;
+            kb.rp.out_gs = out_gs;
+            kb.rp.cs = cs;
+            kb.rp.ps = (size_t)lv * N;
+            kb.rp.tlog = tlog;
+            kb.rp.e0 = e0;
+            kb.rp.galois = g;
+            ks_run(L, kb, lv, gk);
+        }
+        double *next_out = (in == A) ? A : B;        // the array just read is free
+        size_t next_gs = in_gs;
+        in = out;
+        in_gs = out_gs;
+        out = next_out;
+        out_gs = next_gs;
+    }
+    *res = in;
+    *res_gs = in_gs;
+    return PFX_OK;
+}
+
+// Slot 0 of each group into the output ciphertexts.
+pfx_status repack_store(pfx_ctx *c, hipStream_t st, const double *res, size_t res_gs, int G, int lv, double scale,
+                        pfx_ct *const *out) {
+    const size_t N = c->N, ps = (size_t)lv * N;
+    for (int g = 0; g < G; ++g) {
+        const double *src = res + (size_t)g * res_gs;
+        for (int u = 0; u < 2; ++u)
+            HIPCHECK(hipMemcpyAsync(out[g]->poly((uint32_t)u), src + (size_t)u * ps, ps * sizeof(double),
+                                    hipMemcpyDeviceToDevice, st));
+        out[g]->n_limbs = (uint32_t)lv;
+        out[g]->degree = 1;
+        out[g]->scale = scale;
+    }
+    return PFX_OK;
+}
+
+pfx_status check_repack_out(const pfx_ctx *c, pfx_ct *const *out, int G, uint32_t lv) {
+    for (int g = 0; g < G; ++g) {
+        REQUIRE(out[g] && out[g]->ctx == c, PFX_EINVAL, "repacking output from another context");
+        pfx_status r = check_out(out[g], lv, 1);
+        if (r) return r;
+    }
+    return PFX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pfx_status pfx_repack(pfx_ctx *c, const pfx_ct *const *in, size_t n, const pfx_swk *const *gks, size_t n_gks,
+                      pfx_ct *const *out, void *stream) {
+    REQUIRE(c && in && out && n >= 1, PFX_EINVAL, "null argument or no input");
+    REQUIRE(n <= (size_t)1 << 24, PFX_EINVAL, "more than 2^24 inputs");
+    for (size_t i = 0; i < n; ++i) {
+        pfx_status r = check_ct(c, in[i], "in");
+        if (r) return r;
+        REQUIRE(in[i]->degree == 1, PFX_EINVAL, "repacking needs degree-1 ciphertexts");
+        REQUIRE(in[i]->n_limbs == in[0]->n_limbs, PFX_ELEVEL, "repacking inputs at different levels");
+        REQUIRE(in[i]->scale == in[0]->scale, PFX_ESCALE, "repacking inputs at different scales");
+    }
+    const size_t N = c->N;
+    const int G = (int)((n + N - 1) / N);
+    const int lv = (int)in[0]->n_limbs;
+    pfx_status r = check_repack_out(c, out, G, (uint32_t)lv);
+    if (r) return r;
+    for (int g = 0; g < G; ++g)
+        for (size_t i = 0; i < n; ++i)
+            REQUIRE(out[g]->d != in[i]->d, PFX_EINVAL, "repacking output aliases an input");
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    const size_t cs = 2 * (size_t)lv * N;
+    double *A = nullptr;
+    r = get_repack_ws(c, S(stream), (size_t)G * N * cs * 3 / 2, &A);
+    if (r) return r;
+    double *B = A + (size_t)G * N * cs;
+    Launch L{c, S(stream)};
+    // N^-1 c_i into the slots (Alg. 1 pre-multiplication), zeros after the last input
+    std::vector<uint64_t> ninv(lv);
+    for (int i = 0; i < lv; ++i) ninv[i] = invmod_u64((uint64_t)N % c->primes[i], c->primes[i]);
+    ew_collect_begin(L);
+    for (size_t i = 0; i < n; ++i)
+        launch_mulconst(L, A + i * cs, in[i]->d, (size_t)lv * N, (size_t)in[i]->cap_limbs * N, 2, lv, ninv.data());
+    ew_collect_end(L);
+    launch_mono_sum(L, A + n * cs, cs, (size_t)lv * N, nullptr, 0, 0, 0, nullptr, 0, (int)((size_t)G * N - n), lv,
+                    false);
+    const double *res;
+    size_t res_gs;
+    r = repack_rounds(c, L, A, B, G, lv, gks, n_gks, &res, &res_gs);
+    if (r) return r;
+    return repack_store(c, L.st, res, res_gs, G, lv, in[0]->scale, out);
+}
+
+pfx_status pfx_pfe_repack(pfx_ctx *c, const pfx_ct *const *tables, size_t m, const int64_t *exps, size_t n,
+                          const pfx_swk *const *gks, size_t n_gks, pfx_ct *const *out, void *stream) {
+    REQUIRE(c && tables && exps && out && m >= 1 && n >= 1, PFX_EINVAL, "null argument, no table or no record");
+    REQUIRE(m <= 4096 && n <= (size_t)1 << 24, PFX_EINVAL, "more than 4096 tables or 2^24 records");
+    for (size_t l = 0; l < m; ++l) {
+        pfx_status r = check_ct(c, tables[l], "tables");
+        if (r) return r;
+        REQUIRE(tables[l]->degree == 1, PFX_EINVAL, "lookup tables must be degree-1 ciphertexts");
+        REQUIRE(tables[l]->n_limbs == tables[0]->n_limbs, PFX_ELEVEL, "lookup tables at different levels");
+        REQUIRE(tables[l]->scale == tables[0]->scale, PFX_ESCALE, "lookup tables at different scales");
+    }
+    const size_t N = c->N;
+    const int G = (int)((n + N - 1) / N);
+    const int lv = (int)tables[0]->n_limbs;
+    pfx_status r = check_repack_out(c, out, G, (uint32_t)lv);
+    if (r) return r;
+    for (int g = 0; g < G; ++g)
+        for (size_t l = 0; l < m; ++l)
+            REQUIRE(out[g]->d != tables[l]->d, PFX_EINVAL, "repacking output aliases a table");
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    const size_t cs = 2 * (size_t)lv * N;
+    const size_t tbl = (size_t)m * cs;
+    double *T = nullptr;
+    r = get_repack_ws(c, S(stream), tbl + (size_t)G * N * cs * 3 / 2, &T);
+    if (r) return r;
+    double *A = T + tbl, *B = A + (size_t)G * N * cs;
+    Launch L{c, S(stream)};
+    // the tables side by side (contiguous polynomials), then every record's sum
+    for (size_t l = 0; l < m; ++l)
+        for (int u = 0; u < 2; ++u)
+            HIPCHECK(hipMemcpyAsync(T + l * cs + (size_t)u * lv * N, tables[l]->poly((uint32_t)u),
+                                    (size_t)lv * N * sizeof(double), hipMemcpyDeviceToDevice, L.st));
+    launch_mono_sum(L, A, cs, (size_t)lv * N, T, cs, (size_t)lv * N, (int)m, exps, (int)n, (int)((size_t)G * N), lv,
+                    true);
+    const double *res;
+    size_t res_gs;
+    r = repack_rounds(c, L, A, B, G, lv, gks, n_gks, &res, &res_gs);
+    if (r) return r;
+    return repack_store(c, L.st, res, res_gs, G, lv, tables[0]->scale, out);
 }
 
 pfx_status pfx_rotate(pfx_ctx *c, const pfx_ct *a, int32_t step, const pfx_swk *const *keys, size_t n, pfx_ct *out,
@@ -2246,6 +2452,7 @@ pfx_status pfx_stream_destroy(pfx_ctx *c, void *stream) {
         if (it != c->ws.end()) {
             (void)hipFree(it->second->buf);
             (void)hipFree(it->second->bbuf);
+            (void)hipFree(it->second->rbuf);
             delete it->second;
             c->ws.erase(it);
         }

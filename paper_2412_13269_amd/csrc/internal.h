@@ -70,6 +70,8 @@ struct Workspace {
     size_t doubles = 0;
     double *bbuf = nullptr;   // batched key-switch scratch (bcap entries), on demand
     int bcap = 0;
+    double *rbuf = nullptr;   // ring-repacking arrays (rcap doubles), on demand
+    size_t rcap = 0;
 };
 
 struct ProfEntry {
@@ -230,7 +232,9 @@ void launch_automorph(const Launch &L, double *out, const double *in, size_t so,
 //   KS_PLAIN:   switch d, add base0 / base1 (either may be null)
 //   KS_GALOIS:  switch phi_galois(d), add phi_galois(base0) (base1 null)
 //   KS_PRODUCT: switch a1 b1, add a0 b0 and a0 b1 + a1 b0 (HMult + relin)
-enum KsMode { KS_PLAIN = 0, KS_GALOIS = 1, KS_PRODUCT = 2 };
+//   KS_REPACK:  one update of ring repacking (Alg. 1) per entry, entries
+//               described by a RepackDesc instead of operand pointers
+enum KsMode { KS_PLAIN = 0, KS_GALOIS = 1, KS_PRODUCT = 2, KS_REPACK = 3 };
 struct KsOperand {
     int mode = KS_PLAIN;
     const double *d = nullptr;
@@ -244,14 +248,36 @@ struct KsOperand {
 // the key switch covers the whole batch in one launch, and the inner product
 // reads each key residue once for all entries.
 constexpr int kMaxBatch = 8;
+// Ring repacking round of Alg. 1, t = 2^tlog pairs per group: the ciphertexts
+// of a round sit in arrays of groups (group stride in_gs / out_gs, ciphertext
+// stride cs, polynomial stride ps, doubles); batch entry b is pair
+// e = e0 + b, group e >> tlog, j = e mod t, and computes, with
+// lo = c_j and hi = c_(j+t) of the input array,
+//   out_j = lo + X^t hi + phi_g(lo - X^t hi)        (phi_g with key switching)
+// into slot j of its group in the output array (which must not be the input).
+struct RepackDesc {
+    const double *in = nullptr;
+    double *out = nullptr;
+    size_t in_gs = 0, out_gs = 0, cs = 0, ps = 0;
+    int tlog = 0, e0 = 0;
+    uint32_t galois = 0;
+};
 struct KsBatch {
-    int nb = 1, mode = KS_PLAIN;
+    int nb = 1, mode = KS_PLAIN;      // KS_REPACK: nb is not bounded by kMaxBatch
+    RepackDesc rp;
     KsOperand op[kMaxBatch];
     double *out0[kMaxBatch] = {}, *out1[kMaxBatch] = {};
     double *dcoef = nullptr, *ext = nullptr, *acc = nullptr, *tmp = nullptr;
     size_t sdc = 0, sext = 0, sacc = 0, stmp = 0;
 };
 void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int lv);
+void launch_ks_inner_repack(const Launch &L, const KsBatch &kb, const double *key, int lv);
+// Output slot r < n_slots (2 polynomials of lv limbs, slots cs apart,
+// polynomial stride ps) = sum_l tables[l] X^(exps[r m + l]) for r < n, zero for
+// r >= n; m tables of 2 polynomials at `tables` (table stride st, polynomial
+// stride tps); exps in device memory (int64, taken mod 2N); ninv: times N^-1.
+void launch_mono_sum(const Launch &L, double *out, size_t cs, size_t ps, const double *tables, size_t st,
+                     size_t tps, int m, const int64_t *exps, int n, int n_slots, int lv, bool ninv);
 // Rescale of nb ciphertexts of np polynomials at lv limbs (rescale.hip): entry
 // b reads ents[b].in and writes ents[b].out (which may equal in), polynomials
 // si / so doubles apart; scratch `last` (nb np limbs) and `tmp` (nb np (lv - 1)

@@ -305,18 +305,6 @@ static bool record_ew(const Launch &L, int op, double *out, const double *a, con
     return true;
 }
 
-// psi^(k (2 bitrev(j) + 1)) for slot j: the exponent mod 2N, psi^e from the
-// bit-reversed table (tw[bitrev(e)] = psi^e for e < N), negated for e >= N
-// (psi^N = -1).
-__device__ __forceinline__ double monomial_mul(double x, uint32_t j, uint32_t k, int logn, const PrimeDev &P) {
-    const uint32_t N = 1u << logn;
-    const uint32_t ej = 2u * (__brev(j) >> (32 - logn)) + 1u;
-    const uint32_t E = (uint32_t)(((uint64_t)k * ej) & (2ull * N - 1));
-    const double2 w = P.tw[__brev(E & (N - 1)) >> (32 - logn)];
-    const double r = mmulc(x, w.x, w.y, P.q);
-    return (E >= N && r != 0.0) ? P.q - r : r;
-}
-
 static bool record_tensor(const Launch &L, const TensorRec &r, bool acc) {
     Collector *c = collecting(L);
     if (!c) return false;
@@ -464,6 +452,66 @@ void launch_monomial(const Launch &L, double *out, const double *a, size_t so, s
                                                                      k);
     HIP_LAUNCH_CHECK();
     prof_end(L, "monomial", ev, 16.0 * (double)total);
+}
+
+// Score aggregation of the lookup tables (Sec. 3.4, Sec. 4.2): record r gets
+// sum_l T_l X^(k_(r,l)), slot x of a limb being sum_l psi^(k_(r,l) e_x) T_l[x]
+// (monomial_mul), times N^-1 when `ninv` is set (the pre-multiplication of
+// ring repacking; (N^-1 mod q) times the reduced sum is the same residue as
+// the sum of N^-1 T_l X^k).  Grid: x over the N slots, y over polynomial x
+// limb rows, z over records r0 + z; records r >= n are written as zero.
+__global__ __launch_bounds__(256) void k_mono_sum(double *out, size_t cs, size_t ps, const double *tables, size_t st,
+                                                  size_t tps, int m, const int64_t *exps, int n, int r0, int lv,
+                                                  int logn, const PrimeDev *pr, bool ninv) {
+    const int row = blockIdx.y;
+    const int u = row / lv, i = row - u * lv;
+    const int r = r0 + (int)blockIdx.z;
+    const size_t N = (size_t)1 << logn;
+    const size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    double *o = out + (size_t)r * cs + (size_t)u * ps + ((size_t)i << logn);
+    if (r >= n) {
+        o[x] = 0.0;
+        return;
+    }
+    const PrimeDev &P = pr[i];
+    const double q = P.q, qi = P.qinv;
+    const int64_t *ke = exps + (size_t)r * m;
+    const double *tb = tables + (size_t)u * tps + ((size_t)i << logn) + x;
+    const uint32_t mask = (2u << logn) - 1u;
+    // terms in [0, q), q < 2^50: seven of them and a reduced partial sum stay
+    // below 8q < 2^53
+    double s = 0.0;
+    int pend = 0;
+    for (int l = 0; l < m; ++l) {
+        const uint32_t k = (uint32_t)((uint64_t)ke[l] & mask);   // k mod 2N, also for k < 0
+        s += monomial_mul(tb[(size_t)l * st], (uint32_t)x, k, logn, P);
+        if (++pend == 7) {
+            s = mred(s, q, qi);
+            pend = 0;
+        }
+    }
+    s = mred(s, q, qi);
+    o[x] = ninv ? mmulc(s, P.ninv, P.ninv_q, q) : s;
+}
+
+void launch_mono_sum(const Launch &L, double *out, size_t cs, size_t ps, const double *tables, size_t st,
+                     size_t tps, int m, const int64_t *exps, int n, int n_slots, int lv, bool ninv) {
+    if (n_slots <= 0) return;
+    const int logn = L.ctx->logn;
+    const size_t N = L.ctx->N;
+    constexpr int kRecs = 32768;   // records per launch (grid z)
+    hipEvent_t ev;
+    prof_begin(L, "mono_sum", &ev);
+    for (int r0 = 0; r0 < n_slots; r0 += kRecs) {
+        const int nr = std::min(kRecs, n_slots - r0);
+        const dim3 grid((unsigned)std::max<size_t>(1, (N + 255) / 256), (unsigned)(2 * lv), (unsigned)nr);
+        k_mono_sum<<<grid, 256, 0, L.st>>>(out, cs, ps, tables, st, tps, m, exps, n, r0, lv, logn,
+                                           L.ctx->d_primes, ninv);
+        HIP_LAUNCH_CHECK();
+    }
+    // outputs written once, exponents read once (the tables stay in cache)
+    prof_end(L, "mono_sum", ev, 16.0 * (double)N * lv * n_slots + 8.0 * (double)m * std::max(0, std::min(n, n_slots)));
 }
 
 // Tensor product in the NTT domain (Sec. 2.4.2): d0 = a0 b0, d1 = a0 b1 + a1 b0,

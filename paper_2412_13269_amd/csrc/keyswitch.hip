@@ -62,8 +62,29 @@ struct KsArgs {
     int n;          // logical blocks
     int nb, per;    // batch entries, blocks per entry
     size_t sdc, sext, sacc, stmp;
+    RepackDesc rp;  // KS_REPACK entries (op unused; nb may exceed kMaxBatch)
     KsEntry op[kMaxBatch];
 };
+
+// KS_REPACK: c_j (lo) and c_(j+t) (hi) of entry bi in the round's input array,
+// and its slot in the output array.
+struct RpPtrs {
+    const double *lo, *hi;
+    double *out;
+    uint32_t t;
+};
+__device__ __forceinline__ RpPtrs rp_ptrs(const RepackDesc &r, int bi) {
+    const unsigned e = (unsigned)(r.e0 + bi);
+    const unsigned grp = e >> r.tlog, j = e & ((1u << r.tlog) - 1u);
+    const uint32_t t = 1u << r.tlog;
+    const double *lo = r.in + grp * r.in_gs + j * r.cs;
+    return RpPtrs{lo, lo + t * r.cs, r.out + grp * r.out_gs + j * r.cs, t};
+}
+// lo[x] - X^t hi[x] (the difference that Alg. 1 rotates), slot x of one limb
+__device__ __forceinline__ double rp_diff(const double *lo, const double *hi, uint32_t x, uint32_t t, int logn,
+                                          const PrimeDev &P) {
+    return msub(lo[x], monomial_mul(hi[x], x, t, logn, P), P.q);
+}
 
 __device__ __forceinline__ int ks_ext_prime(int t, int j0, int sz, int lv, int L) {
     if (t < j0) return t;
@@ -181,11 +202,23 @@ __global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, const double
     const int gid = xcd_slot(a.n);
     if (gid >= a.n) return;
     const int bi = gid / a.per, id = gid - bi * a.per;
-    const KsEntry &en = a.op[bi];
+    const KsEntry &en = a.op[MODE == KS_REPACK ? 0 : bi];
     acc += bi * a.sacc;
     tmp += bi * a.stmp;
-    double *out0 = en.out0, *out1 = en.out1;
-    const double *base0 = en.base0, *base1 = en.base1;
+    double *out0, *out1;
+    const double *base0, *base1;
+    RpPtrs rp{};
+    if constexpr (MODE == KS_REPACK) {
+        rp = rp_ptrs(a.rp, bi);
+        out0 = rp.out;
+        out1 = rp.out + a.rp.ps;
+        base0 = base1 = nullptr;
+    } else {
+        out0 = en.out0;
+        out1 = en.out1;
+        base0 = en.base0;
+        base1 = en.base1;
+    }
     const int tile = id % a.tiles;
     const int rest = id / a.tiles;
     const int u = rest % 2;
@@ -214,7 +247,13 @@ __global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, const double
         if (e < tot) {
             const unsigned g = (unsigned)(g0 + e);
             xa[k] = ax[g];
-            if (MODE == KS_PRODUCT) {
+            if constexpr (MODE == KS_REPACK) {
+                // c_j + X^t c_(j+t), plus phi_g(c_j - X^t c_(j+t)) for c0
+                const double *lo = rp.lo + (size_t)u * a.rp.ps + li, *hi = rp.hi + (size_t)u * a.rp.ps + li;
+                xb[k] = madd(lo[g], monomial_mul(hi[g], g, rp.t, a.logn, P), q);
+                if (u == 0)
+                    xb[k] = madd(xb[k], rp_diff(lo, hi, galois_src(g, a.logn, a.rp.galois), rp.t, a.logn, P), q);
+            } else if (MODE == KS_PRODUCT) {
                 xb[k] = u == 0 ? mmul(en.a0[li + g], en.b0[li + g], q, P.qinv)
                                : madd(mmul(en.a0[li + g], en.b1[li + g], q, P.qinv),
                                       mmul(en.a1[li + g], en.b0[li + g], q, P.qinv), q);
@@ -237,10 +276,12 @@ __global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__res
     const int gid = xcd_slot(a.n);
     if (gid >= a.n) return;
     const int bi = gid / a.per, id = gid - bi * a.per;
-    const KsEntry &en = a.op[bi];
+    const KsEntry &en = a.op[MODE == KS_REPACK ? 0 : bi];
     dst += bi * a.sdc;
     // the row (first) pass reads the operand, the column pass dst in place
-    const double *src = ROW ? en.d : dst;
+    RpPtrs rp{};
+    if constexpr (MODE == KS_REPACK) rp = rp_ptrs(a.rp, bi);
+    const double *src = ROW ? (MODE == KS_REPACK ? nullptr : en.d) : dst;
     const int i = id / a.tiles;
     const int tile = id - i * a.tiles;
     const PrimeDev &P = a.primes[i];
@@ -250,6 +291,9 @@ __global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__res
     const size_t li = (size_t)i * N;
     auto ld = [&](int g, int) {
         const unsigned e = (unsigned)g;
+        if constexpr (MODE == KS_REPACK)
+            return rp_diff(rp.lo + a.rp.ps + li, rp.hi + a.rp.ps + li, galois_src(e, a.logn, a.rp.galois), rp.t,
+                           a.logn, P);
         if (MODE == KS_PRODUCT) return mmul(en.a1[li + e], en.b1[li + e], P.q, P.qinv);
         return s[MODE == KS_GALOIS ? galois_src(e, a.logn, en.galois) : e];
     };
@@ -292,6 +336,49 @@ __global__ __launch_bounds__(TH) void k_intt_special(const KsArgs a, double *__r
     }
 }
 
+// ---- step 3 for KS_REPACK: the inner product of one entry per blockIdx.z (a
+// batch of any size); the entry's own digit reads phi_g(c_j - X^t c_(j+t)) of
+// the round's input array where the other entries' kernel reads d.
+__global__ __launch_bounds__(256) void k_ks_inner_repack(const KsArgs a, const double *__restrict__ key,
+                                                         const double *__restrict__ ext, double *__restrict__ acc) {
+    const int m = blockIdx.y, bi = blockIdx.z;
+    const int logn = a.logn;
+    const size_t N = (size_t)1 << logn;
+    const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    const int lv = a.lv, E = a.E, alpha = a.alpha, beta = a.beta;
+    const int pid = m < lv ? m : a.L + (m - lv);
+    const PrimeDev &P = a.primes[pid];
+    const double q = P.q, qi = P.qinv;
+    const size_t kstride = (size_t)(a.L + a.K) * N;
+    const double *k0 = key + ((size_t)pid << logn) + c;
+    const RpPtrs rp = rp_ptrs(a.rp, bi);
+    ext += bi * a.sext;
+    acc += bi * a.sacc;
+    const size_t lm = (size_t)m << logn;
+    // products in [0, q), reduced after every fourth digit (sums below 5q < 2^53)
+    double a0 = 0.0, a1 = 0.0;
+    int pend = 0;
+    for (int j = 0; j < beta; ++j) {
+        const int j0 = j * alpha;
+        const int sz = min(alpha, lv - j0);
+        const bool own = m >= j0 && m < j0 + sz;
+        const int tt = m < j0 ? m : m - sz;
+        const double x = own ? rp_diff(rp.lo + a.rp.ps + lm, rp.hi + a.rp.ps + lm,
+                                       galois_src((uint32_t)c, logn, a.rp.galois), rp.t, logn, P)
+                             : ext[((size_t)j * E + tt) * N + c];
+        a0 += mmul(x, k0[(size_t)(2 * j) * kstride], q, qi);
+        a1 += mmul(x, k0[(size_t)(2 * j + 1) * kstride], q, qi);
+        if (++pend == 4) {
+            a0 = mred(a0, q, qi);
+            a1 = mred(a1, q, qi);
+            pend = 0;
+        }
+    }
+    acc[lm + c] = mred(a0, q, qi);
+    acc[((size_t)(E + m) << logn) + c] = mred(a1, q, qi);
+}
+
 // ----------------------------------------------------------------- launchers
 // Term count of a conversion kernel: n rounded up to 1, 2, 4 or 8.
 #define PFX_SWITCH_NT(n_, CALL)                                          \
@@ -306,6 +393,7 @@ __global__ __launch_bounds__(TH) void k_intt_special(const KsArgs a, double *__r
     switch (m_) {                                                      \
         case KS_GALOIS: { constexpr int MD = KS_GALOIS; CALL; } break;  \
         case KS_PRODUCT: { constexpr int MD = KS_PRODUCT; CALL; } break; \
+        case KS_REPACK: { constexpr int MD = KS_REPACK; CALL; } break;   \
         default: { constexpr int MD = KS_PLAIN; CALL; } break;          \
     }
 
@@ -326,9 +414,10 @@ static KsArgs ks_args(pfx_ctx *c, int lv, const KsBatch &kb) {
     a.sext = kb.sext;
     a.sacc = kb.sacc;
     a.stmp = kb.stmp;
+    a.rp = kb.rp;
     for (int b = 0; b < kMaxBatch; ++b) {
         KsEntry &e = a.op[b];
-        if (b < kb.nb) {
+        if (b < kb.nb && kb.mode != KS_REPACK) {
             const KsOperand &o = kb.op[b];
             e = KsEntry{o.d, o.base0, o.base1, o.a0, o.a1, o.b0, o.b1, kb.out0[b], kb.out1[b], o.galois};
         } else {
@@ -444,13 +533,25 @@ void launch_row_moddown(const Launch &L, const KsBatch &kb, int lv) {
     a.tiles = ps.tiles;
     set_blocks(a, 2 * lv * a.tiles);
     const double *acc = kb.acc, *tmp = kb.tmp;
-    const int nbases = kb.mode == KS_PRODUCT ? 4 : (kb.op[0].base0 ? 1 : 0) + (kb.op[0].base1 ? 1 : 0);
+    const int nbases = kb.mode == KS_PRODUCT ? 4 : kb.mode == KS_REPACK ? 3
+                                                 : (kb.op[0].base0 ? 1 : 0) + (kb.op[0].base1 ? 1 : 0);
     hipEvent_t ev;
     prof_begin(L, "ks_row_moddown", &ev);
     PFX_SWITCH_TH(th, PFX_SWITCH_KS(kb.mode, PFX_SWITCH_S(ps.S, (k_row_moddown<SS, MD, TH><<<xcd_grid(a.n), TH, 0,
                                                                                           L.st>>>(a, acc, tmp)))));
     HIP_LAUNCH_CHECK_KS();
     prof_end(L, "ks_row_moddown", ev, 8.0 * (double)L.ctx->N * lv * (6.0 + nbases) * kb.nb);
+}
+
+void launch_ks_inner_repack(const Launch &L, const KsBatch &kb, const double *key, int lv) {
+    KsArgs a = ks_args(L.ctx, lv, kb);
+    const dim3 grid((unsigned)((L.ctx->N + 255) / 256), (unsigned)(lv + L.ctx->K), (unsigned)kb.nb);
+    hipEvent_t ev;
+    prof_begin(L, "ks_inner_repack", &ev);
+    k_ks_inner_repack<<<grid, 256, 0, L.st>>>(a, key, kb.ext, kb.acc);
+    HIP_LAUNCH_CHECK_KS();
+    // per entry: ext or the two input limbs, the accumulators and the key residues
+    prof_end(L, "ks_inner_repack", ev, 8.0 * (double)L.ctx->N * (lv + L.ctx->K) * (a.beta + 2.0 + 2.0 * a.beta) * kb.nb);
 }
 
 }  // namespace pfx

@@ -71,6 +71,19 @@ __device__ __forceinline__ uint32_t galois_src(uint32_t j, int logn, uint32_t g)
     return __brev((e2 - 1u) >> 1) >> (32 - logn);
 }
 
+// Product with the monomial X^k in the NTT domain: slot j holds a(psi^e),
+// e = 2 bitrev(j) + 1, so (X^k a)[j] = psi^(k e) a[j].  The exponent is taken
+// mod 2N; psi^E comes from the bit-reversed table (tw[bitrev(E)] = psi^E for
+// E < N) and is negated for E >= N (psi^N = -1).
+__device__ __forceinline__ double monomial_mul(double x, uint32_t j, uint32_t k, int logn, const PrimeDev &P) {
+    const uint32_t N = 1u << logn;
+    const uint32_t ej = 2u * (__brev(j) >> (32 - logn)) + 1u;
+    const uint32_t E = (uint32_t)(((uint64_t)k * ej) & (2ull * N - 1));
+    const double2 w = P.tw[__brev(E & (N - 1)) >> (32 - logn)];
+    const double r = mmulc(x, w.x, w.y, P.q);
+    return (E >= N && r != 0.0) ? P.q - r : r;
+}
+
 // Arithmetic inside a transform is signed and lazy: a twiddle product returns
 // a representative in [-q, q] (mmulc_lazy), sums and differences are left
 // unreduced, and every value is brought back to [-q/2, q/2] (mred_signed) after

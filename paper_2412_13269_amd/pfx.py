@@ -134,6 +134,8 @@ _SIGS = {
     "pfx_apply_galois_batch": (_i32, [_vp, _VPP, _sz, _vp, _VPP, _vp]),
     "pfx_mul_monomial": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "pfx_mul_inv_n": (_i32, [_vp, _vp, _vp, _vp]),
+    "pfx_repack": (_i32, [_vp, _VPP, _sz, _VPP, _sz, _VPP, _vp]),
+    "pfx_pfe_repack": (_i32, [_vp, _VPP, _sz, _vp, _sz, _VPP, _sz, _VPP, _vp]),
     "pfx_rotate": (_i32, [_vp, _vp, _i32, _VPP, _sz, _vp, _vp]),
     "pfx_conjugate": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp]),
     "pfx_rotate_sum": (_i32, [_vp, _vp, _u32, _VPP, _sz, _vp, _vp]),
@@ -470,6 +472,22 @@ def pfx_mul_monomial(ctx, a, k: int, out, stream=None):
 
 def pfx_mul_inv_n(ctx, a, out, stream=None):
     _check(_lib.pfx_mul_inv_n(ctx, a, out, _stream(stream)))
+
+
+def pfx_repack(ctx, cts, gks, outs, stream=None):
+    n = len(cts)
+    arr = (ctypes.c_void_p * max(1, n))(*cts)
+    O = (ctypes.c_void_p * max(1, len(outs)))(*outs)
+    K, nk = _keys(gks)
+    _check(_lib.pfx_repack(ctx, arr, n, K, nk, O, _stream(stream)))
+
+
+def pfx_pfe_repack(ctx, tables, d_exps: int, n: int, gks, outs, stream=None):
+    """d_exps: device pointer to n * len(tables) int64 exponents (row-major by record)."""
+    T = (ctypes.c_void_p * max(1, len(tables)))(*tables)
+    O = (ctypes.c_void_p * max(1, len(outs)))(*outs)
+    K, nk = _keys(gks)
+    _check(_lib.pfx_pfe_repack(ctx, T, len(tables), d_exps, n, K, nk, O, _stream(stream)))
 
 
 def pfx_rotate(ctx, a, step: int, keys, out, stream=None):

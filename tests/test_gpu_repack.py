@@ -1,0 +1,254 @@
+"""GPU: the lookup-table evaluation, score aggregation and ring repacking
+(Sec. 3.4, Sec. 4.2, Sec. 3.2, Alg. 1) against the oracle word for word --
+as an op list (pfx_run_circuit, eager and graph), pfx_repack and
+pfx_pfe_repack -- their building blocks (monomial product, N^-1 product,
+batched automorphism) against the oracle and against single calls, and at the
+full size (16 groups of 4096 records, 16 tables) the decrypted packed scores
+against the tables themselves."""
+import numpy as np
+import pytest
+
+from oracle import ckks as O
+from oracle import repack as R
+from paper_2412_13269_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+DELTA = 2.0 ** 40
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_2412_13269_amd import pfx
+    return pfx
+
+
+class Ring:
+    """Oracle and library twins at N = 2^12 with the given chain (alpha = 1)."""
+
+    def __init__(self, X, q_bits, seed):
+        self.X = X
+        self.P = O.Params(12, q_bits, [50], alpha=1, mod_log2=0)
+        self.ctx = X.pfx_ctx_create(X.make_params(12, q_bits, [50], 1, 0), 0)
+        q, p, _ = X.pfx_ctx_moduli(self.ctx, self.P.L, 1)
+        assert [int(v) for v in q] == self.P.q and [int(v) for v in p] == self.P.p
+        self.N = self.P.N
+        self.s = I.ternary_secret(self.N, None, seed)
+        self.sk = X.pfx_sk_create(self.ctx, self.s)
+        self.seed = seed * 100
+        self.handles, self.keys = [], []
+        self.ko, self.kx = {}, {}
+
+    def next(self):
+        self.seed += 3
+        return self.seed
+
+    def key(self, g):
+        if g not in self.kx:
+            ext = self.P.ext_mods(self.P.L)
+            a = I.uniform_residues(ext, self.N, self.next(), lead=(self.P.beta,))
+            e = I.gaussian_error((self.P.beta, self.N), self.next())
+            self.ko[g] = O.galois_key(self.P, self.s, g, a, e)
+            self.kx[g] = self.X.pfx_swk_create(self.ctx, self.sk, g, a, e)
+            self.keys.append(self.kx[g])
+        return self.ko[g], self.kx[g]
+
+    def enc(self, coeffs, lv=None):
+        lv = lv or self.P.L
+        m = O.from_ints(np.asarray(coeffs, dtype=np.int64), self.P.mods(lv))
+        a = I.uniform_residues(self.P.mods(lv), self.N, self.next())
+        e = I.gaussian_error(self.N, self.next())
+        co = O.encrypt(self.P, self.s, m, a, e, DELTA)
+        pt = self.X.pfx_pt_import(self.ctx, m, DELTA)
+        cx = self.ct()
+        self.X.pfx_encrypt(self.ctx, self.sk, pt, a, e, cx)
+        self.X.pfx_ct_destroy(pt)
+        return co, cx
+
+    def ct(self):
+        h = self.X.pfx_ct_create(self.ctx, self.P.L, 1)
+        self.handles.append(h)
+        return h
+
+    def words(self, cx):
+        return self.X.pfx_ct_export(self.ctx, cx, self.N)
+
+    def close(self):
+        for h in self.handles:
+            self.X.pfx_ct_destroy(h)
+        for k in self.keys:
+            self.X.pfx_swk_destroy(k)
+        self.X.pfx_sk_destroy(self.sk)
+        self.X.pfx_ctx_destroy(self.ctx)
+
+
+@pytest.fixture(scope="module")
+def ring3(X):
+    r = Ring(X, [50, 50, 50], 5)
+    yield r
+    r.close()
+
+
+@pytest.fixture(scope="module")
+def ring1(X):
+    r = Ring(X, [50], 7)
+    yield r
+    r.close()
+
+
+def test_monomial_and_inverse_n_match_oracle(ring3, X):
+    P = ring3.P
+    rng = np.random.default_rng(1)
+    co, cx = ring3.enc(rng.integers(-2 ** 39, 2 ** 39, size=P.N))
+    out = ring3.ct()
+    for k in (0, 1, 5, P.N - 1, P.N, P.N + 3, 2 * P.N - 1, -1, 3 * P.N + 2):
+        X.pfx_mul_monomial(ring3.ctx, cx, k, out)
+        assert np.array_equal(ring3.words(out), R.ct_monomial(P, co, k).c), k
+    X.pfx_mul_inv_n(ring3.ctx, cx, out)
+    assert np.array_equal(ring3.words(out), R.ct_mul_inv_n(P, co).c)
+    X.pfx_mul_monomial(ring3.ctx, out, 7, out)                        # in place
+    assert np.array_equal(ring3.words(out), R.ct_monomial(P, R.ct_mul_inv_n(P, co), 7).c)
+
+
+def test_galois_batch_equals_single_calls(ring3, X):
+    P = ring3.P
+    g = 2 * P.N - 1
+    ko, kx = ring3.key(g)
+    rng = np.random.default_rng(2)
+    cts = [ring3.enc(rng.integers(-2 ** 39, 2 ** 39, size=P.N), lv=3 if i % 3 else 2) for i in range(10)]
+    outs = [ring3.ct() for _ in cts]
+    X.pfx_apply_galois_batch(ring3.ctx, [c[1] for c in cts], kx, outs)
+    one = ring3.ct()
+    for (co, cx), o in zip(cts, outs):
+        X.pfx_apply_galois(ring3.ctx, cx, kx, one)
+        assert np.array_equal(ring3.words(o), ring3.words(one))
+    assert np.array_equal(ring3.words(outs[0]), O.apply_galois(P, cts[0][0], g, ko).c)
+    with pytest.raises(X.PfxError) as e:             # an output aliasing another entry's input
+        X.pfx_apply_galois_batch(ring3.ctx, [cts[0][1], cts[1][1]], kx, [outs[0], cts[0][1]])
+    assert e.value.status == X.PFX_EINVAL
+
+
+def _run_plan(ring, plan, U, graph=False):
+    from paper_2412_13269_amd.repack import repack_keys_needed
+    X = ring.X
+    gks = [ring.key(g)[1] for g in repack_keys_needed(12)]
+    regs = [U] + [X.pfx_ct_create(ring.ctx, ring.P.L, 1) for _ in range(plan.n_regs - 1)]
+    stream = X.pfx_stream_create(ring.ctx)
+    try:
+        X.pfx_run_circuit(ring.ctx, plan.ops, regs, 1, [], None, gks, X.RUN_GRAPH if graph else X.RUN_EAGER, stream)
+        X.pfx_sync(ring.ctx, stream)
+        return ring.words(regs[plan.out]), X.pfx_ct_info(regs[plan.out]).scale
+    finally:
+        for h in regs[1:]:
+            X.pfx_ct_destroy(h)
+        X.pfx_stream_destroy(ring.ctx, stream)
+
+
+def _gks(ring):
+    from paper_2412_13269_amd.repack import repack_keys_needed
+    return [ring.key(g)[1] for g in repack_keys_needed(12)]
+
+
+@pytest.fixture(scope="module")
+def lookup16(ring1):
+    """16 lookups of one encrypted table and the oracle's repacking of them."""
+    P = ring1.P
+    f = I.uniform_slots(P.N, 3)
+    points = np.random.default_rng(4).integers(0, P.N, size=16)
+    co, cx = ring1.enc(R.lut_poly(f, DELTA))
+    _gks(ring1)
+    want = R.repack(P, R.evaluate(P, co, points), ring1.ko)
+    return dict(f=f, points=points, U=(co, cx), want=want)
+
+
+def test_lookup_plan_matches_oracle(ring1, lookup16, X):
+    from paper_2412_13269_amd.repack import RepackPlan
+    P, L16 = ring1.P, lookup16
+    plan = RepackPlan(12, 16, points=list(L16["points"]))
+    words, scale = _run_plan(ring1, plan, L16["U"][1])
+    assert np.array_equal(words, L16["want"].c)
+    assert scale == L16["want"].scale
+    got = R.packed_values(P, ring1.s, O.Ct(words, scale), P.N)
+    assert np.max(np.abs(got[:16] - L16["f"][L16["points"]])) < 2 ** -15
+    assert np.max(np.abs(got[16:])) < 2 ** -15
+    words_g, _ = _run_plan(ring1, plan, L16["U"][1], graph=True)     # captured as a HIP graph: same words
+    assert np.array_equal(words_g, words)
+
+
+def test_repack_entry_matches_oracle(ring1, lookup16, X):
+    L16 = lookup16
+    ins = [ring1.ct() for _ in L16["points"]]
+    for h, k in zip(ins, L16["points"]):
+        X.pfx_mul_monomial(ring1.ctx, L16["U"][1], int(k), h)
+    out = ring1.ct()
+    X.pfx_repack(ring1.ctx, ins, _gks(ring1), [out])
+    assert np.array_equal(ring1.words(out), L16["want"].c)
+    assert X.pfx_ct_info(out).scale == L16["want"].scale
+    with pytest.raises(X.PfxError) as e:                         # the output may not alias an input
+        X.pfx_repack(ring1.ctx, ins, _gks(ring1), [ins[3]])
+    assert e.value.status == X.PFX_EINVAL
+    with pytest.raises(X.PfxError) as e:                         # a missing Galois key
+        X.pfx_repack(ring1.ctx, ins, _gks(ring1)[:-1], [out])
+    assert e.value.status == X.PFX_ENOKEY
+
+
+def _pfe(ring, tables, exps, n_out):
+    X = ring.X
+    d = X.pfx_dev_alloc(ring.ctx, exps.nbytes)
+    try:
+        X.pfx_memcpy_htod(ring.ctx, d, exps)
+        outs = [ring.ct() for _ in range(n_out)]
+        X.pfx_pfe_repack(ring.ctx, [t[1] for t in tables], d, exps.shape[0], _gks(ring), outs)
+        X.pfx_sync(ring.ctx)
+        return outs
+    finally:
+        X.pfx_dev_free(ring.ctx, d)
+
+
+def test_pfe_repack_two_groups_match_oracle(ring1, X):
+    # 3 tables, 4106 records: a full group and a zero-padded one; exponents
+    # include negative ones and ones beyond N (taken mod 2N)
+    P = ring1.P
+    fs = [I.uniform_slots(P.N, 70 + l) for l in range(3)]
+    tables = [ring1.enc(R.lut_poly(f, DELTA)) for f in fs]
+    rng = np.random.default_rng(71)
+    exps = rng.integers(0, P.N, size=(P.N + 10, 3)).astype(np.int64)
+    exps[:8, 0] = [-1, -P.N, P.N, P.N + 5, 2 * P.N - 1, 3 * P.N, -3 * P.N - 7, 0]
+    outs = _pfe(ring1, tables, exps, 2)
+    want = R.repack_groups(P, R.score_records(P, [t[0] for t in tables], exps), ring1.ko)
+    for o, w in zip(outs, want):
+        assert np.array_equal(ring1.words(o), w.c)
+        assert X.pfx_ct_info(o).scale == w.scale
+    # rows whose exponents all lie in [0, N) read the tables at those points
+    got = np.concatenate([R.packed_values(P, ring1.s, O.Ct(ring1.words(o), DELTA), P.N) for o in outs])
+    ok = np.all((exps >= 0) & (exps < P.N), axis=1)
+    score = sum(f[np.clip(exps[:, l], 0, P.N - 1)] for l, f in enumerate(fs))
+    assert np.max(np.abs(got[:len(exps)][ok] - score[ok])) < 2 ** -14
+    assert np.max(np.abs(got[len(exps):])) < 2 ** -14
+
+
+def test_pfe_repack_full_size_scores(ring1, X):
+    # 16 groups of 4096 records and 16 tables, every record's packed score
+    # against the sum of the tables at its points (decrypted)
+    P = ring1.P
+    m, G = 16, 16
+    fs = [I.uniform_slots(P.N, 90 + l) for l in range(m)]
+    tables = [ring1.enc(R.lut_poly(f, DELTA)) for f in fs]
+    exps = np.random.default_rng(91).integers(0, P.N, size=(G * P.N, m)).astype(np.int64)
+    outs = _pfe(ring1, tables, exps, G)
+    got = np.concatenate([R.packed_values(P, ring1.s, O.Ct(ring1.words(o), DELTA), P.N) for o in outs])
+    score = sum(f[exps[:, l]] for l, f in enumerate(fs))
+    assert np.max(np.abs(got - score)) < 2 ** -12
+
+
+def test_full_ring_of_lookups(ring1, X):
+    # 4096 points, 4095 automorphisms as an op list: the packed coefficients are the table at the points
+    from paper_2412_13269_amd.repack import RepackPlan
+    P = ring1.P
+    f = I.uniform_slots(P.N, 5)
+    points = np.random.default_rng(6).integers(0, P.N, size=P.N)
+    plan = RepackPlan(12, P.N, points=list(points))
+    assert plan.key_switches == P.N - 1
+    words, scale = _run_plan(ring1, plan, ring1.enc(R.lut_poly(f, DELTA))[1])
+    got = R.packed_values(P, ring1.s, O.Ct(words, scale), P.N)
+    assert np.max(np.abs(got - f[points])) < 2 ** -12

@@ -108,3 +108,15 @@ def test_repack_with_wrong_sign_inside_the_automorphism_is_caught(monkeypatch):
         _expect_fail(TR.test_repack_decrypts_to_the_constant_coefficients, 32)
     finally:
         monkeypatch.setattr(O, "ct_sub", orig_sub)
+
+
+def test_score_with_reversed_exponent_is_caught(monkeypatch):
+    orig = RP.ct_monomial
+    monkeypatch.setattr(RP, "ct_monomial", lambda P, x, k: orig(P, x, -k))
+    _expect_fail(TR.test_score_constant_coefficient_is_the_sum_of_the_tables_at_the_points)
+
+
+def test_grouped_repack_dropping_the_tail_group_is_caught(monkeypatch):
+    monkeypatch.setattr(RP, "repack_groups",
+                        lambda P, cts, gks: [RP.repack(P, cts[g:g + P.N], gks) for g in range(0, len(cts) - P.N + 1, P.N)])
+    _expect_fail(TR.test_grouped_repack_packs_each_group)

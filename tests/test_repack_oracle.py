@@ -86,6 +86,34 @@ def test_lookup_then_repack_gives_the_table_at_the_points():
     assert np.max(np.abs(got - f[points])) < 2 ** -16
 
 
+def test_score_constant_coefficient_is_the_sum_of_the_tables_at_the_points():
+    # Sec. 4.2: record r = sum_l X^(k_rl) Enc(u_(f_l)) has f_0(k_r0) + ... in coefficient 0
+    P = params()
+    s = I.ternary_secret(P.N, None, 41)
+    fs = [I.uniform_slots(P.N, 42 + l) for l in range(3)]
+    Us = [enc_poly(P, s, R.lut_poly(f, DELTA), 50 + 2 * l) for l, f in enumerate(fs)]
+    exps = np.random.default_rng(43).integers(0, P.N, size=(6, 3))
+    for row, ct in zip(exps, R.score_records(P, Us, exps)):
+        got = R.packed_values(P, s, ct, 1)[0]
+        assert abs(got - sum(f[k] for f, k in zip(fs, row))) < 2 ** -18, row
+
+
+def test_grouped_repack_packs_each_group():
+    # two groups at N = 32: 40 records -> 32 + 8 (zero padded)
+    P = params()
+    s = I.ternary_secret(P.N, None, 61)
+    gks = keys(P, s, 700)
+    f = I.uniform_slots(P.N, 62)
+    U = enc_poly(P, s, R.lut_poly(f, DELTA), 63)
+    exps = np.random.default_rng(64).integers(0, P.N, size=(40, 1))
+    outs = R.repack_groups(P, R.score_records(P, [U], exps), gks)
+    assert len(outs) == 2
+    got = np.concatenate([R.packed_values(P, s, o, P.N) for o in outs])
+    want = np.zeros(2 * P.N)
+    want[:40] = f[exps[:, 0]]
+    assert np.max(np.abs(got - want)) < 2 ** -16
+
+
 # ---- the library's op list (paper_2412_13269_amd/repack.py), run on plaintexts
 def _run_plan_on_plaintexts(plan, inputs, q, N):
     """Registers hold integer polynomials mod q; the automorphism is the exact
