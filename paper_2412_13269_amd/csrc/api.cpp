@@ -1741,18 +1741,26 @@ int repack_chunk(const pfx_ctx *c) {
     return (int)std::max<size_t>(1, std::min<size_t>(4096, ((size_t)512 << 20) / per));
 }
 
+// Entries per launch of the fused repacking key switch and its scratch (one
+// limb per entry: 256 MiB at N = 2^12).
+constexpr int kFusedChunk = 8192;
+size_t repack_scratch_doubles(const pfx_ctx *c, int lv) {
+    return repack_fused_ok(c, lv) ? (size_t)kFusedChunk * c->N : 0;
+}
+
 // Alg. 1 over G groups of N ciphertexts (2 polynomials of lv limbs each, cs =
 // 2 lv N doubles apart) already multiplied by N^-1 in A (group stride N cs);
 // B holds N/2 ciphertexts per group.  Round i reads one array and writes the
 // other; the result of group g is slot 0 of group g of *res (group stride
-// *res_gs).
-pfx_status repack_rounds(pfx_ctx *c, const Launch &L, double *A, double *B, int G, int lv,
+// *res_gs).  scr: repack_scratch_doubles(c, lv) doubles.
+pfx_status repack_rounds(pfx_ctx *c, const Launch &L, double *A, double *B, double *scr, int G, int lv,
                          const pfx_swk *const *gks, size_t n_gks, const double **res, size_t *res_gs) {
     const size_t N = c->N, cs = 2 * (size_t)lv * N;
     const double *in = A;
     double *out = B;
     size_t in_gs = N * cs, out_gs = (N / 2) * cs;
-    const int chunk = repack_chunk(c);
+    const bool fused = repack_fused_ok(c, lv);
+    const int chunk = fused ? kFusedChunk : repack_chunk(c);
     for (int i = 0; i < c->logn; ++i) {
         const int tlog = c->logn - 1 - i;
         const uint32_t g = repack_galois(c, i);
@@ -1762,8 +1770,10 @@ pfx_status repack_rounds(pfx_ctx *c, const Launch &L, double *A, double *B, int 
         for (int e0 = 0; e0 < total; e0 += chunk) {
             KsBatch kb;
             const int nb = std::min(chunk, total - e0);
-            pfx_status r = get_batch_ws(c, L.st, nb, kb);
-            if (r) return r;
+            if (!fused) {
+                pfx_status r = get_batch_ws(c, L.st, nb, kb);
+                if (r) return r;
+            }
             kb.nb = nb;
             kb.mode = KS_REPACK;
             kb.rp.in = in;
@@ -1775,7 +1785,8 @@ pfx_status repack_rounds(pfx_ctx *c, const Launch &L, double *A, double *B, int 
             kb.rp.tlog = tlog;
             kb.rp.e0 = e0;
             kb.rp.galois = g;
-            ks_run(L, kb, lv, gk);
+            if (fused) launch_repack_fused(L, kb, gk->d_k, scr);
+            else ks_run(L, kb, lv, gk);
         }
         double *next_out = (in == A) ? A : B;        // the array just read is free
         size_t next_gs = in_gs;
@@ -1842,9 +1853,9 @@ pfx_status pfx_repack(pfx_ctx *c, const pfx_ct *const *in, size_t n, const pfx_s
     if (r) return r;
     const size_t cs = 2 * (size_t)lv * N;
     double *A = nullptr;
-    r = get_repack_ws(c, S(stream), (size_t)G * N * cs * 3 / 2, &A);
+    r = get_repack_ws(c, S(stream), (size_t)G * N * cs * 3 / 2 + repack_scratch_doubles(c, lv), &A);
     if (r) return r;
-    double *B = A + (size_t)G * N * cs;
+    double *B = A + (size_t)G * N * cs, *scr = B + (size_t)G * (N / 2) * cs;
     Launch L{c, S(stream)};
     // N^-1 c_i into the slots (Alg. 1 pre-multiplication), zeros after the last input
     std::vector<uint64_t> ninv(lv);
@@ -1857,7 +1868,7 @@ pfx_status pfx_repack(pfx_ctx *c, const pfx_ct *const *in, size_t n, const pfx_s
                     false);
     const double *res;
     size_t res_gs;
-    r = repack_rounds(c, L, A, B, G, lv, gks, n_gks, &res, &res_gs);
+    r = repack_rounds(c, L, A, B, scr, G, lv, gks, n_gks, &res, &res_gs);
     if (r) return r;
     return repack_store(c, L.st, res, res_gs, G, lv, in[0]->scale, out);
 }
@@ -1887,20 +1898,24 @@ pfx_status pfx_pfe_repack(pfx_ctx *c, const pfx_ct *const *tables, size_t m, con
     const size_t cs = 2 * (size_t)lv * N;
     const size_t tbl = (size_t)m * cs;
     double *T = nullptr;
-    r = get_repack_ws(c, S(stream), tbl + (size_t)G * N * cs * 3 / 2, &T);
+    r = get_repack_ws(c, S(stream), tbl + (size_t)G * N * cs * 3 / 2 + repack_scratch_doubles(c, lv), &T);
     if (r) return r;
-    double *A = T + tbl, *B = A + (size_t)G * N * cs;
+    double *A = T + tbl, *B = A + (size_t)G * N * cs, *scr = B + (size_t)G * (N / 2) * cs;
     Launch L{c, S(stream)};
     // the tables side by side (contiguous polynomials), then every record's sum
     for (size_t l = 0; l < m; ++l)
         for (int u = 0; u < 2; ++u)
             HIPCHECK(hipMemcpyAsync(T + l * cs + (size_t)u * lv * N, tables[l]->poly((uint32_t)u),
                                     (size_t)lv * N * sizeof(double), hipMemcpyDeviceToDevice, L.st));
-    launch_mono_sum(L, A, cs, (size_t)lv * N, T, cs, (size_t)lv * N, (int)m, exps, (int)n, (int)((size_t)G * N), lv,
-                    true);
+    if (mono_sum_lds_ok(c, (int)m))
+        launch_mono_sum_lds(L, A, cs, (size_t)lv * N, T, cs, (size_t)lv * N, (int)m, exps, (int)n,
+                            (int)((size_t)G * N), lv, true);
+    else
+        launch_mono_sum(L, A, cs, (size_t)lv * N, T, cs, (size_t)lv * N, (int)m, exps, (int)n, (int)((size_t)G * N),
+                        lv, true);
     const double *res;
     size_t res_gs;
-    r = repack_rounds(c, L, A, B, G, lv, gks, n_gks, &res, &res_gs);
+    r = repack_rounds(c, L, A, B, scr, G, lv, gks, n_gks, &res, &res_gs);
     if (r) return r;
     return repack_store(c, L.st, res, res_gs, G, lv, tables[0]->scale, out);
 }

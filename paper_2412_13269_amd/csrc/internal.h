@@ -272,12 +272,22 @@ struct KsBatch {
 };
 void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int lv);
 void launch_ks_inner_repack(const Launch &L, const KsBatch &kb, const double *key, int lv);
+// The whole repacking key switch of an entry in one workgroup (N = 2^12, one
+// ciphertext limb, one special prime, digits of one prime: repack_fused_ok);
+// scr: kb.nb * N doubles of scratch.  Same words as ks_run in KS_REPACK mode.
+bool repack_fused_ok(const pfx_ctx *c, int lv);
+void launch_repack_fused(const Launch &L, const KsBatch &kb, const double *key, double *scr);
 // Output slot r < n_slots (2 polynomials of lv limbs, slots cs apart,
 // polynomial stride ps) = sum_l tables[l] X^(exps[r m + l]) for r < n, zero for
 // r >= n; m tables of 2 polynomials at `tables` (table stride st, polynomial
 // stride tps); exps in device memory (int64, taken mod 2N); ninv: times N^-1.
 void launch_mono_sum(const Launch &L, double *out, size_t cs, size_t ps, const double *tables, size_t st,
                      size_t tps, int m, const int64_t *exps, int n, int n_slots, int lv, bool ninv);
+// The same for 2^8 <= N <= 2^12 and at most 16 tables (mono_sum_lds_ok),
+// tables in registers and twiddles in LDS.
+bool mono_sum_lds_ok(const pfx_ctx *c, int m);
+void launch_mono_sum_lds(const Launch &L, double *out, size_t cs, size_t ps, const double *tables, size_t st,
+                         size_t tps, int m, const int64_t *exps, int n, int n_slots, int lv, bool ninv);
 // Rescale of nb ciphertexts of np polynomials at lv limbs (rescale.hip): entry
 // b reads ents[b].in and writes ents[b].out (which may equal in), polynomials
 // si / so doubles apart; scratch `last` (nb np limbs) and `tmp` (nb np (lv - 1)

@@ -379,6 +379,88 @@ __global__ __launch_bounds__(256) void k_ks_inner_repack(const KsArgs a, const d
     acc[((size_t)(E + m) << logn) + c] = mred(a1, q, qi);
 }
 
+// ---- ring repacking, fused (KS_REPACK at N = 2^12 with one ciphertext prime
+// and one special prime): one workgroup per entry runs the whole key switch
+// with the arithmetic of the step kernels above (the same words): the INTT of
+// d = phi_g(c_j - X^t c_(j+t)) over q and its scaling (step 1), the ModUp to p
+// and NTT over p (steps 2, 3), and per output polynomial u the product with
+// the key's p residue, its INTT and ModDown conversion (steps 3-5), the NTT
+// over q and (acc_q - x) P^-1 + base (step 6).  A 4096-point transform is one
+// tile of both passes; the passes exchange through one LDS buffer, and the
+// NTT_p output, read by both products, through a per-entry global slot (32
+// KiB, `scr`).  LDS: the pass tile and the buffer, 66 KiB (two groups per CU).
+template <int TH>
+__global__ __launch_bounds__(TH) void k_repack_fused(const KsArgs a, const double *__restrict__ key,
+                                                     double *__restrict__ scr) {
+    constexpr int S = 6, C = 64;                 // N = 2^12: 64 x 64 in both passes
+    constexpr int N = C << S;
+    __shared__ double lds[NttTile<TH>::lds];
+    __shared__ double buf[N];
+    const int bi = blockIdx.x;
+    if (bi >= a.nb) return;
+    const int logn = a.logn;
+    const RpPtrs rp = rp_ptrs(a.rp, bi);
+    const PrimeDev &Pq = a.primes[0], &Pp = a.primes[a.L];
+    const double q = Pq.q, p = Pp.q;
+    const uint32_t g = a.rp.galois, t = rp.t;
+    const double *lo0 = rp.lo, *hi0 = rp.hi, *lo1 = rp.lo + a.rp.ps, *hi1 = rp.hi + a.rp.ps;
+    const size_t kst = (size_t)(a.L + a.K) * N;          // key: (b, a) of digit 0, L + K limbs each
+    double *ext = scr + (size_t)bi * N;
+    auto to_buf = [&](int e, double v, int) { buf[e] = v; };
+    auto from_buf = [&](int e, int) { return buf[e]; };
+
+    // step 1: INTT over q of d, scaled by (Q'/q)^-1; step 2: ModUp to p
+    row_pass<S, true, TH>(Pq, logn, C, 0, lds,
+                          [&](int e, int) { return rp_diff(lo1, hi1, galois_src((uint32_t)e, logn, g), t, logn, Pq); },
+                          to_buf);
+    __syncthreads();
+    const double2 inv = a.mu[0].inv[0], hat = a.mu[0].hat[0][a.L];
+    col_pass<S, true, TH>(Pq, logn, C, 0, lds, from_buf, [&](int e, double v, int) {
+        const double y = mmulc(v, inv.x, inv.y, q);
+        buf[e] = mred_signed(mmulc_lazy(y, hat.x, hat.y, p), p, Pp.qinv);
+    });
+    __syncthreads();
+    // step 3: NTT over p
+    col_pass<S, false, TH>(Pp, logn, C, 0, lds, from_buf, to_buf);
+    __syncthreads();
+    row_pass<S, false, TH>(Pp, logn, C, 0, lds, from_buf, [&](int e, double v, int) { ext[e] = v; });
+    __syncthreads();
+    const double hp = a.md->half[a.L], hq = a.md->half[0];
+    const double2 piv = a.md->phat_inv[0], ph = a.md->phat[0][0], pinv = a.md->pinv[0];
+#pragma unroll 1
+    for (int u = 0; u < 2; ++u) {
+        const double *kp = key + (size_t)u * kst + (size_t)a.L * N, *kq = key + (size_t)u * kst;
+        // steps 3-5: acc_u over p = ext * key_u, its INTT with floor(P/2) and
+        // (P/p)^-1 on the last store, the conversion to q
+        row_pass<S, true, TH>(Pp, logn, C, 0, lds, [&](int e, int) { return mmul(ext[e], kp[e], p, Pp.qinv); },
+                              to_buf);
+        __syncthreads();
+        col_pass<S, true, TH>(Pp, logn, C, 0, lds, from_buf, [&](int e, double v, int) {
+            const double z = mmulc(madd(v, hp, p), piv.x, piv.y, p);
+            buf[e] = mred_signed(-hq + mmulc_lazy(z, ph.x, ph.y, q), q, Pq.qinv);
+        });
+        __syncthreads();
+        // step 6: NTT over q, then (acc_q - x) P^-1 plus c_j + X^t c_(j+t)
+        // (and phi_g(c_j - X^t c_(j+t)) for c0), combined after the transform
+        // two slots at a time (the gathers of all 16 would not fit the registers)
+        col_pass<S, false, TH>(Pq, logn, C, 0, lds, from_buf, to_buf);
+        __syncthreads();
+        row_pass<S, false, TH>(Pq, logn, C, 0, lds, from_buf, to_buf);
+        __syncthreads();
+        const double *lo = u ? lo1 : lo0, *hi = u ? hi1 : hi0;
+        double *out = rp.out + (size_t)u * a.rp.ps;
+#pragma unroll 2
+        for (int k = 0; k < N / TH; ++k) {
+            const uint32_t e = threadIdx.x + k * TH;
+            const double xa = mmul(rp_diff(lo1, hi1, galois_src(e, logn, g), t, logn, Pq), kq[e], q, Pq.qinv);
+            double xb = madd(lo[e], monomial_mul(hi[e], e, t, logn, Pq), q);
+            if (u == 0) xb = madd(xb, rp_diff(lo0, hi0, galois_src(e, logn, g), t, logn, Pq), q);
+            out[e] = madd(mmulc(msub(xa, buf[e], q), pinv.x, pinv.y, q), xb, q);
+        }
+        __syncthreads();
+    }
+}
+
 // ----------------------------------------------------------------- launchers
 // Term count of a conversion kernel: n rounded up to 1, 2, 4 or 8.
 #define PFX_SWITCH_NT(n_, CALL)                                          \
@@ -552,6 +634,22 @@ void launch_ks_inner_repack(const Launch &L, const KsBatch &kb, const double *ke
     HIP_LAUNCH_CHECK_KS();
     // per entry: ext or the two input limbs, the accumulators and the key residues
     prof_end(L, "ks_inner_repack", ev, 8.0 * (double)L.ctx->N * (lv + L.ctx->K) * (a.beta + 2.0 + 2.0 * a.beta) * kb.nb);
+}
+
+bool repack_fused_ok(const pfx_ctx *c, int lv) { return c->logn == 12 && lv == 1 && c->K == 1 && c->alpha == 1; }
+
+void launch_repack_fused(const Launch &L, const KsBatch &kb, const double *key, double *scr) {
+    KsArgs a = ks_args(L.ctx, 1, kb);
+    a.C = 64;
+    a.tiles = 1;
+    set_blocks(a, 1);
+    hipEvent_t ev;
+    prof_begin(L, "repack_fused", &ev);
+    k_repack_fused<256><<<kb.nb, 256, 0, L.st>>>(a, key, scr);
+    HIP_LAUNCH_CHECK_KS();
+    // per entry: c_j and c_(j+t) (4 limbs, read twice), the output (2 limbs),
+    // the NTT_p scratch limb written once and read twice; the key (4 limbs) once
+    prof_end(L, "repack_fused", ev, 8.0 * (double)L.ctx->N * ((8.0 + 2.0 + 3.0) * kb.nb + 4.0));
 }
 
 }  // namespace pfx

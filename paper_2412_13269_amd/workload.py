@@ -14,7 +14,9 @@ runs the step `--steps` times after one warm-up step, the command that
 rocprofv3 wraps for kernel traces and counters.  `--query` runs instead the
 private query on 2^17 records (4 blocks of 2^15, 8 attributes, degree-7 score,
 (7,7,7) sign, InnerSum), blocks interleaved on one stream, eagerly, `--steps`
-times after one warm-up run.  `--calibrate` first imports
+times after one warm-up run.  `--pfe` runs the private lookup-table
+evaluation with ring repacking (PfeWorkload) `--steps` times after one
+warm-up run.  `--calibrate` first imports
 one ciphertext five times: the library's plain word-to-double copy
 (k_u64_to_f64) of one polynomial per launch, 24 limbs = 12 MiB read and 12 MiB
 written, the reference against which HBM counters are scaled.
@@ -141,12 +143,104 @@ def query_runs(w, steps):
     return plan
 
 
+# Phase one of the paper's exploration (Sec. 3.4, Sec. 4.2, Alg. 1): ring
+# degree 2^12, one 50-bit ciphertext prime and one 50-bit special prime (the
+# shape of the paper's Set I), 16 encrypted lookup tables of 4096 entries
+# (scale 2^40), 2^19 records of 16 attributes with uniform discretised values,
+# repacked 4096 records per output ciphertext (128 groups).
+PFE_LOGN = 12
+PFE_TABLES = 16
+PFE_RECORDS = 1 << 19
+PFE_DELTA = 2.0 ** 40
+
+
+class PfeWorkload:
+    """Context, repacking keys, encrypted tables and the record matrix of the
+    lookup-table phase, all resident on the device; run() is one pass over
+    every record (pfx_pfe_repack)."""
+
+    def __init__(self, records=PFE_RECORDS, tables=PFE_TABLES, log=lambda *a: None):
+        import numpy as np
+        from . import inputs as I
+        from . import pfx as X
+        from .repack import repack_keys_needed
+        self.X = X
+        prm = X.make_params(PFE_LOGN, [50], [50], 1, 0)
+        self.ctx = ctx = X.pfx_ctx_create(prm, 0)
+        self.N = N = 1 << PFE_LOGN
+        self.records, self.m = records, tables
+        self.groups = -(-records // N)
+        q, p, _ = X.pfx_ctx_moduli(ctx, 1, 1)
+        self.st = st = X.pfx_stream_create(ctx)
+        s = I.ternary_secret(N, None, 801)
+        self.sk = X.pfx_sk_create(ctx, s)
+        log("pfe keygen ...")
+        self.gks = []
+        for i, g in enumerate(repack_keys_needed(PFE_LOGN)):
+            a, e = key_inputs(list(q) + list(p), N, 1, 810 + 2 * i)
+            self.gks.append(X.pfx_swk_create(ctx, self.sk, g, a, e))
+        self.tables = []
+        for l in range(tables):
+            f = I.uniform_slots(N, 850 + l)
+            u = np.empty(N)
+            u[0] = f[0]
+            u[1:] = -f[N - np.arange(1, N)]
+            coef = np.rint(PFE_DELTA * u).astype(np.int64)          # u_f scaled and rounded
+            words = np.stack([coef % np.int64(qi) for qi in q]).astype(np.uint64)
+            pt = X.pfx_pt_import(ctx, words, PFE_DELTA)
+            ct = X.pfx_ct_create(ctx, 1, 1)
+            X.pfx_encrypt(ctx, self.sk, pt, I.uniform_residues(q, N, 900 + 2 * l), I.gaussian_error(N, 901 + 2 * l),
+                          ct, st)
+            X.pfx_ct_destroy(pt)
+            self.tables.append(ct)
+        exps = I.rng(950).integers(0, N, size=(records, tables)).astype(np.int64)
+        self.d_exps = X.pfx_dev_alloc(ctx, exps.nbytes)
+        X.pfx_memcpy_htod(ctx, self.d_exps, exps, st)
+        self.outs = [X.pfx_ct_create(ctx, 1, 1) for _ in range(self.groups)]
+        X.pfx_sync(ctx, st)
+
+    @property
+    def key_switches(self) -> int:
+        return self.groups * (self.N - 1)
+
+    def run(self):
+        self.X.pfx_pfe_repack(self.ctx, self.tables, self.d_exps, self.records, self.gks, self.outs, self.st)
+
+    def sync(self):
+        self.X.pfx_sync(self.ctx, self.st)
+
+    def close(self):
+        X = self.X
+        for h in self.tables + self.outs:
+            X.pfx_ct_destroy(h)
+        for k in self.gks:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(self.sk)
+        X.pfx_dev_free(self.ctx, self.d_exps)
+        X.pfx_stream_destroy(self.ctx, self.st)
+        X.pfx_ctx_destroy(self.ctx)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--calibrate", action="store_true")
     ap.add_argument("--query", action="store_true")
+    ap.add_argument("--pfe", action="store_true")
     args = ap.parse_args()
+    if args.pfe:
+        import time
+        w = PfeWorkload(log=lambda *a: print(*a, flush=True))
+        w.run()
+        w.sync()
+        time.sleep(0.5)  # an idle gap that marks the end of the setup in kernel traces
+        for _ in range(args.steps):
+            w.run()
+        w.sync()
+        print(f"{args.steps} lookup-table passes done ({w.records} records, {w.key_switches} key switches each)",
+              flush=True)
+        w.close()
+        return
     w = KsWorkload(log=lambda *a: print(*a, flush=True))
     if args.query:
         plan = query_runs(w, args.steps)

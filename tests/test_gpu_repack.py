@@ -252,3 +252,39 @@ def test_full_ring_of_lookups(ring1, X):
     words, scale = _run_plan(ring1, plan, ring1.enc(R.lut_poly(f, DELTA))[1])
     got = R.packed_values(P, ring1.s, O.Ct(words, scale), P.N)
     assert np.max(np.abs(got - f[points])) < 2 ** -12
+
+
+def test_repack_entries_at_two_limbs_equal_the_op_list(ring3, X):
+    # two limbs: the step-kernel repacking (not the fused one-limb kernels),
+    # word for word against the op list of MONO, SUB, GALOIS and ADD
+    from paper_2412_13269_amd.repack import RepackPlan
+    P = ring3.P
+    rng = np.random.default_rng(81)
+    gks = _gks(ring3)
+    ins = [ring3.enc(rng.integers(-2 ** 39, 2 ** 39, size=P.N), lv=2)[1] for _ in range(20)]
+    out = ring3.ct()
+    X.pfx_repack(ring3.ctx, ins, gks, [out])
+    plan = RepackPlan(12, 20)
+    regs = ins + [X.pfx_ct_create(ring3.ctx, P.L, 1) for _ in range(plan.n_regs - plan.n_inputs)]
+    try:
+        X.pfx_run_circuit(ring3.ctx, plan.ops, regs, plan.n_inputs, [], None, gks, X.RUN_EAGER)
+        X.pfx_sync(ring3.ctx)
+        assert np.array_equal(ring3.words(out), ring3.words(regs[plan.out]))
+    finally:
+        for h in regs[plan.n_inputs:]:
+            X.pfx_ct_destroy(h)
+    # the lookup form at two limbs: records sum_l X^k_l T_l built call by call;
+    # 2 tables (the register-table kernel) and 17 (the one-pass-per-table kernel)
+    for m in (2, 17):
+        T = [ring3.enc(rng.integers(-2 ** 39, 2 ** 39, size=P.N), lv=2)[1] for _ in range(m)]
+        exps = rng.integers(-2 * P.N, 2 * P.N, size=(12, m)).astype(np.int64)
+        recs, tmp = [ring3.ct() for _ in exps], ring3.ct()
+        for h, row in zip(recs, exps):
+            X.pfx_mul_monomial(ring3.ctx, T[0], int(row[0]), h)
+            for t, k in zip(T[1:], row[1:]):
+                X.pfx_mul_monomial(ring3.ctx, t, int(k), tmp)
+                X.pfx_add(ring3.ctx, h, tmp, h)
+        want = ring3.ct()
+        X.pfx_repack(ring3.ctx, recs, gks, [want])
+        got = _pfe(ring3, [(None, t) for t in T], exps, 1)[0]
+        assert np.array_equal(ring3.words(got), ring3.words(want)), m
