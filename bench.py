@@ -18,6 +18,11 @@ device time; `traffic` is its measured HBM bytes per launch (rocprofv3
 FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy kernel) from the committed
 summary under profiles/, null if the kernel's sources changed since.  `cpu_baseline` times the CPU oracle on HMult + relin and rotation pairs
 of the same workload for about ten seconds.
+
+Beside the headline figure the line carries the private query (`query`), the
+batched and served forms (`batched`, `served`) and the lookup-table phase
+(`lookup_repack`: 2^19 records x 16 encrypted tables at N = 2^12, scores
+repacked 4096 per ciphertext, microseconds per record with its own roofline).
 """
 from __future__ import annotations
 
@@ -45,16 +50,17 @@ def log(*a):
 
 # sources that define a profiled kernel (their hash ties a committed counter
 # measurement to the code it was taken on)
-_KERNEL_SOURCES = {"ks_inner": ["kernels.hip", "modarith.h", "ntt_core.h", "internal.h"]}
+_KERNEL_SOURCES = {"ks_inner": ["kernels.hip", "modarith.h", "ntt_core.h", "internal.h"],
+                   "repack_fused": ["keyswitch.hip", "modarith.h", "ntt_core.h", "internal.h"]}
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str = "n16_l24"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary (profiles/<kernel>_n16_l24_hbm_traffic.md), or None when
-    there is none or the kernel's sources have changed since it was taken."""
+    WRITE_SIZE summary (profiles/<kernel>_<workload>_hbm_traffic.md), or None
+    when there is none or the kernel's sources have changed since it was taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"{kernel}_n16_l24_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
     if kernel not in _KERNEL_SOURCES or not os.path.exists(path):
         return None
     m = re.search(r"traffic_bytes_per_launch: (\d+) kernel: (\S+) sources_sha256: ([0-9a-f]{64})", open(path).read())
@@ -281,6 +287,49 @@ def served_form(X, I, ctx, sk, q, rlk, gks, st, args):
     return out
 
 
+def pfe_form(X, args):
+    """The lookup-table phase (PfeWorkload): 2^19 records x 16 encrypted tables
+    at N = 2^12, scores repacked 4096 per ciphertext (128 groups, 2^19 - 128
+    automorphisms); one warm-up pass, then timed passes, then one profiled."""
+    from paper_2412_13269_amd.workload import PfeWorkload
+    w = PfeWorkload(log=log)
+    w.run()
+    w.sync()
+    reps = max(3, args.steps // 4)
+    a0 = time.perf_counter()
+    for _ in range(reps):
+        w.run()
+    w.sync()
+    dt = (time.perf_counter() - a0) / reps
+    X.pfx_profile_reset(w.ctx)
+    X.pfx_profile_enable(w.ctx, True)
+    w.run()
+    w.sync()
+    X.pfx_profile_enable(w.ctx, False)
+    kern = {}
+    for name in X.pfx_profile_names(w.ctx):
+        n, ms, by = X.pfx_profile_get(w.ctx, name)
+        kern[name] = {"launches": n, "ms": ms, "bytes": by}
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    d = kern[dom]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    out = {"records": w.records, "tables": w.m, "ring_degree": w.N, "groups": w.groups,
+           "key_switches": w.key_switches, "reps": reps, "ms_per_pass": 1e3 * dt,
+           "us_per_record": 1e6 * dt / w.records,
+           "paper_context_us_per_record_1thread_cpu": 888.0,
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, "n12_2p19"),
+                        "avg_launch_us": 1e3 * d["ms"] / d["launches"],
+                        "algorithmic_bytes_per_launch": d["bytes"] / d["launches"]},
+           "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
+                           "GBps": v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9} for k, v in kern.items()}}
+    log(f"lookup tables + repacking: {1e3 * dt:.2f} ms per pass of {w.records} records, "
+        f"{1e6 * dt / w.records:.4f} us/record; " +
+        ", ".join(f"{k} {v['ms']:.1f} ms" for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])))
+    w.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +490,9 @@ def main():
     # ---- served form: Poisson stream of queries through the request server
     served_out = served_form(X, I, ctx, sk, q, rlk, gks, st, args)
 
+    # ---- the lookup-table phase: private tables, score aggregation, ring repacking
+    pfe_out = pfe_form(X, args)
+
     out = {
         "metric": "key-switch (HMult+relin/rotate) ops/s at N=2^16,L=24",
         "value": ks_per_step * args.steps / elapsed,
@@ -466,6 +518,7 @@ def main():
         "query": query_out,
         "batched": batch_out,
         "served": served_out,
+        "lookup_repack": pfe_out,
         "profiled_ms_per_step": 1e3 * p_elapsed / args.steps,
         "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(1, v["launches"]),
                         "GBps": v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9} for k, v in kern.items()},

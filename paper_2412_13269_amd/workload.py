@@ -221,6 +221,23 @@ class PfeWorkload:
         X.pfx_ctx_destroy(self.ctx)
 
 
+def calibrate_copy_standalone(reps=5):
+    """The copy of KsWorkload.calibrate_copy (k_u64_to_f64 over 24 limbs of
+    N = 2^16: 12 MiB in, 12 MiB out per launch, two per import) on a context of
+    the same parameters without keys, for runs of the other workloads."""
+    from . import inputs as I
+    from . import pfx as X
+    ctx = X.pfx_ctx_create(X.make_params(LOGN, Q_BITS, P_BITS, ALPHA, MOD_LOG2), 0)
+    q, _, _ = X.pfx_ctx_moduli(ctx, len(Q_BITS), len(P_BITS))
+    words = I.uniform_residues(q, 1 << LOGN, 9, lead=(2,))
+    ct = X.pfx_ct_create(ctx, len(Q_BITS), 1)
+    for _ in range(reps):
+        X.pfx_ct_import(ctx, words, SCALE, ct)
+    X.pfx_sync(ctx)
+    X.pfx_ct_destroy(ct)
+    X.pfx_ctx_destroy(ctx)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=20)
@@ -230,6 +247,9 @@ def main():
     args = ap.parse_args()
     if args.pfe:
         import time
+        if args.calibrate:
+            calibrate_copy_standalone()
+            print("copy calibration done", flush=True)
         w = PfeWorkload(log=lambda *a: print(*a, flush=True))
         w.run()
         w.sync()
