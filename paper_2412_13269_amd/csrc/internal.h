@@ -283,7 +283,7 @@ void launch_repack_fused(const Launch &L, const KsBatch &kb, const double *key, 
 // stride tps); exps in device memory (int64, taken mod 2N); ninv: times N^-1.
 void launch_mono_sum(const Launch &L, double *out, size_t cs, size_t ps, const double *tables, size_t st,
                      size_t tps, int m, const int64_t *exps, int n, int n_slots, int lv, bool ninv);
-// The same for 2^8 <= N <= 2^12 and at most 16 tables (mono_sum_lds_ok),
+// The same for 2^9 <= N <= 2^12 and at most 16 tables (mono_sum_lds_ok),
 // tables in registers and twiddles in LDS.
 bool mono_sum_lds_ok(const pfx_ctx *c, int m);
 void launch_mono_sum_lds(const Launch &L, double *out, size_t cs, size_t ps, const double *tables, size_t st,

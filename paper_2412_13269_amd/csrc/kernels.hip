@@ -514,28 +514,33 @@ void launch_mono_sum(const Launch &L, double *out, size_t cs, size_t ps, const d
     prof_end(L, "mono_sum", ev, 16.0 * (double)N * lv * n_slots + 8.0 * (double)m * std::max(0, std::min(n, n_slots)));
 }
 
-// The same sums for 2^8 <= N <= 2^12 with the tables held in registers and
-// the twiddles in LDS: a workgroup owns 256 consecutive slots x of one limb and
-// a run of records; each thread loads T_l[x] of both polynomials for its slot
-// once (at most MT tables), and per record and table reads psi^E, E = k e_x
-// mod 2N, from an LDS copy of the limb's powers psi^0 .. psi^(N-1) in natural
-// order (negated for E >= N; 32 KiB, so four groups share a CU), so the tables
-// are read once per workgroup instead of once per record.  The products are
-// exact residues as in k_mono_sum (mmul with fl(1/q) instead of the stored
-// quotient: the same value), so are the sums (the same words).  Grid: x over the slot blocks, y over the
-// limbs, z over runs of `rpw` records.
+// The same sums for 2^9 <= N <= 2^12 with the tables held in registers and
+// the twiddles in LDS: a workgroup of 512 threads owns 512 consecutive slots x
+// of one limb and a run of records; each thread loads T_l[x] of both
+// polynomials for its slot once (at most MT tables), and per record and table
+// reads psi^E, E = k e_x mod 2N, from an LDS table of psi^0 .. psi^(2N-1) in
+// natural order (64 KiB: two groups, four waves per SIMD), so the tables are
+// read once per workgroup instead of once per record.  Products are left
+// signed in (-q, q) (the steps of mmul without the final correction) and the
+// sums reduced every seven terms; the canonical result is the residue of the
+// same integer as in k_mono_sum (the same words).  Grid: x over the slot
+// blocks, y over the limbs, z over runs of `rpw` records.
 template <int MT>
-__global__ __launch_bounds__(256) void k_mono_sum_lds(double *out, size_t cs, size_t ps, const double *tables,
+__global__ __launch_bounds__(512) void k_mono_sum_lds(double *out, size_t cs, size_t ps, const double *tables,
                                                       size_t st, size_t tps, int m, const int64_t *exps, int n,
                                                       int n_slots, int rpw, int logn, const PrimeDev *pr, bool ninv) {
-    __shared__ double tws[1 << 12];
+    __shared__ double tws[2 << 12];
     const int i = blockIdx.y;
     const PrimeDev &P = pr[i];
     const double q = P.q, qi = P.qinv;
     const uint32_t N = 1u << logn;
-    for (uint32_t j = threadIdx.x; j < N; j += blockDim.x) tws[j] = P.tw[__brev(j) >> (32 - logn)].x;
+    for (uint32_t j = threadIdx.x; j < N; j += blockDim.x) {
+        const double w = P.tw[__brev(j) >> (32 - logn)].x;   // psi^j, and psi^(N + j) = -psi^j
+        tws[j] = w;
+        tws[N + j] = q - w;
+    }
     __syncthreads();
-    const uint32_t x = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t x = blockIdx.x * 512u + threadIdx.x;
     const uint32_t ex = 2u * (__brev(x) >> (32 - logn)) + 1u;
     const uint32_t mask = 2u * N - 1u;
     double t0[MT], t1[MT];
@@ -545,6 +550,13 @@ __global__ __launch_bounds__(256) void k_mono_sum_lds(double *out, size_t cs, si
         t0[l] = l < m ? tl[0] : 0.0;
         t1[l] = l < m ? tl[tps] : 0.0;
     }
+    // a * w - c q with c = rint(fl(a w) fl(1/q)): an integer in (-q, q) (mmul before its correction)
+    auto mul_signed = [&](double a, double w) {
+        const double h = a * w;
+        const double lo = __builtin_fma(a, w, -h);
+        const double c = __builtin_rint(h * qi);
+        return __builtin_fma(-c, q, h) + lo;
+    };
     const int r0 = (int)blockIdx.z * rpw, r1 = min(r0 + rpw, n_slots);
     for (int r = r0; r < r1; ++r) {
         double *o = out + (size_t)r * cs + ((size_t)i << logn) + x;
@@ -554,36 +566,31 @@ __global__ __launch_bounds__(256) void k_mono_sum_lds(double *out, size_t cs, si
             continue;
         }
         const int64_t *ke = exps + (size_t)r * m;
-        // terms in [0, q), q < 2^50: seven of them and a reduced partial sum stay below 8q < 2^53
+        // |term| < q, partial sums reduced to [-q/2, q/2] every seven terms: below 7.5q < 2^53
         double s0 = 0.0, s1 = 0.0;
         int pend = 0;
 #pragma unroll
         for (int l = 0; l < MT; ++l) {
             if (l < m) {
-                const uint32_t E = (uint32_t)((uint64_t)ke[l] * ex) & mask;
-                const double w = tws[E & (N - 1u)];
-                double a0 = mmul(t0[l], w, q, qi), a1 = mmul(t1[l], w, q, qi);
-                if (E >= N) {
-                    a0 = a0 != 0.0 ? q - a0 : a0;
-                    a1 = a1 != 0.0 ? q - a1 : a1;
-                }
-                s0 += a0;
-                s1 += a1;
+                const uint32_t E = ((uint32_t)(uint64_t)ke[l] * ex) & mask;
+                const double w = tws[E];
+                s0 += mul_signed(t0[l], w);
+                s1 += mul_signed(t1[l], w);
                 if (++pend == 7) {
-                    s0 = mred(s0, q, qi);
-                    s1 = mred(s1, q, qi);
+                    s0 = mred_signed(s0, q, qi);
+                    s1 = mred_signed(s1, q, qi);
                     pend = 0;
                 }
             }
         }
-        s0 = mred(s0, q, qi);
-        s1 = mred(s1, q, qi);
+        s0 = mcanon(mred_signed(s0, q, qi), q);
+        s1 = mcanon(mred_signed(s1, q, qi), q);
         o[0] = ninv ? mmulc(s0, P.ninv, P.ninv_q, q) : s0;
         o[ps] = ninv ? mmulc(s1, P.ninv, P.ninv_q, q) : s1;
     }
 }
 
-bool mono_sum_lds_ok(const pfx_ctx *c, int m) { return c->logn >= 8 && c->logn <= 12 && m <= 16; }
+bool mono_sum_lds_ok(const pfx_ctx *c, int m) { return c->logn >= 9 && c->logn <= 12 && m <= 16; }
 
 void launch_mono_sum_lds(const Launch &L, double *out, size_t cs, size_t ps, const double *tables, size_t st,
                          size_t tps, int m, const int64_t *exps, int n, int n_slots, int lv, bool ninv) {
@@ -591,10 +598,10 @@ void launch_mono_sum_lds(const Launch &L, double *out, size_t cs, size_t ps, con
     const int logn = L.ctx->logn;
     const size_t N = L.ctx->N;
     const int rpw = std::max(64, (n_slots + 32767) / 32768);      // records per workgroup
-    const dim3 grid((unsigned)(N / 256), (unsigned)lv, (unsigned)((n_slots + rpw - 1) / rpw));
+    const dim3 grid((unsigned)(N / 512), (unsigned)lv, (unsigned)((n_slots + rpw - 1) / rpw));
     hipEvent_t ev;
     prof_begin(L, "mono_sum_lds", &ev);
-    k_mono_sum_lds<16><<<grid, 256, 0, L.st>>>(out, cs, ps, tables, st, tps, m, exps, n, n_slots, rpw, logn,
+    k_mono_sum_lds<16><<<grid, 512, 0, L.st>>>(out, cs, ps, tables, st, tps, m, exps, n, n_slots, rpw, logn,
                                                L.ctx->d_primes, ninv);
     HIP_LAUNCH_CHECK();
     // outputs written once, exponents read once per slot block (from cache), tables once per workgroup

@@ -388,13 +388,16 @@ __global__ __launch_bounds__(256) void k_ks_inner_repack(const KsArgs a, const d
 // over q and (acc_q - x) P^-1 + base (step 6).  A 4096-point transform is one
 // tile of both passes; the passes exchange through one LDS buffer, and the
 // NTT_p output, read by both products, through a per-entry global slot (32
-// KiB, `scr`).  LDS: the pass tile and the buffer, 66 KiB (two groups per CU).
+// KiB, `scr`).  LDS: the pass exchange area of a 4096-element tile and the
+// buffer, 66 KiB, so two groups share a CU; with 512 threads (8 elements per
+// thread and register round, half the registers of 256) that is four waves
+// per SIMD.
 template <int TH>
 __global__ __launch_bounds__(TH) void k_repack_fused(const KsArgs a, const double *__restrict__ key,
                                                      double *__restrict__ scr) {
     constexpr int S = 6, C = 64;                 // N = 2^12: 64 x 64 in both passes
     constexpr int N = C << S;
-    __shared__ double lds[NttTile<TH>::lds];
+    __shared__ double lds[NttTile<N / kSlots>::lds];   // exchange area of one N-element tile
     __shared__ double buf[N];
     const int bi = blockIdx.x;
     if (bi >= a.nb) return;
@@ -442,7 +445,8 @@ __global__ __launch_bounds__(TH) void k_repack_fused(const KsArgs a, const doubl
         __syncthreads();
         // step 6: NTT over q, then (acc_q - x) P^-1 plus c_j + X^t c_(j+t)
         // (and phi_g(c_j - X^t c_(j+t)) for c0), combined after the transform
-        // two slots at a time (the gathers of all 16 would not fit the registers)
+        // two slots at a time (every slot's gathered operands at once would not
+        // fit the registers)
         col_pass<S, false, TH>(Pq, logn, C, 0, lds, from_buf, to_buf);
         __syncthreads();
         row_pass<S, false, TH>(Pq, logn, C, 0, lds, from_buf, to_buf);
@@ -645,7 +649,7 @@ void launch_repack_fused(const Launch &L, const KsBatch &kb, const double *key, 
     set_blocks(a, 1);
     hipEvent_t ev;
     prof_begin(L, "repack_fused", &ev);
-    k_repack_fused<256><<<kb.nb, 256, 0, L.st>>>(a, key, scr);
+    k_repack_fused<512><<<kb.nb, 512, 0, L.st>>>(a, key, scr);
     HIP_LAUNCH_CHECK_KS();
     // per entry: c_j and c_(j+t) (4 limbs, read twice), the output (2 limbs),
     // the NTT_p scratch limb written once and read twice; the key (4 limbs) once
