@@ -288,3 +288,56 @@ def test_repack_entries_at_two_limbs_equal_the_op_list(ring3, X):
         X.pfx_repack(ring3.ctx, recs, gks, [want])
         got = _pfe(ring3, [(None, t) for t in T], exps, 1)[0]
         assert np.array_equal(ring3.words(got), ring3.words(want)), m
+
+
+def _plan_words(ring, cts, points=None):
+    """RepackPlan of the given inputs through pfx_run_circuit (one group)."""
+    from paper_2412_13269_amd.repack import RepackPlan
+    X = ring.X
+    plan = RepackPlan(12, len(points) if points is not None else len(cts), points=points)
+    regs = list(cts) + [X.pfx_ct_create(ring.ctx, ring.P.L, 1) for _ in range(plan.n_regs - plan.n_inputs)]
+    try:
+        X.pfx_run_circuit(ring.ctx, plan.ops, regs, plan.n_inputs, [], None, _gks(ring), X.RUN_EAGER)
+        X.pfx_sync(ring.ctx)
+        return ring.words(regs[plan.out])
+    finally:
+        for h in regs[plan.n_inputs:]:
+            X.pfx_ct_destroy(h)
+
+
+@pytest.mark.parametrize("n", [1, 4096, 4097])
+def test_repack_group_edges_equal_the_op_list(ring1, X, n):
+    # one input, exactly one full group, a full group plus a group of one (one
+    # special prime: zero pairs switch to zero, so the op list's skipped pairs
+    # give the same words)
+    P = ring1.P
+    rng = np.random.default_rng(100 + n)
+    U = ring1.enc(rng.integers(-2 ** 39, 2 ** 39, size=P.N))[1]
+    ins = [ring1.ct() for _ in range(n)]
+    for h, k in zip(ins, rng.integers(-2 * P.N, 2 * P.N, size=n)):
+        X.pfx_mul_monomial(ring1.ctx, U, int(k), h)
+    outs = [ring1.ct() for _ in range(-(-n // P.N))]
+    X.pfx_repack(ring1.ctx, ins, _gks(ring1), outs)
+    for g, o in enumerate(outs):
+        assert np.array_equal(ring1.words(o), _plan_words(ring1, ins[g * P.N:(g + 1) * P.N])), g
+
+
+def test_pfe_repack_one_table_one_record_and_errors(ring1, X):
+    P = ring1.P
+    f = I.uniform_slots(P.N, 111)
+    U = ring1.enc(R.lut_poly(f, DELTA))
+    exps = np.array([[1234]], dtype=np.int64)
+    out = _pfe(ring1, [U], exps, 1)[0]
+    assert np.array_equal(ring1.words(out), _plan_words(ring1, [U[1]], points=[1234]))
+    got = R.packed_values(P, ring1.s, O.Ct(ring1.words(out), DELTA), P.N)
+    assert abs(got[0] - f[1234]) < 2 ** -15 and np.max(np.abs(got[1:])) < 2 ** -15
+    d = X.pfx_dev_alloc(ring1.ctx, 8)
+    try:
+        with pytest.raises(X.PfxError) as e:                      # no record
+            X.pfx_pfe_repack(ring1.ctx, [U[1]], d, 0, _gks(ring1), [ring1.ct()])
+        assert e.value.status == X.PFX_EINVAL
+        with pytest.raises(X.PfxError) as e:                      # no repacking input
+            X.pfx_repack(ring1.ctx, [], _gks(ring1), [ring1.ct()])
+        assert e.value.status == X.PFX_EINVAL
+    finally:
+        X.pfx_dev_free(ring1.ctx, d)
