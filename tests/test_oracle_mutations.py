@@ -120,3 +120,23 @@ def test_grouped_repack_dropping_the_tail_group_is_caught(monkeypatch):
     monkeypatch.setattr(RP, "repack_groups",
                         lambda P, cts, gks: [RP.repack(P, cts[g:g + P.N], gks) for g in range(0, len(cts) - P.N + 1, P.N)])
     _expect_fail(TR.test_grouped_repack_packs_each_group)
+
+
+# ---- ring merging (oracle/merge.py)
+from oracle import merge as MG
+from tests import test_merge_oracle as TM
+
+
+def test_embedding_by_zero_padding_is_caught(monkeypatch):
+    def padded(a, r):
+        out = np.zeros((a.shape[0], a.shape[1] * r), dtype=a.dtype)
+        out[:, :a.shape[1]] = a
+        return out
+    monkeypatch.setattr(MG, "embed_poly", padded)
+    _expect_fail(TM.test_embedding_is_a_ring_homomorphism)
+
+
+def test_merge_without_the_input_shift_is_caught(monkeypatch):
+    orig = RP.monomial
+    monkeypatch.setattr(RP, "monomial", lambda a, k, mods, N: orig(a, 0, mods, N))
+    _expect_fail(TM.test_merge_places_coefficient_j_of_input_i_at_j_r_plus_i, 4)
