@@ -129,6 +129,13 @@ void pfx_sk_destroy(pfx_sk *sk);
  */
 pfx_status pfx_swk_create(pfx_ctx *ctx, const pfx_sk *sk, uint32_t galois, const uint64_t *a,
                           const int64_t *e, pfx_swk **out);
+/* The same with an arbitrary s_from (N integer coefficients, host): the key
+ * of ring switching (Sec. 3.3), from the secret of a smaller ring embedded in
+ * this one (s_small(X^(N/n)), coefficient j N/n = s_small[j]) to sk.  Such a
+ * key is neither a relinearisation nor a Galois key (PFX_ENOKEY there); a, e as
+ * for pfx_swk_create. */
+pfx_status pfx_swk_create_from(pfx_ctx *ctx, const pfx_sk *sk, const int8_t *s_from, const uint64_t *a,
+                               const int64_t *e, pfx_swk **out);
 /* Words [j][t][prime][coefficient], t = 0 for the b part, 1 for a. */
 pfx_status pfx_swk_export(pfx_ctx *ctx, const pfx_swk *k, uint64_t *words, size_t cap_words);
 uint32_t pfx_swk_galois(const pfx_swk *k);
@@ -270,6 +277,19 @@ pfx_status pfx_repack(pfx_ctx *ctx, const pfx_ct *const *in, size_t n, const pfx
  * one level and scale; out as for pfx_repack. */
 pfx_status pfx_pfe_repack(pfx_ctx *ctx, const pfx_ct *const *tables, size_t m, const int64_t *exps, size_t n,
                           const pfx_swk *const *gks, size_t n_gks, pfx_ct *const *out, void *stream);
+/* Ring merging and ring switching (Sec. 3.3, Sec. 4.3): n <= N/n_small
+ * degree-1 ciphertexts of one limb in the small ring (context `small`, degree
+ * n_small) -> one of one limb in the large ring (context `big`, degree N)
+ * whose plaintext has coefficient j of input i at X^(j N/n_small + i), i.e.
+ * sum_i X^i m_i(X^(N/n_small)) (missing inputs are zero).  The inputs are
+ * embedded (X -> X^(N/n_small), an encryption under the embedded small
+ * secret), shifted by X^i and summed, then key-switched to the large secret
+ * with `swk`, made by pfx_swk_create_from in `big` from the embedded small
+ * secret (PFX_ENOKEY otherwise).  Both contexts must share their first prime
+ * (PFX_EPARAM) and n_small < N.  The scale is the inputs' (PFX_ESCALE if they
+ * differ); out is a ciphertext of `big`. */
+pfx_status pfx_ring_merge(pfx_ctx *big, pfx_ctx *small, const pfx_ct *const *in, size_t n, const pfx_swk *swk,
+                          pfx_ct *out, void *stream);
 /* Rotate slots left by `step` (App. A.1); the key for 5^step mod 2N must be
  * among keys[0..n_keys) (PFX_ENOKEY otherwise). */
 pfx_status pfx_rotate(pfx_ctx *ctx, const pfx_ct *a, int32_t step, const pfx_swk *const *keys,

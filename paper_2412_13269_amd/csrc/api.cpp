@@ -826,34 +826,38 @@ void pfx_sk_destroy(pfx_sk *k) {
     delete k;
 }
 
-pfx_status pfx_swk_create(pfx_ctx *c, const pfx_sk *sk, uint32_t galois, const uint64_t *a, const int64_t *e,
-                          pfx_swk **out) {
-    REQUIRE(c && sk && a && e && out, PFX_EINVAL, "null argument");
-    REQUIRE(sk->ctx == c, PFX_EINVAL, "secret key of another context");
-    REQUIRE(galois == 0 || ((galois & 1) && galois < 2u * c->N), PFX_EINVAL, "galois must be 0 or odd < 2N");
+}  // extern "C"
+
+namespace {
+
+// Inputs of a switching key (Sec. 2.4.1): a words below their primes, errors
+// small.
+pfx_status check_swk_inputs(const pfx_ctx *c, const uint64_t *a, const int64_t *e) {
     const int NP = c->L + c->K;
-    const size_t N = c->N, limb = N;
+    const size_t N = c->N;
     for (int j = 0; j < c->beta; ++j)
         for (int m = 0; m < NP; ++m)
             for (size_t i = 0; i < N; ++i)
                 REQUIRE(a[((size_t)j * NP + m) * N + i] < c->primes[m], PFX_EINVAL, "a word not below its prime");
     for (size_t i = 0; i < (size_t)c->beta * N; ++i)
         REQUIRE(e[i] > -(1ll << 40) && e[i] < (1ll << 40), PFX_EINVAL, "error coefficient too large");
-    HIPCHECK(hipSetDevice(c->device));
-    std::unique_ptr<pfx_swk> k(new pfx_swk);
-    k->ctx = c;
-    k->galois = galois;
+    return PFX_OK;
+}
+
+// swk_j = (-a_j s + e_j + P w_j s_from, a_j) for every digit j, s_from given
+// in the NTT domain over all L + K primes (device).
+pfx_status swk_fill(pfx_ctx *c, const pfx_sk *sk, const double *sfrom, const uint64_t *a, const int64_t *e,
+                    pfx_swk *k) {
+    const int NP = c->L + c->K;
+    const size_t N = c->N, limb = N;
     HIPCHECK(hipMalloc(&k->d_k, (size_t)c->beta * 2 * NP * limb * sizeof(double)));
-    double *sfrom = nullptr, *etmp = nullptr;
+    double *etmp = nullptr;
     uint64_t *stage = nullptr;
     int64_t *edev = nullptr;
-    HIPCHECK(hipMalloc(&sfrom, (size_t)NP * limb * sizeof(double)));
     HIPCHECK(hipMalloc(&etmp, (size_t)NP * limb * sizeof(double)));
     HIPCHECK(hipMalloc(&stage, (size_t)NP * limb * sizeof(uint64_t)));
     HIPCHECK(hipMalloc(&edev, N * sizeof(int64_t)));
     Launch L{c, nullptr};
-    if (galois == 0) launch_ew(L, EW_MUL, sfrom, sk->d_s, sk->d_s, 0, 0, 0, 1, NP);
-    else launch_automorph(L, sfrom, sk->d_s, 0, 0, 1, NP, galois);
     for (int j = 0; j < c->beta; ++j) {
         double *b = k->d_k + (size_t)(2 * j) * NP * limb;
         double *aa = k->d_k + (size_t)(2 * j + 1) * NP * limb;
@@ -866,10 +870,70 @@ pfx_status pfx_swk_create(pfx_ctx *c, const pfx_sk *sk, uint32_t galois, const u
         launch_keygen_b(L, b, aa, etmp, sk->d_s, sfrom, j);
         HIPCHECK(hipStreamSynchronize(nullptr));
     }
-    (void)hipFree(sfrom);
     (void)hipFree(etmp);
     (void)hipFree(stage);
     (void)hipFree(edev);
+    return PFX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pfx_status pfx_swk_create(pfx_ctx *c, const pfx_sk *sk, uint32_t galois, const uint64_t *a, const int64_t *e,
+                          pfx_swk **out) {
+    REQUIRE(c && sk && a && e && out, PFX_EINVAL, "null argument");
+    REQUIRE(sk->ctx == c, PFX_EINVAL, "secret key of another context");
+    REQUIRE(galois == 0 || ((galois & 1) && galois < 2u * c->N), PFX_EINVAL, "galois must be 0 or odd < 2N");
+    pfx_status r = check_swk_inputs(c, a, e);
+    if (r) return r;
+    HIPCHECK(hipSetDevice(c->device));
+    const int NP = c->L + c->K;
+    std::unique_ptr<pfx_swk> k(new pfx_swk);
+    k->ctx = c;
+    k->galois = galois;
+    double *sfrom = nullptr;
+    HIPCHECK(hipMalloc(&sfrom, (size_t)NP * c->N * sizeof(double)));
+    Launch L{c, nullptr};
+    if (galois == 0) launch_ew(L, EW_MUL, sfrom, sk->d_s, sk->d_s, 0, 0, 0, 1, NP);
+    else launch_automorph(L, sfrom, sk->d_s, 0, 0, 1, NP, galois);
+    r = swk_fill(c, sk, sfrom, a, e, k.get());
+    (void)hipFree(sfrom);
+    if (r) {
+        (void)hipFree(k->d_k);
+        return r;
+    }
+    *out = k.release();
+    return PFX_OK;
+}
+
+pfx_status pfx_swk_create_from(pfx_ctx *c, const pfx_sk *sk, const int8_t *s_from, const uint64_t *a,
+                               const int64_t *e, pfx_swk **out) {
+    REQUIRE(c && sk && s_from && a && e && out, PFX_EINVAL, "null argument");
+    REQUIRE(sk->ctx == c, PFX_EINVAL, "secret key of another context");
+    pfx_status r = check_swk_inputs(c, a, e);
+    if (r) return r;
+    HIPCHECK(hipSetDevice(c->device));
+    const int NP = c->L + c->K;
+    std::unique_ptr<pfx_swk> k(new pfx_swk);
+    k->ctx = c;
+    k->galois = 0;
+    k->from_secret = true;
+    double *sfrom = nullptr;
+    int8_t *tmp = nullptr;
+    HIPCHECK(hipMalloc(&sfrom, (size_t)NP * c->N * sizeof(double)));
+    HIPCHECK(hipMalloc(&tmp, c->N));
+    HIPCHECK(hipMemcpy(tmp, s_from, c->N, hipMemcpyHostToDevice));
+    Launch L{c, nullptr};
+    launch_s8_to_rns(L, sfrom, tmp, NP);
+    launch_ntt(L, sfrom, nullptr, contiguous_map(NP, 0), false);
+    r = swk_fill(c, sk, sfrom, a, e, k.get());
+    (void)hipFree(sfrom);
+    (void)hipFree(tmp);
+    if (r) {
+        (void)hipFree(k->d_k);
+        return r;
+    }
     *out = k.release();
     return PFX_OK;
 }
@@ -1287,7 +1351,7 @@ pfx_status pfx_relinearize(pfx_ctx *c, const pfx_ct *a, const pfx_swk *rlk, pfx_
     pfx_status r = check_ct(c, a, "a");
     if (r) return r;
     REQUIRE(rlk && rlk->ctx == c, PFX_EINVAL, "bad relinearisation key");
-    REQUIRE(rlk->galois == 0, PFX_ENOKEY, "key is not a relinearisation key");
+    REQUIRE(rlk->galois == 0 && !rlk->from_secret, PFX_ENOKEY, "key is not a relinearisation key");
     REQUIRE(a->degree == 2, PFX_EINVAL, "relinearize needs a degree-2 ciphertext");
     r = check_out(out, a->n_limbs, 1);
     if (r) return r;
@@ -1311,7 +1375,7 @@ pfx_status pfx_mul_relin(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx
     r = check_ct(c, b, "b");
     if (r) return r;
     REQUIRE(rlk && rlk->ctx == c, PFX_EINVAL, "bad relinearisation key");
-    REQUIRE(rlk->galois == 0, PFX_ENOKEY, "key is not a relinearisation key");
+    REQUIRE(rlk->galois == 0 && !rlk->from_secret, PFX_ENOKEY, "key is not a relinearisation key");
     REQUIRE(a->degree == 1 && b->degree == 1, PFX_EINVAL, "mul_relin needs two degree-1 ciphertexts");
     const uint32_t lv = std::min(a->n_limbs, b->n_limbs);
     r = check_out(out, lv, 1);
@@ -1373,7 +1437,7 @@ pfx_status pfx_mul_relin_batch(pfx_ctx *c, const pfx_ct *const *a, const pfx_ct 
                                const pfx_swk *rlk, pfx_ct *const *out, void *stream) {
     REQUIRE(c && (n == 0 || (a && b && out)), PFX_EINVAL, "null argument");
     REQUIRE(rlk && rlk->ctx == c, PFX_EINVAL, "bad relinearisation key");
-    REQUIRE(rlk->galois == 0, PFX_ENOKEY, "key is not a relinearisation key");
+    REQUIRE(rlk->galois == 0 && !rlk->from_secret, PFX_ENOKEY, "key is not a relinearisation key");
     std::vector<uint32_t> lvs(n);
     for (size_t i = 0; i < n; ++i) {
         pfx_status r = check_ct(c, a[i], "a");
@@ -1419,7 +1483,7 @@ pfx_status pfx_relinearize_batch(pfx_ctx *c, const pfx_ct *const *a, size_t n, c
                                  pfx_ct *const *out, void *stream) {
     REQUIRE(c && (n == 0 || (a && out)), PFX_EINVAL, "null argument");
     REQUIRE(rlk && rlk->ctx == c, PFX_EINVAL, "bad relinearisation key");
-    REQUIRE(rlk->galois == 0, PFX_ENOKEY, "key is not a relinearisation key");
+    REQUIRE(rlk->galois == 0 && !rlk->from_secret, PFX_ENOKEY, "key is not a relinearisation key");
     for (size_t i = 0; i < n; ++i) {
         pfx_status r = check_ct(c, a[i], "a");
         if (r) return r;
@@ -1599,7 +1663,7 @@ pfx_status pfx_key_switch(pfx_ctx *c, const pfx_ct *d, const pfx_swk *k, pfx_ct 
 pfx_status pfx_apply_galois(pfx_ctx *c, const pfx_ct *a, const pfx_swk *gk, pfx_ct *out, void *stream) {
     pfx_status r = check_ct(c, a, "a");
     if (r) return r;
-    REQUIRE(gk && gk->ctx == c && gk->galois != 0, PFX_ENOKEY, "not a Galois key");
+    REQUIRE(gk && gk->ctx == c && gk->galois != 0 && !gk->from_secret, PFX_ENOKEY, "not a Galois key");
     REQUIRE(a->degree == 1, PFX_EINVAL, "automorphism needs a degree-1 ciphertext");
     r = check_out(out, a->n_limbs, 1);
     if (r) return r;
@@ -1609,7 +1673,7 @@ pfx_status pfx_apply_galois(pfx_ctx *c, const pfx_ct *a, const pfx_swk *gk, pfx_
 pfx_status pfx_apply_galois_batch(pfx_ctx *c, const pfx_ct *const *a, size_t n, const pfx_swk *gk,
                                   pfx_ct *const *out, void *stream) {
     REQUIRE(c && (n == 0 || (a && out)), PFX_EINVAL, "null argument");
-    REQUIRE(gk && gk->ctx == c && gk->galois != 0, PFX_ENOKEY, "not a Galois key");
+    REQUIRE(gk && gk->ctx == c && gk->galois != 0 && !gk->from_secret, PFX_ENOKEY, "not a Galois key");
     for (size_t i = 0; i < n; ++i) {
         pfx_status r = check_ct(c, a[i], "a");
         if (r) return r;
@@ -1918,6 +1982,55 @@ pfx_status pfx_pfe_repack(pfx_ctx *c, const pfx_ct *const *tables, size_t m, con
     r = repack_rounds(c, L, A, B, scr, G, lv, gks, n_gks, &res, &res_gs);
     if (r) return r;
     return repack_store(c, L.st, res, res_gs, G, lv, tables[0]->scale, out);
+}
+
+pfx_status pfx_ring_merge(pfx_ctx *big, pfx_ctx *small, const pfx_ct *const *in, size_t n, const pfx_swk *swk,
+                          pfx_ct *out, void *stream) {
+    REQUIRE(big && small && in && swk && out && n >= 1, PFX_EINVAL, "null argument or no input");
+    REQUIRE(small->logn < big->logn, PFX_EINVAL, "the small ring must have the smaller degree");
+    const int log_r = big->logn - small->logn;
+    REQUIRE(n <= ((size_t)1 << log_r), PFX_EINVAL, "more inputs than the ring ratio N / n");
+    REQUIRE(small->primes[0] == big->primes[0], PFX_EPARAM, "the rings do not share their first prime");
+    REQUIRE(swk->ctx == big && swk->from_secret, PFX_ENOKEY, "not a key from the embedded secret (pfx_swk_create_from)");
+    for (size_t i = 0; i < n; ++i) {
+        pfx_status r = check_ct(small, in[i], "in");
+        if (r) return r;
+        REQUIRE(in[i]->degree == 1 && in[i]->n_limbs == 1, PFX_ELEVEL, "merging needs degree-1 ciphertexts of one limb");
+        REQUIRE(in[i]->scale == in[0]->scale, PFX_ESCALE, "merging inputs at different scales");
+    }
+    pfx_status r = check_out(out, 1, 1);
+    if (r) return r;
+    REQUIRE(out->ctx == big, PFX_EINVAL, "output of another context");
+    Ws w;
+    r = get_ws(big, S(stream), w);
+    if (r) return r;
+    const size_t Ns = small->N, Nb = big->N;
+    double *stage = nullptr;                       // 2n small polynomials, then 2 large ones
+    r = get_repack_ws(big, S(stream), 2 * ((size_t)n * Ns + Nb), &stage);
+    if (r) return r;
+    double *merged = stage + 2 * (size_t)n * Ns;
+    for (size_t i = 0; i < n; ++i)
+        for (uint32_t u = 0; u < 2; ++u)
+            HIPCHECK(hipMemcpyAsync(stage + (2 * i + u) * Ns, in[i]->poly(u), Ns * sizeof(double),
+                                    hipMemcpyDeviceToDevice, S(stream)));
+    LimbMap one;
+    one.n = 1;
+    one.off[0] = 0;
+    one.pid[0] = 0;
+    // the inputs to the coefficient domain (small ring), placed in the large
+    // ring, back to the NTT domain (large ring; the shared prime)
+    Launch Ls{small, S(stream)}, Lb{big, S(stream)};
+    launch_ntt_pass(Ls, stage, nullptr, one, true, true, (int)(2 * n), Ns);
+    launch_ntt_pass(Ls, stage, nullptr, one, false, true, (int)(2 * n), Ns);
+    launch_merge_gather(Lb, merged, stage, (int)n, log_r, small->logn);
+    launch_ntt_pass(Lb, merged, nullptr, one, false, false, 2, Nb);
+    launch_ntt_pass(Lb, merged, nullptr, one, true, false, 2, Nb);
+    // ring switching: (b, 0) + SwitchKey(a) from the embedded secret to the large one
+    ks_core(big, Lb, w, ks_plain(merged + Nb, merged, nullptr), 1, swk, out->poly(0), out->poly(1));
+    out->n_limbs = 1;
+    out->degree = 1;
+    out->scale = in[0]->scale;
+    return PFX_OK;
 }
 
 pfx_status pfx_rotate(pfx_ctx *c, const pfx_ct *a, int32_t step, const pfx_swk *const *keys, size_t n, pfx_ct *out,

@@ -132,7 +132,8 @@ struct pfx_sk {
 struct pfx_swk {
     pfx_ctx *ctx;
     uint32_t galois;
-    double *d_k;          // [beta][2][L + K][N], NTT domain
+    double *d_k;               // [beta][2][L + K][N], NTT domain
+    bool from_secret = false;  // pfx_swk_create_from: neither a relinearisation nor a Galois key
 };
 
 struct pfx_ct {
@@ -285,6 +286,11 @@ void launch_mono_sum(const Launch &L, double *out, size_t cs, size_t ps, const d
                      size_t tps, int m, const int64_t *exps, int n, int n_slots, int lv, bool ninv);
 // The same for 2^9 <= N <= 2^12 and at most 16 tables (mono_sum_lds_ok),
 // tables in registers and twiddles in LDS.
+// Ring merging: out (2 polynomials of the large ring, coefficient domain, one
+// limb, N apart) from the coefficient-domain inputs at `stage` (input i,
+// polynomial u at (2i + u) n), coefficient j of input i at j r + i, r = 2^log_r;
+// zero where i >= n_in.
+void launch_merge_gather(const Launch &L, double *out, const double *stage, int n_in, int log_r, int logn_small);
 bool mono_sum_lds_ok(const pfx_ctx *c, int m);
 void launch_mono_sum_lds(const Launch &L, double *out, size_t cs, size_t ps, const double *tables, size_t st,
                          size_t tps, int m, const int64_t *exps, int n, int n_slots, int lv, bool ninv);

@@ -608,6 +608,31 @@ void launch_mono_sum_lds(const Launch &L, double *out, size_t cs, size_t ps, con
     prof_end(L, "mono_sum_lds", ev, 16.0 * (double)N * lv * n_slots + 8.0 * (double)m * std::max(0, std::min(n, n_slots)));
 }
 
+// Ring merging (Sec. 3.3, Sec. 4.3): the coefficient-domain polynomials of up
+// to r = N / n small ciphertexts (stage: input i, polynomial u at (2i + u) n)
+// placed in one of the large ring, coefficient j of input i at X^(j r + i):
+// the embedding X -> X^r of each input times X^i, summed (disjoint supports).
+// Coefficients of missing inputs (i >= n_in) are zero.  Grid: x over the N
+// coefficients, y over the two polynomials.
+__global__ void k_merge_gather(double *out, const double *stage, int n_in, int log_r, int logn_small) {
+    const int u = blockIdx.y;
+    const size_t N = (size_t)1 << (log_r + logn_small);
+    const size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    const int i = (int)(x & (((size_t)1 << log_r) - 1));
+    const size_t j = x >> log_r;
+    out[(size_t)u * N + x] = i < n_in ? stage[(((size_t)(2 * i + u)) << logn_small) + j] : 0.0;
+}
+
+void launch_merge_gather(const Launch &L, double *out, const double *stage, int n_in, int log_r, int logn_small) {
+    const size_t N = (size_t)1 << (log_r + logn_small);
+    hipEvent_t ev;
+    prof_begin(L, "merge_gather", &ev);
+    k_merge_gather<<<dim3((unsigned)((N + 255) / 256), 2), 256, 0, L.st>>>(out, stage, n_in, log_r, logn_small);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "merge_gather", ev, 16.0 * (double)N * 2);
+}
+
 // Tensor product in the NTT domain (Sec. 2.4.2): d0 = a0 b0, d1 = a0 b1 + a1 b0,
 // d2 = a1 b1; ACC adds it to what d0, d1, d2 hold.
 template <bool ACC>

@@ -136,6 +136,8 @@ _SIGS = {
     "pfx_mul_inv_n": (_i32, [_vp, _vp, _vp, _vp]),
     "pfx_repack": (_i32, [_vp, _VPP, _sz, _VPP, _sz, _VPP, _vp]),
     "pfx_pfe_repack": (_i32, [_vp, _VPP, _sz, _vp, _sz, _VPP, _sz, _VPP, _vp]),
+    "pfx_ring_merge": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp, _vp]),
+    "pfx_swk_create_from": (_i32, [_vp, _vp, _vp, _u64p, _i64p, _VPP]),
     "pfx_rotate": (_i32, [_vp, _vp, _i32, _VPP, _sz, _vp, _vp]),
     "pfx_conjugate": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp]),
     "pfx_rotate_sum": (_i32, [_vp, _vp, _u32, _VPP, _sz, _vp, _vp]),
@@ -283,6 +285,15 @@ def pfx_swk_create(ctx, sk, galois: int, a, e):
     e_, ep = _i64(e)
     h = ctypes.c_void_p()
     _check(_lib.pfx_swk_create(ctx, sk, galois, ap, ep, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_swk_create_from(ctx, sk, s_from, a, e):
+    s8 = np.ascontiguousarray(np.asarray(s_from, dtype=np.int8))
+    a_, ap = _u64(a)
+    e_, ep = _i64(e)
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_swk_create_from(ctx, sk, s8.ctypes.data_as(_vp), ap, ep, ctypes.byref(h)))
     return h.value
 
 
@@ -488,6 +499,11 @@ def pfx_pfe_repack(ctx, tables, d_exps: int, n: int, gks, outs, stream=None):
     O = (ctypes.c_void_p * max(1, len(outs)))(*outs)
     K, nk = _keys(gks)
     _check(_lib.pfx_pfe_repack(ctx, T, len(tables), d_exps, n, K, nk, O, _stream(stream)))
+
+
+def pfx_ring_merge(big, small, cts, swk, out, stream=None):
+    arr = (ctypes.c_void_p * max(1, len(cts)))(*cts)
+    _check(_lib.pfx_ring_merge(big, small, arr, len(cts), swk, out, _stream(stream)))
 
 
 def pfx_rotate(ctx, a, step: int, keys, out, stream=None):
