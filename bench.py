@@ -287,10 +287,14 @@ def served_form(X, I, ctx, sk, q, rlk, gks, st, args):
     return out
 
 
-def pfe_form(X, args):
+def pfe_form(X, args, big, big_sk, big_st):
     """The lookup-table phase (PfeWorkload): 2^19 records x 16 encrypted tables
     at N = 2^12, scores repacked 4096 per ciphertext (128 groups, 2^19 - 128
-    automorphisms); one warm-up pass, then timed passes, then one profiled."""
+    automorphisms); one warm-up pass, then timed passes, then one profiled.
+    Then the 128 packed ciphertexts are merged 16 at a time into the N = 2^16
+    ring of the main workload (`big`, same first prime) and switched to its
+    secret (Sec. 3.3): 8 ring merges, timed after one warm-up round."""
+    from paper_2412_13269_amd import inputs as I
     from paper_2412_13269_amd.workload import PfeWorkload
     w = PfeWorkload(log=log)
     w.run()
@@ -326,6 +330,36 @@ def pfe_form(X, args):
     log(f"lookup tables + repacking: {1e3 * dt:.2f} ms per pass of {w.records} records, "
         f"{1e6 * dt / w.records:.4f} us/record; " +
         ", ".join(f"{k} {v['ms']:.1f} ms" for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])))
+    # ring merging + ring switching into N = 2^16 (one limb of the big chain)
+    q, p, _ = X.pfx_ctx_moduli(big, 24, 4)
+    Nb = 1 << 16
+    r = Nb // w.N
+    s_emb = np.zeros(Nb, dtype=np.int8)
+    s_emb[::r] = w.s
+    ext = list(q) + list(p)
+    mk = X.pfx_swk_create_from(big, big_sk, s_emb, I.uniform_residues(ext, Nb, 990, lead=(6,)),
+                               I.gaussian_error((6, Nb), 991))
+    merged = [X.pfx_ct_create(big, 1, 1) for _ in range(w.groups // r)]
+
+    def merge_all():
+        for k, o in enumerate(merged):
+            X.pfx_ring_merge(big, w.ctx, w.outs[k * r:(k + 1) * r], mk, o, big_st)
+
+    merge_all()
+    X.pfx_sync(big, big_st)
+    m0 = time.perf_counter()
+    for _ in range(reps):
+        merge_all()
+    X.pfx_sync(big, big_st)
+    dm = (time.perf_counter() - m0) / reps
+    out["merge"] = {"inputs": w.groups, "outputs": len(merged), "ring_degrees": [w.N, Nb],
+                    "ms_per_merge": 1e3 * dm / len(merged), "ms_all": 1e3 * dm,
+                    "us_per_record": 1e6 * dm / w.records}
+    log(f"ring merge {w.groups} -> {len(merged)} ciphertexts at N=2^16: {1e3 * dm:.3f} ms "
+        f"({1e3 * dm / len(merged):.3f} ms per merge)")
+    for h in merged:
+        X.pfx_ct_destroy(h)
+    X.pfx_swk_destroy(mk)
     w.close()
     return out
 
@@ -491,7 +525,7 @@ def main():
     served_out = served_form(X, I, ctx, sk, q, rlk, gks, st, args)
 
     # ---- the lookup-table phase: private tables, score aggregation, ring repacking
-    pfe_out = pfe_form(X, args)
+    pfe_out = pfe_form(X, args, ctx, sk, st)
 
     out = {
         "metric": "key-switch (HMult+relin/rotate) ops/s at N=2^16,L=24",

@@ -145,8 +145,10 @@ def query_runs(w, steps):
 
 # Phase one of the paper's exploration (Sec. 3.4, Sec. 4.2, Alg. 1): ring
 # degree 2^12, one 50-bit ciphertext prime and one 50-bit special prime (the
-# shape of the paper's Set I), 16 encrypted lookup tables of 4096 entries
-# (scale 2^40), 2^19 records of 16 attributes with uniform discretised values,
+# shape of the paper's Set I; primes 1 mod 2^17, so the first one is also the
+# first prime of the N = 2^16 chain above and the outputs can be merged into
+# that ring, Sec. 3.3), 16 encrypted lookup tables of 4096 entries (scale
+# 2^40), 2^19 records of 16 attributes with uniform discretised values,
 # repacked 4096 records per output ciphertext (128 groups).
 PFE_LOGN = 12
 PFE_TABLES = 16
@@ -165,14 +167,14 @@ class PfeWorkload:
         from . import pfx as X
         from .repack import repack_keys_needed
         self.X = X
-        prm = X.make_params(PFE_LOGN, [50], [50], 1, 0)
+        prm = X.make_params(PFE_LOGN, [50], [50], 1, MOD_LOG2)
         self.ctx = ctx = X.pfx_ctx_create(prm, 0)
         self.N = N = 1 << PFE_LOGN
         self.records, self.m = records, tables
         self.groups = -(-records // N)
         q, p, _ = X.pfx_ctx_moduli(ctx, 1, 1)
         self.st = st = X.pfx_stream_create(ctx)
-        s = I.ternary_secret(N, None, 801)
+        self.s = s = I.ternary_secret(N, None, 801)
         self.sk = X.pfx_sk_create(ctx, s)
         log("pfe keygen ...")
         self.gks = []
