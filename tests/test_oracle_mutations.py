@@ -140,3 +140,19 @@ def test_merge_without_the_input_shift_is_caught(monkeypatch):
     orig = RP.monomial
     monkeypatch.setattr(RP, "monomial", lambda a, k, mods, N: orig(a, 0, mods, N))
     _expect_fail(TM.test_merge_places_coefficient_j_of_input_i_at_j_r_plus_i, 4)
+
+
+# ---- hoisted automorphisms (oracle/hoist.py)
+from tests import test_hoist_oracle as THo
+
+
+def test_hoisting_without_permuting_the_digits_is_caught(monkeypatch):
+    from oracle import hoist as HO
+    setup = THo.setup.__wrapped__()
+    orig = O.automorphism
+
+    def skip_digits(a, g, mods, logn):
+        # the digit polynomials are the calls over the extended basis
+        return a if len(mods) > setup[0].L else orig(a, g, mods, logn)
+    monkeypatch.setattr(O, "automorphism", skip_digits)
+    _expect_fail(THo.test_hoisted_rotations_decrypt_to_the_rotated_slots, setup)
