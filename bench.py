@@ -459,6 +459,33 @@ def main():
         X.pfx_sync(ctx, st)
         return 1e6 * (time.perf_counter() - a) / reps
 
+    # hoisted automorphisms (the BSGS baby steps of bootstrapping's linear
+    # transforms): the 15 rotations of the step from one ModUp, against the same
+    # 15 rotations one by one (outputs kept, so nothing is skipped)
+    hout = [X.pfx_ct_create(ctx, L, 1) for _ in ROT_STEPS]
+
+    def rot_separate():
+        for h, r in zip(hout, ROT_STEPS):
+            X.pfx_rotate(ctx, cts[0], r, gks, h, st)
+
+    def rot_hoisted():
+        X.pfx_apply_galois_hoisted(ctx, cts[0], gks, hout, st)
+
+    hoist = {}
+    for name, fn in (("separate", rot_separate), ("hoisted", rot_hoisted)):
+        fn()
+        X.pfx_sync(ctx, st)
+        h0 = time.perf_counter()
+        for _ in range(10):
+            fn()
+        X.pfx_sync(ctx, st)
+        hoist[name] = 1e3 * (time.perf_counter() - h0) / 10
+    per_op["rotations_15_separate_ms"] = hoist["separate"]
+    per_op["rotations_15_hoisted_ms"] = hoist["hoisted"]
+    log(f"15 rotations of one ciphertext: {hoist['separate']:.3f} ms one by one, {hoist['hoisted']:.3f} ms hoisted")
+    for h in hout:
+        X.pfx_ct_destroy(h)
+
     per_op["ct_import_host_us"] = host_time(lambda: X.pfx_ct_import(ctx, words, SCALE, rot, st))
     per_op["ct_export_host_us"] = host_time(lambda: X.pfx_ct_export(ctx, rot, N, st))
     per_op["ct_interchange_bytes"] = int(words.nbytes)

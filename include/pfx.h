@@ -246,6 +246,15 @@ pfx_status pfx_apply_galois(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *gk, pf
  * Outputs must be distinct and alias no input of any entry (PFX_EINVAL). */
 pfx_status pfx_apply_galois_batch(pfx_ctx *ctx, const pfx_ct *const *a, size_t n, const pfx_swk *gk,
                                   pfx_ct *const *out, void *stream);
+/* Hoisted automorphisms (the baby steps of the BSGS linear transforms, App.
+ * A.4): out[i] = phi_(g_i)(a) for the Galois elements of gks[0..n), the
+ * decomposition (ModUp) of c1 computed once and each key switch fed with its
+ * permutation; decrypts to the same messages as pfx_apply_galois (not the same
+ * words: the permuted decomposition lifts negated residues differently).
+ * Outputs must be distinct and not a (PFX_EINVAL); non-Galois keys
+ * PFX_ENOKEY. */
+pfx_status pfx_apply_galois_hoisted(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *const *gks, size_t n,
+                                    pfx_ct *const *out, void *stream);
 /* a * X^k in R_Q = Z_Q[X]/(X^N + 1) (k taken mod 2N; X^N = -1): the lookup of
  * plaintext point k in an encrypted table (Sec. 3.4) and the X^t of ring
  * repacking (Alg. 1).  Scale and level are kept; out may be a. */

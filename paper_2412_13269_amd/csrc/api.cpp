@@ -182,7 +182,8 @@ pfx_status check_out(const pfx_ct *o, uint32_t lv, uint32_t deg) {
 // bases while other workgroups write the outputs, so no output may alias a
 // permuted base (KS_GALOIS) or a product operand (KS_PRODUCT) of any entry;
 // callers copy or fall back first.
-void ks_run(const Launch &L, const KsBatch &kb, int lv, const pfx_swk *key) {
+// Steps 1-3a (ModUp into the NTT domain of every target limb) of a batch.
+void ks_modup(const Launch &L, const KsBatch &kb, int lv) {
     pfx_ctx *c = L.ctx;
     const int E = lv + c->K;
     launch_intt_scale(L, kb, lv);
@@ -202,11 +203,20 @@ void ks_run(const Launch &L, const KsBatch &kb, int lv, const pfx_swk *key) {
         }
     }
     launch_ntt_pass(L, kb.ext, nullptr, m, true, false, kb.nb, kb.sext);
-    if (kb.mode == KS_REPACK) launch_ks_inner_repack(L, kb, key->d_k, lv);
-    else launch_ks_inner(L, kb, key->d_k, lv);
+}
+
+// Steps 4-6 (ModDown and the combination with the bases) of a batch.
+void ks_moddown(const Launch &L, const KsBatch &kb, int lv) {
     launch_intt_special(L, kb, lv);
     launch_moddown_col(L, kb, lv);
     launch_row_moddown(L, kb, lv);
+}
+
+void ks_run(const Launch &L, const KsBatch &kb, int lv, const pfx_swk *key) {
+    ks_modup(L, kb, lv);
+    if (kb.mode == KS_REPACK) launch_ks_inner_repack(L, kb, key->d_k, lv);
+    else launch_ks_inner(L, kb, key->d_k, lv);
+    ks_moddown(L, kb, lv);
 }
 
 // One key switch in the stream's scratch.
@@ -1729,6 +1739,72 @@ pfx_status pfx_apply_galois_batch(pfx_ctx *c, const pfx_ct *const *a, size_t n, 
         out[i]->n_limbs = lvs[i];
         out[i]->degree = 1;
         out[i]->scale = sc[i];
+    }
+    return PFX_OK;
+}
+
+pfx_status pfx_apply_galois_hoisted(pfx_ctx *c, const pfx_ct *a, const pfx_swk *const *gks, size_t n,
+                                    pfx_ct *const *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(a->degree == 1, PFX_EINVAL, "automorphism needs a degree-1 ciphertext");
+    REQUIRE(n == 0 || (gks && out), PFX_EINVAL, "null argument");
+    {
+        std::unordered_set<const double *> outs;
+        for (size_t i = 0; i < n; ++i) {
+            REQUIRE(gks[i] && gks[i]->ctx == c && gks[i]->galois != 0 && !gks[i]->from_secret, PFX_ENOKEY,
+                    "not a Galois key");
+            r = check_out(out[i], a->n_limbs, 1);
+            if (r) return r;
+            REQUIRE(out[i]->d != a->d, PFX_EINVAL, "hoisted automorphism output aliases the input");
+            REQUIRE(outs.insert(out[i]->d).second, PFX_EINVAL, "hoisted automorphism outputs alias");
+        }
+    }
+    if (n == 0) return PFX_OK;
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    Launch L{c, S(stream)};
+    const int lv = (int)a->n_limbs;
+    const double sc = a->scale;
+    KsBatch kb;
+    r = get_batch_ws(c, L.st, (int)std::min<size_t>(n, kMaxBatch), kb);
+    if (r) return r;
+    // the decomposition of c1, once, into entry 0's ModUp scratch
+    KsBatch up = kb;
+    up.nb = 1;
+    up.mode = KS_PLAIN;
+    up.op[0] = ks_plain(a->poly(1), nullptr, nullptr);
+    ks_modup(L, up, lv);
+    for (size_t s0 = 0; s0 < n; s0 += kMaxBatch) {
+        const int nb = (int)std::min<size_t>(kMaxBatch, n - s0);
+        KsBatch g = kb;
+        g.nb = nb;
+        g.mode = KS_GALOIS;
+        for (int e = 0; e < nb; ++e) {
+            KsOperand &op = g.op[e];
+            op = KsOperand{};
+            op.mode = KS_GALOIS;
+            op.d = a->poly(1);
+            op.base0 = a->poly(0);
+            op.galois = gks[s0 + e]->galois;
+            g.out0[e] = out[s0 + e]->poly(0);
+            g.out1[e] = out[s0 + e]->poly(1);
+        }
+        for (int e = 0; e < nb; ++e) {               // one key per entry: one inner product each
+            KsBatch one = g;
+            one.nb = 1;
+            one.op[0] = g.op[e];
+            one.hoisted = true;
+            one.acc = g.acc + (size_t)e * g.sacc;
+            launch_ks_inner(L, one, gks[s0 + e]->d_k, lv);
+        }
+        ks_moddown(L, g, lv);
+    }
+    for (size_t i = 0; i < n; ++i) {
+        out[i]->n_limbs = (uint32_t)lv;
+        out[i]->degree = 1;
+        out[i]->scale = sc;
     }
     return PFX_OK;
 }

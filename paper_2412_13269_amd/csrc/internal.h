@@ -265,6 +265,7 @@ struct RepackDesc {
 };
 struct KsBatch {
     int nb = 1, mode = KS_PLAIN;      // KS_REPACK: nb is not bounded by kMaxBatch
+    bool hoisted = false;             // KS_GALOIS inner product: ext is the unpermuted (hoisted) ModUp
     RepackDesc rp;
     KsOperand op[kMaxBatch];
     double *out0[kMaxBatch] = {}, *out1[kMaxBatch] = {};

@@ -857,6 +857,7 @@ struct InnerArgs {
     double *acc;
     size_t sext, sacc;
     int nb, lv, logn, L, K, alpha;
+    int hoisted;   // KS_GALOIS: ext holds the unpermuted decomposition, read through phi_g as well
     const PrimeDev *pr;
     const double *d[kMaxBatch], *d2[kMaxBatch];
     uint32_t g[kMaxBatch];
@@ -906,7 +907,8 @@ __global__ __launch_bounds__(256) void k_ks_inner(const InnerArgs a) {
                             else if (MODE == KS_PRODUCT) x[t][b] = mmul(a.d[b][lm + c], a.d2[b][lm + c], q, qi);
                             else x[t][b] = a.d[b][lm + c];
                         } else {
-                            x[t][b] = a.ext[b * a.sext + ((size_t)j * E + tt) * N + c];
+                            const size_t cc = MODE == KS_GALOIS && a.hoisted ? galois_src((uint32_t)c, logn, a.g[b]) : c;
+                            x[t][b] = a.ext[b * a.sext + ((size_t)j * E + tt) * N + cc];
                         }
                     }
                 }
@@ -952,6 +954,7 @@ void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int 
     a.sext = kb.sext;
     a.sacc = kb.sacc;
     a.nb = kb.nb;
+    a.hoisted = kb.hoisted ? 1 : 0;
     a.lv = lv;
     a.logn = ctx->logn;
     a.L = ctx->L;

@@ -135,6 +135,7 @@ _SIGS = {
     "pfx_mul_monomial": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "pfx_mul_inv_n": (_i32, [_vp, _vp, _vp, _vp]),
     "pfx_repack": (_i32, [_vp, _VPP, _sz, _VPP, _sz, _VPP, _vp]),
+    "pfx_apply_galois_hoisted": (_i32, [_vp, _vp, _VPP, _sz, _VPP, _vp]),
     "pfx_pfe_repack": (_i32, [_vp, _VPP, _sz, _vp, _sz, _VPP, _sz, _VPP, _vp]),
     "pfx_ring_merge": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp, _vp]),
     "pfx_swk_create_from": (_i32, [_vp, _vp, _vp, _u64p, _i64p, _VPP]),
@@ -475,6 +476,13 @@ def pfx_apply_galois_batch(ctx, a, gk, outs, stream=None):
     assert len(outs) == n
     arr = lambda xs: (ctypes.c_void_p * max(1, n))(*xs)
     _check(_lib.pfx_apply_galois_batch(ctx, arr(a), n, gk, arr(outs), _stream(stream)))
+
+
+def pfx_apply_galois_hoisted(ctx, a, gks, outs, stream=None):
+    G = (ctypes.c_void_p * max(1, len(gks)))(*gks)
+    O = (ctypes.c_void_p * max(1, len(outs)))(*outs)
+    assert len(gks) == len(outs)
+    _check(_lib.pfx_apply_galois_hoisted(ctx, a, G, len(gks), O, _stream(stream)))
 
 
 def pfx_mul_monomial(ctx, a, k: int, out, stream=None):
