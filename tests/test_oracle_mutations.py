@@ -156,3 +156,13 @@ def test_hoisting_without_permuting_the_digits_is_caught(monkeypatch):
         return a if len(mods) > setup[0].L else orig(a, g, mods, logn)
     monkeypatch.setattr(O, "automorphism", skip_digits)
     _expect_fail(THo.test_hoisted_rotations_decrypt_to_the_rotated_slots, setup)
+
+
+# ---- BSGS linear transform (oracle/linear.py)
+from tests import test_linear_oracle as TL
+
+
+def test_transform_with_diagonals_rotated_forward_is_caught(monkeypatch):
+    from oracle import linear as LTm
+    monkeypatch.setattr(LTm, "giant_back", lambda P, n1, j: O.galois_element(P, n1 * j))
+    _expect_fail(TL.test_transform_is_the_matrix_vector_product, TL.setup.__wrapped__(), 4)
