@@ -480,6 +480,34 @@ def main():
             fn()
         X.pfx_sync(ctx, st)
         hoist[name] = 1e3 * (time.perf_counter() - h0) / 10
+    # a plaintext-matrix product on the slots with 16 diagonals (steps 0..15):
+    # every step a rotation (n1 = 1) against the BSGS split with 4 baby steps
+    extra = []
+    have = {X.pfx_swk_galois(k) for k in gks}
+    for stp in range(1, 16):
+        g = pow(5, stp, 2 * N)
+        if g not in have:
+            extra.append(X.pfx_swk_create(ctx, sk, g, *key_inputs(list(q) + list(p), N, beta, 5000 + 10 * stp)))
+    lt_keys = gks + extra
+    diags = [X.pfx_encode(ctx, I.uniform_slots(N // 2, 800 + k) / 16, None, L, SCALE) for k in range(16)]
+    lt_out = X.pfx_ct_create(ctx, L, 1)
+    for n1 in (1, 4):
+        def lt(n1=n1):
+            X.pfx_linear_transform(ctx, cts[0], diags, list(range(16)), n1, lt_keys, lt_out, st)
+        lt()
+        X.pfx_sync(ctx, st)
+        t0_ = time.perf_counter()
+        for _ in range(5):
+            lt()
+        X.pfx_sync(ctx, st)
+        per_op[f"linear_transform_16_diags_n1_{n1}_ms"] = 1e3 * (time.perf_counter() - t0_) / 5
+    log(f"16-diagonal slot matrix product: {per_op['linear_transform_16_diags_n1_1_ms']:.3f} ms with a rotation "
+        f"per diagonal, {per_op['linear_transform_16_diags_n1_4_ms']:.3f} ms baby-step giant-step (n1 = 4)")
+    for h in diags + [lt_out]:
+        X.pfx_ct_destroy(h)
+    for k in extra:
+        X.pfx_swk_destroy(k)
+
     per_op["rotations_15_separate_ms"] = hoist["separate"]
     per_op["rotations_15_hoisted_ms"] = hoist["hoisted"]
     log(f"15 rotations of one ciphertext: {hoist['separate']:.3f} ms one by one, {hoist['hoisted']:.3f} ms hoisted")

@@ -255,6 +255,18 @@ pfx_status pfx_apply_galois_batch(pfx_ctx *ctx, const pfx_ct *const *a, size_t n
  * PFX_ENOKEY. */
 pfx_status pfx_apply_galois_hoisted(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *const *gks, size_t n,
                                     pfx_ct *const *out, void *stream);
+/* Plaintext-matrix product on the slots by the diagonal method with the
+ * baby-step giant-step split (CoeffsToSlots / SlotsToCoeffs, App. A.4):
+ *   out = sum_k diags[k] (.) rot(a, steps[k])     (steps taken mod N/2)
+ * computed as sum_j rot(sum_{k: s_k = n1 j + i} rot(diags[k], -n1 j) (.) rot(a, i), n1 j):
+ * the distinct baby steps i != 0 as hoisted automorphisms, the diagonals
+ * rotated as plaintexts (no key), one rotation per distinct giant step j != 0.
+ * diags: n plaintexts with at least a's limbs, one scale (PFX_ESCALE);
+ * keys: Galois keys of every baby and giant step (PFX_ENOKEY).  out has a's
+ * level and the scale a.scale * diags' scale (no rescale); out != a. */
+pfx_status pfx_linear_transform(pfx_ctx *ctx, const pfx_ct *a, const pfx_pt *const *diags, const int32_t *steps,
+                                size_t n, uint32_t n1, const pfx_swk *const *keys, size_t n_keys, pfx_ct *out,
+                                void *stream);
 /* a * X^k in R_Q = Z_Q[X]/(X^N + 1) (k taken mod 2N; X^N = -1): the lookup of
  * plaintext point k in an encrypted table (Sec. 3.4) and the X^t of ring
  * repacking (Alg. 1).  Scale and level are kept; out may be a. */

@@ -2067,6 +2067,110 @@ pfx_status pfx_pfe_repack(pfx_ctx *c, const pfx_ct *const *tables, size_t m, con
     return repack_store(c, L.st, res, res_gs, G, lv, tables[0]->scale, out);
 }
 
+pfx_status pfx_linear_transform(pfx_ctx *c, const pfx_ct *a, const pfx_pt *const *diags, const int32_t *steps,
+                                size_t n, uint32_t n1, const pfx_swk *const *keys, size_t n_keys, pfx_ct *out,
+                                void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(a->degree == 1, PFX_EINVAL, "linear transform needs a degree-1 ciphertext");
+    REQUIRE(n >= 1 && diags && steps && n1 >= 1, PFX_EINVAL, "no diagonal, null argument or n1 = 0");
+    const uint32_t lv = a->n_limbs;
+    const int64_t half = c->N / 2;
+    REQUIRE(n1 <= (uint64_t)half, PFX_EINVAL, "n1 beyond the slot count");
+    for (size_t k = 0; k < n; ++k) {
+        r = check_ct(c, diags[k], "diagonal");
+        if (r) return r;
+        REQUIRE(diags[k]->degree == 0 && diags[k]->n_limbs >= lv, PFX_ELEVEL,
+                "diagonals must be plaintexts with at least the ciphertext's limbs");
+        REQUIRE(diags[k]->scale == diags[0]->scale, PFX_ESCALE, "diagonals at different scales");
+    }
+    r = check_out(out, lv, 1);
+    if (r) return r;
+    REQUIRE(out->d != a->d, PFX_EINVAL, "linear transform output aliases the input");
+    // steps = n1 j + i; the distinct baby steps i != 0 (hoisted), the distinct giant steps j
+    std::vector<int64_t> st(n);
+    std::vector<int64_t> babies, giants;
+    for (size_t k = 0; k < n; ++k) {
+        st[k] = (((int64_t)steps[k] % half) + half) % half;
+        babies.push_back(st[k] % n1);
+        giants.push_back(st[k] / n1);
+    }
+    std::sort(babies.begin(), babies.end());
+    babies.erase(std::unique(babies.begin(), babies.end()), babies.end());
+    if (!babies.empty() && babies[0] == 0) babies.erase(babies.begin());
+    std::sort(giants.begin(), giants.end());
+    giants.erase(std::unique(giants.begin(), giants.end()), giants.end());
+    std::vector<const pfx_swk *> bkeys;
+    for (int64_t i : babies) {
+        const pfx_swk *k = find_key(c, rot_element(c, i), keys, n_keys);
+        if (!k) return fail(PFX_ENOKEY, "no Galois key for baby step " + std::to_string(i));
+        bkeys.push_back(k);
+    }
+    for (int64_t j : giants)
+        if (j && !find_key(c, rot_element(c, n1 * j), keys, n_keys))
+            return fail(PFX_ENOKEY, "no Galois key for giant step " + std::to_string(n1 * j));
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    const size_t N = c->N, cs = 2 * (size_t)lv * N;
+    double *buf = nullptr;                     // baby rotations, the group sum, its rotation, a plaintext
+    r = get_repack_ws(c, S(stream), (babies.size() + 2) * cs + (size_t)lv * N, &buf);
+    if (r) return r;
+    auto view = [&](double *d, uint32_t deg, double scale) {
+        pfx_ct v;
+        v.ctx = c;
+        v.cap_limbs = v.n_limbs = lv;
+        v.cap_degree = v.degree = deg;
+        v.scale = scale;
+        v.d = d;
+        v.owns = false;
+        return v;
+    };
+    std::vector<pfx_ct> bv;
+    for (size_t b = 0; b < babies.size(); ++b) bv.push_back(view(buf + b * cs, 1, a->scale));
+    pfx_ct acc = view(buf + babies.size() * cs, 1, 0.0), rot = view(buf + (babies.size() + 1) * cs, 1, 0.0);
+    double *ptd = buf + (babies.size() + 2) * cs;
+    if (!babies.empty()) {
+        std::vector<pfx_ct *> bo;
+        for (pfx_ct &v : bv) bo.push_back(&v);
+        r = pfx_apply_galois_hoisted(c, a, bkeys.data(), bkeys.size(), bo.data(), stream);
+        if (r) return r;
+    }
+    auto baby = [&](int64_t i) -> const pfx_ct * {
+        if (i == 0) return a;
+        return &bv[std::lower_bound(babies.begin(), babies.end(), i) - babies.begin()];
+    };
+    Launch L{c, S(stream)};
+    bool first = true;
+    for (int64_t j : giants) {
+        const uint32_t g_back = rot_element(c, half - (int64_t)n1 * j);    // rot(d, -n1 j)
+        bool any = false;
+        for (size_t k = 0; k < n; ++k) {
+            if (st[k] / n1 != j) continue;
+            pfx_ct pv = view(ptd, 0, diags[k]->scale);
+            const pfx_pt *pt = diags[k];
+            if (g_back != 1) {
+                launch_automorph(L, ptd, diags[k]->d, 0, 0, 1, (int)lv, g_back);
+                pt = &pv;
+            }
+            r = any ? pfx_mul_plain_acc(c, baby(st[k] % n1), pt, &acc, stream)
+                    : pfx_mul_plain(c, baby(st[k] % n1), pt, &acc, stream);
+            if (r) return r;
+            any = true;
+        }
+        const pfx_ct *part = &acc;
+        if (j) {
+            r = pfx_rotate(c, &acc, (int32_t)(n1 * j), keys, n_keys, &rot, stream);
+            if (r) return r;
+            part = &rot;
+        }
+        r = first ? pfx_ct_copy(c, part, out, stream) : pfx_add(c, out, part, out, stream);
+        if (r) return r;
+        first = false;
+    }
+    return PFX_OK;
+}
+
 pfx_status pfx_ring_merge(pfx_ctx *big, pfx_ctx *small, const pfx_ct *const *in, size_t n, const pfx_swk *swk,
                           pfx_ct *out, void *stream) {
     REQUIRE(big && small && in && swk && out && n >= 1, PFX_EINVAL, "null argument or no input");

@@ -136,6 +136,7 @@ _SIGS = {
     "pfx_mul_inv_n": (_i32, [_vp, _vp, _vp, _vp]),
     "pfx_repack": (_i32, [_vp, _VPP, _sz, _VPP, _sz, _VPP, _vp]),
     "pfx_apply_galois_hoisted": (_i32, [_vp, _vp, _VPP, _sz, _VPP, _vp]),
+    "pfx_linear_transform": (_i32, [_vp, _vp, _VPP, _vp, _sz, _u32, _VPP, _sz, _vp, _vp]),
     "pfx_pfe_repack": (_i32, [_vp, _VPP, _sz, _vp, _sz, _VPP, _sz, _VPP, _vp]),
     "pfx_ring_merge": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp, _vp]),
     "pfx_swk_create_from": (_i32, [_vp, _vp, _vp, _u64p, _i64p, _VPP]),
@@ -483,6 +484,15 @@ def pfx_apply_galois_hoisted(ctx, a, gks, outs, stream=None):
     O = (ctypes.c_void_p * max(1, len(outs)))(*outs)
     assert len(gks) == len(outs)
     _check(_lib.pfx_apply_galois_hoisted(ctx, a, G, len(gks), O, _stream(stream)))
+
+
+def pfx_linear_transform(ctx, a, diags, steps, n1: int, keys, out, stream=None):
+    D = (ctypes.c_void_p * max(1, len(diags)))(*diags)
+    st = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
+    assert len(st) == len(diags)
+    K, nk = _keys(keys)
+    _check(_lib.pfx_linear_transform(ctx, a, D, st.ctypes.data_as(_vp), len(diags), n1, K, nk, out,
+                                     _stream(stream)))
 
 
 def pfx_mul_monomial(ctx, a, k: int, out, stream=None):

@@ -1,0 +1,75 @@
+"""GPU: the BSGS plaintext-matrix linear transform (App. A.4) against the
+oracle word for word, for two baby-step counts, at the top level and below;
+and the decrypted slots against the FP64 matrix-vector product."""
+import numpy as np
+import pytest
+
+from oracle import ckks as O
+from oracle import linear as LT
+from paper_2412_13269_amd import inputs as I
+from tests.test_gpu_parity import CONFIGS, Pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_2412_13269_amd import pfx
+    return pfx
+
+
+@pytest.fixture(scope="module", params=["c1", "c2s"])
+def pair(request, X):
+    cfg = CONFIGS[request.param]
+    p = Pair(X, cfg["logn"], cfg["qb"], cfg["pb"], cfg["alpha"], cfg["ml"], cfg["h"], seed=29, scale=cfg["scale"])
+    yield p
+    p.close()
+
+
+def _needed(P, steps, n1):
+    half = P.N // 2
+    st = [s % half for s in steps]
+    return sorted({s % n1 for s in st} - {0}) + sorted({n1 * (s // n1) for s in st} - {0})
+
+
+@pytest.mark.parametrize("n1", [4, 16])
+def test_linear_transform_matches_oracle(pair, X, n1):
+    P = pair.P
+    half = P.N // 2
+    steps = [0, 1, 2, 5, 7, 9, 13, 100, half - 1, half + 3]
+    for k in _needed(P, steps, n1):
+        pair.key(O.galois_element(P, k))
+    for lv in (P.L, max(2, P.L - 2)):       # two limbs at least: the product's scale is scale^2
+        co, cx, z = pair.enc(lv)
+        ds = [(I.uniform_slots(half, 500 + k) + 1j * I.uniform_slots(half, 600 + k)) / len(steps)
+              for k in range(len(steps))]
+        words = [O.encode(P, d, pair.scale, lv) for d in ds]
+        pts = []
+        for w in words:
+            pts.append(X.pfx_pt_import(pair.ctx, w, pair.scale))
+            pair.handles.append(pts[-1])
+        out = pair.ct(lv, deg=1)
+        X.pfx_linear_transform(pair.ctx, cx, pts, steps, n1, list(pair.kx.values()), out)
+        want = LT.linear_transform(P, co, words, pair.scale, steps, n1, pair.ko)
+        pair.same(want, out)
+        got = O.decode(P, O.decrypt(P, pair.s, O.Ct(pair.words(out), want.scale)), want.scale, half)
+        ref = sum(d * np.roll(z, -(s % half)) for d, s in zip(ds, steps))
+        assert np.max(np.abs(got - ref)) < 2 ** -15
+
+
+def test_linear_transform_checks(pair, X):
+    P = pair.P
+    co, cx, z = pair.enc(P.L)
+    w = O.encode(P, I.uniform_slots(P.N // 2, 700), pair.scale, P.L)
+    pt = X.pfx_pt_import(pair.ctx, w, pair.scale)
+    pair.handles.append(pt)
+    out = pair.ct(P.L, deg=1)
+    with pytest.raises(X.PfxError) as e:                        # no key for the step
+        X.pfx_linear_transform(pair.ctx, cx, [pt], [P.N // 2 - 77], 1, [], out)
+    assert e.value.status == X.PFX_ENOKEY
+    with pytest.raises(X.PfxError) as e:                        # in place
+        X.pfx_linear_transform(pair.ctx, cx, [pt], [0], 1, [], cx)
+    assert e.value.status == X.PFX_EINVAL
+    X.pfx_linear_transform(pair.ctx, cx, [pt], [0], 4, [], out)   # step 0 alone: a plaintext product
+    want = O.ct_mul_plain(P, co, w, pair.scale)
+    pair.same(want, out)
