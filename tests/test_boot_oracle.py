@@ -1,0 +1,40 @@
+"""Pins of the ModRaise oracle (CPU only): the raised residues of every
+coefficient are one integer (CRT over all primes of Q_L) congruent to the
+q_0 residue and inside the centred range; the raised ciphertext decrypts
+modulo Q_L to the q_0 decryption plus q_0 I(X) with |I| at most (h + 1)/2 + 1
+(App. A.3)."""
+import numpy as np
+
+from oracle import boot as B
+from oracle import ckks as O
+from paper_2412_13269_amd import inputs as I
+
+
+def setup(h):
+    P = O.Params(6, [50, 45, 45, 45], [50], alpha=1, mod_log2=17)
+    s = I.ternary_secret(P.N, h, 1)
+    m = O.from_ints(np.random.default_rng(2).integers(-2 ** 40, 2 ** 40, size=P.N), P.mods(1))
+    x = O.encrypt(P, s, m, I.uniform_residues(P.mods(1), P.N, 3), I.gaussian_error(P.N, 4), 2.0 ** 40)
+    return P, s, x
+
+
+def test_raised_residues_are_the_centred_lift():
+    P, s, x = setup(16)
+    y = B.mod_raise(P, x, P.L)
+    q0 = P.q[0]
+    for u in range(2):
+        z = O.crt_centered(y.c[u], P.mods(P.L))
+        assert all(int(v) % q0 == int(c) for v, c in zip(z, x.c[u][0]))
+        assert max(abs(int(v)) for v in z) <= (q0 - 1) // 2
+
+
+def test_raised_ciphertext_decrypts_to_m_plus_q0_times_a_small_polynomial():
+    for h in (16, None):
+        P, s, x = setup(h)
+        q0 = P.q[0]
+        m0 = O.crt_centered(O.decrypt(P, s, x), P.mods(1))
+        v = O.crt_centered(O.decrypt(P, s, B.mod_raise(P, x, P.L)), P.mods(P.L))
+        diff = [int(a) - int(b) for a, b in zip(v, m0)]
+        assert all(d % q0 == 0 for d in diff)
+        weight = int(np.count_nonzero(s))
+        assert max(abs(d // q0) for d in diff) <= (weight + 1) // 2 + 1

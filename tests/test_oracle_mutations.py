@@ -166,3 +166,13 @@ def test_transform_with_diagonals_rotated_forward_is_caught(monkeypatch):
     from oracle import linear as LTm
     monkeypatch.setattr(LTm, "giant_back", lambda P, n1, j: O.galois_element(P, n1 * j))
     _expect_fail(TL.test_transform_is_the_matrix_vector_product, TL.setup.__wrapped__(), 4)
+
+
+# ---- ModRaise (oracle/boot.py)
+from tests import test_boot_oracle as TB
+
+
+def test_mod_raise_without_centring_is_caught(monkeypatch):
+    from oracle import boot as BO
+    monkeypatch.setattr(BO, "lift", lambda words, q0: words.astype(np.int64))
+    _expect_fail(TB.test_raised_residues_are_the_centred_lift)
