@@ -298,6 +298,12 @@ pfx_status pfx_repack(pfx_ctx *ctx, const pfx_ct *const *in, size_t n, const pfx
  * one level and scale; out as for pfx_repack. */
 pfx_status pfx_pfe_repack(pfx_ctx *ctx, const pfx_ct *const *tables, size_t m, const int64_t *exps, size_t n,
                           const pfx_swk *const *gks, size_t n_gks, pfx_ct *const *out, void *stream);
+/* ModRaise, the first step of bootstrapping (App. A.3): a ciphertext of one
+ * limb (q_0) read modulo the first n_limbs primes: every coefficient's q_0
+ * residue lifted to [-(q_0-1)/2, (q_0-1)/2] and reduced modulo each prime, so
+ * out decrypts to m + q_0 I(X) with I small.  Scale and degree are kept; out
+ * may be a when its capacity holds n_limbs. */
+pfx_status pfx_mod_raise(pfx_ctx *ctx, const pfx_ct *a, uint32_t n_limbs, pfx_ct *out, void *stream);
 /* Ring merging and ring switching (Sec. 3.3, Sec. 4.3): n <= N/n_small
  * degree-1 ciphertexts of one limb in the small ring (context `small`, degree
  * n_small) -> one of one limb in the large ring (context `big`, degree N)

@@ -2171,6 +2171,39 @@ pfx_status pfx_linear_transform(pfx_ctx *c, const pfx_ct *a, const pfx_pt *const
     return PFX_OK;
 }
 
+pfx_status pfx_mod_raise(pfx_ctx *c, const pfx_ct *a, uint32_t n_limbs, pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(a->n_limbs == 1, PFX_ELEVEL, "ModRaise starts from one limb (q_0)");
+    REQUIRE(n_limbs >= 1 && n_limbs <= (uint32_t)c->L, PFX_ELEVEL, "target level out of range");
+    r = check_out(out, n_limbs, a->degree);
+    if (r) return r;
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    const size_t N = c->N;
+    const int np = (int)a->degree + 1;
+    double *stage = nullptr;
+    r = get_repack_ws(c, S(stream), (size_t)np * N, &stage);
+    if (r) return r;
+    for (int u = 0; u < np; ++u)
+        HIPCHECK(hipMemcpyAsync(stage + (size_t)u * N, a->poly((uint32_t)u), N * sizeof(double),
+                                hipMemcpyDeviceToDevice, S(stream)));
+    Launch L{c, S(stream)};
+    LimbMap one = contiguous_map(1, 0);
+    launch_ntt_pass(L, stage, nullptr, one, true, true, np, N);        // to the coefficient domain over q_0
+    launch_ntt_pass(L, stage, nullptr, one, false, true, np, N);
+    const double sc = a->scale;
+    launch_mod_raise(L, out->d, (size_t)out->cap_limbs * N, stage, N, np, (int)n_limbs);
+    const LimbMap m = contiguous_map((int)n_limbs, 0);
+    launch_ntt_pass(L, out->d, nullptr, m, false, false, np, (size_t)out->cap_limbs * N);
+    launch_ntt_pass(L, out->d, nullptr, m, true, false, np, (size_t)out->cap_limbs * N);
+    out->n_limbs = n_limbs;
+    out->degree = (uint32_t)np - 1;
+    out->scale = sc;
+    return PFX_OK;
+}
+
 pfx_status pfx_ring_merge(pfx_ctx *big, pfx_ctx *small, const pfx_ct *const *in, size_t n, const pfx_swk *swk,
                           pfx_ct *out, void *stream) {
     REQUIRE(big && small && in && swk && out && n >= 1, PFX_EINVAL, "null argument or no input");

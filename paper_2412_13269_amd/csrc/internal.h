@@ -292,6 +292,9 @@ void launch_mono_sum(const Launch &L, double *out, size_t cs, size_t ps, const d
 // polynomial u at (2i + u) n), coefficient j of input i at j r + i, r = 2^log_r;
 // zero where i >= n_in.
 void launch_merge_gather(const Launch &L, double *out, const double *stage, int n_in, int log_r, int logn_small);
+// ModRaise: coefficient-domain q_0 residues (npoly polynomials si apart) lifted
+// to the centred range and reduced modulo the first nl primes (out, so apart).
+void launch_mod_raise(const Launch &L, double *out, size_t so, const double *in, size_t si, int npoly, int nl);
 bool mono_sum_lds_ok(const pfx_ctx *c, int m);
 void launch_mono_sum_lds(const Launch &L, double *out, size_t cs, size_t ps, const double *tables, size_t st,
                          size_t tps, int m, const int64_t *exps, int n, int n_slots, int lv, bool ninv);

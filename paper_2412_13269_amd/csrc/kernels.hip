@@ -633,6 +633,38 @@ void launch_merge_gather(const Launch &L, double *out, const double *stage, int 
     prof_end(L, "merge_gather", ev, 16.0 * (double)N * 2);
 }
 
+// ModRaise (App. A.3): the coefficient-domain residues c of q_0 (one limb
+// per polynomial, `in`, polynomials si apart) lifted to [-(q_0-1)/2, (q_0-1)/2]
+// and reduced modulo each of the first nl primes (`out`, polynomials so
+// apart).  |lift| < 2^49 < 2^50, so mred reduces its magnitude exactly.
+// Grid: x over the N coefficients, y over polynomial x limb rows.
+__global__ void k_mod_raise(double *out, size_t so, const double *in, size_t si, int nl, int logn,
+                            const PrimeDev *pr) {
+    const int row = blockIdx.y;
+    const int u = row / nl, i = row - u * nl;
+    const size_t N = (size_t)1 << logn;
+    const size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    const double q0 = pr[0].q;
+    const double c = in[(size_t)u * si + x];
+    const bool neg = c > 0.5 * (q0 - 1.0);                  // lift c - q_0
+    const double mag = neg ? q0 - c : c;
+    const double q = pr[i].q;
+    const double r = mred(mag, q, pr[i].qinv);
+    out[(size_t)u * so + ((size_t)i << logn) + x] = neg && r != 0.0 ? q - r : r;
+}
+
+void launch_mod_raise(const Launch &L, double *out, size_t so, const double *in, size_t si, int npoly, int nl) {
+    const int logn = L.ctx->logn;
+    const size_t N = L.ctx->N;
+    hipEvent_t ev;
+    prof_begin(L, "mod_raise", &ev);
+    k_mod_raise<<<dim3((unsigned)((N + 255) / 256), (unsigned)(npoly * nl)), 256, 0, L.st>>>(out, so, in, si, nl, logn,
+                                                                                          L.ctx->d_primes);
+    HIP_LAUNCH_CHECK();
+    prof_end(L, "mod_raise", ev, 8.0 * (double)N * npoly * (1 + nl));
+}
+
 // Tensor product in the NTT domain (Sec. 2.4.2): d0 = a0 b0, d1 = a0 b1 + a1 b0,
 // d2 = a1 b1; ACC adds it to what d0, d1, d2 hold.
 template <bool ACC>

@@ -139,6 +139,7 @@ _SIGS = {
     "pfx_linear_transform": (_i32, [_vp, _vp, _VPP, _vp, _sz, _u32, _VPP, _sz, _vp, _vp]),
     "pfx_pfe_repack": (_i32, [_vp, _VPP, _sz, _vp, _sz, _VPP, _sz, _VPP, _vp]),
     "pfx_ring_merge": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp, _vp]),
+    "pfx_mod_raise": (_i32, [_vp, _vp, _u32, _vp, _vp]),
     "pfx_swk_create_from": (_i32, [_vp, _vp, _vp, _u64p, _i64p, _VPP]),
     "pfx_rotate": (_i32, [_vp, _vp, _i32, _VPP, _sz, _vp, _vp]),
     "pfx_conjugate": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp]),
@@ -517,6 +518,10 @@ def pfx_pfe_repack(ctx, tables, d_exps: int, n: int, gks, outs, stream=None):
     O = (ctypes.c_void_p * max(1, len(outs)))(*outs)
     K, nk = _keys(gks)
     _check(_lib.pfx_pfe_repack(ctx, T, len(tables), d_exps, n, K, nk, O, _stream(stream)))
+
+
+def pfx_mod_raise(ctx, a, n_limbs: int, out, stream=None):
+    _check(_lib.pfx_mod_raise(ctx, a, n_limbs, out, _stream(stream)))
 
 
 def pfx_ring_merge(big, small, cts, swk, out, stream=None):
