@@ -9,6 +9,13 @@ integer polynomial (O(sqrt(h)): c0 + c1 s without the reduction mod q_0).
 
 Reading: the lift is the centred one, (-q_0/2, q_0/2] (q_0 odd: [-(q_0-1)/2,
 (q_0-1)/2]), which keeps |I| at most (h + 1)/2 for a secret of h non-zeros.
+
+The trace-like map that follows ModRaise when 2n != N (App. A.3) keeps the
+coefficients of degree a multiple of r = N/2n and cancels the others with
+log r automorphisms: x <- x + phi_g(x) for g = N/2^t + 1, t = 0 .. log r - 1
+(phi_{N/2^t + 1} fixes X^j for j = 0 mod 2^(t+1) and negates it for
+j = 2^t mod 2^(t+1), so after the steps for t < T only multiples of 2^T are
+left, each times 2^T).
 """
 from __future__ import annotations
 
@@ -28,3 +35,16 @@ def mod_raise(P, x: O.Ct, level: int) -> O.Ct:
     assert x.level == 1 and 1 <= level <= P.L
     mods = P.mods(level)
     return O.Ct(np.stack([O.from_ints(lift(c[0], P.q[0]), mods) for c in x.c]), x.scale)
+
+
+def trace_galois(P, t: int) -> int:
+    """Galois element of step t of the trace-like map."""
+    return P.N // (1 << t) + 1
+
+
+def subring_trace(P, x: O.Ct, log_r: int, keys: dict) -> O.Ct:
+    """prod_t (1 + phi_{N/2^t + 1}) applied to x, t < log_r."""
+    for t in range(log_r):
+        g = trace_galois(P, t)
+        x = O.ct_add(P, x, O.apply_galois(P, x, g, keys[g]))
+    return x

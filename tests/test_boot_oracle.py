@@ -38,3 +38,23 @@ def test_raised_ciphertext_decrypts_to_m_plus_q0_times_a_small_polynomial():
         assert all(d % q0 == 0 for d in diff)
         weight = int(np.count_nonzero(s))
         assert max(abs(d // q0) for d in diff) <= (weight + 1) // 2 + 1
+
+
+def test_trace_keeps_multiples_of_r_times_r_and_cancels_the_rest():
+    P = O.Params(6, [50, 45, 45], [50, 50], alpha=1, mod_log2=17)
+    s = I.ternary_secret(P.N, None, 7)
+    ext = P.ext_mods(P.L)
+    log_r = 3
+    keys = {}
+    for t in range(log_r):
+        g = B.trace_galois(P, t)
+        keys[g] = O.galois_key(P, s, g, I.uniform_residues(ext, P.N, 40 + t, lead=(P.beta,)),
+                               I.gaussian_error((P.beta, P.N), 50 + t))
+    m = np.random.default_rng(8).integers(-2 ** 30, 2 ** 30, size=P.N)
+    x = O.encrypt(P, s, O.from_ints(m, P.mods(P.L)), I.uniform_residues(P.mods(P.L), P.N, 9),
+                  I.gaussian_error(P.N, 10), 1.0)
+    got = O.crt_centered(O.decrypt(P, s, B.subring_trace(P, x, log_r, keys)), P.mods(P.L))
+    r = 1 << log_r
+    for j, v in enumerate(got):
+        want = r * int(m[j]) if j % r == 0 else 0
+        assert abs(int(v) - want) < 2 ** 12, j

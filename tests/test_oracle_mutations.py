@@ -176,3 +176,10 @@ def test_mod_raise_without_centring_is_caught(monkeypatch):
     from oracle import boot as BO
     monkeypatch.setattr(BO, "lift", lambda words, q0: words.astype(np.int64))
     _expect_fail(TB.test_raised_residues_are_the_centred_lift)
+
+
+def test_trace_with_wrong_elements_is_caught(monkeypatch):
+    from oracle import boot as BO
+    orig = BO.trace_galois
+    monkeypatch.setattr(BO, "trace_galois", lambda P, t: orig(P, t) - 2)
+    _expect_fail(TB.test_trace_keeps_multiples_of_r_times_r_and_cancels_the_rest)
