@@ -304,6 +304,12 @@ pfx_status pfx_pfe_repack(pfx_ctx *ctx, const pfx_ct *const *tables, size_t m, c
  * out decrypts to m + q_0 I(X) with I small.  Scale and degree are kept; out
  * may be a when its capacity holds n_limbs. */
 pfx_status pfx_mod_raise(pfx_ctx *ctx, const pfx_ct *a, uint32_t n_limbs, pfx_ct *out, void *stream);
+/* The trace-like map after ModRaise (App. A.3): out = prod_{t < log_r}
+ * (1 + phi_{N/2^t + 1}) a, which keeps the coefficients of degree a multiple of
+ * r = 2^log_r (times r) and cancels the others; log_r automorphisms, whose keys
+ * (Galois elements N/2^t + 1) must be among keys (PFX_ENOKEY).  out may be a. */
+pfx_status pfx_subring_trace(pfx_ctx *ctx, const pfx_ct *a, uint32_t log_r, const pfx_swk *const *keys,
+                             size_t n_keys, pfx_ct *out, void *stream);
 /* Ring merging and ring switching (Sec. 3.3, Sec. 4.3): n <= N/n_small
  * degree-1 ciphertexts of one limb in the small ring (context `small`, degree
  * n_small) -> one of one limb in the large ring (context `big`, degree N)

@@ -2204,6 +2204,47 @@ pfx_status pfx_mod_raise(pfx_ctx *c, const pfx_ct *a, uint32_t n_limbs, pfx_ct *
     return PFX_OK;
 }
 
+pfx_status pfx_subring_trace(pfx_ctx *c, const pfx_ct *a, uint32_t log_r, const pfx_swk *const *keys, size_t n_keys,
+                             pfx_ct *out, void *stream) {
+    pfx_status r = check_ct(c, a, "a");
+    if (r) return r;
+    REQUIRE(a->degree == 1, PFX_EINVAL, "the trace needs a degree-1 ciphertext");
+    REQUIRE(log_r < (uint32_t)c->logn, PFX_EINVAL, "log_r must be below log N");
+    r = check_out(out, a->n_limbs, 1);
+    if (r) return r;
+    std::vector<const pfx_swk *> ks;
+    for (uint32_t t = 0; t < log_r; ++t) {
+        const pfx_swk *k = find_key(c, (uint32_t)(c->N >> t) + 1u, keys, n_keys);
+        if (!k) return fail(PFX_ENOKEY, "no Galois key for N/2^" + std::to_string(t) + " + 1");
+        ks.push_back(k);
+    }
+    const uint32_t lv = a->n_limbs;
+    const size_t N = c->N;
+    double *tmpd = nullptr;
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    r = get_repack_ws(c, S(stream), 2 * (size_t)lv * N, &tmpd);
+    if (r) return r;
+    pfx_ct tmp;
+    tmp.ctx = c;
+    tmp.cap_limbs = lv;
+    tmp.cap_degree = 1;
+    tmp.d = tmpd;
+    tmp.owns = false;
+    if (out != a) {
+        r = pfx_ct_copy(c, a, out, stream);
+        if (r) return r;
+    }
+    for (const pfx_swk *k : ks) {           // out <- out + phi_{N/2^t + 1}(out)
+        r = galois_apply(c, out, k, &tmp, S(stream));
+        if (r) return r;
+        r = pfx_add(c, out, &tmp, out, stream);
+        if (r) return r;
+    }
+    return PFX_OK;
+}
+
 pfx_status pfx_ring_merge(pfx_ctx *big, pfx_ctx *small, const pfx_ct *const *in, size_t n, const pfx_swk *swk,
                           pfx_ct *out, void *stream) {
     REQUIRE(big && small && in && swk && out && n >= 1, PFX_EINVAL, "null argument or no input");

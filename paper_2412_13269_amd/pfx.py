@@ -140,6 +140,7 @@ _SIGS = {
     "pfx_pfe_repack": (_i32, [_vp, _VPP, _sz, _vp, _sz, _VPP, _sz, _VPP, _vp]),
     "pfx_ring_merge": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp, _vp]),
     "pfx_mod_raise": (_i32, [_vp, _vp, _u32, _vp, _vp]),
+    "pfx_subring_trace": (_i32, [_vp, _vp, _u32, _VPP, _sz, _vp, _vp]),
     "pfx_swk_create_from": (_i32, [_vp, _vp, _vp, _u64p, _i64p, _VPP]),
     "pfx_rotate": (_i32, [_vp, _vp, _i32, _VPP, _sz, _vp, _vp]),
     "pfx_conjugate": (_i32, [_vp, _vp, _VPP, _sz, _vp, _vp]),
@@ -522,6 +523,11 @@ def pfx_pfe_repack(ctx, tables, d_exps: int, n: int, gks, outs, stream=None):
 
 def pfx_mod_raise(ctx, a, n_limbs: int, out, stream=None):
     _check(_lib.pfx_mod_raise(ctx, a, n_limbs, out, _stream(stream)))
+
+
+def pfx_subring_trace(ctx, a, log_r: int, keys, out, stream=None):
+    K, nk = _keys(keys)
+    _check(_lib.pfx_subring_trace(ctx, a, log_r, K, nk, out, _stream(stream)))
 
 
 def pfx_ring_merge(big, small, cts, swk, out, stream=None):

@@ -35,3 +35,16 @@ def test_mod_raise_matches_oracle(pair, X):
     with pytest.raises(X.PfxError) as e:                        # only from one limb
         X.pfx_mod_raise(pair.ctx, cx, P.L, pair.ct(P.L, deg=1))
     assert e.value.status == X.PFX_ELEVEL
+
+
+def test_subring_trace_matches_oracle(pair, X):
+    P = pair.P
+    log_r = 3
+    for t in range(log_r):
+        pair.key(B.trace_galois(P, t))
+    co, cx, z = pair.enc(P.L)
+    out = pair.ct(P.L, deg=1)
+    X.pfx_subring_trace(pair.ctx, cx, log_r, list(pair.kx.values()), out)
+    pair.same(B.subring_trace(P, co, log_r, pair.ko), out)
+    X.pfx_subring_trace(pair.ctx, cx, log_r, list(pair.kx.values()), cx)    # in place
+    pair.same(B.subring_trace(P, co, log_r, pair.ko), cx)
