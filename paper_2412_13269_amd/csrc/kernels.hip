@@ -929,8 +929,8 @@ __global__ __launch_bounds__(256) void k_ks_inner(const InnerArgs a) {
                 const int sz = min(alpha, lv - j0);
                 const bool own = m >= j0 && m < j0 + sz;
                 const int tt = m < j0 ? m : m - sz;
-                w0[t] = k0[(size_t)(2 * j) * kstride];
-                w1[t] = k0[(size_t)(2 * j + 1) * kstride];
+                w0[t] = __builtin_nontemporal_load(k0 + (size_t)(2 * j) * kstride);
+                w1[t] = __builtin_nontemporal_load(k0 + (size_t)(2 * j + 1) * kstride);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     if (b < a.nb) {
@@ -940,7 +940,7 @@ __global__ __launch_bounds__(256) void k_ks_inner(const InnerArgs a) {
                             else x[t][b] = a.d[b][lm + c];
                         } else {
                             const size_t cc = MODE == KS_GALOIS && a.hoisted ? galois_src((uint32_t)c, logn, a.g[b]) : c;
-                            x[t][b] = a.ext[b * a.sext + ((size_t)j * E + tt) * N + cc];
+                            x[t][b] = __builtin_nontemporal_load(a.ext + b * a.sext + ((size_t)j * E + tt) * N + cc);
                         }
                     }
                 }
