@@ -31,7 +31,13 @@ Every ct x ct product is relinearised and rescaled.
 Readings: the paper's [15,15,15] minimax composite coefficients are not
 printed (Tab. 2); f7 is the closed-form odd polynomial with f7(+-1) = +-1 and
 f7'(+-1) = 0, and the degree-7 score polynomial and the attribute count come
-from the query configuration (N = 2^16, 2^17 records x 8 attributes).
+from the query configuration (N = 2^16, 2^17 records x 8 attributes).  The
+degree-15 stages of the paper's first threshold take the member of the same
+closed-form family of degree 15, f15(x) = x P(x^2) / 2048 with
+P(y) = sum_{i<=7} 4^(7-i) C(2i, i) (1 - y)^i / 4^7 * 2048 (f15(+-1) = +-1, its
+first seven derivatives 0 at +-1), evaluated like f7: y = x^2, the powers of y
+by the tree above, the integer combination, x / 2048 at the next prime's
+scale, one product.
 """
 from __future__ import annotations
 
@@ -39,20 +45,29 @@ import numpy as np
 
 from oracle import ckks as O
 
-F7 = (35, -35, 21, -5)   # coefficients of x, x^3, x^5, x^7 over 16
+# sign stages f(x) = x P(x^2) / den: integer coefficients of P (y^0, y^1, ...)
+SIGN = {7: ((35, -35, 21, -5), 16),
+        15: ((6435, -15015, 27027, -32175, 25025, -12285, 3465, -429), 2048)}
+F7 = SIGN[7][0]
+
+
+def f_sign(x, degree=7):
+    c, den = SIGN[degree]
+    y = x * x
+    return x * sum(ck * y ** k for k, ck in enumerate(c)) / den
 
 
 def f7(x):
-    return (35 * x - 35 * x ** 3 + 21 * x ** 5 - 5 * x ** 7) / 16.0
+    return f_sign(x, 7)
 
 
-def fp64_query(x, w, c, t, eta, stages=3):
+def fp64_query(x, w, c, t, eta, stages=3, sign_degree=7):
     """The circuit in plain FP64 on the records x (records, attributes)."""
     s = x @ w
     z = sum(c[k] * s ** k for k in range(len(c)))
     u = (z - t) * eta
     for _ in range(stages):
-        u = f7(u)
+        u = f_sign(u, sign_degree)
     step = (u + 1.0) / 2.0
     return step, float(step.sum())
 
@@ -104,22 +119,25 @@ def mul_const_next(P, x: O.Ct, value: float) -> O.Ct:
     return O.Ct(O.ct_mul_int(P, x, k).c, x.scale * q)
 
 
-def sign_stage(P, x: O.Ct, rlk) -> O.Ct:
-    x2 = _mr(P, x, x, rlk)
-    x4 = _mr(P, x2, x2, rlk)
-    x6 = _mr(P, x4, x2, rlk)
-    p = O.ct_mul_int(P, x2, -35)
-    p = O.ct_add(P, p, O.ct_mul_int(P, x4, 21))
-    p = O.ct_add(P, p, O.ct_mul_int(P, x6, -5))
-    p = add_const(P, p, 35.0)
-    xs = O.rescale(P, mul_const_next(P, x, 1.0 / 16.0))
+def sign_stage(P, x: O.Ct, rlk, degree=7) -> O.Ct:
+    """f(x) = x P(x^2) / den: y = x^2, y^k by the power tree, P(y) as integer
+    products summed (coefficient of y first) plus the constant, then
+    rescale(x * round(q / den)) times P(y)."""
+    c, den = SIGN[degree]
+    Y = _powers(P, _mr(P, x, x, rlk), len(c) - 1, rlk)
+    p = O.ct_mul_int(P, Y[1], c[1])
+    for k in range(2, len(c)):
+        p = O.ct_add(P, p, O.ct_mul_int(P, Y[k], c[k]))
+    p = add_const(P, p, float(c[0]))
+    xs = O.rescale(P, mul_const_next(P, x, 1.0 / den))
     return _mr(P, xs, p, rlk)
 
 
 FINAL_LIMBS = 2   # limbs the InnerSum runs on
 
 
-def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None, final_limbs=FINAL_LIMBS):
+def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None, final_limbs=FINAL_LIMBS,
+                  sign_degree=7):
     """X[b][a]: plaintext words at scale x_scale; W[a], C[k], T, H: oracle ciphertexts."""
     D = len(C) - 1
     total = None
@@ -135,7 +153,7 @@ def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None,
         z = O.ct_add(P, O.rescale(P, O.relinearize(P, z2, rlk)), C[0])
         u = _mr(P, O.ct_sub(P, z, T), H, rlk)
         for _ in range(stages):
-            u = sign_stage(P, u, rlk)
+            u = sign_stage(P, u, rlk, sign_degree)
         step = add_const(P, u, 1.0)
         step = O.Ct(step.c, step.scale * 2.0)
         total = step if total is None else O.ct_add(P, total, step)

@@ -183,3 +183,16 @@ def test_trace_with_wrong_elements_is_caught(monkeypatch):
     orig = BO.trace_galois
     monkeypatch.setattr(BO, "trace_galois", lambda P, t: orig(P, t) - 2)
     _expect_fail(TB.test_trace_keeps_multiples_of_r_times_r_and_cancels_the_rest)
+
+
+# ---- degree-15 sign stage (oracle/query.py)
+from oracle import query as QO
+from tests import test_query_oracle as TQ
+
+
+def test_sign_coefficient_typo_is_caught(monkeypatch):
+    c, den = QO.SIGN[15]
+    bad = dict(QO.SIGN)
+    bad[15] = (c[:3] + (c[3] + 10,) + c[4:], den)
+    monkeypatch.setattr(QO, "SIGN", bad)
+    _expect_fail(TQ.test_f15_closed_form)

@@ -121,3 +121,25 @@ def test_query_circuit_degrees_3_and_15():
         got = O.decode(P, O.decrypt(P, s_, out), out.scale, P.N // 2).real
         step, count = Q.fp64_query(x, w, c, t, eta)
         assert abs(got[0] - count) < 0.25, D
+
+
+def test_f15_closed_form():
+    # the degree-15 member of the family: odd, f(+-1) = +-1, f'(x) = (6435/2048)(1 - x^2)^7
+    xs = np.linspace(-1, 1, 201)
+    f = lambda v: Q.f_sign(v, 15)
+    assert np.allclose(f(-xs), -f(xs))
+    assert f(1.0) == 1.0 and f(-1.0) == -1.0
+    h = 1e-6
+    d = (f(xs + h) - f(xs - h)) / (2 * h)
+    assert np.allclose(d, 6435 / 2048 * (1 - xs ** 2) ** 7, atol=1e-5)
+    u = np.linspace(0.2, 1.0, 81)                    # three stages: |x| >= 0.2 to within 1e-6 of +-1
+    assert np.all(np.abs(f(f(f(u))) - 1.0) < 1e-6)
+
+
+def test_query_circuit_with_degree_15_sign_stages():
+    P, s_, x, (w, c, t, eta), X, delta, W, C, T, H, rlk, gks = build(9, 1, 17)
+    out = Q.query_circuit(P, X, delta, W, C, T, H, rlk, gks, final_limbs=P.L, sign_degree=15)
+    assert out.level == P.L - 21                             # three stages of depth 5
+    got = O.decode(P, O.decrypt(P, s_, out), out.scale, P.N // 2).real
+    step, count = Q.fp64_query(x, w, c, t, eta, sign_degree=15)
+    assert abs(got[0] - count) < 0.25
