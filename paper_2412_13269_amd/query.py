@@ -10,10 +10,12 @@ slot-domain linear score): for each block b of 2^(logN-1) records
     Z   = rescale(relin(sum_{k=1..D} C[k] (x) Y_k)) + C[0]   (tensor products
           summed at degree 2, one relinearisation)
     U   = rescale(relin((Z - T) H))
-    3 stages of f7(x) = (35x - 35x^3 + 21x^5 - 5x^7)/16:
-        X2 = X^2, X4 = X2^2, X6 = X4 X2
-        P  = (-35) X2 + 21 X4 + (-5) X6 + 35
-        U  = rescale(relin(rescale(X * round(q/16)) * P))
+    3 stages of f(x) = x P(x^2) / den, f7 (sign_degree 7: P = 35 - 35y + 21y^2
+    - 5y^3, den 16) or its degree-15 sibling (sign_degree 15: P of degree 7,
+    den 2048, the paper's first-threshold degree):
+        Y1 = X^2, Y_k = powers of Y1 by the tree above (k <= deg P)
+        P  = c1 Y1 + c2 Y2 + ... + c0            (integer products, constant)
+        U  = rescale(relin(rescale(X * round(q/den)) * P))
     step_b = (U + 1) with the scale doubled
   OUT = InnerSum(step_0 + step_1 + ...) on the first final_limbs limbs
 
@@ -48,6 +50,11 @@ from dataclasses import dataclass, field
 
 from . import pfx as X
 
+# composite-sign stages f(x) = x P(x^2) / den: integer coefficients of P
+# (y^0, y^1, ...) and den, for stage degree 7 (f7) and 15
+SIGN = {7: ((35, -35, 21, -5), 16),
+        15: ((6435, -15015, 27027, -32175, 25025, -12285, 3465, -429), 2048)}
+
 
 @dataclass
 class QueryPlan:
@@ -60,6 +67,7 @@ class QueryPlan:
     lanes: int = 4
     interleave: bool | int = False
     final_limbs: int = 2
+    sign_degree: int = 7      # 7 or 15: the degree of each composite-sign stage
     ops: list = field(default_factory=list)
     n_regs: int = 0
     out: int = -1
@@ -67,6 +75,7 @@ class QueryPlan:
     def __post_init__(self):
         A, D = self.attributes, self.degree
         assert 1 <= D <= 15 and A >= 1 and self.n_blocks >= 1
+        assert self.sign_degree in SIGN
         self.W = list(range(A))
         self.C = list(range(A, A + D + 1))
         self.T = A + D + 1
@@ -136,19 +145,22 @@ class QueryPlan:
         self._op(X.OP_SUB, u, z, self.T)
         self._mr(u, u, self.H)
         self._drop(z)
+        cs, den = SIGN[self.sign_degree]
         for _ in range(self.stages):
-            x2, x4, x6, p = self._new(), self._new(), self._new(), self._new()
-            self._mr(x2, u, u)
-            self._mr(x4, x2, x2)
-            self._mr(x6, x4, x2)
-            self._op(X.OP_MUL_INT, p, x2, k=-35)
-            self._op(X.OP_MUL_INT_ACC, p, x4, k=21)
-            self._op(X.OP_MUL_INT_ACC, p, x6, k=-5)
-            self._op(X.OP_ADD_CONST, p, p, value=35.0)
-            self._op(X.OP_MUL_CONST, x2, u, value=1.0 / 16.0)
-            self._op(X.OP_RESCALE, x2, x2)
-            self._mr(u, x2, p)
-            self._drop(x2, x4, x6, p)
+            ys = {1: self._new()}
+            self._mr(ys[1], u, u)                       # y = x^2
+            for k in range(2, len(cs)):
+                ys[k] = self._new()
+                self._mr(ys[k], ys[tree[k][0]], ys[tree[k][1]])
+            p = self._new()
+            self._op(X.OP_MUL_INT, p, ys[1], k=cs[1])
+            for k in range(2, len(cs)):
+                self._op(X.OP_MUL_INT_ACC, p, ys[k], k=cs[k])
+            self._op(X.OP_ADD_CONST, p, p, value=float(cs[0]))
+            self._op(X.OP_MUL_CONST, ys[1], u, value=1.0 / den)     # x / den at the next prime's scale
+            self._op(X.OP_RESCALE, ys[1], ys[1])
+            self._mr(u, ys[1], p)
+            self._drop(*ys.values(), p)
         self._op(X.OP_ADD_CONST, u, u, value=1.0)
         self._op(X.OP_SCALE_MUL, u, u, value=2.0)
         return u

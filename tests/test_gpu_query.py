@@ -135,7 +135,7 @@ class Setup:
         rlk = O.relin_key(P, self.s, *self.key_in[0])
         gks = {g: O.galois_key(P, self.s, g, *v) for g, v in self.key_in.items() if g}
         Xw = [[self.db_words[b * A + a] for a in range(A)] for b in range(len(self.db_words) // A)]
-        return Q.query_circuit(P, Xw, DELTA, W, C, T, H, rlk, gks)
+        return Q.query_circuit(P, Xw, DELTA, W, C, T, H, rlk, gks, sign_degree=self.plan.sign_degree)
 
     def close(self):
         X = self.X
@@ -351,3 +351,19 @@ def test_elementwise_runs_match_single_calls(X):
         for h in handles:
             X.pfx_ct_destroy(h)
         X.pfx_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("degree", [7, 15])
+def test_degree_15_sign_stages_match_oracle(X, degree):
+    # the paper's first-threshold degrees (15, 15, 15): three stages of depth 5
+    S = Setup(X, 12, 2, 61 + degree, with_oracle=True, degree=degree, sign_degree=15, interleave=True)
+    try:
+        want = S.oracle_out()
+        for graph in (False, True, True):
+            out = S.run(graph=graph)
+            assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), want.c), graph
+        assert X.pfx_ct_info(out).scale == want.scale
+        step, count = Q.fp64_query(S.x, *S.params, sign_degree=15)
+        assert abs(S.count(out)[0] - count) < 0.25
+    finally:
+        S.close()

@@ -136,3 +136,16 @@ def test_one_relinearisation_for_the_score_polynomial():
         assert codes.count(X.OP_RELIN) == 2
         assert codes.count(X.OP_MUL_PLAIN) == 2 and codes.count(X.OP_MUL_PLAIN_ACC) == 2 * 7
         assert sum(plan.reg_degree) == plan.n_regs + 1          # one degree-2 register
+
+
+@pytest.mark.parametrize("kw", VARIANTS, ids=lambda kw: "-".join(f"{k}{v}" for k, v in kw.items()) or "plain")
+def test_plan_with_degree_15_sign_stages(kw):
+    n, A, blocks = 64, 8, 3
+    x = I.synthetic_database(n * blocks, A, 41)
+    w, c, t, eta = I.query_parameters(A, 7, 42)
+    plan = QueryPlan(blocks, A, 7, 3, 6, sign_degree=15, **kw)
+    inputs = [np.full(n, v) for v in list(w) + list(c) + [t, eta]]
+    pts = [x[b * n:(b + 1) * n, a] for b in range(blocks) for a in range(A)]
+    got = interpret(plan, inputs, pts)
+    _, count = Q.fp64_query(x, w, c, t, eta, sign_degree=15)
+    assert np.allclose(got, count, rtol=1e-9, atol=1e-9)
