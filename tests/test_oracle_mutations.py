@@ -196,3 +196,13 @@ def test_sign_coefficient_typo_is_caught(monkeypatch):
     bad[15] = (c[:3] + (c[3] + 10,) + c[4:], den)
     monkeypatch.setattr(QO, "SIGN", bad)
     _expect_fail(TQ.test_f15_closed_form)
+
+
+# ---- EvalMod (oracle/evalmod.py)
+from tests import test_evalmod_oracle as TE
+
+
+def test_evalmod_with_a_wrong_chebyshev_split_is_caught(monkeypatch):
+    from oracle import evalmod as EM
+    monkeypatch.setattr(EM, "cheb_index_pair", lambda k: (k - 1, 1))
+    _expect_fail(TE.test_fp64_steps_are_the_scaled_sine)
