@@ -1,0 +1,62 @@
+"""GPU: the EvalMod op list (App. A.3) through pfx_run_circuit against the
+oracle word for word, eagerly and from a replayed HIP graph, at N = 2^12 with
+the 24-limb chain; decrypted slots against the FP64 steps."""
+import numpy as np
+import pytest
+
+from oracle import ckks as O
+from oracle import evalmod as E
+from paper_2412_13269_amd import inputs as I
+from tests.test_evalmod_oracle import coeffs
+from tests.test_gpu_query import ALPHA, DELTA, ML, PB, QB
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_2412_13269_amd import pfx
+    return pfx
+
+
+def test_evalmod_plan_matches_oracle(X):
+    from paper_2412_13269_amd.evalmod import EvalModPlan
+    logn, K, r, deg = 12, 8.0, 3, 24
+    P = O.Params(logn, QB, PB, alpha=ALPHA, mod_log2=ML)
+    N = P.N
+    ctx = X.pfx_ctx_create(X.make_params(logn, QB, PB, ALPHA, ML), 0)
+    s = I.ternary_secret(N, 192, 71)
+    sk = X.pfx_sk_create(ctx, s)
+    ext = P.ext_mods(P.L)
+    ka, ke = I.uniform_residues(ext, N, 72, lead=(P.beta,)), I.gaussian_error((P.beta, N), 73)
+    rlk_o, rlk = O.relin_key(P, s, ka, ke), X.pfx_swk_create(ctx, sk, 0, ka, ke)
+    rng = np.random.default_rng(74)
+    t = rng.integers(-7, 8, size=N // 2) + rng.uniform(-0.05, 0.05, size=N // 2)
+    m = O.encode(P, t, DELTA, P.L)
+    a, e = I.uniform_residues(P.mods(P.L), N, 75), I.gaussian_error(N, 76)
+    xo = O.encrypt(P, s, m, a, e, DELTA)
+    plan = EvalModPlan(list(coeffs(deg, K, r)), r, K)
+    regs = [X.pfx_ct_create(ctx, P.L, 1) for _ in range(plan.n_regs)]
+    pt = X.pfx_pt_import(ctx, m, DELTA)
+    X.pfx_encrypt(ctx, sk, pt, a, e, regs[0])
+    X.pfx_ct_destroy(pt)
+    stream = X.pfx_stream_create(ctx)
+    try:
+        want = E.evalmod(P, xo, coeffs(deg, K, r), r, K, rlk_o)
+        for graph in (False, True, True):
+            X.pfx_run_circuit(ctx, plan.ops, regs, 1, [], rlk, [], X.RUN_GRAPH if graph else X.RUN_EAGER, stream)
+            X.pfx_sync(ctx, stream)
+            words = X.pfx_ct_export(ctx, regs[plan.out], N)
+            assert np.array_equal(words, want.c), graph
+            assert X.pfx_ct_info(regs[plan.out]).scale == want.scale
+        assert want.level == P.L - plan.depth
+        got = O.decode(P, O.decrypt(P, s, want), want.scale, N // 2).real
+        assert np.max(np.abs(got - E.evalmod_fp64(t, coeffs(deg, K, r), r, K))) < 2 ** -15
+        assert np.max(np.abs(got - (t - np.round(t)))) < 1e-3       # the fractional part, up to its cubic term
+    finally:
+        for h in regs:
+            X.pfx_ct_destroy(h)
+        X.pfx_swk_destroy(rlk)
+        X.pfx_sk_destroy(sk)
+        X.pfx_stream_destroy(ctx, stream)
+        X.pfx_ctx_destroy(ctx)
