@@ -508,6 +508,26 @@ def main():
     for k in extra:
         X.pfx_swk_destroy(k)
 
+    # EvalMod of bootstrapping (App. A.3) on a full-level ciphertext: degree-24
+    # Chebyshev cosine, 3 double angles, the scaled sine (26 HMult + relin)
+    from numpy.polynomial import chebyshev as _cheb
+    from paper_2412_13269_amd.evalmod import EvalModPlan
+    _a = (8.0 + 0.25) / 8
+    em = EvalModPlan(list(_cheb.chebinterpolate(lambda v: np.cos(2 * np.pi * _a * v), 24)), 3, 8.0)
+    em_regs = [cts[0]] + [X.pfx_ct_create(ctx, L, 1) for _ in range(em.n_regs - 1)]
+    for mode, name in ((X.RUN_EAGER, "eager"), (X.RUN_GRAPH, "graph")):
+        X.pfx_run_circuit(ctx, em.ops, em_regs, 1, [], rlk, [], mode, st)
+        X.pfx_sync(ctx, st)
+        e0 = time.perf_counter()
+        for _ in range(5):
+            X.pfx_run_circuit(ctx, em.ops, em_regs, 1, [], rlk, [], mode, st)
+        X.pfx_sync(ctx, st)
+        per_op[f"evalmod_{name}_ms"] = 1e3 * (time.perf_counter() - e0) / 5
+    log(f"EvalMod (degree 24, r = 3, {em.depth} levels): {per_op['evalmod_eager_ms']:.2f} ms eager, "
+        f"{per_op['evalmod_graph_ms']:.2f} ms as a graph")
+    for h in em_regs[1:]:
+        X.pfx_ct_destroy(h)
+
     per_op["rotations_15_separate_ms"] = hoist["separate"]
     per_op["rotations_15_hoisted_ms"] = hoist["hoisted"]
     log(f"15 rotations of one ciphertext: {hoist['separate']:.3f} ms one by one, {hoist['hoisted']:.3f} ms hoisted")
