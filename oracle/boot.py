@@ -16,6 +16,14 @@ log r automorphisms: x <- x + phi_g(x) for g = N/2^t + 1, t = 0 .. log r - 1
 (phi_{N/2^t + 1} fixes X^j for j = 0 mod 2^(t+1) and negates it for
 j = 2^t mod 2^(t+1), so after the steps for t < T only multiples of 2^T are
 left, each times 2^T).
+
+CoeffsToSlots and SlotsToCoeffs (App. A.4) with all N/2 slots: for the
+message m(X) = sum_k m_k X^k (real m_k) the slots are z_l = m(zeta_l),
+zeta_l = exp(i pi 5^l / N); since zeta_l^(N/2) = i, the complex vector
+w_j = m_j + i m_(j+N/2) (j < N/2) gives z = A w with A[l, j] = zeta_l^j, and
+w = B z with B[j, l] = (2/N) zeta_l^(-j) (the conjugate terms cancel).  Both
+are evaluated as dense matrix-vector products on the slots by the BSGS
+diagonal method (oracle.linear), diagonal k of M being M[j, (j + k) mod N/2].
 """
 from __future__ import annotations
 
@@ -48,3 +56,29 @@ def subring_trace(P, x: O.Ct, log_r: int, keys: dict) -> O.Ct:
         g = trace_galois(P, t)
         x = O.ct_add(P, x, O.apply_galois(P, x, g, keys[g]))
     return x
+
+
+def slot_roots(P) -> np.ndarray:
+    n = P.N // 2
+    e = np.array([pow(5, l, 2 * P.N) for l in range(n)], dtype=np.float64)
+    return np.exp(1j * np.pi * e / P.N)
+
+
+def s2c_matrix(P) -> np.ndarray:
+    """A[l, j] = zeta_l^j: slots of the message whose coefficients are w (packed)."""
+    n = P.N // 2
+    return slot_roots(P)[:, None] ** np.arange(n)[None, :]
+
+
+def c2s_matrix(P) -> np.ndarray:
+    """B[j, l] = (2/N) zeta_l^-j: packed coefficients w_j = m_j + i m_(j+N/2) from the slots."""
+    n = P.N // 2
+    return (2.0 / P.N) * np.conj(slot_roots(P)[None, :] ** np.arange(n)[:, None])
+
+
+def diagonals(M: np.ndarray) -> list:
+    """Diagonal k of M: d_k[j] = M[j, (j + k) mod n], so M z = sum_k d_k (.) rot(z, k)."""
+    n = M.shape[0]
+    j = np.arange(n)
+    return [M[j, (j + k) % n] for k in range(n)]
+

@@ -58,3 +58,51 @@ def test_trace_keeps_multiples_of_r_times_r_and_cancels_the_rest():
     for j, v in enumerate(got):
         want = r * int(m[j]) if j % r == 0 else 0
         assert abs(int(v) - want) < 2 ** 12, j
+
+
+def test_slot_dft_matrices_invert_each_other_and_pack_the_coefficients():
+    P = O.Params(6, [50, 45, 45], [50, 50], alpha=1, mod_log2=17)
+    A, Bm = B.s2c_matrix(P), B.c2s_matrix(P)
+    n = P.N // 2
+    assert np.allclose(Bm @ A, np.eye(n), atol=1e-12)
+    # the encoder's slots of a coefficient vector m are A (m_lo + i m_hi)
+    m = np.random.default_rng(3).uniform(-1, 1, size=P.N)
+    z = O.decode(P, O.from_ints(np.round(m * 2.0 ** 30).astype(np.int64), P.mods(1)), 2.0 ** 30, n)
+    w = m[:n] + 1j * m[n:]
+    assert np.allclose(A @ w, z, atol=1e-6)
+    assert np.allclose(Bm @ z, w, atol=1e-6)
+    d = B.diagonals(Bm)
+    zz = np.random.default_rng(4).standard_normal(n) + 1j
+    assert np.allclose(sum(dk * np.roll(zz, -k) for k, dk in enumerate(d)), Bm @ zz)
+
+
+
+def transform_keys(P, s, n1, seed):
+    n = P.N // 2
+    ext = P.ext_mods(P.L)
+    steps = sorted({k % n1 for k in range(1, n)} - {0}) + sorted({n1 * (k // n1) for k in range(n)} - {0})
+    gs = sorted({O.galois_element(P, k) for k in steps})
+    return {g: O.galois_key(P, s, g, I.uniform_residues(ext, P.N, seed + 2 * i, lead=(P.beta,)),
+                            I.gaussian_error((P.beta, P.N), seed + 2 * i + 1)) for i, g in enumerate(gs)}
+
+
+def test_coeffs_to_slots_and_back():
+    # the dense transforms through the BSGS diagonal method (oracle.linear):
+    # CoeffsToSlots puts the packed coefficients m_j + i m_(j+N/2) in the slots,
+    # SlotsToCoeffs returns the original slots
+    from oracle import linear as LT
+    P = O.Params(6, [50, 45, 45, 45], [50, 50], alpha=2, mod_log2=17)
+    n, delta, sd = P.N // 2, 2.0 ** 40, 2.0 ** 45
+    s = I.ternary_secret(P.N, None, 95)
+    keys = transform_keys(P, s, 8, 300)
+    z = I.uniform_slots(n, 96) + 1j * I.uniform_slots(n, 97)
+    m = O.encode(P, z, delta, P.L)
+    x = O.encrypt(P, s, m, I.uniform_residues(P.mods(P.L), P.N, 98), I.gaussian_error(P.N, 99), delta)
+    c2s = [O.encode(P, d, sd, P.L) for d in B.diagonals(B.c2s_matrix(P))]
+    w = O.rescale(P, LT.linear_transform(P, x, c2s, sd, list(range(n)), 8, keys))
+    mc = O.crt_centered(m, P.mods(P.L)).astype(float) / delta
+    got = O.decode(P, O.decrypt(P, s, w), w.scale, n)
+    assert np.max(np.abs(got - (mc[:n] + 1j * mc[n:]))) < 1e-8
+    s2c = [O.encode(P, d, sd, w.level) for d in B.diagonals(B.s2c_matrix(P))]
+    back = O.rescale(P, LT.linear_transform(P, w, s2c, sd, list(range(n)), 8, keys))
+    assert np.max(np.abs(O.decode(P, O.decrypt(P, s, back), back.scale, n) - z)) < 1e-7

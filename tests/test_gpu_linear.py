@@ -73,3 +73,51 @@ def test_linear_transform_checks(pair, X):
     X.pfx_linear_transform(pair.ctx, cx, [pt], [0], 4, [], out)   # step 0 alone: a plaintext product
     want = O.ct_mul_plain(P, co, w, pair.scale)
     pair.same(want, out)
+
+
+def test_dense_coeffs_to_slots_matches_oracle(X):
+    # CoeffsToSlots (App. A.4) as one dense slot matrix at N = 2^12: 2048
+    # diagonals, 63 hoisted baby steps and 31 giant steps (n1 = 64)
+    from oracle import boot as B
+    from tests.test_boot_oracle import transform_keys
+    P = O.Params(12, [50, 45, 45, 45], [50, 50], alpha=2, mod_log2=17)
+    n, delta, sd, n1 = P.N // 2, 2.0 ** 40, 2.0 ** 45, 64
+    ctx = X.pfx_ctx_create(X.make_params(12, [50, 45, 45, 45], [50, 50], 2, 17), 0)
+    s = I.ternary_secret(P.N, None, 401)
+    sk = X.pfx_sk_create(ctx, s)
+    ko = transform_keys(P, s, n1, 500)
+    ext = P.ext_mods(P.L)
+    kx, handles = [], []
+    try:
+        for i, g in enumerate(sorted(ko)):
+            kx.append(X.pfx_swk_create(ctx, sk, g, I.uniform_residues(ext, P.N, 500 + 2 * i, lead=(P.beta,)),
+                                       I.gaussian_error((P.beta, P.N), 501 + 2 * i)))
+        z = I.uniform_slots(n, 402) + 1j * I.uniform_slots(n, 403)
+        m = O.encode(P, z, delta, P.L)
+        a, e = I.uniform_residues(P.mods(P.L), P.N, 404), I.gaussian_error(P.N, 405)
+        xo = O.encrypt(P, s, m, a, e, delta)
+        cx = X.pfx_ct_create(ctx, P.L, 1)
+        handles.append(cx)
+        pt = X.pfx_pt_import(ctx, m, delta)
+        X.pfx_encrypt(ctx, sk, pt, a, e, cx)
+        X.pfx_ct_destroy(pt)
+        words = [O.encode(P, d, sd, P.L) for d in B.diagonals(B.c2s_matrix(P))]
+        pts = []
+        for w in words:
+            pts.append(X.pfx_pt_import(ctx, w, sd))
+            handles.append(pts[-1])
+        out = X.pfx_ct_create(ctx, P.L, 1)
+        handles.append(out)
+        X.pfx_linear_transform(ctx, cx, pts, list(range(n)), n1, kx, out)
+        want = LT.linear_transform(P, xo, words, sd, list(range(n)), n1, ko)
+        assert np.array_equal(X.pfx_ct_export(ctx, out, P.N), want.c)
+        mc = O.crt_centered(m, P.mods(P.L)).astype(float) / delta
+        got = O.decode(P, O.decrypt(P, s, want), want.scale, n)
+        assert np.max(np.abs(got - (mc[:n] + 1j * mc[n:]))) < 1e-6
+    finally:
+        for h in handles:
+            X.pfx_ct_destroy(h)
+        for k in kx:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(sk)
+        X.pfx_ctx_destroy(ctx)
