@@ -24,6 +24,18 @@ w_j = m_j + i m_(j+N/2) (j < N/2) gives z = A w with A[l, j] = zeta_l^j, and
 w = B z with B[j, l] = (2/N) zeta_l^(-j) (the conjugate terms cancel).  Both
 are evaluated as dense matrix-vector products on the slots by the BSGS
 diagonal method (oracle.linear), diagonal k of M being M[j, (j + k) mod N/2].
+
+Half-BTS (Sec. 4.3, App. A.3-A.4): a coefficient-encoded ciphertext of one limb
+-> one at a higher level whose slots hold its coefficients, i.e. ModRaise,
+CoeffsToSlots and EvalMod without the SlotsToCoeffs of a full bootstrapping.
+Reading: after ModRaise the ciphertext is read at scale q_0, so its
+coefficients are t = m'/q_0 = I + m/q_0; CoeffsToSlots applies B/2 (diagonals
+an input, at scale d_scale) and rescales, so the slots hold w/2 with
+w_j = t_j + i t_(j+N/2); re = w/2 + conj(w/2) and im = -i (w/2 - conj(w/2))
+(conjugation: the automorphism 2N - 1; -i: the monomial X^(3N/2)) are the real
+vectors t_j and t_(j+N/2); EvalMod on each (oracle.evalmod, its last constant
+times out_factor = q_0 / Delta) returns m / Delta; the result is
+re + i im (i: X^(N/2)), slot j holding m_j / Delta + i m_(j+N/2) / Delta.
 """
 from __future__ import annotations
 
@@ -82,3 +94,23 @@ def diagonals(M: np.ndarray) -> list:
     j = np.arange(n)
     return [M[j, (j + k) % n] for k in range(n)]
 
+
+
+def half_bootstrap(P, x: O.Ct, c2s_words: list, d_scale: float, n1: int, keys: dict, rlk, coeffs, r: int,
+                   K: float, out_factor: float) -> O.Ct:
+    """x: one limb, coefficient-encoded; c2s_words: the N/2 diagonals of B/2
+    encoded at d_scale (coefficient domain, at least P.L limbs); keys: the
+    Galois keys of the BSGS steps and of 2N - 1."""
+    from oracle import evalmod as EM
+    from oracle import linear as LT
+    from oracle import repack as RP
+    n = P.N // 2
+    y = mod_raise(P, x, P.L)
+    y = O.Ct(y.c, float(P.q[0]))
+    z = O.rescale(P, LT.linear_transform(P, y, c2s_words, d_scale, list(range(n)), n1, keys))
+    zc = O.conjugate(P, z, keys)
+    re = O.ct_add(P, z, zc)
+    im = RP.ct_monomial(P, O.ct_sub(P, z, zc), 3 * n)
+    re = EM.evalmod(P, re, coeffs, r, K, rlk, out_factor)
+    im = EM.evalmod(P, im, coeffs, r, K, rlk, out_factor)
+    return O.ct_add(P, re, RP.ct_monomial(P, im, n))

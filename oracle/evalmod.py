@@ -14,11 +14,24 @@ O((t - I)^3), computed as
     c <- 2 c^2 - 1, r times                         double angle: cos(2 pi (t - 1/4))
     out = c / (2 pi)                                = sin(2 pi t) / (2 pi)
 
+(times an optional factor f folded into the last constant, out_factor, e.g.
+q_0 / Delta to return the message at its own scale)
+
 with T_1 = u, T_2k = 2 T_k^2 - 1, T_2k+1 = 2 T_k T_k+1 - T_1 (relinearised and
-rescaled products, the factor 2 an integer product), each c_k T_k a constant
-product at the scale of the next prime, rescaled, the terms summed in order of
-k (scale of the first), c_0 added last.  The coefficients c_k are an input (the
-caller interpolates them).
+rescaled products, the factor 2 an integer product), c_0 added last, the
+coefficients c_k an input (the caller interpolates them).
+
+Scales.  A sum of two ciphertexts decrypts to x_a + (s_b / s_a) x_b when their
+scales s_a, s_b differ, and rescaling by primes that are only near a power of
+two lets the scales of the T_k drift apart by ~1e-6 relative, which is far
+more than bootstrapping tolerates (the message is the small fraction m / q_0 of
+t).  So every term meets its partner at one scale exactly: a constant factor
+is encoded at the scale c = s_target q / s_x (q the prime the following
+rescale drops), which brings the product to s_target after the rescale
+(mul_const_to).  T_1 enters each odd T_k that way at the product's scale; the
+highest term c_d T_d is taken at the next prime's scale and the other c_k T_k
+are brought to its scale and summed from k = d down.  Constants added with
+add_const are encoded at the ciphertext's own scale and need nothing.
 """
 from __future__ import annotations
 
@@ -35,7 +48,16 @@ def cheb_index_pair(k: int):
     return (k + 1) // 2, k // 2
 
 
-def evalmod(P, x: O.Ct, coeffs, r: int, K: float, rlk) -> O.Ct:
+def mul_const_to(P, x: O.Ct, value: float, target_scale: float) -> O.Ct:
+    """x times `value` encoded at the scale c = target q / s_x (q the prime the
+    next rescale drops): the rescaled product has scale `target_scale`."""
+    q = P.q[x.level - 1]
+    cs = target_scale * q / x.scale
+    k = int(O.round_half_away(np.array([value * cs]))[0])
+    return O.Ct(O.ct_mul_int(P, x, k).c, x.scale * cs)
+
+
+def evalmod(P, x: O.Ct, coeffs, r: int, K: float, rlk, out_factor: float = 1.0) -> O.Ct:
     a = (K + 0.25) / 2 ** r
     d = len(coeffs) - 1
     t = add_const(P, x, -0.25)
@@ -44,18 +66,20 @@ def evalmod(P, x: O.Ct, coeffs, r: int, K: float, rlk) -> O.Ct:
     for k in range(2, d + 1):
         i, j = cheb_index_pair(k)
         p = O.ct_mul_int(P, _mr(P, T[i], T[j], rlk), 2)
-        T[k] = add_const(P, p, -1.0) if i == j else O.ct_sub(P, p, T[1])
-    c = None
-    for k in range(1, d + 1):
-        term = O.rescale(P, mul_const_next(P, T[k], float(coeffs[k])))
-        c = term if c is None else O.ct_add(P, c, term)
+        if i == j:
+            T[k] = add_const(P, p, -1.0)
+        else:
+            T[k] = O.ct_sub(P, p, O.rescale(P, mul_const_to(P, T[1], 1.0, p.scale)))
+    c = O.rescale(P, mul_const_next(P, T[d], float(coeffs[d])))
+    for k in range(d - 1, 0, -1):
+        c = O.ct_add(P, c, O.rescale(P, mul_const_to(P, T[k], float(coeffs[k]), c.scale)))
     c = add_const(P, c, float(coeffs[0]))
     for _ in range(r):
         c = add_const(P, O.ct_mul_int(P, _mr(P, c, c, rlk), 2), -1.0)
-    return O.rescale(P, mul_const_next(P, c, 1.0 / (2 * math.pi)))
+    return O.rescale(P, mul_const_next(P, c, out_factor / (2 * math.pi)))
 
 
-def evalmod_fp64(t, coeffs, r: int, K: float):
+def evalmod_fp64(t, coeffs, r: int, K: float, out_factor: float = 1.0):
     """The same steps on plain FP64 values."""
     a = (K + 0.25) / 2 ** r
     u = (np.asarray(t) - 0.25) / (2 ** r * a)
@@ -64,7 +88,10 @@ def evalmod_fp64(t, coeffs, r: int, K: float):
     for k in range(2, d + 1):
         i, j = cheb_index_pair(k)
         T[k] = 2 * T[i] * T[j] - (1.0 if i == j else T[1])
-    c = sum(float(coeffs[k]) * T[k] for k in range(d + 1))
+    c = float(coeffs[d]) * T[d]
+    for k in range(d - 1, 0, -1):
+        c = c + float(coeffs[k]) * T[k]
+    c = c + float(coeffs[0])
     for _ in range(r):
         c = 2 * c * c - 1
-    return c / (2 * math.pi)
+    return c * (out_factor / (2 * math.pi))

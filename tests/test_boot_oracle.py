@@ -106,3 +106,51 @@ def test_coeffs_to_slots_and_back():
     s2c = [O.encode(P, d, sd, w.level) for d in B.diagonals(B.s2c_matrix(P))]
     back = O.rescale(P, LT.linear_transform(P, w, s2c, sd, list(range(n)), 8, keys))
     assert np.max(np.abs(O.decode(P, O.decrypt(P, s, back), back.scale, n) - z)) < 1e-7
+
+
+def half_boot_setup(logn=7, n1=8, h=16, seed=700):
+    """A one-limb coefficient-encoded ciphertext of v (|v| < 1, Delta = 2^40)
+    over the 50 + 13 x 45-bit chain (4 special primes: the key switches of a
+    ciphertext at scale q_0 need P above each digit), the keys of
+    CoeffsToSlots and of the conjugation, and the diagonals of B/2; with the
+    random inputs each was made from."""
+    from tests.test_evalmod_oracle import coeffs
+    P = O.Params(logn, [50] + [45] * 13, [50] * 4, alpha=4, mod_log2=17)
+    n, delta, sd = P.N // 2, 2.0 ** 40, 2.0 ** 40
+    s = I.ternary_secret(P.N, h, seed)
+    ext = P.ext_mods(P.L)
+
+    def key_inputs(sd_):
+        return I.uniform_residues(ext, P.N, sd_, lead=(P.beta,)), I.gaussian_error((P.beta, P.N), sd_ + 1)
+    steps = sorted({k % n1 for k in range(1, n)} - {0}) + sorted({n1 * (k // n1) for k in range(n)} - {0})
+    gs = sorted({O.galois_element(P, k) for k in steps}) + [2 * P.N - 1]
+    kin = {g: key_inputs(seed + 100 + 2 * i) for i, g in enumerate(gs)}
+    keys = {g: O.galois_key(P, s, g, *kin[g]) for g in gs}
+    rin = key_inputs(seed + 3)
+    rlk = O.relin_key(P, s, *rin)
+    v = I.uniform_slots(P.N, seed + 5)
+    m = O.from_ints(np.round(v * delta).astype(np.int64), P.mods(1))
+    a, e = I.uniform_residues(P.mods(1), P.N, seed + 6), I.gaussian_error(P.N, seed + 7)
+    x = O.encrypt(P, s, m, a, e, delta)
+    c2s = [O.encode(P, d / 2, sd, P.L) for d in B.diagonals(B.c2s_matrix(P))]
+    return dict(P=P, s=s, keys=keys, rlk=rlk, v=v, x=x, c2s=c2s, sd=sd, n1=n1, coeffs=coeffs(),
+                out_factor=P.q[0] / delta, delta=delta, key_inputs=kin, rlk_inputs=rin, enc=(m, a, e))
+
+
+def run_half_boot(d):
+    return B.half_bootstrap(d["P"], d["x"], d["c2s"], d["sd"], d["n1"], d["keys"], d["rlk"], d["coeffs"], 3, 8.0,
+                            d["out_factor"])
+
+
+def test_half_bootstrap_puts_the_coefficients_in_the_slots():
+    # ModRaise, CoeffsToSlots, the conjugate split and EvalMod: slot j decrypts
+    # to v_j + i v_(j+N/2), the message's coefficients, within the scaled
+    # sine's error times q_0 / Delta, at the level the depth leaves
+    d = half_boot_setup()
+    P = d["P"]
+    out = run_half_boot(d)
+    n = P.N // 2
+    got = O.decode(P, O.decrypt(P, d["s"], out), out.scale, n)
+    err = np.max(np.abs(got - (d["v"][:n] + 1j * d["v"][n:])))
+    assert err < 2 ** -14
+    assert out.level == P.L - 1 - (1 + 5 + 1 + 3 + 1)

@@ -206,3 +206,21 @@ def test_evalmod_with_a_wrong_chebyshev_split_is_caught(monkeypatch):
     from oracle import evalmod as EM
     monkeypatch.setattr(EM, "cheb_index_pair", lambda k: (k - 1, 1))
     _expect_fail(TE.test_fp64_steps_are_the_scaled_sine)
+
+
+def test_evalmod_with_unmatched_scales_is_caught(monkeypatch):
+    # constants taken at the next prime's scale whatever the target: the
+    # terms of each sum meet at scales that differ by the primes' offsets
+    from oracle import evalmod as EM
+    monkeypatch.setattr(EM, "mul_const_to", lambda P, x, value, target: EM.mul_const_next(P, x, value))
+    _expect_fail(TE.test_homomorphic_evalmod_decrypts_to_its_fp64_steps, TE.homomorphic_setup())
+
+
+# ---- Half-BTS (oracle/boot.py)
+def test_half_bootstrap_with_the_wrong_imaginary_unit_is_caught(monkeypatch):
+    # X^(N/2) (+i) where the split of the imaginary part needs X^(3N/2) (-i)
+    from oracle import repack as RP
+    from tests import test_boot_oracle as TB
+    orig = RP.ct_monomial
+    monkeypatch.setattr(RP, "ct_monomial", lambda P, x, k: orig(P, x, P.N // 2 if k == 3 * P.N // 2 else k))
+    _expect_fail(TB.test_half_bootstrap_puts_the_coefficients_in_the_slots)
