@@ -378,6 +378,12 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
  *   RESCALE       dst = rescale(a)
  *   ADD_CONST     dst = a + value (pfx_add_const)                value
  *   MUL_CONST     dst = a * value at the last prime's scale      value
+ *   MUL_CONST_TO  dst = a * value, the constant taken at the       value,
+ *                 scale c = scale_b * q_last / scale_a (q_last    b register
+ *                 a's last prime), so that after one RESCALE dst
+ *                 has register b's scale: terms of a sum meet at
+ *                 one scale exactly (App. A.3, EvalMod); only b's
+ *                 scale is read
  *   SCALE_MUL     dst = a with scale * value (value / factor)    value
  *   ROTATE        dst = rotate(a, k)                             k
  *   ROTATE_SUM    dst = InnerSum(a) over 2^k slots               k
@@ -426,6 +432,7 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
 #define PFX_OP_MONO 20
 #define PFX_OP_INV_N 21
 #define PFX_OP_GALOIS 22
+#define PFX_OP_MUL_CONST_TO 23
 
 typedef struct pfx_op {
     int32_t code;

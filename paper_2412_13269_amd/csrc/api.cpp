@@ -340,6 +340,14 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
         case PFX_OP_RESCALE: r = pfx_rescale(c, A, d, stream); break;
         case PFX_OP_ADD_CONST: r = pfx_add_const(c, A, o.value, d, stream); break;
         case PFX_OP_MUL_CONST: r = pfx_mul_const(c, A, o.value, 0.0, d, stream); break;
+        case PFX_OP_MUL_CONST_TO: {
+            const pfx_ct *B = R(o.b);
+            if (!B) return fail(PFX_EINVAL, at + "register index out of range");
+            if (A->n_limbs < 2) return fail(PFX_ELEVEL, at + "no prime left to rescale by");
+            const double cs = B->scale * (double)c->primes[A->n_limbs - 1] / A->scale;
+            r = pfx_mul_const(c, A, o.value, cs, d, stream);
+            break;
+        }
         case PFX_OP_SCALE_MUL: {
             const double sc = A->scale * o.value;
             r = pfx_ct_copy(c, A, d, stream);
@@ -390,7 +398,7 @@ bool ew_code(int32_t code) {
         case PFX_OP_COPY: case PFX_OP_ADD: case PFX_OP_SUB: case PFX_OP_MUL_PLAIN: case PFX_OP_ADD_PLAIN:
         case PFX_OP_MUL_INT: case PFX_OP_MUL: case PFX_OP_MUL_ACC: case PFX_OP_MUL_PLAIN_ACC:
         case PFX_OP_MUL_INT_ACC: case PFX_OP_ADD_CONST: case PFX_OP_MUL_CONST: case PFX_OP_SCALE_MUL:
-        case PFX_OP_DROP: case PFX_OP_MONO: case PFX_OP_INV_N:
+        case PFX_OP_DROP: case PFX_OP_MONO: case PFX_OP_INV_N: case PFX_OP_MUL_CONST_TO:
             return true;
         default:
             return false;
@@ -403,7 +411,7 @@ bool accumulates(int32_t code) {
 
 bool reads_b_reg(int32_t code) {
     return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN || code == PFX_OP_MUL ||
-           code == PFX_OP_MUL_ACC;
+           code == PFX_OP_MUL_ACC || code == PFX_OP_MUL_CONST_TO;
 }
 
 // Registers an op reads (a, a register b, and an accumulator), as indices.
@@ -2431,7 +2439,7 @@ static pfx_status ensure_lanes(pfx_ctx *c) {
 // the fork/join events alone order the list.
 static bool reads_b_register(int32_t code) {
     return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN || code == PFX_OP_MUL ||
-           code == PFX_OP_MUL_ACC;
+           code == PFX_OP_MUL_ACC || code == PFX_OP_MUL_CONST_TO;
 }
 
 static pfx_status check_lanes(const pfx_op *ops, size_t n_ops, size_t n_regs) {

@@ -10,16 +10,23 @@ term:
     c   = sum_k c_k T_k + c_0                    Chebyshev approximation of
                                                  cos(2 pi a u) on [-1, 1]
     c  <- 2 c^2 - 1, r times                     double angle
-    out = c / (2 pi)
+    out = c * f / (2 pi)                         f = out_factor (1 by default)
 
 Every ciphertext product is relinearised and rescaled (MUL_RELIN, RESCALE),
-the factors 2 are integer products (MUL_INT), each c_k T_k a constant product
-at the scale of the next prime (MUL_CONST, RESCALE), the terms summed in order
-of k, constants added with ADD_CONST.  The coefficients are an input (the
-caller interpolates cos(2 pi a x), e.g. at Chebyshev points).  Depth:
-1 + ceil(log2 d) + 1 + r + 1 levels for d = len(coeffs) - 1.
+the factors 2 are integer products (MUL_INT), constants added with ADD_CONST.
+Terms that are added meet at one scale exactly: T_1 enters each odd T_k as
+MUL_CONST_TO(T_1, 1, the product's scale) + RESCALE, c_d T_d is a constant
+product at the next prime's scale (MUL_CONST, RESCALE) and the other c_k T_k
+are brought to its scale (MUL_CONST_TO, RESCALE) and summed from k = d down.
+The coefficients are an input (the caller interpolates cos(2 pi a x), e.g. at
+Chebyshev points).  Depth: 1 + ceil(log2 d) + 1 + r + 1 levels for
+d = len(coeffs) - 1.
 
-Register 0 is the input (read-only); `out` names the result.
+Register 0 is the input (read-only); `out` names the result.  With lanes = n
+the list evaluates n inputs (registers 0 .. n-1) side by side, each op issued
+for every lane in turn, so the lanes' products form runs of independent
+HMult + relin ops that the executor batches into one key switch; `outs` names
+the n results.
 """
 from __future__ import annotations
 
@@ -34,15 +41,30 @@ class EvalModPlan:
     coeffs: list
     r: int = 3
     K: float = 8.0
+    out_factor: float = 1.0
+    lanes: int = 1
     ops: list = field(default_factory=list)
     n_regs: int = 0
     n_inputs: int = 1
     out: int = -1
+    outs: list = field(default_factory=list)
 
     def __post_init__(self):
+        assert self.lanes >= 1
         self._next = 1
         self._build()
-        self.n_regs = self._next
+        n = self.lanes
+        one, self.ops = self.ops, []
+
+        def reg(r, i):                   # register r of the one-lane list, lane i
+            return i if r == 0 else n + (r - 1) * n + i
+        for code, dst, a, b, k, value in one:
+            for i in range(n):
+                self.ops.append((code, reg(dst, i), reg(a, i), reg(b, i) if b >= 0 else b, k, value))
+        self.outs = [reg(self.out, i) for i in range(n)]
+        self.out = self.outs[0]
+        self.n_inputs = n
+        self.n_regs = n + (self._next - 1) * n
         self.reg_degree = [1] * self.n_regs
 
     def _new(self) -> int:
@@ -71,14 +93,17 @@ class EvalModPlan:
             if i == j:
                 self._op(X.OP_ADD_CONST, T[k], T[k], value=-1.0)
             else:
-                self._op(X.OP_SUB, T[k], T[k], T[1])
+                t1 = self._new()                     # T_1 at the product's scale
+                self._op(X.OP_MUL_CONST_TO, t1, T[1], T[k], value=1.0)
+                self._op(X.OP_RESCALE, t1, t1)
+                self._op(X.OP_SUB, T[k], T[k], t1)
         c, term = self._new(), self._new()
-        for k in range(1, d + 1):
-            dst = c if k == 1 else term
-            self._op(X.OP_MUL_CONST, dst, T[k], value=float(self.coeffs[k]))
-            self._op(X.OP_RESCALE, dst, dst)
-            if k > 1:
-                self._op(X.OP_ADD, c, c, term)
+        self._op(X.OP_MUL_CONST, c, T[d], value=float(self.coeffs[d]))
+        self._op(X.OP_RESCALE, c, c)
+        for k in range(d - 1, 0, -1):
+            self._op(X.OP_MUL_CONST_TO, term, T[k], c, value=float(self.coeffs[k]))
+            self._op(X.OP_RESCALE, term, term)
+            self._op(X.OP_ADD, c, c, term)
         self._op(X.OP_ADD_CONST, c, c, value=float(self.coeffs[0]))
         for _ in range(self.r):
             sq = self._new()
@@ -88,7 +113,7 @@ class EvalModPlan:
             self._op(X.OP_ADD_CONST, sq, sq, value=-1.0)
             c = sq
         self.out = self._new()
-        self._op(X.OP_MUL_CONST, self.out, c, value=1.0 / (2 * math.pi))
+        self._op(X.OP_MUL_CONST, self.out, c, value=self.out_factor / (2 * math.pi))
         self._op(X.OP_RESCALE, self.out, self.out)
 
     @property

@@ -50,6 +50,9 @@ def interpret(plan, inputs, pts):
             r = A + value
         elif code == X.OP_MUL_CONST:
             r = A * value
+        elif code == X.OP_MUL_CONST_TO:
+            assert b in reg                      # the register whose scale is the target
+            r = A * value
         elif code == X.OP_SCALE_MUL:
             r = A / value
         elif code == X.OP_ROTATE_SUM:
