@@ -18,8 +18,30 @@ level for CoeffsToSlots plus EvalMod's.
 """
 from __future__ import annotations
 
+import numpy as np
+
 from . import pfx as X
 from .evalmod import EvalModPlan
+
+
+def c2s_half_diagonals(N: int):
+    """The N/2 generalised diagonals of B/2, B[j, l] = (2/N) zeta_l^(-j) with
+    zeta_l = exp(i pi 5^l / N) the slot roots (App. A.4: B maps the slots to
+    w_j = m_j + i m_(j+N/2)); diagonal k holds B[j, (j + k) mod N/2] / 2 at slot
+    j, so B z / 2 = sum_k d_k (.) rot(z, k)."""
+    n = N // 2
+    five = np.empty(n, dtype=np.int64)
+    five[0] = 1
+    for l in range(1, n):
+        five[l] = five[l - 1] * 5 % (2 * N)
+    j = np.arange(n)
+    out = []
+    for k in range(n):
+        l = (j + k) % n
+        # zeta_l^(-j) = exp(-i pi 5^l j / N), the exponent reduced mod 2N
+        e = (five[l] * j) % (2 * N)
+        out.append(np.exp(-1j * np.pi * e / N) / N)
+    return out
 
 
 class HalfBootPlan:

@@ -66,3 +66,14 @@ def test_evalmod_lanes_pair_the_products():
         assert j == i + 1
         a, b = ops[i], ops[j]
         assert a[1] not in (b[2], b[3]) and b[1] not in (a[2], a[3]) and a[1] != b[1]
+
+
+def test_c2s_half_diagonals_are_half_the_oracle_matrix_diagonals():
+    from oracle import boot as B
+    from oracle import ckks as O
+    from paper_2412_13269_amd.boot import c2s_half_diagonals
+    P = O.Params(7, [50, 45], [50], alpha=1, mod_log2=17)
+    got = c2s_half_diagonals(P.N)
+    want = B.diagonals(B.c2s_matrix(P))
+    assert len(got) == len(want) == P.N // 2
+    assert max(np.max(np.abs(g - w / 2)) for g, w in zip(got, want)) < 1e-15
