@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "linear.h"
 
 using namespace pfx;
 
@@ -2121,8 +2122,8 @@ pfx_status pfx_linear_transform(pfx_ctx *c, const pfx_ct *a, const pfx_pt *const
     r = get_ws(c, S(stream), w);
     if (r) return r;
     const size_t N = c->N, cs = 2 * (size_t)lv * N;
-    double *buf = nullptr;                     // baby rotations, the group sum, its rotation, a plaintext
-    r = get_repack_ws(c, S(stream), (babies.size() + 2) * cs + (size_t)lv * N, &buf);
+    double *buf = nullptr;                     // baby rotations, the group sum, its rotation
+    r = get_repack_ws(c, S(stream), (babies.size() + 2) * cs, &buf);
     if (r) return r;
     auto view = [&](double *d, uint32_t deg, double scale) {
         pfx_ct v;
@@ -2137,7 +2138,6 @@ pfx_status pfx_linear_transform(pfx_ctx *c, const pfx_ct *a, const pfx_pt *const
     std::vector<pfx_ct> bv;
     for (size_t b = 0; b < babies.size(); ++b) bv.push_back(view(buf + b * cs, 1, a->scale));
     pfx_ct acc = view(buf + babies.size() * cs, 1, 0.0), rot = view(buf + (babies.size() + 1) * cs, 1, 0.0);
-    double *ptd = buf + (babies.size() + 2) * cs;
     if (!babies.empty()) {
         std::vector<pfx_ct *> bo;
         for (pfx_ct &v : bv) bo.push_back(&v);
@@ -2150,22 +2150,27 @@ pfx_status pfx_linear_transform(pfx_ctx *c, const pfx_ct *a, const pfx_pt *const
     };
     Launch L{c, S(stream)};
     bool first = true;
+    std::vector<size_t> terms;
     for (int64_t j : giants) {
-        const uint32_t g_back = rot_element(c, half - (int64_t)n1 * j);    // rot(d, -n1 j)
-        bool any = false;
-        for (size_t k = 0; k < n; ++k) {
-            if (st[k] / n1 != j) continue;
-            pfx_ct pv = view(ptd, 0, diags[k]->scale);
-            const pfx_pt *pt = diags[k];
-            if (g_back != 1) {
-                launch_automorph(L, ptd, diags[k]->d, 0, 0, 1, (int)lv, g_back);
-                pt = &pv;
+        // sum_k rot(d_k, -n1 j) (.) rot(z, i_k) over the group, up to kMacTerms
+        // terms a launch, the plaintext automorphism applied as the terms are read
+        const uint32_t g_back = rot_element(c, half - (int64_t)n1 * j);
+        terms.clear();
+        for (size_t k = 0; k < n; ++k)
+            if (st[k] / n1 == j) terms.push_back(k);
+        for (size_t t0 = 0; t0 < terms.size(); t0 += kMacTerms) {
+            MacTerms m{};
+            const int nt = (int)std::min<size_t>(kMacTerms, terms.size() - t0);
+            for (int u = 0; u < nt; ++u) {
+                const size_t k = terms[t0 + u];
+                const pfx_ct *b = baby(st[k] % n1);
+                m.pt[u] = diags[k]->d;
+                m.ct[u] = b->d;
+                m.cs[u] = (size_t)b->cap_limbs * N;
             }
-            r = any ? pfx_mul_plain_acc(c, baby(st[k] % n1), pt, &acc, stream)
-                    : pfx_mul_plain(c, baby(st[k] % n1), pt, &acc, stream);
-            if (r) return r;
-            any = true;
+            launch_diag_mac(L, acc.d, (size_t)acc.cap_limbs * N, m, nt, (int)lv, g_back, t0 > 0);
         }
+        acc.scale = a->scale * diags[0]->scale;
         const pfx_ct *part = &acc;
         if (j) {
             r = pfx_rotate(c, &acc, (int32_t)(n1 * j), keys, n_keys, &rot, stream);

@@ -1,0 +1,50 @@
+// Group sums of the BSGS plaintext-matrix product (App. A.4): for one giant
+// step j the terms phi_g(d_k) (.) rot(z, i_k) are summed in one pass, each
+// thread owning one coefficient of one limb and reading every term's residue
+// there, instead of a plaintext automorphism and a product launch per term.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "linear.h"
+#include "modarith.h"
+#include "ntt_core.h"
+
+namespace pfx {
+
+__global__ void __launch_bounds__(256) k_diag_mac(double *out, size_t so, const MacTerms m, int n_terms, int nl,
+                                                  int logn, uint32_t g, int accumulate, const PrimeDev *pr) {
+    const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (idx >= ((size_t)nl << logn)) return;
+    const uint32_t x = (uint32_t)(idx & ((1u << logn) - 1));
+    const size_t row = idx - x;                       // i N
+    const int i = (int)(idx >> logn);
+    const double q = pr[i].q, qi = pr[i].qinv;
+    const uint32_t src = g == 1 ? x : galois_src(x, logn, g);
+    double s0 = accumulate ? out[idx] : 0.0;
+    double s1 = accumulate ? out[so + idx] : 0.0;
+    for (int t = 0; t < n_terms; ++t) {
+        const double w = m.pt[t][row + src];
+        const double *c = m.ct[t];
+        s0 = madd(s0, mmul(c[idx], w, q, qi), q);
+        s1 = madd(s1, mmul(c[m.cs[t] + idx], w, q, qi), q);
+    }
+    out[idx] = s0;
+    out[so + idx] = s1;
+}
+
+void launch_diag_mac(const Launch &L, double *out, size_t so, const MacTerms &m, int n_terms, int nl, uint32_t g,
+                     bool accumulate) {
+    const size_t total = (size_t)nl << L.ctx->logn;
+    hipEvent_t ev;
+    prof_begin(L, "diag_mac", &ev);
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    k_diag_mac<<<blocks, 256, 0, L.st>>>(out, so, m, n_terms, nl, L.ctx->logn, g, accumulate ? 1 : 0,
+                                         L.ctx->d_primes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) set_error(std::string("kernel launch: ") + hipGetErrorString(e));
+    prof_end(L, "diag_mac", ev, 8.0 * (double)total * (3.0 * n_terms + (accumulate ? 4.0 : 2.0)));
+}
+
+}  // namespace pfx
