@@ -365,69 +365,37 @@ def pfe_form(X, args, big, big_sk, big_st):
 
 
 def half_boot_form(X, I, args):
-    """Half-BTS (Sec. 4.3, App. A.3-A.4) at N = 2^12 over the 50 + 13 x 45-bit
-    chain (4 special primes): ModRaise, dense CoeffsToSlots (2048 diagonals,
-    n1 = 64: 63 hoisted baby steps, 31 giant steps), the conjugate split and two
-    EvalMod lanes (degree 24, r = 3)."""
-    from numpy.polynomial import chebyshev as _cheb
-    from paper_2412_13269_amd import boot as HB
-    logn, qb, pb, alpha, n1 = 12, [50] + [45] * 13, [50] * 4, 4, 64
-    ctx = X.pfx_ctx_create(X.make_params(logn, qb, pb, alpha, 17), 0)
-    st = X.pfx_stream_create(ctx)
-    N, L = 1 << logn, len(qb)
-    q, pr, _ = X.pfx_ctx_moduli(ctx, L, len(pb))
-    ext = [int(v) for v in q] + [int(v) for v in pr]
-    beta = -(-L // alpha)
-    sk = X.pfx_sk_create(ctx, I.ternary_secret(N, 32, 801))
-    n = N // 2
-    steps = sorted({k % n1 for k in range(1, n)} - {0}) + sorted({n1 * (k // n1) for k in range(n)} - {0})
-    gs = sorted({pow(5, k, 2 * N) for k in steps}) + [2 * N - 1]
-    log(f"half-BTS keygen ({len(gs)} Galois keys) ...")
-    gks = [X.pfx_swk_create(ctx, sk, g, I.uniform_residues(ext, N, 900 + 2 * i, lead=(beta,)),
-                            I.gaussian_error((beta, N), 901 + 2 * i)) for i, g in enumerate(gs)]
-    rlk = X.pfx_swk_create(ctx, sk, 0, I.uniform_residues(ext, N, 802, lead=(beta,)),
-                           I.gaussian_error((beta, N), 803))
-    delta, sd = 2.0 ** 40, 2.0 ** 40
-    diags = [X.pfx_encode(ctx, d.real, d.imag, L, sd) for d in HB.c2s_half_diagonals(N)]
-    a = (8.0 + 0.25) / 8
-    plan = HB.HalfBootPlan(N, _cheb.chebinterpolate(lambda v: np.cos(2 * np.pi * a * v), 24), 3, 8.0,
-                           float(q[0]) / delta)
-    regs = [X.pfx_ct_create(ctx, L, 1) for _ in range(plan.n_regs)]
-    x = X.pfx_ct_create(ctx, 1, 1)
-    v = I.uniform_slots(N, 804)
-    m = np.mod(np.round(v * delta).astype(np.int64), np.int64(q[0])).astype(np.uint64)[None, :]
-    pt = X.pfx_pt_import(ctx, m, delta)
-    X.pfx_encrypt(ctx, sk, pt, I.uniform_residues([int(q[0])], N, 805), I.gaussian_error(N, 806), x)
-    X.pfx_ct_destroy(pt)
-
-    def run():
-        HB.half_bootstrap(ctx, x, L, float(q[0]), diags, n1, gks, rlk, plan, regs, st)
-    run()
-    X.pfx_sync(ctx, st)
+    """Half-BTS (Sec. 4.3, App. A.3-A.4) at N = 2^12 (workload.HalfBtsWorkload):
+    ModRaise, dense CoeffsToSlots, the conjugate split and two EvalMod lanes;
+    the op-list part eagerly and as a replayed HIP graph."""
+    from paper_2412_13269_amd.workload import HalfBtsWorkload
+    w = HalfBtsWorkload(log=log)
     reps = 5
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        run()
-    X.pfx_sync(ctx, st)
-    t_all = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        X.pfx_run_circuit(ctx, plan.ops, regs, plan.n_inputs, [], rlk, gks, X.RUN_EAGER, st)
-    X.pfx_sync(ctx, st)
-    t_em = (time.perf_counter() - t0) / reps
-    log(f"half-BTS at N=2^12: {1e3 * t_all:.2f} ms ({1e3 * (t_all - t_em):.2f} ms ModRaise + CoeffsToSlots, "
-        f"{1e3 * t_em:.2f} ms conjugate split + 2 EvalMod)")
-    for h in regs + diags + [x]:
-        X.pfx_ct_destroy(h)
-    for k in gks + [rlk]:
-        X.pfx_swk_destroy(k)
-    X.pfx_sk_destroy(sk)
-    X.pfx_stream_destroy(ctx, st)
-    X.pfx_ctx_destroy(ctx)
-    return {"N": N, "limbs": L, "special_primes": len(pb), "diagonals": n, "n1": n1, "galois_keys": len(gs),
-            "evalmod_degree": 24, "double_angles": 3, "depth": plan.depth, "reps": reps,
-            "ms_per_half_bts": 1e3 * t_all, "ms_mod_raise_and_c2s": 1e3 * (t_all - t_em),
-            "ms_split_and_evalmod": 1e3 * t_em}
+    res = {}
+    for mode, name in ((X.RUN_EAGER, "eager"), (X.RUN_GRAPH, "graph")):
+        w.run(mode)
+        w.sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            w.run(mode)
+        w.sync()
+        t_all = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            w.run_circuit(mode)
+        w.sync()
+        res[name] = (t_all, (time.perf_counter() - t0) / reps)
+    words = {m: w.result_words(m) for m in (X.RUN_EAGER, X.RUN_GRAPH)}
+    assert np.array_equal(words[X.RUN_EAGER], words[X.RUN_GRAPH]), "Half-BTS eager and graph disagree"
+    best = min(res, key=lambda k: res[k][0])
+    t_all, t_em = res[best]
+    log(f"half-BTS at N=2^12: {1e3 * t_all:.2f} ms ({best}; {1e3 * (t_all - t_em):.2f} ms ModRaise + "
+        f"CoeffsToSlots, {1e3 * t_em:.2f} ms conjugate split + 2 EvalMod); eager {1e3 * res['eager'][0]:.2f} ms")
+    out = dict(w.describe(), reps=reps, best=best, ms_per_half_bts=1e3 * t_all,
+               ms_mod_raise_and_c2s=1e3 * (t_all - t_em), ms_split_and_evalmod=1e3 * t_em,
+               ms_per_half_bts_by_mode={k: 1e3 * v[0] for k, v in res.items()})
+    w.close()
+    return out
 
 
 def main():

@@ -76,14 +76,17 @@ class HalfBootPlan:
         self.depth = 1 + em.depth
 
 
-def half_bootstrap(ctx, x, n_limbs: int, q0: float, diags, n1: int, gks, rlk, plan: HalfBootPlan, regs, stream=None):
+def half_bootstrap(ctx, x, n_limbs: int, q0: float, diags, n1: int, gks, rlk, plan: HalfBootPlan, regs, stream=None,
+                   mode: int = X.RUN_EAGER):
     """x: one limb, coefficient-encoded; diags: the N/2 plaintext diagonals of
     B/2; gks: the Galois keys of the BSGS steps and of 2N - 1; regs: plan.n_regs
     ciphertexts of n_limbs limbs (register 0 receives the CoeffsToSlots
-    product).  Returns regs[plan.out]."""
+    product); mode: how pfx_run_circuit runs the op list (RUN_GRAPH captures
+    it on the first call for these registers and replays it after).  Returns
+    regs[plan.out]."""
     half = len(diags)
     X.pfx_mod_raise(ctx, x, n_limbs, regs[1], stream)
     X.pfx_ct_set_scale(regs[1], q0)
     X.pfx_linear_transform(ctx, regs[1], diags, list(range(half)), n1, gks, regs[0], stream)
-    X.pfx_run_circuit(ctx, plan.ops, regs, plan.n_inputs, [], rlk, gks, X.RUN_EAGER, stream)
+    X.pfx_run_circuit(ctx, plan.ops, regs, plan.n_inputs, [], rlk, gks, mode, stream)
     return regs[plan.out]

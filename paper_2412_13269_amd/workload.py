@@ -16,7 +16,8 @@ private query on 2^17 records (4 blocks of 2^15, 8 attributes, degree-7 score,
 (7,7,7) sign, InnerSum), blocks interleaved on one stream, eagerly, `--steps`
 times after one warm-up run.  `--pfe` runs the private lookup-table
 evaluation with ring repacking (PfeWorkload) `--steps` times after one
-warm-up run.  `--calibrate` first imports
+warm-up run.  `--half-bts [--graph]` runs Half-BTS at N = 2^12
+(HalfBtsWorkload) likewise.  `--calibrate` first imports
 one ciphertext five times: the library's plain word-to-double copy
 (k_u64_to_f64) of one polynomial per launch, 24 limbs = 12 MiB read and 12 MiB
 written, the reference against which HBM counters are scaled.
@@ -223,6 +224,92 @@ class PfeWorkload:
         X.pfx_ctx_destroy(self.ctx)
 
 
+class HalfBtsWorkload:
+    """Half-BTS (Sec. 4.3, App. A.3-A.4) at N = 2^12 over the 50 + 13 x 45-bit
+    chain with 4 special primes: a one-limb coefficient-encoded ciphertext,
+    the 95 Galois keys of CoeffsToSlots (n1 = 64: 63 baby steps, 31 giant
+    steps) and of the conjugation, the relinearisation key, the 2048
+    diagonals of B/2 and the op list of the rest (degree-24 EvalMod, r = 3),
+    all made by the library from seeded inputs."""
+
+    def __init__(self, log=print):
+        import numpy as np
+        from numpy.polynomial import chebyshev as _cheb
+
+        from . import boot as HB
+        from . import inputs as I
+        from . import pfx as X
+        self.HB, self.X = HB, X
+        logn, qb, pb, alpha, self.n1 = 12, [50] + [45] * 13, [50] * 4, 4, 64
+        self.qb, self.pb = qb, pb
+        self.ctx = X.pfx_ctx_create(X.make_params(logn, qb, pb, alpha, 17), 0)
+        self.st = X.pfx_stream_create(self.ctx)
+        N, L = 1 << logn, len(qb)
+        self.N, self.L = N, L
+        q, pr, _ = X.pfx_ctx_moduli(self.ctx, L, len(pb))
+        self.q0 = float(q[0])
+        ext = [int(v) for v in q] + [int(v) for v in pr]
+        beta = -(-L // alpha)
+        self.sk = X.pfx_sk_create(self.ctx, I.ternary_secret(N, 32, 801))
+        n = N // 2
+        steps = sorted({k % self.n1 for k in range(1, n)} - {0}) + \
+            sorted({self.n1 * (k // self.n1) for k in range(n)} - {0})
+        gs = sorted({pow(5, k, 2 * N) for k in steps}) + [2 * N - 1]
+        log(f"half-BTS keygen ({len(gs)} Galois keys) ...")
+        self.gks = [X.pfx_swk_create(self.ctx, self.sk, g, *key_inputs(ext, N, beta, 900 + 2 * i))
+                    for i, g in enumerate(gs)]
+        self.rlk = X.pfx_swk_create(self.ctx, self.sk, 0, *key_inputs(ext, N, beta, 802))
+        delta, sd = 2.0 ** 40, 2.0 ** 40
+        self.diags = [X.pfx_encode(self.ctx, d.real, d.imag, L, sd) for d in HB.c2s_half_diagonals(N)]
+        a = (8.0 + 0.25) / 8
+        self.plan = HB.HalfBootPlan(N, _cheb.chebinterpolate(lambda v: np.cos(2 * np.pi * a * v), 24), 3, 8.0,
+                                    self.q0 / delta)
+        # one register set per mode: a captured graph stays bound to its registers
+        self.regs = {m: [X.pfx_ct_create(self.ctx, L, 1) for _ in range(self.plan.n_regs)]
+                     for m in (X.RUN_EAGER, X.RUN_GRAPH)}
+        self.x = X.pfx_ct_create(self.ctx, 1, 1)
+        v = I.uniform_slots(N, 804)
+        m = np.mod(np.round(v * delta).astype(np.int64), np.int64(q[0])).astype(np.uint64)[None, :]
+        pt = X.pfx_pt_import(self.ctx, m, delta)
+        X.pfx_encrypt(self.ctx, self.sk, pt, I.uniform_residues([int(q[0])], N, 805), I.gaussian_error(N, 806),
+                      self.x)
+        X.pfx_ct_destroy(pt)
+        self.galois_keys = len(gs)
+
+    def run(self, mode=0):
+        """mode: RUN_EAGER (0) or RUN_GRAPH for the op-list part."""
+        self.HB.half_bootstrap(self.ctx, self.x, self.L, self.q0, self.diags, self.n1, self.gks, self.rlk,
+                               self.plan, self.regs[mode], self.st, mode)
+
+    def run_circuit(self, mode=0):
+        self.X.pfx_run_circuit(self.ctx, self.plan.ops, self.regs[mode], self.plan.n_inputs, [], self.rlk, self.gks,
+                          mode, self.st)
+
+    def result_words(self, mode):
+        return self.X.pfx_ct_export(self.ctx, self.regs[mode][self.plan.out], self.N, self.st)
+
+    def sync(self):
+        self.X.pfx_sync(self.ctx, self.st)
+
+    def describe(self):
+        return {"N": self.N, "limbs": self.L, "special_primes": len(self.pb), "diagonals": self.N // 2,
+                "n1": self.n1, "galois_keys": self.galois_keys, "evalmod_degree": 24, "double_angles": 3,
+                "depth": self.plan.depth}
+
+    def close(self):
+        X = self.X
+        for regs in self.regs.values():
+            for h in regs:
+                X.pfx_ct_destroy(h)
+        for h in self.diags + [self.x]:
+            X.pfx_ct_destroy(h)
+        for k in self.gks + [self.rlk]:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(self.sk)
+        X.pfx_stream_destroy(self.ctx, self.st)
+        X.pfx_ctx_destroy(self.ctx)
+
+
 def calibrate_copy_standalone(reps=5):
     """The copy of KsWorkload.calibrate_copy (k_u64_to_f64 over 24 limbs of
     N = 2^16: 12 MiB in, 12 MiB out per launch, two per import) on a context of
@@ -246,7 +333,21 @@ def main():
     ap.add_argument("--calibrate", action="store_true")
     ap.add_argument("--query", action="store_true")
     ap.add_argument("--pfe", action="store_true")
+    ap.add_argument("--half-bts", action="store_true")
+    ap.add_argument("--graph", action="store_true")
     args = ap.parse_args()
+    if args.half_bts:
+        from . import pfx as X
+        mode = X.RUN_GRAPH if args.graph else X.RUN_EAGER
+        w = HalfBtsWorkload(log=lambda *a: print(*a, flush=True))
+        w.run(mode)
+        w.sync()
+        for _ in range(args.steps):
+            w.run(mode)
+        w.sync()
+        print(f"{args.steps} Half-BTS runs done at N=2^12", flush=True)
+        w.close()
+        return
     if args.pfe:
         import time
         if args.calibrate:

@@ -83,6 +83,19 @@ def test_half_bootstrap_matches_oracle(X):
         out = HB.half_bootstrap(ctx, x, P.L, float(P.q[0]), diags, d["n1"], gks, rlk, plan, regs)
         assert np.array_equal(X.pfx_ct_export(ctx, out, P.N), want.c)
         assert X.pfx_ct_info(out).scale == want.scale
+        # the op-list part captured into a HIP graph on the first call and
+        # replayed, ModRaise and CoeffsToSlots run eagerly between replays
+        gregs = [X.pfx_ct_create(ctx, P.L, 1) for _ in range(plan.n_regs)]
+        handles += gregs
+        stream = X.pfx_stream_create(ctx)
+        try:
+            for rep in range(3):
+                out = HB.half_bootstrap(ctx, x, P.L, float(P.q[0]), diags, d["n1"], gks, rlk, plan, gregs, stream,
+                                        X.RUN_GRAPH)
+                X.pfx_sync(ctx, stream)
+                assert np.array_equal(X.pfx_ct_export(ctx, out, P.N), want.c), rep
+        finally:
+            X.pfx_stream_destroy(ctx, stream)
         n = P.N // 2
         got = O.decode(P, O.decrypt(P, d["s"], want), want.scale, n)
         # the scaled sine's error (< 1e-6 on [-8, 8]) times q_0 / Delta = 2^10
