@@ -339,9 +339,11 @@ def main():
     if args.half_bts:
         from . import pfx as X
         mode = X.RUN_GRAPH if args.graph else X.RUN_EAGER
+        import time
         w = HalfBtsWorkload(log=lambda *a: print(*a, flush=True))
         w.run(mode)
         w.sync()
+        time.sleep(0.5)  # an idle gap that marks the end of the setup in kernel traces
         for _ in range(args.steps):
             w.run(mode)
         w.sync()
