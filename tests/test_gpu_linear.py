@@ -121,3 +121,29 @@ def test_dense_coeffs_to_slots_matches_oracle(X):
             X.pfx_swk_destroy(k)
         X.pfx_sk_destroy(sk)
         X.pfx_ctx_destroy(ctx)
+
+
+def test_linear_transform_group_beyond_one_launch(pair, X):
+    # 70 diagonals in one giant-step group (n1 = 128): the group sum takes two
+    # multiply-accumulate launches of at most 64 terms, the second adding to
+    # the first; a second group (steps 128 + i) rotated by 128
+    P = pair.P
+    if P.logn != 12:
+        pytest.skip("one ring degree suffices")
+    n1 = 128
+    steps = list(range(70)) + [128 + i for i in (0, 3, 65)]
+    for k in _needed(P, steps, n1):
+        pair.key(O.galois_element(P, k))
+    co, cx, z = pair.enc(P.L)
+    half = P.N // 2
+    ds = [(I.uniform_slots(half, 800 + k) + 1j * I.uniform_slots(half, 900 + k)) / len(steps)
+          for k in range(len(steps))]
+    words = [O.encode(P, d, pair.scale, P.L) for d in ds]
+    pts = []
+    for w in words:
+        pts.append(X.pfx_pt_import(pair.ctx, w, pair.scale))
+        pair.handles.append(pts[-1])
+    out = pair.ct(P.L, deg=1)
+    X.pfx_linear_transform(pair.ctx, cx, pts, steps, n1, list(pair.kx.values()), out)
+    want = LT.linear_transform(P, co, words, pair.scale, steps, n1, pair.ko)
+    pair.same(want, out)
