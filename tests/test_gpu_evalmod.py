@@ -60,3 +60,35 @@ def test_evalmod_plan_matches_oracle(X):
         X.pfx_sk_destroy(sk)
         X.pfx_stream_destroy(ctx, stream)
         X.pfx_ctx_destroy(ctx)
+
+
+def test_mul_const_to_checks(X):
+    # MUL_CONST_TO: the target register must exist, and a one-limb operand has
+    # no prime left to rescale by
+    logn = 12
+    P = O.Params(logn, QB[:3], PB, alpha=ALPHA, mod_log2=ML)
+    ctx = X.pfx_ctx_create(X.make_params(logn, QB[:3], PB, ALPHA, ML), 0)
+    sk = X.pfx_sk_create(ctx, I.ternary_secret(P.N, 192, 81))
+    regs = [X.pfx_ct_create(ctx, P.L, 1) for _ in range(3)]
+    try:
+        for lv, reg in ((P.L, regs[0]), (1, regs[1])):
+            m = O.encode(P, I.uniform_slots(P.N // 2, 82), DELTA, lv)
+            pt = X.pfx_pt_import(ctx, m, DELTA)
+            X.pfx_encrypt(ctx, sk, pt, I.uniform_residues(P.mods(lv), P.N, 83), I.gaussian_error(P.N, 84), reg)
+            X.pfx_ct_destroy(pt)
+        with pytest.raises(X.PfxError) as e:
+            X.pfx_run_circuit(ctx, [(X.OP_MUL_CONST_TO, 2, 0, 7, 0, 0.5)], regs, 2, [], None, [])
+        assert e.value.status == X.PFX_EINVAL
+        with pytest.raises(X.PfxError) as e:
+            X.pfx_run_circuit(ctx, [(X.OP_MUL_CONST_TO, 2, 1, 0, 0, 0.5)], regs, 2, [], None, [])
+        assert e.value.status == X.PFX_ELEVEL
+        # the product of a full-level operand, rescaled, carries register 0's scale
+        X.pfx_run_circuit(ctx, [(X.OP_MUL_CONST_TO, 2, 0, 0, 0, 0.5), (X.OP_RESCALE, 2, 2, -1, 0, 0.0)],
+                          regs, 2, [], None, [])
+        got, want = X.pfx_ct_info(regs[2]).scale, X.pfx_ct_info(regs[0]).scale
+        assert abs(got / want - 1) < 1e-15 and X.pfx_ct_info(regs[2]).n_limbs == P.L - 1
+    finally:
+        for h in regs:
+            X.pfx_ct_destroy(h)
+        X.pfx_sk_destroy(sk)
+        X.pfx_ctx_destroy(ctx)
