@@ -340,6 +340,9 @@ def main():
         from . import pfx as X
         mode = X.RUN_GRAPH if args.graph else X.RUN_EAGER
         import time
+        if args.calibrate:
+            calibrate_copy_standalone()
+            print("copy calibration done", flush=True)
         w = HalfBtsWorkload(log=lambda *a: print(*a, flush=True))
         w.run(mode)
         w.sync()
