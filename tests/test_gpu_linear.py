@@ -123,13 +123,20 @@ def test_dense_coeffs_to_slots_matches_oracle(X):
         X.pfx_ctx_destroy(ctx)
 
 
-def test_linear_transform_group_beyond_one_launch(pair, X):
+@pytest.fixture(scope="module")
+def pair_c1(X):
+    cfg = CONFIGS["c1"]
+    p = Pair(X, cfg["logn"], cfg["qb"], cfg["pb"], cfg["alpha"], cfg["ml"], cfg["h"], seed=37, scale=cfg["scale"])
+    yield p
+    p.close()
+
+
+def test_linear_transform_group_beyond_one_launch(pair_c1, X):
     # 70 diagonals in one giant-step group (n1 = 128): the group sum takes two
     # multiply-accumulate launches of at most 64 terms, the second adding to
-    # the first; a second group (steps 128 + i) rotated by 128
+    # the first; a second group (steps 128 + i) rotated by 128 (N = 2^12)
+    pair = pair_c1
     P = pair.P
-    if P.logn != 12:
-        pytest.skip("one ring degree suffices")
     n1 = 128
     steps = list(range(70)) + [128 + i for i in (0, 3, 65)]
     for k in _needed(P, steps, n1):
