@@ -142,7 +142,15 @@ def batched_form(X, I, ctx16, rlk16, st, args):
     outs = [X.pfx_ct_create(ctxs[ln], lv, 1) for ln, lv in shapes]
     bargs = ([ctxs[ln] for ln, _ in shapes], [cut[(ln, lv, 0)] for ln, lv in shapes],
              [cut[(ln, lv, 1)] for ln, lv in shapes], [rlks[ln] for ln, _ in shapes], outs)
-    res = {}
+    def digest():
+        """SHA-256 over every output's canonical words (entry order)."""
+        import hashlib
+        h = hashlib.sha256()
+        for (ln, _), o in zip(shapes, outs):
+            h.update(X.pfx_ct_export(ctxs[ln], o, 1 << ln, st).tobytes())
+        return h.hexdigest()
+
+    res, digests = {}, {}
     reps = max(2, args.steps // 10)
     for mode in (0, 1, 2, 3, 4):
         X.pfx_batch_mul_relin_rescale(*bargs, mode, st)      # warm (and capture for modes 2, 4)
@@ -152,6 +160,10 @@ def batched_form(X, I, ctx16, rlk16, st, args):
             X.pfx_batch_mul_relin_rescale(*bargs, mode, st)
         X.pfx_sync(ctx16, st)
         res[mode] = (time.perf_counter() - a0) / reps
+        digests[mode] = digest()
+    identical = len(set(digests.values())) == 1
+    if not identical:
+        raise SystemExit(f"batched form: modes give different words: {digests}")
     log(f"batched 256: per-ct {1e3 * res[0]:.2f} ms, lanes {1e3 * res[1]:.2f} ms, graph {1e3 * res[2]:.2f} ms, "
         f"grouped lanes {1e3 * res[3]:.2f} ms, grouped graph {1e3 * res[4]:.2f} ms")
     for h in outs + list(cut.values()) + list(base.values()):
@@ -166,7 +178,7 @@ def batched_form(X, I, ctx16, rlk16, st, args):
             "levels": [3, 24], "reps": reps,
             "ms_per_ct_launch_path": 1e3 * res[0], "ms_lanes": 1e3 * res[1], "ms_graph": 1e3 * res[2],
             "ms_grouped_lanes": 1e3 * res[3], "ms_grouped_graph": 1e3 * res[4],
-            "shape_groups": len(set(shapes)),
+            "modes_identical": identical, "shape_groups": len(set(shapes)),
             "us_per_ct_launch_path": 1e6 * res[0] / 256, "us_per_ct_best": 1e6 * min(res.values()) / 256,
             "speedup_best_vs_launch_path": res[0] / min(res.values())}
 

@@ -485,3 +485,98 @@ def test_full_size_standalone_ntt_offset_primes(full, X, inverse):
     fn = O.intt if inverse else O.ntt
     for b in range(3):
         assert np.array_equal(got[b], fn(words[b], mods, psis, P.logn)), b
+
+
+# ------------------------------------------------------------------ N = 2^15 on the 24-limb chain
+# The middle ring degree of the batched workload: its column and row passes
+# are 7 and 8 stages (the other tested rings have equal halves or fewer
+# stages), with their own twiddle tables.
+@pytest.fixture(scope="module")
+def mid(X):
+    p = Pair(X, 15, [50] + [45] * 23, [50] * 4, 4, 17, h=192, seed=215)
+    yield p
+    p.close()
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+def test_n15_standalone_ntt_every_prime(mid, X, inverse):
+    P = mid.P
+    mods, psis = P.q + P.p, P.psi_q + P.psi_p
+    words = I.uniform_residues(mods, P.N, 1517)
+    dev = X.pfx_dev_alloc(mid.ctx, words.nbytes)
+    X.pfx_memcpy_htod(mid.ctx, dev, words)
+    X.pfx_ntt(mid.ctx, dev, 0, len(mods), 1, inverse)
+    got = np.empty_like(words)
+    X.pfx_memcpy_dtoh(mid.ctx, got, dev)
+    X.pfx_dev_free(mid.ctx, dev)
+    fn = O.intt if inverse else O.ntt
+    assert np.array_equal(got, fn(words, mods, psis, P.logn))
+
+
+def test_n15_key_switch_at_partial_levels(mid, X):
+    """Whole digits (4, 24 limbs), a partial last digit (1, 2, 3, 5, 13) on the
+    N = 2^15 ring, against the oracle's ModUp / inner product / ModDown."""
+    P = mid.P
+    ko, kx = mid.key(0)
+    for lv in (1, 2, 3, 4, 5, 13, 24):
+        d = I.uniform_residues(P.mods(lv), P.N, 1500 + lv)
+        dx = mid.ct(lv)
+        X.pfx_ct_import(mid.ctx, d[None], 1.0, dx)
+        out = mid.ct(lv)
+        X.pfx_key_switch(mid.ctx, dx, kx, out)
+        k0, k1 = O.key_switch(P, d, ko)
+        w = mid.words(out)
+        assert np.array_equal(w[0], k0) and np.array_equal(w[1], k1), lv
+
+
+def test_n15_mul_relin_rescale_rotate(mid, X):
+    P = mid.P
+    ko, kx = mid.key(0)
+    c1o, c1x, z1 = mid.enc(24)
+    c2o, c2x, z2 = mid.enc(24)
+    out = mid.ct(24)
+    X.pfx_mul_relin(mid.ctx, c1x, c2x, kx, out)
+    po = O.mul_relin(P, c1o, c2o, ko)
+    mid.same(po, out)
+    X.pfx_rescale(mid.ctx, out, out)
+    po = O.rescale(P, po)
+    mid.same(po, out)
+    keys = {}
+    for step in (1, 1 << 13, -1):
+        g = O.galois_element(P, step)
+        keys[g] = mid.key(g)
+    rot = mid.ct(24)
+    for step in (1, 1 << 13, -1):
+        X.pfx_rotate(mid.ctx, out, step, [k[1] for k in keys.values()], rot)
+        mid.same(O.rotate(P, po, step, {g: k[0] for g, k in keys.items()}), rot)
+    gc = 2 * P.N - 1
+    kco, kcx = mid.key(gc)
+    X.pfx_conjugate(mid.ctx, out, [kcx], rot)
+    mid.same(O.conjugate(P, po, {gc: kco}), rot)
+    dec = X.pfx_decrypt(mid.ctx, mid.sk, out)
+    mid.handles.append(dec)
+    got = X.pfx_decode(mid.ctx, dec, P.N // 2)
+    assert np.max(np.abs(got - z1 * z2)) < 2.0 ** -20
+
+
+def test_n15_rescale_down_the_chain(mid, X):
+    """Rescale at every level from 24 to 2 (each dropped prime has its own
+    constants), word for word."""
+    P = mid.P
+    co, cx, _ = mid.enc(24)
+    for _ in range(23):
+        X.pfx_rescale(mid.ctx, cx, cx)
+        co = O.rescale(P, co)
+        mid.same(co, cx)
+
+
+def test_n15_mul_relin_batch_at_three_levels(mid, X):
+    """Batched HMult + relin at N = 2^15 (entries at 24, 13 and 3 limbs) equals
+    the oracle."""
+    P = mid.P
+    ko, kx = mid.key(0)
+    cts = [mid.enc(lv) for lv in (24, 24, 13, 13, 3, 3)]
+    outs = [mid.ct(24) for _ in range(3)]
+    X.pfx_mul_relin_batch(mid.ctx, [cts[0][1], cts[2][1], cts[4][1]], [cts[1][1], cts[3][1], cts[5][1]], kx, outs)
+    for k in range(3):
+        mid.same(O.mul_relin(P, cts[2 * k][0], cts[2 * k + 1][0], ko), outs[k])

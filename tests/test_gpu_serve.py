@@ -27,19 +27,20 @@ class Bench:
     """Keys, a shared pool of encrypted query parameters (W[8], C[0..15], T, H)
     and a resident database: two full blocks and one half block."""
 
-    def __init__(self, X, seed):
+    def __init__(self, X, seed, logn=LOGN):
         self.X = X
-        N, n = 1 << LOGN, 1 << (LOGN - 1)
+        self.logn = logn
+        N, n = 1 << logn, 1 << (logn - 1)
         self.N, self.n = N, n
-        self.P = O.Params(LOGN, QB, PB, alpha=ALPHA, mod_log2=ML)
-        prm = X.make_params(LOGN, QB, PB, ALPHA, ML)
+        self.P = O.Params(logn, QB, PB, alpha=ALPHA, mod_log2=ML)
+        prm = X.make_params(logn, QB, PB, ALPHA, ML)
         self.ctx = X.pfx_ctx_create(prm, 0)
         ext = self.P.ext_mods(self.P.L)
         beta = self.P.beta
         self.s = I.ternary_secret(N, 192, seed)
         self.sk = X.pfx_sk_create(self.ctx, self.s)
         self.key_in = {0: (I.uniform_residues(ext, N, seed + 1, lead=(beta,)), I.gaussian_error((beta, N), seed + 2))}
-        for k in range(LOGN - 1):
+        for k in range(logn - 1):
             self.key_in[pow(5, 1 << k, 2 * N)] = (I.uniform_residues(ext, N, seed + 10 + 2 * k, lead=(beta,)),
                                                   I.gaussian_error((beta, N), seed + 11 + 2 * k))
         self.rlk = X.pfx_swk_create(self.ctx, self.sk, 0, *self.key_in[0])
@@ -72,7 +73,7 @@ class Bench:
         """(plan, inputs, pts) of a query over `blocks` full blocks, or over the
         half block when blocks == 0."""
         from paper_2412_13269_amd.query import QueryPlan
-        log_slots = LOGN - 1 if blocks else LOGN - 2
+        log_slots = self.logn - 1 if blocks else self.logn - 2
         plan = QueryPlan(max(1, blocks), A, degree, 3, log_slots, interleave=interleave)
         ins = self.inputs[:A] + self.inputs[A:A + degree + 1] + self.inputs[A + MAXD + 1:A + MAXD + 3]
         pts = self.pt_full[:blocks * A] if blocks else self.pt_half
@@ -249,3 +250,22 @@ def test_half_block_query_matches_oracle(X, B, solo):
     step, count = Q.fp64_query(B.x_half, w, c, t, eta)
     got = O.decode(P, O.decrypt(P, B.s, want), want.scale, B.n // 2).real
     assert abs(got[0] - count) < 0.25
+
+
+def test_full_ring_mix_equals_solo(X):
+    """At the served workload's ring degree (N = 2^16, 2^15 slots per block):
+    three requests of different database size and degree in flight on two
+    slots give the words of each request run alone."""
+    b = Bench(X, 516, logn=16)
+    try:
+        mix = [(3, 1), (7, 2), (5, 0)]
+        want = {q: b.solo(*q) for q in mix}
+        budget = 2 * _scratch(X, b) + 4 * max(_footprint(b, q) for q in mix)
+        infos, stats = _serve(X, b, budget, 2, mix)
+        for q, out, info in infos:
+            words, scale = want[q]
+            assert np.array_equal(X.pfx_ct_export(b.ctx, out, b.N), words), q
+            assert X.pfx_ct_info(out).scale == scale
+        assert stats["completed"] == len(mix) and stats["peak_running"] >= 1
+    finally:
+        b.close()
