@@ -224,3 +224,36 @@ def test_half_bootstrap_with_the_wrong_imaginary_unit_is_caught(monkeypatch):
     orig = RP.ct_monomial
     monkeypatch.setattr(RP, "ct_monomial", lambda P, x, k: orig(P, x, P.N // 2 if k == 3 * P.N // 2 else k))
     _expect_fail(TB.test_half_bootstrap_puts_the_coefficients_in_the_slots)
+
+
+# ---- the seeded sampler (oracle/sampler.py)
+from oracle import sampler as SM
+from tests import test_sampler_oracle as TS
+
+
+def test_uniform_mask_one_bit_short_is_caught(monkeypatch):
+    orig = SM.uniform_poly
+
+    def short(seed, tag, index, limb, q, n):
+        half = 1 << ((q - 1).bit_length() - 1)
+        return orig(seed, tag, index, limb, max(2, half), n)     # masks one bit fewer, never reaches [half, q)
+    monkeypatch.setattr(SM, "uniform_poly", short)
+    _expect_fail(TS.test_uniform_is_uniform)
+
+
+def test_gaussian_table_without_doubling_is_caught(monkeypatch):
+    def one_sided(sigma=SM.SIGMA, bound=SM.BOUND):
+        rho = [math.exp(-(k * k) / (2.0 * sigma * sigma)) for k in range(bound + 1)]
+        total, acc, t = sum(rho), 0.0, []
+        for k in range(bound):
+            acc += rho[k] / total
+            t.append(int(math.floor(acc * 2.0 ** 63)))
+        return t + [1 << 63]
+    monkeypatch.setattr(SM, "gaussian_table", one_sided)
+    _expect_fail(TS.test_gaussian_table_and_moments)
+
+
+def test_sparse_secret_without_signs_is_caught(monkeypatch):
+    orig = SM.ternary_sparse
+    monkeypatch.setattr(SM, "ternary_sparse", lambda seed, tag, index, n, h: np.abs(orig(seed, tag, index, n, h)))
+    _expect_fail(TS.test_ternary_secrets)
