@@ -50,6 +50,7 @@ def log(*a):
 
 # sources that define a profiled kernel (their hash ties a committed counter
 # measurement to the code it was taken on)
+_KS_SOURCES = ["kernels.hip", "keyswitch.hip", "modarith.h", "ntt_core.h", "internal.h"]
 _KERNEL_SOURCES = {"ks_inner": ["kernels.hip", "modarith.h", "ntt_core.h", "internal.h"],
                    "repack_fused": ["keyswitch.hip", "modarith.h", "ntt_core.h", "internal.h"]}
 
@@ -73,6 +74,41 @@ def measured_traffic(kernel: str, workload: str = "n16_l24"):
     return int(m.group(1)) if h.hexdigest() == m.group(3) else None
 
 
+# Algorithmic HBM bytes of one operation at N = 2^16, L = 24, K = 4, dnum = 6
+# (each operand read once, each result written once, the switching key read
+# once; no ModUp limbs, twiddles or scratch): limb = 8N bytes.
+def op_bytes(N, L, K, beta):
+    limb = 8 * N
+    ks = 2 * beta * (L + K) * limb               # the switching key
+    return {"ntt_fwd_ct": 2 * 2 * L * limb,       # 2L limbs in, 2L out
+            "intt_ct": 2 * 2 * L * limb,
+            "mul_relin": 6 * L * limb + ks,       # two ciphertexts in, one out
+            "rotate": 4 * L * limb + ks,          # one ciphertext in, one out
+            "rescale": (2 * L + 2 * (L - 1)) * limb}
+
+
+VALU_PEAK_G = 256 * 4 * 2.4 / 4     # G wave64 VALU instructions per second (256 CUs, 4 SIMDs, 2.4 GHz)
+
+
+def measured_valu_per_ks(workload: str = "n16_l24"):
+    """VALU wave instructions of one rotation's key switch (SQ_INSTS_VALU summed
+    over its kernels) from the committed summary profiles/ks_kernels_<workload>_valu_rate.md,
+    or None when there is none or the key-switch sources have changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"ks_kernels_{workload}_valu_rate.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"valu_wave_instructions_per_rotation: ([0-9.e+]+) sources_sha256: ([0-9a-f]{64})", open(path).read())
+    if not m:
+        return None
+    h = hashlib.sha256()
+    for f in _KS_SOURCES:
+        with open(os.path.join(ROOT, "paper_2412_13269_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return float(m.group(1)) if h.hexdigest() == m.group(2) else None
+
+
 def cpu_baseline(q, p):
     """The oracle on HMult + relin and rotation pairs (same seeds as the GPU step)."""
     from oracle import ckks as O
@@ -89,26 +125,32 @@ def cpu_baseline(q, p):
         m = O.encode(P, I.uniform_slots(N // 2, seed), SCALE, P.L)
         cts.append(O.encrypt(P, s, m, I.uniform_residues(P.q, N, seed + 10), I.gaussian_error(N, seed + 20), SCALE))
     cores = O.threads()
+    # whole (HMult+relin, rotation) pairs on every core, at least 3 and ~5 s;
+    # the rate is taken from the median pair
+    pairs = []
     t0 = time.perf_counter()
-    ops = 0
-    while ops == 0 or time.perf_counter() - t0 < 10.0:   # whole (HMult+relin, rotation) pairs, ~10-12 s
+    while len(pairs) < 3 or time.perf_counter() - t0 < 5.0:
+        a = time.perf_counter()
         O.mul_relin(P, cts[0], cts[1], rlk)
         O.rotate(P, cts[0], 1, {g: gk})
-        ops += 2
-    dt = time.perf_counter() - t0
-    # one HMult + relin on one thread (about 20 s on a current server core)
+        pairs.append(time.perf_counter() - a)
+    # HMult + relin on one thread, 3 repetitions (about 9 s each on the GPU machine's host)
     O.set_threads(1)
-    t1 = time.perf_counter()
-    O.mul_relin(P, cts[0], cts[1], rlk)
-    dt1 = time.perf_counter() - t1
+    singles = []
+    for _ in range(3):
+        a = time.perf_counter()
+        O.mul_relin(P, cts[0], cts[1], rlk)
+        singles.append(time.perf_counter() - a)
     O.set_threads(cores)
-    return {"value": ops / dt, "unit": "KS ops/s", "cores": cores, "kind": "oracle",
-            "sample": f"{ops // 2} x (HMult+relin, rotation by 1) at N=2^16, L=24 on the same seeded inputs "
-                      "(oracle C loops, OpenMP over limbs; key generation not timed)",
-            "key_switches": ops,
-            "seconds": dt,
-            "single_thread": {"value": 1.0 / dt1, "unit": "KS ops/s", "cores": 1,
-                              "sample": "1 x HMult+relin at N=2^16, L=24, same inputs", "seconds": dt1}}
+    med, med1 = float(np.median(pairs)), float(np.median(singles))
+    return {"value": 2.0 / med, "unit": "KS ops/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(pairs)} x (HMult+relin, rotation by 1) at N=2^16, L=24 on the same seeded inputs "
+                      "(oracle C loops, OpenMP over limbs; key generation not timed), median pair",
+            "key_switches": 2 * len(pairs), "seconds": float(sum(pairs)),
+            "pair_seconds": [float(x) for x in pairs],
+            "single_thread": {"value": 1.0 / med1, "unit": "KS ops/s", "cores": 1,
+                              "sample": "3 x HMult+relin at N=2^16, L=24, same inputs, median",
+                              "seconds": [float(x) for x in singles]}}
 
 
 def batched_form(X, I, ctx16, rlk16, st, args):
@@ -494,6 +536,24 @@ def main():
             prep=lambda: X.pfx_mul_relin(ctx, cts[0], cts[1], rlk, prod, st))
     X.pfx_event_destroy(ctx, ev0)
     X.pfx_event_destroy(ctx, ev1)
+    # each operation against the HBM roofline: its algorithmic bytes over its
+    # median device time
+    ob = op_bytes(N, L, K, beta)
+    op_fracs = {}
+    for name, by in ob.items():
+        us = per_op[f"{name}_us"]
+        op_fracs[name] = {"us": us, "bytes": by, "GBps": by / (us * 1e-6) / 1e9,
+                          "frac": by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    log("ops vs HBM roofline: " + ", ".join(f"{k} {v['frac']:.3f}" for k, v in op_fracs.items()))
+    # a rotation's key switch against the VALU issue peak: its VALU wave
+    # instructions (committed counter summary, current sources only) over the
+    # rotation's median device time
+    vi = measured_valu_per_ks()
+    valu_ks = None
+    if vi is not None:
+        rate = vi / (per_op["rotate_us"] * 1e-6) / 1e9
+        valu_ks = {"wave_instructions": vi, "rotate_us": per_op["rotate_us"], "G_per_s": rate,
+                   "peak_G_per_s": VALU_PEAK_G, "frac": rate / VALU_PEAK_G}
     # the boundary's host interchange (PCIe-inclusive): canonical words of one
     # ciphertext, 2 x 24 limbs = 24 MiB, host -> device and back
     words = I.uniform_residues(q, N, 9, lead=(2,))
@@ -683,7 +743,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "avg_launch_us": 1e3 * d["ms"] / d["launches"],
-                     "algorithmic_bytes_per_launch": d["bytes"] / d["launches"]},
+                     "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
+                     "ops": op_fracs, "valu_per_ks": valu_ks},
         "per_op_us": per_op,
         "query": query_out,
         "batched": batch_out,

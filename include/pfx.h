@@ -108,6 +108,31 @@ pfx_status pfx_decode_words(const pfx_params *prm, const uint64_t *words, uint32
 /* ------------------------------------------------------------------ context */
 pfx_status pfx_ctx_create(const pfx_params *prm, int hip_device, pfx_ctx **out);
 void pfx_ctx_destroy(pfx_ctx *ctx);
+
+/*
+ * Device memory of a context.  Every device allocation the library makes for
+ * the context after pfx_ctx_create's own tables (twiddles and conversion
+ * constants) goes through one path: ciphertexts and plaintexts, keys, the
+ * per-stream scratch and its batch and repacking regions, the temporaries of
+ * key generation and export, pfx_dev_alloc, and a request server's arena.
+ *   alloc(bytes, stream, user) returns device memory of the context's device
+ *   (NULL when it cannot), free(p, stream, user) gives it back; stream is the
+ *   stream the memory is first used on or NULL.  Both NULL: hipMalloc/hipFree.
+ *   hbm_budget: bytes the context may hold at once, counted from creation
+ *   (tables included, pfx_ctx_mem); 0 = no cap.  An allocation that would
+ *   exceed it, or that the allocator refuses, fails the call with PFX_ENOMEM
+ *   and leaves its outputs untouched.
+ * Memory is freed by the allocator that made it, so the allocator may be
+ * changed at any time; a budget below what the context already holds only
+ * refuses further allocations.  Not thread-safe against calls running on the
+ * context.  user is passed through unchanged.
+ */
+typedef void *(*pfx_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*pfx_free_fn)(void *p, void *stream, void *user);
+pfx_status pfx_ctx_set_allocator(pfx_ctx *ctx, pfx_alloc_fn alloc, pfx_free_fn free_fn, void *user,
+                                 size_t hbm_budget);
+/* Bytes of device memory the context holds now and at most so far. */
+pfx_status pfx_ctx_mem(const pfx_ctx *ctx, size_t *in_use, size_t *peak);
 pfx_status pfx_ctx_moduli(const pfx_ctx *ctx, uint64_t *q, uint64_t *p, uint64_t *psi);
 /* Blocks until all work the library enqueued on `stream` has finished. */
 pfx_status pfx_sync(pfx_ctx *ctx, void *stream);
@@ -138,8 +163,57 @@ pfx_status pfx_swk_create_from(pfx_ctx *ctx, const pfx_sk *sk, const int8_t *s_f
                                const int64_t *e, pfx_swk **out);
 /* Words [j][t][prime][coefficient], t = 0 for the b part, 1 for a. */
 pfx_status pfx_swk_export(pfx_ctx *ctx, const pfx_swk *k, uint64_t *words, size_t cap_words);
+/* A switching key from the words pfx_swk_export writes (canonical residues,
+ * coefficient domain, beta * 2 * (n_q + n_p) * N of them, each below its
+ * prime: PFX_EINVAL otherwise), for Galois element `galois` (0: a
+ * relinearisation key).  Word for word the exported key. */
+pfx_status pfx_swk_import(pfx_ctx *ctx, uint32_t galois, const uint64_t *words, size_t n_words, pfx_swk **out);
 uint32_t pfx_swk_galois(const pfx_swk *k);
 void pfx_swk_destroy(pfx_swk *k);
+/* The secret's N coefficients in {-1, 0, 1} (the scientist's copy, host). */
+pfx_status pfx_sk_export(const pfx_sk *sk, int8_t *s, size_t n);
+
+/*
+ * Seeded key generation and encryption (Sec. 2.3, Sec. 2.4.1), drawing their
+ * randomness on the host from SHAKE-256 (FIPS 202) streams keyed by
+ *   seed (32 bytes) || tag || index || limb   (little-endian uint32 each):
+ *   uniform below m: 8-byte little-endian words masked to bitlen(m - 1) bits,
+ *     rejected while >= m;
+ *   uniform ternary: bytes b, v = b & 3 rejected while 3; 0, 1, 2 -> 0, +1, -1;
+ *   h-sparse ternary: positions 0..N-1, for i < h swap entry i with entry
+ *     i + u (u uniform below N - i); then one byte per chosen position in
+ *     order, bit 0 its sign (0: +1, 1: -1);
+ *   discrete Gaussian, sigma 3.2, |e| <= 19: the cumulative table T[k] =
+ *     floor(2^63 P(|X| <= k)), k < 19 (weights exp(-k^2 / 2 sigma^2), doubled
+ *     for k > 0, summed in order in FP64), T[19] = 2^63; u = word >> 1, |e| the
+ *     least k with u < T[k]; a non-zero |e| takes bit 0 of one more byte as
+ *     its sign.
+ * Tags: 1 the secret (index 0); 2 a switching key's a (index 256 g + j for
+ * Galois element g, 0 for relinearisation, digit j; limb the prime index over
+ * Q then P); 3 its error (index as for a, limb 0); 4 an encryption's a (index
+ * 0, limb the prime index); 5 its error (index 0, limb 0).  Equal seeds give
+ * equal keys and ciphertexts, word for word, on any device.
+ */
+/* Secret with h non-zero coefficients (h < 0: uniform ternary, Sec. 2.3). */
+pfx_status pfx_keygen_secret(pfx_ctx *ctx, const uint8_t *seed, int32_t h, pfx_sk **out);
+/* Relinearisation key (s^2 -> s) from seed. */
+pfx_status pfx_keygen_relin(pfx_ctx *ctx, const pfx_sk *sk, const uint8_t *seed, pfx_swk **out);
+/* Galois keys for slot rotations by steps[0..n) (left, Galois element 5^step
+ * mod 2N) and, when conj is non-zero, conjugation (2N - 1) last: n + (conj !=
+ * 0) keys into out[].  All or nothing: on an error none is kept. */
+pfx_status pfx_keygen_galois(pfx_ctx *ctx, const pfx_sk *sk, const int32_t *steps, size_t n, int conj,
+                             const uint8_t *seed, pfx_swk **out);
+/* pfx_encrypt with a and e drawn from seed (tags 4 and 5). */
+pfx_status pfx_encrypt_seeded(pfx_ctx *ctx, const pfx_sk *sk, const pfx_pt *pt, const uint8_t *seed, pfx_ct *out,
+                              void *stream);
+/* Host only (no device): the draws above, for checking them against another
+ * implementation.  pfx_shake256: outlen bytes of SHAKE-256(msg). */
+pfx_status pfx_shake256(const uint8_t *msg, size_t n, uint8_t *out, size_t outlen);
+pfx_status pfx_sample_uniform(const uint8_t *seed, uint32_t tag, uint32_t index, uint32_t limb, uint64_t q,
+                              size_t n, uint64_t *out);
+/* The secret's coefficients (tag 1): h-sparse, or uniform ternary for h < 0. */
+pfx_status pfx_sample_secret(const uint8_t *seed, size_t n, int32_t h, int8_t *out);
+pfx_status pfx_sample_gaussian(const uint8_t *seed, uint32_t tag, uint32_t index, size_t n, int64_t *out);
 
 /* Slot encoding (App. A.1): n_slots (power of two, <= N/2) complex values
  * (im may be NULL) -> round(scale * tau^-1(z)) at n_limbs limbs.  Rounding
@@ -391,7 +465,15 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
  *   PFX_RUN_GRAPH (non-NULL stream required): the first call for a given op
  *     list, register set, plaintexts and keys is captured into a HIP graph and
  *     launched; later calls replay it.  Register metadata (limbs, scale) after
- *     a replay equals that of the captured run.
+ *     a replay equals that of the captured run.  Graphs are cached process-wide
+ *     (at most 64, least recently used dropped) under the identities of the
+ *     objects (never their addresses), the registers' capacities, the inputs'
+ *     shapes, the plaintexts' levels and scales, the stream and the mode;
+ *     destroying any object a graph uses drops that graph, and a graph
+ *     captured before any library scratch region was freed or moved (stream
+ *     or context destroyed, a batch or repacking region grown) is captured
+ *     again instead of replayed.  Every object must be library-created
+ *     (PFX_EINVAL otherwise).
  *   PFX_RUN_LANES: LANE markers in the list are honoured.  The first marker
  *     LANE k (0 <= k < 8) of a fork records an event on `stream` that all of
  *     the library's lane streams wait for, and the ops after LANE k run on
@@ -468,6 +550,13 @@ pfx_status pfx_run_circuit(pfx_ctx *ctx, const pfx_op *ops, size_t n_ops, pfx_ct
 pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const *a,
                                        const pfx_ct *const *b, const pfx_swk *const *rlk,
                                        pfx_ct *const *out, size_t n, int mode, void *stream);
+
+/*
+ * The process-wide cache of captured graphs (PFX_RUN_GRAPH, batched modes 2
+ * and 4): entries held now, and captures made since the library was loaded
+ * (a replay does not count).  Either pointer may be NULL.  Never fails.
+ */
+pfx_status pfx_graph_cache_stats(size_t *entries, uint64_t *captures);
 
 /* ------------------------------------------------------------ served form */
 /*

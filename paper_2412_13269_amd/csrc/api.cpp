@@ -28,6 +28,92 @@ pfx_status fail(pfx_status s, const std::string &msg) {
     return s;
 }
 
+// A captured graph and the event recorded after its last replay (waited for
+// before the graph is destroyed).
+struct GraphExec {
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    int device = 0;
+};
+
+constexpr size_t kGraphCacheEntries = 64;
+
+// Process-wide, deliberately never destroyed: a static destructor would run
+// after the HIP runtime has been torn down at exit.
+GraphCache<GraphExec> &graphs() {
+    static GraphCache<GraphExec> *g = new GraphCache<GraphExec>(kGraphCacheEntries, [](GraphExec &x) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(x.device);
+        if (x.done) (void)hipEventSynchronize(x.done);
+        if (x.exec) (void)hipGraphExecDestroy(x.exec);
+        if (x.done) (void)hipEventDestroy(x.done);
+        (void)hipSetDevice(prev);
+    });
+    return *g;
+}
+
+void graph_forget(uint64_t uid) {
+    if (uid) graphs().drop_uid(uid);
+}
+
+namespace {
+
+struct MemRecord {
+    std::shared_ptr<MemAccount> acct;
+    size_t bytes;
+    pfx_free_fn free;   // the caller's free function, or null for hipFree
+    void *user;
+};
+std::mutex g_mem_mu;
+std::map<void *, MemRecord> &mem_records() {
+    static std::map<void *, MemRecord> *m = new std::map<void *, MemRecord>;   // never destroyed (see graphs())
+    return *m;
+}
+
+}  // namespace
+
+pfx_status dmalloc(pfx_ctx *c, void **p, size_t bytes) {
+    if (!bytes) bytes = 1;
+    MemAccount &a = *c->mem;
+    std::lock_guard<std::mutex> g(a.mu);
+    if (a.budget && a.in_use + bytes > a.budget)
+        return fail(PFX_ENOMEM, "HBM budget of the context exceeded: " + std::to_string(a.in_use) + " + " +
+                                    std::to_string(bytes) + " > " + std::to_string(a.budget) + " bytes");
+    void *q = nullptr;
+    if (a.alloc) {
+        q = a.alloc(bytes, nullptr, a.user);
+        if (!q) return fail(PFX_ENOMEM, "the context's allocator refused " + std::to_string(bytes) + " bytes");
+    } else if (hipMalloc(&q, bytes) != hipSuccess || !q) {
+        (void)hipGetLastError();
+        return fail(PFX_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    {
+        std::lock_guard<std::mutex> gm(g_mem_mu);
+        mem_records()[q] = MemRecord{c->mem, bytes, a.alloc ? a.free : nullptr, a.user};
+    }
+    a.in_use += bytes;
+    a.peak = std::max(a.peak, a.in_use);
+    *p = q;
+    return PFX_OK;
+}
+
+void dfree(void *p) {
+    if (!p) return;
+    MemRecord rec;
+    {
+        std::lock_guard<std::mutex> gm(g_mem_mu);
+        auto it = mem_records().find(p);
+        if (it == mem_records().end()) return;
+        rec = it->second;
+        mem_records().erase(it);
+    }
+    if (rec.free) rec.free(p, nullptr, rec.user);
+    else (void)hipFree(p);
+    std::lock_guard<std::mutex> g(rec.acct->mu);
+    rec.acct->in_use -= rec.bytes;
+}
+
 }  // namespace pfx
 
 #define HIPCHECK(x)                                                                          \
@@ -35,6 +121,28 @@ pfx_status fail(pfx_status s, const std::string &msg) {
         hipError_t e_ = (x);                                                                 \
         if (e_ != hipSuccess) return fail(PFX_EDEVICE, std::string(#x ": ") + hipGetErrorString(e_)); \
     } while (0)
+
+#define PFX_DMALLOC(ctx, pp, bytes)                               \
+    do {                                                          \
+        pfx_status r_ = dmalloc((ctx), (pp), (bytes));            \
+        if (r_) return r_;                                        \
+    } while (0)
+
+// Device memory of a context held for one call: freed when the holder goes out
+// of scope unless released, so an early error return leaks nothing.
+template <class T>
+struct DevTmp {
+    T *p = nullptr;
+    DevTmp() = default;
+    DevTmp(const DevTmp &) = delete;
+    DevTmp &operator=(const DevTmp &) = delete;
+    ~DevTmp() { pfx::dfree(p); }
+    T *release() {
+        T *q = p;
+        p = nullptr;
+        return q;
+    }
+};
 
 #define REQUIRE(cond, code, msg) \
     do {                         \
@@ -100,11 +208,12 @@ pfx_status get_batch_ws(pfx_ctx *c, hipStream_t st, int nb, KsBatch &kb) {
     if (w->bcap < nb) {
         if (c->capturing) return fail(PFX_EINVAL, "batch workspace must be reserved before graph capture");
         (void)hipStreamSynchronize(st);   // the old region may still be in use on this stream
-        (void)hipFree(w->bbuf);
+        bump_scratch_epoch();             // graphs captured against the old region are stale
+        dfree(w->bbuf);
         w->bbuf = nullptr;
         w->bcap = 0;
-        if (hipMalloc(&w->bbuf, (size_t)nb * per * sizeof(double)) != hipSuccess)
-            return fail(PFX_ENOMEM, "batch workspace allocation failed");
+        pfx_status r = dmalloc(c, &w->bbuf, (size_t)nb * per * sizeof(double));
+        if (r) return r;
         w->bcap = nb;
     }
     double *base = w->bbuf;
@@ -127,9 +236,10 @@ pfx_status get_ws(pfx_ctx *c, hipStream_t st, Ws &out) {
         w->stream = st;
         WsLayout lay = ws_layout(c);
         w->doubles = lay.total;
-        if (hipMalloc(&w->buf, lay.total * sizeof(double)) != hipSuccess) {
+        pfx_status r = dmalloc(c, &w->buf, lay.total * sizeof(double));
+        if (r) {
             delete w;
-            return fail(PFX_ENOMEM, "workspace allocation failed");
+            return r;
         }
         it = c->ws.emplace(st, w).first;
     }
@@ -626,6 +736,7 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
         return fail(PFX_EDEVICE, std::string("libpfx is built for gfx950, device is ") + prop.gcnArchName);
 
     std::unique_ptr<pfx_ctx> c(new pfx_ctx);
+    c->uid = next_uid();
     c->device = device;
     c->logn = prm->log_n;
     c->N = 1 << prm->log_n;
@@ -657,7 +768,10 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
             tw[(2 * (size_t)m + 1) * N + k] = shoup_pair(ipw[b], qq);
         }
     }
-    HIPCHECK(hipMalloc(&c->d_tw, tw.size() * sizeof(double2)));
+    {
+        pfx_status r = dmalloc(c.get(), &c->d_tw, tw.size() * sizeof(double2));
+        if (r) return r;
+    }
     HIPCHECK(hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
     // row-pass generated twiddles (see PrimeDev)
     const int Srow = c->logn - c->logn / 2, R2 = Srow - (Srow + 1) / 2, T = c->logn - R2;
@@ -672,7 +786,10 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
             rtw[(2 * (size_t)m + 1) * nT + P] = (double)powmod_u64(ips, e, qq);
         }
     }
-    HIPCHECK(hipMalloc(&c->d_rtw, rtw.size() * sizeof(double)));
+    {
+        pfx_status r = dmalloc(c.get(), &c->d_rtw, rtw.size() * sizeof(double));
+        if (r) return r;
+    }
     HIPCHECK(hipMemcpy(c->d_rtw, rtw.data(), rtw.size() * sizeof(double), hipMemcpyHostToDevice));
     c->h_primes.resize(NP);
     for (int m = 0; m < NP; ++m) {
@@ -700,7 +817,10 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
                 d.irc[(1 << k) - 1 + x] = (double)powmod_u64(ips, e, qq);
             }
     }
-    HIPCHECK(hipMalloc(&c->d_primes, NP * sizeof(PrimeDev)));
+    {
+        pfx_status r = dmalloc(c.get(), &c->d_primes, NP * sizeof(PrimeDev));
+        if (r) return r;
+    }
     HIPCHECK(hipMemcpy(c->d_primes, c->h_primes.data(), NP * sizeof(PrimeDev), hipMemcpyHostToDevice));
 
     // ModUp: for digit j with sz active primes D = {alpha j, ..., alpha j + sz - 1}
@@ -726,7 +846,10 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
                 }
             }
         }
-    HIPCHECK(hipMalloc(&c->d_modup, mu.size() * sizeof(ModUpConst)));
+    {
+        pfx_status r = dmalloc(c.get(), &c->d_modup, mu.size() * sizeof(ModUpConst));
+        if (r) return r;
+    }
     HIPCHECK(hipMemcpy(c->d_modup, mu.data(), mu.size() * sizeof(ModUpConst), hipMemcpyHostToDevice));
 
     // ModDown and key-generation constants
@@ -758,7 +881,10 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
             md->pmod[m] = shoup_pair(pmod, qm);
         }
     }
-    HIPCHECK(hipMalloc(&c->d_moddown, sizeof(ModDownConst)));
+    {
+        pfx_status r = dmalloc(c.get(), &c->d_moddown, sizeof(ModDownConst));
+        if (r) return r;
+    }
     HIPCHECK(hipMemcpy(c->d_moddown, md.get(), sizeof(ModDownConst), hipMemcpyHostToDevice));
 
     // Rescale: dropping prime l, for i < l
@@ -771,7 +897,10 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
             r.inv = shoup_pair(invmod_u64(ql % qi, qi), qi);
             r.half = (double)((ql / 2) % qi);
         }
-    HIPCHECK(hipMalloc(&c->d_rescale, rc.size() * sizeof(RescaleConst)));
+    {
+        pfx_status r = dmalloc(c.get(), &c->d_rescale, rc.size() * sizeof(RescaleConst));
+        if (r) return r;
+    }
     HIPCHECK(hipMemcpy(c->d_rescale, rc.data(), rc.size() * sizeof(RescaleConst), hipMemcpyHostToDevice));
     *out = c.release();
     return PFX_OK;
@@ -781,10 +910,12 @@ void pfx_ctx_destroy(pfx_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    graph_forget(c->uid);      // every graph that launches on this context's tables or lanes
+    bump_scratch_epoch();      // and any that wrote this context's scratch
     for (auto &kv : c->ws) {
-        (void)hipFree(kv.second->buf);
-        (void)hipFree(kv.second->bbuf);
-        (void)hipFree(kv.second->rbuf);
+        dfree(kv.second->buf);
+        dfree(kv.second->bbuf);
+        dfree(kv.second->rbuf);
         delete kv.second;
     }
     for (auto &e : c->prof_pending) {
@@ -792,16 +923,35 @@ void pfx_ctx_destroy(pfx_ctx *c) {
         (void)hipEventDestroy(e.stop);
     }
     for (auto e : c->prof_pool) (void)(void)hipEventDestroy(e);
-    for (auto &kv : c->graphs) (void)(void)hipGraphExecDestroy(kv.second.exec);
     for (auto st : c->lanes) (void)(void)hipStreamDestroy(st);
     for (auto e : c->lane_events) (void)(void)hipEventDestroy(e);
-    (void)hipFree(c->d_tw);
-    (void)hipFree(c->d_rtw);
-    (void)hipFree(c->d_primes);
-    (void)hipFree(c->d_modup);
-    (void)hipFree(c->d_moddown);
-    (void)hipFree(c->d_rescale);
-    delete c;
+    dfree(c->d_tw);
+    dfree(c->d_rtw);
+    dfree(c->d_primes);
+    dfree(c->d_modup);
+    dfree(c->d_moddown);
+    dfree(c->d_rescale);
+    delete c;   // objects not yet destroyed keep their memory until they are
+}
+
+pfx_status pfx_ctx_set_allocator(pfx_ctx *c, pfx_alloc_fn alloc, pfx_free_fn free_fn, void *user,
+                                 size_t hbm_budget) {
+    REQUIRE(c, PFX_EINVAL, "null context");
+    REQUIRE((alloc == nullptr) == (free_fn == nullptr), PFX_EINVAL, "give both alloc and free, or neither");
+    std::lock_guard<std::mutex> g(c->mem->mu);
+    c->mem->alloc = alloc;
+    c->mem->free = free_fn;
+    c->mem->user = user;
+    c->mem->budget = hbm_budget;
+    return PFX_OK;
+}
+
+pfx_status pfx_ctx_mem(const pfx_ctx *c, size_t *in_use, size_t *peak) {
+    REQUIRE(c, PFX_EINVAL, "null context");
+    std::lock_guard<std::mutex> g(c->mem->mu);
+    if (in_use) *in_use = c->mem->in_use;
+    if (peak) *peak = c->mem->peak;
+    return PFX_OK;
 }
 
 pfx_status pfx_ctx_moduli(const pfx_ctx *c, uint64_t *q, uint64_t *p, uint64_t *psi) {
@@ -826,23 +976,25 @@ pfx_status pfx_sk_create(pfx_ctx *c, const int8_t *s, pfx_sk **out) {
     const int NP = c->L + c->K;
     std::unique_ptr<pfx_sk> k(new pfx_sk);
     k->ctx = c;
+    k->uid = next_uid();
     k->h_s.assign(s, s + c->N);
-    HIPCHECK(hipMalloc(&k->d_s, (size_t)NP * c->N * sizeof(double)));
-    int8_t *tmp = nullptr;
-    HIPCHECK(hipMalloc(&tmp, c->N));
-    HIPCHECK(hipMemcpy(tmp, s, c->N, hipMemcpyHostToDevice));
+    DevTmp<double> ds;
+    DevTmp<int8_t> tmp;
+    PFX_DMALLOC(c, &ds.p, (size_t)NP * c->N * sizeof(double));
+    PFX_DMALLOC(c, &tmp.p, c->N);
+    HIPCHECK(hipMemcpy(tmp.p, s, c->N, hipMemcpyHostToDevice));
     Launch L{c, nullptr};
-    launch_s8_to_rns(L, k->d_s, tmp, NP);
-    launch_ntt(L, k->d_s, nullptr, contiguous_map(NP, 0), false);
+    launch_s8_to_rns(L, ds.p, tmp.p, NP);
+    launch_ntt(L, ds.p, nullptr, contiguous_map(NP, 0), false);
     HIPCHECK(hipStreamSynchronize(nullptr));
-    (void)hipFree(tmp);
+    k->d_s = ds.release();
     *out = k.release();
     return PFX_OK;
 }
 
 void pfx_sk_destroy(pfx_sk *k) {
     if (!k) return;
-    (void)hipFree(k->d_s);
+    dfree(k->d_s);
     delete k;
 }
 
@@ -870,17 +1022,20 @@ pfx_status swk_fill(pfx_ctx *c, const pfx_sk *sk, const double *sfrom, const uin
                     pfx_swk *k) {
     const int NP = c->L + c->K;
     const size_t N = c->N, limb = N;
-    HIPCHECK(hipMalloc(&k->d_k, (size_t)c->beta * 2 * NP * limb * sizeof(double)));
-    double *etmp = nullptr;
-    uint64_t *stage = nullptr;
-    int64_t *edev = nullptr;
-    HIPCHECK(hipMalloc(&etmp, (size_t)NP * limb * sizeof(double)));
-    HIPCHECK(hipMalloc(&stage, (size_t)NP * limb * sizeof(uint64_t)));
-    HIPCHECK(hipMalloc(&edev, N * sizeof(int64_t)));
+    DevTmp<double> dk, etmp_;
+    DevTmp<uint64_t> stage_;
+    DevTmp<int64_t> edev_;
+    PFX_DMALLOC(c, &dk.p, (size_t)c->beta * 2 * NP * limb * sizeof(double));
+    PFX_DMALLOC(c, &etmp_.p, (size_t)NP * limb * sizeof(double));
+    PFX_DMALLOC(c, &stage_.p, (size_t)NP * limb * sizeof(uint64_t));
+    PFX_DMALLOC(c, &edev_.p, N * sizeof(int64_t));
+    double *etmp = etmp_.p;
+    uint64_t *stage = stage_.p;
+    int64_t *edev = edev_.p;
     Launch L{c, nullptr};
     for (int j = 0; j < c->beta; ++j) {
-        double *b = k->d_k + (size_t)(2 * j) * NP * limb;
-        double *aa = k->d_k + (size_t)(2 * j + 1) * NP * limb;
+        double *b = dk.p + (size_t)(2 * j) * NP * limb;
+        double *aa = dk.p + (size_t)(2 * j + 1) * NP * limb;
         HIPCHECK(hipMemcpy(stage, a + (size_t)j * NP * N, (size_t)NP * N * sizeof(uint64_t), hipMemcpyHostToDevice));
         launch_u64_to_f64(L, aa, stage, (size_t)NP * N);
         launch_ntt(L, aa, nullptr, contiguous_map(NP, 0), false);
@@ -890,9 +1045,7 @@ pfx_status swk_fill(pfx_ctx *c, const pfx_sk *sk, const double *sfrom, const uin
         launch_keygen_b(L, b, aa, etmp, sk->d_s, sfrom, j);
         HIPCHECK(hipStreamSynchronize(nullptr));
     }
-    (void)hipFree(etmp);
-    (void)hipFree(stage);
-    (void)hipFree(edev);
+    k->d_k = dk.release();
     return PFX_OK;
 }
 
@@ -911,18 +1064,15 @@ pfx_status pfx_swk_create(pfx_ctx *c, const pfx_sk *sk, uint32_t galois, const u
     const int NP = c->L + c->K;
     std::unique_ptr<pfx_swk> k(new pfx_swk);
     k->ctx = c;
+    k->uid = next_uid();
     k->galois = galois;
-    double *sfrom = nullptr;
-    HIPCHECK(hipMalloc(&sfrom, (size_t)NP * c->N * sizeof(double)));
+    DevTmp<double> sfrom;
+    PFX_DMALLOC(c, &sfrom.p, (size_t)NP * c->N * sizeof(double));
     Launch L{c, nullptr};
-    if (galois == 0) launch_ew(L, EW_MUL, sfrom, sk->d_s, sk->d_s, 0, 0, 0, 1, NP);
-    else launch_automorph(L, sfrom, sk->d_s, 0, 0, 1, NP, galois);
-    r = swk_fill(c, sk, sfrom, a, e, k.get());
-    (void)hipFree(sfrom);
-    if (r) {
-        (void)hipFree(k->d_k);
-        return r;
-    }
+    if (galois == 0) launch_ew(L, EW_MUL, sfrom.p, sk->d_s, sk->d_s, 0, 0, 0, 1, NP);
+    else launch_automorph(L, sfrom.p, sk->d_s, 0, 0, 1, NP, galois);
+    r = swk_fill(c, sk, sfrom.p, a, e, k.get());
+    if (r) return r;
     *out = k.release();
     return PFX_OK;
 }
@@ -937,23 +1087,19 @@ pfx_status pfx_swk_create_from(pfx_ctx *c, const pfx_sk *sk, const int8_t *s_fro
     const int NP = c->L + c->K;
     std::unique_ptr<pfx_swk> k(new pfx_swk);
     k->ctx = c;
+    k->uid = next_uid();
     k->galois = 0;
     k->from_secret = true;
-    double *sfrom = nullptr;
-    int8_t *tmp = nullptr;
-    HIPCHECK(hipMalloc(&sfrom, (size_t)NP * c->N * sizeof(double)));
-    HIPCHECK(hipMalloc(&tmp, c->N));
-    HIPCHECK(hipMemcpy(tmp, s_from, c->N, hipMemcpyHostToDevice));
+    DevTmp<double> sfrom;
+    DevTmp<int8_t> tmp;
+    PFX_DMALLOC(c, &sfrom.p, (size_t)NP * c->N * sizeof(double));
+    PFX_DMALLOC(c, &tmp.p, c->N);
+    HIPCHECK(hipMemcpy(tmp.p, s_from, c->N, hipMemcpyHostToDevice));
     Launch L{c, nullptr};
-    launch_s8_to_rns(L, sfrom, tmp, NP);
-    launch_ntt(L, sfrom, nullptr, contiguous_map(NP, 0), false);
-    r = swk_fill(c, sk, sfrom, a, e, k.get());
-    (void)hipFree(sfrom);
-    (void)hipFree(tmp);
-    if (r) {
-        (void)hipFree(k->d_k);
-        return r;
-    }
+    launch_s8_to_rns(L, sfrom.p, tmp.p, NP);
+    launch_ntt(L, sfrom.p, nullptr, contiguous_map(NP, 0), false);
+    r = swk_fill(c, sk, sfrom.p, a, e, k.get());
+    if (r) return r;
     *out = k.release();
     return PFX_OK;
 }
@@ -964,18 +1110,54 @@ pfx_status pfx_swk_export(pfx_ctx *c, const pfx_swk *k, uint64_t *words, size_t 
     const size_t per = (size_t)NP * c->N;
     REQUIRE(cap >= (size_t)c->beta * 2 * per, PFX_EINVAL, "cap_words too small");
     HIPCHECK(hipSetDevice(c->device));
-    double *tmp = nullptr;
-    uint64_t *u = nullptr;
-    HIPCHECK(hipMalloc(&tmp, per * sizeof(double)));
-    HIPCHECK(hipMalloc(&u, per * sizeof(uint64_t)));
+    DevTmp<double> tmp;
+    DevTmp<uint64_t> u;
+    PFX_DMALLOC(c, &tmp.p, per * sizeof(double));
+    PFX_DMALLOC(c, &u.p, per * sizeof(uint64_t));
     Launch L{c, nullptr};
     for (int p = 0; p < 2 * c->beta; ++p) {
-        launch_ntt(L, tmp, k->d_k + (size_t)p * per, contiguous_map(NP, 0), true);
-        launch_f64_to_u64(L, u, tmp, per);
-        HIPCHECK(hipMemcpy(words + (size_t)p * per, u, per * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        launch_ntt(L, tmp.p, k->d_k + (size_t)p * per, contiguous_map(NP, 0), true);
+        launch_f64_to_u64(L, u.p, tmp.p, per);
+        HIPCHECK(hipMemcpy(words + (size_t)p * per, u.p, per * sizeof(uint64_t), hipMemcpyDeviceToHost));
     }
-    (void)hipFree(tmp);
-    (void)hipFree(u);
+    return PFX_OK;
+}
+
+pfx_status pfx_swk_import(pfx_ctx *c, uint32_t galois, const uint64_t *words, size_t n_words, pfx_swk **out) {
+    REQUIRE(c && words && out, PFX_EINVAL, "null argument");
+    REQUIRE(galois == 0 || ((galois & 1) && galois < 2u * c->N), PFX_EINVAL, "galois must be 0 or odd < 2N");
+    const int NP = c->L + c->K;
+    const size_t N = c->N, per = (size_t)NP * N;
+    REQUIRE(n_words == (size_t)c->beta * 2 * per, PFX_EINVAL, "n_words must be beta * 2 * (n_q + n_p) * N");
+    for (size_t p = 0; p < (size_t)2 * c->beta; ++p)
+        for (int m = 0; m < NP; ++m)
+            for (size_t i = 0; i < N; ++i)
+                REQUIRE(words[p * per + (size_t)m * N + i] < c->primes[m], PFX_EINVAL, "word not below its prime");
+    HIPCHECK(hipSetDevice(c->device));
+    std::unique_ptr<pfx_swk> k(new pfx_swk);
+    k->ctx = c;
+    k->uid = next_uid();
+    k->galois = galois;
+    DevTmp<double> dk;
+    DevTmp<uint64_t> stage;
+    PFX_DMALLOC(c, &dk.p, (size_t)c->beta * 2 * per * sizeof(double));
+    PFX_DMALLOC(c, &stage.p, per * sizeof(uint64_t));
+    Launch L{c, nullptr};
+    for (size_t p = 0; p < (size_t)2 * c->beta; ++p) {
+        HIPCHECK(hipMemcpy(stage.p, words + p * per, per * sizeof(uint64_t), hipMemcpyHostToDevice));
+        launch_u64_to_f64(L, dk.p + p * per, stage.p, per);
+        launch_ntt(L, dk.p + p * per, nullptr, contiguous_map(NP, 0), false);
+        HIPCHECK(hipStreamSynchronize(nullptr));
+    }
+    k->d_k = dk.release();
+    *out = k.release();
+    return PFX_OK;
+}
+
+pfx_status pfx_sk_export(const pfx_sk *sk, int8_t *s, size_t n) {
+    REQUIRE(sk && s, PFX_EINVAL, "null argument");
+    REQUIRE(n == sk->h_s.size(), PFX_EINVAL, "n must be N");
+    std::copy(sk->h_s.begin(), sk->h_s.end(), s);
     return PFX_OK;
 }
 
@@ -983,7 +1165,8 @@ uint32_t pfx_swk_galois(const pfx_swk *k) { return k ? k->galois : 0; }
 
 void pfx_swk_destroy(pfx_swk *k) {
     if (!k) return;
-    (void)hipFree(k->d_k);
+    graph_forget(k->uid);
+    dfree(k->d_k);
     delete k;
 }
 
@@ -995,17 +1178,18 @@ pfx_status pfx_ct_create(pfx_ctx *c, uint32_t cap_limbs, uint32_t cap_degree, pf
     HIPCHECK(hipSetDevice(c->device));
     std::unique_ptr<pfx_ct> x(new pfx_ct);
     x->ctx = c;
+    x->uid = next_uid();
     x->cap_limbs = cap_limbs;
     x->cap_degree = cap_degree;
-    if (hipMalloc(&x->d, (size_t)(cap_degree + 1) * cap_limbs * c->N * sizeof(double)) != hipSuccess)
-        return fail(PFX_ENOMEM, "ciphertext allocation failed");
+    PFX_DMALLOC(c, &x->d, (size_t)(cap_degree + 1) * cap_limbs * c->N * sizeof(double));
     *out = x.release();
     return PFX_OK;
 }
 
 void pfx_ct_destroy(pfx_ct *x) {
     if (!x) return;
-    if (x->owns) (void)hipFree(x->d);
+    graph_forget(x->uid);
+    if (x->owns) dfree(x->d);
     delete x;
 }
 
@@ -1388,8 +1572,11 @@ pfx_status pfx_relinearize(pfx_ctx *c, const pfx_ct *a, const pfx_swk *rlk, pfx_
     return PFX_OK;
 }
 
-pfx_status pfx_mul_relin(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk, pfx_ct *out,
-                         void *stream) {
+}  // extern "C"
+
+namespace pfx {
+
+pfx_status mul_relin_check(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk, pfx_ct *out) {
     pfx_status r = check_ct(c, a, "a");
     if (r) return r;
     r = check_ct(c, b, "b");
@@ -1397,34 +1584,67 @@ pfx_status pfx_mul_relin(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx
     REQUIRE(rlk && rlk->ctx == c, PFX_EINVAL, "bad relinearisation key");
     REQUIRE(rlk->galois == 0 && !rlk->from_secret, PFX_ENOKEY, "key is not a relinearisation key");
     REQUIRE(a->degree == 1 && b->degree == 1, PFX_EINVAL, "mul_relin needs two degree-1 ciphertexts");
+    return check_out(out, std::min(a->n_limbs, b->n_limbs), 1);
+}
+
+// HMult + relin of checked operands with the key-switch scratch given (regions
+// sized for the operands' level; t3 with three polynomials t3_stride apart is
+// only used when the output aliases an operand).
+void mul_relin_run(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk, pfx_ct *out, hipStream_t st,
+                   const KsScratch &s) {
     const uint32_t lv = std::min(a->n_limbs, b->n_limbs);
-    r = check_out(out, lv, 1);
-    if (r) return r;
-    Ws w;
-    r = get_ws(c, S(stream), w);
-    if (r) return r;
-    Launch L{c, S(stream)};
+    Launch L{c, st};
     const double sc = a->scale * b->scale;
+    KsOperand op;
     if (out->d != a->d && out->d != b->d) {
         // the tensor product is formed inside the key switch, never stored
-        KsOperand op;
         op.mode = KS_PRODUCT;
         op.a0 = a->poly(0);
         op.a1 = a->poly(1);
         op.b0 = b->poly(0);
         op.b1 = b->poly(1);
-        ks_core(c, L, w, op, lv, rlk, out->poly(0), out->poly(1));
     } else {
         // the output overwrites an operand that other workgroups of the last
         // launch still read: take the tensor product into scratch first
-        const size_t PL = (size_t)c->L * c->N;
-        double *t0 = w.at(w.lay.t3), *t1 = t0 + PL, *t2 = t1 + PL;
+        double *t0 = s.t3, *t1 = t0 + s.t3_stride, *t2 = t1 + s.t3_stride;
         launch_tensor(L, t0, t1, t2, a->poly(0), a->poly(1), b->poly(0), b->poly(1), lv);
-        ks_core(c, L, w, ks_plain(t2, t0, t1), lv, rlk, out->poly(0), out->poly(1));
+        op = ks_plain(t2, t0, t1);
     }
+    KsBatch kb;
+    kb.nb = 1;
+    kb.mode = op.mode;
+    kb.op[0] = op;
+    kb.out0[0] = out->poly(0);
+    kb.out1[0] = out->poly(1);
+    kb.dcoef = s.dcoef;
+    kb.ext = s.ext;
+    kb.acc = s.acc;
+    kb.tmp = s.tmp;
+    ks_run(L, kb, lv, rlk);
     out->n_limbs = lv;
     out->degree = 1;
     out->scale = sc;
+}
+
+}  // namespace pfx
+
+extern "C" {
+
+pfx_status pfx_mul_relin(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk, pfx_ct *out,
+                         void *stream) {
+    pfx_status r = mul_relin_check(c, a, b, rlk, out);
+    if (r) return r;
+    Ws w;
+    r = get_ws(c, S(stream), w);
+    if (r) return r;
+    KsScratch s;
+    s.dcoef = w.at(w.lay.dcoef);
+    s.ext = w.at(w.lay.ext);
+    s.acc = w.at(w.lay.acc);
+    s.tmp = w.at(w.lay.mdtmp);
+    s.t3 = w.at(w.lay.t3);
+    s.t3_stride = (size_t)c->L * c->N;
+    mul_relin_run(c, a, b, rlk, out, S(stream), s);
     return PFX_OK;
 }
 
@@ -1868,11 +2088,11 @@ pfx_status get_repack_ws(pfx_ctx *c, hipStream_t st, size_t doubles, double **ou
     if (w->rcap < doubles) {
         if (c->capturing) return fail(PFX_EINVAL, "repacking workspace must be reserved before graph capture");
         (void)hipStreamSynchronize(st);
-        (void)hipFree(w->rbuf);
+        bump_scratch_epoch();
+        dfree(w->rbuf);
         w->rbuf = nullptr;
         w->rcap = 0;
-        if (hipMalloc(&w->rbuf, doubles * sizeof(double)) != hipSuccess)
-            return fail(PFX_ENOMEM, "repacking workspace allocation failed");
+        PFX_DMALLOC(c, &w->rbuf, doubles * sizeof(double));
         w->rcap = doubles;
     }
     *out = w->rbuf;
@@ -2550,67 +2770,101 @@ pfx_status pfx_run_circuit(pfx_ctx *c, const pfx_op *ops, size_t n_ops, pfx_ct *
     };
     if (!(mode & PFX_RUN_GRAPH)) return exec();
     REQUIRE(stream != nullptr, PFX_EINVAL, "graph capture needs a non-default stream");
-    // the graph is valid for this op list, these objects and these input shapes
+    // The graph is valid for this op list, these objects (by identity: never
+    // an address that a freed object may have left behind), their capacities,
+    // these input shapes and plaintext levels, this stream and the scratch
+    // epoch it was captured in.
     std::string key((const char *)ops, n_ops * sizeof(pfx_op));
+    std::vector<uint64_t> uids{c->uid};
     auto put = [&](const void *p, size_t n) { key.append((const char *)p, n); };
-    for (size_t i = 0; i < n_regs; ++i) put(&regs[i]->d, sizeof(double *));
+    for (size_t i = 0; i < n_regs; ++i) {
+        put(&regs[i]->uid, sizeof(uint64_t));
+        put(&regs[i]->cap_limbs, sizeof(uint32_t));
+        put(&regs[i]->cap_degree, sizeof(uint32_t));
+        uids.push_back(regs[i]->uid);
+    }
     for (size_t i = 0; i < n_inputs; ++i) {
         put(&regs[i]->n_limbs, sizeof(uint32_t));
         put(&regs[i]->degree, sizeof(uint32_t));
         put(&regs[i]->scale, sizeof(double));
     }
-    for (size_t i = 0; i < n_pts; ++i) put(&pts[i]->d, sizeof(double *));
-    for (size_t i = 0; i < n_gks; ++i) put(&gks[i]->d_k, sizeof(double *));
-    if (rlk) put(&rlk->d_k, sizeof(double *));
+    for (size_t i = 0; i < n_pts; ++i) {
+        REQUIRE(pts[i], PFX_EINVAL, "null plaintext");
+        put(&pts[i]->uid, sizeof(uint64_t));
+        put(&pts[i]->n_limbs, sizeof(uint32_t));
+        put(&pts[i]->scale, sizeof(double));
+        uids.push_back(pts[i]->uid);
+    }
+    for (size_t i = 0; i < n_gks; ++i) {
+        REQUIRE(gks[i], PFX_EINVAL, "null Galois key");
+        put(&gks[i]->uid, sizeof(uint64_t));
+        uids.push_back(gks[i]->uid);
+    }
+    if (rlk) {
+        put(&rlk->uid, sizeof(uint64_t));
+        uids.push_back(rlk->uid);
+    }
+    for (uint64_t u : uids)
+        REQUIRE(u != 0, PFX_EINVAL, "graph mode needs library-created objects");
     put(&stream, sizeof(void *));
     put(&mode, sizeof(int));
-    auto it = c->graphs.find(key);
-    if (it == c->graphs.end()) {
-        Ws w;
-        pfx_status r = get_ws(c, S(stream), w);   // allocate scratch before capturing
+    pfx_status lr = PFX_OK;
+    auto replay = [&](GraphExec &x, const GraphCache<GraphExec>::Meta &meta) {
+        for (size_t i = n_inputs; i < n_regs; ++i) {   // register metadata as the capture left it
+            regs[i]->n_limbs = meta[i].first & 0xffff;
+            regs[i]->degree = meta[i].first >> 16;
+            regs[i]->scale = meta[i].second;
+        }
+        if (hipGraphLaunch(x.exec, S(stream)) != hipSuccess || hipEventRecord(x.done, S(stream)) != hipSuccess)
+            lr = fail(PFX_EDEVICE, "graph launch failed");
+    };
+    if (graphs().launch(key, scratch_epoch().load(), replay)) return lr;
+
+    Ws w;
+    pfx_status r = get_ws(c, S(stream), w);   // allocate scratch before capturing
+    if (r) return r;
+    const int nb = (int)max_mr_run(ops, n_ops, kMaxBatch);
+    KsBatch kb;
+    if (nb > 1 && !lanes) r = get_batch_ws(c, S(stream), nb, kb);
+    if (r) return r;
+    if (lanes) {
+        r = ensure_lanes(c);
+        for (int l = 0; l < kLanes && !r; ++l) {
+            r = get_ws(c, c->lanes[l], w);
+            if (!r && nb > 1) r = get_batch_ws(c, c->lanes[l], nb, kb);
+        }
         if (r) return r;
-        const int nb = (int)max_mr_run(ops, n_ops, kMaxBatch);
-        KsBatch kb;
-        if (nb > 1 && !lanes) r = get_batch_ws(c, S(stream), nb, kb);
-        if (r) return r;
-        if (lanes) {
-            r = ensure_lanes(c);
-            for (int l = 0; l < kLanes && !r; ++l) {
-                r = get_ws(c, c->lanes[l], w);
-                if (!r && nb > 1) r = get_batch_ws(c, c->lanes[l], nb, kb);
-            }
-            if (r) return r;
-        }
-        const bool prof = c->prof_on;
-        c->prof_on = false;
-        c->capturing = true;
-        HIPCHECK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal));
-        r = exec();
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(S(stream), &g);
-        c->capturing = false;
-        c->prof_on = prof;
-        if (r) {
-            if (g) (void)hipGraphDestroy(g);
-            return r;
-        }
-        if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-        pfx_ctx::GraphEntry ent;
-        e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-        for (size_t i = 0; i < n_regs; ++i)
-            ent.meta.push_back({regs[i]->n_limbs | (regs[i]->degree << 16), regs[i]->scale});
-        it = c->graphs.emplace(key, ent).first;
-    } else {
-        for (size_t i = n_inputs; i < n_regs; ++i) {
-            regs[i]->n_limbs = it->second.meta[i].first & 0xffff;
-            regs[i]->degree = it->second.meta[i].first >> 16;
-            regs[i]->scale = it->second.meta[i].second;
-        }
     }
-    HIPCHECK(hipGraphLaunch(it->second.exec, S(stream)));
-    return PFX_OK;
+    // every scratch region this capture writes is in place: the graph belongs
+    // to the current epoch
+    const uint64_t epoch = scratch_epoch().load();
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    c->capturing = true;
+    HIPCHECK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal));
+    r = exec();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(S(stream), &g);
+    c->capturing = false;
+    c->prof_on = prof;
+    if (r) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    GraphExec x;
+    x.device = c->device;
+    e = hipGraphInstantiate(&x.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    if (hipEventCreateWithFlags(&x.done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGraphExecDestroy(x.exec);
+        return fail(PFX_EDEVICE, "graph event creation failed");
+    }
+    GraphCache<GraphExec>::Meta meta;
+    for (size_t i = 0; i < n_regs; ++i) meta.push_back({regs[i]->n_limbs | (regs[i]->degree << 16), regs[i]->scale});
+    graphs().insert_and_launch(key, epoch, x, uids, meta, replay);
+    return lr;
 }
 
 // ------------------------------------------------------------------ batched form
@@ -2735,14 +2989,18 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
         }
     if (mode == 1 || mode == 3) return batch_ops(ctxs, a, b, rlk, out, n, true, group, stream);
     REQUIRE(stream != nullptr, PFX_EINVAL, "graph capture needs a non-default stream");
+    // keyed on object identities and shapes, as pfx_run_circuit's graphs
     std::string key = "batch";
+    std::vector<uint64_t> uids;
     auto put = [&](const void *p, size_t k) { key.append((const char *)p, k); };
     for (size_t i = 0; i < n; ++i) {
-        put(&ctxs[i], sizeof(void *));
-        put(&a[i]->d, sizeof(void *));
-        put(&b[i]->d, sizeof(void *));
-        put(&out[i]->d, sizeof(void *));
-        put(&rlk[i]->d_k, sizeof(void *));
+        for (uint64_t u : {ctxs[i]->uid, a[i]->uid, b[i]->uid, out[i]->uid, rlk[i]->uid}) {
+            REQUIRE(u != 0, PFX_EINVAL, "graph mode needs library-created objects");
+            put(&u, sizeof(uint64_t));
+            uids.push_back(u);
+        }
+        put(&out[i]->cap_limbs, sizeof(uint32_t));
+        put(&out[i]->cap_degree, sizeof(uint32_t));
         put(&a[i]->n_limbs, sizeof(uint32_t));
         put(&b[i]->n_limbs, sizeof(uint32_t));
         put(&a[i]->scale, sizeof(double));
@@ -2750,33 +3008,47 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
     }
     put(&stream, sizeof(void *));
     put(&mode, sizeof(int));
-    auto it = c0->graphs.find(key);
-    if (it == c0->graphs.end()) {
-        for (size_t i = 0; i < n; ++i) ctxs[i]->capturing = true;
-        HIPCHECK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal));
-        r = batch_ops(ctxs, a, b, rlk, out, n, true, group, stream);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(S(stream), &g);
-        for (size_t i = 0; i < n; ++i) ctxs[i]->capturing = false;
-        if (r) {
-            if (g) (void)hipGraphDestroy(g);
-            return r;
-        }
-        if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("batch capture: ") + hipGetErrorString(e));
-        pfx_ctx::GraphEntry ent;
-        e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-        for (size_t i = 0; i < n; ++i) ent.meta.push_back({out[i]->n_limbs | (out[i]->degree << 16), out[i]->scale});
-        it = c0->graphs.emplace(key, ent).first;
-    } else {
+    pfx_status lr = PFX_OK;
+    auto replay = [&](GraphExec &x, const GraphCache<GraphExec>::Meta &meta) {
         for (size_t i = 0; i < n; ++i) {
-            out[i]->n_limbs = it->second.meta[i].first & 0xffff;
-            out[i]->degree = it->second.meta[i].first >> 16;
-            out[i]->scale = it->second.meta[i].second;
+            out[i]->n_limbs = meta[i].first & 0xffff;
+            out[i]->degree = meta[i].first >> 16;
+            out[i]->scale = meta[i].second;
         }
+        if (hipGraphLaunch(x.exec, S(stream)) != hipSuccess || hipEventRecord(x.done, S(stream)) != hipSuccess)
+            lr = fail(PFX_EDEVICE, "graph launch failed");
+    };
+    if (graphs().launch(key, scratch_epoch().load(), replay)) return lr;
+    const uint64_t epoch = scratch_epoch().load();   // scratch of every (context, lane) reserved above
+    for (size_t i = 0; i < n; ++i) ctxs[i]->capturing = true;
+    HIPCHECK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal));
+    r = batch_ops(ctxs, a, b, rlk, out, n, true, group, stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(S(stream), &g);
+    for (size_t i = 0; i < n; ++i) ctxs[i]->capturing = false;
+    if (r) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
     }
-    HIPCHECK(hipGraphLaunch(it->second.exec, S(stream)));
+    if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("batch capture: ") + hipGetErrorString(e));
+    GraphExec x;
+    x.device = c0->device;
+    e = hipGraphInstantiate(&x.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PFX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    if (hipEventCreateWithFlags(&x.done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGraphExecDestroy(x.exec);
+        return fail(PFX_EDEVICE, "graph event creation failed");
+    }
+    GraphCache<GraphExec>::Meta meta;
+    for (size_t i = 0; i < n; ++i) meta.push_back({out[i]->n_limbs | (out[i]->degree << 16), out[i]->scale});
+    graphs().insert_and_launch(key, epoch, x, uids, meta, replay);
+    return lr;
+}
+
+pfx_status pfx_graph_cache_stats(size_t *entries, uint64_t *captures) {
+    if (entries) *entries = graphs().size();
+    if (captures) *captures = graphs().captures();
     return PFX_OK;
 }
 
@@ -2784,13 +3056,13 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
 pfx_status pfx_dev_alloc(pfx_ctx *c, size_t bytes, void **out) {
     REQUIRE(c && out, PFX_EINVAL, "null argument");
     HIPCHECK(hipSetDevice(c->device));
-    if (hipMalloc(out, bytes ? bytes : 1) != hipSuccess) return fail(PFX_ENOMEM, "device allocation failed");
+    PFX_DMALLOC(c, out, bytes);
     return PFX_OK;
 }
 
 pfx_status pfx_dev_free(pfx_ctx *c, void *p) {
     REQUIRE(c, PFX_EINVAL, "null context");
-    HIPCHECK(hipFree(p));
+    dfree(p);
     return PFX_OK;
 }
 
@@ -2852,9 +3124,10 @@ pfx_status pfx_stream_destroy(pfx_ctx *c, void *stream) {
         std::lock_guard<std::mutex> g(c->mu);
         auto it = c->ws.find(S(stream));
         if (it != c->ws.end()) {
-            (void)hipFree(it->second->buf);
-            (void)hipFree(it->second->bbuf);
-            (void)hipFree(it->second->rbuf);
+            bump_scratch_epoch();
+            dfree(it->second->buf);
+            dfree(it->second->bbuf);
+            dfree(it->second->rbuf);
             delete it->second;
             c->ws.erase(it);
         }

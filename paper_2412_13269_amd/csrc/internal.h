@@ -5,10 +5,12 @@
 #include <atomic>
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
 
+#include "graph_cache.h"
 #include "pfx.h"
 
 namespace pfx {
@@ -74,6 +76,16 @@ struct Workspace {
     size_t rcap = 0;
 };
 
+// The device memory of a context: its allocator (the caller's, or hipMalloc
+// when alloc is null), the bytes it holds and their cap (0: none).
+struct MemAccount {
+    std::mutex mu;
+    pfx_alloc_fn alloc = nullptr;
+    pfx_free_fn free = nullptr;
+    void *user = nullptr;
+    size_t budget = 0, in_use = 0, peak = 0;
+};
+
 struct ProfEntry {
     hipEvent_t start, stop;
     std::string name;
@@ -104,15 +116,14 @@ struct pfx_ctx {
     pfx::RescaleConst *d_rescale = nullptr; // [L][L]
     std::vector<pfx::PrimeDev> h_primes;
 
+    uint64_t uid = 0;                 // identity for the graph cache (never reused)
+
+    // Device memory of the context (dmalloc / dfree), shared with the
+    // allocations it made so that they can be freed after the context.
+    std::shared_ptr<pfx::MemAccount> mem = std::make_shared<pfx::MemAccount>();
     std::mutex mu;
     std::map<hipStream_t, pfx::Workspace *> ws;
 
-    // captured op lists (pfx_run_circuit with use_graph)
-    struct GraphEntry {
-        hipGraphExec_t exec;
-        std::vector<std::pair<uint32_t, double>> meta;   // (n_limbs | degree << 16, scale) per register
-    };
-    std::map<std::string, GraphEntry> graphs;
     std::vector<hipStream_t> lanes;       // batch lanes (default priority)
     std::vector<hipEvent_t> lane_events;
     std::atomic<bool> capturing{false};
@@ -125,12 +136,14 @@ struct pfx_ctx {
 
 struct pfx_sk {
     pfx_ctx *ctx;
+    uint64_t uid = 0;
     double *d_s;          // (L + K) limbs, NTT domain
     std::vector<int8_t> h_s;
 };
 
 struct pfx_swk {
     pfx_ctx *ctx;
+    uint64_t uid = 0;
     uint32_t galois;
     double *d_k;               // [beta][2][L + K][N], NTT domain
     bool from_secret = false;  // pfx_swk_create_from: neither a relinearisation nor a Galois key
@@ -138,6 +151,7 @@ struct pfx_swk {
 
 struct pfx_ct {
     pfx_ctx *ctx;
+    uint64_t uid = 0;     // identity for the graph cache (0: library-internal temporary)
     uint32_t cap_limbs, cap_degree;
     uint32_t n_limbs = 0, degree = 0;
     double scale = 1.0;
@@ -149,6 +163,32 @@ struct pfx_ct {
 namespace pfx {
 
 // ---------------------------------------------------------------- host helpers
+// Drops every captured graph that depends on the object (api.cpp).
+void graph_forget(uint64_t uid);
+// Device allocation of `bytes` for context c (api.cpp): through the caller's
+// allocator when set, within the context's budget; PFX_ENOMEM (*p untouched)
+// when the budget or the allocator refuses.  dfree releases memory dmalloc
+// made through the allocator that made it, and returns the bytes to its
+// context's account (also after the context is gone); null and pointers
+// dmalloc did not make are ignored.
+pfx_status dmalloc(pfx_ctx *c, void **p, size_t bytes);
+template <class T>
+pfx_status dmalloc(pfx_ctx *c, T **p, size_t bytes) {
+    void *v = nullptr;
+    pfx_status r = dmalloc(c, &v, bytes);
+    if (!r) *p = static_cast<T *>(v);
+    return r;
+}
+void dfree(void *p);
+// Seeded sampling (sampler.cpp): SHAKE-256 streams keyed by seed, tag, index
+// and limb, and the draws of the secret, of uniform residues and of the
+// discrete Gaussian errors (sigma 3.2, |e| <= 19) read from them.
+constexpr uint32_t kTagSecret = 1, kTagKeyA = 2, kTagKeyE = 3, kTagEncA = 4, kTagEncE = 5;
+void shake256(const uint8_t *msg, size_t n, uint8_t *out, size_t outlen);
+void sample_uniform(const uint8_t seed[32], uint32_t tag, uint32_t index, uint32_t limb, uint64_t q, size_t n,
+                    uint64_t *out);
+void sample_secret(const uint8_t seed[32], size_t n, int32_t h, int8_t *out);
+void sample_gaussian(const uint8_t seed[32], uint32_t tag, uint32_t index, size_t n, int64_t *out);
 void set_error(const std::string &msg);
 pfx_status fail(pfx_status s, const std::string &msg);
 
@@ -273,6 +313,16 @@ struct KsBatch {
     size_t sdc = 0, sext = 0, sacc = 0, stmp = 0;
 };
 void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int lv);
+// Scratch of one key switch (KsBatch entry 0) plus room for a tensor product.
+struct KsScratch {
+    double *dcoef = nullptr, *ext = nullptr, *acc = nullptr, *tmp = nullptr, *t3 = nullptr;
+    size_t t3_stride = 0;
+};
+// HMult + relinearisation (api.cpp): the argument checks of pfx_mul_relin, and
+// its launches with the scratch regions given instead of the stream's.
+pfx_status mul_relin_check(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk, pfx_ct *out);
+void mul_relin_run(pfx_ctx *c, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk, pfx_ct *out, hipStream_t st,
+                   const KsScratch &s);
 void launch_ks_inner_repack(const Launch &L, const KsBatch &kb, const double *key, int lv);
 // The whole repacking key switch of an entry in one workgroup (N = 2^12, one
 // ciphertext limb, one special prime, digits of one prime: repack_fused_ok);

@@ -1015,9 +1015,13 @@ void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int 
     else PFX_KS_INNER(kMaxBatch);
 #undef PFX_KS_INNER
     HIP_LAUNCH_CHECK();
-    // per entry: ext / d and the accumulators; the key once for the batch
+    // Algorithmic bytes of the inner product: the key once for the batch and
+    // each entry's two accumulators.  The decomposition it also reads (the
+    // ModUp limbs, written by the previous launches) is an intermediate of this
+    // launch sequence, not an operand of the key switch, so its re-read counts
+    // as traffic above the algorithmic bytes.
     const int beta = (lv + ctx->alpha - 1) / ctx->alpha;
-    prof_end(L, "ks_inner", ev, 8.0 * (double)ctx->N * (lv + ctx->K) * ((beta + 2.0) * kb.nb + 2.0 * beta));
+    prof_end(L, "ks_inner", ev, 8.0 * (double)ctx->N * (lv + ctx->K) * (2.0 * kb.nb + 2.0 * beta));
 }
 
 // ============================================================== keys, encryption

@@ -165,6 +165,7 @@ void admit(pfx_server *s, Request *r, int slot) {
     for (size_t i = r->n_inputs; i < r->n_regs; ++i) {
         pfx_ct *v = new pfx_ct;
         v->ctx = c;
+        v->uid = next_uid();
         v->cap_limbs = r->reg_limbs;
         v->cap_degree = r->reg_degree[i];
         v->d = next;
@@ -271,8 +272,10 @@ pfx_status pfx_server_create(pfx_ctx *c, size_t hbm_budget, uint32_t slots, uint
     s->scratch = scratch;
     s->max_batch = (int)max_batch;
     const size_t arena_bytes = (hbm_budget - scratch) / kAlign * kAlign;
-    if (arena_bytes && hipMalloc(&s->arena_mem, arena_bytes) != hipSuccess)
-        return fail(PFX_ENOMEM, "arena allocation of " + std::to_string(arena_bytes) + " bytes failed");
+    if (arena_bytes) {
+        pfx_status r = dmalloc(c, &s->arena_mem, arena_bytes);
+        if (r) return r;
+    }
     s->arena.init(static_cast<char *>(s->arena_mem), arena_bytes);
     s->running.assign(slots, nullptr);
     s->callbacks.resize(slots);
@@ -286,7 +289,7 @@ pfx_status pfx_server_create(pfx_ctx *c, size_t hbm_budget, uint32_t slots, uint
         }
         if (r) {
             for (void *x : s->streams) pfx_stream_destroy(c, x);
-            (void)hipFree(s->arena_mem);
+            dfree(s->arena_mem);
             return r;
         }
         s->callbacks[i] = Callback{s.get(), (int)i};
@@ -404,7 +407,7 @@ void pfx_server_destroy(pfx_server *s) {
     s->worker.join();
     for (void *st : s->streams) pfx_stream_destroy(s->ctx, st);   // also waits for the host functions
     for (auto &kv : s->tickets) delete kv.second;                 // queued, finished and unpolled
-    (void)hipFree(s->arena_mem);
+    dfree(s->arena_mem);
     delete s;
 }
 

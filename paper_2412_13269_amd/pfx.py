@@ -99,6 +99,16 @@ _SIGS = {
     "pfx_swk_create": (_i32, [_vp, _vp, _u32, _u64p, _i64p, _VPP]),
     "pfx_swk_export": (_i32, [_vp, _vp, _u64p, _sz]),
     "pfx_swk_galois": (_u32, [_vp]),
+    "pfx_swk_import": (_i32, [_vp, _u32, _u64p, _sz, _VPP]),
+    "pfx_sk_export": (_i32, [_vp, _vp, _sz]),
+    "pfx_keygen_secret": (_i32, [_vp, _vp, _i32, _VPP]),
+    "pfx_keygen_relin": (_i32, [_vp, _vp, _vp, _VPP]),
+    "pfx_keygen_galois": (_i32, [_vp, _vp, _vp, _sz, ctypes.c_int, _vp, _VPP]),
+    "pfx_encrypt_seeded": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pfx_shake256": (_i32, [_vp, _sz, _vp, _sz]),
+    "pfx_sample_uniform": (_i32, [_vp, _u32, _u32, _u32, ctypes.c_uint64, _sz, _u64p]),
+    "pfx_sample_secret": (_i32, [_vp, _sz, _i32, _vp]),
+    "pfx_sample_gaussian": (_i32, [_vp, _u32, _u32, _sz, _i64p]),
     "pfx_swk_destroy": (None, [_vp]),
     "pfx_encode": (_i32, [_vp, _f64p, _f64p, _sz, _u32, ctypes.c_double, _VPP]),
     "pfx_decode": (_i32, [_vp, _vp, _f64p, _f64p, _sz]),
@@ -151,6 +161,9 @@ _SIGS = {
     "pfx_run_circuit": (_i32, [_vp, ctypes.POINTER(pfx_op), _sz, _VPP, _sz, _sz, _VPP, _sz, _vp, _VPP, _sz,
                                ctypes.c_int, _vp]),
     "pfx_batch_mul_relin_rescale": (_i32, [_VPP, _VPP, _VPP, _VPP, _VPP, _sz, ctypes.c_int, _vp]),
+    "pfx_ctx_set_allocator": (_i32, [_vp, _vp, _vp, _vp, _sz]),
+    "pfx_ctx_mem": (_i32, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "pfx_graph_cache_stats": (_i32, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_uint64)]),
     "pfx_server_create": (_i32, [_vp, _sz, _u32, _u32, _vp, _VPP, _sz, _VPP]),
     "pfx_server_submit": (_i32, [_vp, ctypes.POINTER(pfx_request), ctypes.POINTER(ctypes.c_uint64)]),
     "pfx_server_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(pfx_request_info)]),
@@ -309,6 +322,76 @@ def pfx_swk_export(ctx, k, beta: int, n_primes: int, n: int) -> np.ndarray:
 
 def pfx_swk_galois(k) -> int:
     return _lib.pfx_swk_galois(k)
+
+
+def _seed(seed: bytes):
+    seed = bytes(seed)
+    if len(seed) != 32:
+        raise ValueError("seeds are 32 bytes")
+    return ctypes.create_string_buffer(seed, 32)
+
+
+def pfx_swk_import(ctx, galois: int, words):
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    h = ctypes.c_void_p()
+    _check(_lib.pfx_swk_import(ctx, galois, _u64(w)[1], w.size, ctypes.byref(h)))
+    return h.value
+
+
+def pfx_sk_export(sk, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.int8)
+    _check(_lib.pfx_sk_export(sk, out.ctypes.data, n))
+    return out
+
+
+def pfx_keygen_secret(ctx, seed: bytes, h: int):
+    out = ctypes.c_void_p()
+    _check(_lib.pfx_keygen_secret(ctx, _seed(seed), h, ctypes.byref(out)))
+    return out.value
+
+
+def pfx_keygen_relin(ctx, sk, seed: bytes):
+    out = ctypes.c_void_p()
+    _check(_lib.pfx_keygen_relin(ctx, sk, _seed(seed), ctypes.byref(out)))
+    return out.value
+
+
+def pfx_keygen_galois(ctx, sk, steps, conj: bool, seed: bytes):
+    st = np.ascontiguousarray(steps, dtype=np.int32)
+    n = st.size + (1 if conj else 0)
+    outs = (ctypes.c_void_p * max(1, n))()
+    _check(_lib.pfx_keygen_galois(ctx, sk, st.ctypes.data if st.size else None, st.size, int(bool(conj)),
+                                  _seed(seed), outs))
+    return [outs[i] for i in range(n)]
+
+
+def pfx_encrypt_seeded(ctx, sk, pt, seed: bytes, out, stream=None):
+    _check(_lib.pfx_encrypt_seeded(ctx, sk, pt, _seed(seed), out, _stream(stream)))
+
+
+def pfx_shake256(msg: bytes, outlen: int) -> bytes:
+    buf = ctypes.create_string_buffer(bytes(msg), max(1, len(msg)))
+    out = ctypes.create_string_buffer(max(1, outlen))
+    _check(_lib.pfx_shake256(buf, len(msg), out, outlen))
+    return out.raw[:outlen]
+
+
+def pfx_sample_uniform(seed: bytes, tag: int, index: int, limb: int, q: int, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.uint64)
+    _check(_lib.pfx_sample_uniform(_seed(seed), tag, index, limb, q, n, _u64(out)[1]))
+    return out
+
+
+def pfx_sample_secret(seed: bytes, n: int, h: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.int8)
+    _check(_lib.pfx_sample_secret(_seed(seed), n, h, out.ctypes.data))
+    return out
+
+
+def pfx_sample_gaussian(seed: bytes, tag: int, index: int, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.int64)
+    _check(_lib.pfx_sample_gaussian(_seed(seed), tag, index, n, _i64(out)[1]))
+    return out
 
 
 def pfx_swk_destroy(k):
@@ -582,6 +665,40 @@ def pfx_batch_mul_relin_rescale(ctxs, a, b, rlks, outs, mode: int, stream=None):
     arr = lambda xs: (ctypes.c_void_p * max(1, n))(*xs)
     _check(_lib.pfx_batch_mul_relin_rescale(arr(ctxs), arr(a), arr(b), arr(rlks), arr(outs), n, mode,
                                             _stream(stream)))
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+_CALLBACKS = []   # every allocator thunk handed to the library: memory made through one is freed through it
+
+
+def pfx_ctx_set_allocator(ctx, alloc=None, free=None, budget: int = 0):
+    """alloc(bytes, stream) -> device pointer or 0, free(ptr, stream): Python
+    callables (both or neither; their C thunks are kept for the life of the
+    process, since memory is freed through the thunk that made it); budget:
+    bytes the context may hold (0 = no cap)."""
+    fa = ALLOC_FN(lambda n, st, u: alloc(n, st) or None) if alloc else None
+    ff = FREE_FN(lambda p, st, u: free(p, st)) if free else None
+    _CALLBACKS.append((fa, ff))
+    _check(_lib.pfx_ctx_set_allocator(ctx, ctypes.cast(fa, ctypes.c_void_p) if fa else None,
+                                      ctypes.cast(ff, ctypes.c_void_p) if ff else None, None, int(budget)))
+    return (fa, ff)
+
+
+def pfx_ctx_mem(ctx):
+    """(bytes held now, most bytes held so far) of the context's device memory."""
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.pfx_ctx_mem(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def pfx_graph_cache_stats():
+    """(entries held, captures made) of the process-wide graph cache."""
+    e, c = ctypes.c_size_t(), ctypes.c_uint64()
+    _check(_lib.pfx_graph_cache_stats(ctypes.byref(e), ctypes.byref(c)))
+    return e.value, c.value
 
 
 # ---------------------------------------------------------------- served form
