@@ -284,6 +284,24 @@ pfx_status pfx_relinearize_batch(pfx_ctx *ctx, const pfx_ct *const *a, size_t n,
 /* HMult + relinearisation in one call. */
 pfx_status pfx_mul_relin(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk,
                          pfx_ct *out, void *stream);
+/* pfx_mul_relin for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, checks and words as pfx_mul_relin; it calls no hipMalloc,
+ * hipFree or allocating library routine.  Its key-switch scratch is a fixed
+ * device array of the library (pfx_noalloc_scratch_bytes(), 64 MiB, held on
+ * each GPU the library runs on until the process ends; its address is taken
+ * once per device by pfx_ctx_create), not the stream's workspace.  A product
+ * whose scratch would exceed it (N (l + beta (l + K) + 2 (l + K) + 2 l)
+ * doubles at l limbs, plus 3 l N when out aliases an operand; e.g. N = 2^16
+ * at 24 + 4 primes) returns PFX_ENOMEM with nothing launched.  Every call on
+ * one GPU uses the same array and it keeps the last call's contents: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller.  PFX_EINVAL while the library's profiler is on (it
+ * creates events). */
+pfx_status pfx_mul_relin_noalloc(pfx_ctx *ctx, const pfx_ct *a, const pfx_ct *b, const pfx_swk *rlk,
+                                 pfx_ct *out, void *stream);
+/* Bytes of the no-allocation scratch array (per GPU). */
+size_t pfx_noalloc_scratch_bytes(void);
 /* HMult + relinearisation of n pairs under one context and key: out[i] =
  * relin(a[i] * b[i]), word for word what n calls of pfx_mul_relin give.  Pairs
  * of the same level (min of the operands' levels) share the launches of one

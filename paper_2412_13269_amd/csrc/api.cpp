@@ -735,6 +735,8 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(PFX_EDEVICE, std::string("libpfx is built for gfx950, device is ") + prop.gcnArchName);
 
+    pfx_status nr = noalloc_init(device);   // once per device, this device current
+    if (nr) return nr;
     std::unique_ptr<pfx_ctx> c(new pfx_ctx);
     c->uid = next_uid();
     c->device = device;

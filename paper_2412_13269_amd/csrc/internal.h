@@ -180,6 +180,9 @@ pfx_status dmalloc(pfx_ctx *c, T **p, size_t bytes) {
     return r;
 }
 void dfree(void *p);
+// Device address of the no-allocation scratch array on `device`, taken once
+// with that device current (noalloc.hip; pfx_ctx_create calls it).
+pfx_status noalloc_init(int device);
 // Seeded sampling (sampler.cpp): SHAKE-256 streams keyed by seed, tag, index
 // and limb, and the draws of the secret, of uniform residues and of the
 // discrete Gaussian errors (sigma 3.2, |e| <= 19) read from them.

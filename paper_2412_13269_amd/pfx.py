@@ -135,6 +135,8 @@ _SIGS = {
     "pfx_relinearize": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_mul_relin": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "pfx_mul_relin_batch": (_i32, [_vp, _VPP, _VPP, _sz, _vp, _VPP, _vp]),
+    "pfx_mul_relin_noalloc": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pfx_noalloc_scratch_bytes": (_sz, []),
     "pfx_rescale": (_i32, [_vp, _vp, _vp, _vp]),
     "pfx_rescale_batch": (_i32, [_vp, _VPP, _sz, _VPP, _vp]),
     "pfx_relinearize_batch": (_i32, [_vp, _VPP, _sz, _vp, _VPP, _vp]),
@@ -518,6 +520,14 @@ def pfx_relinearize(ctx, a, rlk, out, stream=None):
 
 def pfx_mul_relin(ctx, a, b, rlk, out, stream=None):
     _check(_lib.pfx_mul_relin(ctx, a, b, rlk, out, _stream(stream)))
+
+
+def pfx_mul_relin_noalloc(ctx, a, b, rlk, out, stream=None):
+    _check(_lib.pfx_mul_relin_noalloc(ctx, a, b, rlk, out, _stream(stream)))
+
+
+def pfx_noalloc_scratch_bytes() -> int:
+    return int(_lib.pfx_noalloc_scratch_bytes())
 
 
 def pfx_mul_relin_batch(ctx, a, b, rlk, outs, stream=None):
