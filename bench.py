@@ -194,7 +194,7 @@ def batched_form(X, I, ctx16, rlk16, st, args):
 
     res, digests = {}, {}
     reps = max(2, args.steps // 10)
-    for mode in (0, 1, 2, 3, 4):
+    for mode in (0, 1, 2, 3, 4, 5, 6):
         X.pfx_batch_mul_relin_rescale(*bargs, mode, st)      # warm (and capture for modes 2, 4)
         X.pfx_sync(ctx16, st)
         a0 = time.perf_counter()
@@ -207,7 +207,8 @@ def batched_form(X, I, ctx16, rlk16, st, args):
     if not identical:
         raise SystemExit(f"batched form: modes give different words: {digests}")
     log(f"batched 256: per-ct {1e3 * res[0]:.2f} ms, lanes {1e3 * res[1]:.2f} ms, graph {1e3 * res[2]:.2f} ms, "
-        f"grouped lanes {1e3 * res[3]:.2f} ms, grouped graph {1e3 * res[4]:.2f} ms")
+        f"grouped lanes {1e3 * res[3]:.2f} ms, grouped graph {1e3 * res[4]:.2f} ms, "
+        f"persistent {1e3 * res[5]:.2f} ms, step-major {1e3 * res[6]:.2f} ms")
     for h in outs + list(cut.values()) + list(base.values()):
         X.pfx_ct_destroy(h)
     for ln in (14, 15):
@@ -219,7 +220,7 @@ def batched_form(X, I, ctx16, rlk16, st, args):
     return {"ciphertexts": 256, "op": "HMult+relin+rescale", "ring_degrees": [2 ** 14, 2 ** 15, 2 ** 16],
             "levels": [3, 24], "reps": reps,
             "ms_per_ct_launch_path": 1e3 * res[0], "ms_lanes": 1e3 * res[1], "ms_graph": 1e3 * res[2],
-            "ms_grouped_lanes": 1e3 * res[3], "ms_grouped_graph": 1e3 * res[4],
+            "ms_grouped_lanes": 1e3 * res[3], "ms_grouped_graph": 1e3 * res[4], "ms_persistent": 1e3 * res[5], "ms_step_major": 1e3 * res[6],
             "modes_identical": identical, "shape_groups": len(set(shapes)),
             "us_per_ct_launch_path": 1e6 * res[0] / 256, "us_per_ct_best": 1e6 * min(res.values()) / 256,
             "speedup_best_vs_launch_path": res[0] / min(res.values())}

@@ -562,6 +562,21 @@ pfx_status pfx_run_circuit(pfx_ctx *ctx, const pfx_op *ops, size_t n_ops, pfx_ct
  *           pfx_rescale_batch); an entry whose output aliases its own operand
  *           runs alone
  *   mode 4: mode 3 captured once into a HIP graph and replayed
+ *   mode 5: one persistent cooperative launch for the whole batch: the
+ *           thirteen steps of the key switch and rescale run in order, each
+ *           step's tiles of every entry (any ring degree and level) dealt to
+ *           one grid of resident workgroups, a grid barrier between steps.
+ *           Needs 2^12 <= N <= 2^16, digits of at most 4 primes and at most 4
+ *           special primes (PFX_EINVAL).  An entry whose output aliases an
+ *           operand of any entry runs first, on the per-ciphertext path.
+ *           Scratch for every entry is kept with the stream (grown on
+ *           demand, counted against the first entry's context).  Returns
+ *           after the batch has finished; PFX_EDEVICE if a grid barrier
+ *           timed out (not expected: every workgroup is resident).
+ *   mode 6: mode 5's tiles in step-major order without the persistent grid:
+ *           one launch per step over the tiles of every entry (13 launches
+ *           for the whole batch, each with the registers and occupancy of its
+ *           own step); at most 1024 entries besides those that run alone.
  * Results are identical in every mode.  Outputs must not alias inputs of other
  * batch entries.
  */

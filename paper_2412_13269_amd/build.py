@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpfx.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["kernels.hip", "keyswitch.hip", "rescale.hip", "linear.hip", "noalloc.hip", "api.cpp", "params.cpp", "encoder.cpp", "server.cpp", "sampler.cpp"]
+SOURCES = ["kernels.hip", "keyswitch.hip", "rescale.hip", "linear.hip", "noalloc.hip", "persist.hip", "api.cpp", "params.cpp", "encoder.cpp", "server.cpp", "sampler.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -918,6 +918,7 @@ void pfx_ctx_destroy(pfx_ctx *c) {
         dfree(kv.second->buf);
         dfree(kv.second->bbuf);
         dfree(kv.second->rbuf);
+        dfree(kv.second->pbuf);
         delete kv.second;
     }
     for (auto &e : c->prof_pending) {
@@ -2959,11 +2960,77 @@ static pfx_status batch_ops(pfx_ctx *const *ctxs, const pfx_ct *const *a, const 
     return res;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Modes 5 and 6: entries whose output aliases an operand of any entry run first
+// on the per-ciphertext path (the batch launches read every operand while they
+// write every output); the rest in one persistent launch (5) or one launch per
+// step (6), with the scratch of all of them in the stream's persistent region
+// (grown on demand).
+pfx_status batch_persistent(pfx_ctx *const *ctxs, const pfx_ct *const *a, const pfx_ct *const *b,
+                            const pfx_swk *const *rlk, pfx_ct *const *out, size_t n, void *stream, bool step_major) {
+    std::unordered_set<const double *> operands;
+    for (size_t i = 0; i < n; ++i) {
+        REQUIRE(persist_shape_ok(ctxs[i]), PFX_EINVAL,
+                "persistent mode needs 2^12 <= N <= 2^16, digits of at most 4 primes and at most 4 special primes");
+        REQUIRE(rlk[i]->galois == 0 && !rlk[i]->from_secret, PFX_ENOKEY, "key is not a relinearisation key");
+        REQUIRE(a[i]->degree == 1 && b[i]->degree == 1, PFX_EINVAL, "batch entries must be degree-1 ciphertexts");
+        REQUIRE(out[i]->cap_limbs >= std::min(a[i]->n_limbs, b[i]->n_limbs) && out[i]->cap_degree >= 1, PFX_EINVAL,
+                "output capacity too small");
+        operands.insert(a[i]->d);
+        operands.insert(b[i]->d);
+    }
+    std::vector<size_t> alone, rest;
+    std::unordered_set<const double *> outs;
+    for (size_t i = 0; i < n; ++i) {
+        REQUIRE(outs.insert(out[i]->d).second, PFX_EINVAL, "two entries write one output");
+        (operands.count(out[i]->d) ? alone : rest).push_back(i);
+    }
+    for (size_t i : alone) {
+        pfx_status r = pfx_mul_relin(ctxs[i], a[i], b[i], rlk[i], out[i], stream);
+        if (!r) r = pfx_rescale(ctxs[i], out[i], out[i], stream);
+        if (r) return r;
+    }
+    if (rest.empty()) return PFX_OK;
+    size_t need = 0;
+    for (size_t i : rest) need += persist_entry_doubles(ctxs[i], (int)std::min(a[i]->n_limbs, b[i]->n_limbs));
+    need += (persist_tail_bytes(rest.size()) + sizeof(double) - 1) / sizeof(double);
+    pfx_ctx *c0 = ctxs[rest[0]];
+    Ws w;
+    pfx_status r = get_ws(c0, S(stream), w);
+    if (r) return r;
+    double *region = nullptr;
+    size_t cap = 0;
+    {
+        std::lock_guard<std::mutex> g(c0->mu);
+        Workspace *ws = c0->ws[S(stream)];
+        if (ws->pcap < need) {
+            REQUIRE(!c0->capturing, PFX_EINVAL, "the persistent region must be reserved before graph capture");
+            (void)hipStreamSynchronize(S(stream));
+            bump_scratch_epoch();
+            dfree(ws->pbuf);
+            ws->pbuf = nullptr;
+            ws->pcap = 0;
+            PFX_DMALLOC(c0, &ws->pbuf, need * sizeof(double));
+            ws->pcap = need;
+        }
+        region = ws->pbuf;
+        cap = ws->pcap;
+    }
+    return launch_batch_persistent(ctxs, a, b, rlk, out, rest, region, cap, S(stream), step_major);
+}
+
+}  // namespace
+
+extern "C" {
+
 pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const *a, const pfx_ct *const *b,
                                        const pfx_swk *const *rlk, pfx_ct *const *out, size_t n, int mode,
                                        void *stream) {
     REQUIRE(ctxs && a && b && rlk && out, PFX_EINVAL, "null argument");
-    REQUIRE(mode >= 0 && mode <= 4, PFX_EINVAL, "mode must be 0 to 4");
+    REQUIRE(mode >= 0 && mode <= 6, PFX_EINVAL, "mode must be 0 to 6");
     if (n == 0) return PFX_OK;
     for (size_t i = 0; i < n; ++i) {
         pfx_ctx *c = ctxs[i];
@@ -2975,6 +3042,7 @@ pfx_status pfx_batch_mul_relin_rescale(pfx_ctx *const *ctxs, const pfx_ct *const
     }
     const bool group = mode >= 3;
     if (mode == 0) return batch_ops(ctxs, a, b, rlk, out, n, false, false, stream);
+    if (mode >= 5) return batch_persistent(ctxs, a, b, rlk, out, n, stream, mode == 6);
     pfx_ctx *c0 = ctxs[0];
     pfx_status r = ensure_lanes(c0);
     if (r) return r;
@@ -3130,6 +3198,7 @@ pfx_status pfx_stream_destroy(pfx_ctx *c, void *stream) {
             dfree(it->second->buf);
             dfree(it->second->bbuf);
             dfree(it->second->rbuf);
+            dfree(it->second->pbuf);
             delete it->second;
             c->ws.erase(it);
         }

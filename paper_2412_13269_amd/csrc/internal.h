@@ -74,6 +74,8 @@ struct Workspace {
     int bcap = 0;
     double *rbuf = nullptr;   // ring-repacking arrays (rcap doubles), on demand
     size_t rcap = 0;
+    double *pbuf = nullptr;   // persistent batched form: every entry's scratch (pcap doubles), on demand
+    size_t pcap = 0;
 };
 
 // The device memory of a context: its allocator (the caller's, or hipMalloc
@@ -361,6 +363,17 @@ struct RsEntry {
     size_t si = 0, so = 0;
 };
 void launch_rescale(const Launch &L, const RsEntry *ents, int nb, int np, int lv, double *last, double *tmp);
+// Batched HMult + relin + rescale in one persistent cooperative launch, or
+// step-major (one launch per step over every entry), (persist.hip) for the
+// entries idx of the batch arrays; every entry's scratch
+// sits in `region` (persist_entry_doubles per entry, plus the descriptors and barrier words:
+// persist_tail_bytes).  Returns after the launch has finished.
+bool persist_shape_ok(const pfx_ctx *c);
+size_t persist_entry_doubles(const pfx_ctx *c, int lv);
+size_t persist_tail_bytes(size_t n);
+pfx_status launch_batch_persistent(pfx_ctx *const *ctxs, const pfx_ct *const *a, const pfx_ct *const *b,
+                                   const pfx_swk *const *rlk, pfx_ct *const *out, const std::vector<size_t> &idx,
+                                   double *region, size_t region_doubles, hipStream_t st, bool step_major);
 // Fused key-switching steps (keyswitch.hip).
 void launch_intt_scale(const Launch &L, const KsBatch &kb, int lv);
 void launch_modup_col(const Launch &L, const KsBatch &kb, int lv);

@@ -17,43 +17,16 @@
 // combination, goes through HBM.
 #include "internal.h"
 #include "ntt_core.h"
+#include "rs_steps.h"
 
 namespace pfx {
-
-// A launch covers nb ciphertexts of one level and degree: polynomial index
-// k = entry * np + p runs over all of them; `last` and `tmp` hold every
-// polynomial's scratch back to back.
-struct RsArgs {
-    const PrimeDev *primes;
-    const RescaleConst *rc;
-    int logn, lv, np;
-    int C, tiles, n;
-    RsEntry e[kMaxBatch];
-};
-
-__device__ __forceinline__ const double *rs_in(const RsArgs &a, int k) {
-    const int b = k / a.np;
-    return a.e[b].in + (size_t)(k - b * a.np) * a.e[b].si;
-}
-
-__device__ __forceinline__ double *rs_out(const RsArgs &a, int k) {
-    const int b = k / a.np;
-    return a.e[b].out + (size_t)(k - b * a.np) * a.e[b].so;
-}
 
 template <int S, int TH>
 __global__ __launch_bounds__(TH) void k_rs_intt_row(const RsArgs a, double *__restrict__ last) {
     __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
-    const int k = id / a.tiles, tile = id - k * a.tiles;
-    const PrimeDev &P = a.primes[a.lv - 1];
-    const size_t N = (size_t)1 << a.logn;
-    const double *src = rs_in(a, k) + (size_t)(a.lv - 1) * N;
-    double *dst = last + (size_t)k * N;
-    auto ld = [&](int g, int) { return src[(unsigned)g]; };
-    auto st = [&](int g, double v, int) { dst[(unsigned)g] = v; };
-    row_pass<S, true, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+    rs_intt_row_body<S, TH>(a, a.C, a.tiles, id, last, lds);
 }
 
 template <int S, int TH>
@@ -61,66 +34,24 @@ __global__ __launch_bounds__(TH) void k_rs_intt_col(const RsArgs a, double *__re
     __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
-    const int k = id / a.tiles, tile = id - k * a.tiles;
-    const PrimeDev &P = a.primes[a.lv - 1];
-    const double h = __builtin_floor(P.q * 0.5);
-    double *x = last + ((size_t)k << a.logn);
-    auto ld = [&](int g, int) { return x[(unsigned)g]; };
-    auto st = [&](int g, double v, int) { x[(unsigned)g] = madd(v, h, P.q); };
-    col_pass<S, true, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+    rs_intt_col_body<S, TH>(a, a.C, a.tiles, id, last, lds);
 }
 
-// blocks: (poly k, tile, prime i), i fastest so that the blocks reading one
-// tile of `last` run together
 template <int S, int TH>
 __global__ __launch_bounds__(TH) void k_rs_col(const RsArgs a, double *__restrict__ tmp,
                                                const double *__restrict__ last) {
     __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
-    const int nout = a.lv - 1;
-    const int i = id % nout, rest = id / nout;
-    const int tile = rest % a.tiles, k = rest / a.tiles;
-    const PrimeDev &P = a.primes[i];
-    const double half = a.rc[(a.lv - 1) * PFX_MAX_PRIMES + i].half;
-    const size_t N = (size_t)1 << a.logn;
-    const double *src = last + (size_t)k * N;
-    double *dst = tmp + ((size_t)k * nout + i) * N;
-    // x < q_l < 2^50: mred takes it to [0, q_i); the difference stays in [0, q_i)
-    auto ld = [&](int g, int) { return msub(mred(src[(unsigned)g], P.q, P.qinv), half, P.q); };
-    auto st = [&](int g, double v, int) { dst[(unsigned)g] = v; };
-    col_pass<S, false, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+    rs_col_body<S, TH>(a, a.C, a.tiles, id, tmp, last, lds);
 }
 
-// blocks: (poly k, prime i, tile), tile fastest (one twiddle table per run of blocks)
 template <int S, int TH>
 __global__ __launch_bounds__(TH) void k_rs_row(const RsArgs a, const double *__restrict__ tmp) {
     __shared__ double lds[NttTile<TH>::lds];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
-    const int nout = a.lv - 1;
-    const int tile = id % a.tiles, rest = id / a.tiles;
-    const int i = rest % nout, k = rest / nout;
-    const PrimeDev &P = a.primes[i];
-    const double2 inv = a.rc[(a.lv - 1) * PFX_MAX_PRIMES + i].inv;
-    const size_t N = (size_t)1 << a.logn;
-    const double *src = tmp + ((size_t)k * nout + i) * N;
-    const double *c = rs_in(a, k) + (size_t)i * N;
-    double *o = rs_out(a, k) + (size_t)i * N;
-    // c is loaded before the transform (its latency hides under it); slot k of
-    // this thread is element tid + k * TH of the tile, the row pass's output
-    // order.  out may alias in: each element is read and then written by the
-    // same thread.
-    const int g0 = (tile * a.C) << S, tot = a.C << S;
-    double xc[kSlots];
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) {
-        const int e = threadIdx.x + k * TH;
-        xc[k] = e < tot ? c[(unsigned)(g0 + e)] : 0.0;
-    }
-    auto ld = [&](int g, int) { return src[(unsigned)g]; };
-    auto st = [&](int g, double v, int k) { o[(unsigned)g] = mmulc(msub(xc[k], v, P.q), inv.x, inv.y, P.q); };
-    row_pass<S, false, TH>(P, a.logn, a.C, tile * a.C, lds, ld, st);
+    rs_row_body<S, TH>(a, a.C, a.tiles, id, tmp, lds);
 }
 
 #define HIP_LAUNCH_CHECK_RS()                                                                    \

@@ -1,7 +1,7 @@
 """Batched HMult + relin + rescale over ciphertexts of uneven ring degree and
 level: every mode (per-ciphertext launches, concurrent lanes, batched key
-switches grouped by shape, HIP-graph replay) gives the same words, and
-sampled entries match the oracle."""
+switches grouped by shape, HIP-graph replay, one persistent launch, one launch per
+step) gives the same words, and sampled entries match the oracle."""
 import numpy as np
 import pytest
 
@@ -64,7 +64,7 @@ def _modes_agree_and_match_oracle(X, lognums, shapes, in_place, oracle_levels):
         X.pfx_batch_mul_relin_rescale(*args, 0, stream)
         X.pfx_sync(c0, stream)
         ref = [X.pfx_ct_export(ctxs[e[0]], e[4], 1 << e[0]) for e in entries]
-        for mode in (1, 2, 3, 4, 2, 4, 3, 1, 4):
+        for mode in (1, 2, 3, 4, 5, 6, 2, 4, 3, 1, 4, 6, 5):
             reset()
             X.pfx_batch_mul_relin_rescale(*args, mode, stream)
             X.pfx_sync(c0, stream)
