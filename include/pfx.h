@@ -133,6 +133,31 @@ pfx_status pfx_ctx_set_allocator(pfx_ctx *ctx, pfx_alloc_fn alloc, pfx_free_fn f
                                  size_t hbm_budget);
 /* Bytes of device memory the context holds now and at most so far. */
 pfx_status pfx_ctx_mem(const pfx_ctx *ctx, size_t *in_use, size_t *peak);
+
+/*
+ * Launch geometry of the NTT passes per ring degree (process-wide; every
+ * context of that degree uses it, graphs captured earlier keep theirs):
+ *   row_wg256 / col_wg256: a row / column pass takes 256-thread workgroups
+ *     when that gives at least this many of them, 128 otherwise;
+ *   widen_wg: launches over few limbs (standalone passes, the special-prime
+ *     INTT of key switching) narrow their tiles until they have this many
+ *     workgroups, down to min_col columns (min_col_special for the
+ *     special-prime INTT; powers of two);
+ *   rs_widen_wg: the same for the INTT of a rescale's dropped limb.
+ * Defaults {2048, 0, 1024, 16, 8, 256}.  The geometry never changes a result,
+ * only its speed.  pfx_tuning_load reads lines "log_n row_wg256 col_wg256
+ * widen_wg min_col min_col_special rs_widen_wg" ('#' starts a comment line);
+ * the first pfx_ctx_create loads tuning.txt next to libpfx.so if there is one
+ * (the package's autotuner writes it).
+ */
+typedef struct pfx_pass_tuning {
+    uint32_t log_n;
+    uint32_t row_wg256, col_wg256, widen_wg, min_col, min_col_special, rs_widen_wg;
+} pfx_pass_tuning;
+pfx_status pfx_tuning_set(const pfx_pass_tuning *t);
+pfx_status pfx_tuning_get(uint32_t log_n, pfx_pass_tuning *t);
+pfx_status pfx_tuning_reset(void);
+pfx_status pfx_tuning_load(const char *path);
 pfx_status pfx_ctx_moduli(const pfx_ctx *ctx, uint64_t *q, uint64_t *p, uint64_t *psi);
 /* Blocks until all work the library enqueued on `stream` has finished. */
 pfx_status pfx_sync(pfx_ctx *ctx, void *stream);

@@ -1,5 +1,6 @@
 // C-ABI of libpfx: argument checks, host-side constants, and the sequence of
 // device launches behind each call.  The kernels are in kernels.hip.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,6 +52,28 @@ GraphCache<GraphExec> &graphs() {
         (void)hipSetDevice(prev);
     });
     return *g;
+}
+
+// ---- pass geometry per ring degree (PassTuning), process-wide
+namespace {
+std::mutex g_tune_mu;
+PassTuning g_tune[32];
+
+// Loads the tuning file next to libpfx.so (written by the package's
+// autotuner); a missing file leaves the defaults.
+void tune_autoload() {
+    Dl_info info;
+    if (!dladdr(reinterpret_cast<void *>(&tune_autoload), &info) || !info.dli_fname) return;
+    std::string path(info.dli_fname);
+    const size_t slash = path.rfind('/');
+    path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/tuning.txt";
+    (void)pfx_tuning_load(path.c_str());
+}
+}  // namespace
+
+const PassTuning &pass_tuning(int logn) {
+    if (logn < 0 || logn >= 32) logn = 0;
+    return g_tune[logn];
 }
 
 void graph_forget(uint64_t uid) {
@@ -735,6 +758,8 @@ pfx_status pfx_ctx_create(const pfx_params *prm, int device, pfx_ctx **out) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(PFX_EDEVICE, std::string("libpfx is built for gfx950, device is ") + prop.gcnArchName);
 
+    static std::once_flag tune_once;
+    std::call_once(tune_once, tune_autoload);   // the autotuner's table, if one sits next to the library
     pfx_status nr = noalloc_init(device);   // once per device, this device current
     if (nr) return nr;
     std::unique_ptr<pfx_ctx> c(new pfx_ctx);
@@ -935,6 +960,62 @@ void pfx_ctx_destroy(pfx_ctx *c) {
     dfree(c->d_moddown);
     dfree(c->d_rescale);
     delete c;   // objects not yet destroyed keep their memory until they are
+}
+
+pfx_status pfx_tuning_set(const pfx_pass_tuning *t) {
+    REQUIRE(t, PFX_EINVAL, "null argument");
+    REQUIRE(t->log_n >= 2 && t->log_n <= 16, PFX_EINVAL, "log_n out of range");
+    REQUIRE(t->widen_wg >= 1 && t->rs_widen_wg >= 1, PFX_EINVAL, "widen thresholds must be positive");
+    REQUIRE(t->min_col >= 1 && t->min_col_special >= 1 && !(t->min_col & (t->min_col - 1)) &&
+                !(t->min_col_special & (t->min_col_special - 1)),
+            PFX_EINVAL, "column widths must be powers of two");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    PassTuning &x = g_tune[t->log_n];
+    x.row_wg256 = (int)std::min<uint32_t>(t->row_wg256, 1u << 30);
+    x.col_wg256 = (int)std::min<uint32_t>(t->col_wg256, 1u << 30);
+    x.widen_wg = (int)std::min<uint32_t>(t->widen_wg, 1u << 30);
+    x.min_col = (int)t->min_col;
+    x.min_col_special = (int)t->min_col_special;
+    x.rs_widen_wg = (int)std::min<uint32_t>(t->rs_widen_wg, 1u << 30);
+    return PFX_OK;
+}
+
+pfx_status pfx_tuning_get(uint32_t log_n, pfx_pass_tuning *t) {
+    REQUIRE(t && log_n < 32, PFX_EINVAL, "bad argument");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const PassTuning &x = g_tune[log_n];
+    *t = pfx_pass_tuning{log_n, (uint32_t)x.row_wg256, (uint32_t)x.col_wg256, (uint32_t)x.widen_wg,
+                         (uint32_t)x.min_col, (uint32_t)x.min_col_special, (uint32_t)x.rs_widen_wg};
+    return PFX_OK;
+}
+
+pfx_status pfx_tuning_reset(void) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (PassTuning &x : g_tune) x = PassTuning{};
+    return PFX_OK;
+}
+
+pfx_status pfx_tuning_load(const char *path) {
+    REQUIRE(path, PFX_EINVAL, "null path");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(PFX_EINVAL, std::string("cannot open ") + path);
+    char line[512];
+    int n = 0;
+    pfx_status r = PFX_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        pfx_pass_tuning t;
+        if (std::sscanf(line, "%u %u %u %u %u %u %u", &t.log_n, &t.row_wg256, &t.col_wg256, &t.widen_wg,
+                        &t.min_col, &t.min_col_special, &t.rs_widen_wg) != 7) {
+            r = fail(PFX_EINVAL, std::string("malformed tuning line in ") + path);
+            break;
+        }
+        r = pfx_tuning_set(&t);
+        if (r) break;
+        ++n;
+    }
+    std::fclose(f);
+    return r;
 }
 
 pfx_status pfx_ctx_set_allocator(pfx_ctx *c, pfx_alloc_fn alloc, pfx_free_fn free_fn, void *user,

@@ -88,6 +88,22 @@ struct MemAccount {
     size_t budget = 0, in_use = 0, peak = 0;
 };
 
+// Launch geometry of the transform passes per ring degree (process-wide; set
+// by pfx_tuning_set / pfx_tuning_load, chosen by the package's autotuner):
+//   row_wg256 / col_wg256: a row / column pass over `limbs` limbs takes 256
+//     threads when that gives at least this many workgroups, 128 otherwise;
+//   widen_wg: small launches (standalone passes, the special-prime INTT)
+//     narrow their tiles until they have this many workgroups, down to
+//     min_col columns (min_col_special for the special-prime INTT);
+//   rs_widen_wg: the same for the INTT of the rescale's last limbs.
+// Defaults: rows 128 threads below 2048 workgroups (eight per CU), columns
+// always 256 (16-column tiles read whole 128-byte rows), widen to 1024
+// workgroups (16 / 8 columns), the rescale's INTT to 256.
+struct PassTuning {
+    int row_wg256 = 2048, col_wg256 = 0, widen_wg = 1024, min_col = 16, min_col_special = 8, rs_widen_wg = 256;
+};
+const PassTuning &pass_tuning(int logn);   // api.cpp
+
 struct ProfEntry {
     hipEvent_t start, stop;
     std::string name;

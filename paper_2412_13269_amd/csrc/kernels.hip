@@ -96,8 +96,9 @@ void launch_ntt_pass(const Launch &L, double *base, const double *src, const Lim
     // very small batches: narrower row tiles (idle threads) so that the launch
     // still covers the CUs; column tiles stay >= 16 columns (128-byte rows:
     // 8-column tiles measured 17.0 us against 11.0 us for a 48-limb pass)
-    const int minC = row ? 1 : 16;
-    while (nb * map.n * ps.tiles < 1024 && ps.C / 2 >= minC) {
+    const PassTuning &tu = pass_tuning(logn);
+    const int minC = row ? 1 : tu.min_col;
+    while (nb * map.n * ps.tiles < tu.widen_wg && ps.C / 2 >= minC) {
         ps.C /= 2;
         ps.tiles *= 2;
     }

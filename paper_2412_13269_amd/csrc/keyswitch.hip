@@ -272,12 +272,13 @@ static void set_blocks(KsArgs &a, int per) {
 }
 
 // Narrower tiles (idle threads) until a launch over `limbs` limbs has at least
-// 1024 workgroups: the transforms of the special-prime limbs (2K of them) are
-// too small to fill the chip even with 128-thread groups.  Column tiles keep
-// 8 columns (64-byte rows).
-static void widen_grid(PassShape &pr, PassShape &pc, int limbs) {
-    while (limbs * pr.tiles < 1024 && pr.C > 1) { pr.C /= 2; pr.tiles *= 2; }
-    while (limbs * pc.tiles < 1024 && pc.C / 2 >= 8) { pc.C /= 2; pc.tiles *= 2; }
+// widen_wg workgroups (1024 by default): the transforms of the special-prime
+// limbs (2K of them) are too small to fill the chip even with 128-thread
+// groups.  Column tiles keep min_col_special columns (8: 64-byte rows).
+static void widen_grid(PassShape &pr, PassShape &pc, int limbs, int logn) {
+    const PassTuning &tu = pass_tuning(logn);
+    while (limbs * pr.tiles < tu.widen_wg && pr.C > 1) { pr.C /= 2; pr.tiles *= 2; }
+    while (limbs * pc.tiles < tu.widen_wg && pc.C / 2 >= tu.min_col_special) { pc.C /= 2; pc.tiles *= 2; }
 }
 
 void launch_intt_scale(const Launch &L, const KsBatch &kb, int lv) {
@@ -329,7 +330,7 @@ void launch_intt_special(const Launch &L, const KsBatch &kb, int lv) {
     const int th = pass_threads(a.logn, limbs, true);
     constexpr int tc = 256;
     PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
-    widen_grid(pr, pc, limbs);
+    widen_grid(pr, pc, limbs, a.logn);
     hipEvent_t ev;
     a.C = pr.C;
     a.tiles = pr.tiles;

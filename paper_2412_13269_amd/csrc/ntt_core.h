@@ -446,11 +446,11 @@ inline PassShape row_shape(int logn, int tile = kNttTile) {
     return p;
 }
 
-// Workgroup size of a pass launch over `limbs` limbs: a row pass takes 128
-// threads when 256 would make fewer than 2048 workgroups (eight per CU); a
-// column pass keeps 256, whose 16-column tiles read whole 128-byte rows.
+// Workgroup size of a pass launch over `limbs` limbs (PassTuning).
+
 inline int pass_threads(int logn, int limbs, bool row) {
-    return (!row || limbs * col_shape(logn).tiles >= 2048) ? 256 : 128;
+    const PassTuning &t = pass_tuning(logn);
+    return limbs * col_shape(logn).tiles >= (row ? t.row_wg256 : t.col_wg256) ? 256 : 128;
 }
 
 // Stages of a pass (log N / 2 or the rest) as a compile-time constant SS.

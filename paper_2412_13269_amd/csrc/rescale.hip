@@ -76,8 +76,9 @@ void launch_rescale(const Launch &L, const RsEntry *ents, int nb, int np, int lv
     {
         const int th = pass_threads(a.logn, polys, true), tc = pass_threads(a.logn, polys, false);
         PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
-        while (polys * pr.tiles < 256 && pr.C > 1) { pr.C /= 2; pr.tiles *= 2; }
-        while (polys * pc.tiles < 256 && pc.C / 2 >= 8) { pc.C /= 2; pc.tiles *= 2; }
+        const PassTuning &tu = pass_tuning(a.logn);
+        while (polys * pr.tiles < tu.rs_widen_wg && pr.C > 1) { pr.C /= 2; pr.tiles *= 2; }
+        while (polys * pc.tiles < tu.rs_widen_wg && pc.C / 2 >= tu.min_col_special) { pc.C /= 2; pc.tiles *= 2; }
         a.C = pr.C;
         a.tiles = pr.tiles;
         a.n = polys * pr.tiles;

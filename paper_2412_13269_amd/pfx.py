@@ -38,6 +38,12 @@ class pfx_params(ctypes.Structure):
                 ("mod_log2", ctypes.c_uint32)]
 
 
+class pfx_pass_tuning(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("row_wg256", ctypes.c_uint32), ("col_wg256", ctypes.c_uint32),
+                ("widen_wg", ctypes.c_uint32), ("min_col", ctypes.c_uint32), ("min_col_special", ctypes.c_uint32),
+                ("rs_widen_wg", ctypes.c_uint32)]
+
+
 class pfx_op(ctypes.Structure):
     _fields_ = [("code", ctypes.c_int32), ("dst", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
                 ("k", ctypes.c_int64), ("value", ctypes.c_double)]
@@ -165,6 +171,10 @@ _SIGS = {
     "pfx_batch_mul_relin_rescale": (_i32, [_VPP, _VPP, _VPP, _VPP, _VPP, _sz, ctypes.c_int, _vp]),
     "pfx_ctx_set_allocator": (_i32, [_vp, _vp, _vp, _vp, _sz]),
     "pfx_ctx_mem": (_i32, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "pfx_tuning_set": (_i32, [ctypes.POINTER(pfx_pass_tuning)]),
+    "pfx_tuning_get": (_i32, [_u32, ctypes.POINTER(pfx_pass_tuning)]),
+    "pfx_tuning_reset": (_i32, []),
+    "pfx_tuning_load": (_i32, [ctypes.c_char_p]),
     "pfx_graph_cache_stats": (_i32, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_uint64)]),
     "pfx_server_create": (_i32, [_vp, _sz, _u32, _u32, _vp, _VPP, _sz, _VPP]),
     "pfx_server_submit": (_i32, [_vp, ctypes.POINTER(pfx_request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -702,6 +712,31 @@ def pfx_ctx_mem(ctx):
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
     _check(_lib.pfx_ctx_mem(ctx, ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+TUNING_FIELDS = ("row_wg256", "col_wg256", "widen_wg", "min_col", "min_col_special", "rs_widen_wg")
+
+
+def pfx_tuning_set(log_n: int, **fields):
+    """Pass geometry for ring degree 2^log_n; fields not given keep their value."""
+    t = pfx_tuning_get(log_n)
+    for k, v in fields.items():
+        setattr(t, k, int(v))
+    _check(_lib.pfx_tuning_set(ctypes.byref(t)))
+
+
+def pfx_tuning_get(log_n: int) -> pfx_pass_tuning:
+    t = pfx_pass_tuning()
+    _check(_lib.pfx_tuning_get(log_n, ctypes.byref(t)))
+    return t
+
+
+def pfx_tuning_reset():
+    _check(_lib.pfx_tuning_reset())
+
+
+def pfx_tuning_load(path: str):
+    _check(_lib.pfx_tuning_load(path.encode()))
 
 
 def pfx_graph_cache_stats():

@@ -77,3 +77,28 @@ def test_decoder_centres_negative_values():
     z = -0.75 * np.ones(512)
     w = O.encode(P, z, 2.0 ** 80, 2)       # a value beyond one prime: needs the full CRT
     assert np.allclose(X.pfx_decode_words(prm, w, 2.0 ** 80, 512).real, z, atol=1e-9)
+
+
+def test_pass_tuning_table(tmp_path):
+    """The pass-geometry table (host side): defaults, set/get, the file
+    format the autotuner writes, and rejected values."""
+    X.pfx_tuning_reset()
+    t = X.pfx_tuning_get(16)
+    assert [getattr(t, f) for f in X.TUNING_FIELDS] == [2048, 0, 1024, 16, 8, 256]
+    X.pfx_tuning_set(15, row_wg256=4096, min_col=32)
+    t = X.pfx_tuning_get(15)
+    assert (t.row_wg256, t.min_col, t.widen_wg) == (4096, 32, 1024)
+    assert X.pfx_tuning_get(16).row_wg256 == 2048
+    f = tmp_path / "tuning.txt"
+    f.write_text("# comment\n14 0 0 512 8 4 128\n\n16 8192 4096 2048 16 8 512\n")
+    X.pfx_tuning_load(str(f))
+    assert [getattr(X.pfx_tuning_get(14), k) for k in X.TUNING_FIELDS] == [0, 0, 512, 8, 4, 128]
+    assert [getattr(X.pfx_tuning_get(16), k) for k in X.TUNING_FIELDS] == [8192, 4096, 2048, 16, 8, 512]
+    for bad in ({"min_col": 12}, {"widen_wg": 0}):
+        with pytest.raises(X.PfxError):
+            X.pfx_tuning_set(16, **bad)
+    f.write_text("16 1 2 3\n")
+    with pytest.raises(X.PfxError):
+        X.pfx_tuning_load(str(f))
+    X.pfx_tuning_reset()
+    assert X.pfx_tuning_get(14).widen_wg == 1024
