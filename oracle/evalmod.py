@@ -40,21 +40,12 @@ import math
 import numpy as np
 
 from oracle import ckks as O
-from oracle.query import _mr, add_const, mul_const_next
+from oracle.query import _mr, add_const, mul_const_next, mul_const_to
 
 
 def cheb_index_pair(k: int):
     """T_k = 2 T_a T_b - T_(a-b) with a = ceil(k/2), b = floor(k/2)."""
     return (k + 1) // 2, k // 2
-
-
-def mul_const_to(P, x: O.Ct, value: float, target_scale: float) -> O.Ct:
-    """x times `value` encoded at the scale c = target q / s_x (q the prime the
-    next rescale drops): the rescaled product has scale `target_scale`."""
-    q = P.q[x.level - 1]
-    cs = target_scale * q / x.scale
-    k = int(O.round_half_away(np.array([value * cs]))[0])
-    return O.Ct(O.ct_mul_int(P, x, k).c, x.scale * cs)
 
 
 def evalmod(P, x: O.Ct, coeffs, r: int, K: float, rlk, out_factor: float = 1.0) -> O.Ct:

@@ -38,6 +38,13 @@ P(y) = sum_{i<=7} 4^(7-i) C(2i, i) (1 - y)^i / 4^7 * 2048 (f15(+-1) = +-1, its
 first seven derivatives 0 at +-1), evaluated like f7: y = x^2, the powers of y
 by the tree above, the integer combination, x / 2048 at the next prime's
 scale, one product.
+
+The paper's thresholds themselves (Tab. 2) are composite minimax
+approximations whose coefficients it does not print; oracle/remez.py designs
+them (stage by stage, Remez), and with `sign_coeffs` the query takes those
+stages instead (minimax_stage: odd powers by ODD_TREE, each term's constant
+at the scale that lands on the sum's).  global_threshold is the second,
+global threshold on the count.
 """
 from __future__ import annotations
 
@@ -61,12 +68,14 @@ def f7(x):
     return f_sign(x, 7)
 
 
-def fp64_query(x, w, c, t, eta, stages=3, sign_degree=7):
+def fp64_query(x, w, c, t, eta, stages=3, sign_degree=7, sign_coeffs=None):
     """The circuit in plain FP64 on the records x (records, attributes)."""
     s = x @ w
     z = sum(c[k] * s ** k for k in range(len(c)))
     u = (z - t) * eta
-    for _ in range(stages):
+    if sign_coeffs is not None:
+        u = fp64_minimax(u, sign_coeffs)
+    for _ in range(stages if sign_coeffs is None else 0):
         u = f_sign(u, sign_degree)
     step = (u + 1.0) / 2.0
     return step, float(step.sum())
@@ -133,11 +142,69 @@ def sign_stage(P, x: O.Ct, rlk, degree=7) -> O.Ct:
     return _mr(P, xs, p, rlk)
 
 
+def mul_const_to(P, x: O.Ct, value: float, target_scale: float) -> O.Ct:
+    """x times `value` encoded at the scale c = target q / s_x (q the prime the
+    next rescale drops): the rescaled product has scale `target_scale`."""
+    q = P.q[x.level - 1]
+    cs = target_scale * q / x.scale
+    k = int(O.round_half_away(np.array([value * cs]))[0])
+    return O.Ct(O.ct_mul_int(P, x, k).c, x.scale * cs)
+
+
+# odd powers of a minimax stage and the two lower powers each is the product of
+ODD_TREE = {2: (1, 1), 3: (2, 1), 4: (2, 2), 5: (4, 1), 7: (4, 3), 8: (4, 4), 9: (8, 1), 11: (8, 3),
+            13: (8, 5), 15: (8, 7)}
+
+
+def minimax_stage(P, x: O.Ct, coeffs, rlk) -> O.Ct:
+    """One stage p(x) = sum_k coeffs[k] x^(2k+1) of a composite minimax sign
+    approximation (Tab. 2 thresholds; the coefficients an input, designed by
+    oracle/remez.py): the odd powers x^3 .. x^d and their helpers x^2, x^4,
+    x^8 by ODD_TREE (each relinearised and rescaled, depth 4 for d = 15); the
+    highest term c_d x^d with the constant at the next prime's scale, every
+    other term c_k x^k with its constant at the scale that brings it to the
+    sum's scale after its rescale (mul_const_to), added from k = d - 2 down."""
+    d = 2 * len(coeffs) - 1
+    Xp = {1: x}
+    for k in sorted(ODD_TREE):
+        if (k <= d) if k % 2 else (k + 1 <= d):       # an even power only as a factor
+            a, b = ODD_TREE[k]
+            Xp[k] = _mr(P, Xp[a], Xp[b], rlk)
+    acc = O.rescale(P, mul_const_next(P, Xp[d], float(coeffs[-1])))
+    for k in range(d - 2, 0, -2):
+        term = O.rescale(P, mul_const_to(P, Xp[k], float(coeffs[(k - 1) // 2]), acc.scale))
+        acc = O.ct_add(P, acc, term)
+    return acc
+
+
+def fp64_minimax(u, sign_coeffs):
+    for c in sign_coeffs:
+        u = u * np.polynomial.polynomial.polyval(u * u, np.asarray(c, dtype=np.float64))
+    return u
+
+
+def global_threshold(P, count: O.Ct, T1: O.Ct, inv_p: float, sign_coeffs, rlk) -> O.Ct:
+    """The global threshold on the count (Sec. 5.3, Threshold2 of Tab. 2):
+    step((count - t1) p^-1) with t1 encrypted and p public: the difference,
+    times p^-1 at the next prime's scale and rescaled, the minimax stages,
+    then (u + 1) with the scale doubled."""
+    u = O.ct_sub(P, count, T1)
+    u = O.rescale(P, mul_const_next(P, u, inv_p))
+    for c in sign_coeffs:
+        u = minimax_stage(P, u, c, rlk)
+    s = add_const(P, u, 1.0)
+    return O.Ct(s.c, s.scale * 2.0)
+
+
+def fp64_global_threshold(count, t1, inv_p, sign_coeffs):
+    return (fp64_minimax((np.asarray(count, dtype=np.float64) - t1) * inv_p, sign_coeffs) + 1.0) / 2.0
+
+
 FINAL_LIMBS = 2   # limbs the InnerSum runs on
 
 
 def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None, final_limbs=FINAL_LIMBS,
-                  sign_degree=7):
+                  sign_degree=7, sign_coeffs=None):
     """X[b][a]: plaintext words at scale x_scale; W[a], C[k], T, H: oracle ciphertexts."""
     D = len(C) - 1
     total = None
@@ -152,8 +219,12 @@ def query_circuit(P, X, x_scale, W, C, T, H, rlk, gks, stages=3, log_slots=None,
             z2 = O.ct_add(P, z2, O.tensor(P, C[k], Y[k]))
         z = O.ct_add(P, O.rescale(P, O.relinearize(P, z2, rlk)), C[0])
         u = _mr(P, O.ct_sub(P, z, T), H, rlk)
-        for _ in range(stages):
-            u = sign_stage(P, u, rlk, sign_degree)
+        if sign_coeffs is not None:          # composite minimax stages (their count replaces `stages`)
+            for c in sign_coeffs:
+                u = minimax_stage(P, u, c, rlk)
+        else:
+            for _ in range(stages):
+                u = sign_stage(P, u, rlk, sign_degree)
         step = add_const(P, u, 1.0)
         step = O.Ct(step.c, step.scale * 2.0)
         total = step if total is None else O.ct_add(P, total, step)

@@ -257,3 +257,55 @@ def test_sparse_secret_without_signs_is_caught(monkeypatch):
     orig = SM.ternary_sparse
     monkeypatch.setattr(SM, "ternary_sparse", lambda seed, tag, index, n, h: np.abs(orig(seed, tag, index, n, h)))
     _expect_fail(TS.test_ternary_secrets)
+
+
+# ---- the composite minimax sign design (oracle/remez.py)
+from oracle import remez as RZ
+from tests import test_remez_oracle as TRZ
+
+
+def test_composite_without_normalisation_is_caught(monkeypatch):
+    orig = RZ.remez_sign_stage
+
+    def no_norm(alpha, degree=15, stages=None, beta=None, max_stages=12):
+        tau, cs, es, taus = 2.0 ** -alpha, [], [], []
+        for _ in range(stages):
+            c, e, _ = orig(degree, tau)
+            cs.append(c)                      # image left in [1 - e, 1 + e]: the next stage leaves its domain
+            es.append(e)
+            taus.append(tau)
+            tau = 1.0 - e
+        return cs, es, taus
+    monkeypatch.setattr(RZ, "composite_sign", no_norm)
+    _expect_fail(TRZ.test_stages_stay_in_the_unit_interval)
+
+
+def test_remez_with_one_reference_point_short_is_caught(monkeypatch):
+    def short(degree, tau, iters=80, grid=20000):
+        c, e, ref = RZ.__dict__["_orig_remez"](degree - 2 if degree > 1 else degree, tau, iters, grid)
+        return c, e, ref
+    monkeypatch.setitem(RZ.__dict__, "_orig_remez", RZ.remez_sign_stage)
+    monkeypatch.setattr(RZ, "remez_sign_stage", short)
+    _expect_fail(TRZ.test_equioscillation, 15, 2.0 ** -8)
+
+
+# ---- the minimax threshold stages of the query (oracle/query.py)
+
+
+def test_minimax_stage_with_a_wrong_power_is_caught(monkeypatch):
+    tree = dict(QO.ODD_TREE)
+    tree[7] = (4, 2)                          # x^6 where x^7 belongs
+    monkeypatch.setattr(QO, "ODD_TREE", tree)
+    _expect_fail(TQ.test_minimax_stage_decrypts_to_the_polynomial)
+
+
+def test_minimax_stage_with_terms_at_unmatched_scales_is_caught(monkeypatch):
+    # every term taken at the next prime's scale instead of the sum's
+    monkeypatch.setattr(QO, "mul_const_to", lambda P, x, value, target_scale: QO.mul_const_next(P, x, value))
+    _expect_fail(TQ.test_minimax_stage_decrypts_to_the_polynomial)
+
+
+def test_global_threshold_with_the_difference_reversed_is_caught(monkeypatch):
+    orig = QO.O.ct_sub
+    monkeypatch.setattr(QO.O, "ct_sub", lambda P, a, b: orig(P, b, a))
+    _expect_fail(TQ.test_global_threshold_decides_counts_two_away)

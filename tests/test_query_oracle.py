@@ -143,3 +143,76 @@ def test_query_circuit_with_degree_15_sign_stages():
     got = O.decode(P, O.decrypt(P, s_, out), out.scale, P.N // 2).real
     step, count = Q.fp64_query(x, w, c, t, eta, sign_degree=15)
     assert abs(got[0] - count) < 0.25
+
+
+def _threshold(name):
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sign_minimax.json")))
+    return g[name]["stages"]
+
+
+def test_minimax_stage_decrypts_to_the_polynomial():
+    # one homomorphic stage against the polynomial evaluated in FP64 on the
+    # decrypted input (numpy's polyval, independent of the ciphertext arithmetic)
+    from oracle import remez as R
+    P = O.Params(9, [50] + [45] * 7, [50] * 2, alpha=2, mod_log2=17)
+    n, delta = P.N // 2, 2.0 ** 45
+    s = I.ternary_secret(P.N, 64, 5)
+    z = np.concatenate([np.linspace(-1.0, 1.0, n // 2), I.uniform_slots(n // 2, 6).real])
+    ct = O.encrypt(P, s, O.encode(P, z, delta, P.L), I.uniform_residues(P.q, P.N, 7), I.gaussian_error(P.N, 8), delta)
+    ext = P.ext_mods(P.L)
+    rlk = O.relin_key(P, s, I.uniform_residues(ext, P.N, 9, lead=(P.beta,)), I.gaussian_error((P.beta, P.N), 10))
+    dec = lambda c: O.decode(P, O.decrypt(P, s, c), c.scale, n).real
+    z0 = dec(ct)
+    for c in _threshold("threshold1"):
+        out = Q.minimax_stage(P, ct, c, rlk)
+        assert out.level == ct.level - 5                    # x^2, x^3/x^4, x^5/x^7/x^8, x^9..x^15, c_15 x^15
+        want = R.eval_stage(c, z0)
+        got = dec(out)
+        # each term c_k x^k carries x^k's error (about 2^-38 here) times |c_k|
+        assert np.max(np.abs(got - want)) < 2.0 ** -34 * sum(abs(v) for v in c)
+    # a degree-3 stage against its closed form x (3 - x^2) / 2
+    out = Q.minimax_stage(P, ct, [1.5, -0.5], rlk)
+    assert out.level == ct.level - 3
+    assert np.max(np.abs(dec(out) - z0 * (3 - z0 ** 2) / 2)) < 2.0 ** -34 * 2
+
+
+def test_query_circuit_with_the_first_threshold():
+    # Tab. 2 thresholds: three minimax stages of degree 15 replace the f_d stages
+    sc = _threshold("threshold1")
+    P, s_, x, (w, c, t, eta), X, delta, W, C, T, H, rlk, gks = build(9, 1, 19)
+    out = Q.query_circuit(P, X, delta, W, C, T, H, rlk, gks, final_limbs=P.L, sign_coeffs=sc)
+    assert out.level == P.L - 21                             # 6 + three stages of depth 5
+    got = O.decode(P, O.decrypt(P, s_, out), out.scale, P.N // 2).real
+    step, count = Q.fp64_query(x, w, c, t, eta, sign_coeffs=sc)
+    assert abs(got[0] - count) < 0.25
+    # the thresholds separate: records with |u| >= 2^-8 land within 2^-11 of 0 or 1
+    s = x @ w
+    u = (sum(c[k] * s ** k for k in range(len(c))) - t) * eta
+    far = (np.abs(u) >= 2.0 ** -8) & (np.abs(u) <= 1.0)
+    assert np.all(np.abs(step[far] - (u[far] > 0)) <= 2.0 ** -11)
+
+
+def test_global_threshold_decides_counts_two_away():
+    # Threshold2 (Tab. 2: alpha = 16, beta = 20) on counts up to 2^17 with
+    # p = 2^17: every count at least 2 from t1 (|u| >= 2^-16) is decided
+    # within 2^-20; six stages of depth 5 after the p^-1 product
+    sc = _threshold("threshold2")
+    P = O.Params(9, [50] + [45] * 33, [50] * 4, alpha=4, mod_log2=17)
+    n, delta, t1, inv_p = P.N // 2, 2.0 ** 45, 70000.5, 2.0 ** -17
+    s = I.ternary_secret(P.N, 64, 25)
+    rng = np.random.default_rng(26)
+    counts = np.concatenate([np.arange(69990, 70011), rng.integers(0, 1 << 17, n - 21)]).astype(np.float64)
+    enc = lambda z, sd: O.encrypt(P, s, O.encode(P, z, delta, P.L), I.uniform_residues(P.q, P.N, sd),
+                                  I.gaussian_error(P.N, sd + 1), delta)
+    ext = P.ext_mods(P.L)
+    rlk = O.relin_key(P, s, I.uniform_residues(ext, P.N, 29, lead=(P.beta,)), I.gaussian_error((P.beta, P.N), 30))
+    out = Q.global_threshold(P, enc(counts, 27), enc(np.full(n, t1), 31), inv_p, sc, rlk)
+    assert out.level == P.L - 31
+    got = O.decode(P, O.decrypt(P, s, out), out.scale, n).real
+    far = np.abs(counts - t1) >= 2
+    assert far.sum() >= n - 4
+    assert np.max(np.abs(got - (counts > t1))[far]) <= 2.0 ** -20
+    want = Q.fp64_global_threshold(counts, t1, inv_p, sc)
+    assert np.max(np.abs(got - want)[far]) <= 2.0 ** -22
