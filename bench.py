@@ -48,30 +48,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# sources that define a profiled kernel (their hash ties a committed counter
-# measurement to the code it was taken on)
-_KS_SOURCES = ["kernels.hip", "keyswitch.hip", "modarith.h", "ntt_core.h", "internal.h"]
-_KERNEL_SOURCES = {"ks_inner": ["kernels.hip", "modarith.h", "ntt_core.h", "internal.h"],
-                   "repack_fused": ["keyswitch.hip", "modarith.h", "ntt_core.h", "internal.h"]}
-
-
 def measured_traffic(kernel: str, workload: str = "n16_l24"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (profiles/<kernel>_<workload>_hbm_traffic.md), or None
     when there is none or the kernel's sources have changed since it was taken."""
-    import hashlib
     import re
+    from paper_2412_13269_amd import profsum
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
-    if kernel not in _KERNEL_SOURCES or not os.path.exists(path):
+    if kernel not in profsum.SOURCES or not os.path.exists(path):
         return None
     m = re.search(r"traffic_bytes_per_launch: (\d+) kernel: (\S+) sources_sha256: ([0-9a-f]{64})", open(path).read())
     if not m or m.group(2) != kernel:
         return None
-    h = hashlib.sha256()
-    for f in _KERNEL_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_2412_13269_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return int(m.group(1)) if h.hexdigest() == m.group(3) else None
+    return int(m.group(1)) if profsum.sources_sha256(kernel) == m.group(3) else None
 
 
 # Algorithmic HBM bytes of one operation at N = 2^16, L = 24, K = 4, dnum = 6
@@ -94,19 +83,15 @@ def measured_valu_per_ks(workload: str = "n16_l24"):
     """VALU wave instructions of one rotation's key switch (SQ_INSTS_VALU summed
     over its kernels) from the committed summary profiles/ks_kernels_<workload>_valu_rate.md,
     or None when there is none or the key-switch sources have changed since."""
-    import hashlib
     import re
+    from paper_2412_13269_amd import profsum
     path = os.path.join(ROOT, "profiles", f"ks_kernels_{workload}_valu_rate.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"valu_wave_instructions_per_rotation: ([0-9.e+]+) sources_sha256: ([0-9a-f]{64})", open(path).read())
     if not m:
         return None
-    h = hashlib.sha256()
-    for f in _KS_SOURCES:
-        with open(os.path.join(ROOT, "paper_2412_13269_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return float(m.group(1)) if h.hexdigest() == m.group(2) else None
+    return float(m.group(1)) if profsum.sources_sha256("ks_rotation") == m.group(2) else None
 
 
 def cpu_baseline(q, p):
@@ -656,9 +641,14 @@ def main():
     plan = plans["blocks_on_lanes"]
     # the paper's first-threshold degrees: three composite-sign stages of degree 15
     plan15 = QueryPlan(n_blocks, A, D, 3, LOGN - 1, interleave=True, sign_degree=15)
+    # the paper's first threshold itself (Tab. 2: minimax stages of degree 15,
+    # alpha = 8, beta = 12), coefficients from the stored stage-wise design
+    with open(os.path.join(ROOT, "tests", "golden", "sign_minimax.json")) as f:
+        th1 = json.load(f)["threshold1"]["stages"]
+    plan_mm = QueryPlan(n_blocks, A, D, 3, LOGN - 1, interleave=True, sign_coeffs=th1)
     x = I.synthetic_database(n_blocks * (N // 2), A, 301)
     w, c, t, eta = I.query_parameters(A, D, 302)
-    all_plans = list(plans.values()) + [plan15]
+    all_plans = list(plans.values()) + [plan15, plan_mm]
     regs = [X.pfx_ct_create(ctx, L, max(p.reg_degree[i] if i < p.n_regs else 1 for p in all_plans))
             for i in range(max(p.n_regs for p in all_plans))]
     for i, v in enumerate(list(w) + list(c) + [t, eta]):
@@ -691,13 +681,16 @@ def main():
             query(pl, m)
         X.pfx_sync(ctx, st)
         res[name] = (time.perf_counter() - a0) / reps
-    query(plan15, X.RUN_EAGER)                     # warm
-    X.pfx_sync(ctx, st)
-    a0 = time.perf_counter()
-    for _ in range(reps):
-        query(plan15, X.RUN_EAGER)
-    X.pfx_sync(ctx, st)
-    t15 = (time.perf_counter() - a0) / reps
+    def time_plan(pl):
+        query(pl, X.RUN_EAGER)                     # warm
+        X.pfx_sync(ctx, st)
+        a0 = time.perf_counter()
+        for _ in range(reps):
+            query(pl, X.RUN_EAGER)
+        X.pfx_sync(ctx, st)
+        return (time.perf_counter() - a0) / reps
+    t15 = time_plan(plan15)
+    tmm = time_plan(plan_mm)
     records = n_blocks * (N // 2)
     best = min(res, key=res.get)
     query_out = {"records": records, "attributes": A, "degree": D, "sign_stages": 3,
@@ -706,9 +699,14 @@ def main():
                  "best": best, "ms_best": 1e3 * res[best], "us_per_record": 1e6 * res[best] / records,
                  "sign_degree_15": {"plan": "interleaved/eager", "key_switches": plan15.key_switches,
                                     "ms_per_query": 1e3 * t15, "us_per_record": 1e6 * t15 / records},
+                 "minimax_threshold1": {"plan": "interleaved/eager", "stages": "[15,15,15], alpha 8, beta 12",
+                                        "key_switches": plan_mm.key_switches, "ms_per_query": 1e3 * tmm,
+                                        "us_per_record": 1e6 * tmm / records},
                  "paper_context_us_per_record_1thread_cpu": 1941.0}
     log("query: " + ", ".join(f"{k} {1e3 * v:.2f} ms" for k, v in res.items()) + "\n      " +
-        f"; {1e6 * res[best] / records:.3f} us/record ({best}), {plan.key_switches} key switches")
+        f"; {1e6 * res[best] / records:.3f} us/record ({best}), {plan.key_switches} key switches; "
+        f"degree-15 stages {1e3 * t15:.2f} ms, minimax threshold 1 {1e3 * tmm:.2f} ms "
+        f"({plan_mm.key_switches} key switches)")
     for h in regs + db:
         X.pfx_ct_destroy(h)
 

@@ -16,6 +16,14 @@ slot-domain linear score): for each block b of 2^(logN-1) records
         Y1 = X^2, Y_k = powers of Y1 by the tree above (k <= deg P)
         P  = c1 Y1 + c2 Y2 + ... + c0            (integer products, constant)
         U  = rescale(relin(rescale(X * round(q/den)) * P))
+  or, with sign_coeffs (the composite minimax thresholds of Tab. 2, one
+  tuple of coefficients c_1, c_3, .., c_d per stage, their count replacing
+  `stages`), per stage p(x) = sum c_k x^k:
+        x^2, x^3, x^4, x^5, x^7, x^8, x^9, .. x^d by ODD_TREE (relinearised,
+        rescaled; depth 4 for d = 15)
+        acc = rescale(x^d * c_d at the next prime's scale)
+        acc = acc + rescale(x^k * c_k at the scale that lands on acc's),
+              k = d - 2 down to 1                          (MUL_CONST_TO)
     step_b = (U + 1) with the scale doubled
   OUT = InnerSum(step_0 + step_1 + ...) on the first final_limbs limbs
 
@@ -55,40 +63,16 @@ from . import pfx as X
 SIGN = {7: ((35, -35, 21, -5), 16),
         15: ((6435, -15015, 27027, -32175, 25025, -12285, 3465, -429), 2048)}
 
-
-@dataclass
-class QueryPlan:
-    n_blocks: int
-    attributes: int = 8
-    degree: int = 7
-    stages: int = 3
-    log_slots: int = 15
-    parallel: bool = False
-    lanes: int = 4
-    interleave: bool | int = False
-    final_limbs: int = 2
-    sign_degree: int = 7      # 7 or 15: the degree of each composite-sign stage
-    ops: list = field(default_factory=list)
-    n_regs: int = 0
-    out: int = -1
-
-    def __post_init__(self):
-        A, D = self.attributes, self.degree
-        assert 1 <= D <= 15 and A >= 1 and self.n_blocks >= 1
-        assert self.sign_degree in SIGN
-        self.W = list(range(A))
-        self.C = list(range(A, A + D + 1))
-        self.T = A + D + 1
-        self.H = A + D + 2
-        self.n_inputs = A + D + 3
-        self._free: dict = {1: [], 2: []}
-        self._next = self.n_inputs
-        self._deg2: set = set()
-        self._build()
-        self.n_regs = self._next
-        self.reg_degree = [2 if r in self._deg2 else 1 for r in range(self.n_regs)]
+# minimax stages: the odd powers x^3 .. x^15 and the even helpers x^2, x^4,
+# x^8, each the product of the two lower powers listed
+ODD_TREE = {2: (1, 1), 3: (2, 1), 4: (2, 2), 5: (4, 1), 7: (4, 3), 8: (4, 4), 9: (8, 1), 11: (8, 3),
+            13: (8, 5), 15: (8, 7)}
 
 
+class _OpList:
+    """Op-list building blocks shared by the plans: registers (free lists by
+    capacity degree, inputs never recycled) and the op sequences of an
+    HMult + relin + rescale and of one minimax sign stage."""
 
     # register allocation: free lists by capacity degree
     def _new(self, degree: int = 1) -> int:
@@ -118,6 +102,63 @@ class QueryPlan:
             self._op(X.OP_MUL_RELIN, dst, a, b)
             self._op(X.OP_RESCALE, dst, dst)
 
+    def _minimax_stage(self, u: int, c) -> int:
+        d = 2 * len(c) - 1
+        xp = {1: u}
+        for k in sorted(ODD_TREE):
+            if (k <= d) if k % 2 else (k + 1 <= d):      # an even power only as a factor
+                xp[k] = self._new()
+                self._mr(xp[k], xp[ODD_TREE[k][0]], xp[ODD_TREE[k][1]])
+        acc = self._new()
+        self._op(X.OP_MUL_CONST, acc, xp[d], value=c[-1])
+        self._op(X.OP_RESCALE, acc, acc)
+        t = self._new()
+        for k in range(d - 2, 0, -2):
+            self._op(X.OP_MUL_CONST_TO, t, xp[k], acc, value=c[(k - 1) // 2])
+            self._op(X.OP_RESCALE, t, t)
+            self._op(X.OP_ADD, acc, acc, t)
+        self._drop(t, *xp.values())
+        return acc
+
+
+@dataclass
+class QueryPlan(_OpList):
+    n_blocks: int
+    attributes: int = 8
+    degree: int = 7
+    stages: int = 3
+    log_slots: int = 15
+    parallel: bool = False
+    lanes: int = 4
+    interleave: bool | int = False
+    final_limbs: int = 2
+    sign_degree: int = 7      # 7 or 15: the degree of each composite-sign stage
+    sign_coeffs: tuple | None = None   # minimax stages (c_1, c_3, .., c_d) instead
+    ops: list = field(default_factory=list)
+    n_regs: int = 0
+    out: int = -1
+
+    def __post_init__(self):
+        A, D = self.attributes, self.degree
+        assert 1 <= D <= 15 and A >= 1 and self.n_blocks >= 1
+        assert self.sign_degree in SIGN
+        if self.sign_coeffs is not None:
+            self.sign_coeffs = tuple(tuple(float(v) for v in c) for c in self.sign_coeffs)
+            assert self.sign_coeffs and all(1 <= len(c) <= 8 for c in self.sign_coeffs)
+        self.W = list(range(A))
+        self.C = list(range(A, A + D + 1))
+        self.T = A + D + 1
+        self.H = A + D + 2
+        self.n_inputs = A + D + 3
+        self._free: dict = {1: [], 2: []}
+        self._next = self.n_inputs
+        self._deg2: set = set()
+        self._build()
+        self.n_regs = self._next
+        self.reg_degree = [2 if r in self._deg2 else 1 for r in range(self.n_regs)]
+
+
+
     def _block(self, b: int) -> int:
         A, D = self.attributes, self.degree
         s = self._new()
@@ -145,8 +186,11 @@ class QueryPlan:
         self._op(X.OP_SUB, u, z, self.T)
         self._mr(u, u, self.H)
         self._drop(z)
+        if self.sign_coeffs is not None:
+            for c in self.sign_coeffs:
+                u = self._minimax_stage(u, c)
         cs, den = SIGN[self.sign_degree]
-        for _ in range(self.stages):
+        for _ in range(self.stages if self.sign_coeffs is None else 0):
             ys = {1: self._new()}
             self._mr(ys[1], u, u)                       # y = x^2
             for k in range(2, len(cs)):
@@ -234,3 +278,46 @@ class QueryPlan:
     @property
     def key_switches(self) -> int:
         return sum(1 for o in self.ops if o[0] in (X.OP_MUL_RELIN, X.OP_RELIN)) + self.log_slots
+
+
+@dataclass
+class GlobalThresholdPlan(_OpList):
+    """The global threshold on the count (Sec. 5.3, Threshold2 of Tab. 2):
+    step((count - t1) p^-1) with t1 encrypted and p public, by the minimax
+    stages `sign_coeffs`:
+
+        U   = rescale((COUNT - T1) * p^-1 at the next prime's scale)
+        U   = minimax stage (as in QueryPlan) for each tuple of coefficients
+        OUT = (U + 1) with the scale doubled
+
+    Inputs (registers, read-only): 0 the count (every slot), 1 t1.  Depth
+    1 + 5 per stage of degree 15: with six stages a fresh ciphertext of at
+    least 32 limbs (the count after a bootstrapping, in the paper)."""
+    sign_coeffs: tuple
+    inv_p: float
+    ops: list = field(default_factory=list)
+    n_regs: int = 0
+    out: int = -1
+
+    def __post_init__(self):
+        self.sign_coeffs = tuple(tuple(float(v) for v in c) for c in self.sign_coeffs)
+        assert self.sign_coeffs and all(1 <= len(c) <= 8 for c in self.sign_coeffs) and self.inv_p > 0
+        self.n_inputs = 2
+        self._free: dict = {1: [], 2: []}
+        self._next = self.n_inputs
+        self._deg2: set = set()
+        u = self._new()
+        self._op(X.OP_SUB, u, 0, 1)
+        self._op(X.OP_MUL_CONST, u, u, value=self.inv_p)
+        self._op(X.OP_RESCALE, u, u)
+        for c in self.sign_coeffs:
+            u = self._minimax_stage(u, c)
+        self._op(X.OP_ADD_CONST, u, u, value=1.0)
+        self._op(X.OP_SCALE_MUL, u, u, value=2.0)
+        self.out = u
+        self.n_regs = self._next
+        self.reg_degree = [1] * self.n_regs
+
+    @property
+    def depth(self) -> int:
+        return 1 + sum(1 + (2 * len(c) - 2).bit_length() for c in self.sign_coeffs)   # x^d, then c_d x^d

@@ -135,7 +135,8 @@ class Setup:
         rlk = O.relin_key(P, self.s, *self.key_in[0])
         gks = {g: O.galois_key(P, self.s, g, *v) for g, v in self.key_in.items() if g}
         Xw = [[self.db_words[b * A + a] for a in range(A)] for b in range(len(self.db_words) // A)]
-        return Q.query_circuit(P, Xw, DELTA, W, C, T, H, rlk, gks, sign_degree=self.plan.sign_degree)
+        return Q.query_circuit(P, Xw, DELTA, W, C, T, H, rlk, gks, sign_degree=self.plan.sign_degree,
+                               sign_coeffs=self.plan.sign_coeffs)
 
     def close(self):
         X = self.X
@@ -367,3 +368,111 @@ def test_degree_15_sign_stages_match_oracle(X, degree):
         assert abs(S.count(out)[0] - count) < 0.25
     finally:
         S.close()
+
+
+def _threshold1():
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sign_minimax.json")))
+    return g["threshold1"]["stages"]
+
+
+@pytest.mark.parametrize("plan_kw", [dict(), dict(interleave=True)], ids=["plain", "interleave"])
+def test_minimax_thresholds_match_oracle(X, plan_kw):
+    # Tab. 2's first threshold (three minimax stages of degree 15): the
+    # constants of every term at the scale that lands on the sum's (MUL_CONST_TO)
+    sc = _threshold1()
+    S = Setup(X, 12, 2, 71, with_oracle=True, sign_coeffs=sc, **plan_kw)
+    try:
+        want = S.oracle_out()
+        for graph in (False, True, False, True):
+            out = S.run(graph=graph)
+            assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), want.c), graph
+            assert X.pfx_ct_info(out).scale == want.scale
+        step, count = Q.fp64_query(S.x, *S.params, sign_coeffs=sc)
+        assert abs(S.count(out)[0] - count) < 0.25
+    finally:
+        S.close()
+
+
+def test_full_size_minimax_query_exact_count_at_a_small_margin(X):
+    # 2^17 records at N = 2^16 whose threshold inputs keep |u| >= 2^-7: the
+    # minimax thresholds count them exactly (three f7 stages do not at this margin)
+    sc = _threshold1()
+    S = Setup(X, 16, 4, 73, gap=2.0 ** -7, sign_coeffs=sc, parallel=True)
+    try:
+        ref = X.pfx_ct_export(S.ctx, S.run(graph=False), S.N)
+        out = S.run(graph=True, lanes=True)
+        assert np.array_equal(X.pfx_ct_export(S.ctx, out, S.N), ref)
+        got = S.count(out)
+        step, count = Q.fp64_query(S.x, *S.params, sign_coeffs=sc)
+        exact = int(np.sum(step > 0.5))
+        assert abs(got[0] - count) < 0.25
+        assert int(round(got[0])) == exact
+        assert np.max(np.abs(got - got[0])) < 1e-3
+    finally:
+        S.close()
+
+
+def test_global_threshold_matches_oracle(X):
+    # Threshold2 (Tab. 2, six minimax stages of degree 15 by our design, one
+    # more than the paper's five) on a fresh 34-limb ciphertext of counts, as
+    # after a bootstrapping: word for word, eagerly and from a replayed graph
+    import json
+    import os
+    from paper_2412_13269_amd.query import GlobalThresholdPlan
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sign_minimax.json")))
+    sc = g["threshold2"]["stages"]
+    logn, qb = 12, [50] + [45] * 33
+    N, n, t1, inv_p = 1 << logn, 1 << (logn - 1), 70000.5, 2.0 ** -17
+    P = O.Params(logn, qb, PB, alpha=ALPHA, mod_log2=ML)
+    ctx = X.pfx_ctx_create(X.make_params(logn, qb, PB, ALPHA, ML), 0)
+    handles, keys, sks = [], [], []
+    try:
+        q, p, _ = X.pfx_ctx_moduli(ctx, len(qb), len(PB))
+        assert [int(v) for v in q] == P.q
+        s = I.ternary_secret(N, 192, 81)
+        sk = X.pfx_sk_create(ctx, s)
+        sks.append(sk)
+        ext = P.ext_mods(P.L)
+        k_a, k_e = I.uniform_residues(ext, N, 82, lead=(P.beta,)), I.gaussian_error((P.beta, N), 83)
+        rlk = X.pfx_swk_create(ctx, sk, 0, k_a, k_e)
+        keys.append(rlk)
+        rng = np.random.default_rng(84)
+        counts = np.concatenate([np.arange(69990, 70011), rng.integers(0, 1 << 17, n - 21)]).astype(np.float64)
+        plan = GlobalThresholdPlan(sc, inv_p)
+        regs = [X.pfx_ct_create(ctx, len(qb), 1) for _ in range(plan.n_regs)]
+        handles += regs
+        o_in = []
+        for i, (z, sd) in enumerate(((counts, 85), (np.full(n, t1), 87))):
+            m = O.encode(P, z, DELTA, P.L)
+            a, e = I.uniform_residues(P.q, N, sd), I.gaussian_error(N, sd + 1)
+            pt = X.pfx_pt_import(ctx, m, DELTA)
+            X.pfx_encrypt(ctx, sk, pt, a, e, regs[i])
+            X.pfx_ct_destroy(pt)
+            o_in.append(O.encrypt(P, s, m, a, e, DELTA))
+        want = Q.global_threshold(P, o_in[0], o_in[1], inv_p, sc, O.relin_key(P, s, k_a, k_e))
+        st = X.pfx_stream_create(ctx)
+        try:
+            for graph in (False, True, False, True):
+                X.pfx_run_circuit(ctx, plan.ops, regs, plan.n_inputs, [], rlk, [],
+                                  X.RUN_GRAPH if graph else X.RUN_EAGER, st)
+                X.pfx_sync(ctx, st)
+                out = regs[plan.out]
+                assert np.array_equal(X.pfx_ct_export(ctx, out, N), want.c), graph
+                assert X.pfx_ct_info(out).scale == want.scale
+        finally:
+            X.pfx_stream_destroy(ctx, st)
+        m = X.pfx_decrypt(ctx, sk, out)
+        got = X.pfx_decode(ctx, m, n).real
+        X.pfx_ct_destroy(m)
+        far = np.abs(counts - t1) >= 2
+        assert np.max(np.abs(got - (counts > t1))[far]) <= 2.0 ** -20
+    finally:
+        for h in handles:
+            X.pfx_ct_destroy(h)
+        for k in keys:
+            X.pfx_swk_destroy(k)
+        for k in sks:
+            X.pfx_sk_destroy(k)
+        X.pfx_ctx_destroy(ctx)

@@ -152,3 +152,65 @@ def test_plan_with_degree_15_sign_stages(kw):
     got = interpret(plan, inputs, pts)
     _, count = Q.fp64_query(x, w, c, t, eta, sign_degree=15)
     assert np.allclose(got, count, rtol=1e-9, atol=1e-9)
+
+
+def _threshold1():
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sign_minimax.json")))
+    return g["threshold1"]["stages"]
+
+
+@pytest.mark.parametrize("kw", VARIANTS, ids=lambda kw: "-".join(f"{k}{v}" for k, v in kw.items()) or "plain")
+def test_plan_with_minimax_thresholds(kw):
+    # Tab. 2's first threshold: three minimax stages of degree 15 (designed stage by stage)
+    n, A, blocks = 64, 8, 3
+    x = I.synthetic_database(n * blocks, A, 51)
+    w, c, t, eta = I.query_parameters(A, 7, 52)
+    sc = _threshold1()
+    plan = QueryPlan(blocks, A, 7, 3, 6, sign_coeffs=sc, **kw)
+    inputs = [np.full(n, v) for v in list(w) + list(c) + [t, eta]]
+    pts = [x[b * n:(b + 1) * n, a] for b in range(blocks) for a in range(A)]
+    got = interpret(plan, inputs, pts)
+    _, count = Q.fp64_query(x, w, c, t, eta, sign_coeffs=sc)
+    assert np.allclose(got, count, rtol=1e-9, atol=1e-9)
+    # depth: 6 for the score and the threshold input, 5 per stage
+    codes = [o[0] for o in plan.ops]
+    assert codes.count(X.OP_MUL_CONST_TO) == blocks * 3 * 7
+    assert codes.count(X.OP_MUL_RELIN) == blocks * (6 + 1 + 3 * 10)
+
+
+def test_minimax_stage_of_lower_degree_skips_unused_powers():
+    # a degree-7 stage needs x^2, x^3, x^4, x^5, x^7 only (no x^8)
+    n, A = 64, 8
+    x = I.synthetic_database(n, A, 61)
+    w, c, t, eta = I.query_parameters(A, 7, 62)
+    sc = [[1.5, -0.5, 0.0, 0.0]]            # x (3 - x^2) / 2, degree 7 with zero tail terms
+    plan = QueryPlan(1, A, 7, 3, 6, sign_coeffs=sc)
+    inputs = [np.full(n, v) for v in list(w) + list(c) + [t, eta]]
+    got = interpret(plan, inputs, [x[:, a] for a in range(A)])
+    _, count = Q.fp64_query(x, w, c, t, eta, sign_coeffs=sc)
+    assert np.allclose(got, count, rtol=1e-9, atol=1e-9)
+    codes = [o[0] for o in plan.ops]
+    assert codes.count(X.OP_MUL_RELIN) == 6 + 1 + 5
+
+
+def test_global_threshold_plan_computes_the_step():
+    import json
+    import os
+    from paper_2412_13269_amd.query import GlobalThresholdPlan
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sign_minimax.json")))
+    sc = g["threshold2"]["stages"]
+    counts = np.concatenate([np.arange(69990.0, 70011.0), np.linspace(0, 1 << 17, 43)])
+    plan = GlobalThresholdPlan(sc, 2.0 ** -17)
+    got = interpret(plan, [counts, np.full(len(counts), 70000.5)], [])
+    want = Q.fp64_global_threshold(counts, 70000.5, 2.0 ** -17, sc)
+    # terms summed in another order than Horner's: equal to rounding where the
+    # stages are flat (|count - t1| >= 2); the two counts beside t1 lie below
+    # the design's domain, where the stages amplify rounding
+    far = np.abs(counts - 70000.5) >= 2
+    assert np.allclose(got[far], want[far], rtol=0, atol=1e-10)
+    assert np.allclose(got[~far], want[~far], rtol=1e-3, atol=1e-6)
+    assert plan.depth == 31 and plan.n_inputs == 2
+    codes = [o[0] for o in plan.ops]
+    assert codes.count(X.OP_MUL_RELIN) == 6 * 10 and codes.count(X.OP_MUL_CONST_TO) == 6 * 7
