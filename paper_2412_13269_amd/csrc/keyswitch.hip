@@ -62,7 +62,7 @@ __global__ __launch_bounds__(TH) void k_moddown_col(const KsArgs a, double *__re
 }
 
 template <int S, int MODE, int TH>
-__global__ __launch_bounds__(TH) void k_row_moddown(const KsArgs a, const double *__restrict__ acc,
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(3))) void k_row_moddown(const KsArgs a, const double *__restrict__ acc,
                                                     const double *__restrict__ tmp) {
     __shared__ double lds[NttTile<TH>::lds];
     const int gid = xcd_slot(a.n);

@@ -15,6 +15,14 @@
         the setup: `workload --query` idles 0.5 s there), grouped by kernel
         name, per run (divided by R), with the device's busy and idle time
         over that span
+        with --name NAME it also prints the machine-readable line
+        "traffic_bytes_per_launch: B kernel: NAME sources_sha256: H" (H over
+        the sources that define the kernel, SOURCES[NAME])
+    python -m paper_2412_13269_amd.profsum --valu-per-op <SQ counters csv> --after REGEX --ops K
+        VALU wave instructions (SQ_INSTS_VALU) summed over every dispatch
+        after the last one of the marker kernel REGEX, divided by K, and the
+        line "valu_wave_instructions_per_rotation: V sources_sha256: H" (H over
+        SOURCES["ks_rotation"]); for `workload --rotations-only --calibrate`
     python -m paper_2412_13269_amd.profsum --valu <SQ counters csv> <..._kernel_trace.csv> [--top N]
         per kernel and grid: VALU wave instructions per dispatch (SQ_INSTS_VALU),
         the average duration from the trace run, and the issue rate against
@@ -24,8 +32,24 @@
 from __future__ import annotations
 
 import csv
+import hashlib
+import os
 import sys
 from collections import defaultdict
+
+# sources that define a profiled kernel: their hash ties a committed counter
+# measurement to the code it was taken on
+SOURCES = {"ks_inner": ["kernels.hip", "modarith.h", "ntt_core.h", "internal.h"],
+           "repack_fused": ["keyswitch.hip", "modarith.h", "ntt_core.h", "internal.h"],
+           "ks_rotation": ["kernels.hip", "keyswitch.hip", "modarith.h", "ntt_core.h", "internal.h"]}
+
+
+def sources_sha256(name: str) -> str:
+    h = hashlib.sha256()
+    for f in SOURCES[name]:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def summarise(path: str, top: int = 25) -> str:
@@ -87,7 +111,7 @@ def _per_dispatch(path: str, counter: str, match: str, grid: str | None = None) 
     return list(per.values())
 
 
-def traffic(fetch_csv: str, write_csv: str, kernel: str, copy: str) -> str:
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy: str, name: str | None = None) -> str:
     cname, cgrid, ckib = copy.rsplit(":", 2)
     out = []
     total = 0.0
@@ -103,6 +127,44 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy: str) -> str:
         out.append(f"{ctr}: copy {c_avg:.2f} KiB over {len(cal)} dispatches -> scale {scale:.5f}; "
                    f"kernel {k_avg:.2f} KiB over {len(k)} dispatches -> {nbytes:.0f} bytes")
     out.append(f"total bytes per dispatch: {total:.0f}")
+    if name is not None:
+        out.append(f"traffic_bytes_per_launch: {total:.0f} kernel: {name} sources_sha256: {sources_sha256(name)}")
+    return "\n".join(out)
+
+
+def valu_per_op(counters_csv: str, after: str, ops: int) -> str:
+    """Kernels dispatched a multiple of `ops` times after the marker are the
+    op's own (each op launches the same sequence); any other dispatch (the
+    process's tail) is listed and left out."""
+    import re
+    rows = []
+    with open(counters_csv, newline="") as f:
+        for row in csv.DictReader(f):
+            name = (row.get("Kernel_Name") or "?").split("(")[0].replace("void ", "")
+            rows.append((int(row["Dispatch_Id"]), name, row["Counter_Name"], float(row["Counter_Value"])))
+    marks = [d for d, n, _, _ in rows if re.search(after, n)]
+    if not marks:
+        raise SystemExit(f"no dispatch of {after}")
+    last = max(marks)
+    disp = defaultdict(set)
+    inst = defaultdict(float)
+    for d, n, c, v in rows:
+        if d > last and c == "SQ_INSTS_VALU":
+            disp[n].add(d)
+            inst[n] += v
+    out = ["| kernel | dispatches | VALU wave instr. per dispatch | per op |", "|---|---|---|---|"]
+    per, left = 0.0, []
+    for n in sorted(inst, key=lambda k: -inst[k]):
+        k = len(disp[n])
+        if k % ops:
+            left.append(f"{n} x{k}")
+            continue
+        per += inst[n] / ops
+        out.append(f"| `{n}` | {k} | {inst[n] / k:.4g} | {inst[n] / ops:.4g} |")
+    out.append("")
+    out.append(f"per op: {per:.6g} VALU wave instructions over {sum(len(disp[n]) for n in disp if len(disp[n]) % ops == 0) / ops:.0f} dispatches"
+               + (f"; left out: {', '.join(left)}" if left else ""))
+    out.append(f"valu_wave_instructions_per_rotation: {per:.6g} sources_sha256: {sources_sha256('ks_rotation')}")
     return "\n".join(out)
 
 
@@ -181,8 +243,14 @@ if __name__ == "__main__":
         sys.exit(0)
     if "--traffic" in sys.argv:
         i = sys.argv.index("--traffic")
+        name = sys.argv[sys.argv.index("--name") + 1] if "--name" in sys.argv else None
         print(traffic(sys.argv[i + 1], sys.argv[i + 2], sys.argv[sys.argv.index("--kernel") + 1],
-                      sys.argv[sys.argv.index("--copy") + 1]))
+                      sys.argv[sys.argv.index("--copy") + 1], name))
+        sys.exit(0)
+    if "--valu-per-op" in sys.argv:
+        i = sys.argv.index("--valu-per-op")
+        print(valu_per_op(sys.argv[i + 1], sys.argv[sys.argv.index("--after") + 1],
+                          int(sys.argv[sys.argv.index("--ops") + 1])))
         sys.exit(0)
     if "--pmc" in sys.argv:
         i = sys.argv.index("--pmc")

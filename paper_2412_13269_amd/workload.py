@@ -95,6 +95,10 @@ class KsWorkload:
         for r in ROT_STEPS:
             X.pfx_rotate(ctx, self.cts[0], r, self.gks, self.rot, st)
 
+    def rotations(self):
+        for r in ROT_STEPS:
+            self.X.pfx_rotate(self.ctx, self.cts[0], r, self.gks, self.rot, self.st)
+
     def calibrate_copy(self, reps=5):
         """Two k_u64_to_f64 launches per import, 24 limbs (12 MiB in, 12 MiB out) each."""
         X = self.X
@@ -335,6 +339,8 @@ def main():
     ap.add_argument("--pfe", action="store_true")
     ap.add_argument("--half-bts", action="store_true")
     ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--rotations-only", action="store_true",
+                    help="each step is the 15 rotations alone (after the copy calibration, if asked)")
     args = ap.parse_args()
     if args.half_bts:
         from . import pfx as X
@@ -378,12 +384,17 @@ def main():
     if args.calibrate:
         w.calibrate_copy()
         print("copy calibration done", flush=True)
-    w.step()
+    step = w.rotations if args.rotations_only else w.step
+    step()
     w.sync()
     for _ in range(args.steps):
-        w.step()
+        step()
     w.sync()
-    print(f"{args.steps} steps done ({KS_PER_STEP * args.steps} key switches)", flush=True)
+    if args.rotations_only:
+        print(f"{args.steps + 1} steps of {len(ROT_STEPS)} rotations done "
+              f"({(args.steps + 1) * len(ROT_STEPS)} rotations after the calibration)", flush=True)
+    else:
+        print(f"{args.steps} steps done ({KS_PER_STEP * args.steps} key switches)", flush=True)
     w.close()
 
 
