@@ -78,6 +78,16 @@ __device__ __forceinline__ double mmulc_lazy(double a, double w, double wq, doub
     return __builtin_fma(-c, q, h) + l;
 }
 
+// a*b mod q up to a multiple of q: r = a*b - c*q with |r| <= 0.875 q, for
+// integers |a| < 2^50 and |b| < q < 2^50 of either sign (mmul without its final
+// correction: the estimate c is off from a*b/q by at most 0.875, as there).
+__device__ __forceinline__ double mmul_lazy(double a, double b, double q, double qinv) {
+    double h = a * b;
+    double l = __builtin_fma(a, b, -h);
+    double c = __builtin_rint(h * qinv);
+    return __builtin_fma(-c, q, h) + l;
+}
+
 // x mod q into [-q/2, q/2] (up to a rounding tie) for an integer |x| < 2^53.
 __device__ __forceinline__ double mred_signed(double x, double q, double qinv) {
     return __builtin_fma(-__builtin_rint(x * qinv), q, x);

@@ -86,13 +86,18 @@ __device__ __forceinline__ double monomial_mul(double x, uint32_t j, uint32_t k,
 
 // Arithmetic inside a transform is signed and lazy: a twiddle product returns
 // a representative in [-q, q] (mmulc_lazy), sums and differences are left
-// unreduced, and every value is brought back to [-q/2, q/2] (mred_signed) after
-// every second forward stage and after every inverse stage's sum.  Bounds (q <
-// 2^50, inputs |x| <= q): forward, two stages take |x| <= 0.51q to at most
-// 2.75q before the reduction; inverse sums stay below 2q and differences below
-// 2q before their product.  Every intermediate is an integer below 2^52 in
-// magnitude, so each step is exact.  Group outputs are reduced to
-// [-q/2, q/2]; the last pass of a transform canonicalises to [0, q).
+// unreduced, and values are brought back to [-q/2, q/2] (mred_signed) often
+// enough that every lazy product's input stays within 2^51.  Wide primes
+// (2^47 <= q < 2^50, inputs |x| <= q): after every second forward stage (two
+// stages take |x| <= 0.51q to at most 2.75q) and after every inverse stage's
+// sum (sums and differences stay below 2q).  Narrow primes (q < 2^47, the
+// `narrow` flag, uniform per launch tile): only at the end of a register group
+// of at most 4 stages: forward values grow by at most 1.25q per stage (|x| <=
+// q + 5q), inverse sums double per stage (at most 16q, differences 16q <
+// 2^51).  Every intermediate is an integer below 2^52 in magnitude, so each
+// step is exact.  Group outputs are reduced to [-q/2, q/2]; the last pass of a
+// transform canonicalises to [0, q).
+constexpr double kNarrowPrime = 140737488355328.0;   // 2^47
 
 // Forward butterflies of NST consecutive stages on the E = 2^NST elements of
 // one register group.  At stage kk of the group the butterflies come in 2^kk
@@ -101,7 +106,7 @@ __device__ __forceinline__ double monomial_mul(double x, uint32_t j, uint32_t k,
 // closed form (for the first round of a column pass the index is a
 // compile-time constant, so the twiddles are uniform scalar loads).
 template <int NST, class Twf>
-__device__ __forceinline__ void fwd_group(double *v, double q, double qinv, Twf &&twf) {
+__device__ __forceinline__ void fwd_group(double *v, double q, double qinv, bool narrow, Twf &&twf) {
     constexpr int E = 1 << NST;
 #pragma unroll
     for (int kk = 0; kk < NST; ++kk) {
@@ -118,17 +123,27 @@ __device__ __forceinline__ void fwd_group(double *v, double q, double qinv, Twf 
                 v[u + h] = U - T;
             }
         }
-        if ((kk & 1) || kk == NST - 1) {
+        if (kk == NST - 1 || ((kk & 1) && !narrow)) {
 #pragma unroll
             for (int u = 0; u < E; ++u) v[u] = mred_signed(v[u], q, qinv);
         }
     }
 }
 
+// The sums of inverse group stage kk (the lower element of each pair) back to
+// [-q/2, q/2]; called behind a uniform branch, so narrow primes skip it.
+template <int NST>
+__device__ __forceinline__ void inv_reduce_sums(double *v, int kk, double q, double qinv) {
+    const int h = 1 << (NST - 1 - kk);
+#pragma unroll
+    for (int u = 0; u < (1 << NST); ++u)
+        if (!(u & h)) v[u] = mred_signed(v[u], q, qinv);
+}
+
 // Inverse butterflies, group stages NST - 1 down to 0 (twiddles as above).
 // With `last` the group's stage 0 is global stage 0 and N^-1 is folded into it.
 template <int NST, class Twf>
-__device__ __forceinline__ void inv_group(double *v, const PrimeDev &P, bool last, Twf &&twf) {
+__device__ __forceinline__ void inv_group(double *v, const PrimeDev &P, bool last, bool narrow, Twf &&twf) {
     constexpr int E = 1 << NST;
     const double q = P.q, qinv = P.qinv;
 #pragma unroll
@@ -146,11 +161,12 @@ __device__ __forceinline__ void inv_group(double *v, const PrimeDev &P, bool las
                     v[u] = mmulc_lazy(U + V, P.ninv, P.ninv_q, q);
                     v[u + h] = mmulc_lazy(U - V, P.ninv_w1, P.ninv_w1_q, q);
                 } else {
-                    v[u] = mred_signed(U + V, q, qinv);
+                    v[u] = U + V;
                     v[u + h] = mmulc_lazy(U - V, w.x, w.y, q);
                 }
             }
         }
+        if (!narrow && !(last && kk == 0)) inv_reduce_sums<NST>(v, kk, q, qinv);
     }
 #pragma unroll
     for (int u = 0; u < E; ++u) v[u] = mred_signed(v[u], q, qinv);
@@ -160,15 +176,17 @@ __device__ __forceinline__ void inv_group(double *v, const PrimeDev &P, bool las
 // instead of read from the 2^logn-entry table (which would cost as many bytes
 // as the data).  For the thread's group j = (P << R2) | u the stage-(T + k)
 // twiddle is rc[2^k - 1 + x] * B_k, x = u >> (R2 - k), with B_{R2-1} =
-// rtw[P] and B_{k-1} = B_k^2: 2^R2 - 1 + R2 - 1 modular products per group.
-// Generated twiddles come with wq = fl(w * fl(1/q)), so a lazy product is
-// within 1.25 q (|a| <= 2^51) or 0.875 q (|a| <= q); the two-stage growth
-// stays below 3.2 q < 2^52.
+// rtw[P] and B_{k-1} = B_k^2: 2^R2 - 1 + R2 - 1 modular products per group,
+// each left signed in (-q, q) (mmul_lazy: |w| <= 0.875 q; the bases stay below
+// q in magnitude, which is all the next square needs).  Generated twiddles
+// come with wq = fl(w * fl(1/q)), so a lazy product with one is within 1.25 q
+// (|a| <= 2^51) or 0.875 q (|a| <= q); the two-stage growth stays below
+// 3.2 q < 2^52, the narrow-prime growth over a group below 6 q.
 template <int NST>
 __device__ __forceinline__ void row_twiddle_bases(double *B, double top, double q, double qinv) {
     B[NST - 1] = top;
 #pragma unroll
-    for (int k = NST - 1; k > 0; --k) B[k - 1] = mmul(B[k], B[k], q, qinv);
+    for (int k = NST - 1; k > 0; --k) B[k - 1] = mmul_lazy(B[k], B[k], q, qinv);
 }
 
 // The 2^NST - 1 table twiddles of one register group, loaded ahead of the
@@ -182,14 +200,15 @@ __device__ __forceinline__ void prefetch_twiddles(double2 *W, const GTw &tw, Idx
 }
 
 template <int NST>
-__device__ __forceinline__ void fwd_group_gen(double *v, const double *B, const double *rc, double q, double qinv) {
+__device__ __forceinline__ void fwd_group_gen(double *v, const double *B, const double *rc, double q, double qinv,
+                                              bool narrow) {
     constexpr int E = 1 << NST;
 #pragma unroll
     for (int kk = 0; kk < NST; ++kk) {
         const int h = 1 << (NST - 1 - kk);
 #pragma unroll
         for (int x = 0; x < (1 << kk); ++x) {
-            const double w = mmul(rc[(1 << kk) - 1 + x], B[kk], q, qinv);
+            const double w = mmul_lazy(rc[(1 << kk) - 1 + x], B[kk], q, qinv);
             const double wq = w * qinv;
 #pragma unroll
             for (int lo = 0; lo < h; ++lo) {
@@ -200,7 +219,7 @@ __device__ __forceinline__ void fwd_group_gen(double *v, const double *B, const 
                 v[u + h] = U - T;
             }
         }
-        if ((kk & 1) || kk == NST - 1) {
+        if (kk == NST - 1 || ((kk & 1) && !narrow)) {
 #pragma unroll
             for (int u = 0; u < E; ++u) v[u] = mred_signed(v[u], q, qinv);
         }
@@ -208,23 +227,25 @@ __device__ __forceinline__ void fwd_group_gen(double *v, const double *B, const 
 }
 
 template <int NST>
-__device__ __forceinline__ void inv_group_gen(double *v, const double *B, const double *rc, double q, double qinv) {
+__device__ __forceinline__ void inv_group_gen(double *v, const double *B, const double *rc, double q, double qinv,
+                                              bool narrow) {
     constexpr int E = 1 << NST;
 #pragma unroll
     for (int kk = NST - 1; kk >= 0; --kk) {
         const int h = 1 << (NST - 1 - kk);
 #pragma unroll
         for (int x = 0; x < (1 << kk); ++x) {
-            const double w = mmul(rc[(1 << kk) - 1 + x], B[kk], q, qinv);
+            const double w = mmul_lazy(rc[(1 << kk) - 1 + x], B[kk], q, qinv);
             const double wq = w * qinv;
 #pragma unroll
             for (int lo = 0; lo < h; ++lo) {
                 const int u = (x << (NST - kk)) | lo;
                 const double U = v[u], V = v[u + h];
-                v[u] = mred_signed(U + V, q, qinv);
+                v[u] = U + V;
                 v[u + h] = mmulc_lazy(U - V, w, wq, q);
             }
         }
+        if (!narrow) inv_reduce_sums<NST>(v, kk, q, qinv);
     }
 #pragma unroll
     for (int u = 0; u < E; ++u) v[u] = mred_signed(v[u], q, qinv);
@@ -241,6 +262,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
     constexpr int IT1 = kSlots / E1, IT2 = kSlots / E2;
     const int lo = logn - S;
     const double q = P.q;
+    const bool narrow = q < kNarrowPrime;
     const GTw tw = as_global(INV ? P.itw : P.tw);
     const int n1 = C << (S - R1), n2 = C << R1;
     auto gidx = [&](int c, int mid) { return (mid << lo) | (cbase + c); };
@@ -255,7 +277,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
                 // stage kk < R1: index 2^kk + (mid >> (S - kk)) = 2^kk + x (ml shifts out)
-                fwd_group<R1>(v, q, P.qinv, [&](int kk, int x) { return tw[(1 << kk) + x]; });
+                fwd_group<R1>(v, q, P.qinv, narrow, [&](int kk, int x) { return tw[(1 << kk) + x]; });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) lds[((u << (S - R1)) | ml) * C + c] = v[u];
             }
@@ -271,7 +293,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = lds[((mh << R2) | u) * C + c];
                 // stage R1 + kk: mid >> (R2 - kk) = (mh << kk) | x
-                fwd_group<R2>(v, q, P.qinv, [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
+                fwd_group<R2>(v, q, P.qinv, narrow, [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
 #pragma unroll
                 for (int u = 0; u < E2; ++u) store(gu(u), v[u], gi * E2 + u);
             }
@@ -286,7 +308,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
                 double v[E2];
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = load(gu(u), gi * E2 + u);
-                inv_group<R2>(v, P, false, [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
+                inv_group<R2>(v, P, false, narrow, [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
 #pragma unroll
                 for (int u = 0; u < E2; ++u) lds[((mh << R2) | u) * C + c] = v[u];
             }
@@ -301,7 +323,7 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
                 double v[E1];
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = lds[((u << (S - R1)) | ml) * C + c];
-                inv_group<R1>(v, P, true, [&](int kk, int x) { return tw[(1 << kk) + x]; });
+                inv_group<R1>(v, P, true, narrow, [&](int kk, int x) { return tw[(1 << kk) + x]; });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) store(gu(u), mcanon(v[u], q), gi * E1 + u);
             }
@@ -325,6 +347,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
     constexpr int PAD = R + R / 16;
     const int s0 = logn - S;
     const double q = P.q;
+    const bool narrow = q < kNarrowPrime;
     const GTw tw = as_global(INV ? P.itw : P.tw);
     const int n1 = C << (S - R1), n2 = C << R1;
     const int tot = C * R;
@@ -348,7 +371,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
                 // stage s0 + kk: gidx >> (S - kk) = ((cbase + c) << kk) | x
-                fwd_group<R1>(v, q, P.qinv,
+                fwd_group<R1>(v, q, P.qinv, narrow,
                               [&](int kk, int x) { return tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)]; });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) lds[lidx(c, (u << (S - R1)) | ml)] = v[u];
@@ -364,7 +387,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
                 row_twiddle_bases<R2>(B, IT2 == 1 ? rtop : rt[((cbase + c) << R1) | mh], q, P.qinv);
-                fwd_group_gen<R2>(v, B, P.rc, q, P.qinv);
+                fwd_group_gen<R2>(v, B, P.rc, q, P.qinv, narrow);
 #pragma unroll
                 for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
             }
@@ -396,7 +419,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = lds[lidx(c, (mh << R2) | u)];
                 row_twiddle_bases<R2>(B, IT2 == 1 ? rtop : rt[((cbase + c) << R1) | mh], q, P.qinv);
-                inv_group_gen<R2>(v, B, P.irc, q, P.qinv);
+                inv_group_gen<R2>(v, B, P.irc, q, P.qinv, narrow);
 #pragma unroll
                 for (int u = 0; u < E2; ++u) lds[lidx(c, (mh << R2) | u)] = v[u];
             }
@@ -411,7 +434,7 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
                 double v[E1];
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = lds[lidx(c, (u << (S - R1)) | ml)];
-                inv_group<R1>(v, P, false, [&](int kk, int x) {
+                inv_group<R1>(v, P, false, narrow, [&](int kk, int x) {
                     return IT1 == 1 ? W1[(1 << kk) - 1 + x] : tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)];
                 });
 #pragma unroll
