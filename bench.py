@@ -7,8 +7,13 @@ primes (dnum = 6), scale 2^45, secret with 192 non-zeros, 2^15 real slots
 uniform in [-1, 1].  One step runs every operation of the path once on device-
 resident inputs: forward and inverse NTT of all limbs of a ciphertext, HMult +
 relinearisation, rescale 24 -> 23, and rotations by 2^k for k = 0..14 (15
-distinct Galois keys).  HMult + relin and the rotations are the 16 key
-switches of a step; `value` is key switches per second over the timed steps.
+distinct Galois keys, 15 outputs).  HMult + relin and the rotations are the 16
+key switches of a step; `value` is key switches per second over the timed
+steps.  The 15 rotations are independent key switches and run as one batched
+call (pfx_rotate_batch: every launch covers up to 8 of them, each with its own
+key; nothing is shared between them, no ModUp is hoisted); the same step with
+one launch sequence per rotation is timed beside it
+(`ms_per_step_rotations_one_by_one`).
 
 Prints one JSON line.  `roofline` is for the kernel with the largest device
 time in the timed region, from HIP events the library records around each of
@@ -478,6 +483,15 @@ def main():
     X.pfx_sync(ctx, st)
     p_elapsed = time.perf_counter() - p0
     X.pfx_profile_enable(ctx, False)
+    # the same step with its rotations one key switch launch sequence at a time
+    for _ in range(2):
+        W.step_one_by_one()
+    X.pfx_sync(ctx, st)
+    o0 = time.perf_counter()
+    for _ in range(args.steps):
+        W.step_one_by_one()
+    X.pfx_sync(ctx, st)
+    ms_one_by_one = 1e3 * (time.perf_counter() - o0) / args.steps
     ks_per_step = KS_PER_STEP
     kern = {}
     for name in X.pfx_profile_names(ctx):
@@ -486,7 +500,8 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-    log(f"timed {1e3 * elapsed / args.steps:.3f} ms/step, profiled {1e3 * p_elapsed / args.steps:.3f} ms/step")
+    log(f"timed {1e3 * elapsed / args.steps:.3f} ms/step, profiled {1e3 * p_elapsed / args.steps:.3f} ms/step, "
+        f"rotations one by one {ms_one_by_one:.3f} ms/step")
     log("kernels (profiled region):")
     for name, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"]):
         log(f"  {name:16s} launches={v['launches']:6d} avg_us={1e3 * v['ms'] / max(1, v['launches']):9.2f} "
@@ -563,8 +578,11 @@ def main():
     def rot_hoisted():
         X.pfx_apply_galois_hoisted(ctx, cts[0], gks, hout, st)
 
+    def rot_batched():
+        X.pfx_rotate_batch(ctx, [cts[0]] * len(ROT_STEPS), ROT_STEPS, gks, hout, st)
+
     hoist = {}
-    for name, fn in (("separate", rot_separate), ("hoisted", rot_hoisted)):
+    for name, fn in (("separate", rot_separate), ("batched", rot_batched), ("hoisted", rot_hoisted)):
         fn()
         X.pfx_sync(ctx, st)
         h0 = time.perf_counter()
@@ -622,7 +640,9 @@ def main():
 
     per_op["rotations_15_separate_ms"] = hoist["separate"]
     per_op["rotations_15_hoisted_ms"] = hoist["hoisted"]
-    log(f"15 rotations of one ciphertext: {hoist['separate']:.3f} ms one by one, {hoist['hoisted']:.3f} ms hoisted")
+    per_op["rotations_15_batched_ms"] = hoist["batched"]
+    log(f"15 rotations of one ciphertext: {hoist['separate']:.3f} ms one by one, {hoist['batched']:.3f} ms batched "
+        f"(each its own key switch), {hoist['hoisted']:.3f} ms hoisted (one ModUp)")
     for h in hout:
         X.pfx_ct_destroy(h)
 
@@ -730,6 +750,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step_rotations_one_by_one": ms_one_by_one,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

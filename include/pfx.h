@@ -143,16 +143,22 @@ pfx_status pfx_ctx_mem(const pfx_ctx *ctx, size_t *in_use, size_t *peak);
  *     INTT of key switching) narrow their tiles until they have this many
  *     workgroups, down to min_col columns (min_col_special for the
  *     special-prime INTT; powers of two);
- *   rs_widen_wg: the same for the INTT of a rescale's dropped limb.
- * Defaults {2048, 0, 1024, 16, 8, 256}.  The geometry never changes a result,
- * only its speed.  pfx_tuning_load reads lines "log_n row_wg256 col_wg256
- * widen_wg min_col min_col_special rs_widen_wg" ('#' starts a comment line);
+ *   rs_widen_wg: the same for the INTT of a rescale's dropped limb;
+ *   ks_fuse: key switches (other than hoisted automorphisms and repacking
+ *     rounds) run the ModUp row pass, the key inner product and the first
+ *     pass of the special-prime INTT as one launch of ks_fuse threads per
+ *     workgroup (128 or 256); 0 keeps them separate launches.
+ * Defaults {2048, 0, 1024, 16, 8, 256, 0}.  The geometry never changes a
+ * result, only its speed.  pfx_tuning_load reads lines "log_n row_wg256
+ * col_wg256 widen_wg min_col min_col_special rs_widen_wg [ks_fuse]" ('#'
+ * starts a comment line; a line without ks_fuse keeps its default);
  * the first pfx_ctx_create loads tuning.txt next to libpfx.so if there is one
  * (the package's autotuner writes it).
  */
 typedef struct pfx_pass_tuning {
     uint32_t log_n;
     uint32_t row_wg256, col_wg256, widen_wg, min_col, min_col_special, rs_widen_wg;
+    uint32_t ks_fuse;
 } pfx_pass_tuning;
 pfx_status pfx_tuning_set(const pfx_pass_tuning *t);
 pfx_status pfx_tuning_get(uint32_t log_n, pfx_pass_tuning *t);
@@ -363,6 +369,18 @@ pfx_status pfx_apply_galois(pfx_ctx *ctx, const pfx_ct *a, const pfx_swk *gk, pf
  * Outputs must be distinct and alias no input of any entry (PFX_EINVAL). */
 pfx_status pfx_apply_galois_batch(pfx_ctx *ctx, const pfx_ct *const *a, size_t n, const pfx_swk *gk,
                                   pfx_ct *const *out, void *stream);
+/*
+ * Rotations of n ciphertexts, entry i by its own step steps[i] (slots left by
+ * steps[i], as pfx_rotate), each with its own Galois key found among gks
+ * (PFX_ENOKEY if one is missing).  Entries of one level run as batched key
+ * switches of up to 8 entries: every launch of the key switch covers the whole
+ * batch, so the small launches of a single key switch fill the GPU; the inner
+ * product reads each entry's own key.  A step of 0 (mod n_slots) copies.
+ * Outputs must be distinct and must not alias any input (PFX_EINVAL).  Word
+ * for word the results of pfx_rotate.  Scratch as pfx_mul_relin_batch.
+ */
+pfx_status pfx_rotate_batch(pfx_ctx *ctx, const pfx_ct *const *a, const int32_t *steps, size_t n,
+                            const pfx_swk *const *gks, size_t n_gks, pfx_ct *const *out, void *stream);
 /* Hoisted automorphisms (the baby steps of the BSGS linear transforms, App.
  * A.4): out[i] = phi_(g_i)(a) for the Galois elements of gks[0..n), the
  * decomposition (ModUp) of c1 computed once and each key switch fed with its

@@ -347,6 +347,17 @@ void ks_moddown(const Launch &L, const KsBatch &kb, int lv) {
 }
 
 void ks_run(const Launch &L, const KsBatch &kb, int lv, const pfx_swk *key) {
+    if (row_inner_ok(L.ctx, kb)) {
+        // the ModUp row pass, the inner product and the special limbs' first
+        // INTT pass in one launch
+        launch_intt_scale(L, kb, lv);
+        launch_modup_col(L, kb, lv);
+        launch_row_inner(L, kb, key->d_k, lv);
+        launch_intt_special(L, kb, lv, true);
+        launch_moddown_col(L, kb, lv);
+        launch_row_moddown(L, kb, lv);
+        return;
+    }
     ks_modup(L, kb, lv);
     if (kb.mode == KS_REPACK) launch_ks_inner_repack(L, kb, key->d_k, lv);
     else launch_ks_inner(L, kb, key->d_k, lv);
@@ -969,6 +980,7 @@ pfx_status pfx_tuning_set(const pfx_pass_tuning *t) {
     REQUIRE(t->min_col >= 1 && t->min_col_special >= 1 && !(t->min_col & (t->min_col - 1)) &&
                 !(t->min_col_special & (t->min_col_special - 1)),
             PFX_EINVAL, "column widths must be powers of two");
+    REQUIRE(t->ks_fuse == 0 || t->ks_fuse == 128 || t->ks_fuse == 256, PFX_EINVAL, "ks_fuse must be 0, 128 or 256");
     std::lock_guard<std::mutex> g(g_tune_mu);
     PassTuning &x = g_tune[t->log_n];
     x.row_wg256 = (int)std::min<uint32_t>(t->row_wg256, 1u << 30);
@@ -977,6 +989,7 @@ pfx_status pfx_tuning_set(const pfx_pass_tuning *t) {
     x.min_col = (int)t->min_col;
     x.min_col_special = (int)t->min_col_special;
     x.rs_widen_wg = (int)std::min<uint32_t>(t->rs_widen_wg, 1u << 30);
+    x.ks_fuse = (int)t->ks_fuse;
     return PFX_OK;
 }
 
@@ -985,7 +998,8 @@ pfx_status pfx_tuning_get(uint32_t log_n, pfx_pass_tuning *t) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     const PassTuning &x = g_tune[log_n];
     *t = pfx_pass_tuning{log_n, (uint32_t)x.row_wg256, (uint32_t)x.col_wg256, (uint32_t)x.widen_wg,
-                         (uint32_t)x.min_col, (uint32_t)x.min_col_special, (uint32_t)x.rs_widen_wg};
+                         (uint32_t)x.min_col, (uint32_t)x.min_col_special, (uint32_t)x.rs_widen_wg,
+                         (uint32_t)x.ks_fuse};
     return PFX_OK;
 }
 
@@ -1005,8 +1019,10 @@ pfx_status pfx_tuning_load(const char *path) {
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
         pfx_pass_tuning t;
-        if (std::sscanf(line, "%u %u %u %u %u %u %u", &t.log_n, &t.row_wg256, &t.col_wg256, &t.widen_wg,
-                        &t.min_col, &t.min_col_special, &t.rs_widen_wg) != 7) {
+        t.ks_fuse = (uint32_t)PassTuning{}.ks_fuse;      // a 7-field line keeps the default
+        const int got = std::sscanf(line, "%u %u %u %u %u %u %u %u", &t.log_n, &t.row_wg256, &t.col_wg256,
+                                    &t.widen_wg, &t.min_col, &t.min_col_special, &t.rs_widen_wg, &t.ks_fuse);
+        if (got != 7 && got != 8) {
             r = fail(PFX_EINVAL, std::string("malformed tuning line in ") + path);
             break;
         }
@@ -2049,6 +2065,79 @@ pfx_status pfx_apply_galois_batch(pfx_ctx *c, const pfx_ct *const *a, size_t n, 
         s0 = s1;
     }
     for (size_t i = 0; i < n; ++i) {
+        out[i]->n_limbs = lvs[i];
+        out[i]->degree = 1;
+        out[i]->scale = sc[i];
+    }
+    return PFX_OK;
+}
+
+pfx_status pfx_rotate_batch(pfx_ctx *c, const pfx_ct *const *a, const int32_t *steps, size_t n,
+                            const pfx_swk *const *gks, size_t n_gks, pfx_ct *const *out, void *stream) {
+    REQUIRE(c && (n == 0 || (a && steps && out)), PFX_EINVAL, "null argument");
+    std::vector<const pfx_swk *> key(n, nullptr);
+    std::vector<uint32_t> gel(n, 1);
+    for (size_t i = 0; i < n; ++i) {
+        pfx_status r = check_ct(c, a[i], "a");
+        if (r) return r;
+        REQUIRE(a[i]->degree == 1, PFX_EINVAL, "rotate needs a degree-1 ciphertext");
+        r = check_out(out[i], a[i]->n_limbs, 1);
+        if (r) return r;
+        gel[i] = rot_element(c, steps[i]);
+        if (gel[i] != 1) {
+            key[i] = find_key(c, gel[i], gks, n_gks);
+            if (!key[i]) return fail(PFX_ENOKEY, "no Galois key for rotation step " + std::to_string(steps[i]));
+        }
+    }
+    {                                        // the last launch reads the inputs while writing outputs
+        std::unordered_set<const double *> ins, outs;
+        for (size_t i = 0; i < n; ++i) ins.insert(a[i]->d);
+        for (size_t i = 0; i < n; ++i) {
+            REQUIRE(!ins.count(out[i]->d), PFX_EINVAL, "batched rotation output aliases an input");
+            REQUIRE(outs.insert(out[i]->d).second, PFX_EINVAL, "batched rotation outputs alias");
+        }
+    }
+    if (n == 0) return PFX_OK;
+    Launch L{c, S(stream)};
+    std::vector<int> order;
+    for (size_t i = 0; i < n; ++i) {
+        if (gel[i] == 1) {
+            pfx_status r = pfx_ct_copy(c, a[i], out[i], stream);
+            if (r) return r;
+        } else {
+            order.push_back((int)i);
+        }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return a[x]->n_limbs > a[y]->n_limbs; });
+    std::vector<uint32_t> lvs(n);
+    std::vector<double> sc(n);
+    for (size_t i = 0; i < n; ++i) {
+        lvs[i] = a[i]->n_limbs;
+        sc[i] = a[i]->scale;
+    }
+    for (size_t s0 = 0; s0 < order.size();) {
+        size_t s1 = s0;
+        while (s1 < order.size() && s1 - s0 < (size_t)kMaxBatch && lvs[order[s1]] == lvs[order[s0]]) ++s1;
+        KsBatch kb;
+        pfx_status r = get_batch_ws(c, L.st, (int)(s1 - s0), kb);
+        if (r) return r;
+        kb.nb = (int)(s1 - s0);
+        kb.mode = KS_GALOIS;
+        for (int e = 0; e < kb.nb; ++e) {
+            const int i = order[s0 + e];
+            KsOperand &op = kb.op[e];
+            op.mode = KS_GALOIS;
+            op.d = a[i]->poly(1);
+            op.base0 = a[i]->poly(0);
+            op.galois = gel[i];
+            kb.keys[e] = key[i]->d_k;
+            kb.out0[e] = out[i]->poly(0);
+            kb.out1[e] = out[i]->poly(1);
+        }
+        ks_run(L, kb, (int)lvs[order[s0]], key[order[s0]]);
+        s0 = s1;
+    }
+    for (int i : order) {
         out[i]->n_limbs = lvs[i];
         out[i]->degree = 1;
         out[i]->scale = sc[i];

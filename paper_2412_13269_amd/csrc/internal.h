@@ -101,6 +101,7 @@ struct MemAccount {
 // workgroups (16 / 8 columns), the rescale's INTT to 256.
 struct PassTuning {
     int row_wg256 = 2048, col_wg256 = 0, widen_wg = 1024, min_col = 16, min_col_special = 8, rs_widen_wg = 256;
+    int ks_fuse = 0;     // threads of the fused ModUp row pass + inner product (0: separate launches)
 };
 const PassTuning &pass_tuning(int logn);   // api.cpp
 
@@ -329,6 +330,7 @@ struct KsBatch {
     bool hoisted = false;             // KS_GALOIS inner product: ext is the unpermuted (hoisted) ModUp
     RepackDesc rp;
     KsOperand op[kMaxBatch];
+    const double *keys[kMaxBatch] = {};   // per-entry key data (all null: the launch's one key)
     double *out0[kMaxBatch] = {}, *out1[kMaxBatch] = {};
     double *dcoef = nullptr, *ext = nullptr, *acc = nullptr, *tmp = nullptr;
     size_t sdc = 0, sext = 0, sacc = 0, stmp = 0;
@@ -393,7 +395,12 @@ pfx_status launch_batch_persistent(pfx_ctx *const *ctxs, const pfx_ct *const *a,
 // Fused key-switching steps (keyswitch.hip).
 void launch_intt_scale(const Launch &L, const KsBatch &kb, int lv);
 void launch_modup_col(const Launch &L, const KsBatch &kb, int lv);
-void launch_intt_special(const Launch &L, const KsBatch &kb, int lv);
+void launch_intt_special(const Launch &L, const KsBatch &kb, int lv, bool col_only = false);
+// The ModUp row pass fused with the inner product (and the first pass of the
+// special limbs' INTT) where the tuning enables it and the batch is not
+// hoisted or a repacking round (keyswitch.hip).
+bool row_inner_ok(const pfx_ctx *c, const KsBatch &kb);
+void launch_row_inner(const Launch &L, const KsBatch &kb, const double *key, int lv);
 void launch_moddown_col(const Launch &L, const KsBatch &kb, int lv);
 void launch_row_moddown(const Launch &L, const KsBatch &kb, int lv);
 void launch_keygen_b(const Launch &L, double *b, const double *a, const double *e, const double *s,

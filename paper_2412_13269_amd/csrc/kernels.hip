@@ -893,6 +893,7 @@ struct InnerArgs {
     int hoisted;   // KS_GALOIS: ext holds the unpermuted decomposition, read through phi_g as well
     const PrimeDev *pr;
     const double *d[kMaxBatch], *d2[kMaxBatch];
+    const double *keys[kMaxBatch];   // k_ks_inner_mk: entry b's own key (rotations by different steps)
     uint32_t g[kMaxBatch];
 };
 
@@ -978,6 +979,60 @@ __global__ __launch_bounds__(256) void k_ks_inner(const InnerArgs a) {
     }
 }
 
+// A batch whose entries have keys of their own (rotations by different
+// steps): entry b = blockIdx.z, each workgroup streams one entry's key and
+// ModUp limbs exactly as the one-entry kernel does (every key residue read
+// once per entry; a larger grid, one launch).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_ks_inner_mk(const InnerArgs a) {
+    const int m = blockIdx.y, b = blockIdx.z;
+    const int logn = a.logn;
+    const size_t N = (size_t)1 << logn;
+    const size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    const int lv = a.lv, E = lv + a.K, alpha = a.alpha;
+    const int beta = (lv + alpha - 1) / alpha;
+    const int pid = m < lv ? m : a.L + (m - lv);
+    const double q = a.pr[pid].q, qi = a.pr[pid].qinv;
+    const size_t kstride = (size_t)(a.L + a.K) * N;
+    const double *k0 = a.keys[b] + ((size_t)pid << logn) + c;
+    const double *ext = a.ext + b * a.sext;
+    const size_t lm = (size_t)m << logn;
+    double a0 = 0.0, a1 = 0.0;
+    for (int jb = 0; jb < beta; jb += 4) {
+        double x[4], w0[4], w1[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int j = jb + t;
+            if (j < beta) {
+                const int j0 = j * alpha;
+                const int sz = min(alpha, lv - j0);
+                const bool own = m >= j0 && m < j0 + sz;
+                const int tt = m < j0 ? m : m - sz;
+                w0[t] = __builtin_nontemporal_load(k0 + (size_t)(2 * j) * kstride);
+                w1[t] = __builtin_nontemporal_load(k0 + (size_t)(2 * j + 1) * kstride);
+                if (own) {
+                    if (MODE == KS_GALOIS) x[t] = a.d[b][lm + galois_src((uint32_t)c, logn, a.g[b])];
+                    else x[t] = a.d[b][lm + c];
+                } else {
+                    x[t] = __builtin_nontemporal_load(ext + ((size_t)j * E + tt) * N + c);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (jb + t < beta) {
+                a0 += mmul(x[t], w0[t], q, qi);
+                a1 += mmul(x[t], w1[t], q, qi);
+            }
+        }
+        a0 = mred(a0, q, qi);  // four products in [0, q) on a reduced sum: below 5q
+        a1 = mred(a1, q, qi);
+    }
+    a.acc[b * a.sacc + lm + c] = mred(a0, q, qi);
+    a.acc[b * a.sacc + ((size_t)(E + m) << logn) + c] = mred(a1, q, qi);
+}
+
 void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int lv) {
     pfx_ctx *ctx = L.ctx;
     InnerArgs a;
@@ -1000,7 +1055,9 @@ void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int 
         a.d[b] = on ? (kb.mode == KS_PRODUCT ? o.a1 : o.d) : nullptr;
         a.d2[b] = on && kb.mode == KS_PRODUCT ? o.b1 : nullptr;
         a.g[b] = on ? o.galois : 0;
+        a.keys[b] = on ? kb.keys[b] : nullptr;
     }
+    const bool mk = kb.keys[0] != nullptr;
     dim3 grid((ctx->N + 255) / 256, lv + ctx->K);
     hipEvent_t ev;
     prof_begin(L, "ks_inner", &ev);
@@ -1010,7 +1067,11 @@ void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int 
         else if (kb.mode == KS_PRODUCT) k_ks_inner<KS_PRODUCT, NB_><<<grid, 256, 0, L.st>>>(a);   \
         else k_ks_inner<KS_PLAIN, NB_><<<grid, 256, 0, L.st>>>(a);                                \
     } while (0)
-    if (kb.nb <= 1) PFX_KS_INNER(1);
+    if (mk) {
+        grid.z = (unsigned)kb.nb;
+        if (kb.mode == KS_GALOIS) k_ks_inner_mk<KS_GALOIS><<<grid, 256, 0, L.st>>>(a);
+        else k_ks_inner_mk<KS_PLAIN><<<grid, 256, 0, L.st>>>(a);
+    } else if (kb.nb <= 1) PFX_KS_INNER(1);
     else if (kb.nb <= 2) PFX_KS_INNER(2);
     else if (kb.nb <= 4) PFX_KS_INNER(4);
     else PFX_KS_INNER(kMaxBatch);
@@ -1022,7 +1083,7 @@ void launch_ks_inner(const Launch &L, const KsBatch &kb, const double *key, int 
     // launch sequence, not an operand of the key switch, so its re-read counts
     // as traffic above the algorithmic bytes.
     const int beta = (lv + ctx->alpha - 1) / ctx->alpha;
-    prof_end(L, "ks_inner", ev, 8.0 * (double)ctx->N * (lv + ctx->K) * (2.0 * kb.nb + 2.0 * beta));
+    prof_end(L, "ks_inner", ev, 8.0 * (double)ctx->N * (lv + ctx->K) * (2.0 * kb.nb + 2.0 * beta * (mk ? kb.nb : 1)));
 }
 
 // ============================================================== keys, encryption

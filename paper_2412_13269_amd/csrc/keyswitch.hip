@@ -89,6 +89,104 @@ __global__ __launch_bounds__(TH) void k_intt_special(const KsArgs a, double *__r
     intt_special_body<S, ROW, TH>(a, a.C, a.tiles, bi, id, acc, lds);
 }
 
+// ---- steps 3 and 4a fused (KS_PLAIN, KS_GALOIS, KS_PRODUCT; not hoisted):
+// one workgroup per (target limb m, row tile, batch entry), entries fastest so
+// that the entries of a batch read one key tile from the same XCD's L2.  For
+// every digit j it takes the digit's limb m in the NTT domain, either the
+// forward row pass of the column-pass output in ext (left signed in
+// [-q/2, q/2]) or, for the digit's own primes, the operand itself (d, phi_g(d)
+// through the permutation, or a1 b1), and adds its products with the two key
+// residues to accumulators held in registers (signed lazy products,
+// |r| <= 0.875 q, reduced every fourth digit: below 4 q < 2^53).  Only the
+// accumulators reach HBM: canonical for the q limbs; a special-prime limb
+// first runs the first (row) pass of its inverse transform, whose input is the
+// accumulator in the pass's own element order, so step 4's row launch is not
+// needed.  The ModUp limbs and d are read once, the key once per launch.
+template <int S, int MODE, int TH>
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(2))) void k_row_inner(const KsArgs a, const double *__restrict__ ext,
+                                                  const double *__restrict__ key, double *__restrict__ acc) {
+    __shared__ double lds[NttTile<TH>::lds];
+    const int gid = xcd_slot(a.n);
+    if (gid >= a.n) return;
+    const int bi = gid % a.nb, id = gid / a.nb;
+    const int tile = id % a.tiles, m = id / a.tiles;
+    const KsEntry &en = a.op[bi];
+    const int lv = a.lv, E = a.E;
+    const int pid = m < lv ? m : a.L + (m - lv);
+    const PrimeDev &P = a.primes[pid];
+    const double q = P.q, qi = P.qinv;
+    const int logn = a.logn;
+    const size_t N = (size_t)1 << logn;
+    const size_t kstride = (size_t)(a.L + a.K) * N;
+    const int C = a.C, g0 = (tile * C) << S, tot = C << S;
+    const double *kq = (en.key ? en.key : key) + ((size_t)pid << logn);
+    const size_t lm = (size_t)m << logn;
+    ext += bi * a.sext;
+    acc += bi * a.sacc;
+    double s0[kSlots], s1[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) s0[k] = s1[k] = 0.0;
+    for (int j = 0; j < a.beta; ++j) {
+        const int j0 = j * a.alpha, sz = min(a.alpha, lv - j0);
+        const double *w0 = kq + (size_t)(2 * j) * kstride, *w1 = w0 + kstride;
+        if (m >= j0 && m < j0 + sz) {
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) {
+                const int e = threadIdx.x + k * TH;
+                if (e < tot) {
+                    const unsigned c = (unsigned)(g0 + e);
+                    double x;
+                    if constexpr (MODE == KS_GALOIS) x = en.d[lm + galois_src(c, logn, en.galois)];
+                    else if constexpr (MODE == KS_PRODUCT) x = mmul(en.a1[lm + c], en.b1[lm + c], q, qi);
+                    else x = en.d[lm + c];
+                    s0[k] += mmul_lazy(x, __builtin_nontemporal_load(w0 + c), q, qi);
+                    s1[k] += mmul_lazy(x, __builtin_nontemporal_load(w1 + c), q, qi);
+                }
+            }
+        } else {
+            const double *src = ext + ((size_t)j * E + (m < j0 ? m : m - sz)) * N;
+            auto ld = [&](int g, int) { return __builtin_nontemporal_load(src + (unsigned)g); };
+            auto st = [&](int g, double v, int k) {
+                s0[k] += mmul_lazy(v, __builtin_nontemporal_load(w0 + (unsigned)g), q, qi);
+                s1[k] += mmul_lazy(v, __builtin_nontemporal_load(w1 + (unsigned)g), q, qi);
+            };
+            __syncthreads();                 // the previous pass's last LDS reads are done
+            row_pass<S, false, TH, false>(P, logn, C, tile * C, lds, ld, st);
+        }
+        if ((j & 3) == 3) {
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) {
+                s0[k] = mred_signed(s0[k], q, qi);
+                s1[k] = mred_signed(s1[k], q, qi);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+        s0[k] = mred_signed(s0[k], q, qi);
+        s1[k] = mred_signed(s1[k], q, qi);
+    }
+    if (m < lv) {
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const int e = threadIdx.x + k * TH;
+            if (e < tot) {
+                acc[lm + g0 + e] = mcanon(s0[k], q);
+                acc[((size_t)(E + m) << logn) + g0 + e] = mcanon(s1[k], q);
+            }
+        }
+    } else {
+        // the first pass of the special limb's inverse transform, per polynomial
+        double *x0 = acc + lm, *x1 = acc + ((size_t)(E + m) << logn);
+        __syncthreads();
+        row_pass<S, true, TH>(P, logn, C, tile * C, lds, [&](int, int k) { return s0[k]; },
+                              [&](int g, double v, int) { x0[(unsigned)g] = v; });
+        __syncthreads();
+        row_pass<S, true, TH>(P, logn, C, tile * C, lds, [&](int, int k) { return s1[k]; },
+                              [&](int g, double v, int) { x1[(unsigned)g] = v; });
+    }
+}
+
 // ---- step 3 for KS_REPACK: the inner product of one entry per blockIdx.z (a
 // batch of any size); the entry's own digit reads phi_g(c_j - X^t c_(j+t)) of
 // the round's input array where the other entries' kernel reads d.
@@ -258,7 +356,7 @@ static KsArgs ks_args(pfx_ctx *c, int lv, const KsBatch &kb) {
         KsEntry &e = a.op[b];
         if (b < kb.nb && kb.mode != KS_REPACK) {
             const KsOperand &o = kb.op[b];
-            e = KsEntry{o.d, o.base0, o.base1, o.a0, o.a1, o.b0, o.b1, kb.out0[b], kb.out1[b], o.galois};
+            e = KsEntry{o.d, o.base0, o.base1, o.a0, o.a1, o.b0, o.b1, kb.out0[b], kb.out1[b], o.galois, kb.keys[b]};
         } else {
             e = KsEntry{};
         }
@@ -323,7 +421,34 @@ void launch_modup_col(const Launch &L, const KsBatch &kb, int lv) {
     prof_end(L, "ks_modup_col", ev, 8.0 * (double)L.ctx->N * a.beta * a.E * kb.nb);
 }
 
-void launch_intt_special(const Launch &L, const KsBatch &kb, int lv) {
+bool row_inner_ok(const pfx_ctx *c, const KsBatch &kb) {
+    return pass_tuning(c->logn).ks_fuse != 0 && !kb.hoisted &&
+           (kb.mode == KS_PLAIN || kb.mode == KS_GALOIS || kb.mode == KS_PRODUCT);
+}
+
+void launch_row_inner(const Launch &L, const KsBatch &kb, const double *key, int lv) {
+    KsArgs a = ks_args(L.ctx, lv, kb);
+    const int th = pass_tuning(a.logn).ks_fuse == 256 ? 256 : 128;
+    const PassShape pr = row_shape(a.logn, th * kSlots);
+    a.C = pr.C;
+    a.tiles = pr.tiles;
+    a.per = a.E * a.tiles;
+    a.n = a.nb * a.per;
+    hipEvent_t ev;
+    prof_begin(L, "ks_row_inner", &ev);
+    PFX_SWITCH_TH(th, PFX_SWITCH_KS(kb.mode, PFX_SWITCH_S(pr.S, (k_row_inner<SS, MD == KS_REPACK ? KS_PLAIN : MD, TH>
+                                                                 <<<xcd_grid(a.n), TH, 0, L.st>>>(a, kb.ext, key, kb.acc)))));
+    HIP_LAUNCH_CHECK_KS();
+    // the ModUp limbs and d (a1 and b1 for a product) read, the key read, the
+    // accumulators written
+    const double own = kb.mode == KS_PRODUCT ? 2.0 * lv : (double)lv;
+    const double keys = kb.keys[0] ? kb.nb : 1.0;
+    prof_end(L, "ks_row_inner", ev,
+             8.0 * (double)L.ctx->N * kb.nb * ((a.beta * a.E - lv) + own + 2.0 * a.E) +
+                 16.0 * (double)L.ctx->N * a.beta * a.E * keys);
+}
+
+void launch_intt_special(const Launch &L, const KsBatch &kb, int lv, bool col_only) {
     KsArgs a = ks_args(L.ctx, lv, kb);
     double *acc = kb.acc;
     const int limbs = kb.nb * 2 * a.K;
@@ -332,13 +457,15 @@ void launch_intt_special(const Launch &L, const KsBatch &kb, int lv) {
     PassShape pr = row_shape(a.logn, th * kSlots), pc = col_shape(a.logn, tc * kSlots);
     widen_grid(pr, pc, limbs, a.logn);
     hipEvent_t ev;
-    a.C = pr.C;
-    a.tiles = pr.tiles;
-    set_blocks(a, 2 * a.K * a.tiles);
-    prof_begin(L, "ks_intt_special_row", &ev);
-    PFX_SWITCH_TH(th, PFX_SWITCH_S(pr.S, (k_intt_special<SS, true, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, acc))));
-    HIP_LAUNCH_CHECK_KS();
-    prof_end(L, "ks_intt_special_row", ev, 16.0 * (double)L.ctx->N * limbs);
+    if (!col_only) {
+        a.C = pr.C;
+        a.tiles = pr.tiles;
+        set_blocks(a, 2 * a.K * a.tiles);
+        prof_begin(L, "ks_intt_special_row", &ev);
+        PFX_SWITCH_TH(th, PFX_SWITCH_S(pr.S, (k_intt_special<SS, true, TH><<<xcd_grid(a.n), TH, 0, L.st>>>(a, acc))));
+        HIP_LAUNCH_CHECK_KS();
+        prof_end(L, "ks_intt_special_row", ev, 16.0 * (double)L.ctx->N * limbs);
+    }
     a.C = pc.C;
     a.tiles = pc.tiles;
     set_blocks(a, 2 * a.K * a.tiles);

@@ -18,6 +18,7 @@ struct KsEntry {
     const double *d, *base0, *base1, *a0, *a1, *b0, *b1;
     double *out0, *out1;
     uint32_t galois;
+    const double *key;   // the entry's own key data, or null (the launch's key)
 };
 
 // Kernel arguments.  A launch covers nb batch entries (same level, key and

@@ -332,13 +332,14 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
 }
 
 // Row pass: global stages [logn - S, logn) on the tile of blocks [cbase, cbase + C).
-// Inputs |x| <= q.  Forward: the last pass, outputs in [0, q).  Inverse: the
-// first pass, outputs in [-q/2, q/2] for the column pass.
+// Inputs |x| <= q.  Forward: the last pass, outputs in [0, q) (in [-q/2, q/2]
+// with CANON = false, for a consumer that reduces anyway).  Inverse: the first
+// pass, outputs in [-q/2, q/2] for the column pass.
 // The tile is C * 2^S contiguous doubles; the side of the pass that would own
 // 2^R2 consecutive doubles per thread (forward output, inverse input) goes
 // through LDS in coalesced order instead: element e of the tile belongs to
 // thread e mod TH as slot e / TH.
-template <int S, bool INV, int TH, class Load, class Store>
+template <int S, bool INV, int TH, bool CANON = true, class Load, class Store>
 __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int cbase, double *lds, Load &&load,
                                          Store &&store) {
     constexpr int R = 1 << S;
@@ -396,7 +397,10 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
             const int e = threadIdx.x + k * TH;
-            if (e < tot) store(base + e, mcanon(lds[lidx(e >> S, e & (R - 1))], q), k);
+            if (e < tot) {
+                const double x = lds[lidx(e >> S, e & (R - 1))];
+                store(base + e, CANON ? mcanon(x, q) : x, k);
+            }
         }
     } else {
         double2 W1[E1 - 1];

@@ -41,7 +41,7 @@ class pfx_params(ctypes.Structure):
 class pfx_pass_tuning(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("row_wg256", ctypes.c_uint32), ("col_wg256", ctypes.c_uint32),
                 ("widen_wg", ctypes.c_uint32), ("min_col", ctypes.c_uint32), ("min_col_special", ctypes.c_uint32),
-                ("rs_widen_wg", ctypes.c_uint32)]
+                ("rs_widen_wg", ctypes.c_uint32), ("ks_fuse", ctypes.c_uint32)]
 
 
 class pfx_op(ctypes.Structure):
@@ -150,6 +150,7 @@ _SIGS = {
     "pfx_key_switch": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_apply_galois": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "pfx_apply_galois_batch": (_i32, [_vp, _VPP, _sz, _vp, _VPP, _vp]),
+    "pfx_rotate_batch": (_i32, [_vp, _VPP, _vp, _sz, _VPP, _sz, _VPP, _vp]),
     "pfx_mul_monomial": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "pfx_mul_inv_n": (_i32, [_vp, _vp, _vp, _vp]),
     "pfx_repack": (_i32, [_vp, _VPP, _sz, _VPP, _sz, _VPP, _vp]),
@@ -584,6 +585,16 @@ def pfx_apply_galois_batch(ctx, a, gk, outs, stream=None):
     _check(_lib.pfx_apply_galois_batch(ctx, arr(a), n, gk, arr(outs), _stream(stream)))
 
 
+def pfx_rotate_batch(ctx, a, steps, gks, outs, stream=None):
+    """outs[i] = rotate(a[i], steps[i]) with the key for each step among gks."""
+    n = len(a)
+    assert len(steps) == n and len(outs) == n
+    arr = lambda xs: (ctypes.c_void_p * max(1, len(xs)))(*xs)
+    st = np.ascontiguousarray(steps, dtype=np.int32)
+    _check(_lib.pfx_rotate_batch(ctx, arr(a), st.ctypes.data if n else None, n, arr(gks), len(gks), arr(outs),
+                                 _stream(stream)))
+
+
 def pfx_apply_galois_hoisted(ctx, a, gks, outs, stream=None):
     G = (ctypes.c_void_p * max(1, len(gks)))(*gks)
     O = (ctypes.c_void_p * max(1, len(outs)))(*outs)
@@ -714,7 +725,7 @@ def pfx_ctx_mem(ctx):
     return a.value, b.value
 
 
-TUNING_FIELDS = ("row_wg256", "col_wg256", "widen_wg", "min_col", "min_col_special", "rs_widen_wg")
+TUNING_FIELDS = ("row_wg256", "col_wg256", "widen_wg", "min_col", "min_col_special", "rs_widen_wg", "ks_fuse")
 
 
 def pfx_tuning_set(log_n: int, **fields):

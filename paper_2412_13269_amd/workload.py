@@ -82,22 +82,37 @@ class KsWorkload:
             self.pts.append(pt)
         self.prod = X.pfx_ct_create(ctx, L, 1)
         self.rot = X.pfx_ct_create(ctx, L, 1)
+        self.rots = [X.pfx_ct_create(ctx, L, 1) for _ in ROT_STEPS]     # one output per rotation
         self.words = I.uniform_residues(q, N, 7, lead=(2,))          # one ciphertext: 2 x 24 limbs
         self.dbuf = X.pfx_dev_alloc(ctx, self.words.nbytes)
         X.pfx_memcpy_htod(ctx, self.dbuf, self.words, st)
 
     def step(self):
+        """The 15 rotations (independent key switches, each with its own key
+        and output) run as batched key switches (pfx_rotate_batch)."""
         X, ctx, st, L = self.X, self.ctx, self.st, self.L
         X.pfx_ntt(ctx, self.dbuf, 0, L, 2, False, st)
         X.pfx_ntt(ctx, self.dbuf, 0, L, 2, True, st)
         X.pfx_mul_relin(ctx, self.cts[0], self.cts[1], self.rlk, self.prod, st)
         X.pfx_rescale(ctx, self.prod, self.prod, st)
-        for r in ROT_STEPS:
-            X.pfx_rotate(ctx, self.cts[0], r, self.gks, self.rot, st)
+        self.rotations()
+
+    def step_one_by_one(self):
+        """The same step with every rotation its own key switch launch sequence."""
+        X, ctx, st, L = self.X, self.ctx, self.st, self.L
+        X.pfx_ntt(ctx, self.dbuf, 0, L, 2, False, st)
+        X.pfx_ntt(ctx, self.dbuf, 0, L, 2, True, st)
+        X.pfx_mul_relin(ctx, self.cts[0], self.cts[1], self.rlk, self.prod, st)
+        X.pfx_rescale(ctx, self.prod, self.prod, st)
+        for r, o in zip(ROT_STEPS, self.rots):
+            X.pfx_rotate(ctx, self.cts[0], r, self.gks, o, st)
 
     def rotations(self):
-        for r in ROT_STEPS:
-            self.X.pfx_rotate(self.ctx, self.cts[0], r, self.gks, self.rot, self.st)
+        self.X.pfx_rotate_batch(self.ctx, [self.cts[0]] * len(ROT_STEPS), ROT_STEPS, self.gks, self.rots, self.st)
+
+    def rotations_one_by_one(self):
+        for r, o in zip(ROT_STEPS, self.rots):
+            self.X.pfx_rotate(self.ctx, self.cts[0], r, self.gks, o, self.st)
 
     def calibrate_copy(self, reps=5):
         """Two k_u64_to_f64 launches per import, 24 limbs (12 MiB in, 12 MiB out) each."""
@@ -111,7 +126,7 @@ class KsWorkload:
 
     def close(self):
         X = self.X
-        for h in self.cts + self.pts + [self.prod, self.rot]:
+        for h in self.cts + self.pts + [self.prod, self.rot] + self.rots:
             X.pfx_ct_destroy(h)
         for k in self.gks + [self.rlk]:
             X.pfx_swk_destroy(k)
@@ -340,7 +355,10 @@ def main():
     ap.add_argument("--half-bts", action="store_true")
     ap.add_argument("--graph", action="store_true")
     ap.add_argument("--rotations-only", action="store_true",
-                    help="each step is the 15 rotations alone (after the copy calibration, if asked)")
+                    help="each step is the 15 rotations alone, one key switch launch sequence each "
+                         "(after the copy calibration, if asked)")
+    ap.add_argument("--one-by-one", action="store_true",
+                    help="the step with its rotations one at a time instead of batched")
     args = ap.parse_args()
     if args.half_bts:
         from . import pfx as X
@@ -384,7 +402,7 @@ def main():
     if args.calibrate:
         w.calibrate_copy()
         print("copy calibration done", flush=True)
-    step = w.rotations if args.rotations_only else w.step
+    step = w.rotations_one_by_one if args.rotations_only else (w.step_one_by_one if args.one_by_one else w.step)
     step()
     w.sync()
     for _ in range(args.steps):

@@ -1,0 +1,106 @@
+"""Batched rotations with one key per entry (pfx_rotate_batch) against
+pfx_rotate one at a time: 15 steps over ciphertexts at mixed levels at
+N = 2^16, L = 24 (two and three batches), a step of zero, the argument
+checks, and the oracle's words at N = 2^12."""
+import numpy as np
+import pytest
+
+from paper_2412_13269_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+QB, PB, ALPHA, ML = [50] + [45] * 23, [50] * 4, 4, 17
+STEPS = [1 << k for k in range(15)]
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_2412_13269_amd import pfx
+    return pfx
+
+
+def test_rotate_batch_equals_single_rotations(X):
+    logn = 16
+    N = 1 << logn
+    ctx = X.pfx_ctx_create(X.make_params(logn, QB, PB, ALPHA, ML), 0)
+    st = X.pfx_stream_create(ctx)
+    seed = b"rotate-batch".ljust(32, b".")
+    sk = X.pfx_keygen_secret(ctx, seed, 192)
+    gks = X.pfx_keygen_galois(ctx, sk, STEPS + [-3], False, seed)
+    q, _, _ = X.pfx_ctx_moduli(ctx, len(QB), len(PB))
+    handles = []
+    try:
+        srcs = []
+        for k, lv in enumerate((24, 24, 13, 5)):
+            h = X.pfx_ct_create(ctx, len(QB), 1)
+            X.pfx_ct_import(ctx, I.uniform_residues(q[:lv], N, 700 + k, lead=(2,)), 2.0 ** 45, h, st)
+            srcs.append(h)
+        handles += srcs
+        # every step on the first ciphertext (two batches of the full level),
+        # then mixed levels and steps, a negative step and a zero step
+        cases = [(srcs[0], s) for s in STEPS] + [(srcs[1], 1), (srcs[2], 8), (srcs[3], 1 << 14),
+                                                  (srcs[2], -3), (srcs[1], 0)]
+        outs = [X.pfx_ct_create(ctx, len(QB), 1) for _ in cases]
+        refs = [X.pfx_ct_create(ctx, len(QB), 1) for _ in cases]
+        handles += outs + refs
+        X.pfx_rotate_batch(ctx, [c for c, _ in cases], [s for _, s in cases], gks, outs, st)
+        for (c, s), r in zip(cases, refs):
+            X.pfx_rotate(ctx, c, s, gks, r, st)
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            assert np.array_equal(X.pfx_ct_export(ctx, o, N, st), X.pfx_ct_export(ctx, r, N, st)), cases[i][1]
+            assert X.pfx_ct_info(o).n_limbs == X.pfx_ct_info(r).n_limbs
+        # argument checks
+        with pytest.raises(X.PfxError) as e:
+            X.pfx_rotate_batch(ctx, [srcs[0]], [1], gks, [srcs[0]], st)
+        assert e.value.status == X.PFX_EINVAL
+        with pytest.raises(X.PfxError) as e:
+            X.pfx_rotate_batch(ctx, [srcs[0], srcs[1]], [1, 2], gks, [outs[0], outs[0]], st)
+        assert e.value.status == X.PFX_EINVAL
+        with pytest.raises(X.PfxError) as e:
+            X.pfx_rotate_batch(ctx, [srcs[0]], [7], gks, [outs[0]], st)
+        assert e.value.status == X.PFX_ENOKEY
+        X.pfx_sync(ctx, st)
+    finally:
+        for h in handles:
+            X.pfx_ct_destroy(h)
+        for k in gks:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(sk)
+        X.pfx_stream_destroy(ctx, st)
+        X.pfx_ctx_destroy(ctx)
+
+
+def test_rotate_batch_matches_oracle(X):
+    from oracle import ckks as O
+    logn, qb, pb, alpha = 12, [50] + [45] * 5, [50] * 2, 2
+    N = 1 << logn
+    P = O.Params(logn, qb, pb, alpha=alpha, mod_log2=ML)
+    ctx = X.pfx_ctx_create(X.make_params(logn, qb, pb, alpha, ML), 0)
+    try:
+        s = I.ternary_secret(N, 64, 41)
+        sk = X.pfx_sk_create(ctx, s)
+        ext = P.ext_mods(P.L)
+        steps = [1, 2, 7, -1]
+        okeys, gks = {}, []
+        for k, step in enumerate(steps):
+            g = O.galois_element(P, step)
+            ka, ke = I.uniform_residues(ext, N, 50 + 2 * k, lead=(P.beta,)), I.gaussian_error((P.beta, N), 51 + 2 * k)
+            okeys[g] = O.galois_key(P, s, g, ka, ke)
+            gks.append(X.pfx_swk_create(ctx, sk, g, ka, ke))
+        words = [I.uniform_residues(P.q, N, 60 + k, lead=(2,)) for k in range(2)]
+        a = [X.pfx_ct_create(ctx, len(qb), 1) for _ in words]
+        for h, w in zip(a, words):
+            X.pfx_ct_import(ctx, w, 2.0 ** 45, h)
+        ins = [a[k % 2] for k in range(len(steps))]
+        outs = [X.pfx_ct_create(ctx, len(qb), 1) for _ in steps]
+        X.pfx_rotate_batch(ctx, ins, steps, gks, outs)
+        for k, (step, o) in enumerate(zip(steps, outs)):
+            want = O.rotate(P, O.Ct(words[k % 2], 2.0 ** 45), step, okeys)
+            assert np.array_equal(X.pfx_ct_export(ctx, o, N), want.c), step
+        for h in a + outs:
+            X.pfx_ct_destroy(h)
+        for k in gks:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(sk)
+    finally:
+        X.pfx_ctx_destroy(ctx)
