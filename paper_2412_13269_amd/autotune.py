@@ -30,13 +30,16 @@ OUT = os.path.join(HERE, "tuning.txt")
 QB, PB, ALPHA, ML = [50] + [45] * 23, [50] * 4, 4, 17
 LEVELS = (24, 13, 4)
 DEFAULT = {"row_wg256": 2048, "col_wg256": 0, "widen_wg": 1024, "min_col": 16, "min_col_special": 8,
-           "rs_widen_wg": 256}
+           "rs_widen_wg": 256, "ks_fuse": 0, "ks_batch": 8}
 CANDIDATES = {"row_wg256": [0, 512, 1024, 2048, 4096, 8192, 1 << 30],
               "col_wg256": [0, 2048, 4096, 1 << 30],
               "widen_wg": [256, 512, 1024, 2048],
               "min_col": [8, 16, 32],
               "min_col_special": [4, 8, 16],
-              "rs_widen_wg": [128, 256, 512, 1024]}
+              "rs_widen_wg": [128, 256, 512, 1024],
+              "ks_fuse": [0, 128],
+              "ks_batch": [2, 3, 4, 5, 8]}
+BATCH_STEPS = list(range(1, 9))     # eight rotations, each with its own key
 
 
 class Bench:
@@ -49,9 +52,9 @@ class Bench:
         seed = bytes([logn]) * 32
         self.sk = X.pfx_keygen_secret(self.ctx, seed, 192 if logn >= 13 else 64)
         self.rlk = X.pfx_keygen_relin(self.ctx, self.sk, seed)
-        self.gks = X.pfx_keygen_galois(self.ctx, self.sk, [1], False, seed)
+        self.gks = X.pfx_keygen_galois(self.ctx, self.sk, BATCH_STEPS, False, seed)
         q, _, _ = X.pfx_ctx_moduli(self.ctx, len(QB), len(PB))
-        self.cts, self.outs = {}, {}
+        self.cts, self.outs, self.routs = {}, {}, {}
         for lv in LEVELS:
             pair = []
             for k in range(2):
@@ -61,6 +64,7 @@ class Bench:
                 pair.append(h)
             self.cts[lv] = pair
             self.outs[lv] = X.pfx_ct_create(self.ctx, lv, 1)
+            self.routs[lv] = [X.pfx_ct_create(self.ctx, lv, 1) for _ in BATCH_STEPS]
         self.words = X.pfx_dev_alloc(self.ctx, 2 * len(QB) * self.N * 8)
         X.pfx_memcpy_htod(self.ctx, self.words, I.uniform_residues(q, self.N, 7999, lead=(2,)))
         self.ev0, self.ev1 = X.pfx_event_create(self.ctx), X.pfx_event_create(self.ctx)
@@ -86,6 +90,8 @@ class Bench:
                 X.pfx_rescale(c, o, o, st)
             tot += self.time(mrr, reps)
             tot += self.time(lambda: X.pfx_rotate(c, a, 1, self.gks, o, st), reps)
+            tot += self.time(lambda: X.pfx_rotate_batch(c, [a] * len(BATCH_STEPS), BATCH_STEPS, self.gks,
+                                                        self.routs[lv], st), reps) / len(BATCH_STEPS)
             tot += self.time(lambda: X.pfx_ntt(c, self.words, 0, lv, 2, False, st), reps)
             tot += self.time(lambda: X.pfx_ntt(c, self.words, 0, lv, 2, True, st), reps)
         return tot
@@ -94,7 +100,7 @@ class Bench:
         for pair in self.cts.values():
             for h in pair:
                 X.pfx_ct_destroy(h)
-        for h in self.outs.values():
+        for h in list(self.outs.values()) + [h for hs in self.routs.values() for h in hs]:
             X.pfx_ct_destroy(h)
         for k in [self.rlk] + self.gks:
             X.pfx_swk_destroy(k)
@@ -150,13 +156,14 @@ def main(argv=None) -> int:
              f"--reps {args.reps}",
              "# objective: HMult + relin + rescale, a rotation, forward and inverse NTT of a ciphertext, at",
              "# 24, 13 and 4 limbs of the 24 + 4 prime chain (sum of median device times)",
-             "# log_n row_wg256 col_wg256 widen_wg min_col min_col_special rs_widen_wg   (tuned ms / default ms)"]
+             "# plus an eighth of eight batched rotations (pfx_rotate_batch)",
+             "# log_n row_wg256 col_wg256 widen_wg min_col min_col_special rs_widen_wg ks_fuse ks_batch"
+             "   (tuned ms / default ms)"]
     t0 = time.time()
     for ln in args.lognums:
         r = tune(ln, args.reps, args.min_gain, log=lambda *a: print(*a, flush=True))
         c = r["config"]
-        lines.append(f"{ln} {c['row_wg256']} {c['col_wg256']} {c['widen_wg']} {c['min_col']} "
-                     f"{c['min_col_special']} {c['rs_widen_wg']}")
+        lines.append(f"{ln} " + " ".join(str(c[f]) for f in X.TUNING_FIELDS))
         lines.append(f"#   {r['tuned_ms']:.3f} / {r['default_ms']:.3f}")
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")

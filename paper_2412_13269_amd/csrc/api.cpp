@@ -346,6 +346,19 @@ void ks_moddown(const Launch &L, const KsBatch &kb, int lv) {
     launch_row_moddown(L, kb, lv);
 }
 
+// End of the key-switch batch that starts at order[s0]: entries of one
+// level; a run of equal levels is split into batches of at most the tuned
+// bound (ks_batch, at most kMaxBatch) of sizes as equal as possible.
+template <class Lv>
+size_t ks_batch_end(const pfx_ctx *c, const int *order, size_t n, const Lv &lvs, size_t s0) {
+    size_t e = s0;
+    while (e < n && lvs[order[e]] == lvs[order[s0]]) ++e;
+    const size_t run = e - s0;
+    const size_t bound = (size_t)std::max(1, std::min(kMaxBatch, pass_tuning(c->logn).ks_batch));
+    const size_t nbat = (run + bound - 1) / bound;
+    return s0 + (run + nbat - 1) / nbat;
+}
+
 void ks_run(const Launch &L, const KsBatch &kb, int lv, const pfx_swk *key) {
     if (row_inner_ok(L.ctx, kb)) {
         // the ModUp row pass, the inner product and the special limbs' first
@@ -981,6 +994,7 @@ pfx_status pfx_tuning_set(const pfx_pass_tuning *t) {
                 !(t->min_col_special & (t->min_col_special - 1)),
             PFX_EINVAL, "column widths must be powers of two");
     REQUIRE(t->ks_fuse == 0 || t->ks_fuse == 128 || t->ks_fuse == 256, PFX_EINVAL, "ks_fuse must be 0, 128 or 256");
+    REQUIRE(t->ks_batch >= 1 && t->ks_batch <= (uint32_t)kMaxBatch, PFX_EINVAL, "ks_batch must be in [1, 8]");
     std::lock_guard<std::mutex> g(g_tune_mu);
     PassTuning &x = g_tune[t->log_n];
     x.row_wg256 = (int)std::min<uint32_t>(t->row_wg256, 1u << 30);
@@ -990,6 +1004,7 @@ pfx_status pfx_tuning_set(const pfx_pass_tuning *t) {
     x.min_col_special = (int)t->min_col_special;
     x.rs_widen_wg = (int)std::min<uint32_t>(t->rs_widen_wg, 1u << 30);
     x.ks_fuse = (int)t->ks_fuse;
+    x.ks_batch = (int)t->ks_batch;
     return PFX_OK;
 }
 
@@ -999,7 +1014,7 @@ pfx_status pfx_tuning_get(uint32_t log_n, pfx_pass_tuning *t) {
     const PassTuning &x = g_tune[log_n];
     *t = pfx_pass_tuning{log_n, (uint32_t)x.row_wg256, (uint32_t)x.col_wg256, (uint32_t)x.widen_wg,
                          (uint32_t)x.min_col, (uint32_t)x.min_col_special, (uint32_t)x.rs_widen_wg,
-                         (uint32_t)x.ks_fuse};
+                         (uint32_t)x.ks_fuse, (uint32_t)x.ks_batch};
     return PFX_OK;
 }
 
@@ -1019,10 +1034,12 @@ pfx_status pfx_tuning_load(const char *path) {
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
         pfx_pass_tuning t;
-        t.ks_fuse = (uint32_t)PassTuning{}.ks_fuse;      // a 7-field line keeps the default
-        const int got = std::sscanf(line, "%u %u %u %u %u %u %u %u", &t.log_n, &t.row_wg256, &t.col_wg256,
-                                    &t.widen_wg, &t.min_col, &t.min_col_special, &t.rs_widen_wg, &t.ks_fuse);
-        if (got != 7 && got != 8) {
+        t.ks_fuse = (uint32_t)PassTuning{}.ks_fuse;      // fields left out keep their defaults
+        t.ks_batch = (uint32_t)PassTuning{}.ks_batch;
+        const int got = std::sscanf(line, "%u %u %u %u %u %u %u %u %u", &t.log_n, &t.row_wg256, &t.col_wg256,
+                                    &t.widen_wg, &t.min_col, &t.min_col_special, &t.rs_widen_wg, &t.ks_fuse,
+                                    &t.ks_batch);
+        if (got < 7) {
             r = fail(PFX_EINVAL, std::string("malformed tuning line in ") + path);
             break;
         }
@@ -1804,8 +1821,7 @@ pfx_status pfx_mul_relin_batch(pfx_ctx *c, const pfx_ct *const *a, const pfx_ct 
     for (size_t i = 0; i < n; ++i) order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return lvs[x] > lvs[y]; });
     for (size_t s0 = 0; s0 < n;) {
-        size_t s1 = s0;
-        while (s1 < n && s1 - s0 < (size_t)kMaxBatch && lvs[order[s1]] == lvs[order[s0]]) ++s1;
+        const size_t s1 = ks_batch_end(c, order.data(), n, lvs, s0);
         r = mul_relin_group(c, L, a, b, out, &order[s0], (int)(s1 - s0), (int)lvs[order[s0]], rlk);
         if (r) return r;
         s0 = s1;
@@ -1852,8 +1868,7 @@ pfx_status pfx_relinearize_batch(pfx_ctx *c, const pfx_ct *const *a, size_t n, c
         lvs[i] = a[i]->n_limbs;
     }
     for (size_t s0 = 0; s0 < n;) {
-        size_t s1 = s0;
-        while (s1 < n && s1 - s0 < (size_t)kMaxBatch && lvs[order[s1]] == lvs[order[s0]]) ++s1;
+        const size_t s1 = ks_batch_end(c, order.data(), n, lvs, s0);
         KsBatch kb;
         r = get_batch_ws(c, L.st, (int)(s1 - s0), kb);
         if (r) return r;
@@ -2044,8 +2059,7 @@ pfx_status pfx_apply_galois_batch(pfx_ctx *c, const pfx_ct *const *a, size_t n, 
         sc[i] = a[i]->scale;
     }
     for (size_t s0 = 0; s0 < n;) {
-        size_t s1 = s0;
-        while (s1 < n && s1 - s0 < (size_t)kMaxBatch && lvs[order[s1]] == lvs[order[s0]]) ++s1;
+        const size_t s1 = ks_batch_end(c, order.data(), n, lvs, s0);
         KsBatch kb;
         r = get_batch_ws(c, L.st, (int)(s1 - s0), kb);
         if (r) return r;
@@ -2116,8 +2130,7 @@ pfx_status pfx_rotate_batch(pfx_ctx *c, const pfx_ct *const *a, const int32_t *s
         sc[i] = a[i]->scale;
     }
     for (size_t s0 = 0; s0 < order.size();) {
-        size_t s1 = s0;
-        while (s1 < order.size() && s1 - s0 < (size_t)kMaxBatch && lvs[order[s1]] == lvs[order[s0]]) ++s1;
+        const size_t s1 = ks_batch_end(c, order.data(), order.size(), lvs, s0);
         KsBatch kb;
         pfx_status r = get_batch_ws(c, L.st, (int)(s1 - s0), kb);
         if (r) return r;
