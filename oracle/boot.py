@@ -88,6 +88,64 @@ def c2s_matrix(P) -> np.ndarray:
     return (2.0 / P.N) * np.conj(slot_roots(P)[None, :] ** np.arange(n)[:, None])
 
 
+def bit_reverse(n: int) -> np.ndarray:
+    L = n.bit_length() - 1
+    return np.array([int(format(j, f"0{L}b")[::-1], 2) if L else 0 for j in range(n)])
+
+
+def fft_stage_inverse(P, s: int):
+    """F_s^-1 as a sparse n x n matrix: rows j (lower) (u + v) / 2, rows
+    j + 2^(s-1) (upper) (u - v) / (2 w_j) of the pair (u, v)."""
+    from scipy import sparse
+    n = P.N // 2
+    ln, lh = 1 << s, 1 << (s - 1)
+    rows, cols, vals = [], [], []
+    for i in range(0, n, ln):
+        for j in range(lh):
+            w = np.exp(2j * np.pi * (pow(5, j, 4 * ln)) / (4 * ln))
+            lo, hi = i + j, i + j + lh
+            rows += [lo, lo, hi, hi]
+            cols += [lo, hi, lo, hi]
+            vals += [0.5, 0.5, 0.5 / w, -0.5 / w]
+    return sparse.csr_matrix((vals, (rows, cols)), shape=(n, n), dtype=complex)
+
+
+def c2s_factor_matrices(P, levels: int, factor: float = 1.0) -> list:
+    """The merged stages of R B (times `factor`), in the order they apply:
+    the L = log2(N/2) inverse stages F_L^-1 (first) .. F_1^-1 split into
+    `levels` consecutive groups of ceil(L / levels) stages (the last group
+    takes what is left)."""
+    n = P.N // 2
+    L = n.bit_length() - 1
+    k = -(-L // levels)
+    order = list(range(L, 0, -1))                   # F_L^-1 applies first
+    mats = []
+    for g in range(0, L, k):
+        M = None
+        for s in order[g:g + k]:
+            F = fft_stage_inverse(P, s)
+            M = F if M is None else F @ M
+        mats.append(M)
+    mats[0] = mats[0] * factor
+    return mats
+
+
+def sparse_diagonals(M) -> tuple:
+    """(steps, diagonals) of the non-zero generalised diagonals of a sparse
+    matrix: d_k[j] = M[j, (j + k) mod n]."""
+    n = M.shape[0]
+    C = M.tocoo()
+    k = (C.col - C.row) % n
+    steps = sorted(set(int(x) for x in k))
+    out = []
+    for st in steps:
+        d = np.zeros(n, dtype=complex)
+        sel = k == st
+        d[C.row[sel]] = C.data[sel]
+        out.append(d)
+    return steps, out
+
+
 def diagonals(M: np.ndarray) -> list:
     """Diagonal k of M: d_k[j] = M[j, (j + k) mod n], so M z = sum_k d_k (.) rot(z, k)."""
     n = M.shape[0]
@@ -108,6 +166,33 @@ def half_bootstrap(P, x: O.Ct, c2s_words: list, d_scale: float, n1: int, keys: d
     y = mod_raise(P, x, P.L)
     y = O.Ct(y.c, float(P.q[0]))
     z = O.rescale(P, LT.linear_transform(P, y, c2s_words, d_scale, list(range(n)), n1, keys))
+    zc = O.conjugate(P, z, keys)
+    re = O.ct_add(P, z, zc)
+    im = RP.ct_monomial(P, O.ct_sub(P, z, zc), 3 * n)
+    re = EM.evalmod(P, re, coeffs, r, K, rlk, out_factor)
+    im = EM.evalmod(P, im, coeffs, r, K, rlk, out_factor)
+    return O.ct_add(P, re, RP.ct_monomial(P, im, n))
+
+
+def half_bootstrap_factorised(P, x: O.Ct, stages: list, keys: dict, rlk, coeffs, r: int, K: float,
+                              out_factor: float) -> O.Ct:
+    """Half-BTS with the factorised CoeffsToSlots: stages[i] = (steps, words,
+    n1, d_scale) of merged stage i (words: its diagonals of R B / 2, the factor
+    1/2 in the first stage, encoded at d_scale), each a BSGS transform followed
+    by a rescale; then the conjugate split and EvalMod as in half_bootstrap.
+    Slot p of the result holds m_rev(p) / Delta + i m_(rev(p) + N/2) / Delta.
+    Reading (scales): the first stage's diagonals take the dense transform's
+    scale, every later stage's the prime its rescale drops, so the scale after
+    CoeffsToSlots is the dense one's times the ratio of the dropped primes (each
+    later stage keeps the scale it receives exactly)."""
+    from oracle import evalmod as EM
+    from oracle import linear as LT
+    from oracle import repack as RP
+    n = P.N // 2
+    y = mod_raise(P, x, P.L)
+    z = O.Ct(y.c, float(P.q[0]))
+    for steps, words, n1, d_scale in stages:
+        z = O.rescale(P, LT.linear_transform(P, z, words, d_scale, steps, n1, keys))
     zc = O.conjugate(P, z, keys)
     re = O.ct_add(P, z, zc)
     im = RP.ct_monomial(P, O.ct_sub(P, z, zc), 3 * n)

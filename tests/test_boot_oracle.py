@@ -4,6 +4,7 @@ q_0 residue and inside the centred range; the raised ciphertext decrypts
 modulo Q_L to the q_0 decryption plus q_0 I(X) with |I| at most (h + 1)/2 + 1
 (App. A.3)."""
 import numpy as np
+import pytest
 
 from oracle import boot as B
 from oracle import ckks as O
@@ -108,14 +109,14 @@ def test_coeffs_to_slots_and_back():
     assert np.max(np.abs(O.decode(P, O.decrypt(P, s, back), back.scale, n) - z)) < 1e-7
 
 
-def half_boot_setup(logn=7, n1=8, h=16, seed=700):
+def half_boot_setup(logn=7, n1=8, h=16, seed=700, n_q=14):
     """A one-limb coefficient-encoded ciphertext of v (|v| < 1, Delta = 2^40)
     over the 50 + 13 x 45-bit chain (4 special primes: the key switches of a
     ciphertext at scale q_0 need P above each digit), the keys of
     CoeffsToSlots and of the conjugation, and the diagonals of B/2; with the
     random inputs each was made from."""
     from tests.test_evalmod_oracle import coeffs
-    P = O.Params(logn, [50] + [45] * 13, [50] * 4, alpha=4, mod_log2=17)
+    P = O.Params(logn, [50] + [45] * (n_q - 1), [50] * 4, alpha=4, mod_log2=17)
     n, delta, sd = P.N // 2, 2.0 ** 40, 2.0 ** 40
     s = I.ternary_secret(P.N, h, seed)
     ext = P.ext_mods(P.L)
@@ -154,3 +155,76 @@ def test_half_bootstrap_puts_the_coefficients_in_the_slots():
     err = np.max(np.abs(got - (d["v"][:n] + 1j * d["v"][n:])))
     assert err < 2 ** -14
     assert out.level == P.L - 1 - (1 + 5 + 1 + 3 + 1)
+
+
+@pytest.mark.parametrize("logn", [4, 6, 9])
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_factorised_c2s_multiplies_out_to_the_dense_matrix(logn, levels):
+    # App. A.4's FFT-like split: the merged sparse stages, applied in order,
+    # are B / 2 with its rows in bit-reversed order (checked against the dense
+    # B of the definition B[j, l] = (2/N) zeta_l^-j)
+    P = O.Params(logn, [50, 45], [50], alpha=1, mod_log2=17)
+    n = P.N // 2
+    prod = None
+    for M in B.c2s_factor_matrices(P, levels, 0.5):
+        prod = M.toarray() if prod is None else M.toarray() @ prod
+    want = 0.5 * B.c2s_matrix(P)[B.bit_reverse(n)]
+    assert np.max(np.abs(prod - want)) < 1e-12
+
+
+def test_factorised_c2s_stages_are_sparse():
+    # k merged radix-2 stages with stride 2^(s-1): at most 2^(k+1) - 1
+    # diagonals, all at multiples of the stride (N = 2^12: 11 stages in 3
+    # groups of 4, 4, 3)
+    P = O.Params(12, [50, 45], [50], alpha=1, mod_log2=17)
+    n = P.N // 2
+    mats = B.c2s_factor_matrices(P, 3)
+    for g, (M, k, stride) in enumerate(zip(mats, (4, 4, 3), (1 << 7, 1 << 3, 1))):
+        steps, diags = B.sparse_diagonals(M)
+        assert len(steps) <= (1 << (k + 1)) - 1
+        assert all(st % stride == 0 for st in steps)
+        assert all(np.max(np.abs(d)) > 0 for d in diags)
+    # the first group's +-n/2 coincide: 2^k distinct steps
+    assert len(B.sparse_diagonals(mats[0])[0]) == 16
+
+
+def factorised_stages(P, levels, sd):
+    """(steps, diagonal words, n1, scale) per merged stage: the first at sd,
+    stage i > 0 at the prime its rescale drops (q_(L-1-i))."""
+    out = []
+    for i, M in enumerate(B.c2s_factor_matrices(P, levels, 0.5)):
+        steps, diags = B.sparse_diagonals(M)
+        n1 = 1 << max(0, (len(steps).bit_length() + 1) // 2)
+        stride = min([s for s in steps if s] or [1])
+        scale = sd if i == 0 else float(P.q[P.L - 1 - i])
+        out.append((steps, [O.encode(P, d, scale, P.L) for d in diags], n1 * stride, scale))
+    return out
+
+
+def test_factorised_half_bootstrap_equals_the_dense_one_up_to_slot_order():
+    # the same message through the factorised CoeffsToSlots (3 levels) and the
+    # dense one (1 level): slot p of the first holds what slot rev(p) of the
+    # second holds, 2 levels lower
+    d = half_boot_setup(n_q=16)
+    P = d["P"]
+    n = P.N // 2
+    stages = factorised_stages(P, 3, d["sd"])
+    gs = set()
+    for steps, _, n1, _ in stages:
+        gs |= {O.galois_element(P, s % n1) for s in steps if s % n1} | \
+              {O.galois_element(P, n1 * (s // n1)) for s in steps if s // n1}
+    ext = P.ext_mods(P.L)
+    keys = dict(d["keys"])
+    for i, g in enumerate(sorted(gs - set(keys))):
+        a = I.uniform_residues(ext, P.N, 900 + 2 * i, lead=(P.beta,))
+        e = I.gaussian_error((P.beta, P.N), 901 + 2 * i)
+        keys[g] = O.galois_key(P, d["s"], g, a, e)
+    out = B.half_bootstrap_factorised(P, d["x"], stages, keys, d["rlk"], d["coeffs"], 3, 8.0, d["out_factor"])
+    dense = run_half_boot(d)
+    assert out.level == dense.level - 2
+    got = O.decode(P, O.decrypt(P, d["s"], out), out.scale, n)
+    ref = O.decode(P, O.decrypt(P, d["s"], dense), dense.scale, n)
+    rev = B.bit_reverse(n)
+    want = d["v"][:n] + 1j * d["v"][n:]
+    assert np.max(np.abs(got - want[rev])) < 2 ** -14
+    assert np.max(np.abs(got - ref[rev])) < 2 ** -14

@@ -309,3 +309,33 @@ def test_global_threshold_with_the_difference_reversed_is_caught(monkeypatch):
     orig = QO.O.ct_sub
     monkeypatch.setattr(QO.O, "ct_sub", lambda P, a, b: orig(P, b, a))
     _expect_fail(TQ.test_global_threshold_decides_counts_two_away)
+
+
+# ---- the factorised CoeffsToSlots (oracle/boot.py)
+from oracle import boot as BOOT
+
+
+def test_factorised_c2s_with_stages_in_reverse_order_is_caught(monkeypatch):
+    orig = BOOT.c2s_factor_matrices
+    monkeypatch.setattr(BOOT, "c2s_factor_matrices", lambda P, levels, factor=1.0: orig(P, levels, factor)[::-1])
+    _expect_fail(TB.test_factorised_c2s_multiplies_out_to_the_dense_matrix, 6, 3)
+
+
+def test_factorised_c2s_with_a_wrong_twiddle_is_caught(monkeypatch):
+    from scipy import sparse
+    import numpy as np
+
+    def wrong(P, s):                        # the root's exponent taken mod 2^(s+1) instead of 2^(s+2)
+        n = P.N // 2
+        ln, lh = 1 << s, 1 << (s - 1)
+        rows, cols, vals = [], [], []
+        for i in range(0, n, ln):
+            for j in range(lh):
+                w = np.exp(2j * np.pi * (pow(5, j, 2 * ln)) / (4 * ln))
+                lo, hi = i + j, i + j + lh
+                rows += [lo, lo, hi, hi]
+                cols += [lo, hi, lo, hi]
+                vals += [0.5, 0.5, 0.5 / w, -0.5 / w]
+        return sparse.csr_matrix((vals, (rows, cols)), shape=(n, n), dtype=complex)
+    monkeypatch.setattr(BOOT, "fft_stage_inverse", wrong)
+    _expect_fail(TB.test_factorised_c2s_multiplies_out_to_the_dense_matrix, 6, 1)
