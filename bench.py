@@ -443,6 +443,46 @@ def half_boot_form(X, I, args):
     return out
 
 
+def half_boot_form_n16(X, I, args):
+    """Half-BTS at the paper's ring, N = 2^16 (workload.FactorisedHalfBtsWorkload):
+    ModRaise, the factorised CoeffsToSlots (3 sparse levels), the conjugate
+    split and two EvalMod lanes; eager and with the op-list part replayed from a
+    graph (the two checked equal word for word), and the decrypted result
+    checked against the message's coefficients."""
+    from paper_2412_13269_amd.workload import FactorisedHalfBtsWorkload
+    w = FactorisedHalfBtsWorkload(log=log)
+    reps = 5
+    res = {}
+    for mode, name in ((X.RUN_EAGER, "eager"), (X.RUN_GRAPH, "graph")):
+        w.run(mode)
+        w.sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            w.run(mode)
+        w.sync()
+        t_all = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            w.run_circuit(mode)
+        w.sync()
+        res[name] = (t_all, (time.perf_counter() - t0) / reps)
+    assert np.array_equal(w.result_words(X.RUN_EAGER), w.result_words(X.RUN_GRAPH)), \
+        "Half-BTS eager and graph disagree"
+    err = w.max_error(X.RUN_EAGER)
+    assert err < 2 ** -10, err
+    best = min(res, key=lambda k: res[k][0])
+    t_all, t_em = res[best]
+    log(f"half-BTS at N=2^16 (factorised CoeffsToSlots): {1e3 * t_all:.2f} ms ({best}; "
+        f"{1e3 * (t_all - t_em):.2f} ms ModRaise + CoeffsToSlots, {1e3 * t_em:.2f} ms conjugate split + 2 EvalMod), "
+        f"max slot error {err:.2e}")
+    out = dict(w.describe(), reps=reps, best=best, ms_per_half_bts=1e3 * t_all,
+               ms_mod_raise_and_c2s=1e3 * (t_all - t_em), ms_split_and_evalmod=1e3 * t_em,
+               ms_per_half_bts_by_mode={k: 1e3 * v[0] for k, v in res.items()}, max_slot_error=err,
+               paper_context_half_bts_share_of_time=0.072)
+    w.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -741,6 +781,7 @@ def main():
 
     # ---- Half-BTS at N = 2^12: coefficients -> slots
     hb_out = half_boot_form(X, I, args)
+    hb16_out = half_boot_form_n16(X, I, args)
 
     out = {
         "metric": "key-switch (HMult+relin/rotate) ops/s at N=2^16,L=24",
@@ -771,6 +812,7 @@ def main():
         "served": served_out,
         "lookup_repack": pfe_out,
         "half_bts": hb_out,
+        "half_bts_n16": hb16_out,
         "profiled_ms_per_step": 1e3 * p_elapsed / args.steps,
         "kernels": {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(1, v["launches"]),
                         "GBps": v["bytes"] / max(1e-12, v["ms"] * 1e-3) / 1e9} for k, v in kern.items()},

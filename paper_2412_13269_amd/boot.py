@@ -15,6 +15,17 @@ After ModRaise the coefficients read at scale q_0 are t = I + m/q_0; the slots
 of re and im are t_j and t_(j+N/2), EvalMod's last constant carries q_0 / Delta,
 so slot j of out holds m_j / Delta + i m_(j+N/2) / Delta.  Its depth is one
 level for CoeffsToSlots plus EvalMod's.
+
+Factorised CoeffsToSlots (App. A.4, for the paper's ring): B = A^-1 with A the
+slot transform, and A = F_L ... F_1 R (R the bit reversal of the n = N/2
+packed coefficients, F_s the radix-2 butterfly stage of length 2^s, twiddle of
+pair j: exp(2 pi i (5^j mod 2^(s+2)) / 2^(s+2))).  So F_1^-1 ... F_L^-1 = R B
+needs no permutation and leaves slot p holding w_rev(p): every stage has three
+generalised diagonals (steps 0, +-2^(s-1)), and `levels` groups of consecutive
+stages, each one BSGS transform and one rescale, replace the dense product
+(N/2 diagonals) at a cost of levels - 1 extra levels.  The slots of the result
+are then in bit-reversed order, which EvalMod (slot-wise) and what follows
+Half-BTS (thresholds, InnerSum) do not see.
 """
 from __future__ import annotations
 
@@ -42,6 +53,75 @@ def c2s_half_diagonals(N: int):
         e = (five[l] * j) % (2 * N)
         out.append(np.exp(-1j * np.pi * e / N) / N)
     return out
+
+
+def _inverse_stage(n: int, s: int) -> dict:
+    """F_s^-1 as {step: diagonal}: a lower row p of a pair takes (u + v) / 2,
+    the upper row (u - v) / (2 w_j)."""
+    lh = 1 << (s - 1)
+    ln = lh << 1
+    p = np.arange(n)
+    j = p % ln
+    lower = j < lh
+    jj = np.where(lower, j, j - lh)
+    pw = np.empty(lh, dtype=np.int64)            # 5^t mod 4 ln, t < lh
+    pw[0] = 1
+    for t in range(1, lh):
+        pw[t] = pw[t - 1] * 5 % (4 * ln)
+    w = np.exp(2j * np.pi * pw[jj] / (4 * ln))
+    out = {0: np.where(lower, 0.5, -0.5 / w)}
+    for step, d in ((lh % n, np.where(lower, 0.5, 0.0)), ((n - lh) % n, np.where(lower, 0.0, 0.5 / w))):
+        out[step] = out.get(step, 0) + d
+    return out
+
+
+def _after(m2: dict, m1: dict, n: int) -> dict:
+    """Diagonals of m2 applied after m1: d_k[p] = sum_a m2_a[p] m1_(k-a)[p + a]."""
+    out = {}
+    for a, d2 in m2.items():
+        for b, d1 in m1.items():
+            k = (a + b) % n
+            out[k] = out.get(k, 0) + d2 * np.roll(d1, -a)
+    return out
+
+
+def c2s_factor_stages(N: int, levels: int, factor: float = 0.5) -> list:
+    """[(steps, diagonals)] of the merged stages of factor * R B in the order
+    they apply (F_L^-1 first; ceil(L / levels) radix-2 stages per group)."""
+    n = N // 2
+    L = n.bit_length() - 1
+    k = -(-L // levels)
+    order = list(range(L, 0, -1))
+    out = []
+    for g in range(0, L, k):
+        acc = None
+        for s in order[g:g + k]:
+            st = _inverse_stage(n, s)
+            acc = st if acc is None else _after(st, acc, n)
+        if not out:
+            acc = {o: factor * d for o, d in acc.items()}
+        steps = sorted(o for o, d in acc.items() if np.any(d != 0))
+        out.append((steps, [acc[o] for o in steps]))
+    return out
+
+
+def bsgs_n1(steps) -> int:
+    """Baby-step count for a stage's steps: the stride times the power of two
+    nearest the square root of their number."""
+    stride = min([s for s in steps if s] or [1])
+    return stride * (1 << max(0, (len(steps).bit_length() + 1) // 2))
+
+
+def bsgs_rotations(N: int, steps, n1: int) -> set:
+    """Slot rotations (mod N/2, non-zero) of the baby and giant steps of one
+    BSGS transform."""
+    half = N // 2
+    return {r % half for s in steps for r in (s % n1, n1 * (s // n1)) if r % half}
+
+
+def bsgs_galois(N: int, steps, n1: int) -> set:
+    """Galois elements of the baby and giant steps of one BSGS transform."""
+    return {pow(5, r, 2 * N) for r in bsgs_rotations(N, steps, n1)}
 
 
 class HalfBootPlan:
@@ -88,5 +168,27 @@ def half_bootstrap(ctx, x, n_limbs: int, q0: float, diags, n1: int, gks, rlk, pl
     X.pfx_mod_raise(ctx, x, n_limbs, regs[1], stream)
     X.pfx_ct_set_scale(regs[1], q0)
     X.pfx_linear_transform(ctx, regs[1], diags, list(range(half)), n1, gks, regs[0], stream)
+    X.pfx_run_circuit(ctx, plan.ops, regs, plan.n_inputs, [], rlk, gks, mode, stream)
+    return regs[plan.out]
+
+
+def half_bootstrap_factorised(ctx, x, n_limbs: int, q0: float, stages, gks, rlk, plan: HalfBootPlan, regs,
+                              stream=None, mode: int = X.RUN_EAGER):
+    """Half-BTS with the factorised CoeffsToSlots: stages = [(steps, diagonal
+    plaintexts, n1)] of factor-1/2 R B (c2s_factor_stages), each a BSGS
+    transform; every stage but the last is rescaled here, the last one's
+    product goes to regs[0] for the op list (whose first op rescales it).
+    regs[1] and regs[2] hold the stages' intermediates before the op list
+    reuses them.  Slot p of regs[plan.out] holds m_rev(p) / Delta +
+    i m_(rev(p) + N/2) / Delta."""
+    X.pfx_mod_raise(ctx, x, n_limbs, regs[1], stream)
+    X.pfx_ct_set_scale(regs[1], q0)
+    cur, other = 1, 2
+    for i, (steps, pts, n1) in enumerate(stages):
+        last = i == len(stages) - 1
+        dst = 0 if last else other
+        X.pfx_linear_transform(ctx, regs[cur], pts, steps, n1, gks, regs[dst], stream)
+        if not last:
+            X.pfx_rescale(ctx, regs[dst], regs[cur], stream)
     X.pfx_run_circuit(ctx, plan.ops, regs, plan.n_inputs, [], rlk, gks, mode, stream)
     return regs[plan.out]

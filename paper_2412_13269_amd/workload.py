@@ -329,6 +329,104 @@ class HalfBtsWorkload:
         X.pfx_ctx_destroy(self.ctx)
 
 
+class FactorisedHalfBtsWorkload:
+    """Half-BTS at the paper's ring, N = 2^16, over the 24 + 4 prime chain:
+    ModRaise, CoeffsToSlots in 3 sparse levels (factorised, slots left in
+    bit-reversed order), the conjugate split and two EvalMod lanes (degree 24,
+    K = 12, four double angles); a sparse secret of 32 non-zeros (the paper's
+    bootstrapping secret), seeded keys (39 Galois keys and the
+    relinearisation key), all made by the library."""
+
+    def __init__(self, log=print, levels=3):
+        import math
+
+        import numpy as np
+        from numpy.polynomial import chebyshev as _cheb
+
+        from . import boot as HB
+        from . import inputs as I
+        from . import pfx as X
+        self.HB, self.X, self.np = HB, X, np
+        logn, qb, pb = LOGN, Q_BITS, P_BITS
+        self.ctx = X.pfx_ctx_create(X.make_params(logn, qb, pb, ALPHA, MOD_LOG2), 0)
+        self.st = X.pfx_stream_create(self.ctx)
+        N, L = 1 << logn, len(qb)
+        self.N, self.L, self.levels = N, L, levels
+        q, _, _ = X.pfx_ctx_moduli(self.ctx, L, len(pb))
+        q = [int(v) for v in q]
+        self.q0 = float(q[0])
+        seed = b"half-bts at 2^16".ljust(32, b".")
+        self.sk = X.pfx_keygen_secret(self.ctx, seed, 32)
+        self.rlk = X.pfx_keygen_relin(self.ctx, self.sk, seed)
+        fs = HB.c2s_factor_stages(N, levels)
+        rots = set()
+        for steps, _ in fs:
+            rots |= HB.bsgs_rotations(N, steps, HB.bsgs_n1(steps))
+        log(f"half-BTS at N=2^16: keygen ({len(rots) + 1} Galois keys) ...")
+        self.gks = X.pfx_keygen_galois(self.ctx, self.sk, sorted(rots), True, seed)
+        self.delta, sd, K, r = 2.0 ** 40, 2.0 ** 40, 12.0, 4
+        self.stages, self.pts = [], []
+        for i, (steps, diags) in enumerate(fs):
+            scale = sd if i == 0 else float(q[L - 1 - i])
+            pts = [X.pfx_encode(self.ctx, d.real, d.imag, L, scale) for d in diags]
+            self.pts += pts
+            self.stages.append((steps, pts, HB.bsgs_n1(steps)))
+        a = (K + 0.25) / 2 ** r
+        self.plan = HB.HalfBootPlan(N, _cheb.chebinterpolate(lambda v: np.cos(2 * math.pi * a * v), 24), r, K,
+                                    self.q0 / self.delta)
+        self.regs = {m: [X.pfx_ct_create(self.ctx, L, 1) for _ in range(self.plan.n_regs)]
+                     for m in (X.RUN_EAGER, X.RUN_GRAPH)}
+        self.x = X.pfx_ct_create(self.ctx, 1, 1)
+        self.v = I.uniform_slots(N, 920)
+        m = np.mod(np.round(self.v * self.delta).astype(np.int64), np.int64(q[0])).astype(np.uint64)[None, :]
+        pt = X.pfx_pt_import(self.ctx, m, self.delta)
+        X.pfx_encrypt(self.ctx, self.sk, pt, I.uniform_residues(q[:1], N, 921), I.gaussian_error(N, 922), self.x)
+        X.pfx_ct_destroy(pt)
+        self.galois_keys = len(self.gks)
+        self.diagonals = [len(s[0]) for s in fs]
+
+    def run(self, mode=0):
+        self.HB.half_bootstrap_factorised(self.ctx, self.x, self.L, self.q0, self.stages, self.gks, self.rlk,
+                                          self.plan, self.regs[mode], self.st, mode)
+
+    def run_circuit(self, mode=0):
+        self.X.pfx_run_circuit(self.ctx, self.plan.ops, self.regs[mode], self.plan.n_inputs, [], self.rlk,
+                               self.gks, mode, self.st)
+
+    def result_words(self, mode):
+        return self.X.pfx_ct_export(self.ctx, self.regs[mode][self.plan.out], self.N, self.st)
+
+    def max_error(self, mode=0) -> float:
+        """Largest slot error of the last result against the message's
+        coefficients in bit-reversed slot order."""
+        np, X = self.np, self.X
+        n = self.N // 2
+        m = X.pfx_decrypt(self.ctx, self.sk, self.regs[mode][self.plan.out])
+        got = X.pfx_decode(self.ctx, m, n)
+        X.pfx_ct_destroy(m)
+        rev = np.array([int(format(j, f"0{n.bit_length() - 1}b")[::-1], 2) for j in range(n)])
+        return float(np.max(np.abs(got - (self.v[:n] + 1j * self.v[n:])[rev])))
+
+    def sync(self):
+        self.X.pfx_sync(self.ctx, self.st)
+
+    def describe(self):
+        return {"N": self.N, "limbs": self.L, "special_primes": len(P_BITS), "c2s_levels": self.levels,
+                "diagonals_per_level": self.diagonals, "galois_keys": self.galois_keys, "secret_weight": 32,
+                "evalmod_degree": 24, "evalmod_K": 12, "double_angles": 4,
+                "depth": self.plan.depth + self.levels - 1, "slot_order": "bit-reversed"}
+
+    def close(self):
+        X = self.X
+        for h in self.pts + [self.x] + [r for regs in self.regs.values() for r in regs]:
+            X.pfx_ct_destroy(h)
+        for k in self.gks + [self.rlk]:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(self.sk)
+        X.pfx_stream_destroy(self.ctx, self.st)
+        X.pfx_ctx_destroy(self.ctx)
+
+
 def calibrate_copy_standalone(reps=5):
     """The copy of KsWorkload.calibrate_copy (k_u64_to_f64 over 24 limbs of
     N = 2^16: 12 MiB in, 12 MiB out per launch, two per import) on a context of
@@ -353,6 +451,7 @@ def main():
     ap.add_argument("--query", action="store_true")
     ap.add_argument("--pfe", action="store_true")
     ap.add_argument("--half-bts", action="store_true")
+    ap.add_argument("--half-bts-n16", action="store_true", help="the factorised Half-BTS at N = 2^16")
     ap.add_argument("--graph", action="store_true")
     ap.add_argument("--rotations-only", action="store_true",
                     help="each step is the 15 rotations alone, one key switch launch sequence each "
@@ -360,6 +459,19 @@ def main():
     ap.add_argument("--one-by-one", action="store_true",
                     help="the step with its rotations one at a time instead of batched")
     args = ap.parse_args()
+    if args.half_bts_n16:
+        from . import pfx as X
+        import time
+        w = FactorisedHalfBtsWorkload(log=lambda *a: print(*a, flush=True))
+        w.run(X.RUN_EAGER)
+        w.sync()
+        time.sleep(0.5)  # an idle gap that marks the end of the setup in kernel traces
+        for _ in range(args.steps):
+            w.run(X.RUN_EAGER)
+        w.sync()
+        print(f"{args.steps} Half-BTS runs done at N=2^16", flush=True)
+        w.close()
+        return
     if args.half_bts:
         from . import pfx as X
         mode = X.RUN_GRAPH if args.graph else X.RUN_EAGER

@@ -201,6 +201,32 @@ def factorised_stages(P, levels, sd):
     return out
 
 
+def factorised_setup(logn=7, levels=3, h=16, seed=700, n_q=16):
+    """half_boot_setup's inputs plus the factorised stages and the Galois keys
+    their BSGS steps need (with the random inputs each key was made from)."""
+    d = half_boot_setup(logn, 8, h=h, seed=seed, n_q=n_q)
+    P = d["P"]
+    stages = factorised_stages(P, levels, d["sd"])
+    gs = {2 * P.N - 1}
+    for steps, _, n1, _ in stages:
+        gs |= {O.galois_element(P, s % n1) for s in steps if s % n1} | \
+              {O.galois_element(P, n1 * (s // n1)) for s in steps if s // n1}
+    ext = P.ext_mods(P.L)
+    kin = {}
+    for i, g in enumerate(sorted(gs)):
+        kin[g] = (I.uniform_residues(ext, P.N, seed + 300 + 2 * i, lead=(P.beta,)),
+                  I.gaussian_error((P.beta, P.N), seed + 301 + 2 * i))
+    d["fkeys"] = {g: O.galois_key(P, d["s"], g, *v) for g, v in kin.items()}
+    d["fkey_inputs"] = kin
+    d["stages"] = stages
+    return d
+
+
+def run_factorised(d):
+    return B.half_bootstrap_factorised(d["P"], d["x"], d["stages"], d["fkeys"], d["rlk"], d["coeffs"], 3, 8.0,
+                                       d["out_factor"])
+
+
 def test_factorised_half_bootstrap_equals_the_dense_one_up_to_slot_order():
     # the same message through the factorised CoeffsToSlots (3 levels) and the
     # dense one (1 level): slot p of the first holds what slot rev(p) of the

@@ -5,6 +5,7 @@ CoeffsToSlots's output w/2 to EvalMod(Re w) + i EvalMod(Im w), the oracle's
 FP64 EvalMod steps on each part; EvalMod's two lanes pair every HMult + relin
 with its twin."""
 import numpy as np
+import pytest
 
 from oracle import evalmod as E
 from paper_2412_13269_amd import pfx as X
@@ -77,3 +78,32 @@ def test_c2s_half_diagonals_are_half_the_oracle_matrix_diagonals():
     want = B.diagonals(B.c2s_matrix(P))
     assert len(got) == len(want) == P.N // 2
     assert max(np.max(np.abs(g - w / 2)) for g, w in zip(got, want)) < 1e-15
+
+
+@pytest.mark.parametrize("logn", [5, 8, 12])
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_factorised_c2s_stages_equal_the_oracle(logn, levels):
+    # the library's stage diagonals (composed as diagonal vectors) against the
+    # oracle's (products of sparse matrices): same steps, same values
+    from oracle import boot as B
+    from oracle import ckks as O
+    from paper_2412_13269_amd import boot as HB
+    P = O.Params(logn, [50, 45], [50], alpha=1, mod_log2=17)
+    mine = HB.c2s_factor_stages(P.N, levels, 0.5)
+    ref = [B.sparse_diagonals(M) for M in B.c2s_factor_matrices(P, levels, 0.5)]
+    assert len(mine) == len(ref) <= levels
+    for (s1, d1), (s2, d2) in zip(mine, ref):
+        assert s1 == s2
+        assert max(np.max(np.abs(x - y)) for x, y in zip(d1, d2)) < 1e-12
+
+
+def test_bsgs_steps_cover_every_diagonal():
+    from paper_2412_13269_amd import boot as HB
+    N = 1 << 16
+    for steps, _ in HB.c2s_factor_stages(N, 3):
+        n1 = HB.bsgs_n1(steps)
+        g = HB.bsgs_galois(N, steps, n1)
+        for s in steps:
+            for r in (s % n1, n1 * (s // n1)):
+                assert r % (N // 2) == 0 or pow(5, r % (N // 2), 2 * N) in g
+        assert len(g) <= 2 * int(np.sqrt(len(steps))) + 4
