@@ -149,6 +149,10 @@ class HalfBootPlan:
         ops.append((X.OP_ADD, top + 1, reg(em.outs[0]), top, 0, 0.0))
         self.ops = ops
         self.out = top + 1
+        # the two real ciphertexts the paper's Half-BTS returns (Sec. 4.3): the
+        # scores of the real and of the imaginary parts (ctL, ctR), each real
+        # in every slot, before they are recombined into `out`
+        self.out_lr = (reg(em.outs[0]), reg(em.outs[1]))
         self.n_regs = top + 2
         self.n_inputs = 1
         self.reg_degree = [1] * self.n_regs
