@@ -799,8 +799,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single-ciphertext kernel bench: N=2^16, L=24 (+4 special primes, dnum=6), "
                                "scale 2^45; per step NTT+INTT of a ciphertext, HMult+relin, rescale, "
-                               "rotations by 2^0..2^14",
-                   "N": N, "L": L, "K": K, "dnum": beta, "ks_ops_per_step": ks_per_step},
+                               "rotations by 2^0..2^14 (independent key switches, batched)",
+                   "N": N, "L": L, "K": K, "dnum": beta, "ks_ops_per_step": ks_per_step,
+                   "prime_bits": {"q": list(Q_BITS), "p": list(P_BITS)},
+                   "prime_substitution": "every modulus below 2^50 (FP64-exact residues): q_0 and the 4 "
+                                         "special primes of 50 bits, q_1..q_23 near 2^45 (the ~50-bit chain "
+                                         "with a 2^45 scale); the 60-bit special prime of the N=2^12 "
+                                         "configuration is a 50-bit one in the tests"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "avg_launch_us": 1e3 * d["ms"] / d["launches"],
