@@ -151,10 +151,15 @@ pfx_status pfx_ctx_mem(const pfx_ctx *ctx, size_t *in_use, size_t *peak);
  *   ks_batch: batched key switches (pfx_rotate_batch, pfx_apply_galois_batch,
  *     pfx_mul_relin_batch, pfx_relinearize_batch) split a run of entries of
  *     one level into batches of at most ks_batch (1..8) entries, as equal in
- *     size as possible.
- * Defaults {2048, 0, 1024, 16, 8, 256, 0, 8}.  The geometry never changes a
- * result, only its speed.  pfx_tuning_load reads lines "log_n row_wg256
- * col_wg256 widen_wg min_col min_col_special rs_widen_wg [ks_fuse [ks_batch]]"
+ *     size as possible;
+ *   ks_modup_batch: inside a batched key switch the ModUp conversion, its row
+ *     pass and the inner product run for this many entries at a time (0: the
+ *     whole batch), so that the ModUp limbs stay in the last-level cache from
+ *     one launch to the next.
+ * Defaults {2048, 0, 1024, 16, 8, 256, 0, 8, 0}.  The geometry never changes
+ * a result, only its speed.  pfx_tuning_load reads lines "log_n row_wg256
+ * col_wg256 widen_wg min_col min_col_special rs_widen_wg [ks_fuse [ks_batch
+ * [ks_modup_batch]]]"
  * ('#' starts a comment line; fields left out keep their defaults);
  * the first pfx_ctx_create loads tuning.txt next to libpfx.so if there is one
  * (the package's autotuner writes it).
@@ -162,7 +167,7 @@ pfx_status pfx_ctx_mem(const pfx_ctx *ctx, size_t *in_use, size_t *peak);
 typedef struct pfx_pass_tuning {
     uint32_t log_n;
     uint32_t row_wg256, col_wg256, widen_wg, min_col, min_col_special, rs_widen_wg;
-    uint32_t ks_fuse, ks_batch;
+    uint32_t ks_fuse, ks_batch, ks_modup_batch;
 } pfx_pass_tuning;
 pfx_status pfx_tuning_set(const pfx_pass_tuning *t);
 pfx_status pfx_tuning_get(uint32_t log_n, pfx_pass_tuning *t);

@@ -317,10 +317,18 @@ pfx_status check_out(const pfx_ct *o, uint32_t lv, uint32_t deg) {
 // permuted base (KS_GALOIS) or a product operand (KS_PRODUCT) of any entry;
 // callers copy or fall back first.
 // Steps 1-3a (ModUp into the NTT domain of every target limb) of a batch.
+void ks_modup_ext(const Launch &L, const KsBatch &kb, int lv);
+
 void ks_modup(const Launch &L, const KsBatch &kb, int lv) {
+    launch_intt_scale(L, kb, lv);
+    ks_modup_ext(L, kb, lv);
+}
+
+// Steps 2-3a: the conversion into the column pass and the row pass of the
+// ModUp limbs.
+void ks_modup_ext(const Launch &L, const KsBatch &kb, int lv) {
     pfx_ctx *c = L.ctx;
     const int E = lv + c->K;
-    launch_intt_scale(L, kb, lv);
     launch_modup_col(L, kb, lv);
     const int beta = (lv + c->alpha - 1) / c->alpha;
     LimbMap m;
@@ -359,7 +367,41 @@ size_t ks_batch_end(const pfx_ctx *c, const int *order, size_t n, const Lv &lvs,
     return s0 + (run + nbat - 1) / nbat;
 }
 
+// Entries [b0, b0 + n) of a batch (not a repacking round) as a batch of their
+// own: the same kernels over the entries' scratch regions.
+KsBatch ks_slice(const KsBatch &kb, int b0, int n) {
+    KsBatch s = kb;
+    s.nb = n;
+    for (int e = 0; e < kMaxBatch; ++e) {
+        const bool on = e < n;
+        s.op[e] = on ? kb.op[b0 + e] : KsOperand{};
+        s.keys[e] = on ? kb.keys[b0 + e] : nullptr;
+        s.out0[e] = on ? kb.out0[b0 + e] : nullptr;
+        s.out1[e] = on ? kb.out1[b0 + e] : nullptr;
+    }
+    s.dcoef = kb.dcoef + (size_t)b0 * kb.sdc;
+    s.ext = kb.ext + (size_t)b0 * kb.sext;
+    s.acc = kb.acc + (size_t)b0 * kb.sacc;
+    s.tmp = kb.tmp + (size_t)b0 * kb.stmp;
+    return s;
+}
+
 void ks_run(const Launch &L, const KsBatch &kb, int lv, const pfx_swk *key) {
+    const int sub = pass_tuning(L.ctx->logn).ks_modup_batch;
+    if (kb.mode != KS_REPACK && !kb.hoisted && sub > 0 && sub < kb.nb && !row_inner_ok(L.ctx, kb)) {
+        // the ModUp limbs of a few entries at a time, written by the
+        // conversion, read and rewritten by the row pass and read by the inner
+        // product while they still sit in the last-level cache; the small
+        // launches before and after cover the whole batch
+        launch_intt_scale(L, kb, lv);
+        for (int b0 = 0; b0 < kb.nb; b0 += sub) {
+            const KsBatch s = ks_slice(kb, b0, std::min(sub, kb.nb - b0));
+            ks_modup_ext(L, s, lv);
+            launch_ks_inner(L, s, key->d_k, lv);
+        }
+        ks_moddown(L, kb, lv);
+        return;
+    }
     if (row_inner_ok(L.ctx, kb)) {
         // the ModUp row pass, the inner product and the special limbs' first
         // INTT pass in one launch
@@ -995,6 +1037,7 @@ pfx_status pfx_tuning_set(const pfx_pass_tuning *t) {
             PFX_EINVAL, "column widths must be powers of two");
     REQUIRE(t->ks_fuse == 0 || t->ks_fuse == 128 || t->ks_fuse == 256, PFX_EINVAL, "ks_fuse must be 0, 128 or 256");
     REQUIRE(t->ks_batch >= 1 && t->ks_batch <= (uint32_t)kMaxBatch, PFX_EINVAL, "ks_batch must be in [1, 8]");
+    REQUIRE(t->ks_modup_batch <= (uint32_t)kMaxBatch, PFX_EINVAL, "ks_modup_batch must be in [0, 8]");
     std::lock_guard<std::mutex> g(g_tune_mu);
     PassTuning &x = g_tune[t->log_n];
     x.row_wg256 = (int)std::min<uint32_t>(t->row_wg256, 1u << 30);
@@ -1005,6 +1048,7 @@ pfx_status pfx_tuning_set(const pfx_pass_tuning *t) {
     x.rs_widen_wg = (int)std::min<uint32_t>(t->rs_widen_wg, 1u << 30);
     x.ks_fuse = (int)t->ks_fuse;
     x.ks_batch = (int)t->ks_batch;
+    x.ks_modup_batch = (int)t->ks_modup_batch;
     return PFX_OK;
 }
 
@@ -1014,7 +1058,7 @@ pfx_status pfx_tuning_get(uint32_t log_n, pfx_pass_tuning *t) {
     const PassTuning &x = g_tune[log_n];
     *t = pfx_pass_tuning{log_n, (uint32_t)x.row_wg256, (uint32_t)x.col_wg256, (uint32_t)x.widen_wg,
                          (uint32_t)x.min_col, (uint32_t)x.min_col_special, (uint32_t)x.rs_widen_wg,
-                         (uint32_t)x.ks_fuse, (uint32_t)x.ks_batch};
+                         (uint32_t)x.ks_fuse, (uint32_t)x.ks_batch, (uint32_t)x.ks_modup_batch};
     return PFX_OK;
 }
 
@@ -1036,9 +1080,10 @@ pfx_status pfx_tuning_load(const char *path) {
         pfx_pass_tuning t;
         t.ks_fuse = (uint32_t)PassTuning{}.ks_fuse;      // fields left out keep their defaults
         t.ks_batch = (uint32_t)PassTuning{}.ks_batch;
-        const int got = std::sscanf(line, "%u %u %u %u %u %u %u %u %u", &t.log_n, &t.row_wg256, &t.col_wg256,
+        t.ks_modup_batch = (uint32_t)PassTuning{}.ks_modup_batch;
+        const int got = std::sscanf(line, "%u %u %u %u %u %u %u %u %u %u", &t.log_n, &t.row_wg256, &t.col_wg256,
                                     &t.widen_wg, &t.min_col, &t.min_col_special, &t.rs_widen_wg, &t.ks_fuse,
-                                    &t.ks_batch);
+                                    &t.ks_batch, &t.ks_modup_batch);
         if (got < 7) {
             r = fail(PFX_EINVAL, std::string("malformed tuning line in ") + path);
             break;

@@ -103,6 +103,7 @@ struct PassTuning {
     int row_wg256 = 2048, col_wg256 = 0, widen_wg = 1024, min_col = 16, min_col_special = 8, rs_widen_wg = 256;
     int ks_fuse = 0;     // threads of the fused ModUp row pass + inner product (0: separate launches)
     int ks_batch = 8;    // entries per batched key switch (at most kMaxBatch)
+    int ks_modup_batch = 0;   // entries per ModUp + inner-product launch inside a batch (0: all)
 };
 const PassTuning &pass_tuning(int logn);   // api.cpp
 

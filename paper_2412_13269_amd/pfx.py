@@ -41,7 +41,8 @@ class pfx_params(ctypes.Structure):
 class pfx_pass_tuning(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("row_wg256", ctypes.c_uint32), ("col_wg256", ctypes.c_uint32),
                 ("widen_wg", ctypes.c_uint32), ("min_col", ctypes.c_uint32), ("min_col_special", ctypes.c_uint32),
-                ("rs_widen_wg", ctypes.c_uint32), ("ks_fuse", ctypes.c_uint32), ("ks_batch", ctypes.c_uint32)]
+                ("rs_widen_wg", ctypes.c_uint32), ("ks_fuse", ctypes.c_uint32), ("ks_batch", ctypes.c_uint32),
+                ("ks_modup_batch", ctypes.c_uint32)]
 
 
 class pfx_op(ctypes.Structure):
@@ -726,7 +727,7 @@ def pfx_ctx_mem(ctx):
 
 
 TUNING_FIELDS = ("row_wg256", "col_wg256", "widen_wg", "min_col", "min_col_special", "rs_widen_wg", "ks_fuse",
-                 "ks_batch")
+                 "ks_batch", "ks_modup_batch")
 
 
 def pfx_tuning_set(log_n: int, **fields):

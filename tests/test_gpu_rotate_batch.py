@@ -104,3 +104,47 @@ def test_rotate_batch_matches_oracle(X):
         X.pfx_sk_destroy(sk)
     finally:
         X.pfx_ctx_destroy(ctx)
+
+
+def test_modup_sub_batches_give_the_same_words(X):
+    # ks_modup_batch: the ModUp conversion, its row pass and the inner product
+    # of a batch run a few entries at a time; batched rotations (a key each) and
+    # batched HMult + relin (one key) give the words of the whole-batch launches
+    logn = 16
+    N = 1 << logn
+    saved = X.pfx_tuning_get(logn)
+    ctx = X.pfx_ctx_create(X.make_params(logn, QB, PB, ALPHA, ML), 0)
+    st = X.pfx_stream_create(ctx)
+    seed = b"modup sub-batches".ljust(32, b".")
+    sk = X.pfx_keygen_secret(ctx, seed, 192)
+    rlk = X.pfx_keygen_relin(ctx, sk, seed)
+    gks = X.pfx_keygen_galois(ctx, sk, STEPS[:7], False, seed)
+    q, _, _ = X.pfx_ctx_moduli(ctx, len(QB), len(PB))
+    handles = []
+    try:
+        a = []
+        for k in range(2):
+            h = X.pfx_ct_create(ctx, len(QB), 1)
+            X.pfx_ct_import(ctx, I.uniform_residues(q, N, 760 + k, lead=(2,)), 2.0 ** 45, h, st)
+            a.append(h)
+        outs = [X.pfx_ct_create(ctx, len(QB), 1) for _ in range(7)]
+        handles += a + outs
+        res = {}
+        for sub in (0, 2, 3, 1):
+            X.pfx_tuning_set(logn, ks_modup_batch=sub)
+            X.pfx_rotate_batch(ctx, [a[k % 2] for k in range(7)], STEPS[:7], gks, outs, st)
+            words = [X.pfx_ct_export(ctx, h, N, st) for h in outs]
+            X.pfx_mul_relin_batch(ctx, [a[0], a[1], a[0], a[1], a[0]], [a[1], a[1], a[0], a[0], a[1]], rlk,
+                                  outs[:5], st)
+            res[sub] = words + [X.pfx_ct_export(ctx, h, N, st) for h in outs[:5]]
+        for sub in (2, 3, 1):
+            assert all(np.array_equal(x, y) for x, y in zip(res[sub], res[0])), sub
+    finally:
+        X.pfx_tuning_set(logn, **{f: getattr(saved, f) for f in X.TUNING_FIELDS})
+        for h in handles:
+            X.pfx_ct_destroy(h)
+        for k in gks + [rlk]:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(sk)
+        X.pfx_stream_destroy(ctx, st)
+        X.pfx_ctx_destroy(ctx)

@@ -84,17 +84,17 @@ def test_pass_tuning_table(tmp_path):
     format the autotuner writes, and rejected values."""
     X.pfx_tuning_reset()
     t = X.pfx_tuning_get(16)
-    assert [getattr(t, f) for f in X.TUNING_FIELDS] == [2048, 0, 1024, 16, 8, 256, 0, 8]
+    assert [getattr(t, f) for f in X.TUNING_FIELDS] == [2048, 0, 1024, 16, 8, 256, 0, 8, 0]
     X.pfx_tuning_set(15, row_wg256=4096, min_col=32)
     t = X.pfx_tuning_get(15)
     assert (t.row_wg256, t.min_col, t.widen_wg) == (4096, 32, 1024)
     assert X.pfx_tuning_get(16).row_wg256 == 2048
     f = tmp_path / "tuning.txt"
-    f.write_text("# comment\n14 0 0 512 8 4 128\n\n16 8192 4096 2048 16 8 512 256 4\n")
+    f.write_text("# comment\n14 0 0 512 8 4 128\n\n16 8192 4096 2048 16 8 512 256 4 2\n")
     X.pfx_tuning_load(str(f))      # a line of seven fields keeps the default ks_fuse
-    assert [getattr(X.pfx_tuning_get(14), k) for k in X.TUNING_FIELDS] == [0, 0, 512, 8, 4, 128, 0, 8]
-    assert [getattr(X.pfx_tuning_get(16), k) for k in X.TUNING_FIELDS] == [8192, 4096, 2048, 16, 8, 512, 256, 4]
-    for bad in ({"min_col": 12}, {"widen_wg": 0}, {"ks_fuse": 64}, {"ks_batch": 9}, {"ks_batch": 0}):
+    assert [getattr(X.pfx_tuning_get(14), k) for k in X.TUNING_FIELDS] == [0, 0, 512, 8, 4, 128, 0, 8, 0]
+    assert [getattr(X.pfx_tuning_get(16), k) for k in X.TUNING_FIELDS] == [8192, 4096, 2048, 16, 8, 512, 256, 4, 2]
+    for bad in ({"min_col": 12}, {"widen_wg": 0}, {"ks_fuse": 64}, {"ks_batch": 9}, {"ks_batch": 0}, {"ks_modup_batch": 9}):
         with pytest.raises(X.PfxError):
             X.pfx_tuning_set(16, **bad)
     f.write_text("16 1 2 3\n")
