@@ -133,14 +133,16 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy: str, name: str | 
 
 
 def valu_per_op(counters_csv: str, after: str, ops: int) -> str:
-    """Kernels dispatched a multiple of `ops` times after the marker are the
-    op's own (each op launches the same sequence); any other dispatch (the
-    process's tail) is listed and left out."""
+    """Kernels (by name and grid) dispatched a multiple of `ops` times after
+    the marker are the op's own (each op launches the same sequence); any
+    other dispatch (the process's tail) is listed and left out."""
     import re
     rows = []
     with open(counters_csv, newline="") as f:
         for row in csv.DictReader(f):
             name = (row.get("Kernel_Name") or "?").split("(")[0].replace("void ", "")
+            if row.get("Grid_Size"):
+                name += f" [{row['Grid_Size']}]"
             rows.append((int(row["Dispatch_Id"]), name, row["Counter_Name"], float(row["Counter_Value"])))
     marks = [d for d, n, _, _ in rows if re.search(after, n)]
     if not marks:
