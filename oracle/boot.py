@@ -25,6 +25,16 @@ w = B z with B[j, l] = (2/N) zeta_l^(-j) (the conjugate terms cancel).  Both
 are evaluated as dense matrix-vector products on the slots by the BSGS
 diagonal method (oracle.linear), diagonal k of M being M[j, (j + k) mod N/2].
 
+Sparse packing (App. A.3-A.4, n slots, 2n < N): a message in the subring of
+Y = X^r, r = N/2n, has n slots xi_l = exp(i pi 5^l / 2n), l < n, each repeated
+r times among the N/2 slots of the full ring (zeta_l^r = xi_(l mod n)).  The
+same packing holds with n in place of N/2: w_j = m'_j + i m'_(j+n) for the
+subring coefficients m'_k = m_(k r), z = A' w with A'[l, j] = xi_l^j and
+w = B' z with B'[j, l] = (1/n) xi_l^(-j); a slot rotation by k of the full ring
+rotates every period of n slots by k mod n, so the diagonal method on n
+diagonals of length n (each repeated r times) applies B' to the periodic slot
+vector.  After ModRaise the trace-like map leaves r times the subring part.
+
 Half-BTS (Sec. 4.3, App. A.3-A.4): a coefficient-encoded ciphertext of one limb
 -> one at a higher level whose slots hold its coefficients, i.e. ModRaise,
 CoeffsToSlots and EvalMod without the SlotsToCoeffs of a full bootstrapping.
@@ -70,22 +80,24 @@ def subring_trace(P, x: O.Ct, log_r: int, keys: dict) -> O.Ct:
     return x
 
 
-def slot_roots(P) -> np.ndarray:
-    n = P.N // 2
-    e = np.array([pow(5, l, 2 * P.N) for l in range(n)], dtype=np.float64)
-    return np.exp(1j * np.pi * e / P.N)
+def slot_roots(P, n: int | None = None) -> np.ndarray:
+    """exp(i pi 5^l / 2n), l < n (n slots; n = N/2: the full ring's zeta_l)."""
+    n = n or P.N // 2
+    e = np.array([pow(5, l, 4 * n) for l in range(n)], dtype=np.float64)
+    return np.exp(1j * np.pi * e / (2 * n))
 
 
-def s2c_matrix(P) -> np.ndarray:
+def s2c_matrix(P, n: int | None = None) -> np.ndarray:
     """A[l, j] = zeta_l^j: slots of the message whose coefficients are w (packed)."""
-    n = P.N // 2
-    return slot_roots(P)[:, None] ** np.arange(n)[None, :]
+    n = n or P.N // 2
+    return slot_roots(P, n)[:, None] ** np.arange(n)[None, :]
 
 
-def c2s_matrix(P) -> np.ndarray:
-    """B[j, l] = (2/N) zeta_l^-j: packed coefficients w_j = m_j + i m_(j+N/2) from the slots."""
-    n = P.N // 2
-    return (2.0 / P.N) * np.conj(slot_roots(P)[None, :] ** np.arange(n)[:, None])
+def c2s_matrix(P, n: int | None = None) -> np.ndarray:
+    """B[j, l] = (1/n) zeta_l^-j: packed coefficients w_j = m_j + i m_(j+n) from
+    the n slots (n = N/2: the factor is 2/N)."""
+    n = n or P.N // 2
+    return (1.0 / n) * np.conj(slot_roots(P, n)[None, :] ** np.arange(n)[:, None])
 
 
 def bit_reverse(n: int) -> np.ndarray:
@@ -93,11 +105,12 @@ def bit_reverse(n: int) -> np.ndarray:
     return np.array([int(format(j, f"0{L}b")[::-1], 2) if L else 0 for j in range(n)])
 
 
-def fft_stage_inverse(P, s: int):
-    """F_s^-1 as a sparse n x n matrix: rows j (lower) (u + v) / 2, rows
-    j + 2^(s-1) (upper) (u - v) / (2 w_j) of the pair (u, v)."""
+def fft_stage_inverse(P, s: int, n: int | None = None):
+    """F_s^-1 as a sparse n x n matrix (n slots, N/2 by default): rows j
+    (lower) (u + v) / 2, rows j + 2^(s-1) (upper) (u - v) / (2 w_j) of the pair
+    (u, v)."""
     from scipy import sparse
-    n = P.N // 2
+    n = n or P.N // 2
     ln, lh = 1 << s, 1 << (s - 1)
     rows, cols, vals = [], [], []
     for i in range(0, n, ln):
@@ -110,12 +123,12 @@ def fft_stage_inverse(P, s: int):
     return sparse.csr_matrix((vals, (rows, cols)), shape=(n, n), dtype=complex)
 
 
-def c2s_factor_matrices(P, levels: int, factor: float = 1.0) -> list:
+def c2s_factor_matrices(P, levels: int, factor: float = 1.0, n: int | None = None) -> list:
     """The merged stages of R B (times `factor`), in the order they apply:
-    the L = log2(N/2) inverse stages F_L^-1 (first) .. F_1^-1 split into
+    the L = log2(n) inverse stages F_L^-1 (first) .. F_1^-1 split into
     `levels` consecutive groups of ceil(L / levels) stages (the last group
-    takes what is left)."""
-    n = P.N // 2
+    takes what is left); n slots, N/2 by default."""
+    n = n or P.N // 2
     L = n.bit_length() - 1
     k = -(-L // levels)
     order = list(range(L, 0, -1))                   # F_L^-1 applies first
@@ -123,7 +136,7 @@ def c2s_factor_matrices(P, levels: int, factor: float = 1.0) -> list:
     for g in range(0, L, k):
         M = None
         for s in order[g:g + k]:
-            F = fft_stage_inverse(P, s)
+            F = fft_stage_inverse(P, s, n)
             M = F if M is None else F @ M
         mats.append(M)
     mats[0] = mats[0] * factor
@@ -175,7 +188,7 @@ def half_bootstrap(P, x: O.Ct, c2s_words: list, d_scale: float, n1: int, keys: d
 
 
 def half_bootstrap_factorised(P, x: O.Ct, stages: list, keys: dict, rlk, coeffs, r: int, K: float,
-                              out_factor: float) -> O.Ct:
+                              out_factor: float, log_r: int = 0) -> O.Ct:
     """Half-BTS with the factorised CoeffsToSlots: stages[i] = (steps, words,
     n1, d_scale) of merged stage i (words: its diagonals of R B / 2, the factor
     1/2 in the first stage, encoded at d_scale), each a BSGS transform followed
@@ -184,12 +197,20 @@ def half_bootstrap_factorised(P, x: O.Ct, stages: list, keys: dict, rlk, coeffs,
     Reading (scales): the first stage's diagonals take the dense transform's
     scale, every later stage's the prime its rescale drops, so the scale after
     CoeffsToSlots is the dense one's times the ratio of the dropped primes (each
-    later stage keeps the scale it receives exactly)."""
+    later stage keeps the scale it receives exactly).
+    Sparse packing (log_r > 0, n = N / 2^(log_r + 1) slots): the trace-like
+    map follows ModRaise (keys of N/2^t + 1 among `keys`) and the stages are
+    those of R B' for n slots with the factor 1/(2 * 2^log_r) in the first
+    (the trace multiplies the subring part by 2^log_r); slot p (and every
+    slot p + k n) of the result holds m'_rev(p) / Delta + i m'_(rev(p) + n) /
+    Delta, m'_k = m_(k 2^log_r), rev over log2(n) bits."""
     from oracle import evalmod as EM
     from oracle import linear as LT
     from oracle import repack as RP
     n = P.N // 2
     y = mod_raise(P, x, P.L)
+    if log_r:
+        y = subring_trace(P, y, log_r, keys)
     z = O.Ct(y.c, float(P.q[0]))
     for steps, words, n1, d_scale in stages:
         z = O.rescale(P, LT.linear_transform(P, z, words, d_scale, steps, n1, keys))

@@ -188,11 +188,14 @@ def test_factorised_c2s_stages_are_sparse():
     assert len(B.sparse_diagonals(mats[0])[0]) == 16
 
 
-def factorised_stages(P, levels, sd):
+def factorised_stages(P, levels, sd, log_r=0):
     """(steps, diagonal words, n1, scale) per merged stage: the first at sd,
-    stage i > 0 at the prime its rescale drops (q_(L-1-i))."""
+    stage i > 0 at the prime its rescale drops (q_(L-1-i)).  log_r > 0: the
+    stages for n = N / 2^(log_r + 1) slots (diagonals of length n, encoded
+    sparsely, so repeated 2^log_r times), 1 / 2^log_r in the first stage."""
     out = []
-    for i, M in enumerate(B.c2s_factor_matrices(P, levels, 0.5)):
+    n = P.N >> (log_r + 1)
+    for i, M in enumerate(B.c2s_factor_matrices(P, levels, 0.5 / (1 << log_r), n)):
         steps, diags = B.sparse_diagonals(M)
         n1 = 1 << max(0, (len(steps).bit_length() + 1) // 2)
         stride = min([s for s in steps if s] or [1])
@@ -201,13 +204,14 @@ def factorised_stages(P, levels, sd):
     return out
 
 
-def factorised_setup(logn=7, levels=3, h=16, seed=700, n_q=16):
+def factorised_setup(logn=7, levels=3, h=16, seed=700, n_q=16, log_r=0):
     """half_boot_setup's inputs plus the factorised stages and the Galois keys
-    their BSGS steps need (with the random inputs each key was made from)."""
+    their BSGS steps (and, for log_r > 0, the trace-like map) need, with the
+    random inputs each key was made from."""
     d = half_boot_setup(logn, 8, h=h, seed=seed, n_q=n_q)
     P = d["P"]
-    stages = factorised_stages(P, levels, d["sd"])
-    gs = {2 * P.N - 1}
+    stages = factorised_stages(P, levels, d["sd"], log_r)
+    gs = {2 * P.N - 1} | {B.trace_galois(P, t) for t in range(log_r)}
     for steps, _, n1, _ in stages:
         gs |= {O.galois_element(P, s % n1) for s in steps if s % n1} | \
               {O.galois_element(P, n1 * (s // n1)) for s in steps if s // n1}
@@ -219,12 +223,13 @@ def factorised_setup(logn=7, levels=3, h=16, seed=700, n_q=16):
     d["fkeys"] = {g: O.galois_key(P, d["s"], g, *v) for g, v in kin.items()}
     d["fkey_inputs"] = kin
     d["stages"] = stages
+    d["log_r"] = log_r
     return d
 
 
 def run_factorised(d):
     return B.half_bootstrap_factorised(d["P"], d["x"], d["stages"], d["fkeys"], d["rlk"], d["coeffs"], 3, 8.0,
-                                       d["out_factor"])
+                                       d["out_factor"], d["log_r"])
 
 
 def test_factorised_half_bootstrap_equals_the_dense_one_up_to_slot_order():
@@ -254,3 +259,53 @@ def test_factorised_half_bootstrap_equals_the_dense_one_up_to_slot_order():
     want = d["v"][:n] + 1j * d["v"][n:]
     assert np.max(np.abs(got - want[rev])) < 2 ** -14
     assert np.max(np.abs(got - ref[rev])) < 2 ** -14
+
+
+def test_sparse_slot_matrices_pack_the_subring_coefficients():
+    # n = N/8 slots: the encoder puts the message on X^(4k) (Y = X^4), and its
+    # coefficients m'_j + i m'_(j+n) are B' z for B'[j, l] = (1/n) xi_l^-j,
+    # xi_l = exp(i pi 5^l / 2n); A' = B'^-1; n = N/2 gives the full-ring B
+    P = O.Params(6, [50, 45, 45], [50, 50], alpha=1, mod_log2=17)
+    n = P.N // 8
+    A, Bm = B.s2c_matrix(P, n), B.c2s_matrix(P, n)
+    assert np.allclose(Bm @ A, np.eye(n), atol=1e-12)
+    z = I.uniform_slots(n, 31) + 1j * I.uniform_slots(n, 32)
+    words = O.encode(P, z, 2.0 ** 30, 1)
+    c = O.crt_centered(words, P.mods(1)).astype(float) / 2.0 ** 30
+    assert not np.any(c.reshape(-1, 4)[:, 1:])
+    sub = c[::4]
+    assert np.allclose(Bm @ z, sub[:n] + 1j * sub[n:], atol=1e-8)
+    # rotating the full ring's N/2 slots by k rotates each period of n by k
+    full = O.decode(P, words, 2.0 ** 30, P.N // 2)
+    assert np.allclose(full, np.tile(z, P.N // (2 * n)), atol=1e-8)
+    assert np.allclose(B.c2s_matrix(P, P.N // 2), (2.0 / P.N) * np.conj(B.s2c_matrix(P)).T, atol=1e-12)
+
+
+@pytest.mark.parametrize("logn,n", [(6, 8), (9, 32), (9, 2)])
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_sparse_factorised_c2s_multiplies_out_to_the_dense_matrix(logn, n, levels):
+    # the radix-2 split for n < N/2 slots: the stages multiply out to B'/2 with
+    # its rows bit-reversed over log2(n) bits
+    P = O.Params(logn, [50, 45], [50], alpha=1, mod_log2=17)
+    prod = None
+    for M in B.c2s_factor_matrices(P, levels, 0.5, n):
+        assert M.shape == (n, n)
+        prod = M.toarray() if prod is None else M.toarray() @ prod
+    want = 0.5 * B.c2s_matrix(P, n)[B.bit_reverse(n)]
+    assert np.max(np.abs(prod - want)) < 1e-12
+
+
+def test_sparse_half_bootstrap_puts_the_subring_coefficients_in_the_slots():
+    # sparse packing, n = N/8 (r = 4): ModRaise, the trace-like map (2
+    # automorphisms), CoeffsToSlots in 2 levels over n slots, the conjugate
+    # split and EvalMod; slot p and every p + k n decrypt to m'_rev(p) + i
+    # m'_(rev(p) + n), m'_k = m_(4k), at the level the depth leaves
+    d = factorised_setup(7, 2, log_r=2)
+    P = d["P"]
+    n = P.N // 8
+    out = run_factorised(d)
+    got = O.decode(P, O.decrypt(P, d["s"], out), out.scale, P.N // 2)
+    sub = d["v"][::4]
+    want = (sub[:n] + 1j * sub[n:])[B.bit_reverse(n)]
+    assert np.max(np.abs(got - np.tile(want, 4))) < 2 ** -14
+    assert out.level == P.L - 1 - (2 + 5 + 1 + 3 + 1)

@@ -317,7 +317,8 @@ from oracle import boot as BOOT
 
 def test_factorised_c2s_with_stages_in_reverse_order_is_caught(monkeypatch):
     orig = BOOT.c2s_factor_matrices
-    monkeypatch.setattr(BOOT, "c2s_factor_matrices", lambda P, levels, factor=1.0: orig(P, levels, factor)[::-1])
+    monkeypatch.setattr(BOOT, "c2s_factor_matrices",
+                        lambda P, levels, factor=1.0, n=None: orig(P, levels, factor, n)[::-1])
     _expect_fail(TB.test_factorised_c2s_multiplies_out_to_the_dense_matrix, 6, 3)
 
 
@@ -325,8 +326,8 @@ def test_factorised_c2s_with_a_wrong_twiddle_is_caught(monkeypatch):
     from scipy import sparse
     import numpy as np
 
-    def wrong(P, s):                        # the root's exponent taken mod 2^(s+1) instead of 2^(s+2)
-        n = P.N // 2
+    def wrong(P, s, n=None):                # the root's exponent taken mod 2^(s+1) instead of 2^(s+2)
+        n = n or P.N // 2
         ln, lh = 1 << s, 1 << (s - 1)
         rows, cols, vals = [], [], []
         for i in range(0, n, ln):
@@ -339,3 +340,25 @@ def test_factorised_c2s_with_a_wrong_twiddle_is_caught(monkeypatch):
         return sparse.csr_matrix((vals, (rows, cols)), shape=(n, n), dtype=complex)
     monkeypatch.setattr(BOOT, "fft_stage_inverse", wrong)
     _expect_fail(TB.test_factorised_c2s_multiplies_out_to_the_dense_matrix, 6, 1)
+
+
+def test_sparse_c2s_with_the_full_ring_roots_is_caught(monkeypatch):
+    # the stages of n < N/2 slots built on the N/2 slot roots' twiddles
+    orig = BOOT.fft_stage_inverse
+
+    def wrong(P, s, n=None):
+        full = orig(P, s + (P.N // 2).bit_length() - (n or P.N // 2).bit_length(), None)
+        return full[:n, :n] if n else full
+    monkeypatch.setattr(BOOT, "fft_stage_inverse", wrong)
+    _expect_fail(TB.test_sparse_factorised_c2s_multiplies_out_to_the_dense_matrix, 6, 8, 1)
+
+
+def test_sparse_half_bootstrap_without_the_trace_is_caught(monkeypatch):
+    monkeypatch.setattr(BOOT, "subring_trace", lambda P, x, log_r, keys: x)
+    _expect_fail(TB.test_sparse_half_bootstrap_puts_the_subring_coefficients_in_the_slots)
+
+
+def test_sparse_half_bootstrap_with_a_short_trace_is_caught(monkeypatch):
+    orig = BOOT.subring_trace
+    monkeypatch.setattr(BOOT, "subring_trace", lambda P, x, log_r, keys: orig(P, x, log_r - 1, keys))
+    _expect_fail(TB.test_sparse_half_bootstrap_puts_the_subring_coefficients_in_the_slots)
