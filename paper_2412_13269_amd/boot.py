@@ -26,6 +26,16 @@ stages, each one BSGS transform and one rescale, replace the dense product
 (N/2 diagonals) at a cost of levels - 1 extra levels.  The slots of the result
 are then in bit-reversed order, which EvalMod (slot-wise) and what follows
 Half-BTS (thresholds, InnerSum) do not see.
+
+Sparse packing (App. A.3-A.4, n = N/2r slots): a message on the powers of
+Y = X^r has n slots, each repeated r times among the N/2, and its packed
+coefficients w_j = m_(jr) + i m_((j+n)r) are B' z for the n-slot matrix B'
+(roots exp(i pi 5^l / 2n)).  The trace-like map after ModRaise
+(pfx_subring_trace, log r automorphisms) leaves r times the subring part, so
+the stages are those of R B' / (2r) on n slots: their steps are below n and
+their diagonals have length n (encoded with n slots, hence repeated), and a
+rotation of the full ring by k rotates every period of n slots by k mod n.
+The op list is unchanged: conjugation and the monomials act slot by slot.
 """
 from __future__ import annotations
 
@@ -85,10 +95,13 @@ def _after(m2: dict, m1: dict, n: int) -> dict:
     return out
 
 
-def c2s_factor_stages(N: int, levels: int, factor: float = 0.5) -> list:
+def c2s_factor_stages(N: int, levels: int, factor: float = 0.5, n_slots: int | None = None) -> list:
     """[(steps, diagonals)] of the merged stages of factor * R B in the order
-    they apply (F_L^-1 first; ceil(L / levels) radix-2 stages per group)."""
-    n = N // 2
+    they apply (F_L^-1 first; ceil(L / levels) radix-2 stages per group); for
+    n_slots < N/2 those of the n-slot matrix B' (steps below n_slots,
+    diagonals of length n_slots)."""
+    n = n_slots or N // 2
+    assert n & (n - 1) == 0 and 1 <= n <= N // 2
     L = n.bit_length() - 1
     k = -(-L // levels)
     order = list(range(L, 0, -1))
@@ -176,16 +189,38 @@ def half_bootstrap(ctx, x, n_limbs: int, q0: float, diags, n1: int, gks, rlk, pl
     return regs[plan.out]
 
 
+def trace_rotations(N: int, log_r: int) -> list:
+    """Slot rotations k whose Galois elements 5^k mod 2N are the trace-like
+    map's, N/2^t + 1 for t < log_r (each is 1 mod 4, so a power of 5, for
+    log_r <= log2(N) - 2)."""
+    assert 0 <= log_r <= N.bit_length() - 3
+    want = {N // (1 << t) + 1: t for t in range(log_r)}
+    out = [0] * log_r
+    g = 1
+    for k in range(N // 2):
+        if g in want:
+            out[want[g]] = k
+        g = g * 5 % (2 * N)
+    return out
+
+
 def half_bootstrap_factorised(ctx, x, n_limbs: int, q0: float, stages, gks, rlk, plan: HalfBootPlan, regs,
-                              stream=None, mode: int = X.RUN_EAGER):
+                              stream=None, mode: int = X.RUN_EAGER, log_r: int = 0):
     """Half-BTS with the factorised CoeffsToSlots: stages = [(steps, diagonal
     plaintexts, n1)] of factor-1/2 R B (c2s_factor_stages), each a BSGS
     transform; every stage but the last is rescaled here, the last one's
     product goes to regs[0] for the op list (whose first op rescales it).
     regs[1] and regs[2] hold the stages' intermediates before the op list
     reuses them.  Slot p of regs[plan.out] holds m_rev(p) / Delta +
-    i m_(rev(p) + N/2) / Delta."""
+    i m_(rev(p) + N/2) / Delta.
+    Sparse packing (log_r > 0): the trace-like map runs after ModRaise (its
+    keys, trace_rotations, among gks) and the stages are c2s_factor_stages(N,
+    levels, 0.5 / 2^log_r, N / 2^(log_r + 1)); slot p, and every slot p + k n,
+    then holds m_(rev(p) r) / Delta + i m_((rev(p) + n) r) / Delta (n =
+    N / 2r slots, r = 2^log_r, rev over log2(n) bits)."""
     X.pfx_mod_raise(ctx, x, n_limbs, regs[1], stream)
+    if log_r:
+        X.pfx_subring_trace(ctx, regs[1], log_r, gks, regs[1], stream)
     X.pfx_ct_set_scale(regs[1], q0)
     cur, other = 1, 2
     for i, (steps, pts, n1) in enumerate(stages):
