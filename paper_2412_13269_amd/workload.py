@@ -335,9 +335,10 @@ class FactorisedHalfBtsWorkload:
     bit-reversed order), the conjugate split and two EvalMod lanes (degree 24,
     K = 12, four double angles); a sparse secret of 32 non-zeros (the paper's
     bootstrapping secret), seeded keys (39 Galois keys and the
-    relinearisation key), all made by the library."""
+    relinearisation key), all made by the library.  log_r > 0: sparse
+    packing on N / 2^(log_r + 1) slots, the trace-like map after ModRaise."""
 
-    def __init__(self, log=print, levels=3):
+    def __init__(self, log=print, levels=3, log_r=0):
         import math
 
         import numpy as np
@@ -351,15 +352,16 @@ class FactorisedHalfBtsWorkload:
         self.ctx = X.pfx_ctx_create(X.make_params(logn, qb, pb, ALPHA, MOD_LOG2), 0)
         self.st = X.pfx_stream_create(self.ctx)
         N, L = 1 << logn, len(qb)
-        self.N, self.L, self.levels = N, L, levels
+        self.N, self.L, self.levels, self.log_r = N, L, levels, log_r
+        self.n = N >> (log_r + 1)
         q, _, _ = X.pfx_ctx_moduli(self.ctx, L, len(pb))
         q = [int(v) for v in q]
         self.q0 = float(q[0])
         seed = b"half-bts at 2^16".ljust(32, b".")
         self.sk = X.pfx_keygen_secret(self.ctx, seed, 32)
         self.rlk = X.pfx_keygen_relin(self.ctx, self.sk, seed)
-        fs = HB.c2s_factor_stages(N, levels)
-        rots = set()
+        fs = HB.c2s_factor_stages(N, levels, 0.5 / (1 << log_r), self.n)
+        rots = set(HB.trace_rotations(N, log_r))
         for steps, _ in fs:
             rots |= HB.bsgs_rotations(N, steps, HB.bsgs_n1(steps))
         log(f"half-BTS at N=2^16: keygen ({len(rots) + 1} Galois keys) ...")
@@ -387,7 +389,7 @@ class FactorisedHalfBtsWorkload:
 
     def run(self, mode=0):
         self.HB.half_bootstrap_factorised(self.ctx, self.x, self.L, self.q0, self.stages, self.gks, self.rlk,
-                                          self.plan, self.regs[mode], self.st, mode)
+                                          self.plan, self.regs[mode], self.st, mode, self.log_r)
 
     def run_circuit(self, mode=0):
         self.X.pfx_run_circuit(self.ctx, self.plan.ops, self.regs[mode], self.plan.n_inputs, [], self.rlk,
@@ -398,14 +400,16 @@ class FactorisedHalfBtsWorkload:
 
     def max_error(self, mode=0) -> float:
         """Largest slot error of the last result against the message's
-        coefficients in bit-reversed slot order."""
+        coefficients (those of the subring for sparse packing) in bit-reversed
+        slot order, over all N/2 slots."""
         np, X = self.np, self.X
-        n = self.N // 2
+        n, r = self.n, 1 << self.log_r
         m = X.pfx_decrypt(self.ctx, self.sk, self.regs[mode][self.plan.out])
-        got = X.pfx_decode(self.ctx, m, n)
+        got = X.pfx_decode(self.ctx, m, self.N // 2)
         X.pfx_ct_destroy(m)
         rev = np.array([int(format(j, f"0{n.bit_length() - 1}b")[::-1], 2) for j in range(n)])
-        return float(np.max(np.abs(got - (self.v[:n] + 1j * self.v[n:])[rev])))
+        sub = self.v[::r]
+        return float(np.max(np.abs(got - np.tile((sub[:n] + 1j * sub[n:])[rev], r))))
 
     def sync(self):
         self.X.pfx_sync(self.ctx, self.st)
@@ -414,7 +418,8 @@ class FactorisedHalfBtsWorkload:
         return {"N": self.N, "limbs": self.L, "special_primes": len(P_BITS), "c2s_levels": self.levels,
                 "diagonals_per_level": self.diagonals, "galois_keys": self.galois_keys, "secret_weight": 32,
                 "evalmod_degree": 24, "evalmod_K": 12, "double_angles": 4,
-                "depth": self.plan.depth + self.levels - 1, "slot_order": "bit-reversed"}
+                "depth": self.plan.depth + self.levels - 1, "slot_order": "bit-reversed", "slots": self.n,
+                "trace_automorphisms": self.log_r}
 
     def close(self):
         X = self.X
