@@ -124,7 +124,7 @@ def cpu_baseline(q, p):
         O.mul_relin(P, cts[0], cts[1], rlk)
         O.rotate(P, cts[0], 1, {g: gk})
         pairs.append(time.perf_counter() - a)
-    # HMult + relin on one thread, 3 repetitions (about 9 s each on the GPU machine's host)
+    # HMult + relin on one thread, 3 repetitions (about 9 s each on the host of the MI355X machine)
     O.set_threads(1)
     singles = []
     for _ in range(3):

@@ -225,12 +225,12 @@ class Params:
         return self.psi_q[:level] + self.psi_p
 
 
-def config1() -> Params:
+def params_n12_three_50bit() -> Params:
     """N = 2^12, three 50-bit ciphertext primes and one 50-bit special prime."""
     return Params(12, [50, 50, 50], [50], alpha=1)
 
 
-def config2(logn: int = 16, level: int = 24) -> Params:
+def params_50_45_chain(logn: int = 16, level: int = 24) -> Params:
     """N = 2^16, 24 ciphertext primes (one 50-bit, then 45-bit), 4 special
     primes of 50 bits, digits of 4 primes (dnum = 6).  Primes are 1 mod 2^17
     so the same chain serves every ring degree up to 2^16."""

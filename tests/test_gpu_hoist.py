@@ -18,7 +18,7 @@ def X():
     return pfx
 
 
-@pytest.fixture(scope="module", params=["c1", "c2s"])
+@pytest.fixture(scope="module", params=["n12_3x50", "n13_9_limbs"])
 def pair(request, X):
     cfg = CONFIGS[request.param]
     p = Pair(X, cfg["logn"], cfg["qb"], cfg["pb"], cfg["alpha"], cfg["ml"], cfg["h"], seed=23, scale=cfg["scale"])

@@ -18,7 +18,7 @@ def X():
     return pfx
 
 
-@pytest.fixture(scope="module", params=["c1", "c2s"])
+@pytest.fixture(scope="module", params=["n12_3x50", "n13_9_limbs"])
 def pair(request, X):
     cfg = CONFIGS[request.param]
     p = Pair(X, cfg["logn"], cfg["qb"], cfg["pb"], cfg["alpha"], cfg["ml"], cfg["h"], seed=29, scale=cfg["scale"])
@@ -125,7 +125,7 @@ def test_dense_coeffs_to_slots_matches_oracle(X):
 
 @pytest.fixture(scope="module")
 def pair_c1(X):
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["n12_3x50"]
     p = Pair(X, cfg["logn"], cfg["qb"], cfg["pb"], cfg["alpha"], cfg["ml"], cfg["h"], seed=37, scale=cfg["scale"])
     yield p
     p.close()

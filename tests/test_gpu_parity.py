@@ -86,10 +86,10 @@ class Pair:
 
 CONFIGS = {
     # N = 2^12, three 50-bit primes, one special prime, digits of one prime
-    "c1": dict(logn=12, qb=[50, 50, 50], pb=[50], alpha=1, ml=0, h=None, scale=2.0 ** 40),
+    "n12_3x50": dict(logn=12, qb=[50, 50, 50], pb=[50], alpha=1, ml=0, h=None, scale=2.0 ** 40),
     # the 50 + 45-bit chain with 4 special primes at N = 2^13 and 9 limbs: a partial
     # last digit (9 = 4 + 4 + 1)
-    "c2s": dict(logn=13, qb=[50] + [45] * 8, pb=[50] * 4, alpha=4, ml=17, h=192, scale=2.0 ** 45),
+    "n13_9_limbs": dict(logn=13, qb=[50] + [45] * 8, pb=[50] * 4, alpha=4, ml=17, h=192, scale=2.0 ** 45),
 }
 
 

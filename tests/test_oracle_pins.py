@@ -79,7 +79,7 @@ SMALL4 = O.Params(4, [50, 45, 45, 45, 45], [50, 50], alpha=2, mod_log2=17)
 
 
 # ---------------------------------------------------------------- primes
-@pytest.mark.parametrize("P", [O.config1(), O.config2()], ids=["c1", "c2"])
+@pytest.mark.parametrize("P", [O.params_n12_three_50bit(), O.params_50_45_chain()], ids=["n12_3x50", "n16_l24"])
 def test_primes_certified_and_ntt_friendly(P):
     allp = P.q + P.p
     assert len(set(allp)) == len(allp)
@@ -90,7 +90,7 @@ def test_primes_certified_and_ntt_friendly(P):
 
 
 def test_prime_rule_largest_below_and_nearest():
-    P = O.config2()
+    P = O.params_50_45_chain()
     step = 1 << 17
     # q_0 is the largest prime below 2^50 on the 1 mod 2^17 lattice: every
     # lattice point above it is composite (a Fermat witness proves it).
@@ -107,7 +107,7 @@ def test_prime_rule_largest_below_and_nearest():
         c += step
 
 
-@pytest.mark.parametrize("P", [O.config1(), O.config2(), O.config2(logn=14)], ids=["c1", "c2", "c2n14"])
+@pytest.mark.parametrize("P", [O.params_n12_three_50bit(), O.params_50_45_chain(), O.params_50_45_chain(logn=14)], ids=["n12_3x50", "n16_l24", "n14_l24"])
 def test_psi_is_primitive_2n_root(P):
     for q, psi in zip(P.q + P.p, P.psi_q + P.psi_p):
         assert pow(psi, P.N, q) == q - 1          # order divides 2N but not N
@@ -200,7 +200,7 @@ def test_encoding_inverts_the_slot_evaluation(n):
 
 
 def test_encode_decode_roundtrip_and_constant():
-    P = O.config1()
+    P = O.params_n12_three_50bit()
     z = I.uniform_slots(P.N // 2, seed=5)
     m = O.encode(P, z, 2.0 ** 40, 3)
     back = O.decode(P, m, 2.0 ** 40, P.N // 2)
