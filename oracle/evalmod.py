@@ -25,13 +25,19 @@ Scales.  A sum of two ciphertexts decrypts to x_a + (s_b / s_a) x_b when their
 scales s_a, s_b differ, and rescaling by primes that are only near a power of
 two lets the scales of the T_k drift apart by ~1e-6 relative, which is far
 more than bootstrapping tolerates (the message is the small fraction m / q_0 of
-t).  So every term meets its partner at one scale exactly: a constant factor
-is encoded at the scale c = s_target q / s_x (q the prime the following
-rescale drops), which brings the product to s_target after the rescale
-(mul_const_to).  T_1 enters each odd T_k that way at the product's scale; the
-highest term c_d T_d is taken at the next prime's scale and the other c_k T_k
-are brought to its scale and summed from k = d down.  Constants added with
-add_const are encoded at the ciphertext's own scale and need nothing.
+t).  So every term meets its partner at one scale exactly, and every sum is
+formed before its one rescale: a constant factor is encoded at the scale
+c = s_target / s_x, which brings the term to the sum's scale before the
+rescale exactly (mul_const_like; the sum sits at the level of its lowest
+term, the others' extra primes dropped).  T_1 enters each odd T_k that way:
+T_k = rescale(2 T_i T_j - T_1 c) with the relinearised product not yet
+rescaled; the highest term c_d T_d is taken at the next prime's scale, the
+other c_k T_k are brought to its scale, summed from k = d down and rescaled
+once.  Constants added with add_const are encoded at the ciphertext's own
+scale and need nothing.
+Reading (App. A.3 does not place the rescales): one rescale per sum, not one
+per term; both give the same scale and level, the first with fewer
+rescalings (one rounding per sum).
 """
 from __future__ import annotations
 
@@ -40,7 +46,7 @@ import math
 import numpy as np
 
 from oracle import ckks as O
-from oracle.query import _mr, add_const, mul_const_next, mul_const_to
+from oracle.query import _mr, add_const, mul_const_like, mul_const_next
 
 
 def cheb_index_pair(k: int):
@@ -56,15 +62,15 @@ def evalmod(P, x: O.Ct, coeffs, r: int, K: float, rlk, out_factor: float = 1.0) 
     T = {1: u}
     for k in range(2, d + 1):
         i, j = cheb_index_pair(k)
-        p = O.ct_mul_int(P, _mr(P, T[i], T[j], rlk), 2)
         if i == j:
-            T[k] = add_const(P, p, -1.0)
+            T[k] = add_const(P, O.ct_mul_int(P, _mr(P, T[i], T[j], rlk), 2), -1.0)
         else:
-            T[k] = O.ct_sub(P, p, O.rescale(P, mul_const_to(P, T[1], 1.0, p.scale)))
-    c = O.rescale(P, mul_const_next(P, T[d], float(coeffs[d])))
+            p = O.ct_mul_int(P, O.mul_relin(P, T[i], T[j], rlk), 2)
+            T[k] = O.rescale(P, O.ct_sub(P, p, mul_const_like(P, T[1], 1.0, p.scale)))
+    acc = mul_const_next(P, T[d], float(coeffs[d]))
     for k in range(d - 1, 0, -1):
-        c = O.ct_add(P, c, O.rescale(P, mul_const_to(P, T[k], float(coeffs[k]), c.scale)))
-    c = add_const(P, c, float(coeffs[0]))
+        acc = O.ct_add(P, acc, mul_const_like(P, T[k], float(coeffs[k]), acc.scale))
+    c = add_const(P, O.rescale(P, acc), float(coeffs[0]))
     for _ in range(r):
         c = add_const(P, O.ct_mul_int(P, _mr(P, c, c, rlk), 2), -1.0)
     return O.rescale(P, mul_const_next(P, c, out_factor / (2 * math.pi)))

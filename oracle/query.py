@@ -151,6 +151,14 @@ def mul_const_to(P, x: O.Ct, value: float, target_scale: float) -> O.Ct:
     return O.Ct(O.ct_mul_int(P, x, k).c, x.scale * cs)
 
 
+def mul_const_like(P, x: O.Ct, value: float, target_scale: float) -> O.Ct:
+    """x times `value` encoded at the scale c = target / s_x: the product has
+    scale `target_scale` itself (a term of a sum formed before its rescale)."""
+    cs = target_scale / x.scale
+    k = int(O.round_half_away(np.array([value * cs]))[0])
+    return O.Ct(O.ct_mul_int(P, x, k).c, x.scale * cs)
+
+
 # odd powers of a minimax stage and the two lower powers each is the product of
 ODD_TREE = {2: (1, 1), 3: (2, 1), 4: (2, 2), 5: (4, 1), 7: (4, 3), 8: (4, 4), 9: (8, 1), 11: (8, 3),
             13: (8, 5), 15: (8, 7)}

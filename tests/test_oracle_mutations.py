@@ -212,7 +212,17 @@ def test_evalmod_with_unmatched_scales_is_caught(monkeypatch):
     # constants taken at the next prime's scale whatever the target: the
     # terms of each sum meet at scales that differ by the primes' offsets
     from oracle import evalmod as EM
-    monkeypatch.setattr(EM, "mul_const_to", lambda P, x, value, target: EM.mul_const_next(P, x, value))
+    monkeypatch.setattr(EM, "mul_const_like", lambda P, x, value, target: EM.mul_const_next(P, x, value))
+    _expect_fail(TE.test_homomorphic_evalmod_decrypts_to_its_fp64_steps, TE.homomorphic_setup())
+
+
+def test_evalmod_with_a_rescale_per_term_and_one_per_sum_mixed_is_caught(monkeypatch):
+    # each term rescaled on its own before it joins a sum formed for one
+    # rescale: the terms land a prime below the sum's scale
+    from oracle import evalmod as EM
+    orig = EM.mul_const_like
+    monkeypatch.setattr(EM, "mul_const_like",
+                        lambda P, x, value, target: EM.O.rescale(P, orig(P, x, value, target)))
     _expect_fail(TE.test_homomorphic_evalmod_decrypts_to_its_fp64_steps, TE.homomorphic_setup())
 
 
