@@ -683,6 +683,10 @@ def main():
     per_op["rotations_15_separate_ms"] = hoist["separate"]
     per_op["rotations_15_hoisted_ms"] = hoist["hoisted"]
     per_op["rotations_15_batched_ms"] = hoist["batched"]
+    # a rotation inside the batched call, against the same roofline
+    us = 1e3 * hoist["batched"] / 15
+    op_fracs["rotate_in_batch_of_15"] = {"us": us, "bytes": ob["rotate"], "GBps": ob["rotate"] / (us * 1e-6) / 1e9,
+                                         "frac": ob["rotate"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
     log(f"15 rotations of one ciphertext: {hoist['separate']:.3f} ms one by one, {hoist['batched']:.3f} ms batched "
         f"(each its own key switch), {hoist['hoisted']:.3f} ms hoisted (one ModUp)")
     for h in hout:

@@ -528,6 +528,11 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
  *                 has register b's scale: terms of a sum meet at
  *                 one scale exactly (App. A.3, EvalMod); only b's
  *                 scale is read
+ *   MUL_CONST_LIKE dst = a * value, the constant taken at the      value,
+ *                 scale scale_b / scale_a, so that dst has register b register
+ *                 b's scale exactly: a term joins a sum formed
+ *                 before its one RESCALE (App. A.3, EvalMod);
+ *                 only b's scale is read
  *   SCALE_MUL     dst = a with scale * value (value / factor)    value
  *   ROTATE        dst = rotate(a, k)                             k
  *   ROTATE_SUM    dst = InnerSum(a) over 2^k slots               k
@@ -585,6 +590,7 @@ pfx_status pfx_ntt(pfx_ctx *ctx, uint64_t *d_words, uint32_t first_prime, uint32
 #define PFX_OP_INV_N 21
 #define PFX_OP_GALOIS 22
 #define PFX_OP_MUL_CONST_TO 23
+#define PFX_OP_MUL_CONST_LIKE 24
 
 typedef struct pfx_op {
     int32_t code;

@@ -548,6 +548,12 @@ static pfx_status run_op(pfx_ctx *c, size_t i, const pfx_op &o, pfx_ct *const *r
             r = pfx_mul_const(c, A, o.value, cs, d, stream);
             break;
         }
+        case PFX_OP_MUL_CONST_LIKE: {
+            const pfx_ct *B = R(o.b);
+            if (!B) return fail(PFX_EINVAL, at + "register index out of range");
+            r = pfx_mul_const(c, A, o.value, B->scale / A->scale, d, stream);
+            break;
+        }
         case PFX_OP_SCALE_MUL: {
             const double sc = A->scale * o.value;
             r = pfx_ct_copy(c, A, d, stream);
@@ -599,6 +605,7 @@ bool ew_code(int32_t code) {
         case PFX_OP_MUL_INT: case PFX_OP_MUL: case PFX_OP_MUL_ACC: case PFX_OP_MUL_PLAIN_ACC:
         case PFX_OP_MUL_INT_ACC: case PFX_OP_ADD_CONST: case PFX_OP_MUL_CONST: case PFX_OP_SCALE_MUL:
         case PFX_OP_DROP: case PFX_OP_MONO: case PFX_OP_INV_N: case PFX_OP_MUL_CONST_TO:
+        case PFX_OP_MUL_CONST_LIKE:
             return true;
         default:
             return false;
@@ -611,7 +618,8 @@ bool accumulates(int32_t code) {
 
 bool reads_b_reg(int32_t code) {
     return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN || code == PFX_OP_MUL ||
-           code == PFX_OP_MUL_ACC || code == PFX_OP_MUL_CONST_TO;
+           code == PFX_OP_MUL_ACC || code == PFX_OP_MUL_CONST_TO ||
+           code == PFX_OP_MUL_CONST_LIKE;
 }
 
 // Registers an op reads (a, a register b, and an accumulator), as indices.
@@ -2895,7 +2903,8 @@ static pfx_status ensure_lanes(pfx_ctx *c) {
 // the fork/join events alone order the list.
 static bool reads_b_register(int32_t code) {
     return code == PFX_OP_ADD || code == PFX_OP_SUB || code == PFX_OP_MUL_RELIN || code == PFX_OP_MUL ||
-           code == PFX_OP_MUL_ACC || code == PFX_OP_MUL_CONST_TO;
+           code == PFX_OP_MUL_ACC || code == PFX_OP_MUL_CONST_TO ||
+           code == PFX_OP_MUL_CONST_LIKE;
 }
 
 static pfx_status check_lanes(const pfx_op *ops, size_t n_ops, size_t n_regs) {

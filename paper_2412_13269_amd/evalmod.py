@@ -12,12 +12,16 @@ term:
     c  <- 2 c^2 - 1, r times                     double angle
     out = c * f / (2 pi)                         f = out_factor (1 by default)
 
-Every ciphertext product is relinearised and rescaled (MUL_RELIN, RESCALE),
-the factors 2 are integer products (MUL_INT), constants added with ADD_CONST.
-Terms that are added meet at one scale exactly: T_1 enters each odd T_k as
-MUL_CONST_TO(T_1, 1, the product's scale) + RESCALE, c_d T_d is a constant
-product at the next prime's scale (MUL_CONST, RESCALE) and the other c_k T_k
-are brought to its scale (MUL_CONST_TO, RESCALE) and summed from k = d down.
+Every ciphertext product is relinearised (MUL_RELIN) and rescaled, the
+factors 2 are integer products (MUL_INT), constants added with ADD_CONST.
+Terms that are added meet at one scale exactly, and a sum is rescaled once,
+after its last term: T_1 enters each odd T_k as MUL_CONST_LIKE(T_1, 1, the
+product before its rescale), T_k = RESCALE(2 T_i T_j - that); c_d T_d is a
+constant product at the next prime's scale (MUL_CONST), the other c_k T_k are
+brought to that scale (MUL_CONST_LIKE) and summed from k = d down, then one
+RESCALE (the sum sits at the level of T_d; ADD drops the others' extra
+primes).  Per lane that is 30 rescales for d = 24, r = 4 instead of 64 with
+one per term.
 The coefficients are an input (the caller interpolates cos(2 pi a x), e.g. at
 Chebyshev points).  Depth: 1 + ceil(log2 d) + 1 + r + 1 levels for
 d = len(coeffs) - 1.
@@ -88,22 +92,22 @@ class EvalModPlan:
             i, j = (k + 1) // 2, k // 2              # T_k = 2 T_i T_j - T_(i-j)
             T[k] = self._new()
             self._op(X.OP_MUL_RELIN, T[k], T[i], T[j])
-            self._op(X.OP_RESCALE, T[k], T[k])
-            self._op(X.OP_MUL_INT, T[k], T[k], k=2)
             if i == j:
+                self._op(X.OP_RESCALE, T[k], T[k])
+                self._op(X.OP_MUL_INT, T[k], T[k], k=2)
                 self._op(X.OP_ADD_CONST, T[k], T[k], value=-1.0)
             else:
-                t1 = self._new()                     # T_1 at the product's scale
-                self._op(X.OP_MUL_CONST_TO, t1, T[1], T[k], value=1.0)
-                self._op(X.OP_RESCALE, t1, t1)
+                self._op(X.OP_MUL_INT, T[k], T[k], k=2)
+                t1 = self._new()                     # T_1 at the unrescaled product's scale
+                self._op(X.OP_MUL_CONST_LIKE, t1, T[1], T[k], value=1.0)
                 self._op(X.OP_SUB, T[k], T[k], t1)
+                self._op(X.OP_RESCALE, T[k], T[k])
         c, term = self._new(), self._new()
         self._op(X.OP_MUL_CONST, c, T[d], value=float(self.coeffs[d]))
-        self._op(X.OP_RESCALE, c, c)
         for k in range(d - 1, 0, -1):
-            self._op(X.OP_MUL_CONST_TO, term, T[k], c, value=float(self.coeffs[k]))
-            self._op(X.OP_RESCALE, term, term)
+            self._op(X.OP_MUL_CONST_LIKE, term, T[k], c, value=float(self.coeffs[k]))
             self._op(X.OP_ADD, c, c, term)
+        self._op(X.OP_RESCALE, c, c)
         self._op(X.OP_ADD_CONST, c, c, value=float(self.coeffs[0]))
         for _ in range(self.r):
             sq = self._new()

@@ -53,7 +53,7 @@ class pfx_op(ctypes.Structure):
 OP_COPY, OP_ADD, OP_SUB, OP_MUL_PLAIN, OP_ADD_PLAIN, OP_MUL_INT, OP_MUL_RELIN = 0, 1, 2, 3, 4, 5, 6
 OP_RESCALE, OP_ADD_CONST, OP_MUL_CONST, OP_SCALE_MUL, OP_ROTATE, OP_ROTATE_SUM = 7, 8, 9, 10, 11, 12
 OP_LANE, OP_MUL, OP_RELIN, OP_MUL_ACC, OP_MUL_PLAIN_ACC, OP_MUL_INT_ACC, OP_DROP = 13, 14, 15, 16, 17, 18, 19
-OP_MONO, OP_INV_N, OP_GALOIS, OP_MUL_CONST_TO = 20, 21, 22, 23
+OP_MONO, OP_INV_N, OP_GALOIS, OP_MUL_CONST_TO, OP_MUL_CONST_LIKE = 20, 21, 22, 23, 24
 
 
 class pfx_info(ctypes.Structure):

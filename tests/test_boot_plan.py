@@ -29,7 +29,7 @@ def interpret(plan, N, z0):
             r = A * k
         elif code == X.OP_ADD_CONST:
             r = A + value
-        elif code in (X.OP_MUL_CONST, X.OP_MUL_CONST_TO):
+        elif code in (X.OP_MUL_CONST, X.OP_MUL_CONST_TO, X.OP_MUL_CONST_LIKE):
             assert code == X.OP_MUL_CONST or b in reg
             r = A * value
         elif code == X.OP_GALOIS:

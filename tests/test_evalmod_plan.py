@@ -27,7 +27,8 @@ def test_plan_computes_evalmod(deg, r):
 def test_plan_adds_terms_at_one_scale():
     # scale and level of every register over the 50 + 45-bit chain: each
     # ADD / SUB meets its operands at one scale (to rounding), the property
-    # MUL_CONST_TO exists for; the output lands at the depth's level
+    # MUL_CONST_LIKE exists for; the output lands at the depth's level, with
+    # one rescale per sum
     from oracle import ckks as O
     P = O.Params(7, [50] + [45] * 13, [50] * 3, alpha=4, mod_log2=17)
     plan = EvalModPlan(list(coeffs(24, 8.0, 3)), 3, 8.0)
@@ -48,8 +49,11 @@ def test_plan_adds_terms_at_one_scale():
             reg[dst] = (sa * P.q[la - 1], la)
         elif code == X.OP_MUL_CONST_TO:
             reg[dst] = (sa * (reg[b][0] * P.q[la - 1] / sa), la)
+        elif code == X.OP_MUL_CONST_LIKE:
+            reg[dst] = (sa * (reg[b][0] / sa), la)
         else:
             assert code in (X.OP_ADD_CONST, X.OP_MUL_INT)
             reg[dst] = (sa, la)
     assert worst < 1e-12
     assert reg[plan.out][1] == P.L - plan.depth
+    assert [c for c, *_ in plan.ops].count(X.OP_RESCALE) == 1 + 23 + 1 + 3 + 1     # T_1, products, sum, r, out

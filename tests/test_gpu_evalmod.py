@@ -64,7 +64,7 @@ def test_evalmod_plan_matches_oracle(X):
 
 def test_mul_const_to_checks(X):
     # MUL_CONST_TO: the target register must exist, and a one-limb operand has
-    # no prime left to rescale by
+    # no prime left to rescale by; MUL_CONST_LIKE against the oracle
     logn = 12
     P = O.Params(logn, QB[:3], PB, alpha=ALPHA, mod_log2=ML)
     ctx = X.pfx_ctx_create(X.make_params(logn, QB[:3], PB, ALPHA, ML), 0)
@@ -87,6 +87,19 @@ def test_mul_const_to_checks(X):
                           regs, 2, [], None, [])
         got, want = X.pfx_ct_info(regs[2]).scale, X.pfx_ct_info(regs[0]).scale
         assert abs(got / want - 1) < 1e-15 and X.pfx_ct_info(regs[2]).n_limbs == P.L - 1
+        # MUL_CONST_LIKE: the product carries register b's scale, at a's level,
+        # with the constant round(value * scale_b / scale_a) (the oracle's)
+        X.pfx_ct_set_scale(regs[1], DELTA * 2.0 ** 20)
+        X.pfx_run_circuit(ctx, [(X.OP_MUL_CONST_LIKE, 2, 0, 1, 0, -0.75)], regs, 2, [], None, [])
+        info = X.pfx_ct_info(regs[2])
+        assert info.scale == X.pfx_ct_info(regs[0]).scale * (DELTA * 2.0 ** 20 / X.pfx_ct_info(regs[0]).scale)
+        assert info.n_limbs == P.L
+        from oracle.query import mul_const_like
+        x0 = O.Ct(X.pfx_ct_export(ctx, regs[0], P.N), X.pfx_ct_info(regs[0]).scale)
+        assert np.array_equal(X.pfx_ct_export(ctx, regs[2], P.N), mul_const_like(P, x0, -0.75, DELTA * 2.0 ** 20).c)
+        with pytest.raises(X.PfxError) as e:
+            X.pfx_run_circuit(ctx, [(X.OP_MUL_CONST_LIKE, 2, 0, 7, 0, 0.5)], regs, 2, [], None, [])
+        assert e.value.status == X.PFX_EINVAL
     finally:
         for h in regs:
             X.pfx_ct_destroy(h)

@@ -50,7 +50,7 @@ def interpret(plan, inputs, pts):
             r = A + value
         elif code == X.OP_MUL_CONST:
             r = A * value
-        elif code == X.OP_MUL_CONST_TO:
+        elif code in (X.OP_MUL_CONST_TO, X.OP_MUL_CONST_LIKE):
             assert b in reg                      # the register whose scale is the target
             r = A * value
         elif code == X.OP_SCALE_MUL:
