@@ -171,18 +171,19 @@ def minimax_stage(P, x: O.Ct, coeffs, rlk) -> O.Ct:
     x^8 by ODD_TREE (each relinearised and rescaled, depth 4 for d = 15); the
     highest term c_d x^d with the constant at the next prime's scale, every
     other term c_k x^k with its constant at the scale that brings it to the
-    sum's scale after its rescale (mul_const_to), added from k = d - 2 down."""
+    sum's scale before the rescale (mul_const_like), added from k = d - 2
+    down, and the sum rescaled once (the reading of EvalMod's sums, App. A.3:
+    one rescale per sum)."""
     d = 2 * len(coeffs) - 1
     Xp = {1: x}
     for k in sorted(ODD_TREE):
         if (k <= d) if k % 2 else (k + 1 <= d):       # an even power only as a factor
             a, b = ODD_TREE[k]
             Xp[k] = _mr(P, Xp[a], Xp[b], rlk)
-    acc = O.rescale(P, mul_const_next(P, Xp[d], float(coeffs[-1])))
+    acc = mul_const_next(P, Xp[d], float(coeffs[-1]))
     for k in range(d - 2, 0, -2):
-        term = O.rescale(P, mul_const_to(P, Xp[k], float(coeffs[(k - 1) // 2]), acc.scale))
-        acc = O.ct_add(P, acc, term)
-    return acc
+        acc = O.ct_add(P, acc, mul_const_like(P, Xp[k], float(coeffs[(k - 1) // 2]), acc.scale))
+    return O.rescale(P, acc)
 
 
 def fp64_minimax(u, sign_coeffs):

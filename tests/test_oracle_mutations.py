@@ -311,7 +311,7 @@ def test_minimax_stage_with_a_wrong_power_is_caught(monkeypatch):
 
 def test_minimax_stage_with_terms_at_unmatched_scales_is_caught(monkeypatch):
     # every term taken at the next prime's scale instead of the sum's
-    monkeypatch.setattr(QO, "mul_const_to", lambda P, x, value, target_scale: QO.mul_const_next(P, x, value))
+    monkeypatch.setattr(QO, "mul_const_like", lambda P, x, value, target_scale: QO.mul_const_next(P, x, value))
     _expect_fail(TQ.test_minimax_stage_decrypts_to_the_polynomial)
 
 
