@@ -21,9 +21,10 @@ slot-domain linear score): for each block b of 2^(logN-1) records
   `stages`), per stage p(x) = sum c_k x^k:
         x^2, x^3, x^4, x^5, x^7, x^8, x^9, .. x^d by ODD_TREE (relinearised,
         rescaled; depth 4 for d = 15)
-        acc = rescale(x^d * c_d at the next prime's scale)
-        acc = acc + rescale(x^k * c_k at the scale that lands on acc's),
-              k = d - 2 down to 1                          (MUL_CONST_TO)
+        acc = x^d * c_d at the next prime's scale
+        acc = acc + x^k * c_k at acc's scale, k = d - 2 down to 1
+                                                           (MUL_CONST_LIKE)
+        acc = rescale(acc)                                 (one per sum)
     step_b = (U + 1) with the scale doubled
   OUT = InnerSum(step_0 + step_1 + ...) on the first final_limbs limbs
 
@@ -111,12 +112,11 @@ class _OpList:
                 self._mr(xp[k], xp[ODD_TREE[k][0]], xp[ODD_TREE[k][1]])
         acc = self._new()
         self._op(X.OP_MUL_CONST, acc, xp[d], value=c[-1])
-        self._op(X.OP_RESCALE, acc, acc)
         t = self._new()
         for k in range(d - 2, 0, -2):
-            self._op(X.OP_MUL_CONST_TO, t, xp[k], acc, value=c[(k - 1) // 2])
-            self._op(X.OP_RESCALE, t, t)
+            self._op(X.OP_MUL_CONST_LIKE, t, xp[k], acc, value=c[(k - 1) // 2])
             self._op(X.OP_ADD, acc, acc, t)
+        self._op(X.OP_RESCALE, acc, acc)
         self._drop(t, *xp.values())
         return acc
 

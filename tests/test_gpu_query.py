@@ -380,7 +380,7 @@ def _threshold1():
 @pytest.mark.parametrize("plan_kw", [dict(), dict(interleave=True)], ids=["plain", "interleave"])
 def test_minimax_thresholds_match_oracle(X, plan_kw):
     # Tab. 2's first threshold (three minimax stages of degree 15): the
-    # constants of every term at the scale that lands on the sum's (MUL_CONST_TO)
+    # constants of every term at the sum's scale, one rescale per sum (MUL_CONST_LIKE)
     sc = _threshold1()
     S = Setup(X, 12, 2, 71, with_oracle=True, sign_coeffs=sc, **plan_kw)
     try:

@@ -176,8 +176,11 @@ def test_plan_with_minimax_thresholds(kw):
     assert np.allclose(got, count, rtol=1e-9, atol=1e-9)
     # depth: 6 for the score and the threshold input, 5 per stage
     codes = [o[0] for o in plan.ops]
-    assert codes.count(X.OP_MUL_CONST_TO) == blocks * 3 * 7
+    assert codes.count(X.OP_MUL_CONST_LIKE) == blocks * 3 * 7
     assert codes.count(X.OP_MUL_RELIN) == blocks * (6 + 1 + 3 * 10)
+    # one rescale per product and per sum (the attribute sum, the score sum
+    # and one per minimax stage)
+    assert codes.count(X.OP_RESCALE) == codes.count(X.OP_MUL_RELIN) + blocks * (2 + 3)
 
 
 def test_minimax_stage_of_lower_degree_skips_unused_powers():
@@ -213,4 +216,4 @@ def test_global_threshold_plan_computes_the_step():
     assert np.allclose(got[~far], want[~far], rtol=1e-3, atol=1e-6)
     assert plan.depth == 31 and plan.n_inputs == 2
     codes = [o[0] for o in plan.ops]
-    assert codes.count(X.OP_MUL_RELIN) == 6 * 10 and codes.count(X.OP_MUL_CONST_TO) == 6 * 7
+    assert codes.count(X.OP_MUL_RELIN) == 6 * 10 and codes.count(X.OP_MUL_CONST_LIKE) == 6 * 7
