@@ -267,6 +267,18 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
     const int n1 = C << (S - R1), n2 = C << R1;
     auto gidx = [&](int c, int mid) { return (mid << lo) | (cbase + c); };
     if (!INV) {
+        // The second round's table twiddles depend only on mh (E1 groups of
+        // E2 - 1): staged once per block in LDS, one load per thread, and read
+        // there (16 lanes of a wave share each) instead of 2^R2 - 1 vector
+        // loads per thread after the barrier.
+        constexpr int NTW = E1 * (E2 - 1);
+        constexpr bool STAGE = IT2 == 1 && NTW <= TH;
+        __shared__ double2 twl[STAGE ? NTW : 1];
+        if (STAGE && (int)threadIdx.x < NTW) {
+            const int t = threadIdx.x, mh = t / (E2 - 1), j = t - mh * (E2 - 1);
+            const int kk = 31 - __clz(j + 1), x = j + 1 - (1 << kk);
+            twl[t] = tw[(1 << (R1 + kk)) + ((mh << kk) | x)];
+        }
 #pragma unroll
         for (int gi = 0; gi < IT1; ++gi) {
             const int g = threadIdx.x + gi * TH;
@@ -293,24 +305,55 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
 #pragma unroll
                 for (int u = 0; u < E2; ++u) v[u] = lds[((mh << R2) | u) * C + c];
                 // stage R1 + kk: mid >> (R2 - kk) = (mh << kk) | x
-                fwd_group<R2>(v, q, P.qinv, narrow, [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
+                fwd_group<R2>(v, q, P.qinv, narrow, [&](int kk, int x) {
+                    return STAGE ? twl[mh * (E2 - 1) + (1 << kk) - 1 + x] : tw[(1 << (R1 + kk)) + ((mh << kk) | x)];
+                });
 #pragma unroll
                 for (int u = 0; u < E2; ++u) store(gu(u), v[u], gi * E2 + u);
             }
         }
     } else {
+        // the first round's table twiddles, staged in LDS as in the forward
+        // pass's second round (data loads first, one barrier for both)
+        constexpr int NTW = E1 * (E2 - 1);
+        constexpr bool STAGE = IT2 == 1 && NTW <= TH;
+        if constexpr (STAGE) {
+            __shared__ double2 twl[NTW];
+            const int g = threadIdx.x;
+            const bool on = g < n2;
+            const int c = g % C, mh = g / C;
+            auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
+            double v[E2];
+            if (on) {
 #pragma unroll
-        for (int gi = 0; gi < IT2; ++gi) {
-            const int g = threadIdx.x + gi * TH;
-            if (g < n2) {
-                const int c = g % C, mh = g / C;
-                auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
-                double v[E2];
-#pragma unroll
-                for (int u = 0; u < E2; ++u) v[u] = load(gu(u), gi * E2 + u);
-                inv_group<R2>(v, P, false, narrow, [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
+                for (int u = 0; u < E2; ++u) v[u] = load(gu(u), u);
+            }
+            if (g < NTW) {
+                const int m2 = g / (E2 - 1), j = g - m2 * (E2 - 1);
+                const int kk = 31 - __clz(j + 1), x = j + 1 - (1 << kk);
+                twl[g] = tw[(1 << (R1 + kk)) + ((m2 << kk) | x)];
+            }
+            __syncthreads();
+            if (on) {
+                inv_group<R2>(v, P, false, narrow, [&](int kk, int x) { return twl[mh * (E2 - 1) + (1 << kk) - 1 + x]; });
 #pragma unroll
                 for (int u = 0; u < E2; ++u) lds[((mh << R2) | u) * C + c] = v[u];
+            }
+        } else {
+#pragma unroll
+            for (int gi = 0; gi < IT2; ++gi) {
+                const int g = threadIdx.x + gi * TH;
+                if (g < n2) {
+                    const int c = g % C, mh = g / C;
+                    auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
+                    double v[E2];
+#pragma unroll
+                    for (int u = 0; u < E2; ++u) v[u] = load(gu(u), gi * E2 + u);
+                    inv_group<R2>(v, P, false, narrow,
+                                  [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
+#pragma unroll
+                    for (int u = 0; u < E2; ++u) lds[((mh << R2) | u) * C + c] = v[u];
+                }
             }
         }
         __syncthreads();
@@ -362,20 +405,53 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
     double rtop = 0.0;
     if (IT2 == 1 && (int)threadIdx.x < n2) rtop = rt[((cbase + ((int)threadIdx.x >> R1)) << R1) | ((int)threadIdx.x & (E1 - 1))];
     if (!INV) {
+        // The first round's table twiddles depend only on the row c of the
+        // tile (C groups of E1 - 1): when each thread owns one group they are
+        // staged once per block in LDS, one load per thread, and read there
+        // (the lanes of one row share them) instead of 2^R1 - 1 vector loads
+        // per thread.
+        constexpr int NTW = (kSlots * TH >> S) * (E1 - 1);
+        constexpr bool STAGE = IT1 == 1 && NTW <= TH;
+        if constexpr (STAGE) {
+            // one group per thread: its data loads go out first, then the
+            // block's twiddle loads, and one barrier covers both
+            __shared__ double2 twl[NTW];
+            const int g = threadIdx.x;
+            const bool on = g < n1;
+            const int ml = g & ((1 << (S - R1)) - 1), c = g >> (S - R1);
+            auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
+            double v[E1];
+            if (on) {
 #pragma unroll
-        for (int gi = 0; gi < IT1; ++gi) {
-            const int g = threadIdx.x + gi * TH;
-            if (g < n1) {
-                const int ml = g & ((1 << (S - R1)) - 1), c = g >> (S - R1);
-                auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
-                double v[E1];
-#pragma unroll
-                for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
-                // stage s0 + kk: gidx >> (S - kk) = ((cbase + c) << kk) | x
-                fwd_group<R1>(v, q, P.qinv, narrow,
-                              [&](int kk, int x) { return tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)]; });
+                for (int u = 0; u < E1; ++u) v[u] = load(gu(u), u);
+            }
+            if (g < C * (E1 - 1)) {
+                const int cc = g / (E1 - 1), j = g - cc * (E1 - 1);
+                const int kk = 31 - __clz(j + 1), x = j + 1 - (1 << kk);
+                twl[g] = tw[(1 << (s0 + kk)) + (((cbase + cc) << kk) | x)];
+            }
+            __syncthreads();
+            if (on) {
+                fwd_group<R1>(v, q, P.qinv, narrow, [&](int kk, int x) { return twl[c * (E1 - 1) + (1 << kk) - 1 + x]; });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) lds[lidx(c, (u << (S - R1)) | ml)] = v[u];
+            }
+        } else {
+#pragma unroll
+            for (int gi = 0; gi < IT1; ++gi) {
+                const int g = threadIdx.x + gi * TH;
+                if (g < n1) {
+                    const int ml = g & ((1 << (S - R1)) - 1), c = g >> (S - R1);
+                    auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
+                    double v[E1];
+#pragma unroll
+                    for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
+                    // stage s0 + kk: gidx >> (S - kk) = ((cbase + c) << kk) | x
+                    fwd_group<R1>(v, q, P.qinv, narrow,
+                                  [&](int kk, int x) { return tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)]; });
+#pragma unroll
+                    for (int u = 0; u < E1; ++u) lds[lidx(c, (u << (S - R1)) | ml)] = v[u];
+                }
             }
         }
         __syncthreads();
@@ -403,10 +479,16 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
             }
         }
     } else {
-        double2 W1[E1 - 1];
-        if (IT1 == 1 && (int)threadIdx.x < n1) {
-            const int c1 = (int)threadIdx.x >> (S - R1);
-            prefetch_twiddles<R1>(W1, tw, [&](int kk, int x) { return (1 << (s0 + kk)) + (((cbase + c1) << kk) | x); });
+        // the second round's table twiddles (C groups of E1 - 1, by row),
+        // staged in LDS before the first barrier when each thread owns one
+        // group there
+        constexpr int NTW = (kSlots * TH >> S) * (E1 - 1);
+        constexpr bool STAGE = IT1 == 1 && NTW <= TH;
+        __shared__ double2 twl[STAGE ? NTW : 1];
+        if (STAGE && (int)threadIdx.x < C * (E1 - 1)) {
+            const int t = threadIdx.x, cc = t / (E1 - 1), j = t - cc * (E1 - 1);
+            const int kk = 31 - __clz(j + 1), x = j + 1 - (1 << kk);
+            twl[t] = tw[(1 << (s0 + kk)) + (((cbase + cc) << kk) | x)];
         }
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
@@ -439,7 +521,8 @@ __device__ __forceinline__ void row_pass(const PrimeDev &P, int logn, int C, int
 #pragma unroll
                 for (int u = 0; u < E1; ++u) v[u] = lds[lidx(c, (u << (S - R1)) | ml)];
                 inv_group<R1>(v, P, false, narrow, [&](int kk, int x) {
-                    return IT1 == 1 ? W1[(1 << kk) - 1 + x] : tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)];
+                    return STAGE ? twl[c * (E1 - 1) + (1 << kk) - 1 + x]
+                                 : tw[(1 << (s0 + kk)) + (((cbase + c) << kk) | x)];
                 });
 #pragma unroll
                 for (int u = 0; u < E1; ++u) store(gu(u), v[u], gi * E1 + u);
