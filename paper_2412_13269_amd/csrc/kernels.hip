@@ -520,7 +520,8 @@ void launch_mono_sum(const Launch &L, double *out, size_t cs, size_t ps, const d
 // of one limb and a run of records; each thread loads T_l[x] of both
 // polynomials for its slot once (at most MT tables), and per record and table
 // reads psi^E, E = k e_x mod 2N, from an LDS table of psi^0 .. psi^(2N-1) in
-// natural order (64 KiB: two groups, four waves per SIMD), so the tables are
+// natural order with a pad entry every 128 (64.5 KiB: two groups, four waves
+// per SIMD), so the tables are
 // read once per workgroup instead of once per record.  Products are left
 // signed in (-q, q) (the steps of mmul without the final correction) and the
 // sums reduced every seven terms; the canonical result is the residue of the
@@ -530,15 +531,19 @@ template <int MT>
 __global__ __launch_bounds__(512) void k_mono_sum_lds(double *out, size_t cs, size_t ps, const double *tables,
                                                       size_t st, size_t tps, int m, const int64_t *exps, int n,
                                                       int n_slots, int rpw, int logn, const PrimeDev *pr, bool ninv) {
-    __shared__ double tws[2 << 12];
+    // psi^E at tws[E + E / 128]: one pad entry per 128, so that the 64 lanes'
+    // exponents k e_x (e_x = 2 bitrev(x) + 1 for 64 consecutive slots x, which
+    // are k + 128 k r: all one bank without the pad) spread over the banks
+    __shared__ double tws[(2 << 12) + ((2 << 12) >> 7)];
+    auto pidx = [](uint32_t e) { return e + (e >> 7); };
     const int i = blockIdx.y;
     const PrimeDev &P = pr[i];
     const double q = P.q, qi = P.qinv;
     const uint32_t N = 1u << logn;
     for (uint32_t j = threadIdx.x; j < N; j += blockDim.x) {
         const double w = P.tw[__brev(j) >> (32 - logn)].x;   // psi^j, and psi^(N + j) = -psi^j
-        tws[j] = w;
-        tws[N + j] = q - w;
+        tws[pidx(j)] = w;
+        tws[pidx(N + j)] = q - w;
     }
     __syncthreads();
     const uint32_t x = blockIdx.x * 512u + threadIdx.x;
@@ -574,7 +579,7 @@ __global__ __launch_bounds__(512) void k_mono_sum_lds(double *out, size_t cs, si
         for (int l = 0; l < MT; ++l) {
             if (l < m) {
                 const uint32_t E = ((uint32_t)(uint64_t)ke[l] * ex) & mask;
-                const double w = tws[E];
+                const double w = tws[pidx(E)];
                 s0 += mul_signed(t0[l], w);
                 s1 += mul_signed(t1[l], w);
                 if (++pend == 7) {
