@@ -752,6 +752,9 @@ pfx_status pfx_event_create(pfx_ctx *ctx, void **out);
 pfx_status pfx_event_record(pfx_ctx *ctx, void *event, void *stream);
 pfx_status pfx_event_elapsed(pfx_ctx *ctx, void *start, void *end, float *ms);
 pfx_status pfx_event_destroy(pfx_ctx *ctx, void *event);
+/* Work enqueued on `stream` after this call waits until `event` (recorded on
+ * another stream) has completed: independent calls on two streams joined. */
+pfx_status pfx_stream_wait_event(pfx_ctx *ctx, void *stream, void *event);
 
 /* ------------------------------------------------------------ profiling */
 /* When on, the library brackets each kernel launch with HIP events on the

@@ -3411,6 +3411,12 @@ pfx_status pfx_event_record(pfx_ctx *c, void *event, void *stream) {
     return PFX_OK;
 }
 
+pfx_status pfx_stream_wait_event(pfx_ctx *c, void *stream, void *event) {
+    REQUIRE(c && event, PFX_EINVAL, "null argument");
+    HIPCHECK(hipStreamWaitEvent(S(stream), (hipEvent_t)event, 0));
+    return PFX_OK;
+}
+
 pfx_status pfx_event_elapsed(pfx_ctx *c, void *start, void *end, float *ms) {
     REQUIRE(c && start && end && ms, PFX_EINVAL, "null argument");
     HIPCHECK(hipEventSynchronize((hipEvent_t)end));

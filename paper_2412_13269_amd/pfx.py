@@ -191,6 +191,7 @@ _SIGS = {
     "pfx_stream_destroy": (_i32, [_vp, _vp]),
     "pfx_event_create": (_i32, [_vp, _VPP]),
     "pfx_event_record": (_i32, [_vp, _vp, _vp]),
+    "pfx_stream_wait_event": (_i32, [_vp, _vp, _vp]),
     "pfx_event_elapsed": (_i32, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)]),
     "pfx_event_destroy": (_i32, [_vp, _vp]),
     "pfx_profile_enable": (_i32, [_vp, ctypes.c_int]),
@@ -843,6 +844,10 @@ def pfx_event_create(ctx) -> int:
 
 def pfx_event_record(ctx, event: int, stream=None):
     _check(_lib.pfx_event_record(ctx, ctypes.c_void_p(event), _stream(stream)))
+
+
+def pfx_stream_wait_event(ctx, stream, event: int):
+    _check(_lib.pfx_stream_wait_event(ctx, _stream(stream), ctypes.c_void_p(event)))
 
 
 def pfx_event_elapsed(ctx, start: int, end: int) -> float:

@@ -148,3 +148,48 @@ def test_modup_sub_batches_give_the_same_words(X):
         X.pfx_sk_destroy(sk)
         X.pfx_stream_destroy(ctx, st)
         X.pfx_ctx_destroy(ctx)
+
+
+def test_stream_join_orders_work_on_two_streams(X):
+    # pfx_stream_wait_event: HMult + relin on a second stream forked from the
+    # first, a rotation of its product on the first after the join; words equal
+    # the same calls on one stream
+    logn = 12
+    N = 1 << logn
+    ctx = X.pfx_ctx_create(X.make_params(logn, QB[:6], PB, ALPHA, ML), 0)
+    st, st2 = X.pfx_stream_create(ctx), X.pfx_stream_create(ctx)
+    fork, join = X.pfx_event_create(ctx), X.pfx_event_create(ctx)
+    seed = b"stream join".ljust(32, b".")
+    sk = X.pfx_keygen_secret(ctx, seed, 192)
+    rlk = X.pfx_keygen_relin(ctx, sk, seed)
+    gks = X.pfx_keygen_galois(ctx, sk, [3], False, seed)
+    q, _, _ = X.pfx_ctx_moduli(ctx, 6, len(PB))
+    hs = [X.pfx_ct_create(ctx, 6, 1) for _ in range(6)]
+    a, b, p1, r1, p2, r2 = hs
+    try:
+        for k, h in enumerate((a, b)):
+            X.pfx_ct_import(ctx, I.uniform_residues(q, N, 780 + k, lead=(2,)), 2.0 ** 45, h, st)
+        X.pfx_mul_relin(ctx, a, b, rlk, p1, st)
+        X.pfx_rotate(ctx, p1, 3, gks, r1, st)
+        for _ in range(3):
+            X.pfx_event_record(ctx, fork, st)
+            X.pfx_stream_wait_event(ctx, st2, fork)
+            X.pfx_mul_relin(ctx, a, b, rlk, p2, st2)
+            X.pfx_event_record(ctx, join, st2)
+            X.pfx_stream_wait_event(ctx, st, join)
+            X.pfx_rotate(ctx, p2, 3, gks, r2, st)
+            assert np.array_equal(X.pfx_ct_export(ctx, r2, N, st), X.pfx_ct_export(ctx, r1, N, st))
+        with pytest.raises(X.PfxError):
+            X.pfx_stream_wait_event(ctx, st, 0)
+    finally:
+        X.pfx_sync(ctx, st2)
+        for h in hs:
+            X.pfx_ct_destroy(h)
+        for k in gks + [rlk]:
+            X.pfx_swk_destroy(k)
+        X.pfx_sk_destroy(sk)
+        X.pfx_event_destroy(ctx, fork)
+        X.pfx_event_destroy(ctx, join)
+        X.pfx_stream_destroy(ctx, st2)
+        X.pfx_stream_destroy(ctx, st)
+        X.pfx_ctx_destroy(ctx)
