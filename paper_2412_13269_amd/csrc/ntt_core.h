@@ -189,16 +189,6 @@ __device__ __forceinline__ void row_twiddle_bases(double *B, double top, double 
     for (int k = NST - 1; k > 0; --k) B[k - 1] = mmul_lazy(B[k], B[k], q, qinv);
 }
 
-// The 2^NST - 1 table twiddles of one register group, loaded ahead of the
-// group (index of stage kk, run x: base(kk) + x, kept at W[2^kk - 1 + x]).
-template <int NST, class Idx>
-__device__ __forceinline__ void prefetch_twiddles(double2 *W, const GTw &tw, Idx &&idx) {
-#pragma unroll
-    for (int kk = 0; kk < NST; ++kk)
-#pragma unroll
-        for (int x = 0; x < (1 << kk); ++x) W[(1 << kk) - 1 + x] = tw[idx(kk, x)];
-}
-
 template <int NST>
 __device__ __forceinline__ void fwd_group_gen(double *v, const double *B, const double *rc, double q, double qinv,
                                               bool narrow) {

@@ -87,6 +87,11 @@ def test_mul_const_to_checks(X):
                           regs, 2, [], None, [])
         got, want = X.pfx_ct_info(regs[2]).scale, X.pfx_ct_info(regs[0]).scale
         assert abs(got / want - 1) < 1e-15 and X.pfx_ct_info(regs[2]).n_limbs == P.L - 1
+        # the product's words before the rescale are the oracle's
+        from oracle.query import mul_const_to
+        X.pfx_run_circuit(ctx, [(X.OP_MUL_CONST_TO, 2, 0, 0, 0, 0.5)], regs, 2, [], None, [])
+        x0 = O.Ct(X.pfx_ct_export(ctx, regs[0], P.N), X.pfx_ct_info(regs[0]).scale)
+        assert np.array_equal(X.pfx_ct_export(ctx, regs[2], P.N), mul_const_to(P, x0, 0.5, x0.scale).c)
         # MUL_CONST_LIKE: the product carries register b's scale, at a's level,
         # with the constant round(value * scale_b / scale_a) (the oracle's)
         X.pfx_ct_set_scale(regs[1], DELTA * 2.0 ** 20)
