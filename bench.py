@@ -806,8 +806,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single-ciphertext kernel bench: N=2^16, L=24 (+4 special primes, dnum=6), "
                                "scale 2^45; per step NTT+INTT of a ciphertext, HMult+relin, rescale, "
-                               "rotations by 2^0..2^14 (independent key switches, batched; HMult+relin+"
-                               "rescale on a second stream beside them)",
+                               "rotations by 2^0..2^14 (independent key switches, batched)",
                    "N": N, "L": L, "K": K, "dnum": beta, "ks_ops_per_step": ks_per_step,
                    "prime_bits": {"q": list(Q_BITS), "p": list(P_BITS)},
                    "prime_substitution": "every modulus below 2^50 (FP64-exact residues): q_0 and the 4 "

@@ -86,40 +86,26 @@ class KsWorkload:
         self.words = I.uniform_residues(q, N, 7, lead=(2,))          # one ciphertext: 2 x 24 limbs
         self.dbuf = X.pfx_dev_alloc(ctx, self.words.nbytes)
         X.pfx_memcpy_htod(ctx, self.dbuf, self.words, st)
-        # HMult + relin + rescale, independent of the rest of the step, run on
-        # a second stream forked from and joined back into `st`
-        self.st2 = X.pfx_stream_create(ctx)
-        self.fork, self.join = X.pfx_event_create(ctx), X.pfx_event_create(ctx)
-
-    def _mult_beside(self):
-        X, ctx = self.X, self.ctx
-        X.pfx_event_record(ctx, self.fork, self.st)
-        X.pfx_stream_wait_event(ctx, self.st2, self.fork)
-        X.pfx_mul_relin(ctx, self.cts[0], self.cts[1], self.rlk, self.prod, self.st2)
-        X.pfx_rescale(ctx, self.prod, self.prod, self.st2)
-        X.pfx_event_record(ctx, self.join, self.st2)
 
     def step(self):
-        """NTT + INTT of a ciphertext and the 15 rotations (independent key
-        switches, each with its own key and output, run as batched key
-        switches, pfx_rotate_batch) on `st`; HMult + relin + rescale beside
-        them on a second stream, joined before the step ends."""
+        """The 15 rotations (independent key switches, each with its own key
+        and output) run as batched key switches (pfx_rotate_batch)."""
         X, ctx, st, L = self.X, self.ctx, self.st, self.L
-        self._mult_beside()
         X.pfx_ntt(ctx, self.dbuf, 0, L, 2, False, st)
         X.pfx_ntt(ctx, self.dbuf, 0, L, 2, True, st)
+        X.pfx_mul_relin(ctx, self.cts[0], self.cts[1], self.rlk, self.prod, st)
+        X.pfx_rescale(ctx, self.prod, self.prod, st)
         self.rotations()
-        X.pfx_stream_wait_event(ctx, st, self.join)
 
     def step_one_by_one(self):
         """The same step with every rotation its own key switch launch sequence."""
         X, ctx, st, L = self.X, self.ctx, self.st, self.L
-        self._mult_beside()
         X.pfx_ntt(ctx, self.dbuf, 0, L, 2, False, st)
         X.pfx_ntt(ctx, self.dbuf, 0, L, 2, True, st)
+        X.pfx_mul_relin(ctx, self.cts[0], self.cts[1], self.rlk, self.prod, st)
+        X.pfx_rescale(ctx, self.prod, self.prod, st)
         for r, o in zip(ROT_STEPS, self.rots):
             X.pfx_rotate(ctx, self.cts[0], r, self.gks, o, st)
-        X.pfx_stream_wait_event(ctx, st, self.join)
 
     def rotations(self):
         self.X.pfx_rotate_batch(self.ctx, [self.cts[0]] * len(ROT_STEPS), ROT_STEPS, self.gks, self.rots, self.st)
@@ -146,10 +132,6 @@ class KsWorkload:
             X.pfx_swk_destroy(k)
         X.pfx_sk_destroy(self.sk)
         X.pfx_dev_free(self.ctx, self.dbuf)
-        X.pfx_sync(self.ctx, self.st2)
-        X.pfx_event_destroy(self.ctx, self.fork)
-        X.pfx_event_destroy(self.ctx, self.join)
-        X.pfx_stream_destroy(self.ctx, self.st2)
         X.pfx_stream_destroy(self.ctx, self.st)
         X.pfx_ctx_destroy(self.ctx)
 
