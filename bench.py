@@ -13,7 +13,9 @@ steps.  The 15 rotations are independent key switches and run as one batched
 call (pfx_rotate_batch: every launch covers up to 8 of them, each with its own
 key; nothing is shared between them, no ModUp is hoisted); the same step with
 one launch sequence per rotation is timed beside it
-(`ms_per_step_rotations_one_by_one`).
+(`ms_per_step_rotations_one_by_one`), and so is the step with each rotation
+reading its own copy of the input (`ms_per_step_distinct_inputs`: no
+rotation's input reads served from a cache an earlier entry filled).
 
 Prints one JSON line.  `roofline` is for the kernel with the largest device
 time in the timed region, from HIP events the library records around each of
@@ -534,6 +536,15 @@ def main():
         W.step_one_by_one()
     X.pfx_sync(ctx, st)
     ms_one_by_one = 1e3 * (time.perf_counter() - o0) / args.steps
+    # the same step with the 15 rotations reading 15 separate copies of the input
+    for _ in range(2):
+        W.step_distinct_inputs()
+    X.pfx_sync(ctx, st)
+    o0 = time.perf_counter()
+    for _ in range(args.steps):
+        W.step_distinct_inputs()
+    X.pfx_sync(ctx, st)
+    ms_distinct = 1e3 * (time.perf_counter() - o0) / args.steps
     ks_per_step = KS_PER_STEP
     kern = {}
     for name in X.pfx_profile_names(ctx):
@@ -543,7 +554,7 @@ def main():
     d = kern[dom]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
     log(f"timed {1e3 * elapsed / args.steps:.3f} ms/step, profiled {1e3 * p_elapsed / args.steps:.3f} ms/step, "
-        f"rotations one by one {ms_one_by_one:.3f} ms/step")
+        f"rotations one by one {ms_one_by_one:.3f} ms/step, distinct inputs {ms_distinct:.3f} ms/step")
     log("kernels (profiled region):")
     for name, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"]):
         log(f"  {name:16s} launches={v['launches']:6d} avg_us={1e3 * v['ms'] / max(1, v['launches']):9.2f} "
@@ -799,6 +810,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / args.steps,
         "ms_per_step_rotations_one_by_one": ms_one_by_one,
+        "ms_per_step_distinct_inputs": ms_distinct,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

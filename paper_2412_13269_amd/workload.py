@@ -110,6 +110,21 @@ class KsWorkload:
     def rotations(self):
         self.X.pfx_rotate_batch(self.ctx, [self.cts[0]] * len(ROT_STEPS), ROT_STEPS, self.gks, self.rots, self.st)
 
+    def step_distinct_inputs(self):
+        """The same step with every rotation reading a ciphertext of its own
+        (copies of the input in separate buffers), so no rotation's input
+        reads are served from a cache that a previous entry filled."""
+        X, ctx, st, L = self.X, self.ctx, self.st, self.L
+        if not hasattr(self, "srcs"):
+            self.srcs = [X.pfx_ct_create(ctx, L, 1) for _ in ROT_STEPS]
+            for c in self.srcs:
+                X.pfx_ct_copy(ctx, self.cts[0], c, st)
+        X.pfx_ntt(ctx, self.dbuf, 0, L, 2, False, st)
+        X.pfx_ntt(ctx, self.dbuf, 0, L, 2, True, st)
+        X.pfx_mul_relin(ctx, self.cts[0], self.cts[1], self.rlk, self.prod, st)
+        X.pfx_rescale(ctx, self.prod, self.prod, st)
+        X.pfx_rotate_batch(ctx, self.srcs, ROT_STEPS, self.gks, self.rots, st)
+
     def rotations_one_by_one(self):
         for r, o in zip(ROT_STEPS, self.rots):
             self.X.pfx_rotate(self.ctx, self.cts[0], r, self.gks, o, self.st)
