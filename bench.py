@@ -536,10 +536,17 @@ def main():
         W.step_one_by_one()
     X.pfx_sync(ctx, st)
     ms_one_by_one = 1e3 * (time.perf_counter() - o0) / args.steps
-    # the same step with the 15 rotations reading 15 separate copies of the input
+    # the same step with the 15 rotations reading 15 separate copies of the input;
+    # its outputs must equal those of the one-by-one step above word for word
+    shared_words = [X.pfx_ct_export(ctx, o, N, st) for o in W.rots]
     for _ in range(2):
         W.step_distinct_inputs()
     X.pfx_sync(ctx, st)
+    distinct_identical = all(np.array_equal(w, X.pfx_ct_export(ctx, o, N, st))
+                             for w, o in zip(shared_words, W.rots))
+    del shared_words
+    if not distinct_identical:
+        raise RuntimeError("batched rotations of separate input copies differ from the one-by-one rotations")
     o0 = time.perf_counter()
     for _ in range(args.steps):
         W.step_distinct_inputs()
@@ -811,6 +818,7 @@ def main():
         "ms_per_step": 1e3 * elapsed / args.steps,
         "ms_per_step_rotations_one_by_one": ms_one_by_one,
         "ms_per_step_distinct_inputs": ms_distinct,
+        "distinct_inputs_identical": distinct_identical,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
