@@ -44,7 +44,7 @@ struct NttArgs {
 
 template <int S, bool ROW, bool INV, int TH>
 __global__ __launch_bounds__(TH) void k_ntt_pass(const NttArgs a) {
-    __shared__ double lds[NttTile<TH>::lds];
+    __shared__ double lds[ROW ? NttTile<TH>::lds : col_lds<S, TH>()];
     const int id = xcd_slot(a.nblk);
     if (id >= a.nblk) return;
     const int bl = id / a.tiles;

@@ -44,7 +44,7 @@ namespace pfx {
 template <int S, int NT, int TH>
 __global__ __launch_bounds__(TH) void k_modup_col(const KsArgs a, double *__restrict__ ext,
                                                            const double *__restrict__ dcoef) {
-    __shared__ double lds[NttTile<TH>::lds];
+    __shared__ double lds[col_lds<S, TH>()];
     const int gid = xcd_slot(a.n);
     if (gid >= a.n) return;
     const int bi = gid / a.per, id = gid - bi * a.per;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(TH) void k_modup_col(const KsArgs a, double *__rest
 template <int S, int NT, int TH>
 __global__ __launch_bounds__(TH) void k_moddown_col(const KsArgs a, double *__restrict__ tmp,
                                                              const double *__restrict__ acc) {
-    __shared__ double lds[NttTile<TH>::lds];
+    __shared__ double lds[col_lds<S, TH>()];
     const int gid = xcd_slot(a.n);
     if (gid >= a.n) return;
     const int bi = gid / a.per, id = gid - bi * a.per;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(3))) void k_
 
 template <int S, bool ROW, int MODE, int TH>
 __global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__restrict__ dst) {
-    __shared__ double lds[NttTile<TH>::lds];
+    __shared__ double lds[ROW ? NttTile<TH>::lds : col_lds<S, TH>()];
     const int gid = xcd_slot(a.n);
     if (gid >= a.n) return;
     const int bi = gid / a.per, id = gid - bi * a.per;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(TH) void k_intt_scale(const KsArgs a, double *__res
 
 template <int S, bool ROW, int TH>
 __global__ __launch_bounds__(TH) void k_intt_special(const KsArgs a, double *__restrict__ acc) {
-    __shared__ double lds[NttTile<TH>::lds];
+    __shared__ double lds[ROW ? NttTile<TH>::lds : col_lds<S, TH>()];
     const int gid = xcd_slot(a.n);
     if (gid >= a.n) return;
     const int bi = gid / a.per, id = gid - bi * a.per;

@@ -49,6 +49,14 @@ struct NttTile {
     static constexpr int lds = n + n / 16;
 };
 constexpr int kNttLds = NttTile<kNttThreads>::lds;
+// When both rounds of a column pass are one kSlots-point group per thread
+// (2^S = kSlots^2), the pass exchanges its tile through LDS in two halves
+// (rows below 2^(S-1), then the rest): a block that runs only column passes
+// needs half a tile of LDS, so twice as many blocks fit on a CU.
+template <int S>
+constexpr bool col_half_exchange() { return (1 << ((S + 1) / 2)) == kSlots && (1 << (S / 2)) == kSlots; }
+template <int S, int TH>
+constexpr int col_lds() { return col_half_exchange<S>() ? NttTile<TH>::n / 2 : NttTile<TH>::lds; }
 
 // Twiddle tables live in device global memory; their pointers are read from
 // the PrimeDev records, so without this the compiler would emit generic (flat)
@@ -256,80 +264,123 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
     const GTw tw = as_global(INV ? P.itw : P.tw);
     const int n1 = C << (S - R1), n2 = C << R1;
     auto gidx = [&](int c, int mid) { return (mid << lo) | (cbase + c); };
-    if (!INV) {
-        // The second round's table twiddles depend only on mh (E1 groups of
-        // E2 - 1): staged once per block in LDS, one load per thread, and read
-        // there (16 lanes of a wave share each) instead of 2^R2 - 1 vector
-        // loads per thread after the barrier.
-        constexpr int NTW = E1 * (E2 - 1);
-        constexpr bool STAGE = IT2 == 1 && NTW <= TH;
-        __shared__ double2 twl[STAGE ? NTW : 1];
-        if (STAGE && (int)threadIdx.x < NTW) {
-            const int t = threadIdx.x, mh = t / (E2 - 1), j = t - mh * (E2 - 1);
-            const int kk = 31 - __clz(j + 1), x = j + 1 - (1 << kk);
-            twl[t] = tw[(1 << (R1 + kk)) + ((mh << kk) | x)];
-        }
+    if constexpr (col_half_exchange<S>()) {
+        // One group per thread in each round (E1 = E2 = kSlots).  Round-1
+        // group g = (c, m) holds rows (u << R2) | m and round-2 group g holds
+        // rows (m << R2) | u, so the exchange splits on the row's top bit: u
+        // below H in the first half, m below H reads only the first half.
+        // LDS rows are local to the half (C * 2^(S-1) doubles).
+        constexpr int H = kSlots / 2;
+        constexpr int NTW = E1 * (E2 - 1);   // round-2 table twiddles, staged in LDS
+        __shared__ double2 twl[NTW];
+        const int g = threadIdx.x, c = g % C, m = g / C;
+        const bool on1 = g < n1, on2 = g < n2;
+        auto lrow1 = [&](int u) { return ((u & (H - 1)) << (S - R1)) | m; };   // round-1 slot u, local row
+        auto lrow2 = [&](int u) { return ((m & (H - 1)) << R2) | u; };         // round-2 slot u, local row
+        double v[kSlots], w[kSlots];
+        if (!INV) {
+            if (on1) {
 #pragma unroll
-        for (int gi = 0; gi < IT1; ++gi) {
-            const int g = threadIdx.x + gi * TH;
-            if (g < n1) {
-                const int c = g % C, ml = g / C;
-                auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
-                double v[E1];
-#pragma unroll
-                for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
-                // stage kk < R1: index 2^kk + (mid >> (S - kk)) = 2^kk + x (ml shifts out)
+                for (int u = 0; u < kSlots; ++u) v[u] = load(gidx(c, (u << (S - R1)) | m), u);
+            }
+            for (int t = g; t < NTW; t += TH) {
+                const int mh = t / (E2 - 1), j = t - mh * (E2 - 1);
+                const int kk = 31 - __clz(j + 1), x = j + 1 - (1 << kk);
+                twl[t] = tw[(1 << (R1 + kk)) + ((mh << kk) | x)];
+            }
+            if (on1) {
                 fwd_group<R1>(v, q, P.qinv, narrow, [&](int kk, int x) { return tw[(1 << kk) + x]; });
 #pragma unroll
-                for (int u = 0; u < E1; ++u) lds[((u << (S - R1)) | ml) * C + c] = v[u];
+                for (int u = 0; u < H; ++u) lds[lrow1(u) * C + c] = v[u];
             }
-        }
-        __syncthreads();
+            __syncthreads();
+            if (on2 && m < H) {
 #pragma unroll
-        for (int gi = 0; gi < IT2; ++gi) {
-            const int g = threadIdx.x + gi * TH;
-            if (g < n2) {
-                const int c = g % C, mh = g / C;
-                auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
-                double v[E2];
+                for (int u = 0; u < kSlots; ++u) w[u] = lds[lrow2(u) * C + c];
+            }
+            __syncthreads();
+            if (on1) {
 #pragma unroll
-                for (int u = 0; u < E2; ++u) v[u] = lds[((mh << R2) | u) * C + c];
-                // stage R1 + kk: mid >> (R2 - kk) = (mh << kk) | x
-                fwd_group<R2>(v, q, P.qinv, narrow, [&](int kk, int x) {
-                    return STAGE ? twl[mh * (E2 - 1) + (1 << kk) - 1 + x] : tw[(1 << (R1 + kk)) + ((mh << kk) | x)];
-                });
+                for (int u = H; u < kSlots; ++u) lds[lrow1(u) * C + c] = v[u];
+            }
+            __syncthreads();
+            if (on2) {
+                if (m >= H) {
 #pragma unroll
-                for (int u = 0; u < E2; ++u) store(gu(u), v[u], gi * E2 + u);
+                    for (int u = 0; u < kSlots; ++u) w[u] = lds[lrow2(u) * C + c];
+                }
+                fwd_group<R2>(w, q, P.qinv, narrow,
+                              [&](int kk, int x) { return twl[m * (E2 - 1) + (1 << kk) - 1 + x]; });
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) store(gidx(c, (m << R2) | u), w[u], u);
+            }
+        } else {
+            if (on2) {
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) v[u] = load(gidx(c, (m << R2) | u), u);
+            }
+            for (int t = g; t < NTW; t += TH) {
+                const int m2 = t / (E2 - 1), j = t - m2 * (E2 - 1);
+                const int kk = 31 - __clz(j + 1), x = j + 1 - (1 << kk);
+                twl[t] = tw[(1 << (R1 + kk)) + ((m2 << kk) | x)];
+            }
+            __syncthreads();
+            if (on2) {
+                inv_group<R2>(v, P, false, narrow, [&](int kk, int x) { return twl[m * (E2 - 1) + (1 << kk) - 1 + x]; });
+                if (m < H) {
+#pragma unroll
+                    for (int u = 0; u < kSlots; ++u) lds[lrow2(u) * C + c] = v[u];
+                }
+            }
+            __syncthreads();
+            if (on1) {
+#pragma unroll
+                for (int u = 0; u < H; ++u) w[u] = lds[lrow1(u) * C + c];
+            }
+            __syncthreads();
+            if (on2 && m >= H) {
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) lds[lrow2(u) * C + c] = v[u];
+            }
+            __syncthreads();
+            if (on1) {
+#pragma unroll
+                for (int u = H; u < kSlots; ++u) w[u] = lds[lrow1(u) * C + c];
+                inv_group<R1>(w, P, true, narrow, [&](int kk, int x) { return tw[(1 << kk) + x]; });
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) store(gidx(c, (u << (S - R1)) | m), mcanon(w[u], q), u);
             }
         }
     } else {
-        // the first round's table twiddles, staged in LDS as in the forward
-        // pass's second round (data loads first, one barrier for both)
-        constexpr int NTW = E1 * (E2 - 1);
-        constexpr bool STAGE = IT2 == 1 && NTW <= TH;
-        if constexpr (STAGE) {
-            __shared__ double2 twl[NTW];
-            const int g = threadIdx.x;
-            const bool on = g < n2;
-            const int c = g % C, mh = g / C;
-            auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
-            double v[E2];
-            if (on) {
-#pragma unroll
-                for (int u = 0; u < E2; ++u) v[u] = load(gu(u), u);
-            }
-            if (g < NTW) {
-                const int m2 = g / (E2 - 1), j = g - m2 * (E2 - 1);
+        if (!INV) {
+            // The second round's table twiddles depend only on mh (E1 groups of
+            // E2 - 1): staged once per block in LDS, one load per thread, and read
+            // there (16 lanes of a wave share each) instead of 2^R2 - 1 vector
+            // loads per thread after the barrier.
+            constexpr int NTW = E1 * (E2 - 1);
+            constexpr bool STAGE = IT2 == 1 && NTW <= TH;
+            __shared__ double2 twl[STAGE ? NTW : 1];
+            if (STAGE && (int)threadIdx.x < NTW) {
+                const int t = threadIdx.x, mh = t / (E2 - 1), j = t - mh * (E2 - 1);
                 const int kk = 31 - __clz(j + 1), x = j + 1 - (1 << kk);
-                twl[g] = tw[(1 << (R1 + kk)) + ((m2 << kk) | x)];
+                twl[t] = tw[(1 << (R1 + kk)) + ((mh << kk) | x)];
+            }
+#pragma unroll
+            for (int gi = 0; gi < IT1; ++gi) {
+                const int g = threadIdx.x + gi * TH;
+                if (g < n1) {
+                    const int c = g % C, ml = g / C;
+                    auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
+                    double v[E1];
+#pragma unroll
+                    for (int u = 0; u < E1; ++u) v[u] = load(gu(u), gi * E1 + u);
+                    // stage kk < R1: index 2^kk + (mid >> (S - kk)) = 2^kk + x (ml shifts out)
+                    fwd_group<R1>(v, q, P.qinv, narrow, [&](int kk, int x) { return tw[(1 << kk) + x]; });
+#pragma unroll
+                    for (int u = 0; u < E1; ++u) lds[((u << (S - R1)) | ml) * C + c] = v[u];
+                }
             }
             __syncthreads();
-            if (on) {
-                inv_group<R2>(v, P, false, narrow, [&](int kk, int x) { return twl[mh * (E2 - 1) + (1 << kk) - 1 + x]; });
-#pragma unroll
-                for (int u = 0; u < E2; ++u) lds[((mh << R2) | u) * C + c] = v[u];
-            }
-        } else {
 #pragma unroll
             for (int gi = 0; gi < IT2; ++gi) {
                 const int g = threadIdx.x + gi * TH;
@@ -338,27 +389,73 @@ __device__ __forceinline__ void col_pass(const PrimeDev &P, int logn, int C, int
                     auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
                     double v[E2];
 #pragma unroll
-                    for (int u = 0; u < E2; ++u) v[u] = load(gu(u), gi * E2 + u);
-                    inv_group<R2>(v, P, false, narrow,
-                                  [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
+                    for (int u = 0; u < E2; ++u) v[u] = lds[((mh << R2) | u) * C + c];
+                    // stage R1 + kk: mid >> (R2 - kk) = (mh << kk) | x
+                    fwd_group<R2>(v, q, P.qinv, narrow, [&](int kk, int x) {
+                        return STAGE ? twl[mh * (E2 - 1) + (1 << kk) - 1 + x] : tw[(1 << (R1 + kk)) + ((mh << kk) | x)];
+                    });
+#pragma unroll
+                    for (int u = 0; u < E2; ++u) store(gu(u), v[u], gi * E2 + u);
+                }
+            }
+        } else {
+            // the first round's table twiddles, staged in LDS as in the forward
+            // pass's second round (data loads first, one barrier for both)
+            constexpr int NTW = E1 * (E2 - 1);
+            constexpr bool STAGE = IT2 == 1 && NTW <= TH;
+            if constexpr (STAGE) {
+                __shared__ double2 twl[NTW];
+                const int g = threadIdx.x;
+                const bool on = g < n2;
+                const int c = g % C, mh = g / C;
+                auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
+                double v[E2];
+                if (on) {
+#pragma unroll
+                    for (int u = 0; u < E2; ++u) v[u] = load(gu(u), u);
+                }
+                if (g < NTW) {
+                    const int m2 = g / (E2 - 1), j = g - m2 * (E2 - 1);
+                    const int kk = 31 - __clz(j + 1), x = j + 1 - (1 << kk);
+                    twl[g] = tw[(1 << (R1 + kk)) + ((m2 << kk) | x)];
+                }
+                __syncthreads();
+                if (on) {
+                    inv_group<R2>(v, P, false, narrow, [&](int kk, int x) { return twl[mh * (E2 - 1) + (1 << kk) - 1 + x]; });
 #pragma unroll
                     for (int u = 0; u < E2; ++u) lds[((mh << R2) | u) * C + c] = v[u];
                 }
+            } else {
+#pragma unroll
+                for (int gi = 0; gi < IT2; ++gi) {
+                    const int g = threadIdx.x + gi * TH;
+                    if (g < n2) {
+                        const int c = g % C, mh = g / C;
+                        auto gu = [&](int u) { return gidx(c, (mh << R2) | u); };
+                        double v[E2];
+#pragma unroll
+                        for (int u = 0; u < E2; ++u) v[u] = load(gu(u), gi * E2 + u);
+                        inv_group<R2>(v, P, false, narrow,
+                                      [&](int kk, int x) { return tw[(1 << (R1 + kk)) + ((mh << kk) | x)]; });
+#pragma unroll
+                        for (int u = 0; u < E2; ++u) lds[((mh << R2) | u) * C + c] = v[u];
+                    }
+                }
             }
-        }
-        __syncthreads();
+            __syncthreads();
 #pragma unroll
-        for (int gi = 0; gi < IT1; ++gi) {
-            const int g = threadIdx.x + gi * TH;
-            if (g < n1) {
-                const int c = g % C, ml = g / C;
-                auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
-                double v[E1];
+            for (int gi = 0; gi < IT1; ++gi) {
+                const int g = threadIdx.x + gi * TH;
+                if (g < n1) {
+                    const int c = g % C, ml = g / C;
+                    auto gu = [&](int u) { return gidx(c, (u << (S - R1)) | ml); };
+                    double v[E1];
 #pragma unroll
-                for (int u = 0; u < E1; ++u) v[u] = lds[((u << (S - R1)) | ml) * C + c];
-                inv_group<R1>(v, P, true, narrow, [&](int kk, int x) { return tw[(1 << kk) + x]; });
+                    for (int u = 0; u < E1; ++u) v[u] = lds[((u << (S - R1)) | ml) * C + c];
+                    inv_group<R1>(v, P, true, narrow, [&](int kk, int x) { return tw[(1 << kk) + x]; });
 #pragma unroll
-                for (int u = 0; u < E1; ++u) store(gu(u), mcanon(v[u], q), gi * E1 + u);
+                    for (int u = 0; u < E1; ++u) store(gu(u), mcanon(v[u], q), gi * E1 + u);
+                }
             }
         }
     }

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(TH) void k_rs_intt_row(const RsArgs a, double *__re
 
 template <int S, int TH>
 __global__ __launch_bounds__(TH) void k_rs_intt_col(const RsArgs a, double *__restrict__ last) {
-    __shared__ double lds[NttTile<TH>::lds];
+    __shared__ double lds[col_lds<S, TH>()];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
     rs_intt_col_body<S, TH>(a, a.C, a.tiles, id, last, lds);
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(TH) void k_rs_intt_col(const RsArgs a, double *__re
 template <int S, int TH>
 __global__ __launch_bounds__(TH) void k_rs_col(const RsArgs a, double *__restrict__ tmp,
                                                const double *__restrict__ last) {
-    __shared__ double lds[NttTile<TH>::lds];
+    __shared__ double lds[col_lds<S, TH>()];
     const int id = xcd_slot(a.n);
     if (id >= a.n) return;
     rs_col_body<S, TH>(a, a.C, a.tiles, id, tmp, last, lds);
